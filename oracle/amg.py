@@ -1,0 +1,187 @@
+"""Smoothed-aggregation AMG preconditioner (oracle).
+
+Paper, Section 3.2 and Table 1:
+
+* aggregates are cubes of 3^d lattice vertices (prolongation-operator paragraph); the
+  tentative prolongator has a 1 in row i, column j when vertex i belongs to aggregate j;
+* the tentative prolongator is smoothed by one damped-Jacobi step,
+  P = (I - omega D^-1 A) P_tent;
+* restriction is the transpose, R = P^T, and the level operator is the Galerkin
+  product A_{l+1} = P^T A_l P;
+* the smoother is a Chebyshev polynomial in D^-1 A on an interval below an estimate
+  of the largest eigenvalue, used for both pre- and post-smoothing;
+* the coarsest level (at most ``max_coarse`` = 1000 unknowns) is solved directly;
+* the cycle is the V-cycle of Algorithm 1.
+
+Readings where the paper is silent (listed in the design doc):
+
+* aggregates are the index blocks [3I, 3I+3) x [3J, 3J+3) x [3K, 3K+3) of the level's
+  logical box; a block's unknowns form one aggregate, partial blocks are kept; the
+  coarse level's logical box has ceil(n/3) points per axis;
+* lambda_hat of D^-1 A comes from ``eig_iters`` = 15 power steps started from
+  v_i = ((i * 2654435761) mod 2^32) / 2^32 - 1/2 (i = logical box index), followed by
+  the D-weighted Rayleigh quotient u^T A u / u^T D u of the last normalised iterate;
+* omega = (4/3) / lambda_hat; the Chebyshev interval is [lambda_hi / 10, lambda_hi]
+  with lambda_hi = 1.1 * lambda_hat, degree 2;
+* the Chebyshev recurrence is the classical three-term Chebyshev acceleration
+  (Saad, Iterative Methods for Sparse Linear Systems, Alg. 12.1) preconditioned by D.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Tuple
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+
+@dataclasses.dataclass
+class Options:
+    max_coarse: int = 1000
+    max_levels: int = 10
+    cheb_degree: int = 2
+    cheb_ratio: float = 10.0
+    cheb_boost: float = 1.1
+    eig_iters: int = 15
+    omega_scale: float = 4.0 / 3.0
+
+
+@dataclasses.dataclass
+class Level:
+    A: sp.csr_matrix
+    D: np.ndarray
+    dims: Tuple[int, int, int]        # logical box of this level
+    lin: np.ndarray                    # logical box index of each unknown (ascending)
+    lam: float = 0.0
+    lam_hi: float = 0.0
+    omega: float = 0.0
+    Ptent: Optional[sp.csr_matrix] = None
+    P: Optional[sp.csr_matrix] = None
+
+    @property
+    def n(self) -> int:
+        return self.lin.size
+
+
+@dataclasses.dataclass
+class Hierarchy:
+    levels: List[Level]
+    opts: Options
+    coarse_lu: tuple = None
+
+    @property
+    def sizes(self) -> List[int]:
+        return [lv.n for lv in self.levels]
+
+
+def start_vector(lin: np.ndarray) -> np.ndarray:
+    """Deterministic power-iteration start vector (integer hash of the box index)."""
+    h = (lin.astype(np.uint64) * np.uint64(2654435761)) % np.uint64(1 << 32)
+    return h.astype(np.float64) / 4294967296.0 - 0.5
+
+
+def power_lambda(A: sp.csr_matrix, D: np.ndarray, lin: np.ndarray, iters: int) -> float:
+    """Largest-eigenvalue estimate of D^-1 A by the power method."""
+    v = start_vector(lin)
+    u = v
+    w = v
+    for _ in range(iters):
+        u = v / np.linalg.norm(v)
+        w = (A @ u) / D
+        v = w
+    return float(np.dot(u, D * w) / np.dot(u, D * u))
+
+
+def aggregate(lin: np.ndarray, dims: Tuple[int, int, int]):
+    """Aggregate id of each unknown, the coarse unknowns' logical indices and box."""
+    mx, my, mz = dims
+    X = lin % mx
+    Y = (lin // mx) % my
+    Z = lin // (mx * my)
+    cdims = (-(-mx // 3), -(-my // 3), -(-mz // 3))
+    clin = X // 3 + cdims[0] * (Y // 3 + cdims[1] * (Z // 3))
+    coarse, agg = np.unique(clin, return_inverse=True)
+    return agg.astype(np.int64), coarse.astype(np.int64), cdims
+
+
+def tentative_prolongator(agg: np.ndarray, nc: int) -> sp.csr_matrix:
+    n = agg.size
+    return sp.csr_matrix((np.ones(n), (np.arange(n), agg)), shape=(n, nc))
+
+
+def chebyshev(lv: Level, f: np.ndarray, x: Optional[np.ndarray], degree: int,
+              ratio: float) -> np.ndarray:
+    """Chebyshev smoothing of A x = f on [lam_hi/ratio, lam_hi], preconditioned by D.
+
+    ``x is None`` means a zero initial guess (the pre-smoother of Algorithm 1).
+    """
+    hi = lv.lam_hi
+    lo = hi / ratio
+    theta = 0.5 * (hi + lo)
+    delta = 0.5 * (hi - lo)
+    sigma1 = theta / delta
+    rho = 1.0 / sigma1
+    if x is None:
+        x = np.zeros_like(f)
+        r = f.copy()
+    else:
+        r = f - lv.A @ x
+    d = r / lv.D / theta
+    x = x + d
+    for _ in range(1, degree):
+        r = f - lv.A @ x
+        rho_new = 1.0 / (2.0 * sigma1 - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * (r / lv.D)
+        rho = rho_new
+        x = x + d
+    return x
+
+
+def setup(A0: sp.csr_matrix, dims0: Tuple[int, int, int], lin0: np.ndarray,
+          opts: Optional[Options] = None) -> Hierarchy:
+    """Build the level hierarchy, coarsening until a level has at most max_coarse unknowns."""
+    opts = opts or Options()
+    A = A0.tocsr()
+    levels = [Level(A, A.diagonal().copy(), dims0, lin0)]
+    while levels[-1].n > opts.max_coarse and len(levels) < opts.max_levels:
+        lv = levels[-1]
+        agg, clin, cdims = aggregate(lv.lin, lv.dims)
+        if clin.size >= lv.n:
+            break
+        lv.lam = power_lambda(lv.A, lv.D, lv.lin, opts.eig_iters)
+        lv.lam_hi = opts.cheb_boost * lv.lam
+        lv.omega = opts.omega_scale / lv.lam
+        lv.Ptent = tentative_prolongator(agg, clin.size)
+        Dinv = sp.diags(1.0 / lv.D)
+        lv.P = (lv.Ptent - lv.omega * (Dinv @ (lv.A @ lv.Ptent))).tocsr()
+        Ac = (lv.P.T @ (lv.A @ lv.P)).tocsr()
+        Ac.sort_indices()
+        levels.append(Level(Ac, Ac.diagonal().copy(), cdims, clin))
+    H = Hierarchy(levels, opts)
+    H.coarse_lu = sla.lu_factor(levels[-1].A.toarray())
+    return H
+
+
+def coarse_solve(H: Hierarchy, b: np.ndarray) -> np.ndarray:
+    return sla.lu_solve(H.coarse_lu, b)
+
+
+def vcycle(H: Hierarchy, b: np.ndarray, level: int = 0) -> np.ndarray:
+    """Algorithm 1 (MultiGridSolve) with a zero initial guess on the given level."""
+    if level == len(H.levels) - 1:
+        return coarse_solve(H, b)
+    lv = H.levels[level]
+    o = H.opts
+    x = chebyshev(lv, b, None, o.cheb_degree, o.cheb_ratio)          # pre-smoothing
+    r = b - lv.A @ x                                                   # residual
+    bc = lv.P.T @ r                                                    # restriction R = P^T
+    v = vcycle(H, bc, level + 1)                                       # coarse problem
+    x = x + lv.P @ v                                                   # coarse-grid correction
+    return chebyshev(lv, b, x, o.cheb_degree, o.cheb_ratio)           # post-smoothing
+
+
+def coarse_box_coords(lv: Level) -> np.ndarray:
+    """(n, 3) logical (X, Y, Z) coordinates of a level's unknowns."""
+    mx, my, _ = lv.dims
+    return np.stack([lv.lin % mx, (lv.lin // mx) % my, lv.lin // (mx * my)], axis=1)

@@ -1,0 +1,145 @@
+"""Finite-difference Poisson matrix on the masked lattice (oracle).
+
+Paper, Section 2.  At an unknown x every axis i contributes the 1-D difference
+(-u(x - h e_i) + 2 u(x) - u(x + h e_i)) / h_i^2 (eq. 7pt-star).  When a neighbour lies
+outside the domain, its value is replaced by an extrapolation through the wall point
+at fraction s (homogeneous wall data, g = 0):
+
+* constant (eq. const_extrapol):  u(x') = 0;
+* linear   (eq. lin_extrapol):    u(x') = (1 - 1/s) u(x);
+* quadratic, other neighbour x'' inside (eq. quad_extrapol):
+      u(x') = 2(s - 1)/s u(x) - (s - 1)/(s + 1) u(x'');
+* quadratic, both neighbours outside with fractions s and t (eq. quad_extrapol1):
+      u(x') = (s - 1)(t + 1)/(s t) u(x),   u(x'') = (s + 1)(t - 1)/(s t) u(x).
+
+Each axis is handled on its own and the contributions add up (the paper applies the
+rules in every direction in which the point is near the wall).  The substitution is
+carried out literally below, term by term, so that a reader can match it against the
+equations; the resulting per-axis rows are what the tests pin against closed forms.
+
+Scaling (end of Section 2): with D = diag(A) the system A x = b is replaced by
+(D^-1/2 A D^-1/2) y = D^-1/2 b, x = D^-1/2 y.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Tuple
+
+import numpy as np
+import scipy.sparse as sp
+
+from .grid import Domain
+
+CONST, LIN, QUAD = 0, 1, 2
+
+
+@dataclasses.dataclass
+class System:
+    """Assembled system over the unknowns of a domain, in box-lexicographic order."""
+
+    dom: Domain
+    variant: int
+    A: sp.csr_matrix          # unscaled matrix
+    idx: np.ndarray           # box-linear index of each unknown
+    sigma: np.ndarray         # D^-1/2
+    As: sp.csr_matrix         # scaled matrix D^-1/2 A D^-1/2
+
+    @property
+    def n(self) -> int:
+        return self.idx.size
+
+    def gather(self, box: np.ndarray) -> np.ndarray:
+        return np.asarray(box, dtype=np.float64).reshape(-1)[self.idx]
+
+    def scatter(self, v: np.ndarray) -> np.ndarray:
+        out = np.zeros(self.dom.nx * self.dom.ny * self.dom.nz)
+        out[self.idx] = v
+        return out.reshape(self.dom.nz, self.dom.ny, self.dom.nx)
+
+
+def _axis_terms(variant: int, in_m: np.ndarray, in_p: np.ndarray, s_m: np.ndarray,
+                s_p: np.ndarray) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Coefficients (times h^2) of u(x), u(x - h e) and u(x + h e) for one axis.
+
+    Start from -u(x-) + 2 u(x) - u(x+) and substitute every outside neighbour by its
+    extrapolation; the returned neighbour coefficients are zero for outside neighbours.
+    """
+    c_self = np.full(in_m.shape, 2.0)
+    c_m = np.where(in_m, -1.0, 0.0)
+    c_p = np.where(in_p, -1.0, 0.0)
+    out_m, out_p = ~in_m, ~in_p
+    if variant == CONST:
+        # u(x') = g = 0: the outside term simply disappears.
+        return c_self, c_m, c_p
+    if variant == LIN:
+        # -u(x') = -(1 - 1/s) u(x), for each outside side independently.
+        c_self = c_self - np.where(out_m, 1.0 - 1.0 / s_m, 0.0)
+        c_self = c_self - np.where(out_p, 1.0 - 1.0 / s_p, 0.0)
+        return c_self, c_m, c_p
+    if variant != QUAD:
+        raise ValueError(variant)
+    one_m = out_m & in_p
+    one_p = out_p & in_m
+    both = out_m & out_p
+    # One side outside: -u(x') = -2(s-1)/s u(x) + (s-1)/(s+1) u(x'').
+    c_self = c_self - np.where(one_m, 2.0 * (s_m - 1.0) / s_m, 0.0)
+    c_p = c_p + np.where(one_m, (s_m - 1.0) / (s_m + 1.0), 0.0)
+    c_self = c_self - np.where(one_p, 2.0 * (s_p - 1.0) / s_p, 0.0)
+    c_m = c_m + np.where(one_p, (s_p - 1.0) / (s_p + 1.0), 0.0)
+    # Both outside (s on the minus side, t on the plus side).
+    s, t = s_m, s_p
+    c_self = c_self - np.where(both, (s - 1.0) * (t + 1.0) / (s * t), 0.0)
+    c_self = c_self - np.where(both, (s + 1.0) * (t - 1.0) / (s * t), 0.0)
+    return c_self, c_m, c_p
+
+
+def assemble(dom: Domain, variant: int) -> System:
+    """Unscaled and scaled matrices of the discrete Poisson problem."""
+    nx, ny, nz = dom.nx, dom.ny, dom.nz
+    mask = dom.mask
+    ks, js, is_ = np.nonzero(mask)
+    idx = (is_ + nx * (js + ny * ks)).astype(np.int64)
+    n = idx.size
+    compact = np.full(nx * ny * nz, -1, dtype=np.int64)
+    compact[idx] = np.arange(n)
+    rows, cols, vals = [np.arange(n)], [np.arange(n)], []
+    diag = np.zeros(n)
+    for axis in range(3):
+        d_m, d_p = 2 * axis, 2 * axis + 1
+        step = [0, 0, 0]
+        step[axis] = 1
+        dz, dy, dx = step[2], step[1], step[0]
+        in_m = mask[ks - dz, js - dy, is_ - dx]
+        in_p = mask[ks + dz, js + dy, is_ + dx]
+        s_m = dom.frac[d_m, ks, js, is_]
+        s_p = dom.frac[d_p, ks, js, is_]
+        c_self, c_m, c_p = _axis_terms(variant, in_m, in_p, s_m, s_p)
+        inv_h2 = 1.0 / (dom.h[axis] * dom.h[axis])
+        diag += c_self * inv_h2
+        lin_step = dx + nx * (dy + ny * dz)
+        for c, sgn, inside in ((c_m, -1, in_m), (c_p, 1, in_p)):
+            sel = np.nonzero(inside)[0]
+            rows.append(sel)
+            cols.append(compact[idx[sel] + sgn * lin_step])
+            vals.append(c[sel] * inv_h2)
+    vals.insert(0, diag)
+    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n))
+    A.sum_duplicates()
+    A.eliminate_zeros()
+    D = A.diagonal()
+    sigma = 1.0 / np.sqrt(D)
+    S = sp.diags(sigma)
+    As = (S @ A @ S).tocsr()
+    As.sort_indices()
+    return System(dom, variant, A, idx, sigma, As)
+
+
+def scaled_rhs(sys_: System, b_box: np.ndarray) -> np.ndarray:
+    """D^-1/2 b over the unknowns."""
+    return sys_.sigma * sys_.gather(b_box)
+
+
+def unscale(sys_: System, y: np.ndarray) -> np.ndarray:
+    """x = D^-1/2 y over the unknowns."""
+    return sys_.sigma * y

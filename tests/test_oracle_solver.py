@@ -1,0 +1,210 @@
+"""Pins of the oracle's AMG hierarchy, smoother, V-cycle and PCG (CPU).
+
+Each test checks the oracle against something fixed outside it: closed-form spectra of
+the box Laplacian, Chebyshev polynomials, the algebra of Galerkin coarse spaces, an
+independent CG implementation, or a dense direct solve.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from oracle import amg, grid, operator, pcg, solve
+
+
+def _box_system(n=(11, 9, 13), variant=operator.LIN):
+    """Rectangular box domain: every wall fraction is 1, Dirichlet Laplacian."""
+    nx, ny, nz = n
+    # a box cavity longer than the pipe: the domain is the whole box interior
+    shape = W.Shape(W.BOXBORE, 1.0, 0.7, 2.0, 0.1, 2.0)
+    dom = grid.from_shape(shape, nx, ny, nz)
+    assert np.all(dom.frac == 1.0)
+    assert dom.n_unknowns == (nx - 2) * (ny - 2) * (nz - 2)
+    return dom, operator.assemble(dom, variant)
+
+
+def _box_mode(dom, kx, ky, kz):
+    nx, ny, nz = dom.nx, dom.ny, dom.nz
+    i = np.arange(nx)
+    j = np.arange(ny)
+    k = np.arange(nz)
+    v = (np.sin(np.pi * kz * k / (nz - 1))[:, None, None]
+         * np.sin(np.pi * ky * j / (ny - 1))[None, :, None]
+         * np.sin(np.pi * kx * i / (nx - 1))[None, None, :])
+    lam = sum(2.0 / h ** 2 * (1.0 - np.cos(np.pi * kk / (nn - 1)))
+              for h, kk, nn in zip(dom.h, (kx, ky, kz), (nx, ny, nz)))
+    return v, lam
+
+
+def test_box_eigenvector_closed_form():
+    dom, s = _box_system()
+    v, lam = _box_mode(dom, 2, 3, 1)
+    vv = s.gather(v)
+    assert np.allclose(s.A @ vv, lam * vv, rtol=0, atol=1e-10 * lam)
+
+
+def test_power_estimate_below_exact_lambda_max():
+    """Rayleigh quotient of a symmetric D^-1 A never exceeds lambda_max (box: closed form)."""
+    dom, s = _box_system((15, 13, 17))
+    D0 = s.A.diagonal()[0]
+    lam_max = sum(2.0 / h ** 2 * (1.0 + np.cos(np.pi / (n - 1)))
+                  for h, n in zip(dom.h, (dom.nx, dom.ny, dom.nz))) / D0
+    est = amg.power_lambda(s.A, s.A.diagonal(), s.idx, 15)
+    assert est <= lam_max * (1 + 1e-12)
+    assert est > 0.85 * lam_max
+    assert amg.power_lambda(s.A, s.A.diagonal(), s.idx, 200) > 0.995 * lam_max
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3])
+def test_chebyshev_error_polynomial(degree):
+    """On an eigenvector of D^-1 A the smoother's error is T_m((theta - mu)/delta) / T_m(theta/delta)."""
+    dom, s = _box_system()
+    D = s.A.diagonal()
+    lv = amg.Level(s.A, D, (dom.nx, dom.ny, dom.nz), s.idx)
+    lv.lam_hi = 2.05
+    ratio = 30.0
+    lo = lv.lam_hi / ratio
+    theta, delta = 0.5 * (lv.lam_hi + lo), 0.5 * (lv.lam_hi - lo)
+    for mode in ((1, 1, 1), (3, 2, 5), (8, 6, 10)):
+        v, lam = _box_mode(dom, *mode)
+        e0 = s.gather(v)
+        mu = lam / D[0]
+        # solve A x = 0 from x0 = e0: the iterate is the propagated error
+        e = amg.chebyshev(lv, np.zeros_like(e0), e0, degree, ratio)
+        T = np.polynomial.chebyshev.Chebyshev.basis(degree)
+        want = T((theta - mu) / delta) / T(theta / delta)
+        assert np.allclose(e, want * e0, atol=1e-12 * np.abs(e0).max())
+
+
+def test_zero_guess_chebyshev_equals_nonzero_form():
+    dom, s = _box_system()
+    lv = amg.Level(s.A, s.A.diagonal(), (dom.nx, dom.ny, dom.nz), s.idx)
+    lv.lam_hi = 2.0
+    f = s.gather(W.random_box_vector((dom.nx, dom.ny, dom.nz), 1))
+    a = amg.chebyshev(lv, f, None, 2, 30.0)
+    b = amg.chebyshev(lv, f, np.zeros_like(f), 2, 30.0)
+    assert np.allclose(a, b, rtol=1e-14, atol=1e-14)
+
+
+def _c1_hier(variant=operator.LIN):
+    w = W.c1_cylinder33()
+    return solve.build(w.shape, 33, 33, 33, variant)
+
+
+def test_cylinder33_three_levels():
+    """Table 1's coarse-size limit of 1000 gives three levels on the 33^3 cylinder."""
+    _, H = _c1_hier()
+    assert H.sizes == [24583, 1111, 64]
+
+
+def test_aggregates_are_3_cubes():
+    _, H = _c1_hier()
+    lv = H.levels[0]
+    cols = lv.Ptent.tocsr().indices
+    fine = amg.coarse_box_coords(lv)
+    coarse = amg.coarse_box_coords(H.levels[1])
+    assert np.array_equal(fine // 3, coarse[cols])
+    counts = np.bincount(cols)
+    assert counts.max() == 27 and counts.min() >= 1
+
+
+@pytest.mark.parametrize("variant", [operator.LIN, operator.QUAD])
+def test_coarse_operators_are_27_point(variant):
+    _, H = _c1_hier(variant)
+    for l in (1, 2):
+        lv = H.levels[l]
+        c = amg.coarse_box_coords(lv)
+        A = lv.A.tocoo()
+        d = np.abs(c[A.row] - c[A.col]).max(axis=1)
+        assert d.max() == 1
+        assert np.all(lv.A.diagonal() > 0)
+
+
+def test_galerkin_two_level_projection():
+    """E = I - P (P^T A P)^-1 P^T A is an A-orthogonal projector: E^2 = E, P^T A E = 0."""
+    s, H = solve.build(W.Shape.cylinder(1.0, 2.0), 13, 13, 13, operator.LIN,
+                       amg.Options(max_coarse=10))
+    lv = H.levels[0]
+    A = lv.A.toarray()
+    P = lv.P.toarray()
+    Ac = H.levels[1].A.toarray()
+    E = np.eye(A.shape[0]) - P @ np.linalg.solve(Ac, P.T @ A)
+    assert np.abs(E @ E - E).max() < 1e-10
+    assert np.abs(P.T @ A @ E).max() < 1e-10
+    assert np.abs(A @ E - (A @ E).T).max() < 1e-10
+
+
+def test_vcycle_symmetric_positive_for_linear_rule():
+    s, H = _c1_hier(operator.LIN)
+    rng = np.random.default_rng(0)
+    u, w = rng.standard_normal((2, s.n))
+    Mu, Mw = amg.vcycle(H, u), amg.vcycle(H, w)
+    assert abs(u @ Mw - w @ Mu) < 1e-12 * abs(u @ Mw)
+    assert u @ Mu > 0 and w @ Mw > 0
+
+
+def test_vcycle_is_linear():
+    s, H = _c1_hier(operator.QUAD)
+    rng = np.random.default_rng(1)
+    u, w = rng.standard_normal((2, s.n))
+    lhs = amg.vcycle(H, 2.0 * u - 3.0 * w)
+    rhs = 2.0 * amg.vcycle(H, u) - 3.0 * amg.vcycle(H, w)
+    assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-12 * np.abs(rhs).max())
+
+
+def test_cg_without_preconditioner_matches_scipy():
+    s, _ = _c1_hier(operator.LIN)
+    b = s.sigma * s.gather(W.rhs(W.c1_cylinder33()))
+    res = pcg.pcg(s.As, b, lambda r: r, tol=1e-10, max_iter=2000)
+    x_sp, info = spla.cg(s.As, b, rtol=1e-12, maxiter=5000)
+    assert res.status == pcg.OK and info == 0
+    assert np.linalg.norm(res.x - x_sp) / np.linalg.norm(x_sp) < 1e-8
+
+
+@pytest.mark.parametrize("variant", [operator.LIN, operator.QUAD, operator.CONST])
+def test_pcg_matches_dense_direct_solve(variant):
+    shape = W.Shape.ellipse(1.0, 0.6, 2.0)
+    wl = W.small(shape, 21, 17, 19, variant)
+    s, H = solve.build(shape, 21, 17, 19, variant, amg.Options(max_coarse=100))
+    assert len(H.levels) >= 2
+    b = W.rhs(wl)
+    res = solve.solve(s, H, b, tol=1e-12)
+    xd = np.linalg.solve(s.A.toarray(), s.gather(b))
+    x = operator.unscale(s, res.x)
+    assert res.status == pcg.OK
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-9
+
+
+def test_pcg_box_sine_mode_closed_form():
+    """Right-hand side = one eigenvector of the box Laplacian: x = b / lambda."""
+    dom, s = _box_system((17, 15, 13))
+    v, lam = _box_mode(dom, 1, 2, 1)
+    H = amg.setup(s.As, (dom.nx, dom.ny, dom.nz), s.idx, amg.Options(max_coarse=50))
+    res = solve.solve(s, H, v, tol=1e-12)
+    x = operator.unscale(s, res.x)
+    assert np.linalg.norm(x - s.gather(v) / lam) < 1e-9 * np.linalg.norm(s.gather(v) / lam)
+
+
+def test_pcg_special_cases():
+    s, H = _c1_hier(operator.LIN)
+    zero = np.zeros((33, 33, 33))
+    r0 = solve.solve(s, H, zero)
+    assert r0.iterations == 0 and np.all(r0.x == 0)
+    b = W.rhs(W.c1_cylinder33())
+    full = solve.solve(s, H, b)
+    x_box = s.scatter(operator.unscale(s, full.x))
+    again = solve.solve(s, H, b, x0_box=x_box)
+    assert again.iterations == 0
+    near = solve.solve(s, H, b, x0_box=x_box * (1 + 1e-5))
+    assert 0 < near.iterations < full.iterations
+    one = solve.solve(s, H, b, max_iter=1)
+    assert one.status == pcg.NOT_CONVERGED and one.iterations == 1
+
+
+def test_scaling_leaves_unscaled_solution_unchanged():
+    s, H = _c1_hier(operator.QUAD)
+    b = W.rhs(W.c1_cylinder33())
+    res = solve.solve(s, H, b, tol=1e-12)
+    x = operator.unscale(s, res.x)
+    r = s.gather(b) - s.A @ x
+    assert np.linalg.norm(r) < 1e-9 * np.linalg.norm(s.gather(b))
