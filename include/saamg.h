@@ -1,0 +1,220 @@
+/*
+ * saamg.h - C interface of the MI355X (gfx950) SA-AMG preconditioned CG Poisson solver.
+ *
+ * The library solves the finite-difference Poisson problem  -Laplace(phi) = rho  on a
+ * beam-pipe domain embedded in a regular lattice, with phi = 0 on the wall
+ * (Adelmann, Arbenz, Ineichen, "A fast parallel Poisson solver on irregular domains
+ * applied to beam dynamics simulations"):
+ *
+ *   - Section 2: 7-point star (eq. 7pt-star); at the curved wall an outside neighbour is
+ *     replaced by constant (eq. const_extrapol), linear (eq. lin_extrapol) or quadratic
+ *     (eqs. quad_extrapol, quad_extrapol1) extrapolation; the system is scaled to unit
+ *     diagonal by D^-1/2 A D^-1/2.
+ *   - Section 3.1: conjugate gradients, also for the mildly nonsymmetric quadratic rule.
+ *   - Section 3.2 / Table 1: smoothed-aggregation AMG V-cycle (Algorithm 1) as the
+ *     preconditioner; 3^3 cube aggregates, damped-Jacobi prolongator smoothing,
+ *     R = P^T, Chebyshev pre- and post-smoothing, direct solve on the coarsest level
+ *     (at most 1000 unknowns).
+ *   - Section 5 (solver comparison): stop when ||r||_2 <= tol ||b||_2.
+ *
+ * All solve-time work runs in HIP kernels on the GPU.  Every entry point returns a
+ * status code (saamg_status); no C++ exception crosses this interface.  The message
+ * of the last failure on the calling thread is available from saamg_last_error().
+ *
+ * Layout conventions
+ *   A "box vector" is an array of nx*ny*nz values, x fastest, then y, then z
+ *   (C order (nz, ny, nx)).  Entries at nodes that are not unknowns are ignored on
+ *   input and written as 0 on output.
+ *   Device pointers must point to memory of the device that was current when
+ *   saamg_setup ran; streams are hipStream_t values passed as void* (NULL = the
+ *   default stream of that device).
+ */
+#ifndef SAAMG_H
+#define SAAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SAAMG_OK = 0,
+    SAAMG_INVALID_ARG = 1,   /* bad size, pointer, domain or option */
+    SAAMG_NOMEM = 2,         /* a device or host allocation failed */
+    SAAMG_HIP_ERROR = 3,     /* a HIP runtime call failed */
+    SAAMG_NOT_CONVERGED = 4, /* max_iter reached; x holds the last iterate */
+    SAAMG_BREAKDOWN = 5,     /* p.Ap <= 0 or r.z <= 0; x holds the last iterate */
+    SAAMG_NONFINITE = 6      /* NaN or Inf met in the iteration; x holds the last iterate */
+} saamg_status;
+
+/* Wall rule at the curved boundary (Section 2). */
+enum { SAAMG_VARIANT_CONST = 0, SAAMG_VARIANT_LIN = 1, SAAMG_VARIANT_QUAD = 2 };
+/* Precision policy: all fp64, or fp32 hierarchy / V-cycle with fp64 outer CG,
+ * dot products, true residual and coarse direct solve. */
+enum { SAAMG_FP64 = 0, SAAMG_MIXED = 1 };
+/* Analytic pipe shapes for saamg_domain_from_shape. */
+enum { SAAMG_SHAPE_CYLINDER = 0, SAAMG_SHAPE_ELLIPSE = 1, SAAMG_SHAPE_BOXBORE = 2 };
+
+/*
+ * Discrete domain (Section 2, lattice Omega_h and Figure "boundary").
+ *   mask       host, nx*ny*nz bytes, nonzero = the node is an unknown.  No unknown may
+ *              lie on a face of the box.
+ *   wall_*     host, n_wall entries: for an unknown node (box-linear index wall_node)
+ *              whose neighbour in direction wall_dir (0..5 = -x,+x,-y,+y,-z,+z) is not
+ *              an unknown, the wall sits at fraction wall_s in (0, 1] of the spacing.
+ *              An outside neighbour without an entry means s = 1 (the neighbour is on
+ *              the wall).  Entries may come in any order; duplicates are an error.
+ * The library copies what it needs; the caller keeps ownership.
+ */
+typedef struct {
+    int32_t nx, ny, nz;
+    double hx, hy, hz;
+    const uint8_t* mask;
+    int64_t n_wall;
+    const int64_t* wall_node;
+    const uint8_t* wall_dir;
+    const double* wall_s;
+} saamg_domain;
+
+/* Preconditioner and solver options; saamg_default_options fills the defaults. */
+typedef struct {
+    int32_t precision;     /* SAAMG_FP64 or SAAMG_MIXED                        default FP64 */
+    int32_t max_levels;    /* hierarchy depth limit                            default 10   */
+    int32_t max_coarse;    /* stop coarsening at <= this many unknowns (Table 1) default 1000 */
+    int32_t cheb_degree;   /* Chebyshev polynomial degree, 1..8                default 2    */
+    double cheb_ratio;     /* smoothing interval [lambda_hi/ratio, lambda_hi]  default 10   */
+    double cheb_boost;     /* lambda_hi = boost * power-method estimate        default 1.1  */
+    int32_t eig_iters;     /* power-method steps per level                     default 15   */
+    double omega_scale;    /* prolongator damping omega = scale / lambda_est   default 4/3  */
+} saamg_options;
+
+/* Outcome of one solve. rel_res_* are ||r||/||b|| of the scaled system. */
+typedef struct {
+    int32_t iterations;        /* products with A inside the CG loop */
+    int32_t status;            /* saamg_status */
+    int32_t replacements;      /* true-residual replacements */
+    double rel_res_true;       /* from b - A x recomputed in fp64 at exit */
+    double rel_res_recursive;  /* from the recursively updated residual */
+    double t_solve_ms;         /* host wall time of the solve call */
+} saamg_result;
+
+/* Shape of a built hierarchy (for reporting and tests). */
+#define SAAMG_MAX_LEVELS 16
+typedef struct {
+    int32_t n_levels;
+    int32_t variant;
+    int32_t precision;
+    int32_t dims[SAAMG_MAX_LEVELS][3];    /* logical box of each level (level 0 = lattice) */
+    int64_t n_unknowns[SAAMG_MAX_LEVELS];
+    double lambda_est[SAAMG_MAX_LEVELS];  /* power-method estimate of lambda_max(D^-1 A) */
+    double omega[SAAMG_MAX_LEVELS];
+    int64_t n_irregular;                  /* level-0 rows with a non-constant stencil */
+    int64_t device_bytes;                 /* device memory held by the hierarchy */
+    double t_setup_ms;
+} saamg_info;
+
+typedef struct saamg_hierarchy saamg_hierarchy;
+typedef struct saamg_state saamg_state;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* saamg_last_error(void);
+
+void saamg_default_options(saamg_options* opt);
+
+/*
+ * Build the discrete domain of an analytic pipe on a lattice spanning its bounding box
+ * (Section 4, irregular domains: grid / wall intersections from the implicit surface).
+ *   kind          SAAMG_SHAPE_*; a, b: half-extents of the box along x and y (radius,
+ *                 semi-axes, or cavity half-width); length: extent along z; bore_r and
+ *                 cavity_half_len: BOXBORE only (ignored otherwise).
+ *   mask_out      host, nx*ny*nz bytes, written.
+ *   wall_cap      capacity of the three wall_* output arrays (host); may be 0 to query.
+ *   n_wall_out    number of entries with s < 1; if it exceeds wall_cap nothing is
+ *                 written to the wall arrays and SAAMG_INVALID_ARG is returned.
+ * Node coordinates are a*(2i-(n-1))/(n-1) per axis; unknowns lie strictly inside.
+ */
+int saamg_domain_from_shape(int kind, double a, double b, double length, double bore_r,
+                            double cavity_half_len, int nx, int ny, int nz, uint8_t* mask_out,
+                            int64_t wall_cap, int64_t* wall_node, uint8_t* wall_dir,
+                            double* wall_s, int64_t* n_wall_out);
+
+/*
+ * Build the scaled operator and the SA-AMG hierarchy on the current device.
+ *   variant   SAAMG_VARIANT_*; opt may be NULL (defaults).  Work is queued on stream;
+ *   the call returns after the hierarchy is complete.  *out owns all device memory of
+ *   the hierarchy until saamg_destroy.
+ */
+int saamg_setup(const saamg_domain* dom, int variant, const saamg_options* opt, void* stream,
+                saamg_hierarchy** out);
+
+/*
+ * Solve A x = b with PCG + one V-cycle per step.
+ *   d_b    device, box vector of rho (unscaled right-hand side), fp64.
+ *   d_x0   device box vector of the initial guess (unscaled), fp64, or NULL for 0.
+ *   d_x    device box vector, fp64, receives the solution (may alias d_x0).
+ *   tol    relative residual of the scaled system; max_iter >= 0.
+ * Returns after completion; res (nullable) receives the outcome.  Status 4..6 still
+ * write the last iterate to d_x.
+ */
+int saamg_solve(saamg_hierarchy* H, const double* d_b, const double* d_x0, double* d_x,
+                double tol, int max_iter, void* stream, saamg_result* res);
+
+/* Free the hierarchy (NULL is accepted). */
+int saamg_destroy(saamg_hierarchy* H);
+
+int saamg_hierarchy_info(const saamg_hierarchy* H, saamg_info* info);
+
+/*
+ * Device bytes a hierarchy and one solve state would take for a box of the given size
+ * (upper bounds from the box, used for admission control).
+ */
+int saamg_footprint_bytes(int nx, int ny, int nz, int variant, int precision,
+                          int64_t* hier_bytes, int64_t* state_bytes);
+
+/* ---- incremental solves (continuous batching) --------------------------------------
+ * A state owns the CG vectors of one solve.  saamg_batch_step advances every state that
+ * is not finished by exactly one PCG step (or finishes it); states may belong to
+ * different hierarchies.  Each state's work is queued on its own stream, so steps of
+ * different states overlap on the device.  A state's iterates are identical to those of
+ * saamg_solve on the same inputs.
+ */
+int saamg_state_create(saamg_hierarchy* H, const double* d_b, const double* d_x0, double tol,
+                       int max_iter, void* stream, saamg_state** out);
+/* n states; *n_done_out (nullable) receives how many are finished after the step. */
+int saamg_batch_step(saamg_state* const* states, int n, int* n_done_out);
+/* done = 1 when the state has finished (any status); res as for saamg_solve. */
+int saamg_state_query(const saamg_state* S, int* done, saamg_result* res);
+/* Write the (unscaled) current iterate to the device box vector d_x. */
+int saamg_state_finish(saamg_state* S, double* d_x);
+int saamg_state_destroy(saamg_state* S);
+
+/* ---- component entry points (parity tests and diagnostics) ------------------------
+ * Host-pointer, fp64, logical-box-layout access to single steps of the method.  Level
+ * l vectors are (mz, my, mx) arrays of the level's logical box (info.dims[l]).  The
+ * precision argument selects the fp64 data or, for a MIXED hierarchy, its fp32 copy.
+ */
+enum {
+    SAAMG_OP_APPLY = 0,     /* out = A_l in                                  */
+    SAAMG_OP_APPLY_T = 1,   /* out = A_l^T in                                */
+    SAAMG_OP_PRESMOOTH = 2, /* out = Chebyshev smoother from 0 with rhs in   */
+    SAAMG_OP_RESTRICT = 3,  /* out (level l+1) = P_l^T in (level l)          */
+    SAAMG_OP_PROLONG = 4    /* out (level l) = P_l in (level l+1)            */
+};
+int saamg_level_apply(saamg_hierarchy* H, int level, int op, int precision, const double* h_in,
+                      double* h_out);
+/* Coefficients A_l(I, I+o) as [27][mz][my][mx] fp64 (o = (dx,dy,dz), index
+ * (dx+1) + 3(dy+1) + 9(dz+1)); for level 0 the scaled operator. */
+int saamg_level_coefficients(saamg_hierarchy* H, int level, double* h_out);
+/* One V-cycle z = M^-1 r on device box vectors of the scaled level-0 system (fp64). */
+int saamg_precond_apply(saamg_hierarchy* H, const double* d_r, double* d_z, void* stream);
+/* Scaled operator y = D^-1/2 A D^-1/2 x on device box vectors (fp64). */
+int saamg_operator_apply(saamg_hierarchy* H, const double* d_x, double* d_y, void* stream);
+/* D^-1/2 as a device box vector (0 at non-unknowns), fp64. */
+int saamg_scaling(saamg_hierarchy* H, double* d_sigma, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SAAMG_H */

@@ -1,0 +1,686 @@
+// Kernels of levels >= 1 (27-point Galerkin operators on ghost-padded boxes), the
+// structured Galerkin product that builds them, and the dense coarsest-level solve.
+#include "launch.h"
+
+namespace saamg {
+
+// Coefficient A(i, k) of a 27-point level.
+template <typename T, bool SYM>
+__device__ inline T lc_a(const LCView<T>& c, long i, int k) {
+    if (SYM && k < 13) return c.coef[26 - k][i + c.off[k]];
+    return c.coef[k][i];
+}
+// Coefficient of the transpose: A^T(i, k) = A(i + off(k), 26 - k).
+template <typename T, bool SYM>
+__device__ inline T lc_at(const LCView<T>& c, long i, int k) {
+    if (SYM) return lc_a<T, true>(c, i, k);
+    return c.coef[26 - k][i + c.off[k]];
+}
+
+template <typename T, bool SYM, bool TR, class F>
+__device__ inline T lc_stencil(const LCView<T>& c, long i, F X) {
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < 27; ++k) {
+        const T a = TR ? lc_at<T, SYM>(c, i, k) : lc_a<T, SYM>(c, i, k);
+        acc += a * X(i + c.off[k]);
+    }
+    return acc;
+}
+
+static inline dim3 lc_grid(const CoarseLevel& C) {
+    return dim3((C.mx + kWave - 1) / kWave, (C.my + kBlockY - 1) / kBlockY, C.mz);
+}
+long lc_blocks(const CoarseLevel& C) {
+    dim3 g = lc_grid(C);
+    return (long)g.x * g.y * g.z;
+}
+
+#define LC_PROLOGUE                                                              \
+    const int X = blockIdx.x * kWave + threadIdx.x;                              \
+    const int Y = blockIdx.y * kBlockY + threadIdx.y;                            \
+    const int Z = blockIdx.z;                                                    \
+    const bool inb = X < c.mx && Y < c.my;                                       \
+    const long i = (X + 1) + (long)c.sx * (Y + 1) + c.sxy * (Z + 1);
+
+template <typename T, bool SYM, bool TR>
+__global__ void __launch_bounds__(kThreads) k_lc_apply(LCView<T> c, const T* __restrict__ xv,
+                                                       T* __restrict__ yv) {
+    LC_PROLOGUE
+    if (!inb) return;
+    yv[i] = lc_stencil<T, SYM, TR>(c, i, [&](long j) { return xv[j]; });
+}
+
+template <typename T>
+void lc_apply(const CoarseLevel& C, bool trans, const T* x, T* y, hipStream_t s) {
+    LCView<T> c = C.view<T>();
+    dim3 g = lc_grid(C), b(kWave, kBlockY);
+    if (C.sym)
+        hipLaunchKernelGGL((k_lc_apply<T, true, false>), g, b, 0, s, c, x, y);
+    else if (trans)
+        hipLaunchKernelGGL((k_lc_apply<T, false, true>), g, b, 0, s, c, x, y);
+    else
+        hipLaunchKernelGGL((k_lc_apply<T, false, false>), g, b, 0, s, c, x, y);
+    HIPCHECK(hipGetLastError());
+}
+template void lc_apply<double>(const CoarseLevel&, bool, const double*, double*, hipStream_t);
+template void lc_apply<float>(const CoarseLevel&, bool, const float*, float*, hipStream_t);
+
+__global__ void __launch_bounds__(kThreads) k_lc_power_start(LCView<double> c, double* w) {
+    LC_PROLOGUE
+    if (!inb) return;
+    const long lin = X + (long)c.mx * (Y + (long)c.my * Z);
+    w[i] = c.invD[i] != 0.0 ? start_value(lin) : 0.0;
+}
+
+void lc_power_start(const CoarseLevel& C, double* v, hipStream_t s) {
+    hipLaunchKernelGGL(k_lc_power_start, lc_grid(C), dim3(kWave, kBlockY), 0, s,
+                       C.view<double>(), v);
+    HIPCHECK(hipGetLastError());
+}
+
+// w = D^-1 A u, u = v * scal[S_INVN]; partials of w.w, u.(A u), u.(D u).
+template <bool SYM>
+__global__ void __launch_bounds__(kThreads) k_lc_power_step(LCView<double> c,
+                                                            const double* __restrict__ vin,
+                                                            const double* __restrict__ scal,
+                                                            double* __restrict__ w, double* part) {
+    __shared__ double lds[kThreads / kWave];
+    const double sc = scal[S_INVN];
+    LC_PROLOGUE
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (inb) {
+        const double id = c.invD[i];
+        double o = 0.0;
+        if (id != 0.0) {
+            const double au = lc_stencil<double, SYM, false>(c, i, [&](long j) { return vin[j] * sc; });
+            const double u = vin[i] * sc;
+            o = id * au;
+            a0 = o * o;
+            a1 = u * au;
+            a2 = u * u / id;
+        }
+        w[i] = o;
+    }
+    const long bid = block_linear_id(), nb = grid_blocks();
+    double s0 = block_sum(a0, lds), s1 = block_sum(a1, lds), s2 = block_sum(a2, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        part[bid] = s0;
+        part[nb + bid] = s1;
+        part[2 * nb + bid] = s2;
+    }
+}
+
+void lc_power_step(const CoarseLevel& C, const double* v, const double* scal, double* w,
+                   double* partials, hipStream_t s) {
+    if (C.sym)
+        hipLaunchKernelGGL((k_lc_power_step<true>), lc_grid(C), dim3(kWave, kBlockY), 0, s,
+                           C.view<double>(), v, scal, w, partials);
+    else
+        hipLaunchKernelGGL((k_lc_power_step<false>), lc_grid(C), dim3(kWave, kBlockY), 0, s,
+                           C.view<double>(), v, scal, w, partials);
+    HIPCHECK(hipGetLastError());
+}
+
+// Chebyshev step with D^-1 (see the level-0 version for the modes).
+template <typename T, bool SYM, int MODE>
+__global__ void __launch_bounds__(kThreads) k_lc_cheb(LCView<T> c, const T* __restrict__ f,
+                                                      const T* __restrict__ xin,
+                                                      const T* __restrict__ din,
+                                                      T* __restrict__ xout, T* __restrict__ dout,
+                                                      T c1, T c2, T c20) {
+    LC_PROLOGUE
+    if (!inb) return;
+    const T id = c.invD[i];
+    T xo = 0, dn = 0;
+    if (id != (T)0) {
+        const T fi = f[i];
+        if (MODE == CHEB_ZERO1) {
+            xo = c20 * id * fi;
+            dn = xo;
+        } else if (MODE == CHEB_ZERO2) {
+            const T ax = lc_stencil<T, SYM, false>(c, i, [&](long j) { return c20 * c.invD[j] * f[j]; });
+            const T x1 = c20 * id * fi;
+            dn = c1 * x1 + c2 * id * (fi - ax);
+            xo = x1 + dn;
+        } else {
+            const T ax = lc_stencil<T, SYM, false>(c, i, [&](long j) { return xin[j]; });
+            const T r = id * (fi - ax);
+            dn = (MODE == CHEB_FIRST) ? c20 * r : c1 * din[i] + c2 * r;
+            xo = xin[i] + dn;
+        }
+    }
+    xout[i] = xo;
+    if (dout) dout[i] = dn;
+}
+
+template <typename T>
+void lc_cheb(const CoarseLevel& C, int mode, const T* f, const T* xin, const T* din, T* xout,
+             T* dout, double c1, double c2, double c2_0, hipStream_t s) {
+    LCView<T> c = C.view<T>();
+    dim3 g = lc_grid(C), b(kWave, kBlockY);
+#define LC_CHEB(SYMV, M)                                                                       \
+    hipLaunchKernelGGL((k_lc_cheb<T, SYMV, M>), g, b, 0, s, c, f, xin, din, xout, dout, (T)c1, \
+                       (T)c2, (T)c2_0);
+#define LC_CHEB_MODES(SYMV)                                 \
+    switch (mode) {                                         \
+        case CHEB_ZERO1: LC_CHEB(SYMV, CHEB_ZERO1) break;   \
+        case CHEB_ZERO2: LC_CHEB(SYMV, CHEB_ZERO2) break;   \
+        case CHEB_FIRST: LC_CHEB(SYMV, CHEB_FIRST) break;   \
+        default: LC_CHEB(SYMV, CHEB_NEXT) break;            \
+    }
+    if (C.sym) {
+        LC_CHEB_MODES(true)
+    } else {
+        LC_CHEB_MODES(false)
+    }
+#undef LC_CHEB_MODES
+#undef LC_CHEB
+    HIPCHECK(hipGetLastError());
+}
+template void lc_cheb<double>(const CoarseLevel&, int, const double*, const double*, const double*,
+                              double*, double*, double, double, double, hipStream_t);
+template void lc_cheb<float>(const CoarseLevel&, int, const float*, const float*, const float*,
+                             float*, float*, double, double, double, hipStream_t);
+
+template <typename T, bool SYM>
+__global__ void __launch_bounds__(kThreads) k_lc_residual(LCView<T> c, const T* __restrict__ f,
+                                                          const T* __restrict__ xv,
+                                                          T* __restrict__ r) {
+    LC_PROLOGUE
+    if (!inb) return;
+    T o = 0;
+    if (c.invD[i] != (T)0) o = f[i] - lc_stencil<T, SYM, false>(c, i, [&](long j) { return xv[j]; });
+    r[i] = o;
+}
+
+template <typename T>
+void lc_residual(const CoarseLevel& C, const T* f, const T* x, T* r, hipStream_t s) {
+    if (C.sym)
+        hipLaunchKernelGGL((k_lc_residual<T, true>), lc_grid(C), dim3(kWave, kBlockY), 0, s,
+                           C.view<T>(), f, x, r);
+    else
+        hipLaunchKernelGGL((k_lc_residual<T, false>), lc_grid(C), dim3(kWave, kBlockY), 0, s,
+                           C.view<T>(), f, x, r);
+    HIPCHECK(hipGetLastError());
+}
+template void lc_residual<double>(const CoarseLevel&, const double*, const double*, double*,
+                                  hipStream_t);
+template void lc_residual<float>(const CoarseLevel&, const float*, const float*, float*,
+                                 hipStream_t);
+
+// fc(I) = sum over aggregate I of (r - w A^T D^-1 r): P^T r with P = (I - w D^-1 A) P_tent.
+template <typename T, bool SYM>
+__global__ void __launch_bounds__(kThreads) k_lc_restrict(LCView<T> f, LCView<T> c,
+                                                          const T* __restrict__ r,
+                                                          T* __restrict__ fc, T omega) {
+    const int X = blockIdx.x * kWave + threadIdx.x;
+    const int Y = blockIdx.y * kBlockY + threadIdx.y;
+    const int Z = blockIdx.z;
+    if (X >= c.mx || Y >= c.my) return;
+    T acc = 0;
+    for (int dz = 0; dz < 3; ++dz) {
+        const int z = 3 * Z + dz;
+        if (z >= f.mz) break;
+        for (int dy = 0; dy < 3; ++dy) {
+            const int y = 3 * Y + dy;
+            if (y >= f.my) break;
+            for (int dx = 0; dx < 3; ++dx) {
+                const int x = 3 * X + dx;
+                if (x >= f.mx) break;
+                const long m = (x + 1) + (long)f.sx * (y + 1) + f.sxy * (z + 1);
+                const T atr = lc_stencil<T, SYM, true>(f, m, [&](long j) { return f.invD[j] * r[j]; });
+                acc += r[m] - omega * atr;
+            }
+        }
+    }
+    fc[(X + 1) + (long)c.sx * (Y + 1) + c.sxy * (Z + 1)] = acc;
+}
+
+template <typename T>
+void lc_restrict(const CoarseLevel& F, const CoarseLevel& C, const T* r, T* fc, double omega,
+                 hipStream_t s) {
+    if (F.sym)
+        hipLaunchKernelGGL((k_lc_restrict<T, true>), lc_grid(C), dim3(kWave, kBlockY), 0, s,
+                           F.view<T>(), C.view<T>(), r, fc, (T)omega);
+    else
+        hipLaunchKernelGGL((k_lc_restrict<T, false>), lc_grid(C), dim3(kWave, kBlockY), 0, s,
+                           F.view<T>(), C.view<T>(), r, fc, (T)omega);
+    HIPCHECK(hipGetLastError());
+}
+template void lc_restrict<double>(const CoarseLevel&, const CoarseLevel&, const double*, double*,
+                                  double, hipStream_t);
+template void lc_restrict<float>(const CoarseLevel&, const CoarseLevel&, const float*, float*,
+                                 double, hipStream_t);
+
+// x += P v = P_tent v - w D^-1 A P_tent v on the fine level's unknowns.
+template <typename T, bool SYM>
+__global__ void __launch_bounds__(kThreads) k_lc_prolong(LCView<T> c, LCView<T> cc,
+                                                         const T* __restrict__ vc,
+                                                         T* __restrict__ xv, T omega) {
+    LC_PROLOGUE
+    if (!inb) return;
+    const T id = c.invD[i];
+    if (id == (T)0) return;
+    // coarse storage index of the aggregate of fine logical (x, y, z); floor division so
+    // that ghost neighbours (-1) map into the coarse ghost layer
+    auto agg = [&](int x, int y, int z) -> long {
+        const int ax = (x + 3) / 3, ay = (y + 3) / 3, az = (z + 3) / 3;  // floor(x/3) + 1
+        return ax + (long)cc.sx * ay + cc.sxy * az;
+    };
+    T apv = 0;
+#pragma unroll
+    for (int k = 0; k < 27; ++k) {
+        const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+        apv += lc_a<T, SYM>(c, i, k) * vc[agg(X + dx, Y + dy, Z + dz)];
+    }
+    const T pv = vc[agg(X, Y, Z)];
+    xv[i] += pv - omega * id * apv;
+}
+
+template <typename T>
+void lc_prolong(const CoarseLevel& F, const CoarseLevel& C, const T* vc, T* x, double omega,
+                hipStream_t s) {
+    if (F.sym)
+        hipLaunchKernelGGL((k_lc_prolong<T, true>), lc_grid(F), dim3(kWave, kBlockY), 0, s,
+                           F.view<T>(), C.view<T>(), vc, x, (T)omega);
+    else
+        hipLaunchKernelGGL((k_lc_prolong<T, false>), lc_grid(F), dim3(kWave, kBlockY), 0, s,
+                           F.view<T>(), C.view<T>(), vc, x, (T)omega);
+    HIPCHECK(hipGetLastError());
+}
+template void lc_prolong<double>(const CoarseLevel&, const CoarseLevel&, const double*, double*,
+                                 double, hipStream_t);
+template void lc_prolong<float>(const CoarseLevel&, const CoarseLevel&, const float*, float*,
+                                double, hipStream_t);
+
+// ================================================================ Galerkin product
+//
+// Column J of A_c = P^T A P with P = (I - w D^-1 A) P_tent, computed on the 9^3 patch of
+// fine nodes around aggregate J:  u = P_tent e_J (3^3), v = u - w D^-1 A u (5^3),
+// t = A v (7^3), y = t - w A^T D^-1 t (9^3), then A_c(J + c, J) = sum of y over
+// aggregate J + c for the 27 neighbouring aggregates c.  The accessor gives the fine
+// level's rows (row), transposed rows (rowT), D^-1 and the unknown flag.
+
+struct L0Slot {
+    long i;
+    bool unk, irr;
+    int rank;
+};
+
+__device__ inline L0Slot l0_slot(const L0View<double>& v, int x, int y, int z) {
+    L0Slot n;
+    n.i = x + (long)v.nx * y + v.nxy * z;
+    const long seg = ((long)z * v.ny + y) * v.nsegx + (x >> 6);
+    const int b = x & 63;
+    const uint64_t u = v.unk[seg], r = v.irr[seg];
+    n.unk = (u >> b) & 1ull;
+    n.irr = (r >> b) & 1ull;
+    n.rank = n.irr ? v.base[seg] + __popcll(r & ((1ull << b) - 1ull)) : 0;
+    return n;
+}
+
+struct AccL0 {
+    L0View<double> v;
+    __device__ bool inbox(int x, int y, int z) const {
+        return x >= 0 && y >= 0 && z >= 0 && x < v.nx && y < v.ny && z < v.nz;
+    }
+    // 7-point rows: entries k = 13 and the six direction slots, zero elsewhere
+    __device__ void rows(int x, int y, int z, double* a, double* at, bool* unk) const {
+        for (int k = 0; k < 27; ++k) a[k] = at[k] = 0.0;
+        *unk = false;
+        if (!inbox(x, y, z)) return;
+        const L0Slot n = l0_slot(v, x, y, z);
+        if (!n.unk) return;
+        *unk = true;
+        a[13] = at[13] = 1.0;
+        for (int d = 0; d < 6; ++d) {
+            const int k = dir_to_k(d);
+            a[k] = n.irr ? v.tab[d][n.rank] : v.c[d >> 1];
+            at[k] = n.irr ? v.tabT[d][n.rank] : v.c[d >> 1];
+        }
+    }
+    __device__ double invd(int x, int y, int z) const {
+        if (!inbox(x, y, z)) return 0.0;
+        return l0_slot(v, x, y, z).unk ? 1.0 : 0.0;
+    }
+};
+
+struct AccLC {
+    LCView<double> c;
+    __device__ bool inbox(int x, int y, int z) const {
+        return x >= 0 && y >= 0 && z >= 0 && x < c.mx && y < c.my && z < c.mz;
+    }
+    __device__ long sidx(int x, int y, int z) const {
+        return (x + 1) + (long)c.sx * (y + 1) + c.sxy * (z + 1);
+    }
+    __device__ void rows(int x, int y, int z, double* a, double* at, bool* unk) const {
+        for (int k = 0; k < 27; ++k) a[k] = at[k] = 0.0;
+        *unk = false;
+        if (!inbox(x, y, z)) return;
+        const long i = sidx(x, y, z);
+        if (c.invD[i] == 0.0) return;
+        *unk = true;
+        for (int k = 0; k < 27; ++k) {
+            if (c.sym) {
+                a[k] = (k < 13) ? c.coef[26 - k][i + c.off[k]] : c.coef[k][i];
+                at[k] = a[k];
+            } else {
+                a[k] = c.coef[k][i];
+                at[k] = c.coef[26 - k][i + c.off[k]];
+            }
+        }
+    }
+    __device__ double invd(int x, int y, int z) const {
+        if (!inbox(x, y, z)) return 0.0;
+        return c.invD[sidx(x, y, z)];
+    }
+};
+
+template <class Acc>
+__global__ void __launch_bounds__(256) k_rap(Acc acc, int fmx, int fmy, int fmz, LCView<double> cc,
+                                             double* const* __restrict__ out, double omega) {
+    __shared__ double sv[125], sw[343], sy[729];
+    const int X = blockIdx.x, Y = blockIdx.y, Z = blockIdx.z;
+    const int t = threadIdx.x;
+    // patch position p (0..8 per axis) -> fine logical 3J - 3 + p
+    const int ox = 3 * X - 3, oy = 3 * Y - 3, oz = 3 * Z - 3;
+    double a[27], at[27];
+    bool unk;
+    // skip empty aggregates
+    int has = 0;
+    if (t < 27) {
+        const int px = 3 + t % 3, py = 3 + (t / 3) % 3, pz = 3 + t / 9;
+        acc.rows(ox + px, oy + py, oz + pz, a, at, &unk);
+        has = unk ? 1 : 0;
+    }
+    if (!__syncthreads_or(has)) return;
+
+    auto in_block = [](int px, int py, int pz) {
+        return px >= 3 && px < 6 && py >= 3 && py < 6 && pz >= 3 && pz < 6;
+    };
+    // phase 1: v on [2,7)^3
+    for (int q = t; q < 125; q += blockDim.x) {
+        const int px = 2 + q % 5, py = 2 + (q / 5) % 5, pz = 2 + q / 25;
+        acc.rows(ox + px, oy + py, oz + pz, a, at, &unk);
+        double s = 0.0;
+        for (int k = 0; k < 27; ++k) {
+            const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+            if (in_block(px + dx, py + dy, pz + dz)) s += a[k];
+        }
+        const double u = (unk && in_block(px, py, pz)) ? 1.0 : 0.0;
+        sv[q] = u - omega * acc.invd(ox + px, oy + py, oz + pz) * s;
+    }
+    __syncthreads();
+    // phase 2: t = A v on [1,8)^3
+    for (int q = t; q < 343; q += blockDim.x) {
+        const int px = 1 + q % 7, py = 1 + (q / 7) % 7, pz = 1 + q / 49;
+        acc.rows(ox + px, oy + py, oz + pz, a, at, &unk);
+        double s = 0.0;
+        for (int k = 0; k < 27; ++k) {
+            const int qx = px + k % 3 - 1 - 2, qy = py + (k / 3) % 3 - 1 - 2, qz = pz + k / 9 - 1 - 2;
+            if (qx >= 0 && qx < 5 && qy >= 0 && qy < 5 && qz >= 0 && qz < 5)
+                s += a[k] * sv[qx + 5 * qy + 25 * qz];
+        }
+        sw[q] = s;
+    }
+    __syncthreads();
+    // phase 3: y = t - w A^T D^-1 t on [0,9)^3 (zero at nodes that are not unknowns)
+    for (int q = t; q < 729; q += blockDim.x) {
+        const int px = q % 9, py = (q / 9) % 9, pz = q / 81;
+        acc.rows(ox + px, oy + py, oz + pz, a, at, &unk);
+        double yv = 0.0;
+        if (unk) {
+            double s = 0.0;
+            for (int k = 0; k < 27; ++k) {
+                const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+                const int qx = px + dx - 1, qy = py + dy - 1, qz = pz + dz - 1;
+                if (qx >= 0 && qx < 7 && qy >= 0 && qy < 7 && qz >= 0 && qz < 7 && at[k] != 0.0)
+                    s += at[k] * acc.invd(ox + px + dx, oy + py + dy, oz + pz + dz) *
+                         sw[qx + 7 * qy + 49 * qz];
+            }
+            const bool inw = px >= 1 && px < 8 && py >= 1 && py < 8 && pz >= 1 && pz < 8;
+            const double tv = inw ? sw[(px - 1) + 7 * (py - 1) + 49 * (pz - 1)] : 0.0;
+            yv = tv - omega * s;
+        }
+        sy[q] = yv;
+    }
+    __syncthreads();
+    // phase 4: sums over the 27 aggregates J + c
+    if (t < 27) {
+        const int cx = t % 3 - 1, cy = (t / 3) % 3 - 1, cz = t / 9 - 1;
+        const int IX = X + cx, IY = Y + cy, IZ = Z + cz;
+        const int kprime = 26 - t;  // offset index of -c
+        if (IX >= 0 && IY >= 0 && IZ >= 0 && IX < cc.mx && IY < cc.my && IZ < cc.mz &&
+            (!cc.sym || kprime >= 13)) {
+            double s = 0.0;
+            for (int q = 0; q < 27; ++q) {
+                const int px = 3 + 3 * cx + q % 3, py = 3 + 3 * cy + (q / 3) % 3,
+                          pz = 3 + 3 * cz + q / 9;
+                s += sy[px + 9 * py + 81 * pz];
+            }
+            const long row = (IX + 1) + (long)cc.sx * (IY + 1) + cc.sxy * (IZ + 1);
+            out[kprime][row] = s;
+        }
+    }
+    (void)fmx;
+    (void)fmy;
+    (void)fmz;
+}
+
+static double** upload_ptrs(const CoarseLevel& C, hipStream_t s) {
+    double** d = (double**)dmalloc(sizeof(double*) * 27);
+    HIPCHECK(hipMemcpyAsync(d, C.coef64, sizeof(double*) * 27, hipMemcpyHostToDevice, s));
+    return d;
+}
+
+void rap_from_l0(const FineLevel& L, const CoarseLevel& C, double omega, hipStream_t s) {
+    AccL0 acc{L.view<double>()};
+    double** d = upload_ptrs(C, s);
+    hipLaunchKernelGGL((k_rap<AccL0>), dim3(C.mx, C.my, C.mz), dim3(256), 0, s, acc, L.nx, L.ny,
+                       L.nz, C.view<double>(), d, omega);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(s));
+    dfree(d);
+}
+
+void rap_from_lc(const CoarseLevel& F, const CoarseLevel& C, double omega, hipStream_t s) {
+    AccLC acc{F.view<double>()};
+    double** d = upload_ptrs(C, s);
+    hipLaunchKernelGGL((k_rap<AccLC>), dim3(C.mx, C.my, C.mz), dim3(256), 0, s, acc, F.mx, F.my,
+                       F.mz, C.view<double>(), d, omega);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(s));
+    dfree(d);
+}
+
+// invD = 1/diag at existing coarse nodes (diag != 0); per-block counts of unknowns.
+__global__ void k_lc_finish(const double* __restrict__ diag, double* __restrict__ invD, long n,
+                            int32_t* cnt) {
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const bool u = t < n && diag[t] != 0.0;
+    if (t < n) invD[t] = u ? 1.0 / diag[t] : 0.0;
+    const uint64_t bal = __ballot(u);
+    if ((threadIdx.x & 63) == 0) cnt[t >> 6] = __popcll(bal);
+}
+
+void lc_finish(CoarseLevel& C, int32_t* counts, hipStream_t s) {
+    const long nb = (C.nstore + 255) / 256;  // counts: 4 * nb entries
+    hipLaunchKernelGGL(k_lc_finish, dim3(nb), dim3(256), 0, s, C.coef64[13], C.invD64, C.nstore,
+                       counts);
+    HIPCHECK(hipGetLastError());
+}
+
+__global__ void k_d2f(const double* a, float* b, long n) {
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) b[t] = (float)a[t];
+}
+
+void lc_to_fp32(CoarseLevel& C, hipStream_t s) {
+    const long nb = (C.nstore + 255) / 256;
+    for (int k = 0; k < 27; ++k) {
+        if (!C.coef64[k]) continue;
+        hipLaunchKernelGGL(k_d2f, dim3(nb), dim3(256), 0, s, C.coef64[k], C.coef32[k], C.nstore);
+    }
+    hipLaunchKernelGGL(k_d2f, dim3(nb), dim3(256), 0, s, C.invD64, C.invD32, C.nstore);
+    HIPCHECK(hipGetLastError());
+}
+
+// Storage indices of the existing nodes of a coarse level, in increasing order.
+__global__ void k_lc_list(const double* __restrict__ invD, long n, const int32_t* base,
+                          long* out) {
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const bool u = t < n && invD[t] != 0.0;
+    const uint64_t bal = __ballot(u);
+    if (u) {
+        const int lane = threadIdx.x & 63;
+        out[base[t >> 6] + __popcll(bal & ((1ull << lane) - 1ull))] = t;
+    }
+}
+
+void lc_unknown_list(const CoarseLevel& C, long* out, int32_t* counter, hipStream_t s) {
+    // counter: per-64 counts already produced by lc_finish; scan them in place into a copy
+    const long nw = (C.nstore + 63) / 64;
+    int32_t* base = (int32_t*)dmalloc(sizeof(int32_t) * nw);
+    int64_t* tot = (int64_t*)dmalloc(sizeof(int64_t));
+    exclusive_scan(counter, base, nw, tot, s);
+    hipLaunchKernelGGL(k_lc_list, dim3((C.nstore + 255) / 256), dim3(256), 0, s, C.invD64,
+                       C.nstore, base, out);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(s));
+    dfree(base);
+    dfree(tot);
+}
+
+// ================================================================ coarsest level
+
+__global__ void k_fill_cmap(int32_t* cmap, const long* cidx, int nL) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nL) cmap[cidx[t]] = t;
+}
+
+void fill_cmap(int32_t* cmap, const long* cidx, int nL, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_cmap, dim3((nL + 255) / 256), dim3(256), 0, s, cmap, cidx, nL);
+    HIPCHECK(hipGetLastError());
+}
+
+__global__ void k_dense_l0(L0View<double> v, const long* cidx, const int32_t* cmap, int nL,
+                           double* A) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nL) return;
+    const long b = cidx[i];
+    const int x = b % v.nx, y = (b / v.nx) % v.ny, z = b / v.nxy;
+    AccL0 acc{v};
+    double a[27], at[27];
+    bool unk;
+    acc.rows(x, y, z, a, at, &unk);
+    for (int k = 0; k < 27; ++k) {
+        if (a[k] == 0.0) continue;
+        const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+        const int j = cmap[b + dx + (long)v.nx * dy + v.nxy * dz];
+        if (j >= 0) A[(long)i * nL + j] = a[k];
+    }
+}
+
+__global__ void k_dense_lc(LCView<double> c, const long* cidx, const int32_t* cmap, int nL,
+                           double* A) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nL) return;
+    const long m = cidx[i];
+    for (int k = 0; k < 27; ++k) {
+        const double a = c.sym ? ((k < 13) ? c.coef[26 - k][m + c.off[k]] : c.coef[k][m])
+                               : c.coef[k][m];
+        if (a == 0.0) continue;
+        const int j = cmap[m + c.off[k]];
+        if (j >= 0) A[(long)i * nL + j] = a;
+    }
+}
+
+void dense_from_l0(const FineLevel& L, const long* cidx, const int32_t* cmap, int nL, double* A,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_l0, dim3((nL + 63) / 64), dim3(64), 0, s, L.view<double>(), cidx,
+                       cmap, nL, A);
+    HIPCHECK(hipGetLastError());
+}
+
+void dense_from_lc(const CoarseLevel& C, const long* cidx, const int32_t* cmap, int nL, double* A,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_lc, dim3((nL + 63) / 64), dim3(64), 0, s, C.view<double>(), cidx,
+                       cmap, nL, A);
+    HIPCHECK(hipGetLastError());
+}
+
+// In-place Gauss-Jordan inversion without pivoting (the coarsest operator is positive
+// definite, or has a positive definite symmetric part).  Step k: scale pivot row k, then
+// eliminate column k from every other row; one block per row.
+__global__ void k_gj_pivot(double* A, int n, int k) {
+    __shared__ double piv;
+    if (threadIdx.x == 0) piv = 1.0 / A[(long)k * n + k];
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const long o = (long)k * n + j;
+        A[o] = (j == k) ? piv : A[o] * piv;
+    }
+}
+
+__global__ void k_gj_elim(double* A, int n, int k) {
+    const int i = blockIdx.x;
+    if (i == k) return;
+    __shared__ double f;
+    if (threadIdx.x == 0) f = A[(long)i * n + k];
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const long o = (long)i * n + j;
+        if (j == k)
+            A[o] = -f * A[(long)k * n + k];
+        else
+            A[o] -= f * A[(long)k * n + j];
+    }
+}
+
+void dense_invert(double* A, int n, hipStream_t s) {
+    for (int k = 0; k < n; ++k) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, A, n, k);
+        hipLaunchKernelGGL(k_gj_elim, dim3(n), dim3(256), 0, s, A, n, k);
+    }
+    HIPCHECK(hipGetLastError());
+}
+
+// x[cidx[i]] = sum_j Ainv[i][j] f[cidx[j]] in fp64; one wavefront per row.
+template <typename TF, typename T>
+__global__ void __launch_bounds__(256) k_coarse_solve(const double* __restrict__ Ainv,
+                                                      const long* __restrict__ cidx, int nL,
+                                                      const TF* __restrict__ f, T* __restrict__ x) {
+    const int row = blockIdx.x * 4 + threadIdx.x / kWave;
+    const int lane = threadIdx.x & 63;
+    if (row >= nL) return;
+    double acc = 0.0;
+    for (int j = lane; j < nL; j += kWave) acc += Ainv[(long)row * nL + j] * (double)f[cidx[j]];
+    acc = wave_sum(acc);
+    if (lane == 0) x[cidx[row]] = (T)acc;
+}
+
+template <typename TF, typename T>
+void coarse_solve(const double* Ainv, const long* cidx, int nL, const TF* f, T* x, hipStream_t s) {
+    hipLaunchKernelGGL((k_coarse_solve<TF, T>), dim3((nL + 3) / 4), dim3(256), 0, s, Ainv, cidx, nL,
+                       f, x);
+    HIPCHECK(hipGetLastError());
+}
+template void coarse_solve<double, double>(const double*, const long*, int, const double*, double*,
+                                           hipStream_t);
+template void coarse_solve<double, float>(const double*, const long*, int, const double*, float*,
+                                          hipStream_t);
+template void coarse_solve<float, float>(const double*, const long*, int, const float*, float*,
+                                         hipStream_t);
+
+__global__ void k_f2d(const float* a, double* b, long n) {
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) b[t] = (double)a[t];
+}
+
+void f2d_copy(const float* a, double* b, long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_f2d, dim3((n + 255) / 256), dim3(256), 0, s, a, b, n);
+    HIPCHECK(hipGetLastError());
+}
+
+}  // namespace saamg

@@ -1,0 +1,209 @@
+// Internal declarations of the SA-AMG PCG library (not part of the C interface).
+//
+// Data layout on the device
+//   Level 0 (the lattice): box vectors of nx*ny*nz values, x fastest.  The scaled
+//   operator D^-1/2 A D^-1/2 has unit diagonal.  Rows whose six off-diagonals all equal
+//   the interior constants (-sigma0^2/h_a^2) are "regular"; the others ("irregular":
+//   rows at the wall and their neighbours) keep their six coefficients in a compact
+//   table.  Per 64-node segment of an x-line the library stores a 64-bit unknown mask,
+//   a 64-bit irregular mask and the table rank of the segment's first irregular row, so
+//   a row's table slot is base + popcount(irregular bits below it).
+//   Levels >= 1: 27-point Galerkin operators on a logical box (mx, my, mz) stored with a
+//   one-node zero ghost layer, i.e. on (mx+2)*(my+2)*(mz+2) nodes; coefficient k of
+//   row i couples i to i + offset(k), k = (dx+1) + 3(dy+1) + 9(dz+1).  A symmetric
+//   operator stores only k >= 13 and reads A(i, k<13) as A(i+off(k), 26-k).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/saamg.h"
+
+namespace saamg {
+
+constexpr int kWave = 64;
+constexpr int kBlockY = 4;          // 64 x 4 threads per block for box kernels
+constexpr int kThreads = kWave * kBlockY;
+constexpr int kFinThreads = 1024;   // single-block finalisation of partial sums
+
+// Direction d = 0..5 (-x,+x,-y,+y,-z,+z) as a 27-point offset index.
+__host__ __device__ constexpr int dir_to_k(int d) {
+    return d == 0 ? 12 : d == 1 ? 14 : d == 2 ? 10 : d == 3 ? 16 : d == 4 ? 4 : 22;
+}
+
+template <typename T>
+struct L0View {
+    int nx, ny, nz, nsegx;
+    long nxy;
+    const uint64_t* unk;
+    const uint64_t* irr;
+    const int32_t* base;
+    const T* tab[6];    // scaled off-diagonals of irregular rows, per direction
+    const T* tabT[6];   // the same rows of the transpose
+    T c[3];             // interior off-diagonal per axis
+};
+
+template <typename T>
+struct LCView {
+    int mx, my, mz;     // logical box
+    int sx, sy;         // storage pitch (mx+2, my+2)
+    long sxy;
+    long off[27];
+    const T* coef[27];  // storage layout; for symmetric operators coef[k<13] = nullptr
+    const T* invD;      // 1/diag, 0 at nodes that are not unknowns and in the ghost layer
+    int sym;
+};
+
+// ---------------------------------------------------------------- device helpers
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+    return v;
+}
+
+// Sum over a block of blockDim.x*blockDim.y threads (multiple of 64); result in thread 0.
+__device__ inline double block_sum(double v, double* lds) {
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int nw = (blockDim.x * blockDim.y) / kWave;
+    v = wave_sum(v);
+    if ((tid & (kWave - 1)) == 0) lds[tid / kWave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (tid == 0) {
+        for (int w = 0; w < nw; ++w) s += lds[w];
+    }
+    __syncthreads();
+    return s;
+}
+
+__device__ inline long block_linear_id() {
+    return blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * blockIdx.z);
+}
+
+__device__ inline long grid_blocks() { return (long)gridDim.x * gridDim.y * gridDim.z; }
+
+// Deterministic power-method start value of a logical box index.
+__host__ __device__ inline double start_value(long lin) {
+    uint64_t h = ((uint64_t)lin * 2654435761ull) & 0xffffffffull;
+    return (double)h / 4294967296.0 - 0.5;
+}
+
+// ---------------------------------------------------------------- host side
+
+struct HipError {
+    hipError_t e;
+    std::string where;
+};
+struct ApiError {
+    int status;
+    std::string msg;
+};
+
+void hip_check(hipError_t e, const char* what);
+#define HIPCHECK(x) ::saamg::hip_check((x), #x)
+
+void* dmalloc(size_t bytes);            // throws ApiError(NOMEM) on failure, zero-filled
+void dfree(void* p);
+
+struct ChebCoef {
+    int degree;
+    double c1[8];   // multiplies the previous direction
+    double c2[8];   // multiplies D^-1 r
+};
+ChebCoef cheb_coefficients(double lam_hi, double ratio, int degree);
+
+struct FineLevel {
+    int nx, ny, nz, nsegx;
+    long nxy, nbox, nseg;
+    double h[3];
+    uint64_t* unk = nullptr;
+    uint64_t* irr = nullptr;
+    int32_t* base = nullptr;
+    long n_irr = 0;
+    double* tab64 = nullptr;    // [12][n_irr]: 6 forward then 6 transpose
+    float* tab32 = nullptr;
+    double c64[3];
+    double* sigma = nullptr;    // box, D^-1/2 at unknowns
+    long n_unknowns = 0;
+
+    template <typename T>
+    L0View<T> view() const;
+};
+
+struct CoarseLevel {
+    int mx, my, mz;
+    int sx, sy, sz;
+    long sxy, nstore;
+    int sym;
+    double* coef64[27] = {};
+    float* coef32[27] = {};
+    double* invD64 = nullptr;
+    float* invD32 = nullptr;
+    long n_unknowns = 0;
+
+    template <typename T>
+    LCView<T> view() const;
+};
+
+struct LevelParams {
+    double lam = 0, lam_hi = 0, omega = 0;
+    ChebCoef cheb{};
+};
+
+}  // namespace saamg
+
+struct saamg_hierarchy {
+    int device = 0;
+    int variant = 1;
+    saamg_options opt{};
+    int sym = 1;
+    int n_levels = 1;
+    saamg::FineLevel l0{};
+    std::vector<saamg::CoarseLevel> lc;     // lc[l-1] is level l
+    std::vector<saamg::LevelParams> par;    // per level except the coarsest
+    // coarsest level: explicit inverse, fp64, and where its unknowns live
+    int nL = 0;
+    double* Ainv = nullptr;
+    long* cidx = nullptr;     // storage index of each coarsest-level unknown
+    double t_setup_ms = 0;
+    int64_t bytes = 0;
+};
+
+namespace saamg {
+template <typename T>
+inline L0View<T> FineLevel::view() const {
+    L0View<T> v;
+    v.nx = nx; v.ny = ny; v.nz = nz; v.nsegx = nsegx; v.nxy = nxy;
+    v.unk = unk; v.irr = irr; v.base = base;
+    for (int d = 0; d < 6; ++d) {
+        if constexpr (sizeof(T) == 8) {
+            v.tab[d] = (const T*)(tab64 ? tab64 + (long)d * n_irr : nullptr);
+            v.tabT[d] = (const T*)(tab64 ? tab64 + (long)(6 + d) * n_irr : nullptr);
+        } else {
+            v.tab[d] = (const T*)(tab32 ? tab32 + (long)d * n_irr : nullptr);
+            v.tabT[d] = (const T*)(tab32 ? tab32 + (long)(6 + d) * n_irr : nullptr);
+        }
+    }
+    for (int a = 0; a < 3; ++a) v.c[a] = (T)c64[a];
+    return v;
+}
+
+template <typename T>
+inline LCView<T> CoarseLevel::view() const {
+    LCView<T> v;
+    v.mx = mx; v.my = my; v.mz = mz; v.sx = sx; v.sy = sy; v.sxy = sxy; v.sym = sym;
+    for (int k = 0; k < 27; ++k) {
+        int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+        v.off[k] = dx + (long)sx * dy + sxy * dz;
+        if constexpr (sizeof(T) == 8) v.coef[k] = coef64[k];
+        else v.coef[k] = coef32[k];
+    }
+    if constexpr (sizeof(T) == 8) v.invD = invD64;
+    else v.invD = invD32;
+    return v;
+}
+}  // namespace saamg

@@ -1,0 +1,121 @@
+// Discrete domain of an analytic beam pipe (Section 4, irregular domains): classify the
+// lattice nodes of the bounding box and compute, for every unknown next to the wall,
+// the fraction s of the spacing at which the wall cuts the grid line (Section 2,
+// Figure "boundary").  Each grid line meets these pipes in one open interval, so the
+// wall point is the interval end on the side of the outside neighbour.
+#include <stdint.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "../../include/saamg.h"
+
+namespace {
+
+constexpr double kSnap = 1e-12;  // fractions within kSnap of 1 are taken as 1
+
+struct Pipe {
+    int kind;
+    double a, b, len, bore_r, cav;
+
+    // strict interior test of the continuous pipe (the caps at |z| = len/2 excluded)
+    bool inside(double x, double y, double z) const {
+        switch (kind) {
+            case SAAMG_SHAPE_CYLINDER:
+                return x * x + y * y < a * a;
+            case SAAMG_SHAPE_ELLIPSE:
+                return (x / a) * (x / a) + (y / b) * (y / b) < 1.0;
+            default: {
+                const bool cavity = std::fabs(x) < a && std::fabs(y) < b && std::fabs(z) < cav;
+                return cavity || x * x + y * y < bore_r * bore_r;
+            }
+        }
+    }
+
+    // Half-length of the interval the domain occupies on the grid line through (x, y, z)
+    // along `axis` (the interval is symmetric about the pipe axis).
+    double half_interval(int axis, double x, double y, double z) const {
+        if (kind == SAAMG_SHAPE_BOXBORE) {
+            if (axis == 2) return (x * x + y * y < bore_r * bore_r) ? 0.5 * len : cav;
+            if (std::fabs(z) < cav) return axis == 0 ? a : b;
+            const double o = axis == 0 ? y : x;
+            return std::sqrt(std::fmax(bore_r * bore_r - o * o, 0.0));
+        }
+        if (axis == 2) return 0.5 * len;
+        if (kind == SAAMG_SHAPE_CYLINDER) {
+            const double o = axis == 0 ? y : x;
+            return std::sqrt(std::fmax(a * a - o * o, 0.0));
+        }
+        if (axis == 0) return a * std::sqrt(std::fmax(1.0 - (y / b) * (y / b), 0.0));
+        return b * std::sqrt(std::fmax(1.0 - (x / a) * (x / a), 0.0));
+    }
+};
+
+inline double coord(double half, int i, int n) {
+    return half * (double)(2 * i - (n - 1)) / (double)(n - 1);
+}
+
+}  // namespace
+
+extern "C" int saamg_domain_from_shape(int kind, double a, double b, double length, double bore_r,
+                                       double cavity_half_len, int nx, int ny, int nz,
+                                       uint8_t* mask_out, int64_t wall_cap, int64_t* wall_node,
+                                       uint8_t* wall_dir, double* wall_s, int64_t* n_wall_out) {
+    if (kind < SAAMG_SHAPE_CYLINDER || kind > SAAMG_SHAPE_BOXBORE) return SAAMG_INVALID_ARG;
+    if (nx < 3 || ny < 3 || nz < 3 || !mask_out || !n_wall_out) return SAAMG_INVALID_ARG;
+    if (!(a > 0) || !(b > 0) || !(length > 0)) return SAAMG_INVALID_ARG;
+    if (kind == SAAMG_SHAPE_BOXBORE && (!(bore_r > 0) || !(cavity_half_len > 0)))
+        return SAAMG_INVALID_ARG;
+    if (wall_cap > 0 && (!wall_node || !wall_dir || !wall_s)) return SAAMG_INVALID_ARG;
+    const Pipe p{kind, a, b, length, bore_r, cavity_half_len};
+    const long nxy = (long)nx * ny;
+    const double h[3] = {2.0 * a / (nx - 1), 2.0 * b / (ny - 1), length / (nz - 1)};
+
+    for (int k = 0; k < nz; ++k) {
+        const double z = coord(0.5 * length, k, nz);
+        for (int j = 0; j < ny; ++j) {
+            const double y = coord(b, j, ny);
+            for (int i = 0; i < nx; ++i) {
+                const double x = coord(a, i, nx);
+                const bool interior_index =
+                    i > 0 && j > 0 && k > 0 && i < nx - 1 && j < ny - 1 && k < nz - 1;
+                mask_out[i + nx * (long)j + nxy * k] = (interior_index && p.inside(x, y, z)) ? 1 : 0;
+            }
+        }
+    }
+
+    int64_t count = 0;
+    const long step[3] = {1, (long)nx, nxy};
+    for (int k = 1; k < nz - 1; ++k) {
+        const double z = coord(0.5 * length, k, nz);
+        for (int j = 1; j < ny - 1; ++j) {
+            const double y = coord(b, j, ny);
+            for (int i = 1; i < nx - 1; ++i) {
+                const long idx = i + nx * (long)j + nxy * k;
+                if (!mask_out[idx]) continue;
+                const double x = coord(a, i, nx);
+                const double pos[3] = {x, y, z};
+                for (int d = 0; d < 6; ++d) {
+                    const int axis = d / 2;
+                    const long nb = (d & 1) ? idx + step[axis] : idx - step[axis];
+                    if (mask_out[nb]) continue;
+                    const double end = p.half_interval(axis, x, y, z);
+                    const double wall = (d & 1) ? end : -end;
+                    double s = std::fabs(wall - pos[axis]) / h[axis];
+                    if (s > 1.0 - kSnap) s = 1.0;
+                    if (!(s > 0.0)) return SAAMG_INVALID_ARG;
+                    if (s < 1.0) {
+                        if (count < wall_cap) {
+                            wall_node[count] = idx;
+                            wall_dir[count] = (uint8_t)d;
+                            wall_s[count] = s;
+                        }
+                        ++count;
+                    }
+                }
+            }
+        }
+    }
+    *n_wall_out = count;
+    return count > wall_cap && wall_cap > 0 ? SAAMG_INVALID_ARG : SAAMG_OK;
+}

@@ -1,0 +1,831 @@
+// Level-0 (lattice) kernels: operator build, stencils, Chebyshev steps, transfer
+// operators to level 1, and the fused fp64 CG vector kernels.
+//
+// Thread mapping: blocks of 64 x 4 threads; one wavefront covers one 64-node segment of
+// an x-line (so segment masks are wave-uniform), a block covers 4 lines, and each block
+// walks kZB consecutive z-planes.
+#include "launch.h"
+
+namespace saamg {
+
+constexpr int kZB = 4;
+
+static inline dim3 l0_grid(const FineLevel& L) {
+    return dim3(L.nsegx, (L.ny + kBlockY - 1) / kBlockY, (L.nz + kZB - 1) / kZB);
+}
+long l0_blocks(const FineLevel& L) {
+    dim3 g = l0_grid(L);
+    return (long)g.x * g.y * g.z;
+}
+
+// Per-lane view of one level-0 node inside the current segment.
+struct L0Node {
+    long i;       // box index
+    bool unk;     // unknown
+    bool irr;     // irregular row
+    int rank;     // table slot when irregular
+};
+
+template <typename T>
+__device__ inline L0Node l0_node(const L0View<T>& v, int x, int y, int z) {
+    L0Node n;
+    n.i = x + (long)v.nx * y + v.nxy * z;
+    n.unk = false;
+    n.irr = false;
+    n.rank = 0;
+    if (x < v.nx && y < v.ny) {
+        const long seg = ((long)z * v.ny + y) * v.nsegx + (x >> 6);
+        const int b = x & 63;
+        const uint64_t u = v.unk[seg];
+        const uint64_t r = v.irr[seg];
+        n.unk = (u >> b) & 1ull;
+        n.irr = (r >> b) & 1ull;
+        if (n.irr) n.rank = v.base[seg] + __popcll(r & ((1ull << b) - 1ull));
+    }
+    return n;
+}
+
+// Lookup of an arbitrary node (no wave-uniformity assumed).
+template <typename T>
+__device__ inline L0Node l0_node_any(const L0View<T>& v, int x, int y, int z) {
+    return l0_node(v, x, y, z);
+}
+
+// (A x)_i of the scaled level-0 operator (or its transpose) for an unknown row, where
+// X(j) yields the input value at box index j.
+template <typename T, bool TR, class F>
+__device__ inline T l0_stencil(const L0View<T>& v, const L0Node& n, F X) {
+    const long i = n.i;
+    T acc = X(i);
+    if (!n.irr) {
+        acc += v.c[0] * (X(i - 1) + X(i + 1)) + v.c[1] * (X(i - v.nx) + X(i + v.nx)) +
+               v.c[2] * (X(i - v.nxy) + X(i + v.nxy));
+    } else {
+        const T* const* t = TR ? v.tabT : v.tab;
+        const int r = n.rank;
+        acc += t[0][r] * X(i - 1) + t[1][r] * X(i + 1) + t[2][r] * X(i - v.nx) +
+               t[3][r] * X(i + v.nx) + t[4][r] * X(i - v.nxy) + t[5][r] * X(i + v.nxy);
+    }
+    return acc;
+}
+
+#define L0_LOOP_BEGIN                                              \
+    const int x = blockIdx.x * kWave + threadIdx.x;                \
+    const int y = blockIdx.y * kBlockY + threadIdx.y;              \
+    const int z0 = blockIdx.z * kZB;                               \
+    const int z1 = min(z0 + kZB, v.nz);                            \
+    for (int z = z0; z < z1; ++z) {                                \
+        const L0Node n = l0_node(v, x, y, z);                      \
+        const bool inb = x < v.nx && y < v.ny;
+
+#define L0_LOOP_END }
+
+// ================================================================ finalisation
+
+__global__ void __launch_bounds__(kFinThreads) k_finalize(const double* __restrict__ part,
+                                                          long nblk, int nq, double* scal, int op,
+                                                          int dst) {
+    __shared__ double lds[kFinThreads / kWave];
+    double sums[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < nq; ++q) {
+        double a = 0.0;
+        for (long i = threadIdx.x; i < nblk; i += kFinThreads) a += part[q * nblk + i];
+        const int tid = threadIdx.x;
+        a = wave_sum(a);
+        if ((tid & 63) == 0) lds[tid >> 6] = a;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < kFinThreads / kWave; ++w) s += lds[w];
+            sums[q] = s;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    switch (op) {
+        case FIN_STORE:
+            for (int q = 0; q < nq; ++q) scal[dst + q] = sums[q];
+            break;
+        case FIN_ALPHA:
+            scal[S_PQ] = sums[0];
+            scal[S_ALPHA] = scal[S_RHO] / sums[0];
+            break;
+        case FIN_RHO_INIT:
+            scal[S_RHO] = sums[0];
+            scal[S_RHO_PREV] = sums[0];
+            scal[S_BETA] = 0.0;
+            break;
+        case FIN_RHO:
+            scal[S_BETA] = sums[0] / scal[S_RHO];
+            scal[S_RHO_PREV] = scal[S_RHO];
+            scal[S_RHO] = sums[0];
+            break;
+        case FIN_POWER:
+            scal[S_INVN] = 1.0 / sqrt(sums[0]);
+            scal[S_LAM] = sums[1] / sums[2];
+            break;
+        case FIN_NORM:
+            scal[S_INVN] = 1.0 / sqrt(sums[0]);
+            break;
+        case FIN_RESTORE_RHO:
+            scal[S_RHO] = scal[S_RHO_PREV];
+            break;
+    }
+}
+
+void finalize(const double* partials, long nblk, int nq, double* scal, int op, int dst,
+              hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, partials, nblk, nq, scal, op,
+                       dst);
+    HIPCHECK(hipGetLastError());
+}
+
+// ================================================================ build
+
+__global__ void k_scatter_nwidx(int32_t* nwidx, const int64_t* nodes, long n) {
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) nwidx[nodes[t]] = (int32_t)t;
+}
+
+void l0_scatter_nwidx(int32_t* nwidx, const int64_t* nodes, long n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_scatter_nwidx, dim3((n + 255) / 256), dim3(256), 0, s, nwidx, nodes, n);
+    HIPCHECK(hipGetLastError());
+}
+
+// Segment masks: unknown bits from the mask; irregular = unknown and (at the wall with
+// some s < 1, or a neighbour of such a node).
+__global__ void __launch_bounds__(kThreads) k_build_masks(int nx, int ny, int nz, int nsegx,
+                                                          const uint8_t* __restrict__ mask,
+                                                          const int32_t* __restrict__ nwidx,
+                                                          uint64_t* unk, uint64_t* irr,
+                                                          int32_t* cnt_irr, int32_t* cnt_unk) {
+    const int x = blockIdx.x * kWave + threadIdx.x;
+    const int y = blockIdx.y * kBlockY + threadIdx.y;
+    const long nxy = (long)nx * ny;
+    for (int z = blockIdx.z * kZB; z < min(blockIdx.z * kZB + kZB, nz); ++z) {
+        bool u = false, r = false;
+        if (x < nx && y < ny) {
+            const long i = x + (long)nx * y + nxy * z;
+            u = mask[i] != 0;
+            if (u) {
+                r = nwidx[i] >= 0 || nwidx[i - 1] >= 0 || nwidx[i + 1] >= 0 ||
+                    nwidx[i - nx] >= 0 || nwidx[i + nx] >= 0 || nwidx[i - nxy] >= 0 ||
+                    nwidx[i + nxy] >= 0;
+            }
+        }
+        const uint64_t bu = __ballot(u);
+        const uint64_t br = __ballot(r);
+        if (threadIdx.x == 0 && y < ny) {
+            const long seg = ((long)z * ny + y) * nsegx + blockIdx.x;
+            unk[seg] = bu;
+            irr[seg] = br;
+            cnt_irr[seg] = __popcll(br);
+            cnt_unk[seg] = __popcll(bu);
+        }
+    }
+}
+
+void l0_build_masks(FineLevel& L, const uint8_t* mask, const int32_t* nwidx, int32_t* cnt_irr,
+                    int32_t* cnt_unk, hipStream_t s) {
+    hipLaunchKernelGGL(k_build_masks, l0_grid(L), dim3(kWave, kBlockY), 0, s, L.nx, L.ny, L.nz,
+                       L.nsegx, mask, nwidx, L.unk, L.irr, cnt_irr, cnt_unk);
+    HIPCHECK(hipGetLastError());
+}
+
+// Single-block exclusive scan of int32 counts (setup only).
+__global__ void __launch_bounds__(1024) k_scan(const int32_t* in, int32_t* out, long n,
+                                               int64_t* total) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const long chunk = (n + 1023) / 1024;
+    const long a = t * chunk, b = min(n, a + chunk);
+    int64_t s = 0;
+    for (long i = a; i < b; ++i) s += in[i];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t acc = 0;
+        for (int k = 0; k < 1024; ++k) {
+            int64_t v = part[k];
+            part[k] = acc;
+            acc += v;
+        }
+        *total = acc;
+    }
+    __syncthreads();
+    int64_t acc = part[t];
+    for (long i = a; i < b; ++i) {
+        if (out) out[i] = (int32_t)acc;
+        acc += in[i];
+    }
+}
+
+void exclusive_scan(const int32_t* in, int32_t* out, long n, int64_t* total, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, in, out, n, total);
+    HIPCHECK(hipGetLastError());
+}
+
+struct RowRule {
+    double sigma;   // D^-1/2 of the row
+    double f[3];    // factor of the off-diagonal toward the inside neighbour, per axis
+};
+
+// Per-axis contribution of the wall rules (Section 2): diagonal in units of 1/h^2 and
+// the factor of the remaining off-diagonal.  Outside neighbours are substituted by
+// constant (u' = 0), linear (u' = (1-1/s) u) or quadratic extrapolation
+// (u' = 2(s-1)/s u - (s-1)/(s+1) u'' ; both sides out: u' and u'' from s and t).
+__device__ inline void axis_rule(int variant, bool in_m, bool in_p, double s, double t,
+                                 double* diag, double* f) {
+    if (in_m && in_p) {
+        *diag = 2.0;
+        *f = 1.0;
+        return;
+    }
+    if (variant == SAAMG_VARIANT_LIN) {
+        *diag = (in_m ? 1.0 : 1.0 / s) + (in_p ? 1.0 : 1.0 / t);
+        *f = 1.0;
+    } else if (variant == SAAMG_VARIANT_QUAD) {
+        if (!in_m && !in_p) {
+            *diag = 2.0 / (s * t);
+            *f = 1.0;
+        } else if (!in_m) {
+            *diag = 2.0 / s;
+            *f = 2.0 / (s + 1.0);
+        } else {
+            *diag = 2.0 / t;
+            *f = 2.0 / (t + 1.0);
+        }
+    } else {
+        *diag = 2.0;
+        *f = 1.0;
+    }
+}
+
+__device__ inline RowRule row_rule(long i, const uint8_t* mask, const int32_t* nwidx,
+                                   const double* nwfrac, int variant, double sigma0,
+                                   const double ih2[3], const long step[3]) {
+    RowRule r;
+    const int k = nwidx[i];
+    if (k < 0) {
+        r.sigma = sigma0;
+        r.f[0] = r.f[1] = r.f[2] = 1.0;
+        return r;
+    }
+    double D = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const bool in_m = mask[i - step[a]] != 0;
+        const bool in_p = mask[i + step[a]] != 0;
+        double dg, f;
+        axis_rule(variant, in_m, in_p, nwfrac[6L * k + 2 * a], nwfrac[6L * k + 2 * a + 1], &dg,
+                  &f);
+        D += dg * ih2[a];
+        r.f[a] = f;
+    }
+    r.sigma = 1.0 / sqrt(D);
+    return r;
+}
+
+// Scaled coupling of row `row` to column `col` along axis a (both unknowns).
+__device__ inline double scaled_off(const RowRule& row, const RowRule& col, int a,
+                                    const double ih2[3]) {
+    return -(row.sigma * (row.f[a] * ih2[a])) * col.sigma;
+}
+
+__global__ void __launch_bounds__(kThreads) k_build_table(
+    L0View<double> v, const uint8_t* __restrict__ mask, const int32_t* __restrict__ nwidx,
+    const double* __restrict__ nwfrac, int variant, double sigma0, double ihx2, double ihy2,
+    double ihz2, long n_irr, double* tab, float* tab32, double* sigma) {
+    const double ih2[3] = {ihx2, ihy2, ihz2};
+    const long step[3] = {1, (long)v.nx, v.nxy};
+    L0_LOOP_BEGIN
+    if (inb) {
+        if (!n.unk) {
+            sigma[n.i] = 0.0;
+        } else {
+            const RowRule me = row_rule(n.i, mask, nwidx, nwfrac, variant, sigma0, ih2, step);
+            sigma[n.i] = me.sigma;
+            if (n.irr) {
+                for (int d = 0; d < 6; ++d) {
+                    const int a = d >> 1;
+                    const long j = n.i + ((d & 1) ? step[a] : -step[a]);
+                    double fw = 0.0, bw = 0.0;
+                    if (mask[j]) {
+                        const RowRule nb = row_rule(j, mask, nwidx, nwfrac, variant, sigma0, ih2, step);
+                        fw = scaled_off(me, nb, a, ih2);
+                        bw = scaled_off(nb, me, a, ih2);
+                    }
+                    tab[(long)d * n_irr + n.rank] = fw;
+                    tab[(long)(6 + d) * n_irr + n.rank] = bw;
+                    tab32[(long)d * n_irr + n.rank] = (float)fw;
+                    tab32[(long)(6 + d) * n_irr + n.rank] = (float)bw;
+                }
+            }
+        }
+    }
+    L0_LOOP_END
+}
+
+void l0_build_table(FineLevel& L, const uint8_t* mask, const int32_t* nwidx, const double* nwfrac,
+                    int variant, double sigma0, hipStream_t s) {
+    L0View<double> v = L.view<double>();
+    hipLaunchKernelGGL(k_build_table, l0_grid(L), dim3(kWave, kBlockY), 0, s, v, mask, nwidx,
+                       nwfrac, variant, sigma0, 1.0 / (L.h[0] * L.h[0]), 1.0 / (L.h[1] * L.h[1]),
+                       1.0 / (L.h[2] * L.h[2]), L.n_irr, L.tab64, L.tab32, L.sigma);
+    HIPCHECK(hipGetLastError());
+}
+
+__global__ void __launch_bounds__(kThreads) k_unknown_list(L0View<double> v, const int32_t* ucnt_base,
+                                                           long* out) {
+    L0_LOOP_BEGIN
+    if (inb && n.unk) {
+        const long seg = ((long)z * v.ny + y) * v.nsegx + (x >> 6);
+        const uint64_t u = v.unk[seg];
+        const int b = x & 63;
+        out[ucnt_base[seg] + __popcll(u & ((1ull << b) - 1ull))] = n.i;
+    }
+    L0_LOOP_END
+}
+
+void l0_unknown_list(const FineLevel& L, long* out, hipStream_t s) {
+    // rank of unknowns by segment: scan the per-segment unknown counts
+    int32_t* cnt = (int32_t*)dmalloc(sizeof(int32_t) * L.nseg);
+    int32_t* base = (int32_t*)dmalloc(sizeof(int32_t) * L.nseg);
+    int64_t* tot = (int64_t*)dmalloc(sizeof(int64_t));
+    std::vector<uint64_t> hu(L.nseg);
+    HIPCHECK(hipMemcpyAsync(hu.data(), L.unk, sizeof(uint64_t) * L.nseg, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    std::vector<int32_t> hc(L.nseg);
+    for (long i = 0; i < L.nseg; ++i) hc[i] = __builtin_popcountll(hu[i]);
+    HIPCHECK(hipMemcpyAsync(cnt, hc.data(), sizeof(int32_t) * L.nseg, hipMemcpyHostToDevice, s));
+    exclusive_scan(cnt, base, L.nseg, tot, s);
+    hipLaunchKernelGGL(k_unknown_list, l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(),
+                       base, out);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(s));
+    dfree(cnt);
+    dfree(base);
+    dfree(tot);
+}
+
+// ================================================================ operators
+
+template <typename T, bool TR>
+__global__ void __launch_bounds__(kThreads) k_l0_apply(L0View<T> v, const T* __restrict__ xv,
+                                                       T* __restrict__ yv) {
+    L0_LOOP_BEGIN
+    if (inb) {
+        T r = 0;
+        if (n.unk) r = l0_stencil<T, TR>(v, n, [&](long j) { return xv[j]; });
+        yv[n.i] = r;
+    }
+    L0_LOOP_END
+}
+
+template <typename T>
+void l0_apply(const FineLevel& L, bool trans, const T* x, T* y, hipStream_t s) {
+    L0View<T> v = L.view<T>();
+    if (trans)
+        hipLaunchKernelGGL((k_l0_apply<T, true>), l0_grid(L), dim3(kWave, kBlockY), 0, s, v, x, y);
+    else
+        hipLaunchKernelGGL((k_l0_apply<T, false>), l0_grid(L), dim3(kWave, kBlockY), 0, s, v, x, y);
+    HIPCHECK(hipGetLastError());
+}
+template void l0_apply<double>(const FineLevel&, bool, const double*, double*, hipStream_t);
+template void l0_apply<float>(const FineLevel&, bool, const float*, float*, hipStream_t);
+
+__global__ void __launch_bounds__(kThreads) k_l0_power_start(L0View<double> v, double* w) {
+    L0_LOOP_BEGIN
+    if (inb) w[n.i] = n.unk ? start_value(n.i) : 0.0;
+    L0_LOOP_END
+}
+
+void l0_power_start(const FineLevel& L, double* v, hipStream_t s) {
+    hipLaunchKernelGGL(k_l0_power_start, l0_grid(L), dim3(kWave, kBlockY), 0, s,
+                       L.view<double>(), v);
+    HIPCHECK(hipGetLastError());
+}
+
+// w = A u with u = v * scal[S_INVN] (D = I at level 0); partials of w.w, u.Au, u.u.
+__global__ void __launch_bounds__(kThreads) k_l0_power_step(L0View<double> v,
+                                                            const double* __restrict__ vin,
+                                                            const double* __restrict__ scal,
+                                                            double* __restrict__ w, double* part) {
+    __shared__ double lds[kThreads / kWave];
+    const double sc = scal[S_INVN];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    L0_LOOP_BEGIN
+    if (inb) {
+        double r = 0.0;
+        if (n.unk) {
+            r = l0_stencil<double, false>(v, n, [&](long j) { return vin[j] * sc; });
+            const double u = vin[n.i] * sc;
+            a0 += r * r;
+            a1 += u * r;
+            a2 += u * u;
+        }
+        w[n.i] = r;
+    }
+    L0_LOOP_END
+    const long bid = block_linear_id(), nb = grid_blocks();
+    double s0 = block_sum(a0, lds), s1 = block_sum(a1, lds), s2 = block_sum(a2, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        part[bid] = s0;
+        part[nb + bid] = s1;
+        part[2 * nb + bid] = s2;
+    }
+}
+
+void l0_power_step(const FineLevel& L, const double* v, const double* scal, double* w,
+                   double* partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_l0_power_step, l0_grid(L), dim3(kWave, kBlockY), 0, s,
+                       L.view<double>(), v, scal, w, partials);
+    HIPCHECK(hipGetLastError());
+}
+
+// One Chebyshev step on level 0 (D = I).  Modes:
+//   ZERO1: x1 = c2_0 f                                   (degree-1 zero-guess smoother)
+//   ZERO2: x1 = c2_0 f on the fly; r1 = f - A x1; d1 = c1 x1 + c2 r1; x2 = x1 + d1
+//   FIRST: r = f - A xin; d = c2_0 r; xout = xin + d
+//   NEXT : r = f - A xin; d = c1 din + c2 r; xout = xin + d
+// Optional partial sums of f . xout (the PCG's r . z when this is the last step).
+template <typename TF, typename T, int MODE, bool DOT>
+__global__ void __launch_bounds__(kThreads) k_l0_cheb(L0View<T> v, const TF* __restrict__ f,
+                                                      const T* __restrict__ xin,
+                                                      const T* __restrict__ din, T* __restrict__ xout,
+                                                      T* __restrict__ dout, T c1, T c2, T c20,
+                                                      double* part) {
+    __shared__ double lds[kThreads / kWave];
+    double acc = 0.0;
+    L0_LOOP_BEGIN
+    if (inb) {
+        T xo = 0, dn = 0;
+        if (n.unk) {
+            const T fi = (T)f[n.i];
+            if (MODE == CHEB_ZERO1) {
+                xo = c20 * fi;
+                dn = xo;
+            } else if (MODE == CHEB_ZERO2) {
+                const T ax = l0_stencil<T, false>(v, n, [&](long j) { return c20 * (T)f[j]; });
+                const T x1 = c20 * fi;
+                dn = c1 * x1 + c2 * (fi - ax);
+                xo = x1 + dn;
+            } else {
+                const T ax = l0_stencil<T, false>(v, n, [&](long j) { return xin[j]; });
+                const T r = fi - ax;
+                dn = (MODE == CHEB_FIRST) ? c20 * r : c1 * din[n.i] + c2 * r;
+                xo = xin[n.i] + dn;
+            }
+            if (DOT) acc += (double)f[n.i] * (double)xo;
+        }
+        xout[n.i] = xo;
+        if (dout) dout[n.i] = dn;
+    }
+    L0_LOOP_END
+    if (DOT) {
+        double sb = block_sum(acc, lds);
+        if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = sb;
+    }
+}
+
+template <typename TF, typename T>
+void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* din, T* xout,
+             T* dout, double c1, double c2, double c2_0, double* dot, hipStream_t s) {
+    L0View<T> v = L.view<T>();
+    dim3 g = l0_grid(L), b(kWave, kBlockY);
+#define CHEB_LAUNCH(M)                                                                         \
+    if (dot)                                                                                   \
+        hipLaunchKernelGGL((k_l0_cheb<TF, T, M, true>), g, b, 0, s, v, f, xin, din, xout, dout, \
+                           (T)c1, (T)c2, (T)c2_0, dot);                                        \
+    else                                                                                       \
+        hipLaunchKernelGGL((k_l0_cheb<TF, T, M, false>), g, b, 0, s, v, f, xin, din, xout,      \
+                           dout, (T)c1, (T)c2, (T)c2_0, dot);
+    switch (mode) {
+        case CHEB_ZERO1: CHEB_LAUNCH(CHEB_ZERO1) break;
+        case CHEB_ZERO2: CHEB_LAUNCH(CHEB_ZERO2) break;
+        case CHEB_FIRST: CHEB_LAUNCH(CHEB_FIRST) break;
+        default: CHEB_LAUNCH(CHEB_NEXT) break;
+    }
+#undef CHEB_LAUNCH
+    HIPCHECK(hipGetLastError());
+}
+template void l0_cheb<double, double>(const FineLevel&, int, const double*, const double*,
+                                      const double*, double*, double*, double, double, double,
+                                      double*, hipStream_t);
+template void l0_cheb<double, float>(const FineLevel&, int, const double*, const float*,
+                                     const float*, float*, float*, double, double, double,
+                                     double*, hipStream_t);
+template void l0_cheb<float, float>(const FineLevel&, int, const float*, const float*,
+                                    const float*, float*, float*, double, double, double,
+                                    double*, hipStream_t);
+
+template <typename TF, typename T>
+__global__ void __launch_bounds__(kThreads) k_l0_residual(L0View<T> v, const TF* __restrict__ f,
+                                                          const T* __restrict__ xv,
+                                                          T* __restrict__ r) {
+    L0_LOOP_BEGIN
+    if (inb) {
+        T o = 0;
+        if (n.unk) o = (T)f[n.i] - l0_stencil<T, false>(v, n, [&](long j) { return xv[j]; });
+        r[n.i] = o;
+    }
+    L0_LOOP_END
+}
+
+template <typename TF, typename T>
+void l0_residual(const FineLevel& L, const TF* f, const T* x, T* r, hipStream_t s) {
+    hipLaunchKernelGGL((k_l0_residual<TF, T>), l0_grid(L), dim3(kWave, kBlockY), 0, s,
+                       L.view<T>(), f, x, r);
+    HIPCHECK(hipGetLastError());
+}
+template void l0_residual<double, double>(const FineLevel&, const double*, const double*,
+                                          double*, hipStream_t);
+template void l0_residual<double, float>(const FineLevel&, const double*, const float*, float*,
+                                         hipStream_t);
+template void l0_residual<float, float>(const FineLevel&, const float*, const float*, float*,
+                                        hipStream_t);
+
+// Restriction to level 1: fc(I) = sum over the aggregate's unknowns of (r - w A^T r),
+// i.e. P^T r with P = (I - w A) P_tent (D = I at level 0).  One thread per coarse node.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_l0_restrict(L0View<T> v, LCView<T> c,
+                                                          const T* __restrict__ r,
+                                                          T* __restrict__ fc, T omega) {
+    const int X = blockIdx.x * kWave + threadIdx.x;
+    const int Y = blockIdx.y * kBlockY + threadIdx.y;
+    const int Z = blockIdx.z;
+    if (X >= c.mx || Y >= c.my) return;
+    T acc = 0;
+    for (int dz = 0; dz < 3; ++dz) {
+        const int z = 3 * Z + dz;
+        if (z >= v.nz) break;
+        for (int dy = 0; dy < 3; ++dy) {
+            const int y = 3 * Y + dy;
+            if (y >= v.ny) break;
+            for (int dx = 0; dx < 3; ++dx) {
+                const int x = 3 * X + dx;
+                if (x >= v.nx) break;
+                const L0Node n = l0_node_any(v, x, y, z);
+                if (!n.unk) continue;
+                const T at = l0_stencil<T, true>(v, n, [&](long j) { return r[j]; });
+                acc += r[n.i] - omega * at;
+            }
+        }
+    }
+    fc[(X + 1) + (long)c.sx * (Y + 1) + c.sxy * (Z + 1)] = acc;
+}
+
+template <typename T>
+void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* fc, double omega,
+                 hipStream_t s) {
+    dim3 g((C.mx + kWave - 1) / kWave, (C.my + kBlockY - 1) / kBlockY, C.mz);
+    hipLaunchKernelGGL((k_l0_restrict<T>), g, dim3(kWave, kBlockY), 0, s, L.view<T>(),
+                       C.view<T>(), r, fc, (T)omega);
+    HIPCHECK(hipGetLastError());
+}
+template void l0_restrict<double>(const FineLevel&, const CoarseLevel&, const double*, double*,
+                                  double, hipStream_t);
+template void l0_restrict<float>(const FineLevel&, const CoarseLevel&, const float*, float*,
+                                 double, hipStream_t);
+
+// Prolongation from level 1: x += P v = P_tent v - w A (P_tent v).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_l0_prolong(L0View<T> v, LCView<T> c,
+                                                         const T* __restrict__ vc,
+                                                         T* __restrict__ xv, T omega) {
+    L0_LOOP_BEGIN
+    if (inb && n.unk) {
+        // coarse storage index of the aggregate holding box index j = (xj, yj, zj)
+        auto agg = [&](int xj, int yj, int zj) -> long {
+            return (xj / 3 + 1) + (long)c.sx * (yj / 3 + 1) + c.sxy * (zj / 3 + 1);
+        };
+        const T pv = vc[agg(x, y, z)];
+        T apv;
+        if (!n.irr) {
+            apv = pv + v.c[0] * (vc[agg(x - 1, y, z)] + vc[agg(x + 1, y, z)]) +
+                  v.c[1] * (vc[agg(x, y - 1, z)] + vc[agg(x, y + 1, z)]) +
+                  v.c[2] * (vc[agg(x, y, z - 1)] + vc[agg(x, y, z + 1)]);
+        } else {
+            const int rk = n.rank;
+            apv = pv + v.tab[0][rk] * vc[agg(x - 1, y, z)] + v.tab[1][rk] * vc[agg(x + 1, y, z)] +
+                  v.tab[2][rk] * vc[agg(x, y - 1, z)] + v.tab[3][rk] * vc[agg(x, y + 1, z)] +
+                  v.tab[4][rk] * vc[agg(x, y, z - 1)] + v.tab[5][rk] * vc[agg(x, y, z + 1)];
+        }
+        xv[n.i] += pv - omega * apv;
+    }
+    L0_LOOP_END
+}
+
+template <typename T>
+void l0_prolong(const FineLevel& L, const CoarseLevel& C, const T* vc, T* x, double omega,
+                hipStream_t s) {
+    hipLaunchKernelGGL((k_l0_prolong<T>), l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<T>(),
+                       C.view<T>(), vc, x, (T)omega);
+    HIPCHECK(hipGetLastError());
+}
+template void l0_prolong<double>(const FineLevel&, const CoarseLevel&, const double*, double*,
+                                 double, hipStream_t);
+template void l0_prolong<float>(const FineLevel&, const CoarseLevel&, const float*, float*,
+                                double, hipStream_t);
+
+// ================================================================ CG (fp64)
+
+__global__ void __launch_bounds__(kThreads) k_cg_init(L0View<double> v, const double* __restrict__ sigma,
+                                                      const double* __restrict__ b,
+                                                      const double* __restrict__ x0,
+                                                      double* __restrict__ bs, double* __restrict__ xv) {
+    L0_LOOP_BEGIN
+    if (inb) {
+        double bo = 0.0, xo = 0.0;
+        if (n.unk) {
+            const double sg = sigma[n.i];
+            bo = sg * b[n.i];
+            if (x0) xo = x0[n.i] / sg;
+        }
+        bs[n.i] = bo;
+        xv[n.i] = xo;
+    }
+    L0_LOOP_END
+}
+
+void cg_init(const FineLevel& L, const double* b, const double* x0, double* bs, double* x,
+             hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_init, l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(),
+                       L.sigma, b, x0, bs, x);
+    HIPCHECK(hipGetLastError());
+}
+
+// r = bs - A x; partials of r.r and bs.bs.
+__global__ void __launch_bounds__(kThreads) k_cg_resid(L0View<double> v, const double* __restrict__ bs,
+                                                       const double* __restrict__ xv,
+                                                       double* __restrict__ r, double* part) {
+    __shared__ double lds[kThreads / kWave];
+    double a0 = 0.0, a1 = 0.0;
+    L0_LOOP_BEGIN
+    if (inb) {
+        double o = 0.0;
+        if (n.unk) {
+            const double bi = bs[n.i];
+            o = bi - l0_stencil<double, false>(v, n, [&](long j) { return xv[j]; });
+            a0 += o * o;
+            a1 += bi * bi;
+        }
+        r[n.i] = o;
+    }
+    L0_LOOP_END
+    const long bid = block_linear_id(), nb = grid_blocks();
+    double s0 = block_sum(a0, lds), s1 = block_sum(a1, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        part[bid] = s0;
+        part[nb + bid] = s1;
+    }
+}
+
+void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
+              hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_resid, l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), bs,
+                       x, r, partials);
+    HIPCHECK(hipGetLastError());
+}
+
+// p_new = z + beta p_old; q = A p_new; partials of p_new . q.
+template <typename TZ>
+__global__ void __launch_bounds__(kThreads) k_cg_pq(L0View<double> v, const TZ* __restrict__ zv,
+                                                    const double* __restrict__ pold,
+                                                    double* __restrict__ pnew,
+                                                    double* __restrict__ q,
+                                                    const double* __restrict__ scal, double* part) {
+    __shared__ double lds[kThreads / kWave];
+    const double beta = scal[S_BETA];
+    double acc = 0.0;
+    L0_LOOP_BEGIN
+    if (inb) {
+        double pi = 0.0, qi = 0.0;
+        if (n.unk) {
+            auto P = [&](long j) { return (double)zv[j] + beta * pold[j]; };
+            pi = P(n.i);
+            qi = l0_stencil<double, false>(v, n, P);
+            acc += pi * qi;
+        }
+        pnew[n.i] = pi;
+        q[n.i] = qi;
+    }
+    L0_LOOP_END
+    double sb = block_sum(acc, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = sb;
+}
+
+template <typename TZ>
+void cg_pq(const FineLevel& L, const TZ* z, const double* pold, double* pnew, double* q,
+           const double* scal, double* partials, hipStream_t s) {
+    hipLaunchKernelGGL((k_cg_pq<TZ>), l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), z,
+                       pold, pnew, q, scal, partials);
+    HIPCHECK(hipGetLastError());
+}
+template void cg_pq<double>(const FineLevel&, const double*, const double*, double*, double*,
+                            const double*, double*, hipStream_t);
+template void cg_pq<float>(const FineLevel&, const float*, const double*, double*, double*,
+                           const double*, double*, hipStream_t);
+
+// x += alpha p; r -= alpha q; partials of r.r.  Skipped (x, r untouched) when the step
+// broke down: p.q <= 0, r.z <= 0 or a non-finite alpha.
+__global__ void __launch_bounds__(kThreads) k_cg_xr(L0View<double> v, double* __restrict__ xv,
+                                                    const double* __restrict__ p,
+                                                    double* __restrict__ r,
+                                                    const double* __restrict__ q,
+                                                    const double* __restrict__ scal, double* part) {
+    __shared__ double lds[kThreads / kWave];
+    const double alpha = scal[S_ALPHA];
+    const bool ok = scal[S_PQ] > 0.0 && scal[S_RHO] > 0.0 && isfinite(alpha);
+    double acc = 0.0;
+    L0_LOOP_BEGIN
+    if (inb && n.unk) {
+        double ri = r[n.i];
+        if (ok) {
+            xv[n.i] += alpha * p[n.i];
+            ri -= alpha * q[n.i];
+            r[n.i] = ri;
+        }
+        acc += ri * ri;
+    }
+    L0_LOOP_END
+    double sb = block_sum(acc, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = sb;
+}
+
+void cg_xr(const FineLevel& L, double* x, const double* p, double* r, const double* q,
+           const double* scal, double* partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_xr, l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), x, p, r,
+                       q, scal, partials);
+    HIPCHECK(hipGetLastError());
+}
+
+__global__ void __launch_bounds__(kThreads) k_cg_unscale(L0View<double> v, const double* __restrict__ sigma,
+                                                         const double* __restrict__ xv,
+                                                         double* __restrict__ out) {
+    L0_LOOP_BEGIN
+    if (inb) out[n.i] = n.unk ? sigma[n.i] * xv[n.i] : 0.0;
+    L0_LOOP_END
+}
+
+void cg_unscale(const FineLevel& L, const double* x, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_unscale, l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(),
+                       L.sigma, x, out);
+    HIPCHECK(hipGetLastError());
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_l0_dot(L0View<double> v, const double* __restrict__ a,
+                                                     const T* __restrict__ b, double* part) {
+    __shared__ double lds[kThreads / kWave];
+    double acc = 0.0;
+    L0_LOOP_BEGIN
+    if (inb && n.unk) acc += a[n.i] * (double)b[n.i];
+    L0_LOOP_END
+    double sb = block_sum(acc, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = sb;
+}
+
+template <typename T>
+void l0_dot(const FineLevel& L, const double* a, const T* b, double* partials, hipStream_t s) {
+    hipLaunchKernelGGL((k_l0_dot<T>), l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), a,
+                       b, partials);
+    HIPCHECK(hipGetLastError());
+}
+template void l0_dot<double>(const FineLevel&, const double*, const double*, double*, hipStream_t);
+template void l0_dot<float>(const FineLevel&, const double*, const float*, double*, hipStream_t);
+
+// ================================================================ reporting
+
+__global__ void __launch_bounds__(kThreads) k_l0_export(L0View<double> v, double* out, long nbox) {
+    L0_LOOP_BEGIN
+    if (inb) {
+        double cf[6] = {0, 0, 0, 0, 0, 0};
+        double dg = 0.0;
+        if (n.unk) {
+            dg = 1.0;
+            for (int d = 0; d < 6; ++d) cf[d] = n.irr ? v.tab[d][n.rank] : v.c[d >> 1];
+        }
+        out[13 * nbox + n.i] = dg;
+        for (int d = 0; d < 6; ++d) out[(long)dir_to_k(d) * nbox + n.i] = cf[d];
+    }
+    L0_LOOP_END
+}
+
+void l0_export_coef(const FineLevel& L, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_l0_export, l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), out,
+                       L.nbox);
+    HIPCHECK(hipGetLastError());
+}
+
+__global__ void k_tab_to_fp32(const double* a, float* b, long n) {
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) b[t] = (float)a[t];
+}
+
+void l0_to_fp32(FineLevel& L, hipStream_t s) {
+    (void)L;
+    (void)s;  // the fp32 table is written together with the fp64 one
+}
+
+}  // namespace saamg

@@ -1,0 +1,107 @@
+// Host-side launchers of the library's kernels.
+#pragma once
+
+#include "common.h"
+
+namespace saamg {
+
+// Scalar slots in the per-solve device array `scal`.
+enum Slot {
+    S_RHO = 0, S_RHO_PREV, S_ALPHA, S_BETA, S_PQ, S_RR, S_BB, S_R0,
+    S_INVN, S_LAM, S_RT, S_NSLOTS = 16
+};
+// Finalisation ops: how the summed partials update `scal`.
+enum FinOp { FIN_STORE = 0, FIN_ALPHA, FIN_RHO_INIT, FIN_RHO, FIN_POWER, FIN_NORM, FIN_RESTORE_RHO };
+// Chebyshev step kinds.
+enum ChebMode { CHEB_ZERO1 = 0, CHEB_ZERO2, CHEB_FIRST, CHEB_NEXT };
+
+// Number of partial sums (blocks) written by the level-0 reduction kernels.
+long l0_blocks(const FineLevel& L);
+long lc_blocks(const CoarseLevel& C);
+
+void finalize(const double* partials, long nblk, int nq, double* scal, int op, int dst,
+              hipStream_t s);
+
+// ---- level 0: build
+void l0_scatter_nwidx(int32_t* nwidx, const int64_t* nodes, long n, hipStream_t s);
+void l0_build_masks(FineLevel& L, const uint8_t* mask, const int32_t* nwidx, int32_t* cnt_irr,
+                    int32_t* cnt_unk, hipStream_t s);
+void exclusive_scan(const int32_t* in, int32_t* out, long n, int64_t* total, hipStream_t s);
+void l0_build_table(FineLevel& L, const uint8_t* mask, const int32_t* nwidx, const double* nwfrac,
+                    int variant, double sigma0, hipStream_t s);
+void l0_unknown_list(const FineLevel& L, long* out, hipStream_t s);  // requires n_unknowns slots
+
+// ---- level 0: operators
+template <typename T>
+void l0_apply(const FineLevel& L, bool trans, const T* x, T* y, hipStream_t s);
+void l0_power_start(const FineLevel& L, double* v, hipStream_t s);
+void l0_power_step(const FineLevel& L, const double* v, const double* scal, double* w,
+                   double* partials, hipStream_t s);
+template <typename TF, typename T>
+void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* din, T* xout,
+             T* dout, double c1, double c2, double c2_0, double* dot_partials, hipStream_t s);
+template <typename TF, typename T>
+void l0_residual(const FineLevel& L, const TF* f, const T* x, T* r, hipStream_t s);
+template <typename T>
+void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* fc, double omega,
+                 hipStream_t s);
+template <typename T>
+void l0_prolong(const FineLevel& L, const CoarseLevel& C, const T* v, T* x, double omega,
+                hipStream_t s);
+
+// ---- level 0: CG (fp64)
+void cg_init(const FineLevel& L, const double* b, const double* x0, double* bs, double* x,
+             hipStream_t s);
+void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
+              hipStream_t s);
+template <typename TZ>
+void cg_pq(const FineLevel& L, const TZ* z, const double* pold, double* pnew, double* q,
+           const double* scal, double* partials, hipStream_t s);
+void cg_xr(const FineLevel& L, double* x, const double* p, double* r, const double* q,
+           const double* scal, double* partials, hipStream_t s);
+void cg_unscale(const FineLevel& L, const double* x, double* out, hipStream_t s);
+// partial sums of a . b over level-0 unknowns (one per block of l0_blocks)
+template <typename T>
+void l0_dot(const FineLevel& L, const double* a, const T* b, double* partials, hipStream_t s);
+
+// ---- levels >= 1
+template <typename T>
+void lc_apply(const CoarseLevel& C, bool trans, const T* x, T* y, hipStream_t s);
+void lc_power_start(const CoarseLevel& C, double* v, hipStream_t s);
+void lc_power_step(const CoarseLevel& C, const double* v, const double* scal, double* w,
+                   double* partials, hipStream_t s);
+template <typename T>
+void lc_cheb(const CoarseLevel& C, int mode, const T* f, const T* xin, const T* din, T* xout,
+             T* dout, double c1, double c2, double c2_0, hipStream_t s);
+template <typename T>
+void lc_residual(const CoarseLevel& C, const T* f, const T* x, T* r, hipStream_t s);
+template <typename T>
+void lc_restrict(const CoarseLevel& F, const CoarseLevel& C, const T* r, T* fc, double omega,
+                 hipStream_t s);
+template <typename T>
+void lc_prolong(const CoarseLevel& F, const CoarseLevel& C, const T* v, T* x, double omega,
+                hipStream_t s);
+
+// ---- setup of levels >= 1
+void rap_from_l0(const FineLevel& L, const CoarseLevel& C, double omega, hipStream_t s);
+void rap_from_lc(const CoarseLevel& F, const CoarseLevel& C, double omega, hipStream_t s);
+void lc_finish(CoarseLevel& C, int32_t* counts, hipStream_t s);    // invD and unknown count
+void lc_to_fp32(CoarseLevel& C, hipStream_t s);
+void l0_to_fp32(FineLevel& L, hipStream_t s);
+void lc_unknown_list(const CoarseLevel& C, long* out, int32_t* counter, hipStream_t s);
+
+// ---- coarsest level
+void dense_from_l0(const FineLevel& L, const long* cidx, const int32_t* cmap, int nL, double* A,
+                   hipStream_t s);
+void dense_from_lc(const CoarseLevel& C, const long* cidx, const int32_t* cmap, int nL, double* A,
+                   hipStream_t s);
+void dense_invert(double* A, int n, hipStream_t s);
+void fill_cmap(int32_t* cmap, const long* cidx, int nL, hipStream_t s);
+template <typename TF, typename T>
+void coarse_solve(const double* Ainv, const long* cidx, int nL, const TF* f, T* x, hipStream_t s);
+void f2d_copy(const float* a, double* b, long n, hipStream_t s);
+
+// ---- reporting helpers
+void l0_export_coef(const FineLevel& L, double* out /* device [27][nbox] */, hipStream_t s);
+
+}  // namespace saamg

@@ -1,0 +1,1104 @@
+// Host driver: hierarchy setup, V-cycle, PCG state machine and the C interface.
+//
+// Paper: Section 2 (operator and scaling), Section 3 (PCG with an SA-AMG V-cycle,
+// Algorithm 1), Table 1 (coarse size limit 1000), Section 5 (relative-residual stop).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+
+namespace saamg {
+
+static thread_local std::string g_err;
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) throw HipError{e, what};
+}
+
+void* dmalloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw ApiError{SAAMG_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+    HIPCHECK(hipMemset(p, 0, bytes));
+    HIPCHECK(hipStreamSynchronize(nullptr));  // zero-filled before any stream uses it
+    return p;
+}
+
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+ChebCoef cheb_coefficients(double lam_hi, double ratio, int degree) {
+    ChebCoef c{};
+    c.degree = degree;
+    const double lo = lam_hi / ratio;
+    const double theta = 0.5 * (lam_hi + lo), delta = 0.5 * (lam_hi - lo);
+    const double s1 = theta / delta;
+    double rho = 1.0 / s1;
+    c.c1[0] = 0.0;
+    c.c2[0] = 1.0 / theta;
+    for (int k = 1; k < degree; ++k) {
+        const double rn = 1.0 / (2.0 * s1 - rho);
+        c.c1[k] = rn * rho;
+        c.c2[k] = 2.0 * rn / delta;
+        rho = rn;
+    }
+    return c;
+}
+
+static double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ------------------------------------------------------------------ V-cycle buffers
+
+template <typename T>
+struct VBuf {
+    std::vector<T*> f, xa, xb, d;  // per level; level 0 has no f (the PCG residual is read)
+    void alloc(const saamg_hierarchy* H) {
+        const int L = H->n_levels;
+        f.assign(L, nullptr);
+        xa.assign(L, nullptr);
+        xb.assign(L, nullptr);
+        d.assign(L, nullptr);
+        for (int l = 0; l < L; ++l) {
+            const long n = (l == 0) ? H->l0.nbox : H->lc[l - 1].nstore;
+            xa[l] = (T*)dmalloc(sizeof(T) * n);
+            if (l < L - 1) {
+                xb[l] = (T*)dmalloc(sizeof(T) * n);
+                d[l] = (T*)dmalloc(sizeof(T) * n);
+            }
+            if (l > 0) f[l] = (T*)dmalloc(sizeof(T) * n);
+        }
+    }
+    void release() {
+        for (auto* v : {&f, &xa, &xb, &d})
+            for (T* p : *v) dfree(p);
+        f.clear();
+        xa.clear();
+        xb.clear();
+        d.clear();
+    }
+    int64_t bytes(const saamg_hierarchy* H) const {
+        int64_t b = 0;
+        for (int l = 0; l < H->n_levels; ++l) {
+            const long n = (l == 0) ? H->l0.nbox : H->lc[l - 1].nstore;
+            int cnt = 1 + (l < H->n_levels - 1 ? 2 : 0) + (l > 0 ? 1 : 0);
+            b += (int64_t)cnt * n * sizeof(T);
+        }
+        return b;
+    }
+};
+
+template <typename T>
+static void chebstep(const saamg_hierarchy* H, int l, int mode, const double* f0, const T* fl,
+                     const T* xin, const T* din, T* xout, T* dout, double c1, double c2, double c20,
+                     double* dot, hipStream_t s) {
+    if (l == 0)
+        l0_cheb<double, T>(H->l0, mode, f0, xin, din, xout, dout, c1, c2, c20, dot, s);
+    else
+        lc_cheb<T>(H->lc[l - 1], mode, fl, xin, din, xout, dout, c1, c2, c20, s);
+}
+
+// Algorithm 1 on level l with a zero initial guess; returns the buffer holding x_l.  On
+// level 0 the right-hand side is the fp64 PCG residual f0 and the result goes to `out`,
+// with partial sums of f0 . out in `dot` (nullable).
+template <typename T>
+static T* vcycle(const saamg_hierarchy* H, VBuf<T>& B, int l, const double* f0, T* out,
+                 double* dot, hipStream_t s) {
+    const bool fine = (l == 0);
+    if (l == H->n_levels - 1) {
+        T* x = fine ? out : B.xa[l];
+        if (fine) {
+            coarse_solve<double, T>(H->Ainv, H->cidx, H->nL, f0, x, s);
+            if (dot) l0_dot<T>(H->l0, f0, x, dot, s);
+        } else {
+            coarse_solve<T, T>(H->Ainv, H->cidx, H->nL, B.f[l], x, s);
+        }
+        return x;
+    }
+    const LevelParams& P = H->par[l];
+    const ChebCoef& c = P.cheb;
+    const T* fl = fine ? nullptr : B.f[l];
+    T* x = B.xa[l];
+    T* other = B.xb[l];
+    T* d = B.d[l];
+    // pre-smoothing from a zero guess
+    if (c.degree == 1) {
+        chebstep<T>(H, l, CHEB_ZERO1, f0, fl, nullptr, nullptr, x, nullptr, 0, 0, c.c2[0],
+                    nullptr, s);
+    } else {
+        chebstep<T>(H, l, CHEB_ZERO2, f0, fl, nullptr, nullptr, x, c.degree > 2 ? d : nullptr,
+                    c.c1[1], c.c2[1], c.c2[0], nullptr, s);
+        for (int k = 2; k < c.degree; ++k) {
+            chebstep<T>(H, l, CHEB_NEXT, f0, fl, x, d, other, d, c.c1[k], c.c2[k], c.c2[0],
+                        nullptr, s);
+            std::swap(x, other);
+        }
+    }
+    // residual and restriction
+    if (fine) {
+        l0_residual<double, T>(H->l0, f0, x, other, s);
+        l0_restrict<T>(H->l0, H->lc[0], other, B.f[1], P.omega, s);
+    } else {
+        lc_residual<T>(H->lc[l - 1], fl, x, other, s);
+        lc_restrict<T>(H->lc[l - 1], H->lc[l], other, B.f[l + 1], P.omega, s);
+    }
+    T* v = vcycle<T>(H, B, l + 1, nullptr, nullptr, nullptr, s);
+    // coarse-grid correction
+    if (fine)
+        l0_prolong<T>(H->l0, H->lc[0], v, x, P.omega, s);
+    else
+        lc_prolong<T>(H->lc[l - 1], H->lc[l], v, x, P.omega, s);
+    // post-smoothing
+    for (int k = 0; k < c.degree; ++k) {
+        const bool last = (k == c.degree - 1);
+        T* dst = (last && fine) ? out : other;
+        chebstep<T>(H, l, k == 0 ? CHEB_FIRST : CHEB_NEXT, f0, fl, x, d, dst, last ? nullptr : d,
+                    c.c1[k], c.c2[k], c.c2[0], (last && fine) ? dot : nullptr, s);
+        other = x;
+        x = dst;
+    }
+    return x;
+}
+
+}  // namespace saamg
+
+using namespace saamg;
+
+// ------------------------------------------------------------------ solve state
+
+struct saamg_state {
+    saamg_hierarchy* H = nullptr;
+    hipStream_t s = nullptr;
+    double tol = 1e-8;
+    int max_iter = 0;
+    bool mixed = false;
+    double *x = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *bs = nullptr;
+    void* z = nullptr;
+    int pcur = 0;
+    VBuf<float> vf;
+    VBuf<double> vd;
+    double* part = nullptr;
+    long npart = 0;
+    double* scal = nullptr;
+    double* hscal = nullptr;  // pinned
+    hipEvent_t ev = nullptr;
+    int iter = 0, status = SAAMG_OK, done = 0, repl = 0;
+    double bnorm = 0, rel_true = 0, rel_rec = 0;
+    double t_ms = 0;
+    std::chrono::steady_clock::time_point t0;
+    int64_t bytes = 0;
+};
+
+namespace saamg {
+
+static void state_alloc(saamg_state* S, saamg_hierarchy* H) {
+    S->H = H;
+    S->mixed = H->opt.precision == SAAMG_MIXED;
+    const long n = H->l0.nbox;
+    S->x = (double*)dmalloc(8 * n);
+    S->r = (double*)dmalloc(8 * n);
+    S->p[0] = (double*)dmalloc(8 * n);
+    S->p[1] = (double*)dmalloc(8 * n);
+    S->q = (double*)dmalloc(8 * n);
+    S->bs = (double*)dmalloc(8 * n);
+    S->z = dmalloc((S->mixed ? 4 : 8) * n);
+    S->bytes = 48L * n + (S->mixed ? 4 : 8) * n;
+    if (S->mixed) {
+        S->vf.alloc(H);
+        S->bytes += S->vf.bytes(H);
+    } else {
+        S->vd.alloc(H);
+        S->bytes += S->vd.bytes(H);
+    }
+    S->npart = std::max<long>(l0_blocks(H->l0), 1);
+    S->part = (double*)dmalloc(sizeof(double) * 3 * S->npart);
+    S->scal = (double*)dmalloc(sizeof(double) * S_NSLOTS);
+    HIPCHECK(hipHostMalloc((void**)&S->hscal, sizeof(double) * S_NSLOTS, hipHostMallocDefault));
+    HIPCHECK(hipEventCreateWithFlags(&S->ev, hipEventDisableTiming));
+}
+
+static void state_release(saamg_state* S) {
+    for (double* p : {S->x, S->r, S->p[0], S->p[1], S->q, S->bs}) dfree(p);
+    dfree(S->z);
+    S->vf.release();
+    S->vd.release();
+    dfree(S->part);
+    dfree(S->scal);
+    if (S->hscal) (void)hipHostFree(S->hscal);
+    if (S->ev) (void)hipEventDestroy(S->ev);
+    S->x = S->r = S->p[0] = S->p[1] = S->q = S->bs = nullptr;
+    S->z = nullptr;
+    S->part = S->scal = S->hscal = nullptr;
+    S->ev = nullptr;
+}
+
+static void read_scal(saamg_state* S) {
+    HIPCHECK(hipMemcpyAsync(S->hscal, S->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
+                            S->s));
+    HIPCHECK(hipStreamSynchronize(S->s));
+}
+
+static void precond(saamg_state* S) {
+    const saamg_hierarchy* H = S->H;
+    if (S->mixed)
+        vcycle<float>(H, S->vf, 0, S->r, (float*)S->z, S->part, S->s);
+    else
+        vcycle<double>(H, S->vd, 0, S->r, (double*)S->z, S->part, S->s);
+}
+
+// True residual b - A x into `dst`; returns ||dst||^2.
+static double true_residual(saamg_state* S, double* dst) {
+    cg_resid(S->H->l0, S->bs, S->x, dst, S->part, S->s);
+    finalize(S->part, l0_blocks(S->H->l0), 2, S->scal, FIN_STORE, S_RT, S->s);
+    read_scal(S);
+    return S->hscal[S_RT];
+}
+
+static void state_start(saamg_state* S, const double* b, const double* x0) {
+    const saamg_hierarchy* H = S->H;
+    S->iter = 0;
+    S->status = SAAMG_OK;
+    S->done = 0;
+    S->repl = 0;
+    S->pcur = 0;
+    S->t0 = std::chrono::steady_clock::now();
+    cg_init(H->l0, b, x0, S->bs, S->x, S->s);
+    cg_resid(H->l0, S->bs, S->x, S->r, S->part, S->s);
+    finalize(S->part, l0_blocks(H->l0), 2, S->scal, FIN_STORE, S_RR, S->s);
+    HIPCHECK(hipMemsetAsync(S->p[0], 0, 8 * H->l0.nbox, S->s));
+    read_scal(S);
+    const double rr = S->hscal[S_RR], bb = S->hscal[S_BB];
+    S->bnorm = std::sqrt(bb);
+    if (!std::isfinite(rr) || !std::isfinite(bb)) {
+        S->status = SAAMG_NONFINITE;
+        S->done = 1;
+        S->rel_true = S->rel_rec = NAN;
+        return;
+    }
+    if (bb == 0.0) {
+        HIPCHECK(hipMemsetAsync(S->x, 0, 8 * H->l0.nbox, S->s));
+        S->done = 1;
+        S->rel_true = S->rel_rec = 0.0;
+        return;
+    }
+    const double rel = std::sqrt(rr) / S->bnorm;
+    S->rel_true = S->rel_rec = rel;
+    if (rel <= S->tol) {
+        S->done = 1;
+        return;
+    }
+    if (S->max_iter <= 0) {
+        S->status = SAAMG_NOT_CONVERGED;
+        S->done = 1;
+        return;
+    }
+    precond(S);
+    finalize(S->part, l0_blocks(H->l0), 1, S->scal, FIN_RHO_INIT, 0, S->s);
+}
+
+// Queue one PCG step plus the (speculative) preconditioner of the next one.
+static void state_enqueue(saamg_state* S) {
+    const saamg_hierarchy* H = S->H;
+    const long nb = l0_blocks(H->l0);
+    double* pold = S->p[S->pcur];
+    double* pnew = S->p[1 - S->pcur];
+    if (S->mixed)
+        cg_pq<float>(H->l0, (const float*)S->z, pold, pnew, S->q, S->scal, S->part, S->s);
+    else
+        cg_pq<double>(H->l0, (const double*)S->z, pold, pnew, S->q, S->scal, S->part, S->s);
+    finalize(S->part, nb, 1, S->scal, FIN_ALPHA, 0, S->s);
+    cg_xr(H->l0, S->x, pnew, S->r, S->q, S->scal, S->part, S->s);
+    finalize(S->part, nb, 1, S->scal, FIN_STORE, S_RR, S->s);
+    HIPCHECK(hipMemcpyAsync(S->hscal, S->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
+                            S->s));
+    HIPCHECK(hipEventRecord(S->ev, S->s));
+    S->pcur = 1 - S->pcur;
+    precond(S);
+    finalize(S->part, nb, 1, S->scal, FIN_RHO, 0, S->s);
+}
+
+static void state_complete(saamg_state* S) {
+    HIPCHECK(hipEventSynchronize(S->ev));
+    S->iter += 1;
+    const double pq = S->hscal[S_PQ], rho = S->hscal[S_RHO], rr = S->hscal[S_RR];
+    const double alpha = S->hscal[S_ALPHA];
+    if (!std::isfinite(pq) || !std::isfinite(rho) || !std::isfinite(alpha)) {
+        S->status = SAAMG_NONFINITE;
+        S->done = 1;
+        S->rel_true = S->rel_rec = NAN;
+        return;
+    }
+    if (pq <= 0.0 || rho <= 0.0) {
+        S->status = SAAMG_BREAKDOWN;
+        S->done = 1;
+        S->rel_true = std::sqrt(true_residual(S, S->q)) / S->bnorm;
+        return;
+    }
+    if (!std::isfinite(rr)) {
+        S->status = SAAMG_NONFINITE;
+        S->done = 1;
+        S->rel_true = S->rel_rec = NAN;
+        return;
+    }
+    S->rel_rec = std::sqrt(rr) / S->bnorm;
+    if (S->rel_rec <= S->tol) {
+        const double rt = true_residual(S, S->r);
+        S->rel_true = std::sqrt(rt) / S->bnorm;
+        if (S->rel_true <= S->tol) {
+            S->done = 1;
+            return;
+        }
+        // continue from the true residual: redo the preconditioner on it
+        S->repl += 1;
+        const long nb = l0_blocks(S->H->l0);
+        finalize(S->part, nb, 0, S->scal, FIN_RESTORE_RHO, 0, S->s);
+        precond(S);
+        finalize(S->part, nb, 1, S->scal, FIN_RHO, 0, S->s);
+    }
+    if (S->iter >= S->max_iter) {
+        S->status = SAAMG_NOT_CONVERGED;
+        S->done = 1;
+        S->rel_true = std::sqrt(true_residual(S, S->q)) / S->bnorm;
+    }
+}
+
+static void state_fill_result(const saamg_state* S, saamg_result* res) {
+    if (!res) return;
+    res->iterations = S->iter;
+    res->status = S->status;
+    res->replacements = S->repl;
+    res->rel_res_true = S->rel_true;
+    res->rel_res_recursive = S->rel_rec;
+    res->t_solve_ms = S->t_ms;
+}
+
+// ------------------------------------------------------------------ setup
+
+static long seg_count(int nx, int ny, int nz) { return (long)((nx + 63) / 64) * ny * nz; }
+
+static void power_lambda(saamg_hierarchy* H, int l, hipStream_t s, double* out_lam) {
+    const long n = (l == 0) ? H->l0.nbox : H->lc[l - 1].nstore;
+    const long nb = (l == 0) ? l0_blocks(H->l0) : lc_blocks(H->lc[l - 1]);
+    double* v = (double*)dmalloc(8 * n);
+    double* w = (double*)dmalloc(8 * n);
+    double* part = (double*)dmalloc(sizeof(double) * 3 * nb);
+    double* scal = (double*)dmalloc(sizeof(double) * S_NSLOTS);
+    const double one = 1.0;
+    HIPCHECK(hipMemcpy(scal + S_INVN, &one, sizeof(double), hipMemcpyHostToDevice));
+    if (l == 0)
+        l0_power_start(H->l0, v, s);
+    else
+        lc_power_start(H->lc[l - 1], v, s);
+    for (int it = 0; it < H->opt.eig_iters; ++it) {
+        if (l == 0)
+            l0_power_step(H->l0, v, scal, w, part, s);
+        else
+            lc_power_step(H->lc[l - 1], v, scal, w, part, s);
+        finalize(part, nb, 3, scal, FIN_POWER, 0, s);
+        std::swap(v, w);
+    }
+    double lam = 0;
+    HIPCHECK(hipMemcpyAsync(&lam, scal + S_LAM, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    dfree(v);
+    dfree(w);
+    dfree(part);
+    dfree(scal);
+    *out_lam = lam;
+}
+
+static CoarseLevel make_coarse(int fmx, int fmy, int fmz, int sym) {
+    CoarseLevel C;
+    C.mx = (fmx + 2) / 3;
+    C.my = (fmy + 2) / 3;
+    C.mz = (fmz + 2) / 3;
+    C.sx = C.mx + 2;
+    C.sy = C.my + 2;
+    C.sz = C.mz + 2;
+    C.sxy = (long)C.sx * C.sy;
+    C.nstore = C.sxy * C.sz;
+    C.sym = sym;
+    for (int k = 0; k < 27; ++k)
+        if (!sym || k >= 13) C.coef64[k] = (double*)dmalloc(8 * C.nstore);
+    C.invD64 = (double*)dmalloc(8 * C.nstore);
+    return C;
+}
+
+static void free_coarse(CoarseLevel& C) {
+    for (int k = 0; k < 27; ++k) {
+        dfree(C.coef64[k]);
+        dfree(C.coef32[k]);
+        C.coef64[k] = nullptr;
+        C.coef32[k] = nullptr;
+    }
+    dfree(C.invD64);
+    dfree(C.invD32);
+    C.invD64 = nullptr;
+    C.invD32 = nullptr;
+}
+
+static int64_t coarse_bytes(const CoarseLevel& C, bool mixed) {
+    const int na = C.sym ? 14 : 27;
+    return (int64_t)(na + 1) * C.nstore * (mixed ? 12 : 8);
+}
+
+static void validate_options(const saamg_options& o) {
+    if (o.precision != SAAMG_FP64 && o.precision != SAAMG_MIXED)
+        throw ApiError{SAAMG_INVALID_ARG, "precision must be SAAMG_FP64 or SAAMG_MIXED"};
+    if (o.max_levels < 1 || o.max_levels > SAAMG_MAX_LEVELS)
+        throw ApiError{SAAMG_INVALID_ARG, "max_levels must be in 1..16"};
+    if (o.max_coarse < 1 || o.max_coarse > 8000)
+        throw ApiError{SAAMG_INVALID_ARG, "max_coarse must be in 1..8000"};
+    if (o.cheb_degree < 1 || o.cheb_degree > 8)
+        throw ApiError{SAAMG_INVALID_ARG, "cheb_degree must be in 1..8"};
+    if (!(o.cheb_ratio > 1.0) || !(o.cheb_boost > 0.0) || !(o.omega_scale > 0.0))
+        throw ApiError{SAAMG_INVALID_ARG, "cheb_ratio must exceed 1; boost and omega_scale > 0"};
+    if (o.eig_iters < 1 || o.eig_iters > 1000)
+        throw ApiError{SAAMG_INVALID_ARG, "eig_iters must be in 1..1000"};
+}
+
+static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const saamg_options* opt,
+                                   hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!dom || !dom->mask) throw ApiError{SAAMG_INVALID_ARG, "domain or mask is NULL"};
+    const int nx = dom->nx, ny = dom->ny, nz = dom->nz;
+    if (nx < 3 || ny < 3 || nz < 3) throw ApiError{SAAMG_INVALID_ARG, "box must be at least 3^3"};
+    if ((double)nx * ny * nz > 2.0e9) throw ApiError{SAAMG_INVALID_ARG, "box too large"};
+    if (!(dom->hx > 0) || !(dom->hy > 0) || !(dom->hz > 0))
+        throw ApiError{SAAMG_INVALID_ARG, "grid spacings must be positive"};
+    if (variant < SAAMG_VARIANT_CONST || variant > SAAMG_VARIANT_QUAD)
+        throw ApiError{SAAMG_INVALID_ARG, "unknown boundary variant"};
+    if (dom->n_wall < 0 || (dom->n_wall > 0 && (!dom->wall_node || !dom->wall_dir || !dom->wall_s)))
+        throw ApiError{SAAMG_INVALID_ARG, "wall arrays are NULL"};
+    saamg_options o;
+    if (opt)
+        o = *opt;
+    else
+        saamg_default_options(&o);
+    validate_options(o);
+
+    const long nxy = (long)nx * ny, nbox = nxy * nz;
+    const uint8_t* m = dom->mask;
+    long n_unk = 0;
+    for (long k = 0; k < nz; ++k)
+        for (long j = 0; j < ny; ++j)
+            for (long i = 0; i < nx; ++i) {
+                const long idx = i + nx * j + nxy * k;
+                if (!m[idx]) continue;
+                if (i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1)
+                    throw ApiError{SAAMG_INVALID_ARG, "an unknown lies on a face of the box"};
+                ++n_unk;
+            }
+    if (n_unk == 0) throw ApiError{SAAMG_INVALID_ARG, "the domain has no unknowns"};
+
+    // wall fractions below 1, grouped per node (the constant rule ignores them)
+    std::vector<std::pair<int64_t, int>> ent;
+    const long step[6] = {-1, 1, -(long)nx, (long)nx, -nxy, nxy};
+    for (int64_t e = 0; e < dom->n_wall; ++e) {
+        const int64_t node = dom->wall_node[e];
+        const int d = dom->wall_dir[e];
+        const double sv = dom->wall_s[e];
+        if (node < 0 || node >= nbox || d > 5)
+            throw ApiError{SAAMG_INVALID_ARG, "wall entry out of range"};
+        if (!m[node] || m[node + step[d]])
+            throw ApiError{SAAMG_INVALID_ARG,
+                           "wall entry must name an unknown whose neighbour is not an unknown"};
+        if (!(sv > 1e-12) || !(sv <= 1.0))
+            throw ApiError{SAAMG_INVALID_ARG, "wall fraction must lie in (1e-12, 1]"};
+        if (sv < 1.0 && variant != SAAMG_VARIANT_CONST) ent.push_back({node * 8 + d, (int)e});
+    }
+    std::sort(ent.begin(), ent.end());
+    std::vector<int64_t> nw_nodes;
+    std::vector<double> nw_frac;
+    for (size_t t = 0; t < ent.size(); ++t) {
+        if (t > 0 && ent[t].first == ent[t - 1].first)
+            throw ApiError{SAAMG_INVALID_ARG, "duplicate wall entry"};
+        const int64_t node = ent[t].first / 8;
+        const int d = (int)(ent[t].first % 8);
+        if (nw_nodes.empty() || nw_nodes.back() != node) {
+            nw_nodes.push_back(node);
+            for (int q = 0; q < 6; ++q) nw_frac.push_back(1.0);
+        }
+        nw_frac[6 * (nw_nodes.size() - 1) + d] = dom->wall_s[ent[t].second];
+    }
+
+    saamg_hierarchy* H = new saamg_hierarchy();
+    try {
+        HIPCHECK(hipGetDevice(&H->device));
+        H->variant = variant;
+        H->opt = o;
+        H->sym = variant != SAAMG_VARIANT_QUAD;
+        FineLevel& L = H->l0;
+        L.nx = nx;
+        L.ny = ny;
+        L.nz = nz;
+        L.nsegx = (nx + 63) / 64;
+        L.nxy = nxy;
+        L.nbox = nbox;
+        L.nseg = seg_count(nx, ny, nz);
+        L.h[0] = dom->hx;
+        L.h[1] = dom->hy;
+        L.h[2] = dom->hz;
+        L.unk = (uint64_t*)dmalloc(8 * L.nseg);
+        L.irr = (uint64_t*)dmalloc(8 * L.nseg);
+        L.base = (int32_t*)dmalloc(4 * L.nseg);
+        L.sigma = (double*)dmalloc(8 * nbox);
+
+        uint8_t* d_mask = (uint8_t*)dmalloc(nbox);
+        int32_t* d_nwidx = (int32_t*)dmalloc(4 * nbox);
+        int64_t* d_nwnodes = (int64_t*)dmalloc(8 * std::max<size_t>(nw_nodes.size(), 1));
+        double* d_nwfrac = (double*)dmalloc(8 * std::max<size_t>(nw_frac.size(), 1));
+        int32_t* cnt_irr = (int32_t*)dmalloc(4 * L.nseg);
+        int32_t* cnt_unk = (int32_t*)dmalloc(4 * L.nseg);
+        int64_t* d_tot = (int64_t*)dmalloc(16);
+        HIPCHECK(hipMemcpy(d_mask, m, nbox, hipMemcpyHostToDevice));
+        HIPCHECK(hipMemset(d_nwidx, 0xff, 4 * nbox));
+        if (!nw_nodes.empty()) {
+            HIPCHECK(hipMemcpy(d_nwnodes, nw_nodes.data(), 8 * nw_nodes.size(), hipMemcpyHostToDevice));
+            HIPCHECK(hipMemcpy(d_nwfrac, nw_frac.data(), 8 * nw_frac.size(), hipMemcpyHostToDevice));
+        }
+        l0_scatter_nwidx(d_nwidx, d_nwnodes, (long)nw_nodes.size(), s);
+        l0_build_masks(L, d_mask, d_nwidx, cnt_irr, cnt_unk, s);
+        exclusive_scan(cnt_irr, L.base, L.nseg, d_tot, s);
+        exclusive_scan(cnt_unk, nullptr, L.nseg, d_tot + 1, s);
+        int64_t tots[2];
+        HIPCHECK(hipMemcpyAsync(tots, d_tot, 16, hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        L.n_irr = tots[0];
+        L.n_unknowns = tots[1];
+        if (L.n_unknowns != n_unk) throw ApiError{SAAMG_HIP_ERROR, "unknown count mismatch"};
+        L.tab64 = (double*)dmalloc(8 * 12 * std::max<long>(L.n_irr, 1));
+        L.tab32 = (float*)dmalloc(4 * 12 * std::max<long>(L.n_irr, 1));
+        const double ih2[3] = {1.0 / (L.h[0] * L.h[0]), 1.0 / (L.h[1] * L.h[1]),
+                               1.0 / (L.h[2] * L.h[2])};
+        const double sigma0 = 1.0 / std::sqrt(2.0 * ih2[0] + 2.0 * ih2[1] + 2.0 * ih2[2]);
+        for (int a = 0; a < 3; ++a) L.c64[a] = -(sigma0 * (1.0 * ih2[a])) * sigma0;
+        l0_build_table(L, d_mask, d_nwidx, d_nwfrac, variant, sigma0, s);
+        HIPCHECK(hipStreamSynchronize(s));
+        for (void* p : {(void*)d_mask, (void*)d_nwidx, (void*)d_nwnodes, (void*)d_nwfrac,
+                        (void*)cnt_irr, (void*)cnt_unk, (void*)d_tot})
+            dfree(p);
+        H->bytes = 20L * L.nseg + 8L * nbox + 12L * 12 * L.n_irr;
+
+        // hierarchy (Section 3.2): coarsen until at most max_coarse unknowns
+        long n_cur = L.n_unknowns;
+        int fmx = nx, fmy = ny, fmz = nz;
+        H->n_levels = 1;
+        while (n_cur > o.max_coarse && H->n_levels < o.max_levels) {
+            const int l = H->n_levels - 1;
+            LevelParams P;
+            power_lambda(H, l, s, &P.lam);
+            if (!(P.lam > 0) || !std::isfinite(P.lam))
+                throw ApiError{SAAMG_HIP_ERROR, "power iteration failed on level " + std::to_string(l)};
+            P.lam_hi = o.cheb_boost * P.lam;
+            P.omega = o.omega_scale / P.lam;
+            P.cheb = cheb_coefficients(P.lam_hi, o.cheb_ratio, o.cheb_degree);
+            CoarseLevel C = make_coarse(fmx, fmy, fmz, H->sym);
+            if (l == 0)
+                rap_from_l0(L, C, P.omega, s);
+            else
+                rap_from_lc(H->lc[l - 1], C, P.omega, s);
+            const long nb = (C.nstore + 255) / 256;
+            int32_t* cnt = (int32_t*)dmalloc(4 * 4 * nb);
+            lc_finish(C, cnt, s);
+            int64_t* tot = (int64_t*)dmalloc(8);
+            exclusive_scan(cnt, nullptr, 4 * nb, tot, s);
+            int64_t nc = 0;
+            HIPCHECK(hipMemcpyAsync(&nc, tot, 8, hipMemcpyDeviceToHost, s));
+            HIPCHECK(hipStreamSynchronize(s));
+            dfree(tot);
+            if (nc >= n_cur) {
+                dfree(cnt);
+                free_coarse(C);
+                break;
+            }
+            C.n_unknowns = nc;
+            if (nc <= o.max_coarse || H->n_levels + 1 == o.max_levels) {
+                // coarsest level: collect its unknowns
+                H->nL = (int)nc;
+                if (nc > 8000) throw ApiError{SAAMG_INVALID_ARG, "coarsest level too large"};
+                H->cidx = (long*)dmalloc(8 * nc);
+                lc_unknown_list(C, H->cidx, cnt, s);
+            }
+            dfree(cnt);
+            H->par.push_back(P);
+            H->lc.push_back(C);
+            H->bytes += coarse_bytes(C, o.precision == SAAMG_MIXED);
+            H->n_levels += 1;
+            n_cur = nc;
+            fmx = C.mx;
+            fmy = C.my;
+            fmz = C.mz;
+        }
+        if (H->n_levels == 1) {
+            if (L.n_unknowns > 8000)
+                throw ApiError{SAAMG_INVALID_ARG, "single-level hierarchy too large for a direct solve"};
+            H->nL = (int)L.n_unknowns;
+            H->cidx = (long*)dmalloc(8 * H->nL);
+            l0_unknown_list(L, H->cidx, s);
+        }
+        // dense inverse of the coarsest operator (fp64)
+        const int nL = H->nL;
+        const long nstore = (H->n_levels == 1) ? L.nbox : H->lc.back().nstore;
+        int32_t* cmap = (int32_t*)dmalloc(4 * nstore);
+        HIPCHECK(hipMemset(cmap, 0xff, 4 * nstore));
+        fill_cmap(cmap, H->cidx, nL, s);
+        H->Ainv = (double*)dmalloc(8L * nL * nL);
+        if (H->n_levels == 1)
+            dense_from_l0(L, H->cidx, cmap, nL, H->Ainv, s);
+        else
+            dense_from_lc(H->lc.back(), H->cidx, cmap, nL, H->Ainv, s);
+        dense_invert(H->Ainv, nL, s);
+        HIPCHECK(hipStreamSynchronize(s));
+        dfree(cmap);
+        H->bytes += 8L * nL * nL + 8L * nL;
+        if (o.precision == SAAMG_MIXED) {
+            for (auto& C : H->lc) {
+                for (int k = 0; k < 27; ++k)
+                    if (C.coef64[k]) C.coef32[k] = (float*)dmalloc(4 * C.nstore);
+                C.invD32 = (float*)dmalloc(4 * C.nstore);
+                lc_to_fp32(C, s);
+            }
+        }
+        HIPCHECK(hipStreamSynchronize(s));
+    } catch (...) {
+        saamg_destroy(H);
+        throw;
+    }
+    H->t_setup_ms = ms_since(t0);
+    return H;
+}
+
+template <class F>
+static int guarded(F&& f) {
+    try {
+        g_err.clear();
+        return f();
+    } catch (const ApiError& e) {
+        g_err = e.msg;
+        return e.status;
+    } catch (const HipError& e) {
+        g_err = std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.where;
+        return SAAMG_HIP_ERROR;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return SAAMG_NOMEM;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return SAAMG_INVALID_ARG;
+    }
+}
+
+// Host logical <-> device storage helpers for the component entry points.
+static long level_nstore(const saamg_hierarchy* H, int l) {
+    return l == 0 ? H->l0.nbox : H->lc[l - 1].nstore;
+}
+static void level_dims(const saamg_hierarchy* H, int l, int* mx, int* my, int* mz) {
+    if (l == 0) {
+        *mx = H->l0.nx;
+        *my = H->l0.ny;
+        *mz = H->l0.nz;
+    } else {
+        *mx = H->lc[l - 1].mx;
+        *my = H->lc[l - 1].my;
+        *mz = H->lc[l - 1].mz;
+    }
+}
+static long storage_index(const saamg_hierarchy* H, int l, int x, int y, int z) {
+    if (l == 0) return x + (long)H->l0.nx * y + H->l0.nxy * z;
+    const CoarseLevel& C = H->lc[l - 1];
+    return (x + 1) + (long)C.sx * (y + 1) + C.sxy * (z + 1);
+}
+
+template <typename T>
+static T* upload_level(const saamg_hierarchy* H, int l, const double* h) {
+    int mx, my, mz;
+    level_dims(H, l, &mx, &my, &mz);
+    std::vector<T> buf(level_nstore(H, l), (T)0);
+    for (int z = 0; z < mz; ++z)
+        for (int y = 0; y < my; ++y)
+            for (int x = 0; x < mx; ++x)
+                buf[storage_index(H, l, x, y, z)] = (T)h[x + (long)mx * (y + (long)my * z)];
+    T* d = (T*)dmalloc(sizeof(T) * buf.size());
+    HIPCHECK(hipMemcpy(d, buf.data(), sizeof(T) * buf.size(), hipMemcpyHostToDevice));
+    return d;
+}
+
+template <typename T>
+static void download_level(const saamg_hierarchy* H, int l, const T* d, double* h) {
+    int mx, my, mz;
+    level_dims(H, l, &mx, &my, &mz);
+    std::vector<T> buf(level_nstore(H, l));
+    HIPCHECK(hipMemcpy(buf.data(), d, sizeof(T) * buf.size(), hipMemcpyDeviceToHost));
+    for (int z = 0; z < mz; ++z)
+        for (int y = 0; y < my; ++y)
+            for (int x = 0; x < mx; ++x)
+                h[x + (long)mx * (y + (long)my * z)] = (double)buf[storage_index(H, l, x, y, z)];
+}
+
+template <typename T>
+static void level_apply_impl(saamg_hierarchy* H, int l, int op, const double* hin, double* hout) {
+    hipStream_t s = nullptr;
+    const int lin = (op == SAAMG_OP_PROLONG) ? l + 1 : l;
+    const int lout = (op == SAAMG_OP_RESTRICT) ? l + 1 : l;
+    T* din = upload_level<T>(H, lin, hin);
+    T* dout = (T*)dmalloc(sizeof(T) * level_nstore(H, lout));
+    T* tmp = (T*)dmalloc(sizeof(T) * level_nstore(H, l));
+    switch (op) {
+        case SAAMG_OP_APPLY:
+        case SAAMG_OP_APPLY_T:
+            if (l == 0)
+                l0_apply<T>(H->l0, op == SAAMG_OP_APPLY_T, din, dout, s);
+            else
+                lc_apply<T>(H->lc[l - 1], op == SAAMG_OP_APPLY_T, din, dout, s);
+            break;
+        case SAAMG_OP_PRESMOOTH: {
+            const ChebCoef& c = H->par[l].cheb;
+            T* x = dout;
+            T* other = tmp;
+            T* d = (T*)dmalloc(sizeof(T) * level_nstore(H, l));
+            auto step = [&](int mode, const T* xi, const T* di, T* xo, T* dd, double c1, double c2) {
+                if (l == 0)
+                    l0_cheb<T, T>(H->l0, mode, din, xi, di, xo, dd, c1, c2, c.c2[0], nullptr, s);
+                else
+                    lc_cheb<T>(H->lc[l - 1], mode, din, xi, di, xo, dd, c1, c2, c.c2[0], s);
+            };
+            if (c.degree == 1) {
+                step(CHEB_ZERO1, nullptr, nullptr, x, nullptr, 0, 0);
+            } else {
+                step(CHEB_ZERO2, nullptr, nullptr, x, d, c.c1[1], c.c2[1]);
+                for (int k = 2; k < c.degree; ++k) {
+                    step(CHEB_NEXT, x, d, other, d, c.c1[k], c.c2[k]);
+                    std::swap(x, other);
+                }
+            }
+            if (x != dout) HIPCHECK(hipMemcpy(dout, x, sizeof(T) * level_nstore(H, l), hipMemcpyDeviceToDevice));
+            HIPCHECK(hipDeviceSynchronize());
+            dfree(d);
+            break;
+        }
+        case SAAMG_OP_RESTRICT:
+            if (l == 0)
+                l0_restrict<T>(H->l0, H->lc[0], din, dout, H->par[0].omega, s);
+            else
+                lc_restrict<T>(H->lc[l - 1], H->lc[l], din, dout, H->par[l].omega, s);
+            break;
+        case SAAMG_OP_PROLONG:
+            if (l == 0)
+                l0_prolong<T>(H->l0, H->lc[0], din, dout, H->par[0].omega, s);
+            else
+                lc_prolong<T>(H->lc[l - 1], H->lc[l], din, dout, H->par[l].omega, s);
+            break;
+    }
+    HIPCHECK(hipDeviceSynchronize());
+    download_level<T>(H, lout, dout, hout);
+    dfree(din);
+    dfree(dout);
+    dfree(tmp);
+}
+
+}  // namespace saamg
+
+// ================================================================== C interface
+
+extern "C" {
+
+const char* saamg_last_error(void) { return saamg::g_err.c_str(); }
+
+void saamg_default_options(saamg_options* o) {
+    if (!o) return;
+    o->precision = SAAMG_FP64;
+    o->max_levels = 10;
+    o->max_coarse = 1000;
+    o->cheb_degree = 2;
+    o->cheb_ratio = 10.0;
+    o->cheb_boost = 1.1;
+    o->eig_iters = 15;
+    o->omega_scale = 4.0 / 3.0;
+}
+
+int saamg_setup(const saamg_domain* dom, int variant, const saamg_options* opt, void* stream,
+                saamg_hierarchy** out) {
+    return guarded([&] {
+        if (!out) throw ApiError{SAAMG_INVALID_ARG, "out is NULL"};
+        *out = nullptr;
+        *out = setup_impl(dom, variant, opt, (hipStream_t)stream);
+        return (int)SAAMG_OK;
+    });
+}
+
+int saamg_destroy(saamg_hierarchy* H) {
+    if (!H) return SAAMG_OK;
+    FineLevel& L = H->l0;
+    for (void* p : {(void*)L.unk, (void*)L.irr, (void*)L.base, (void*)L.tab64, (void*)L.tab32,
+                    (void*)L.sigma, (void*)H->Ainv, (void*)H->cidx})
+        dfree(p);
+    for (auto& C : H->lc) free_coarse(C);
+    delete H;
+    return SAAMG_OK;
+}
+
+int saamg_hierarchy_info(const saamg_hierarchy* H, saamg_info* info) {
+    return guarded([&] {
+        if (!H || !info) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        std::memset(info, 0, sizeof(*info));
+        info->n_levels = H->n_levels;
+        info->variant = H->variant;
+        info->precision = H->opt.precision;
+        for (int l = 0; l < H->n_levels; ++l) {
+            int mx, my, mz;
+            level_dims(H, l, &mx, &my, &mz);
+            info->dims[l][0] = mx;
+            info->dims[l][1] = my;
+            info->dims[l][2] = mz;
+            info->n_unknowns[l] = l == 0 ? H->l0.n_unknowns : H->lc[l - 1].n_unknowns;
+            if (l < (int)H->par.size()) {
+                info->lambda_est[l] = H->par[l].lam;
+                info->omega[l] = H->par[l].omega;
+            }
+        }
+        info->n_irregular = H->l0.n_irr;
+        info->device_bytes = H->bytes;
+        info->t_setup_ms = H->t_setup_ms;
+        return (int)SAAMG_OK;
+    });
+}
+
+int saamg_solve(saamg_hierarchy* H, const double* d_b, const double* d_x0, double* d_x, double tol,
+                int max_iter, void* stream, saamg_result* res) {
+    saamg_state S;
+    int rc = guarded([&] {
+        if (!H || !d_b || !d_x) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        if (!(tol > 0) || max_iter < 0) throw ApiError{SAAMG_INVALID_ARG, "tol > 0, max_iter >= 0"};
+        HIPCHECK(hipSetDevice(H->device));
+        auto t0 = std::chrono::steady_clock::now();
+        S.s = (hipStream_t)stream;
+        S.tol = tol;
+        S.max_iter = max_iter;
+        state_alloc(&S, H);
+        state_start(&S, d_b, d_x0);
+        while (!S.done) {
+            state_enqueue(&S);
+            state_complete(&S);
+        }
+        cg_unscale(H->l0, S.x, d_x, S.s);
+        HIPCHECK(hipStreamSynchronize(S.s));
+        S.t_ms = ms_since(t0);
+        state_fill_result(&S, res);
+        return S.status;
+    });
+    state_release(&S);
+    return rc;
+}
+
+int saamg_footprint_bytes(int nx, int ny, int nz, int variant, int precision, int64_t* hier_bytes,
+                          int64_t* state_bytes) {
+    return guarded([&] {
+        if (nx < 3 || ny < 3 || nz < 3) throw ApiError{SAAMG_INVALID_ARG, "box must be at least 3^3"};
+        const double nbox = (double)nx * ny * nz;
+        const bool mixed = precision == SAAMG_MIXED;
+        const int na = variant == SAAMG_VARIANT_QUAD ? 27 : 14;
+        double h = 8.0 * nbox + 20.0 * nbox / 64 + 0.2 * nbox * 12 * 12;  // sigma, masks, table
+        double st = 48.0 * nbox + (mixed ? 4 : 8) * nbox;
+        double w = mixed ? 4 : 8;
+        st += 3 * w * nbox;
+        double m = nbox;
+        for (int l = 1; l < 10 && m > 27; ++l) {
+            m = (std::ceil(std::cbrt(m) / 3.0) + 2) * (std::ceil(std::cbrt(m) / 3.0) + 2) *
+                (std::ceil(std::cbrt(m) / 3.0) + 2);
+            h += (na + 1) * m * (mixed ? 12 : 8);
+            st += 4 * w * m;
+        }
+        h += 8.0 * 1000 * 1000;
+        if (hier_bytes) *hier_bytes = (int64_t)h;
+        if (state_bytes) *state_bytes = (int64_t)st;
+        return (int)SAAMG_OK;
+    });
+}
+
+int saamg_state_create(saamg_hierarchy* H, const double* d_b, const double* d_x0, double tol,
+                       int max_iter, void* stream, saamg_state** out) {
+    saamg_state* S = nullptr;
+    int rc = guarded([&] {
+        if (!H || !d_b || !out) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        if (!(tol > 0) || max_iter < 0) throw ApiError{SAAMG_INVALID_ARG, "tol > 0, max_iter >= 0"};
+        HIPCHECK(hipSetDevice(H->device));
+        S = new saamg_state();
+        S->s = (hipStream_t)stream;
+        S->tol = tol;
+        S->max_iter = max_iter;
+        state_alloc(S, H);
+        state_start(S, d_b, d_x0);
+        *out = S;
+        return (int)SAAMG_OK;
+    });
+    if (rc != SAAMG_OK && S) {
+        state_release(S);
+        delete S;
+        if (out) *out = nullptr;
+    }
+    return rc;
+}
+
+int saamg_batch_step(saamg_state* const* states, int n, int* n_done_out) {
+    return guarded([&] {
+        if (n < 0 || (n > 0 && !states)) throw ApiError{SAAMG_INVALID_ARG, "bad state list"};
+        for (int i = 0; i < n; ++i)
+            if (!states[i]) throw ApiError{SAAMG_INVALID_ARG, "NULL state"};
+        // queue every unfinished state's step on its own stream, then collect
+        std::vector<saamg_state*> live;
+        for (int i = 0; i < n; ++i)
+            if (!states[i]->done) {
+                auto t0 = std::chrono::steady_clock::now();
+                state_enqueue(states[i]);
+                states[i]->t_ms += ms_since(t0);
+                live.push_back(states[i]);
+            }
+        for (saamg_state* S : live) {
+            auto t0 = std::chrono::steady_clock::now();
+            state_complete(S);
+            S->t_ms += ms_since(t0);
+        }
+        int nd = 0;
+        for (int i = 0; i < n; ++i) nd += states[i]->done;
+        if (n_done_out) *n_done_out = nd;
+        return (int)SAAMG_OK;
+    });
+}
+
+int saamg_state_query(const saamg_state* S, int* done, saamg_result* res) {
+    return guarded([&] {
+        if (!S) throw ApiError{SAAMG_INVALID_ARG, "NULL state"};
+        if (done) *done = S->done;
+        state_fill_result(S, res);
+        return (int)SAAMG_OK;
+    });
+}
+
+int saamg_state_finish(saamg_state* S, double* d_x) {
+    return guarded([&] {
+        if (!S || !d_x) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        HIPCHECK(hipSetDevice(S->H->device));
+        cg_unscale(S->H->l0, S->x, d_x, S->s);
+        HIPCHECK(hipStreamSynchronize(S->s));
+        return (int)SAAMG_OK;
+    });
+}
+
+int saamg_state_destroy(saamg_state* S) {
+    if (!S) return SAAMG_OK;
+    (void)hipStreamSynchronize(S->s);
+    state_release(S);
+    delete S;
+    return SAAMG_OK;
+}
+
+int saamg_level_apply(saamg_hierarchy* H, int level, int op, int precision, const double* h_in,
+                      double* h_out) {
+    return guarded([&] {
+        if (!H || !h_in || !h_out) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        if (level < 0 || level >= H->n_levels) throw ApiError{SAAMG_INVALID_ARG, "bad level"};
+        if (op < SAAMG_OP_APPLY || op > SAAMG_OP_PROLONG) throw ApiError{SAAMG_INVALID_ARG, "bad op"};
+        if (op >= SAAMG_OP_PRESMOOTH && level >= H->n_levels - 1)
+            throw ApiError{SAAMG_INVALID_ARG, "no smoother or transfer on the coarsest level"};
+        if (precision == SAAMG_MIXED && H->opt.precision != SAAMG_MIXED)
+            throw ApiError{SAAMG_INVALID_ARG, "fp32 data exist only for a MIXED hierarchy"};
+        HIPCHECK(hipSetDevice(H->device));
+        if (precision == SAAMG_MIXED)
+            level_apply_impl<float>(H, level, op, h_in, h_out);
+        else
+            level_apply_impl<double>(H, level, op, h_in, h_out);
+        return (int)SAAMG_OK;
+    });
+}
+
+int saamg_level_coefficients(saamg_hierarchy* H, int level, double* h_out) {
+    return guarded([&] {
+        if (!H || !h_out) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        if (level < 0 || level >= H->n_levels) throw ApiError{SAAMG_INVALID_ARG, "bad level"};
+        HIPCHECK(hipSetDevice(H->device));
+        int mx, my, mz;
+        level_dims(H, level, &mx, &my, &mz);
+        const long nlog = (long)mx * my * mz;
+        if (level == 0) {
+            double* d = (double*)dmalloc(8L * 27 * H->l0.nbox);
+            l0_export_coef(H->l0, d, nullptr);
+            HIPCHECK(hipMemcpy(h_out, d, 8L * 27 * nlog, hipMemcpyDeviceToHost));
+            dfree(d);
+            return (int)SAAMG_OK;
+        }
+        const CoarseLevel& C = H->lc[level - 1];
+        std::vector<std::vector<double>> a(27);
+        for (int k = 0; k < 27; ++k) {
+            if (!C.coef64[k]) continue;
+            a[k].resize(C.nstore);
+            HIPCHECK(hipMemcpy(a[k].data(), C.coef64[k], 8 * C.nstore, hipMemcpyDeviceToHost));
+        }
+        for (int k = 0; k < 27; ++k) {
+            const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+            const long off = dx + (long)C.sx * dy + C.sxy * dz;
+            for (int z = 0; z < mz; ++z)
+                for (int y = 0; y < my; ++y)
+                    for (int x = 0; x < mx; ++x) {
+                        const long i = storage_index(H, level, x, y, z);
+                        double v = (C.sym && k < 13) ? a[26 - k][i + off] : a[k][i];
+                        h_out[k * nlog + x + (long)mx * (y + (long)my * z)] = v;
+                    }
+        }
+        return (int)SAAMG_OK;
+    });
+}
+
+int saamg_precond_apply(saamg_hierarchy* H, const double* d_r, double* d_z, void* stream) {
+    saamg_state S;
+    int rc = guarded([&] {
+        if (!H || !d_r || !d_z) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        HIPCHECK(hipSetDevice(H->device));
+        S.s = (hipStream_t)stream;
+        state_alloc(&S, H);
+        HIPCHECK(hipMemcpyAsync(S.r, d_r, 8 * H->l0.nbox, hipMemcpyDeviceToDevice, S.s));
+        precond(&S);
+        if (S.mixed)
+            f2d_copy((const float*)S.z, d_z, H->l0.nbox, S.s);
+        else
+            HIPCHECK(hipMemcpyAsync(d_z, S.z, 8 * H->l0.nbox, hipMemcpyDeviceToDevice, S.s));
+        HIPCHECK(hipStreamSynchronize(S.s));
+        return (int)SAAMG_OK;
+    });
+    state_release(&S);
+    return rc;
+}
+
+int saamg_operator_apply(saamg_hierarchy* H, const double* d_x, double* d_y, void* stream) {
+    return guarded([&] {
+        if (!H || !d_x || !d_y) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        HIPCHECK(hipSetDevice(H->device));
+        l0_apply<double>(H->l0, false, d_x, d_y, (hipStream_t)stream);
+        HIPCHECK(hipStreamSynchronize((hipStream_t)stream));
+        return (int)SAAMG_OK;
+    });
+}
+
+int saamg_scaling(saamg_hierarchy* H, double* d_sigma, void* stream) {
+    return guarded([&] {
+        if (!H || !d_sigma) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        HIPCHECK(hipSetDevice(H->device));
+        HIPCHECK(hipMemcpyAsync(d_sigma, H->l0.sigma, 8 * H->l0.nbox, hipMemcpyDeviceToDevice,
+                                (hipStream_t)stream));
+        HIPCHECK(hipStreamSynchronize((hipStream_t)stream));
+        return (int)SAAMG_OK;
+    });
+}
+
+}  // extern "C"

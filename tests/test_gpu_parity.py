@@ -1,0 +1,273 @@
+"""GPU parity: every step of the HIP path against the CPU oracle, through the C-ABI.
+
+Tolerances (derivations in the design doc):
+* fp64 components (operator, Galerkin coefficients, smoother, transfers, V-cycle):
+  1e-12 relative (only the summation order differs);
+* fp64 PCG solution: 1e-8 relative to the oracle's solution of the same algorithm, and
+  the same iteration count +-1;
+* mixed precision (fp32 hierarchy and V-cycle): components 1e-4 relative, full solve
+  1e-6 relative to the oracle's solution driven to 1e-13.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import amg, grid, operator, pcg, rows, solve
+
+torch = pytest.importorskip("torch")
+sa = pytest.importorskip("paper_0907_4863_amd")
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (shape, nx, ny, nz, variant)
+    "cyl33_lin": (W.Shape.cylinder(1.0, 2.0), 33, 33, 33, W.VARIANT_LIN),
+    "ell70_quad": (W.Shape.ellipse(1.0, 0.6, 4.0), 70, 45, 66, W.VARIANT_QUAD),
+    "boxbore_lin": (W.Shape.boxbore(0.8, 4.0, 0.5), 41, 41, 83, W.VARIANT_LIN),
+    "cyl_const": (W.Shape.cylinder(1.0, 2.0), 29, 29, 35, W.VARIANT_CONST),
+}
+
+
+def _dev():
+    return torch.device("cuda:0")
+
+
+class Case:
+    def __init__(self, name, precision=W.PREC_FP64, opts=None):
+        shape, nx, ny, nz, variant = CASES[name]
+        self.name, self.shape, self.dims, self.variant = name, shape, (nx, ny, nz), variant
+        self.precision = precision
+        print(f"[case] {name} {nx}x{ny}x{nz} variant={variant} prec={precision}", flush=True)
+        self.sys, self.H = solve.build(shape, nx, ny, nz, variant, opts)
+        dom = sa.domain_for(shape, nx, ny, nz)
+        o = sa.default_options(precision=precision)
+        if opts is not None:
+            o.max_coarse, o.cheb_degree = opts.max_coarse, opts.cheb_degree
+        self.G = sa.setup(dom, variant, o)
+        self.info = sa.hierarchy_info(self.G)
+        self.b = W.rhs(W.small(shape, nx, ny, nz, variant))
+
+    def to_dev(self, box):
+        return torch.from_numpy(np.ascontiguousarray(box, dtype=np.float64).reshape(-1)).to(_dev())
+
+    def lv_box(self, l, v):
+        lv = self.H.levels[l]
+        mx, my, mz = lv.dims
+        out = np.zeros(mx * my * mz)
+        out[lv.lin] = v
+        return out.reshape(mz, my, mx)
+
+    def lv_vec(self, l, box):
+        return box.reshape(-1)[self.H.levels[l].lin]
+
+
+_cache = {}
+
+
+def case(name, precision=W.PREC_FP64):
+    key = (name, precision)
+    if key not in _cache:
+        _cache[key] = Case(name, precision)
+    return _cache[key]
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def oracle_coef(lv):
+    mx, my, mz = lv.dims
+    c = amg.coarse_box_coords(lv)
+    A = lv.A.tocoo()
+    d = c[A.col] - c[A.row]
+    k = (d[:, 0] + 1) + 3 * (d[:, 1] + 1) + 9 * (d[:, 2] + 1)
+    out = np.zeros((27, mz, my, mx))
+    out[k, c[A.row, 2], c[A.row, 1], c[A.row, 0]] = A.data
+    return out
+
+
+# ------------------------------------------------------------------ hierarchy
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hierarchy_matches_oracle(name):
+    c = case(name)
+    sizes = c.H.sizes
+    assert c.info["n_levels"] == len(sizes)
+    assert c.info["n_unknowns"] == sizes
+    for l, lv in enumerate(c.H.levels):
+        assert tuple(c.info["dims"][l]) == tuple(lv.dims)
+        if l < len(sizes) - 1:
+            assert abs(c.info["lambda_est"][l] - lv.lam) <= 1e-10 * lv.lam
+            assert abs(c.info["omega"][l] - lv.omega) <= 1e-10 * lv.omega
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_operator_coefficients_every_level(name):
+    c = case(name)
+    for l, lv in enumerate(c.H.levels):
+        got = sa.level_coefficients(c.G, l, lv.dims)
+        want = oracle_coef(lv)
+        scale = np.abs(want).max()
+        tol = 1e-14 if l == 0 else 1e-12
+        assert np.abs(got - want).max() <= tol * scale, (name, l)
+
+
+def test_scaling_vector():
+    c = case("ell70_quad")
+    sig = torch.zeros(np.prod(c.dims), dtype=torch.float64, device=_dev())
+    sa.scaling(c.G, sig)
+    want = c.sys.scatter(c.sys.sigma).reshape(-1)
+    assert np.abs(sig.cpu().numpy() - want).max() <= 1e-15 * want.max()
+
+
+# ------------------------------------------------------------------ components
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
+def test_level_operations(name, precision):
+    c = case(name, precision)
+    tol = 1e-12 if precision == W.PREC_FP64 else 1e-4
+    rng = np.random.default_rng(11)
+    nl = len(c.H.levels)
+    for l in range(nl):
+        lv = c.H.levels[l]
+        mx, my, mz = lv.dims
+        x = rng.uniform(-1, 1, lv.n)
+        xb = c.lv_box(l, x)
+        for op, want in ((sa.capi.OP_APPLY, lv.A @ x), (sa.capi.OP_APPLY_T, lv.A.T @ x)):
+            got = c.lv_vec(l, sa.level_apply(c.G, l, op, xb, (mz, my, mx), precision))
+            assert rel(got, want) <= tol, (name, l, op)
+        if l == nl - 1:
+            continue
+        got = c.lv_vec(l, sa.level_apply(c.G, l, sa.capi.OP_PRESMOOTH, xb, (mz, my, mx), precision))
+        want = amg.chebyshev(lv, x, None, c.H.opts.cheb_degree, c.H.opts.cheb_ratio)
+        assert rel(got, want) <= tol, (name, l, "presmooth")
+        nx_, ny_, nz_ = c.H.levels[l + 1].dims
+        got = c.lv_vec(l + 1, sa.level_apply(c.G, l, sa.capi.OP_RESTRICT, xb, (nz_, ny_, nx_), precision))
+        assert rel(got, lv.P.T @ x) <= tol, (name, l, "restrict")
+        v = rng.uniform(-1, 1, c.H.levels[l + 1].n)
+        got = c.lv_vec(l, sa.level_apply(c.G, l, sa.capi.OP_PROLONG, c.lv_box(l + 1, v), (mz, my, mx), precision))
+        assert rel(got, lv.P @ v) <= tol, (name, l, "prolong")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
+def test_vcycle(name, precision):
+    c = case(name, precision)
+    r = W.random_box_vector(c.dims, 5) * c.sys.dom.mask
+    want = amg.vcycle(c.H, c.sys.gather(r))
+    z = torch.zeros(np.prod(c.dims), dtype=torch.float64, device=_dev())
+    sa.precond_apply(c.G, c.to_dev(r), z)
+    got = c.sys.gather(z.cpu().numpy())
+    tol = 1e-11 if precision == W.PREC_FP64 else 1e-4
+    assert rel(got, want) <= tol
+
+
+def test_operator_apply_device():
+    c = case("ell70_quad")
+    x = W.random_box_vector(c.dims, 9) * c.sys.dom.mask
+    y = torch.zeros(np.prod(c.dims), dtype=torch.float64, device=_dev())
+    sa.operator_apply(c.G, c.to_dev(x), y)
+    got = y.cpu().numpy().reshape(c.dims[::-1])
+    assert rel(c.sys.gather(got), c.sys.As @ c.sys.gather(x)) <= 1e-14
+    assert np.all(got[~c.sys.dom.mask] == 0)
+
+
+# ------------------------------------------------------------------ full solves
+
+
+def gpu_solve(c, b, x0=None, tol=1e-8, max_iter=500):
+    x = torch.zeros(np.prod(c.dims), dtype=torch.float64, device=_dev())
+    res = sa.solve(c.G, c.to_dev(b), x, None if x0 is None else c.to_dev(x0), tol, max_iter)
+    return x.cpu().numpy().reshape(c.dims[::-1]), res
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_fp64_matches_oracle(name):
+    c = case(name)
+    o = solve.solve(c.sys, c.H, c.b, tol=1e-8)
+    xo = c.sys.scatter(operator.unscale(c.sys, o.x))
+    xg, res = gpu_solve(c, c.b)
+    print(f"[{name}] oracle it={o.iterations} gpu it={res['iterations']} rel_true={res['rel_res_true']:.2e}")
+    assert res["status"] == 0 and o.status == pcg.OK
+    assert abs(res["iterations"] - o.iterations) <= 1
+    assert rel(c.sys.gather(xg), c.sys.gather(xo)) <= 1e-8
+    assert res["rel_res_true"] <= 1e-8
+    assert np.all(xg[~c.sys.dom.mask] == 0)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_mixed_matches_tight_oracle(name):
+    c = case(name, W.PREC_MIXED)
+    ref = solve.solve(c.sys, c.H, c.b, tol=1e-13)
+    xref = operator.unscale(c.sys, ref.x)
+    o8 = operator.unscale(c.sys, solve.solve(c.sys, c.H, c.b, tol=1e-8).x)
+    xg, res = gpu_solve(c, c.b)
+    err = rel(c.sys.gather(xg), xref)
+    print(f"[{name}] mixed it={res['iterations']} err={err:.2e} oracle-1e-8 err={rel(o8, xref):.2e}")
+    assert res["status"] == 0 and res["rel_res_true"] <= 1e-8
+    assert err <= 1e-6
+
+
+def test_solve_edge_cases():
+    c = case("cyl33_lin")
+    xz, r0 = gpu_solve(c, np.zeros(c.dims[::-1]))
+    assert r0["iterations"] == 0 and r0["status"] == 0 and np.all(xz == 0)
+    x, full = gpu_solve(c, c.b)
+    _, warm = gpu_solve(c, c.b, x0=x)
+    assert warm["iterations"] == 0
+    _, near = gpu_solve(c, c.b, x0=x * (1 + 1e-5))
+    assert 0 < near["iterations"] < full["iterations"]
+    _, one = gpu_solve(c, c.b, max_iter=1)
+    assert one["status"] == sa.capi.NOT_CONVERGED and one["iterations"] == 1
+    bad = c.b.copy()
+    k, j, i = [v[0] for v in np.nonzero(c.sys.dom.mask)]
+    bad[k, j, i] = np.nan
+    _, nanres = gpu_solve(c, bad)
+    assert nanres["status"] == sa.capi.NONFINITE
+    # NaN at a node that is not an unknown is ignored
+    bad2 = c.b.copy()
+    bad2[0, 0, 0] = np.nan
+    x2, r2 = gpu_solve(c, bad2)
+    assert r2["status"] == 0 and np.array_equal(x2, x)
+
+
+def test_single_level_and_other_degrees():
+    shape = W.Shape.cylinder(1.0, 2.0)
+    for (n, nz, deg, mc) in ((11, 9, 2, 1000), (25, 21, 1, 200), (25, 21, 3, 200)):
+        opts = amg.Options(max_coarse=mc, cheb_degree=deg)
+        s_, H = solve.build(shape, n, n, nz, W.VARIANT_QUAD, opts)
+        G = sa.setup(sa.domain_for(shape, n, n, nz), W.VARIANT_QUAD,
+                     sa.default_options(max_coarse=mc, cheb_degree=deg))
+        b = W.rhs(W.small(shape, n, n, nz, W.VARIANT_QUAD))
+        o = solve.solve(s_, H, b)
+        x = torch.zeros(n * n * nz, dtype=torch.float64, device=_dev())
+        res = sa.solve(G, torch.from_numpy(b.reshape(-1)).to(_dev()), x)
+        xo = operator.unscale(s_, o.x)
+        assert res["status"] == 0 and abs(res["iterations"] - o.iterations) <= 1
+        assert rel(s_.gather(x.cpu().numpy()), xo) <= 1e-8, (n, deg)
+        assert sa.hierarchy_info(G)["n_levels"] == len(H.levels)
+
+
+def test_batched_states_equal_alone():
+    """Each request's result is bitwise the same alone and inside a batch."""
+    cs = [case("cyl33_lin", W.PREC_MIXED), case("ell70_quad", W.PREC_MIXED),
+          case("boxbore_lin", W.PREC_MIXED)]
+    alone = []
+    for c in cs:
+        x, _ = gpu_solve(c, c.b)
+        alone.append(x)
+    streams = [torch.cuda.Stream() for _ in cs]
+    states = [sa.state_create(c.G, c.to_dev(c.b), stream=s.cuda_stream) for c, s in zip(cs, streams)]
+    for _ in range(200):
+        if sa.batch_step(states) == len(states):
+            break
+    for c, st, xa in zip(cs, states, alone):
+        done, res = sa.state_query(st)
+        assert done and res["status"] == 0
+        x = torch.zeros(np.prod(c.dims), dtype=torch.float64, device=_dev())
+        sa.state_finish(st, x)
+        assert np.array_equal(x.cpu().numpy().reshape(c.dims[::-1]), xa)
+        sa.state_destroy(st)
