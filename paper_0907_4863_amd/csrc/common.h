@@ -2,12 +2,13 @@
 //
 // Data layout on the device
 //   Level 0 (the lattice): box vectors of nx*ny*nz values, x fastest.  The scaled
-//   operator D^-1/2 A D^-1/2 has unit diagonal.  Rows whose six off-diagonals all equal
-//   the interior constants (-sigma0^2/h_a^2) are "regular"; the others ("irregular":
-//   rows at the wall and their neighbours) keep their six coefficients in a compact
-//   table.  Per 64-node segment of an x-line the library stores a 64-bit unknown mask,
-//   a 64-bit irregular mask and the table rank of the segment's first irregular row, so
-//   a row's table slot is base + popcount(irregular bits below it).
+//   operator D^-1/2 A D^-1/2 has unit diagonal.  Rows of interior points whose six
+//   off-diagonals all equal the interior constants (-sigma0^2/h_a^2) are "regular"; the
+//   others ("irregular": rows with an outside neighbour, and the neighbours of rows
+//   with a cut wall) keep their six coefficients in a compact table.  Per 64-node
+//   segment of an x-line the library stores a 64-bit unknown mask, a 64-bit irregular
+//   mask and the table rank of the segment's first irregular row, so a row's table
+//   slot is base + popcount(irregular bits below it).
 //   Levels >= 1: 27-point Galerkin operators on a logical box (mx, my, mz) stored with a
 //   one-node zero ghost layer, i.e. on (mx+2)*(my+2)*(mz+2) nodes; coefficient k of
 //   row i couples i to i + offset(k), k = (dx+1) + 3(dy+1) + 9(dz+1).  A symmetric

@@ -153,8 +153,11 @@ void l0_scatter_nwidx(int32_t* nwidx, const int64_t* nodes, long n, hipStream_t 
     HIPCHECK(hipGetLastError());
 }
 
-// Segment masks: unknown bits from the mask; irregular = unknown and (at the wall with
-// some s < 1, or a neighbour of such a node).
+// Segment masks: unknown bits from the mask.  A row is regular only at an interior point
+// (all six neighbours are unknowns, Section 2) whose neighbours all have the interior
+// diagonal; every other unknown row (a neighbour outside, a wall fraction s < 1 at the
+// node or at a neighbour) is irregular and keeps explicit coefficients, zero toward
+// outside neighbours.
 __global__ void __launch_bounds__(kThreads) k_build_masks(int nx, int ny, int nz, int nsegx,
                                                           const uint8_t* __restrict__ mask,
                                                           const int32_t* __restrict__ nwidx,
@@ -169,7 +172,9 @@ __global__ void __launch_bounds__(kThreads) k_build_masks(int nx, int ny, int nz
             const long i = x + (long)nx * y + nxy * z;
             u = mask[i] != 0;
             if (u) {
-                r = nwidx[i] >= 0 || nwidx[i - 1] >= 0 || nwidx[i + 1] >= 0 ||
+                const bool interior = mask[i - 1] && mask[i + 1] && mask[i - nx] &&
+                                      mask[i + nx] && mask[i - nxy] && mask[i + nxy];
+                r = !interior || nwidx[i] >= 0 || nwidx[i - 1] >= 0 || nwidx[i + 1] >= 0 ||
                     nwidx[i - nx] >= 0 || nwidx[i + nx] >= 0 || nwidx[i - nxy] >= 0 ||
                     nwidx[i + nxy] >= 0;
             }
