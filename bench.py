@@ -1,0 +1,222 @@
+#!/usr/bin/env python
+"""Benchmark of the SA-AMG preconditioned CG Poisson solve on one MI355X.
+
+A step is one complete solve to relative residual 1e-8 (scaled system) from x0 = 0,
+reusing the preconditioner built once before the warm-up (the paper's "reusing the
+preconditioner" mode), on the 256 x 256 x 768 elliptic pipe (semi-axes 1.0 x 0.6,
+length 4, 39.1M unknowns, quadratic wall rule) with a seeded 1M-particle Gaussian
+bunch deposited by cloud-in-cell.  The headline value is DOF*iter/s of the mixed
+path (fp32 hierarchy / fp64 CG); the all-fp64 path is run on the same right-hand side
+and reported beside it.  Setup time is reported separately (the paper's
+"construction").
+
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ell256_mixed",
+                    help="workloads.by_name key (default: the 256x256x768 ellipse, mixed)")
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timers", action="store_true",
+                    help="time without per-kernel HIP events (roofline omitted)")
+    ap.add_argument("--cpu-sample-planes", type=int, default=48)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, planes: int) -> dict:
+    """The oracle, single-threaded, on a z-slab of the same pipe cross-section and spacing."""
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle import solve
+
+    L = w.shape.length * (planes - 1) / (w.nz - 1)
+    shape = W.Shape(w.shape.kind, w.shape.a, w.shape.b, L, w.shape.bore_r, w.shape.cavity_half_len)
+    bunch = W.Bunch(w.bunch.n, (w.bunch.sigma[0], w.bunch.sigma[1], L / 6.0), w.bunch.seed)
+    ws = W.Workload("sample", shape, w.nx, w.ny, planes, w.variant, W.PREC_FP64, bunch=bunch)
+    b = W.rhs(ws)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        sys_, H = solve.build(shape, w.nx, w.ny, planes, w.variant)
+        t1 = time.perf_counter()
+        res = solve.solve(sys_, H, b, tol=w.tol)
+        t2 = time.perf_counter()
+    dof = sys_.n
+    return {
+        "value": dof * res.iterations / (t2 - t1),
+        "unit": "DOF*iter/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle (numpy/scipy fp64, 1 thread) on a {w.nx}x{w.ny}x{planes} slab of the "
+                   f"same pipe (same spacing, {dof} unknowns): setup {t1 - t0:.2f} s, "
+                   f"{res.iterations} iterations in {t2 - t1:.2f} s"),
+        "setup_s": t1 - t0,
+        "solve_s": t2 - t1,
+        "iterations": res.iterations,
+        "host_cpu": platform.processor() or platform.machine(),
+        "host_threads": os.cpu_count(),
+    }
+
+
+def run_solves(sa, torch, H, b, nbox, steps, warmup, dev, timers: bool):
+    x = torch.zeros(nbox, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        sa.solve(H, b, x, tol=1e-8, max_iter=500)
+    torch.cuda.synchronize()
+    if timers:
+        sa.capi.timer_reset()
+        for k in sa.capi.TIMER_KINDS:
+            sa.capi.timer_enable(k, True)
+    iters = []
+    res = None
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        res = sa.solve(H, b, x, tol=1e-8, max_iter=500)
+        iters.append(res["iterations"])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = {}
+    if timers:
+        for k in sa.capi.TIMER_KINDS:
+            sa.capi.timer_enable(k, False)
+        for k in sa.capi.TIMER_KINDS:
+            ms, n, byts = sa.capi.timer_read(k)
+            if n:
+                kern[k] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / n,
+                           "alg_bytes_per_launch": byts / n,
+                           "achieved_GBs": byts / (ms * 1e-3) / 1e9 if ms > 0 else None}
+        sa.capi.timer_reset()
+    return x, iters, wall, res, kern
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this solver runs on a single GPU "
+              f"(one solve per device). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_0907_4863_amd as sa
+    import workloads as W
+
+    w = W.by_name(args.workload)
+    dev = torch.device("cuda:0")
+    print(f"[bench] workload {w.name} {w.nx}x{w.ny}x{w.nz}", file=sys.stderr, flush=True)
+    dom = sa.domain_for(w.shape, w.nx, w.ny, w.nz)
+    dof = dom.n_unknowns
+    b = torch.from_numpy(W.rhs(w).reshape(-1)).to(dev)
+    nbox = w.box_nodes
+    out = {}
+    for tag, prec in (("mixed", sa.MIXED), ("fp64", sa.FP64)):
+        if w.precision == sa.FP64 and tag == "mixed":
+            continue
+        steps = args.steps if tag == ("mixed" if w.precision == sa.MIXED else "fp64") else \
+            (args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H = sa.setup(dom, w.variant, sa.default_options(precision=prec))
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        info = sa.hierarchy_info(H)
+        print(f"[bench] {tag}: setup {setup_s:.3f} s levels {info['n_unknowns']}",
+              file=sys.stderr, flush=True)
+        x, iters, wall, res, kern = run_solves(sa, torch, H, b, nbox, steps, args.warmup, dev,
+                                               timers=not args.no_timers)
+        out[tag] = {"x": x, "iters": iters, "wall": wall, "res": res, "kern": kern,
+                    "setup_s": setup_s, "info": info, "steps": steps}
+        print(f"[bench] {tag}: {steps} solves in {wall:.3f} s, iterations {iters}",
+              file=sys.stderr, flush=True)
+        sa.destroy(H)
+
+    head = out["mixed"] if "mixed" in out else out["fp64"]
+    total_iters = sum(head["iters"])
+    value = dof * total_iters / head["wall"]
+    line = {
+        "metric": "DOF*iter/s at rel-res 1e-8 (fp32-AMG/fp64-CG vs fp64)",
+        "value": value,
+        "unit": "DOF*iter/s",
+        "n_gpus": 1,
+        "steps": head["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * head["wall"] / head["steps"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if "mixed" in out else "f64",
+        "data": "synthetic (seeded Gaussian bunch, cloud-in-cell)",
+        "config": {"workload": f"{w.name}: ellipse 1.0x0.6 L={w.shape.length} "
+                               f"{w.nx}x{w.ny}x{w.nz} box, {dof} unknowns, "
+                               f"{W.VARIANT_NAMES[w.variant]} wall rule, rel-res {w.tol}",
+                   "dof": dof, "levels": head["info"]["n_unknowns"]},
+        "solves_per_s": head["steps"] / head["wall"],
+        "iterations": head["iters"][-1],
+        "setup_ms": 1e3 * head["setup_s"],
+        "rel_res_true": head["res"]["rel_res_true"],
+    }
+    if "fp64" in out and "mixed" in out:
+        f = out["fp64"]
+        xm = out["mixed"]["x"]
+        xf = f["x"]
+        line["fp64"] = {
+            "value": dof * sum(f["iters"]) / f["wall"],
+            "ms_per_step": 1e3 * f["wall"] / f["steps"],
+            "solves_per_s": f["steps"] / f["wall"],
+            "iterations": f["iters"][-1],
+            "setup_ms": 1e3 * f["setup_s"],
+            "rel_res_true": f["res"]["rel_res_true"],
+        }
+        line["mixed_vs_fp64_rel_err"] = float(torch.linalg.norm(xm - xf) / torch.linalg.norm(xf))
+    kern = head["kern"]
+    if kern:
+        dom_k = max(kern, key=lambda k: kern[k]["total_ms"])
+        kd = kern[dom_k]
+        line["roofline"] = {
+            "kernel": dom_k,
+            "bound": "hbm",
+            "achieved": kd["achieved_GBs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": kd["achieved_GBs"] / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_us": kd["avg_us"],
+            "alg_bytes_per_launch": kd["alg_bytes_per_launch"],
+        }
+        line["kernels"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                               for kk, vv in v.items()} for k, v in kern.items()}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_planes)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -214,6 +214,20 @@ int saamg_operator_apply(saamg_hierarchy* H, const double* d_x, double* d_y, voi
 /* D^-1/2 as a device box vector (0 at non-unknowns), fp64. */
 int saamg_scaling(saamg_hierarchy* H, double* d_sigma, void* stream);
 
+/* ---- kernel timing (diagnostics) ----------------------------------------------------
+ * When enabled for a kernel class, every launch of that class records a pair of HIP
+ * events on its own stream; saamg_timer_read synchronises on them and returns the
+ * summed event-to-event time, the launch count and the algorithmic bytes moved (each
+ * array the kernel must read or write counted once over the unknowns it covers).
+ * Classes: 0 level-0 Chebyshev steps, 1 level-0 residual, 2 restriction to level 1,
+ * 3 prolongation from level 1, 4 CG direction update + product with A, 5 CG x/r update,
+ * 6 all coarse-level kernels, 7 reduction finalisation.  At most 65536 launches are
+ * kept between resets; later ones are not timed.
+ */
+int saamg_timer_enable(int kind, int enable);
+int saamg_timer_read(int kind, double* total_ms, int64_t* launches, int64_t* alg_bytes);
+int saamg_timer_reset(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -100,6 +100,8 @@ def lib() -> C.CDLL:
     L.saamg_precond_apply.argtypes = [_P, _P, _P, _P]
     L.saamg_operator_apply.argtypes = [_P, _P, _P, _P]
     L.saamg_scaling.argtypes = [_P, _P, _P]
+    L.saamg_timer_enable.argtypes = [C.c_int, C.c_int]
+    L.saamg_timer_read.argtypes = [C.c_int, _DP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     _lib = L
     return L
 
@@ -342,3 +344,23 @@ def operator_apply(H: Hierarchy, x, y, stream=None) -> None:
 
 def scaling(H: Hierarchy, sigma, stream=None) -> None:
     _check(lib().saamg_scaling(H.handle, _dptr(sigma, H.nbox), _stream(stream)))
+
+
+# --------------------------------------------------------------------------- timing
+
+TIMER_KINDS = {"l0_cheb": 0, "l0_resid": 1, "l0_restrict": 2, "l0_prolong": 3, "cg_pq": 4,
+               "cg_xr": 5, "coarse": 6, "finalize": 7}
+
+
+def timer_enable(kind: str, enable: bool = True) -> None:
+    _check(lib().saamg_timer_enable(TIMER_KINDS[kind], int(enable)))
+
+
+def timer_read(kind: str) -> Tuple[float, int, int]:
+    ms, n, u = C.c_double(0), C.c_int64(0), C.c_int64(0)
+    _check(lib().saamg_timer_read(TIMER_KINDS[kind], C.byref(ms), C.byref(n), C.byref(u)))
+    return ms.value, n.value, u.value
+
+
+def timer_reset() -> None:
+    _check(lib().saamg_timer_reset())

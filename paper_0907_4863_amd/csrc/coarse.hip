@@ -154,9 +154,16 @@ __global__ void __launch_bounds__(kThreads) k_lc_cheb(LCView<T> c, const T* __re
     if (dout) dout[i] = dn;
 }
 
+// Algorithmic bytes of one coarse-level stencil sweep: coefficient arrays, 1/diag and
+// `nvec` vectors over the level's unknowns.
+static inline long lc_bytes(const CoarseLevel& C, int wsize, int nvec) {
+    return C.n_unknowns * (long)wsize * ((C.sym ? 14 : 27) + 1 + nvec);
+}
+
 template <typename T>
 void lc_cheb(const CoarseLevel& C, int mode, const T* f, const T* xin, const T* din, T* xout,
              T* dout, double c1, double c2, double c2_0, hipStream_t s) {
+    KTimer kt_(T_COARSE, s, lc_bytes(C, sizeof(T), (mode == CHEB_NEXT ? 4 : 3) + (dout ? 1 : 0)));
     LCView<T> c = C.view<T>();
     dim3 g = lc_grid(C), b(kWave, kBlockY);
 #define LC_CHEB(SYMV, M)                                                                       \
@@ -196,6 +203,7 @@ __global__ void __launch_bounds__(kThreads) k_lc_residual(LCView<T> c, const T* 
 
 template <typename T>
 void lc_residual(const CoarseLevel& C, const T* f, const T* x, T* r, hipStream_t s) {
+    KTimer kt_(T_COARSE, s, lc_bytes(C, sizeof(T), 3));
     if (C.sym)
         hipLaunchKernelGGL((k_lc_residual<T, true>), lc_grid(C), dim3(kWave, kBlockY), 0, s,
                            C.view<T>(), f, x, r);
@@ -240,6 +248,7 @@ __global__ void __launch_bounds__(kThreads) k_lc_restrict(LCView<T> f, LCView<T>
 template <typename T>
 void lc_restrict(const CoarseLevel& F, const CoarseLevel& C, const T* r, T* fc, double omega,
                  hipStream_t s) {
+    KTimer kt_(T_COARSE, s, lc_bytes(F, sizeof(T), 1) + C.n_unknowns * (long)sizeof(T));
     if (F.sym)
         hipLaunchKernelGGL((k_lc_restrict<T, true>), lc_grid(C), dim3(kWave, kBlockY), 0, s,
                            F.view<T>(), C.view<T>(), r, fc, (T)omega);
@@ -281,6 +290,7 @@ __global__ void __launch_bounds__(kThreads) k_lc_prolong(LCView<T> c, LCView<T> 
 template <typename T>
 void lc_prolong(const CoarseLevel& F, const CoarseLevel& C, const T* vc, T* x, double omega,
                 hipStream_t s) {
+    KTimer kt_(T_COARSE, s, lc_bytes(F, sizeof(T), 2) + C.n_unknowns * (long)sizeof(T));
     if (F.sym)
         hipLaunchKernelGGL((k_lc_prolong<T, true>), lc_grid(F), dim3(kWave, kBlockY), 0, s,
                            F.view<T>(), C.view<T>(), vc, x, (T)omega);
@@ -662,6 +672,7 @@ __global__ void __launch_bounds__(256) k_coarse_solve(const double* __restrict__
 
 template <typename TF, typename T>
 void coarse_solve(const double* Ainv, const long* cidx, int nL, const TF* f, T* x, hipStream_t s) {
+    KTimer kt_(T_COARSE, s, 8L * nL * nL + nL * (long)(sizeof(TF) + sizeof(T) + 8));
     hipLaunchKernelGGL((k_coarse_solve<TF, T>), dim3((nL + 3) / 4), dim3(256), 0, s, Ainv, cidx, nL,
                        f, x);
     HIPCHECK(hipGetLastError());

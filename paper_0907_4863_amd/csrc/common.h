@@ -110,6 +110,20 @@ void hip_check(hipError_t e, const char* what);
 void* dmalloc(size_t bytes);            // throws ApiError(NOMEM) on failure, zero-filled
 void dfree(void* p);
 
+// Opt-in kernel timing: HIP events recorded on the launching stream around every
+// launch of one kernel class (see saamg_timer_* in the C interface).
+enum TimerKind {
+    T_L0_CHEB = 0, T_L0_RESID, T_L0_RESTRICT, T_L0_PROLONG, T_CG_PQ, T_CG_XR, T_COARSE,
+    T_FINALIZE, T_NKIND
+};
+struct KTimer {
+    int slot = -1;
+    int kind;
+    hipStream_t s;
+    KTimer(int kind, hipStream_t s, long units);
+    ~KTimer();
+};
+
 struct ChebCoef {
     int degree;
     double c1[8];   // multiplies the previous direction

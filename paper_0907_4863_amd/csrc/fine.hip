@@ -13,6 +13,12 @@ constexpr int kZB = 4;
 static inline dim3 l0_grid(const FineLevel& L) {
     return dim3(L.nsegx, (L.ny + kBlockY - 1) / kBlockY, (L.nz + kZB - 1) / kZB);
 }
+// Level-0 metadata streamed by every stencil launch: segment masks and table slots,
+// plus the irregular rows' coefficients.
+static inline long l0_meta_bytes(const FineLevel& L, int wsize, bool trans_too) {
+    return L.nseg * 20 + L.n_irr * 6L * wsize * (trans_too ? 2 : 1);
+}
+
 long l0_blocks(const FineLevel& L) {
     dim3 g = l0_grid(L);
     return (long)g.x * g.y * g.z;
@@ -135,6 +141,7 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(const double* __restri
 
 void finalize(const double* partials, long nblk, int nq, double* scal, int op, int dst,
               hipStream_t s) {
+    KTimer kt_(T_FINALIZE, s, nblk * 8L * nq);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, partials, nblk, nq, scal, op,
                        dst);
     HIPCHECK(hipGetLastError());
@@ -496,6 +503,10 @@ __global__ void __launch_bounds__(kThreads) k_l0_cheb(L0View<T> v, const TF* __r
 template <typename TF, typename T>
 void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* din, T* xout,
              T* dout, double c1, double c2, double c2_0, double* dot, hipStream_t s) {
+    const long wf = sizeof(TF), w = sizeof(T), n = L.n_unknowns;
+    const long vec = (mode == CHEB_ZERO1 || mode == CHEB_ZERO2) ? wf + w
+                     : (mode == CHEB_FIRST) ? wf + 2 * w : wf + 3 * w;
+    KTimer kt_(T_L0_CHEB, s, n * (vec + (dout ? w : 0)) + l0_meta_bytes(L, w, false));
     L0View<T> v = L.view<T>();
     dim3 g = l0_grid(L), b(kWave, kBlockY);
 #define CHEB_LAUNCH(M)                                                                         \
@@ -539,6 +550,8 @@ __global__ void __launch_bounds__(kThreads) k_l0_residual(L0View<T> v, const TF*
 
 template <typename TF, typename T>
 void l0_residual(const FineLevel& L, const TF* f, const T* x, T* r, hipStream_t s) {
+    KTimer kt_(T_L0_RESID, s, L.n_unknowns * (long)(sizeof(TF) + 2 * sizeof(T)) +
+                                 l0_meta_bytes(L, sizeof(T), false));
     hipLaunchKernelGGL((k_l0_residual<TF, T>), l0_grid(L), dim3(kWave, kBlockY), 0, s,
                        L.view<T>(), f, x, r);
     HIPCHECK(hipGetLastError());
@@ -583,6 +596,8 @@ __global__ void __launch_bounds__(kThreads) k_l0_restrict(L0View<T> v, LCView<T>
 template <typename T>
 void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* fc, double omega,
                  hipStream_t s) {
+    KTimer kt_(T_L0_RESTRICT, s, (L.n_unknowns + C.n_unknowns) * (long)sizeof(T) +
+                                    l0_meta_bytes(L, sizeof(T), false));
     dim3 g((C.mx + kWave - 1) / kWave, (C.my + kBlockY - 1) / kBlockY, C.mz);
     hipLaunchKernelGGL((k_l0_restrict<T>), g, dim3(kWave, kBlockY), 0, s, L.view<T>(),
                        C.view<T>(), r, fc, (T)omega);
@@ -624,6 +639,8 @@ __global__ void __launch_bounds__(kThreads) k_l0_prolong(L0View<T> v, LCView<T> 
 template <typename T>
 void l0_prolong(const FineLevel& L, const CoarseLevel& C, const T* vc, T* x, double omega,
                 hipStream_t s) {
+    KTimer kt_(T_L0_PROLONG, s, (2 * L.n_unknowns + C.n_unknowns) * (long)sizeof(T) +
+                                   l0_meta_bytes(L, sizeof(T), false));
     hipLaunchKernelGGL((k_l0_prolong<T>), l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<T>(),
                        C.view<T>(), vc, x, (T)omega);
     HIPCHECK(hipGetLastError());
@@ -723,6 +740,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_pq(L0View<double> v, const TZ* 
 template <typename TZ>
 void cg_pq(const FineLevel& L, const TZ* z, const double* pold, double* pnew, double* q,
            const double* scal, double* partials, hipStream_t s) {
+    KTimer kt_(T_CG_PQ, s, L.n_unknowns * (long)(sizeof(TZ) + 24) + l0_meta_bytes(L, 8, false));
     hipLaunchKernelGGL((k_cg_pq<TZ>), l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), z,
                        pold, pnew, q, scal, partials);
     HIPCHECK(hipGetLastError());
@@ -760,6 +778,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_xr(L0View<double> v, double* __
 
 void cg_xr(const FineLevel& L, double* x, const double* p, double* r, const double* q,
            const double* scal, double* partials, hipStream_t s) {
+    KTimer kt_(T_CG_XR, s, L.n_unknowns * 48L);
     hipLaunchKernelGGL(k_cg_xr, l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), x, p, r,
                        q, scal, partials);
     HIPCHECK(hipGetLastError());
