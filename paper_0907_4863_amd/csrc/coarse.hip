@@ -29,18 +29,21 @@ __device__ inline T lc_stencil(const LCView<T>& c, long i, F X) {
 }
 
 static inline dim3 lc_grid(const CoarseLevel& C) {
-    return dim3((C.mx + kWave - 1) / kWave, (C.my + kBlockY - 1) / kBlockY, C.mz);
+    return dim3((unsigned)(((long)C.mx * C.my + kThreads - 1) / kThreads), C.mz);
 }
 long lc_blocks(const CoarseLevel& C) {
     dim3 g = lc_grid(C);
     return (long)g.x * g.y * g.z;
 }
 
+// One thread per node of a z-plane (flattened over x and y so that wavefronts stay full
+// on narrow coarse boxes), one block row per plane.
 #define LC_PROLOGUE                                                              \
-    const int X = blockIdx.x * kWave + threadIdx.x;                              \
-    const int Y = blockIdx.y * kBlockY + threadIdx.y;                            \
-    const int Z = blockIdx.z;                                                    \
-    const bool inb = X < c.mx && Y < c.my;                                       \
+    const long t_ = blockIdx.x * (long)blockDim.x + threadIdx.x;                 \
+    const bool inb = t_ < (long)c.mx * c.my;                                     \
+    const int X = inb ? (int)(t_ % c.mx) : 0;                                    \
+    const int Y = inb ? (int)(t_ / c.mx) : 0;                                    \
+    const int Z = blockIdx.y;                                                    \
     const long i = (X + 1) + (long)c.sx * (Y + 1) + c.sxy * (Z + 1);
 
 template <typename T, bool SYM, bool TR>
@@ -54,7 +57,7 @@ __global__ void __launch_bounds__(kThreads) k_lc_apply(LCView<T> c, const T* __r
 template <typename T>
 void lc_apply(const CoarseLevel& C, bool trans, const T* x, T* y, hipStream_t s) {
     LCView<T> c = C.view<T>();
-    dim3 g = lc_grid(C), b(kWave, kBlockY);
+    dim3 g = lc_grid(C), b(kThreads);
     if (C.sym)
         hipLaunchKernelGGL((k_lc_apply<T, true, false>), g, b, 0, s, c, x, y);
     else if (trans)
@@ -74,7 +77,7 @@ __global__ void __launch_bounds__(kThreads) k_lc_power_start(LCView<double> c, d
 }
 
 void lc_power_start(const CoarseLevel& C, double* v, hipStream_t s) {
-    hipLaunchKernelGGL(k_lc_power_start, lc_grid(C), dim3(kWave, kBlockY), 0, s,
+    hipLaunchKernelGGL(k_lc_power_start, lc_grid(C), dim3(kThreads), 0, s,
                        C.view<double>(), v);
     HIPCHECK(hipGetLastError());
 }
@@ -114,10 +117,10 @@ __global__ void __launch_bounds__(kThreads) k_lc_power_step(LCView<double> c,
 void lc_power_step(const CoarseLevel& C, const double* v, const double* scal, double* w,
                    double* partials, hipStream_t s) {
     if (C.sym)
-        hipLaunchKernelGGL((k_lc_power_step<true>), lc_grid(C), dim3(kWave, kBlockY), 0, s,
+        hipLaunchKernelGGL((k_lc_power_step<true>), lc_grid(C), dim3(kThreads), 0, s,
                            C.view<double>(), v, scal, w, partials);
     else
-        hipLaunchKernelGGL((k_lc_power_step<false>), lc_grid(C), dim3(kWave, kBlockY), 0, s,
+        hipLaunchKernelGGL((k_lc_power_step<false>), lc_grid(C), dim3(kThreads), 0, s,
                            C.view<double>(), v, scal, w, partials);
     HIPCHECK(hipGetLastError());
 }
@@ -165,7 +168,7 @@ void lc_cheb(const CoarseLevel& C, int mode, const T* f, const T* xin, const T* 
              T* dout, double c1, double c2, double c2_0, hipStream_t s) {
     KTimer kt_(T_COARSE, s, lc_bytes(C, sizeof(T), (mode == CHEB_NEXT ? 4 : 3) + (dout ? 1 : 0)));
     LCView<T> c = C.view<T>();
-    dim3 g = lc_grid(C), b(kWave, kBlockY);
+    dim3 g = lc_grid(C), b(kThreads);
 #define LC_CHEB(SYMV, M)                                                                       \
     hipLaunchKernelGGL((k_lc_cheb<T, SYMV, M>), g, b, 0, s, c, f, xin, din, xout, dout, (T)c1, \
                        (T)c2, (T)c2_0);
@@ -205,10 +208,10 @@ template <typename T>
 void lc_residual(const CoarseLevel& C, const T* f, const T* x, T* r, hipStream_t s) {
     KTimer kt_(T_COARSE, s, lc_bytes(C, sizeof(T), 3));
     if (C.sym)
-        hipLaunchKernelGGL((k_lc_residual<T, true>), lc_grid(C), dim3(kWave, kBlockY), 0, s,
+        hipLaunchKernelGGL((k_lc_residual<T, true>), lc_grid(C), dim3(kThreads), 0, s,
                            C.view<T>(), f, x, r);
     else
-        hipLaunchKernelGGL((k_lc_residual<T, false>), lc_grid(C), dim3(kWave, kBlockY), 0, s,
+        hipLaunchKernelGGL((k_lc_residual<T, false>), lc_grid(C), dim3(kThreads), 0, s,
                            C.view<T>(), f, x, r);
     HIPCHECK(hipGetLastError());
 }
@@ -217,15 +220,23 @@ template void lc_residual<double>(const CoarseLevel&, const double*, const doubl
 template void lc_residual<float>(const CoarseLevel&, const float*, const float*, float*,
                                  hipStream_t);
 
-// fc(I) = sum over aggregate I of (r - w A^T D^-1 r): P^T r with P = (I - w D^-1 A) P_tent.
+// P^T r with P = (I - w D^-1 A) P_tent in two passes: y = r - w A^T D^-1 r on every fine
+// node (one thread per node), then fc(I) = sum of y over aggregate I.
 template <typename T, bool SYM>
-__global__ void __launch_bounds__(kThreads) k_lc_restrict(LCView<T> f, LCView<T> c,
-                                                          const T* __restrict__ r,
-                                                          T* __restrict__ fc, T omega) {
-    const int X = blockIdx.x * kWave + threadIdx.x;
-    const int Y = blockIdx.y * kBlockY + threadIdx.y;
-    const int Z = blockIdx.z;
-    if (X >= c.mx || Y >= c.my) return;
+__global__ void __launch_bounds__(kThreads) k_lc_restrict_y(LCView<T> c, const T* __restrict__ r,
+                                                            T* __restrict__ yv, T omega) {
+    LC_PROLOGUE
+    if (!inb) return;
+    const T atr = lc_stencil<T, SYM, true>(c, i, [&](long j) { return c.invD[j] * r[j]; });
+    yv[i] = r[i] - omega * atr;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_lc_restrict_sum(LCView<T> f, LCView<T> c,
+                                                              const T* __restrict__ yv,
+                                                              T* __restrict__ fc) {
+    LC_PROLOGUE
+    if (!inb) return;
     T acc = 0;
     for (int dz = 0; dz < 3; ++dz) {
         const int z = 3 * Z + dz;
@@ -233,34 +244,34 @@ __global__ void __launch_bounds__(kThreads) k_lc_restrict(LCView<T> f, LCView<T>
         for (int dy = 0; dy < 3; ++dy) {
             const int y = 3 * Y + dy;
             if (y >= f.my) break;
+            const long row = (long)f.sx * (y + 1) + f.sxy * (z + 1) + 1;
             for (int dx = 0; dx < 3; ++dx) {
                 const int x = 3 * X + dx;
-                if (x >= f.mx) break;
-                const long m = (x + 1) + (long)f.sx * (y + 1) + f.sxy * (z + 1);
-                const T atr = lc_stencil<T, SYM, true>(f, m, [&](long j) { return f.invD[j] * r[j]; });
-                acc += r[m] - omega * atr;
+                if (x < f.mx) acc += yv[row + x];
             }
         }
     }
-    fc[(X + 1) + (long)c.sx * (Y + 1) + c.sxy * (Z + 1)] = acc;
+    fc[i] = acc;
 }
 
 template <typename T>
-void lc_restrict(const CoarseLevel& F, const CoarseLevel& C, const T* r, T* fc, double omega,
+void lc_restrict(const CoarseLevel& F, const CoarseLevel& C, const T* r, T* y, T* fc, double omega,
                  hipStream_t s) {
-    KTimer kt_(T_COARSE, s, lc_bytes(F, sizeof(T), 1) + C.n_unknowns * (long)sizeof(T));
+    KTimer kt_(T_COARSE, s, lc_bytes(F, sizeof(T), 3) + C.n_unknowns * (long)sizeof(T));
     if (F.sym)
-        hipLaunchKernelGGL((k_lc_restrict<T, true>), lc_grid(C), dim3(kWave, kBlockY), 0, s,
-                           F.view<T>(), C.view<T>(), r, fc, (T)omega);
+        hipLaunchKernelGGL((k_lc_restrict_y<T, true>), lc_grid(F), dim3(kThreads), 0, s,
+                           F.view<T>(), r, y, (T)omega);
     else
-        hipLaunchKernelGGL((k_lc_restrict<T, false>), lc_grid(C), dim3(kWave, kBlockY), 0, s,
-                           F.view<T>(), C.view<T>(), r, fc, (T)omega);
+        hipLaunchKernelGGL((k_lc_restrict_y<T, false>), lc_grid(F), dim3(kThreads), 0, s,
+                           F.view<T>(), r, y, (T)omega);
+    hipLaunchKernelGGL((k_lc_restrict_sum<T>), lc_grid(C), dim3(kThreads), 0, s, F.view<T>(),
+                       C.view<T>(), y, fc);
     HIPCHECK(hipGetLastError());
 }
 template void lc_restrict<double>(const CoarseLevel&, const CoarseLevel&, const double*, double*,
-                                  double, hipStream_t);
+                                  double*, double, hipStream_t);
 template void lc_restrict<float>(const CoarseLevel&, const CoarseLevel&, const float*, float*,
-                                 double, hipStream_t);
+                                 float*, double, hipStream_t);
 
 // x += P v = P_tent v - w D^-1 A P_tent v on the fine level's unknowns.
 template <typename T, bool SYM>
@@ -292,10 +303,10 @@ void lc_prolong(const CoarseLevel& F, const CoarseLevel& C, const T* vc, T* x, d
                 hipStream_t s) {
     KTimer kt_(T_COARSE, s, lc_bytes(F, sizeof(T), 2) + C.n_unknowns * (long)sizeof(T));
     if (F.sym)
-        hipLaunchKernelGGL((k_lc_prolong<T, true>), lc_grid(F), dim3(kWave, kBlockY), 0, s,
+        hipLaunchKernelGGL((k_lc_prolong<T, true>), lc_grid(F), dim3(kThreads), 0, s,
                            F.view<T>(), C.view<T>(), vc, x, (T)omega);
     else
-        hipLaunchKernelGGL((k_lc_prolong<T, false>), lc_grid(F), dim3(kWave, kBlockY), 0, s,
+        hipLaunchKernelGGL((k_lc_prolong<T, false>), lc_grid(F), dim3(kThreads), 0, s,
                            F.view<T>(), C.view<T>(), vc, x, (T)omega);
     HIPCHECK(hipGetLastError());
 }

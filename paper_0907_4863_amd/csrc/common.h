@@ -38,6 +38,7 @@ __host__ __device__ constexpr int dir_to_k(int d) {
 template <typename T>
 struct L0View {
     int nx, ny, nz, nsegx;
+    int gy, zb;         // solve-time tiling: line groups of 4, planes per block
     long nxy;
     const uint64_t* unk;
     const uint64_t* irr;
@@ -133,6 +134,7 @@ ChebCoef cheb_coefficients(double lam_hi, double ratio, int degree);
 
 struct FineLevel {
     int nx, ny, nz, nsegx;
+    int zb = 4;                 // planes per block of the solve-time kernels
     long nxy, nbox, nseg;
     double h[3];
     uint64_t* unk = nullptr;
@@ -186,6 +188,8 @@ struct saamg_hierarchy {
     long* cidx = nullptr;     // storage index of each coarsest-level unknown
     double t_setup_ms = 0;
     int64_t bytes = 0;
+    // work vectors of saamg_solve / saamg_precond_apply, allocated on first use
+    saamg_state* ws = nullptr;
 };
 
 namespace saamg {
@@ -193,6 +197,8 @@ template <typename T>
 inline L0View<T> FineLevel::view() const {
     L0View<T> v;
     v.nx = nx; v.ny = ny; v.nz = nz; v.nsegx = nsegx; v.nxy = nxy;
+    v.gy = (ny + kBlockY - 1) / kBlockY;
+    v.zb = zb;
     v.unk = unk; v.irr = irr; v.base = base;
     for (int d = 0; d < 6; ++d) {
         if constexpr (sizeof(T) == 8) {

@@ -1,30 +1,49 @@
 // Level-0 (lattice) kernels: operator build, stencils, Chebyshev steps, transfer
 // operators to level 1, and the fused fp64 CG vector kernels.
 //
-// Thread mapping: blocks of 64 x 4 threads; one wavefront covers one 64-node segment of
-// an x-line (so segment masks are wave-uniform), a block covers 4 lines, and each block
-// walks kZB consecutive z-planes.
+// Solve-time kernels use one mapping: a block of 64 x 4 threads owns a tile of one
+// 64-node x-segment by 4 lines and marches along z through `zb` planes.  One wavefront
+// is one segment row, so segment masks are wave-uniform (scalar loads) and empty
+// segments are skipped.  Along z each lane carries its column (z-1, z, z+1) in
+// registers; x-neighbours come from adjacent lanes, y-neighbours from L1/L2.  Block
+// numbers are remapped so that the blocks dispatched to one XCD form a contiguous
+// z-slab of tiles (the chip hands out blocks round-robin over its 8 XCDs, each with its
+// own L2).  Kernels write only unknown nodes; every level-0 work vector is zero at
+// the other nodes from allocation on.
 #include "launch.h"
 
 namespace saamg {
 
-constexpr int kZB = 4;
+// setup kernels: plain 3-D grid of 64 x 4 blocks, kZBS planes per block
+constexpr int kZBS = 4;
 
 static inline dim3 l0_grid(const FineLevel& L) {
-    return dim3(L.nsegx, (L.ny + kBlockY - 1) / kBlockY, (L.nz + kZB - 1) / kZB);
+    return dim3(L.nsegx, (L.ny + kBlockY - 1) / kBlockY, (L.nz + kZBS - 1) / kZBS);
 }
+
 // Level-0 metadata streamed by every stencil launch: segment masks and table slots,
 // plus the irregular rows' coefficients.
 static inline long l0_meta_bytes(const FineLevel& L, int wsize, bool trans_too) {
     return L.nseg * 20 + L.n_irr * 6L * wsize * (trans_too ? 2 : 1);
 }
 
-long l0_blocks(const FineLevel& L) {
-    dim3 g = l0_grid(L);
-    return (long)g.x * g.y * g.z;
+// Planes per block for the solve-time kernels: long z-marches, but enough blocks to
+// fill the chip.
+int l0_choose_zb(int nsegx, int ny, int nz) {
+    const long tiles = (long)nsegx * ((ny + kBlockY - 1) / kBlockY);
+    int zb = 32;
+    while (zb > 2 && tiles * ((nz + zb - 1) / zb) < 8192) zb /= 2;
+    return zb;
 }
 
-// Per-lane view of one level-0 node inside the current segment.
+long l0_blocks(const FineLevel& L) {
+    const long gy = (L.ny + kBlockY - 1) / kBlockY;
+    return (long)L.nsegx * gy * ((L.nz + L.zb - 1) / L.zb);
+}
+
+static inline dim3 l0_mgrid(const FineLevel& L) { return dim3((unsigned)l0_blocks(L)); }
+
+// Per-lane view of one level-0 node (setup kernels).
 struct L0Node {
     long i;       // box index
     bool unk;     // unknown
@@ -51,40 +70,88 @@ __device__ inline L0Node l0_node(const L0View<T>& v, int x, int y, int z) {
     return n;
 }
 
-// Lookup of an arbitrary node (no wave-uniformity assumed).
-template <typename T>
-__device__ inline L0Node l0_node_any(const L0View<T>& v, int x, int y, int z) {
-    return l0_node(v, x, y, z);
-}
-
-// (A x)_i of the scaled level-0 operator (or its transpose) for an unknown row, where
-// X(j) yields the input value at box index j.
-template <typename T, bool TR, class F>
-__device__ inline T l0_stencil(const L0View<T>& v, const L0Node& n, F X) {
-    const long i = n.i;
-    T acc = X(i);
-    if (!n.irr) {
-        acc += v.c[0] * (X(i - 1) + X(i + 1)) + v.c[1] * (X(i - v.nx) + X(i + v.nx)) +
-               v.c[2] * (X(i - v.nxy) + X(i + v.nxy));
-    } else {
-        const T* const* t = TR ? v.tabT : v.tab;
-        const int r = n.rank;
-        acc += t[0][r] * X(i - 1) + t[1][r] * X(i + 1) + t[2][r] * X(i - v.nx) +
-               t[3][r] * X(i + v.nx) + t[4][r] * X(i - v.nxy) + t[5][r] * X(i + v.nxy);
-    }
-    return acc;
-}
-
 #define L0_LOOP_BEGIN                                              \
     const int x = blockIdx.x * kWave + threadIdx.x;                \
     const int y = blockIdx.y * kBlockY + threadIdx.y;              \
-    const int z0 = blockIdx.z * kZB;                               \
-    const int z1 = min(z0 + kZB, v.nz);                            \
+    const int z0 = blockIdx.z * kZBS;                              \
+    const int z1 = min(z0 + kZBS, v.nz);                           \
     for (int z = z0; z < z1; ++z) {                                \
         const L0Node n = l0_node(v, x, y, z);                      \
         const bool inb = x < v.nx && y < v.ny;
 
 #define L0_LOOP_END }
+
+// ---------------------------------------------------------------- solve-time engine
+
+// Tile of this block after the XCD-aware remap.
+template <typename T>
+__device__ inline void l0_tile(const L0View<T>& v, int* bx, int* by, int* bz) {
+    const long b = blockIdx.x, nb = gridDim.x;
+    const long q = nb >> 3;
+    const long lb = (b < 8 * q) ? (b & 7) * q + (b >> 3) : b;
+    *bx = (int)(lb % v.nsegx);
+    const long t = lb / v.nsegx;
+    *by = (int)(t % v.gy);
+    *bz = (int)(t / v.gy);
+}
+
+// March over this block's tile.  For every unknown node, body(i, c, ax, x, y, z) is called
+// with its box index and coordinates, the input value c = X(i) and, when STENCIL, ax = (A X)_i (TR: A^T X)
+// of the scaled operator.  X(j) must be zero at nodes that are not unknowns.
+template <typename T, bool STENCIL, bool TR, class Load, class Body>
+__device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Body body) {
+    int bx, by, bz;
+    l0_tile(v, &bx, &by, &bz);
+    const int lane = threadIdx.x;
+    const int x = bx * kWave + lane;
+    const int y = __builtin_amdgcn_readfirstlane(by * kBlockY + (int)threadIdx.y);
+    if (y < 1 || y > v.ny - 2) return;
+    const bool inx = x < v.nx;
+    const int z0 = max(bz * v.zb, 1), z1 = min(bz * v.zb + v.zb, v.nz - 1);
+    const long nx = v.nx, nxy = v.nxy;
+    const T* const* tb = TR ? v.tabT : v.tab;
+    bool valid = false;
+    T zm = 0, c = 0;
+    for (int z = z0; z < z1; ++z) {
+        const long seg = ((long)z * v.ny + y) * v.nsegx + bx;
+        const uint64_t u = v.unk[seg];
+        if (u == 0) {
+            valid = false;
+            continue;
+        }
+        const long i = x + nx * y + nxy * z;
+        const bool unk = (u >> lane) & 1ull;
+        if (!STENCIL) {
+            if (unk) body(i, T(0), T(0), x, y, z);
+            continue;
+        }
+        if (!valid) {
+            c = inx ? X(i) : T(0);
+            zm = inx ? X(i - nxy) : T(0);
+            valid = true;
+        }
+        const T zp = inx ? X(i + nxy) : T(0);
+        T xm = __shfl_up(c, 1, kWave);
+        T xp = __shfl_down(c, 1, kWave);
+        if (lane == 0) xm = unk ? X(i - 1) : T(0);
+        if (lane == kWave - 1) xp = unk ? X(i + 1) : T(0);
+        if (unk) {
+            const uint64_t r = v.irr[seg];
+            const T ym = X(i - nx), yp = X(i + nx);
+            T ax;
+            if (!((r >> lane) & 1ull)) {
+                ax = c + v.c[0] * (xm + xp) + v.c[1] * (ym + yp) + v.c[2] * (zm + zp);
+            } else {
+                const int rk = v.base[seg] + __popcll(r & ((1ull << lane) - 1ull));
+                ax = c + tb[0][rk] * xm + tb[1][rk] * xp + tb[2][rk] * ym + tb[3][rk] * yp +
+                     tb[4][rk] * zm + tb[5][rk] * zp;
+            }
+            body(i, c, ax, x, y, z);
+        }
+        zm = c;
+        c = zp;
+    }
+}
 
 // ================================================================ finalisation
 
@@ -173,7 +240,7 @@ __global__ void __launch_bounds__(kThreads) k_build_masks(int nx, int ny, int nz
     const int x = blockIdx.x * kWave + threadIdx.x;
     const int y = blockIdx.y * kBlockY + threadIdx.y;
     const long nxy = (long)nx * ny;
-    for (int z = blockIdx.z * kZB; z < min(blockIdx.z * kZB + kZB, nz); ++z) {
+    for (int z = blockIdx.z * kZBS; z < min(blockIdx.z * kZBS + kZBS, nz); ++z) {
         bool u = false, r = false;
         if (x < nx && y < ny) {
             const long i = x + (long)nx * y + nxy * z;
@@ -382,38 +449,34 @@ void l0_unknown_list(const FineLevel& L, long* out, hipStream_t s) {
 
 // ================================================================ operators
 
+// y = A x (or A^T x) on every box node (zero where not an unknown).
 template <typename T, bool TR>
 __global__ void __launch_bounds__(kThreads) k_l0_apply(L0View<T> v, const T* __restrict__ xv,
                                                        T* __restrict__ yv) {
-    L0_LOOP_BEGIN
-    if (inb) {
-        T r = 0;
-        if (n.unk) r = l0_stencil<T, TR>(v, n, [&](long j) { return xv[j]; });
-        yv[n.i] = r;
-    }
-    L0_LOOP_END
+    l0_march<T, true, TR>(v, [&](long j) { return xv[j]; },
+                          [&](long i, T c, T ax, int, int, int) { yv[i] = ax; });
 }
 
 template <typename T>
 void l0_apply(const FineLevel& L, bool trans, const T* x, T* y, hipStream_t s) {
     L0View<T> v = L.view<T>();
+    HIPCHECK(hipMemsetAsync(y, 0, sizeof(T) * L.nbox, s));
     if (trans)
-        hipLaunchKernelGGL((k_l0_apply<T, true>), l0_grid(L), dim3(kWave, kBlockY), 0, s, v, x, y);
+        hipLaunchKernelGGL((k_l0_apply<T, true>), l0_mgrid(L), dim3(kWave, kBlockY), 0, s, v, x, y);
     else
-        hipLaunchKernelGGL((k_l0_apply<T, false>), l0_grid(L), dim3(kWave, kBlockY), 0, s, v, x, y);
+        hipLaunchKernelGGL((k_l0_apply<T, false>), l0_mgrid(L), dim3(kWave, kBlockY), 0, s, v, x, y);
     HIPCHECK(hipGetLastError());
 }
 template void l0_apply<double>(const FineLevel&, bool, const double*, double*, hipStream_t);
 template void l0_apply<float>(const FineLevel&, bool, const float*, float*, hipStream_t);
 
 __global__ void __launch_bounds__(kThreads) k_l0_power_start(L0View<double> v, double* w) {
-    L0_LOOP_BEGIN
-    if (inb) w[n.i] = n.unk ? start_value(n.i) : 0.0;
-    L0_LOOP_END
+    l0_march<double, false, false>(v, [&](long) { return 0.0; },
+                                   [&](long i, double, double, int, int, int) { w[i] = start_value(i); });
 }
 
 void l0_power_start(const FineLevel& L, double* v, hipStream_t s) {
-    hipLaunchKernelGGL(k_l0_power_start, l0_grid(L), dim3(kWave, kBlockY), 0, s,
+    hipLaunchKernelGGL(k_l0_power_start, l0_mgrid(L), dim3(kWave, kBlockY), 0, s,
                        L.view<double>(), v);
     HIPCHECK(hipGetLastError());
 }
@@ -426,20 +489,14 @@ __global__ void __launch_bounds__(kThreads) k_l0_power_step(L0View<double> v,
     __shared__ double lds[kThreads / kWave];
     const double sc = scal[S_INVN];
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    L0_LOOP_BEGIN
-    if (inb) {
-        double r = 0.0;
-        if (n.unk) {
-            r = l0_stencil<double, false>(v, n, [&](long j) { return vin[j] * sc; });
-            const double u = vin[n.i] * sc;
-            a0 += r * r;
-            a1 += u * r;
-            a2 += u * u;
-        }
-        w[n.i] = r;
-    }
-    L0_LOOP_END
-    const long bid = block_linear_id(), nb = grid_blocks();
+    l0_march<double, true, false>(v, [&](long j) { return vin[j] * sc; },
+                                  [&](long i, double u, double au, int, int, int) {
+                                      w[i] = au;
+                                      a0 += au * au;
+                                      a1 += u * au;
+                                      a2 += u * u;
+                                  });
+    const long bid = blockIdx.x, nb = gridDim.x;
     double s0 = block_sum(a0, lds), s1 = block_sum(a1, lds), s2 = block_sum(a2, lds);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
         part[bid] = s0;
@@ -450,7 +507,7 @@ __global__ void __launch_bounds__(kThreads) k_l0_power_step(L0View<double> v,
 
 void l0_power_step(const FineLevel& L, const double* v, const double* scal, double* w,
                    double* partials, hipStream_t s) {
-    hipLaunchKernelGGL(k_l0_power_step, l0_grid(L), dim3(kWave, kBlockY), 0, s,
+    hipLaunchKernelGGL(k_l0_power_step, l0_mgrid(L), dim3(kWave, kBlockY), 0, s,
                        L.view<double>(), v, scal, w, partials);
     HIPCHECK(hipGetLastError());
 }
@@ -469,34 +526,31 @@ __global__ void __launch_bounds__(kThreads) k_l0_cheb(L0View<T> v, const TF* __r
                                                       double* part) {
     __shared__ double lds[kThreads / kWave];
     double acc = 0.0;
-    L0_LOOP_BEGIN
-    if (inb) {
-        T xo = 0, dn = 0;
-        if (n.unk) {
-            const T fi = (T)f[n.i];
-            if (MODE == CHEB_ZERO1) {
-                xo = c20 * fi;
-                dn = xo;
-            } else if (MODE == CHEB_ZERO2) {
-                const T ax = l0_stencil<T, false>(v, n, [&](long j) { return c20 * (T)f[j]; });
-                const T x1 = c20 * fi;
-                dn = c1 * x1 + c2 * (fi - ax);
-                xo = x1 + dn;
-            } else {
-                const T ax = l0_stencil<T, false>(v, n, [&](long j) { return xin[j]; });
-                const T r = fi - ax;
-                dn = (MODE == CHEB_FIRST) ? c20 * r : c1 * din[n.i] + c2 * r;
-                xo = xin[n.i] + dn;
-            }
-            if (DOT) acc += (double)f[n.i] * (double)xo;
-        }
-        xout[n.i] = xo;
-        if (dout) dout[n.i] = dn;
+    auto emit = [&](long i, T xo, T dn) {
+        xout[i] = xo;
+        if (dout) dout[i] = dn;
+        if (DOT) acc += (double)f[i] * (double)xo;
+    };
+    if (MODE == CHEB_ZERO1) {
+        l0_march<T, false, false>(v, [&](long) { return T(0); }, [&](long i, T, T, int, int, int) {
+            const T xo = c20 * (T)f[i];
+            emit(i, xo, xo);
+        });
+    } else if (MODE == CHEB_ZERO2) {
+        l0_march<T, true, false>(v, [&](long j) { return c20 * (T)f[j]; }, [&](long i, T x1, T ax, int, int, int) {
+            const T dn = c1 * x1 + c2 * ((T)f[i] - ax);
+            emit(i, x1 + dn, dn);
+        });
+    } else {
+        l0_march<T, true, false>(v, [&](long j) { return xin[j]; }, [&](long i, T xi, T ax, int, int, int) {
+            const T r = (T)f[i] - ax;
+            const T dn = (MODE == CHEB_FIRST) ? c20 * r : c1 * din[i] + c2 * r;
+            emit(i, xi + dn, dn);
+        });
     }
-    L0_LOOP_END
     if (DOT) {
         double sb = block_sum(acc, lds);
-        if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = sb;
+        if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
     }
 }
 
@@ -508,7 +562,7 @@ void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* d
                      : (mode == CHEB_FIRST) ? wf + 2 * w : wf + 3 * w;
     KTimer kt_(T_L0_CHEB, s, n * (vec + (dout ? w : 0)) + l0_meta_bytes(L, w, false));
     L0View<T> v = L.view<T>();
-    dim3 g = l0_grid(L), b(kWave, kBlockY);
+    dim3 g = l0_mgrid(L), b(kWave, kBlockY);
 #define CHEB_LAUNCH(M)                                                                         \
     if (dot)                                                                                   \
         hipLaunchKernelGGL((k_l0_cheb<TF, T, M, true>), g, b, 0, s, v, f, xin, din, xout, dout, \
@@ -539,20 +593,15 @@ template <typename TF, typename T>
 __global__ void __launch_bounds__(kThreads) k_l0_residual(L0View<T> v, const TF* __restrict__ f,
                                                           const T* __restrict__ xv,
                                                           T* __restrict__ r) {
-    L0_LOOP_BEGIN
-    if (inb) {
-        T o = 0;
-        if (n.unk) o = (T)f[n.i] - l0_stencil<T, false>(v, n, [&](long j) { return xv[j]; });
-        r[n.i] = o;
-    }
-    L0_LOOP_END
+    l0_march<T, true, false>(v, [&](long j) { return xv[j]; },
+                             [&](long i, T, T ax, int, int, int) { r[i] = (T)f[i] - ax; });
 }
 
 template <typename TF, typename T>
 void l0_residual(const FineLevel& L, const TF* f, const T* x, T* r, hipStream_t s) {
     KTimer kt_(T_L0_RESID, s, L.n_unknowns * (long)(sizeof(TF) + 2 * sizeof(T)) +
                                  l0_meta_bytes(L, sizeof(T), false));
-    hipLaunchKernelGGL((k_l0_residual<TF, T>), l0_grid(L), dim3(kWave, kBlockY), 0, s,
+    hipLaunchKernelGGL((k_l0_residual<TF, T>), l0_mgrid(L), dim3(kWave, kBlockY), 0, s,
                        L.view<T>(), f, x, r);
     HIPCHECK(hipGetLastError());
 }
@@ -563,30 +612,34 @@ template void l0_residual<double, float>(const FineLevel&, const double*, const 
 template void l0_residual<float, float>(const FineLevel&, const float*, const float*, float*,
                                         hipStream_t);
 
-// Restriction to level 1: fc(I) = sum over the aggregate's unknowns of (r - w A^T r),
-// i.e. P^T r with P = (I - w A) P_tent (D = I at level 0).  One thread per coarse node.
+// Restriction to level 1, P^T r with P = (I - w A) P_tent (D = I at level 0), in two
+// passes: y = r - w A^T r on every fine unknown, then the sum of y over each aggregate.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_l0_restrict(L0View<T> v, LCView<T> c,
-                                                          const T* __restrict__ r,
-                                                          T* __restrict__ fc, T omega) {
-    const int X = blockIdx.x * kWave + threadIdx.x;
-    const int Y = blockIdx.y * kBlockY + threadIdx.y;
-    const int Z = blockIdx.z;
-    if (X >= c.mx || Y >= c.my) return;
+__global__ void __launch_bounds__(kThreads) k_l0_restrict_y(L0View<T> v, const T* __restrict__ r,
+                                                            T* __restrict__ yv, T omega) {
+    l0_march<T, true, true>(v, [&](long j) { return r[j]; },
+                            [&](long i, T ri, T atr, int, int, int) { yv[i] = ri - omega * atr; });
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_l0_restrict_sum(int nx, int ny, int nz, LCView<T> c,
+                                                         const T* __restrict__ yv,
+                                                         T* __restrict__ fc) {
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= (long)c.mx * c.my) return;
+    const int X = (int)(t % c.mx), Y = (int)(t / c.mx), Z = blockIdx.y;
+    const long nxy = (long)nx * ny;
     T acc = 0;
     for (int dz = 0; dz < 3; ++dz) {
         const int z = 3 * Z + dz;
-        if (z >= v.nz) break;
+        if (z >= nz) break;
         for (int dy = 0; dy < 3; ++dy) {
             const int y = 3 * Y + dy;
-            if (y >= v.ny) break;
+            if (y >= ny) break;
+            const long row = (long)nx * y + nxy * z;
             for (int dx = 0; dx < 3; ++dx) {
                 const int x = 3 * X + dx;
-                if (x >= v.nx) break;
-                const L0Node n = l0_node_any(v, x, y, z);
-                if (!n.unk) continue;
-                const T at = l0_stencil<T, true>(v, n, [&](long j) { return r[j]; });
-                acc += r[n.i] - omega * at;
+                if (x < nx) acc += yv[row + x];
             }
         }
     }
@@ -594,18 +647,20 @@ __global__ void __launch_bounds__(kThreads) k_l0_restrict(L0View<T> v, LCView<T>
 }
 
 template <typename T>
-void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* fc, double omega,
+void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* fc, double omega,
                  hipStream_t s) {
-    KTimer kt_(T_L0_RESTRICT, s, (L.n_unknowns + C.n_unknowns) * (long)sizeof(T) +
-                                    l0_meta_bytes(L, sizeof(T), false));
-    dim3 g((C.mx + kWave - 1) / kWave, (C.my + kBlockY - 1) / kBlockY, C.mz);
-    hipLaunchKernelGGL((k_l0_restrict<T>), g, dim3(kWave, kBlockY), 0, s, L.view<T>(),
-                       C.view<T>(), r, fc, (T)omega);
+    KTimer kt_(T_L0_RESTRICT, s, (L.n_unknowns * 3 + C.n_unknowns) * (long)sizeof(T) +
+                                    l0_meta_bytes(L, sizeof(T), true));
+    hipLaunchKernelGGL((k_l0_restrict_y<T>), l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<T>(),
+                       r, y, (T)omega);
+    dim3 g((unsigned)(((long)C.mx * C.my + 255) / 256), C.mz);
+    hipLaunchKernelGGL((k_l0_restrict_sum<T>), g, dim3(256), 0, s, L.nx, L.ny, L.nz, C.view<T>(),
+                       y, fc);
     HIPCHECK(hipGetLastError());
 }
 template void l0_restrict<double>(const FineLevel&, const CoarseLevel&, const double*, double*,
-                                  double, hipStream_t);
-template void l0_restrict<float>(const FineLevel&, const CoarseLevel&, const float*, float*,
+                                  double*, double, hipStream_t);
+template void l0_restrict<float>(const FineLevel&, const CoarseLevel&, const float*, float*, float*,
                                  double, hipStream_t);
 
 // Prolongation from level 1: x += P v = P_tent v - w A (P_tent v).
@@ -613,27 +668,28 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads) k_l0_prolong(L0View<T> v, LCView<T> c,
                                                          const T* __restrict__ vc,
                                                          T* __restrict__ xv, T omega) {
-    L0_LOOP_BEGIN
-    if (inb && n.unk) {
-        // coarse storage index of the aggregate holding box index j = (xj, yj, zj)
+    l0_march<T, false, false>(v, [&](long) { return T(0); }, [&](long i, T, T, int x, int y, int z) {
+        // coarse storage index of the aggregate holding box node (xj, yj, zj)
         auto agg = [&](int xj, int yj, int zj) -> long {
             return (xj / 3 + 1) + (long)c.sx * (yj / 3 + 1) + c.sxy * (zj / 3 + 1);
         };
+        const int sx = x & 63;
+        const long seg = ((long)z * v.ny + y) * v.nsegx + (x >> 6);
+        const uint64_t r = v.irr[seg];
         const T pv = vc[agg(x, y, z)];
         T apv;
-        if (!n.irr) {
+        if (!((r >> sx) & 1ull)) {
             apv = pv + v.c[0] * (vc[agg(x - 1, y, z)] + vc[agg(x + 1, y, z)]) +
                   v.c[1] * (vc[agg(x, y - 1, z)] + vc[agg(x, y + 1, z)]) +
                   v.c[2] * (vc[agg(x, y, z - 1)] + vc[agg(x, y, z + 1)]);
         } else {
-            const int rk = n.rank;
+            const int rk = v.base[seg] + __popcll(r & ((1ull << sx) - 1ull));
             apv = pv + v.tab[0][rk] * vc[agg(x - 1, y, z)] + v.tab[1][rk] * vc[agg(x + 1, y, z)] +
                   v.tab[2][rk] * vc[agg(x, y - 1, z)] + v.tab[3][rk] * vc[agg(x, y + 1, z)] +
                   v.tab[4][rk] * vc[agg(x, y, z - 1)] + v.tab[5][rk] * vc[agg(x, y, z + 1)];
         }
-        xv[n.i] += pv - omega * apv;
-    }
-    L0_LOOP_END
+        xv[i] += pv - omega * apv;
+    });
 }
 
 template <typename T>
@@ -641,7 +697,7 @@ void l0_prolong(const FineLevel& L, const CoarseLevel& C, const T* vc, T* x, dou
                 hipStream_t s) {
     KTimer kt_(T_L0_PROLONG, s, (2 * L.n_unknowns + C.n_unknowns) * (long)sizeof(T) +
                                    l0_meta_bytes(L, sizeof(T), false));
-    hipLaunchKernelGGL((k_l0_prolong<T>), l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<T>(),
+    hipLaunchKernelGGL((k_l0_prolong<T>), l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<T>(),
                        C.view<T>(), vc, x, (T)omega);
     HIPCHECK(hipGetLastError());
 }
@@ -656,23 +712,16 @@ __global__ void __launch_bounds__(kThreads) k_cg_init(L0View<double> v, const do
                                                       const double* __restrict__ b,
                                                       const double* __restrict__ x0,
                                                       double* __restrict__ bs, double* __restrict__ xv) {
-    L0_LOOP_BEGIN
-    if (inb) {
-        double bo = 0.0, xo = 0.0;
-        if (n.unk) {
-            const double sg = sigma[n.i];
-            bo = sg * b[n.i];
-            if (x0) xo = x0[n.i] / sg;
-        }
-        bs[n.i] = bo;
-        xv[n.i] = xo;
-    }
-    L0_LOOP_END
+    l0_march<double, false, false>(v, [&](long) { return 0.0; }, [&](long i, double, double, int, int, int) {
+        const double sg = sigma[i];
+        bs[i] = sg * b[i];
+        xv[i] = x0 ? x0[i] / sg : 0.0;
+    });
 }
 
 void cg_init(const FineLevel& L, const double* b, const double* x0, double* bs, double* x,
              hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_init, l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(),
+    hipLaunchKernelGGL(k_cg_init, l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(),
                        L.sigma, b, x0, bs, x);
     HIPCHECK(hipGetLastError());
 }
@@ -683,19 +732,14 @@ __global__ void __launch_bounds__(kThreads) k_cg_resid(L0View<double> v, const d
                                                        double* __restrict__ r, double* part) {
     __shared__ double lds[kThreads / kWave];
     double a0 = 0.0, a1 = 0.0;
-    L0_LOOP_BEGIN
-    if (inb) {
-        double o = 0.0;
-        if (n.unk) {
-            const double bi = bs[n.i];
-            o = bi - l0_stencil<double, false>(v, n, [&](long j) { return xv[j]; });
-            a0 += o * o;
-            a1 += bi * bi;
-        }
-        r[n.i] = o;
-    }
-    L0_LOOP_END
-    const long bid = block_linear_id(), nb = grid_blocks();
+    l0_march<double, true, false>(v, [&](long j) { return xv[j]; }, [&](long i, double, double ax, int, int, int) {
+        const double bi = bs[i];
+        const double o = bi - ax;
+        r[i] = o;
+        a0 += o * o;
+        a1 += bi * bi;
+    });
+    const long bid = blockIdx.x, nb = gridDim.x;
     double s0 = block_sum(a0, lds), s1 = block_sum(a1, lds);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
         part[bid] = s0;
@@ -705,7 +749,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_resid(L0View<double> v, const d
 
 void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
               hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_resid, l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), bs,
+    hipLaunchKernelGGL(k_cg_resid, l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), bs,
                        x, r, partials);
     HIPCHECK(hipGetLastError());
 }
@@ -720,28 +764,21 @@ __global__ void __launch_bounds__(kThreads) k_cg_pq(L0View<double> v, const TZ* 
     __shared__ double lds[kThreads / kWave];
     const double beta = scal[S_BETA];
     double acc = 0.0;
-    L0_LOOP_BEGIN
-    if (inb) {
-        double pi = 0.0, qi = 0.0;
-        if (n.unk) {
-            auto P = [&](long j) { return (double)zv[j] + beta * pold[j]; };
-            pi = P(n.i);
-            qi = l0_stencil<double, false>(v, n, P);
-            acc += pi * qi;
-        }
-        pnew[n.i] = pi;
-        q[n.i] = qi;
-    }
-    L0_LOOP_END
+    l0_march<double, true, false>(v, [&](long j) { return (double)zv[j] + beta * pold[j]; },
+                                  [&](long i, double pi, double qi, int, int, int) {
+                                      pnew[i] = pi;
+                                      q[i] = qi;
+                                      acc += pi * qi;
+                                  });
     double sb = block_sum(acc, lds);
-    if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = sb;
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
 template <typename TZ>
 void cg_pq(const FineLevel& L, const TZ* z, const double* pold, double* pnew, double* q,
            const double* scal, double* partials, hipStream_t s) {
     KTimer kt_(T_CG_PQ, s, L.n_unknowns * (long)(sizeof(TZ) + 24) + l0_meta_bytes(L, 8, false));
-    hipLaunchKernelGGL((k_cg_pq<TZ>), l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), z,
+    hipLaunchKernelGGL((k_cg_pq<TZ>), l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), z,
                        pold, pnew, q, scal, partials);
     HIPCHECK(hipGetLastError());
 }
@@ -761,29 +798,28 @@ __global__ void __launch_bounds__(kThreads) k_cg_xr(L0View<double> v, double* __
     const double alpha = scal[S_ALPHA];
     const bool ok = scal[S_PQ] > 0.0 && scal[S_RHO] > 0.0 && isfinite(alpha);
     double acc = 0.0;
-    L0_LOOP_BEGIN
-    if (inb && n.unk) {
-        double ri = r[n.i];
+    l0_march<double, false, false>(v, [&](long) { return 0.0; }, [&](long i, double, double, int, int, int) {
+        double ri = r[i];
         if (ok) {
-            xv[n.i] += alpha * p[n.i];
-            ri -= alpha * q[n.i];
-            r[n.i] = ri;
+            xv[i] += alpha * p[i];
+            ri -= alpha * q[i];
+            r[i] = ri;
         }
         acc += ri * ri;
-    }
-    L0_LOOP_END
+    });
     double sb = block_sum(acc, lds);
-    if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = sb;
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
 void cg_xr(const FineLevel& L, double* x, const double* p, double* r, const double* q,
            const double* scal, double* partials, hipStream_t s) {
     KTimer kt_(T_CG_XR, s, L.n_unknowns * 48L);
-    hipLaunchKernelGGL(k_cg_xr, l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), x, p, r,
+    hipLaunchKernelGGL(k_cg_xr, l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), x, p, r,
                        q, scal, partials);
     HIPCHECK(hipGetLastError());
 }
 
+// out = sigma x on every box node (0 where not an unknown): the caller's buffer.
 __global__ void __launch_bounds__(kThreads) k_cg_unscale(L0View<double> v, const double* __restrict__ sigma,
                                                          const double* __restrict__ xv,
                                                          double* __restrict__ out) {
@@ -798,21 +834,33 @@ void cg_unscale(const FineLevel& L, const double* x, double* out, hipStream_t s)
     HIPCHECK(hipGetLastError());
 }
 
+__global__ void __launch_bounds__(kThreads) k_mask_copy(L0View<double> v, const double* __restrict__ a,
+                                                        double* __restrict__ b) {
+    l0_march<double, false, false>(v, [&](long) { return 0.0; },
+                                   [&](long i, double, double, int, int, int) { b[i] = a[i]; });
+}
+
+void cg_mask_copy(const FineLevel& L, const double* in, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_mask_copy, l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), in,
+                       out);
+    HIPCHECK(hipGetLastError());
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_l0_dot(L0View<double> v, const double* __restrict__ a,
                                                      const T* __restrict__ b, double* part) {
     __shared__ double lds[kThreads / kWave];
     double acc = 0.0;
-    L0_LOOP_BEGIN
-    if (inb && n.unk) acc += a[n.i] * (double)b[n.i];
-    L0_LOOP_END
+    l0_march<double, false, false>(v, [&](long) { return 0.0; }, [&](long i, double, double, int, int, int) {
+        acc += a[i] * (double)b[i];
+    });
     double sb = block_sum(acc, lds);
-    if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = sb;
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
 template <typename T>
 void l0_dot(const FineLevel& L, const double* a, const T* b, double* partials, hipStream_t s) {
-    hipLaunchKernelGGL((k_l0_dot<T>), l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), a,
+    hipLaunchKernelGGL((k_l0_dot<T>), l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), a,
                        b, partials);
     HIPCHECK(hipGetLastError());
 }
@@ -840,16 +888,6 @@ void l0_export_coef(const FineLevel& L, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_l0_export, l0_grid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), out,
                        L.nbox);
     HIPCHECK(hipGetLastError());
-}
-
-__global__ void k_tab_to_fp32(const double* a, float* b, long n) {
-    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t < n) b[t] = (float)a[t];
-}
-
-void l0_to_fp32(FineLevel& L, hipStream_t s) {
-    (void)L;
-    (void)s;  // the fp32 table is written together with the fp64 one
 }
 
 }  // namespace saamg

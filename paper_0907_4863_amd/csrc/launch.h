@@ -17,6 +17,7 @@ enum ChebMode { CHEB_ZERO1 = 0, CHEB_ZERO2, CHEB_FIRST, CHEB_NEXT };
 
 // Number of partial sums (blocks) written by the level-0 reduction kernels.
 long l0_blocks(const FineLevel& L);
+int l0_choose_zb(int nsegx, int ny, int nz);
 long lc_blocks(const CoarseLevel& C);
 
 void finalize(const double* partials, long nblk, int nq, double* scal, int op, int dst,
@@ -42,8 +43,9 @@ void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* d
              T* dout, double c1, double c2, double c2_0, double* dot_partials, hipStream_t s);
 template <typename TF, typename T>
 void l0_residual(const FineLevel& L, const TF* f, const T* x, T* r, hipStream_t s);
+// fc = P^T r in two passes; y is a level-0 scratch vector (zero off the unknowns)
 template <typename T>
-void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* fc, double omega,
+void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* fc, double omega,
                  hipStream_t s);
 template <typename T>
 void l0_prolong(const FineLevel& L, const CoarseLevel& C, const T* v, T* x, double omega,
@@ -60,6 +62,8 @@ void cg_pq(const FineLevel& L, const TZ* z, const double* pold, double* pnew, do
 void cg_xr(const FineLevel& L, double* x, const double* p, double* r, const double* q,
            const double* scal, double* partials, hipStream_t s);
 void cg_unscale(const FineLevel& L, const double* x, double* out, hipStream_t s);
+// out = in on the unknowns (out untouched elsewhere)
+void cg_mask_copy(const FineLevel& L, const double* in, double* out, hipStream_t s);
 // partial sums of a . b over level-0 unknowns (one per block of l0_blocks)
 template <typename T>
 void l0_dot(const FineLevel& L, const double* a, const T* b, double* partials, hipStream_t s);
@@ -76,7 +80,7 @@ void lc_cheb(const CoarseLevel& C, int mode, const T* f, const T* xin, const T* 
 template <typename T>
 void lc_residual(const CoarseLevel& C, const T* f, const T* x, T* r, hipStream_t s);
 template <typename T>
-void lc_restrict(const CoarseLevel& F, const CoarseLevel& C, const T* r, T* fc, double omega,
+void lc_restrict(const CoarseLevel& F, const CoarseLevel& C, const T* r, T* y, T* fc, double omega,
                  hipStream_t s);
 template <typename T>
 void lc_prolong(const CoarseLevel& F, const CoarseLevel& C, const T* v, T* x, double omega,

@@ -148,10 +148,10 @@ static T* vcycle(const saamg_hierarchy* H, VBuf<T>& B, int l, const double* f0, 
     // residual and restriction
     if (fine) {
         l0_residual<double, T>(H->l0, f0, x, other, s);
-        l0_restrict<T>(H->l0, H->lc[0], other, B.f[1], P.omega, s);
+        l0_restrict<T>(H->l0, H->lc[0], other, d, B.f[1], P.omega, s);
     } else {
         lc_residual<T>(H->lc[l - 1], fl, x, other, s);
-        lc_restrict<T>(H->lc[l - 1], H->lc[l], other, B.f[l + 1], P.omega, s);
+        lc_restrict<T>(H->lc[l - 1], H->lc[l], other, d, B.f[l + 1], P.omega, s);
     }
     T* v = vcycle<T>(H, B, l + 1, nullptr, nullptr, nullptr, s);
     // coarse-grid correction
@@ -547,6 +547,7 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
         L.nxy = nxy;
         L.nbox = nbox;
         L.nseg = seg_count(nx, ny, nz);
+        L.zb = l0_choose_zb(L.nsegx, ny, nz);
         L.h[0] = dom->hx;
         L.h[1] = dom->hy;
         L.h[2] = dom->hz;
@@ -790,9 +791,9 @@ static void level_apply_impl(saamg_hierarchy* H, int l, int op, const double* hi
         }
         case SAAMG_OP_RESTRICT:
             if (l == 0)
-                l0_restrict<T>(H->l0, H->lc[0], din, dout, H->par[0].omega, s);
+                l0_restrict<T>(H->l0, H->lc[0], din, tmp, dout, H->par[0].omega, s);
             else
-                lc_restrict<T>(H->lc[l - 1], H->lc[l], din, dout, H->par[l].omega, s);
+                lc_restrict<T>(H->lc[l - 1], H->lc[l], din, tmp, dout, H->par[l].omega, s);
             break;
         case SAAMG_OP_PROLONG:
             if (l == 0)
@@ -845,6 +846,11 @@ int saamg_destroy(saamg_hierarchy* H) {
                     (void*)L.sigma, (void*)H->Ainv, (void*)H->cidx})
         dfree(p);
     for (auto& C : H->lc) free_coarse(C);
+    if (H->ws) {
+        (void)hipStreamSynchronize(H->ws->s);
+        state_release(H->ws);
+        delete H->ws;
+    }
     delete H;
     return SAAMG_OK;
 }
@@ -875,18 +881,32 @@ int saamg_hierarchy_info(const saamg_hierarchy* H, saamg_info* info) {
     });
 }
 
+static saamg_state* workspace(saamg_hierarchy* H) {
+    if (!H->ws) {
+        saamg_state* S = new saamg_state();
+        try {
+            state_alloc(S, H);
+        } catch (...) {
+            state_release(S);
+            delete S;
+            throw;
+        }
+        H->ws = S;
+    }
+    return H->ws;
+}
+
 int saamg_solve(saamg_hierarchy* H, const double* d_b, const double* d_x0, double* d_x, double tol,
                 int max_iter, void* stream, saamg_result* res) {
-    saamg_state S;
-    int rc = guarded([&] {
+    return guarded([&] {
         if (!H || !d_b || !d_x) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
         if (!(tol > 0) || max_iter < 0) throw ApiError{SAAMG_INVALID_ARG, "tol > 0, max_iter >= 0"};
         HIPCHECK(hipSetDevice(H->device));
         auto t0 = std::chrono::steady_clock::now();
+        saamg_state& S = *workspace(H);
         S.s = (hipStream_t)stream;
         S.tol = tol;
         S.max_iter = max_iter;
-        state_alloc(&S, H);
         state_start(&S, d_b, d_x0);
         while (!S.done) {
             state_enqueue(&S);
@@ -898,8 +918,6 @@ int saamg_solve(saamg_hierarchy* H, const double* d_b, const double* d_x0, doubl
         state_fill_result(&S, res);
         return S.status;
     });
-    state_release(&S);
-    return rc;
 }
 
 int saamg_footprint_bytes(int nx, int ny, int nz, int variant, int precision, int64_t* hier_bytes,
@@ -1061,13 +1079,13 @@ int saamg_level_coefficients(saamg_hierarchy* H, int level, double* h_out) {
 }
 
 int saamg_precond_apply(saamg_hierarchy* H, const double* d_r, double* d_z, void* stream) {
-    saamg_state S;
-    int rc = guarded([&] {
+    return guarded([&] {
         if (!H || !d_r || !d_z) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
         HIPCHECK(hipSetDevice(H->device));
+        saamg_state& S = *workspace(H);
         S.s = (hipStream_t)stream;
-        state_alloc(&S, H);
-        HIPCHECK(hipMemcpyAsync(S.r, d_r, 8 * H->l0.nbox, hipMemcpyDeviceToDevice, S.s));
+        // the residual buffer must stay zero off the unknowns: copy via the scaled mask
+        cg_mask_copy(H->l0, d_r, S.r, S.s);
         precond(&S);
         if (S.mixed)
             f2d_copy((const float*)S.z, d_z, H->l0.nbox, S.s);
@@ -1076,8 +1094,6 @@ int saamg_precond_apply(saamg_hierarchy* H, const double* d_r, double* d_z, void
         HIPCHECK(hipStreamSynchronize(S.s));
         return (int)SAAMG_OK;
     });
-    state_release(&S);
-    return rc;
 }
 
 int saamg_operator_apply(saamg_hierarchy* H, const double* d_x, double* d_y, void* stream) {
