@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-timers", action="store_true",
                     help="time without per-kernel HIP events (roofline omitted)")
     ap.add_argument("--cpu-sample-planes", type=int, default=48)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
+    ap.add_argument("--skip-fp64", action="store_true")
     return ap.parse_args()
 
 
@@ -130,6 +133,15 @@ def main():
 
     w = W.by_name(args.workload)
     dev = torch.device("cuda:0")
+    if args.copy_mb:
+        n = args.copy_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {args.copy_mb} MiB done", file=sys.stderr, flush=True)
+        del src, dst
     print(f"[bench] workload {w.name} {w.nx}x{w.ny}x{w.nz}", file=sys.stderr, flush=True)
     dom = sa.domain_for(w.shape, w.nx, w.ny, w.nz)
     dof = dom.n_unknowns
@@ -138,6 +150,8 @@ def main():
     out = {}
     for tag, prec in (("mixed", sa.MIXED), ("fp64", sa.FP64)):
         if w.precision == sa.FP64 and tag == "mixed":
+            continue
+        if args.skip_fp64 and tag == "fp64" and w.precision == sa.MIXED:
             continue
         steps = args.steps if tag == ("mixed" if w.precision == sa.MIXED else "fp64") else \
             (args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2))

@@ -28,6 +28,8 @@ namespace saamg {
 constexpr int kWave = 64;
 constexpr int kBlockY = 4;          // 64 x 4 threads per block for box kernels
 constexpr int kThreads = kWave * kBlockY;
+constexpr int kMY = 4;              // lines per block of the level-0 solve-time kernels
+constexpr int kMThreads = kWave * kMY;
 constexpr int kFinThreads = 1024;   // single-block finalisation of partial sums
 
 // Direction d = 0..5 (-x,+x,-y,+y,-z,+z) as a 27-point offset index.
@@ -197,7 +199,7 @@ template <typename T>
 inline L0View<T> FineLevel::view() const {
     L0View<T> v;
     v.nx = nx; v.ny = ny; v.nz = nz; v.nsegx = nsegx; v.nxy = nxy;
-    v.gy = (ny + kBlockY - 1) / kBlockY;
+    v.gy = (ny + kMY - 1) / kMY;
     v.zb = zb;
     v.unk = unk; v.irr = irr; v.base = base;
     for (int d = 0; d < 6; ++d) {

@@ -30,14 +30,14 @@ static inline long l0_meta_bytes(const FineLevel& L, int wsize, bool trans_too) 
 // Planes per block for the solve-time kernels: long z-marches, but enough blocks to
 // fill the chip.
 int l0_choose_zb(int nsegx, int ny, int nz) {
-    const long tiles = (long)nsegx * ((ny + kBlockY - 1) / kBlockY);
+    const long tiles = (long)nsegx * ((ny + kMY - 1) / kMY);
     int zb = 32;
     while (zb > 2 && tiles * ((nz + zb - 1) / zb) < 8192) zb /= 2;
     return zb;
 }
 
 long l0_blocks(const FineLevel& L) {
-    const long gy = (L.ny + kBlockY - 1) / kBlockY;
+    const long gy = (L.ny + kMY - 1) / kMY;
     return (long)L.nsegx * gy * ((L.nz + L.zb - 1) / L.zb);
 }
 
@@ -95,63 +95,131 @@ __device__ inline void l0_tile(const L0View<T>& v, int* bx, int* by, int* bz) {
     *bz = (int)(t / v.gy);
 }
 
-// March over this block's tile.  For every unknown node, body(i, c, ax, x, y, z) is called
-// with its box index and coordinates, the input value c = X(i) and, when STENCIL, ax = (A X)_i (TR: A^T X)
-// of the scaled operator.  X(j) must be zero at nodes that are not unknowns.
-template <typename T, bool STENCIL, bool TR, class Load, class Body>
-__device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Body body) {
+// 64-bit value of lane k of a wavefront, as a wave-uniform (scalar) value.
+__device__ inline uint64_t lane_u64(uint64_t v, int k) {
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, k);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), k);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// March over this block's tile.  For every unknown node the march calls
+//   fv = fetch(i, x, y, z, irr, rk)            (issued one plane ahead)
+//   body(i, fv, c, ax, x, y, z, irr, rk)       (arithmetic and stores)
+// with the box index i, coordinates, irregular flag and table slot, the input value
+// c = X(i) and, when STENCIL, ax = (A X)_i (TR: A^T X) of the scaled operator.  X(j)
+// must be zero at nodes that are not unknowns, so a segment row without unknowns
+// contributes zeros without being read.  The segment words of planes z0-1 .. z1 are
+// fetched up front (one plane per lane) and broadcast per step.  The loads of plane z+1
+// are issued before the arithmetic of plane z (software pipelining), which doubles the
+// bytes each wavefront keeps in flight at little register cost.
+template <typename T, class FV>
+struct PlaneLoads {
+    uint64_t u;   // unknown bits of the segment row
+    bool irr;
+    int rk;
+    T nxt, ym, yp, edge;  // X at (x, y, z+1), (x, y-1, z), (x, y+1, z), lane-edge x-neighbour
+    FV fv;
+};
+
+template <typename T, bool STENCIL, bool TR, class Load, class Fetch, class Body>
+__device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch, Body body) {
+    // fp64 kernels carry twice the register payload per plane; they run unpipelined
+    constexpr bool kPipe = sizeof(T) == 4;
+    using FV = decltype(fetch(0L, 0, 0, 0, false, 0));
     int bx, by, bz;
     l0_tile(v, &bx, &by, &bz);
     const int lane = threadIdx.x;
     const int x = bx * kWave + lane;
-    const int y = __builtin_amdgcn_readfirstlane(by * kBlockY + (int)threadIdx.y);
+    const int y = __builtin_amdgcn_readfirstlane(by * kMY + (int)threadIdx.y);
     if (y < 1 || y > v.ny - 2) return;
     const bool inx = x < v.nx;
     const int z0 = max(bz * v.zb, 1), z1 = min(bz * v.zb + v.zb, v.nz - 1);
+    if (z0 >= z1) return;
     const long nx = v.nx, nxy = v.nxy;
     const T* const* tb = TR ? v.tabT : v.tab;
-    bool valid = false;
-    T zm = 0, c = 0;
-    for (int z = z0; z < z1; ++z) {
-        const long seg = ((long)z * v.ny + y) * v.nsegx + bx;
-        const uint64_t u = v.unk[seg];
-        if (u == 0) {
-            valid = false;
-            continue;
-        }
-        const long i = x + nx * y + nxy * z;
-        const bool unk = (u >> lane) & 1ull;
-        if (!STENCIL) {
-            if (unk) body(i, T(0), T(0), x, y, z);
-            continue;
-        }
-        if (!valid) {
-            c = inx ? X(i) : T(0);
-            zm = inx ? X(i - nxy) : T(0);
-            valid = true;
-        }
-        const T zp = inx ? X(i + nxy) : T(0);
-        T xm = __shfl_up(c, 1, kWave);
-        T xp = __shfl_down(c, 1, kWave);
-        if (lane == 0) xm = unk ? X(i - 1) : T(0);
-        if (lane == kWave - 1) xp = unk ? X(i + 1) : T(0);
-        if (unk) {
-            const uint64_t r = v.irr[seg];
-            const T ym = X(i - nx), yp = X(i + nx);
-            T ax;
-            if (!((r >> lane) & 1ull)) {
-                ax = c + v.c[0] * (xm + xp) + v.c[1] * (ym + yp) + v.c[2] * (zm + zp);
-            } else {
-                const int rk = v.base[seg] + __popcll(r & ((1ull << lane) - 1ull));
-                ax = c + tb[0][rk] * xm + tb[1][rk] * xp + tb[2][rk] * ym + tb[3][rk] * yp +
-                     tb[4][rk] * zm + tb[5][rk] * zp;
+    // words of planes q = z0-1+lane, lane < z1-z0+2 (at most zb+2 <= 34 planes)
+    uint64_t wu = 0, wr = 0;
+    int wb = 0;
+    if (lane < z1 - z0 + 2) {
+        const long sg = ((long)(z0 - 1 + lane) * v.ny + y) * v.nsegx + bx;
+        wu = v.unk[sg];
+        wr = v.irr[sg];
+        wb = v.base[sg];
+    }
+    const long ib = x + nx * y;  // box index of this lane at plane 0
+    auto load_plane = [&](int q) {
+        PlaneLoads<T, FV> P;
+        const int k = q - (z0 - 1);
+        P.u = lane_u64(wu, k);
+        const uint64_t r = lane_u64(wr, k);
+        P.irr = (r >> lane) & 1ull;
+        P.rk = P.irr ? __builtin_amdgcn_readlane(wb, k) + __popcll(r & ((1ull << lane) - 1ull)) : 0;
+        P.nxt = P.ym = P.yp = P.edge = T(0);
+        const long i = ib + nxy * q;
+        const bool unk = (P.u >> lane) & 1ull;
+        if (unk) P.fv = fetch(i, x, y, q, P.irr, P.rk);
+        if (STENCIL) {
+            if (inx && lane_u64(wu, k + 1) != 0) P.nxt = X(i + nxy);
+            if (unk) {
+                P.ym = X(i - nx);
+                P.yp = X(i + nx);
+                if (lane == 0) P.edge = X(i - 1);
+                if (lane == kWave - 1) P.edge = X(i + 1);
             }
-            body(i, c, ax, x, y, z);
         }
-        zm = c;
-        c = zp;
+        return P;
+    };
+    T zm = 0, c = 0;
+    if (STENCIL && inx) {
+        if (lane_u64(wu, 0) != 0) zm = X(ib + nxy * (z0 - 1));
+        if (lane_u64(wu, 1) != 0) c = X(ib + nxy * z0);
+    }
+    PlaneLoads<T, FV> cur = load_plane(z0);
+    for (int z = z0; z < z1; ++z) {
+        PlaneLoads<T, FV> nxtp;
+        if (kPipe && z + 1 < z1) nxtp = load_plane(z + 1);
+        if (cur.u != 0) {
+            T xm = T(0), xp = T(0);
+            if (STENCIL) {
+                xm = __shfl_up(c, 1, kWave);
+                xp = __shfl_down(c, 1, kWave);
+                if (lane == 0) xm = cur.edge;
+                if (lane == kWave - 1) xp = cur.edge;
+            }
+            if ((cur.u >> lane) & 1ull) {
+                const long i = ib + nxy * z;
+                const int r = cur.rk;
+                T ax = T(0);
+                if (STENCIL) {
+                    if (!cur.irr) {
+                        ax = c + v.c[0] * (xm + xp) + v.c[1] * (cur.ym + cur.yp) +
+                             v.c[2] * (zm + cur.nxt);
+                    } else {
+                        ax = c + tb[0][r] * xm + tb[1][r] * xp + tb[2][r] * cur.ym +
+                             tb[3][r] * cur.yp + tb[4][r] * zm + tb[5][r] * cur.nxt;
+                    }
+                }
+                body(i, cur.fv, c, ax, x, y, z, cur.irr, r);
+            }
+        }
+        if (STENCIL) {
+            zm = c;
+            c = cur.nxt;
+        }
+        if (kPipe)
+            cur = nxtp;
+        else if (z + 1 < z1)
+            cur = load_plane(z + 1);
     }
 }
+
+// Small fixed-size records for the fetch phase.
+template <typename A, int N>
+struct Vals {
+    A v[N];
+};
+struct NoVals {};
+#define NOFETCH [&](long, int, int, int, bool, int) { return NoVals{}; }
 
 // ================================================================ finalisation
 
@@ -451,10 +519,10 @@ void l0_unknown_list(const FineLevel& L, long* out, hipStream_t s) {
 
 // y = A x (or A^T x) on every box node (zero where not an unknown).
 template <typename T, bool TR>
-__global__ void __launch_bounds__(kThreads) k_l0_apply(L0View<T> v, const T* __restrict__ xv,
+__global__ void __launch_bounds__(kMThreads) k_l0_apply(L0View<T> v, const T* __restrict__ xv,
                                                        T* __restrict__ yv) {
-    l0_march<T, true, TR>(v, [&](long j) { return xv[j]; },
-                          [&](long i, T c, T ax, int, int, int) { yv[i] = ax; });
+    l0_march<T, true, TR>(v, [&](long j) { return xv[j]; }, NOFETCH,
+                          [&](long i, NoVals, T, T ax, int, int, int, bool, int) { yv[i] = ax; });
 }
 
 template <typename T>
@@ -462,35 +530,37 @@ void l0_apply(const FineLevel& L, bool trans, const T* x, T* y, hipStream_t s) {
     L0View<T> v = L.view<T>();
     HIPCHECK(hipMemsetAsync(y, 0, sizeof(T) * L.nbox, s));
     if (trans)
-        hipLaunchKernelGGL((k_l0_apply<T, true>), l0_mgrid(L), dim3(kWave, kBlockY), 0, s, v, x, y);
+        hipLaunchKernelGGL((k_l0_apply<T, true>), l0_mgrid(L), dim3(kWave, kMY), 0, s, v, x, y);
     else
-        hipLaunchKernelGGL((k_l0_apply<T, false>), l0_mgrid(L), dim3(kWave, kBlockY), 0, s, v, x, y);
+        hipLaunchKernelGGL((k_l0_apply<T, false>), l0_mgrid(L), dim3(kWave, kMY), 0, s, v, x, y);
     HIPCHECK(hipGetLastError());
 }
 template void l0_apply<double>(const FineLevel&, bool, const double*, double*, hipStream_t);
 template void l0_apply<float>(const FineLevel&, bool, const float*, float*, hipStream_t);
 
-__global__ void __launch_bounds__(kThreads) k_l0_power_start(L0View<double> v, double* w) {
-    l0_march<double, false, false>(v, [&](long) { return 0.0; },
-                                   [&](long i, double, double, int, int, int) { w[i] = start_value(i); });
+__global__ void __launch_bounds__(kMThreads) k_l0_power_start(L0View<double> v, double* w) {
+    l0_march<double, false, false>(v, [&](long) { return 0.0; }, NOFETCH,
+                                   [&](long i, NoVals, double, double, int, int, int, bool, int) {
+                                       w[i] = start_value(i);
+                                   });
 }
 
 void l0_power_start(const FineLevel& L, double* v, hipStream_t s) {
-    hipLaunchKernelGGL(k_l0_power_start, l0_mgrid(L), dim3(kWave, kBlockY), 0, s,
+    hipLaunchKernelGGL(k_l0_power_start, l0_mgrid(L), dim3(kWave, kMY), 0, s,
                        L.view<double>(), v);
     HIPCHECK(hipGetLastError());
 }
 
 // w = A u with u = v * scal[S_INVN] (D = I at level 0); partials of w.w, u.Au, u.u.
-__global__ void __launch_bounds__(kThreads) k_l0_power_step(L0View<double> v,
+__global__ void __launch_bounds__(kMThreads) k_l0_power_step(L0View<double> v,
                                                             const double* __restrict__ vin,
                                                             const double* __restrict__ scal,
                                                             double* __restrict__ w, double* part) {
-    __shared__ double lds[kThreads / kWave];
+    __shared__ double lds[kMThreads / kWave];
     const double sc = scal[S_INVN];
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    l0_march<double, true, false>(v, [&](long j) { return vin[j] * sc; },
-                                  [&](long i, double u, double au, int, int, int) {
+    l0_march<double, true, false>(v, [&](long j) { return vin[j] * sc; }, NOFETCH,
+                                  [&](long i, NoVals, double u, double au, int, int, int, bool, int) {
                                       w[i] = au;
                                       a0 += au * au;
                                       a1 += u * au;
@@ -507,7 +577,7 @@ __global__ void __launch_bounds__(kThreads) k_l0_power_step(L0View<double> v,
 
 void l0_power_step(const FineLevel& L, const double* v, const double* scal, double* w,
                    double* partials, hipStream_t s) {
-    hipLaunchKernelGGL(k_l0_power_step, l0_mgrid(L), dim3(kWave, kBlockY), 0, s,
+    hipLaunchKernelGGL(k_l0_power_step, l0_mgrid(L), dim3(kWave, kMY), 0, s,
                        L.view<double>(), v, scal, w, partials);
     HIPCHECK(hipGetLastError());
 }
@@ -517,37 +587,51 @@ void l0_power_step(const FineLevel& L, const double* v, const double* scal, doub
 //   ZERO2: x1 = c2_0 f on the fly; r1 = f - A x1; d1 = c1 x1 + c2 r1; x2 = x1 + d1
 //   FIRST: r = f - A xin; d = c2_0 r; xout = xin + d
 //   NEXT : r = f - A xin; d = c1 din + c2 r; xout = xin + d
-// Optional partial sums of f . xout (the PCG's r . z when this is the last step).
+// Optional partial sums of fdot . xout (the PCG's r . z when this is the last step).
 template <typename TF, typename T, int MODE, bool DOT>
-__global__ void __launch_bounds__(kThreads) k_l0_cheb(L0View<T> v, const TF* __restrict__ f,
+__global__ void __launch_bounds__(kMThreads) k_l0_cheb(L0View<T> v, const TF* __restrict__ f,
                                                       const T* __restrict__ xin,
                                                       const T* __restrict__ din, T* __restrict__ xout,
                                                       T* __restrict__ dout, T c1, T c2, T c20,
-                                                      double* part) {
-    __shared__ double lds[kThreads / kWave];
+                                                      const double* __restrict__ fdot, double* part) {
+    __shared__ double lds[kMThreads / kWave];
     double acc = 0.0;
-    auto emit = [&](long i, T xo, T dn) {
+    auto fetch = [&](long i, int, int, int, bool, int) {
+        Vals<T, 2> a;
+        a.v[0] = (T)f[i];
+        a.v[1] = (MODE == CHEB_NEXT) ? din[i] : T(0);
+        Vals<double, 1> b;
+        b.v[0] = DOT ? fdot[i] : 0.0;
+        struct R {
+            Vals<T, 2> a;
+            Vals<double, 1> b;
+        };
+        return R{a, b};
+    };
+    auto body = [&](long i, auto fv, T cv, T ax, int, int, int, bool, int) {
+        const T fi = fv.a.v[0];
+        T xo, dn;
+        if (MODE == CHEB_ZERO1) {
+            xo = c20 * fi;
+            dn = xo;
+        } else if (MODE == CHEB_ZERO2) {
+            dn = c1 * cv + c2 * (fi - ax);
+            xo = cv + dn;
+        } else {
+            const T r = fi - ax;
+            dn = (MODE == CHEB_FIRST) ? c20 * r : c1 * fv.a.v[1] + c2 * r;
+            xo = cv + dn;
+        }
         xout[i] = xo;
         if (dout) dout[i] = dn;
-        if (DOT) acc += (double)f[i] * (double)xo;
+        if (DOT) acc += fv.b.v[0] * (double)xo;
     };
-    if (MODE == CHEB_ZERO1) {
-        l0_march<T, false, false>(v, [&](long) { return T(0); }, [&](long i, T, T, int, int, int) {
-            const T xo = c20 * (T)f[i];
-            emit(i, xo, xo);
-        });
-    } else if (MODE == CHEB_ZERO2) {
-        l0_march<T, true, false>(v, [&](long j) { return c20 * (T)f[j]; }, [&](long i, T x1, T ax, int, int, int) {
-            const T dn = c1 * x1 + c2 * ((T)f[i] - ax);
-            emit(i, x1 + dn, dn);
-        });
-    } else {
-        l0_march<T, true, false>(v, [&](long j) { return xin[j]; }, [&](long i, T xi, T ax, int, int, int) {
-            const T r = (T)f[i] - ax;
-            const T dn = (MODE == CHEB_FIRST) ? c20 * r : c1 * din[i] + c2 * r;
-            emit(i, xi + dn, dn);
-        });
-    }
+    if (MODE == CHEB_ZERO1)
+        l0_march<T, false, false>(v, [&](long) { return T(0); }, fetch, body);
+    else if (MODE == CHEB_ZERO2)
+        l0_march<T, true, false>(v, [&](long j) { return c20 * (T)f[j]; }, fetch, body);
+    else
+        l0_march<T, true, false>(v, [&](long j) { return xin[j]; }, fetch, body);
     if (DOT) {
         double sb = block_sum(acc, lds);
         if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
@@ -556,20 +640,21 @@ __global__ void __launch_bounds__(kThreads) k_l0_cheb(L0View<T> v, const TF* __r
 
 template <typename TF, typename T>
 void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* din, T* xout,
-             T* dout, double c1, double c2, double c2_0, double* dot, hipStream_t s) {
+             T* dout, double c1, double c2, double c2_0, const double* fdot, double* dot,
+             hipStream_t s) {
     const long wf = sizeof(TF), w = sizeof(T), n = L.n_unknowns;
     const long vec = (mode == CHEB_ZERO1 || mode == CHEB_ZERO2) ? wf + w
                      : (mode == CHEB_FIRST) ? wf + 2 * w : wf + 3 * w;
-    KTimer kt_(T_L0_CHEB, s, n * (vec + (dout ? w : 0)) + l0_meta_bytes(L, w, false));
+    KTimer kt_(T_L0_CHEB, s, n * (vec + (dout ? w : 0) + (dot ? 8 : 0)) + l0_meta_bytes(L, w, false));
     L0View<T> v = L.view<T>();
-    dim3 g = l0_mgrid(L), b(kWave, kBlockY);
+    dim3 g = l0_mgrid(L), b(kWave, kMY);
 #define CHEB_LAUNCH(M)                                                                         \
     if (dot)                                                                                   \
         hipLaunchKernelGGL((k_l0_cheb<TF, T, M, true>), g, b, 0, s, v, f, xin, din, xout, dout, \
-                           (T)c1, (T)c2, (T)c2_0, dot);                                        \
+                           (T)c1, (T)c2, (T)c2_0, fdot, dot);                                  \
     else                                                                                       \
         hipLaunchKernelGGL((k_l0_cheb<TF, T, M, false>), g, b, 0, s, v, f, xin, din, xout,      \
-                           dout, (T)c1, (T)c2, (T)c2_0, dot);
+                           dout, (T)c1, (T)c2, (T)c2_0, fdot, dot);
     switch (mode) {
         case CHEB_ZERO1: CHEB_LAUNCH(CHEB_ZERO1) break;
         case CHEB_ZERO2: CHEB_LAUNCH(CHEB_ZERO2) break;
@@ -581,44 +666,43 @@ void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* d
 }
 template void l0_cheb<double, double>(const FineLevel&, int, const double*, const double*,
                                       const double*, double*, double*, double, double, double,
-                                      double*, hipStream_t);
-template void l0_cheb<double, float>(const FineLevel&, int, const double*, const float*,
-                                     const float*, float*, float*, double, double, double,
-                                     double*, hipStream_t);
+                                      const double*, double*, hipStream_t);
 template void l0_cheb<float, float>(const FineLevel&, int, const float*, const float*,
                                     const float*, float*, float*, double, double, double,
-                                    double*, hipStream_t);
+                                    const double*, double*, hipStream_t);
 
 template <typename TF, typename T>
-__global__ void __launch_bounds__(kThreads) k_l0_residual(L0View<T> v, const TF* __restrict__ f,
+__global__ void __launch_bounds__(kMThreads) k_l0_residual(L0View<T> v, const TF* __restrict__ f,
                                                           const T* __restrict__ xv,
                                                           T* __restrict__ r) {
-    l0_march<T, true, false>(v, [&](long j) { return xv[j]; },
-                             [&](long i, T, T ax, int, int, int) { r[i] = (T)f[i] - ax; });
+    l0_march<T, true, false>(
+        v, [&](long j) { return xv[j]; },
+        [&](long i, int, int, int, bool, int) { return Vals<T, 1>{{(T)f[i]}}; },
+        [&](long i, Vals<T, 1> fv, T, T ax, int, int, int, bool, int) { r[i] = fv.v[0] - ax; });
 }
 
 template <typename TF, typename T>
 void l0_residual(const FineLevel& L, const TF* f, const T* x, T* r, hipStream_t s) {
     KTimer kt_(T_L0_RESID, s, L.n_unknowns * (long)(sizeof(TF) + 2 * sizeof(T)) +
                                  l0_meta_bytes(L, sizeof(T), false));
-    hipLaunchKernelGGL((k_l0_residual<TF, T>), l0_mgrid(L), dim3(kWave, kBlockY), 0, s,
+    hipLaunchKernelGGL((k_l0_residual<TF, T>), l0_mgrid(L), dim3(kWave, kMY), 0, s,
                        L.view<T>(), f, x, r);
     HIPCHECK(hipGetLastError());
 }
 template void l0_residual<double, double>(const FineLevel&, const double*, const double*,
                                           double*, hipStream_t);
-template void l0_residual<double, float>(const FineLevel&, const double*, const float*, float*,
-                                         hipStream_t);
 template void l0_residual<float, float>(const FineLevel&, const float*, const float*, float*,
                                         hipStream_t);
 
 // Restriction to level 1, P^T r with P = (I - w A) P_tent (D = I at level 0), in two
 // passes: y = r - w A^T r on every fine unknown, then the sum of y over each aggregate.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_l0_restrict_y(L0View<T> v, const T* __restrict__ r,
+__global__ void __launch_bounds__(kMThreads) k_l0_restrict_y(L0View<T> v, const T* __restrict__ r,
                                                             T* __restrict__ yv, T omega) {
-    l0_march<T, true, true>(v, [&](long j) { return r[j]; },
-                            [&](long i, T ri, T atr, int, int, int) { yv[i] = ri - omega * atr; });
+    l0_march<T, true, true>(v, [&](long j) { return r[j]; }, NOFETCH,
+                            [&](long i, NoVals, T ri, T atr, int, int, int, bool, int) {
+                                yv[i] = ri - omega * atr;
+                            });
 }
 
 template <typename T>
@@ -651,7 +735,7 @@ void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* 
                  hipStream_t s) {
     KTimer kt_(T_L0_RESTRICT, s, (L.n_unknowns * 3 + C.n_unknowns) * (long)sizeof(T) +
                                     l0_meta_bytes(L, sizeof(T), true));
-    hipLaunchKernelGGL((k_l0_restrict_y<T>), l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<T>(),
+    hipLaunchKernelGGL((k_l0_restrict_y<T>), l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<T>(),
                        r, y, (T)omega);
     dim3 g((unsigned)(((long)C.mx * C.my + 255) / 256), C.mz);
     hipLaunchKernelGGL((k_l0_restrict_sum<T>), g, dim3(256), 0, s, L.nx, L.ny, L.nz, C.view<T>(),
@@ -663,32 +747,38 @@ template void l0_restrict<double>(const FineLevel&, const CoarseLevel&, const do
 template void l0_restrict<float>(const FineLevel&, const CoarseLevel&, const float*, float*, float*,
                                  double, hipStream_t);
 
-// Prolongation from level 1: x += P v = P_tent v - w A (P_tent v).
+// Prolongation from level 1: x += P v = P_tent v - w A (P_tent v).  A node's aggregate
+// is (x/3, y/3, z/3); a neighbour's differs by one coarse step exactly when the node sits
+// on the corresponding face of its 3^3 block.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_l0_prolong(L0View<T> v, LCView<T> c,
+__global__ void __launch_bounds__(kMThreads) k_l0_prolong(L0View<T> v, LCView<T> c,
                                                          const T* __restrict__ vc,
                                                          T* __restrict__ xv, T omega) {
-    l0_march<T, false, false>(v, [&](long) { return T(0); }, [&](long i, T, T, int x, int y, int z) {
-        // coarse storage index of the aggregate holding box node (xj, yj, zj)
-        auto agg = [&](int xj, int yj, int zj) -> long {
-            return (xj / 3 + 1) + (long)c.sx * (yj / 3 + 1) + c.sxy * (zj / 3 + 1);
-        };
-        const int sx = x & 63;
-        const long seg = ((long)z * v.ny + y) * v.nsegx + (x >> 6);
-        const uint64_t r = v.irr[seg];
-        const T pv = vc[agg(x, y, z)];
+    auto fetch = [&](long i, int x, int y, int z, bool, int) {
+        const int qx = x / 3, qy = y / 3, qz = z / 3;
+        const long a = (qx + 1) + (long)c.sx * (qy + 1) + c.sxy * (qz + 1);
+        Vals<T, 8> f;
+        f.v[0] = vc[a];
+        f.v[1] = vc[a - (x - 3 * qx == 0)];
+        f.v[2] = vc[a + (x - 3 * qx == 2)];
+        f.v[3] = vc[a - (y - 3 * qy == 0 ? c.sx : 0)];
+        f.v[4] = vc[a + (y - 3 * qy == 2 ? c.sx : 0)];
+        f.v[5] = vc[a - (z - 3 * qz == 0 ? c.sxy : 0)];
+        f.v[6] = vc[a + (z - 3 * qz == 2 ? c.sxy : 0)];
+        f.v[7] = xv[i];
+        return f;
+    };
+    l0_march<T, false, false>(v, [&](long) { return T(0); }, fetch,
+                              [&](long i, Vals<T, 8> f, T, T, int, int, int, bool irrow, int rk) {
         T apv;
-        if (!((r >> sx) & 1ull)) {
-            apv = pv + v.c[0] * (vc[agg(x - 1, y, z)] + vc[agg(x + 1, y, z)]) +
-                  v.c[1] * (vc[agg(x, y - 1, z)] + vc[agg(x, y + 1, z)]) +
-                  v.c[2] * (vc[agg(x, y, z - 1)] + vc[agg(x, y, z + 1)]);
+        if (!irrow) {
+            apv = f.v[0] + v.c[0] * (f.v[1] + f.v[2]) + v.c[1] * (f.v[3] + f.v[4]) +
+                  v.c[2] * (f.v[5] + f.v[6]);
         } else {
-            const int rk = v.base[seg] + __popcll(r & ((1ull << sx) - 1ull));
-            apv = pv + v.tab[0][rk] * vc[agg(x - 1, y, z)] + v.tab[1][rk] * vc[agg(x + 1, y, z)] +
-                  v.tab[2][rk] * vc[agg(x, y - 1, z)] + v.tab[3][rk] * vc[agg(x, y + 1, z)] +
-                  v.tab[4][rk] * vc[agg(x, y, z - 1)] + v.tab[5][rk] * vc[agg(x, y, z + 1)];
+            apv = f.v[0] + v.tab[0][rk] * f.v[1] + v.tab[1][rk] * f.v[2] + v.tab[2][rk] * f.v[3] +
+                  v.tab[3][rk] * f.v[4] + v.tab[4][rk] * f.v[5] + v.tab[5][rk] * f.v[6];
         }
-        xv[i] += pv - omega * apv;
+        xv[i] = f.v[7] + (f.v[0] - omega * apv);
     });
 }
 
@@ -697,7 +787,7 @@ void l0_prolong(const FineLevel& L, const CoarseLevel& C, const T* vc, T* x, dou
                 hipStream_t s) {
     KTimer kt_(T_L0_PROLONG, s, (2 * L.n_unknowns + C.n_unknowns) * (long)sizeof(T) +
                                    l0_meta_bytes(L, sizeof(T), false));
-    hipLaunchKernelGGL((k_l0_prolong<T>), l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<T>(),
+    hipLaunchKernelGGL((k_l0_prolong<T>), l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<T>(),
                        C.view<T>(), vc, x, (T)omega);
     HIPCHECK(hipGetLastError());
 }
@@ -708,37 +798,46 @@ template void l0_prolong<float>(const FineLevel&, const CoarseLevel&, const floa
 
 // ================================================================ CG (fp64)
 
-__global__ void __launch_bounds__(kThreads) k_cg_init(L0View<double> v, const double* __restrict__ sigma,
+__global__ void __launch_bounds__(kMThreads) k_cg_init(L0View<double> v, const double* __restrict__ sigma,
                                                       const double* __restrict__ b,
                                                       const double* __restrict__ x0,
                                                       double* __restrict__ bs, double* __restrict__ xv) {
-    l0_march<double, false, false>(v, [&](long) { return 0.0; }, [&](long i, double, double, int, int, int) {
-        const double sg = sigma[i];
-        bs[i] = sg * b[i];
-        xv[i] = x0 ? x0[i] / sg : 0.0;
-    });
+    l0_march<double, false, false>(
+        v, [&](long) { return 0.0; },
+        [&](long i, int, int, int, bool, int) {
+            return Vals<double, 3>{{sigma[i], b[i], x0 ? x0[i] : 0.0}};
+        },
+        [&](long i, Vals<double, 3> f, double, double, int, int, int, bool, int) {
+            bs[i] = f.v[0] * f.v[1];
+            xv[i] = x0 ? f.v[2] / f.v[0] : 0.0;
+        });
 }
 
 void cg_init(const FineLevel& L, const double* b, const double* x0, double* bs, double* x,
              hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_init, l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(),
+    hipLaunchKernelGGL(k_cg_init, l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(),
                        L.sigma, b, x0, bs, x);
     HIPCHECK(hipGetLastError());
 }
 
 // r = bs - A x; partials of r.r and bs.bs.
-__global__ void __launch_bounds__(kThreads) k_cg_resid(L0View<double> v, const double* __restrict__ bs,
+__global__ void __launch_bounds__(kMThreads) k_cg_resid(L0View<double> v, const double* __restrict__ bs,
                                                        const double* __restrict__ xv,
-                                                       double* __restrict__ r, double* part) {
-    __shared__ double lds[kThreads / kWave];
+                                                       double* __restrict__ r, double* part,
+                                                       float* __restrict__ r32) {
+    __shared__ double lds[kMThreads / kWave];
     double a0 = 0.0, a1 = 0.0;
-    l0_march<double, true, false>(v, [&](long j) { return xv[j]; }, [&](long i, double, double ax, int, int, int) {
-        const double bi = bs[i];
-        const double o = bi - ax;
-        r[i] = o;
-        a0 += o * o;
-        a1 += bi * bi;
-    });
+    l0_march<double, true, false>(
+        v, [&](long j) { return xv[j]; },
+        [&](long i, int, int, int, bool, int) { return Vals<double, 1>{{bs[i]}}; },
+        [&](long i, Vals<double, 1> f, double, double ax, int, int, int, bool, int) {
+            const double bi = f.v[0];
+            const double o = bi - ax;
+            r[i] = o;
+            if (r32) r32[i] = (float)o;
+            a0 += o * o;
+            a1 += bi * bi;
+        });
     const long bid = blockIdx.x, nb = gridDim.x;
     double s0 = block_sum(a0, lds), s1 = block_sum(a1, lds);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
@@ -748,74 +847,83 @@ __global__ void __launch_bounds__(kThreads) k_cg_resid(L0View<double> v, const d
 }
 
 void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
-              hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_resid, l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), bs,
-                       x, r, partials);
+              float* r32, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_resid, l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), bs,
+                       x, r, partials, r32);
     HIPCHECK(hipGetLastError());
 }
 
-// p_new = z + beta p_old; q = A p_new; partials of p_new . q.
+// Direction update with the product by A carried along:  p <- z + beta p and
+// q <- A z + beta q, which equals A p_new because q held A p_old.  The stencil runs on z
+// (fp32 in mixed precision), the sums in fp64; partials of p . q.
 template <typename TZ>
-__global__ void __launch_bounds__(kThreads) k_cg_pq(L0View<double> v, const TZ* __restrict__ zv,
-                                                    const double* __restrict__ pold,
-                                                    double* __restrict__ pnew,
-                                                    double* __restrict__ q,
+__global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ* __restrict__ zv,
+                                                    double* __restrict__ p, double* __restrict__ q,
                                                     const double* __restrict__ scal, double* part) {
-    __shared__ double lds[kThreads / kWave];
+    __shared__ double lds[kMThreads / kWave];
     const double beta = scal[S_BETA];
     double acc = 0.0;
-    l0_march<double, true, false>(v, [&](long j) { return (double)zv[j] + beta * pold[j]; },
-                                  [&](long i, double pi, double qi, int, int, int) {
-                                      pnew[i] = pi;
-                                      q[i] = qi;
-                                      acc += pi * qi;
-                                  });
+    l0_march<double, true, false>(
+        v, [&](long j) { return (double)zv[j]; },
+        [&](long i, int, int, int, bool, int) { return Vals<double, 2>{{p[i], q[i]}}; },
+        [&](long i, Vals<double, 2> f, double zi, double az, int, int, int, bool, int) {
+            const double pi = zi + beta * f.v[0];
+            const double qi = az + beta * f.v[1];
+            p[i] = pi;
+            q[i] = qi;
+            acc += pi * qi;
+        });
     double sb = block_sum(acc, lds);
     if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
 template <typename TZ>
-void cg_pq(const FineLevel& L, const TZ* z, const double* pold, double* pnew, double* q,
-           const double* scal, double* partials, hipStream_t s) {
-    KTimer kt_(T_CG_PQ, s, L.n_unknowns * (long)(sizeof(TZ) + 24) + l0_meta_bytes(L, 8, false));
-    hipLaunchKernelGGL((k_cg_pq<TZ>), l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), z,
-                       pold, pnew, q, scal, partials);
+void cg_pq(const FineLevel& L, const TZ* z, double* p, double* q, const double* scal,
+           double* partials, hipStream_t s) {
+    KTimer kt_(T_CG_PQ, s, L.n_unknowns * (long)(sizeof(TZ) + 32) + l0_meta_bytes(L, 8, false));
+    hipLaunchKernelGGL((k_cg_pq<TZ>), l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), z,
+                       p, q, scal, partials);
     HIPCHECK(hipGetLastError());
 }
-template void cg_pq<double>(const FineLevel&, const double*, const double*, double*, double*,
-                            const double*, double*, hipStream_t);
-template void cg_pq<float>(const FineLevel&, const float*, const double*, double*, double*,
-                           const double*, double*, hipStream_t);
+template void cg_pq<double>(const FineLevel&, const double*, double*, double*, const double*,
+                            double*, hipStream_t);
+template void cg_pq<float>(const FineLevel&, const float*, double*, double*, const double*,
+                           double*, hipStream_t);
 
 // x += alpha p; r -= alpha q; partials of r.r.  Skipped (x, r untouched) when the step
 // broke down: p.q <= 0, r.z <= 0 or a non-finite alpha.
-__global__ void __launch_bounds__(kThreads) k_cg_xr(L0View<double> v, double* __restrict__ xv,
+__global__ void __launch_bounds__(kMThreads) k_cg_xr(L0View<double> v, double* __restrict__ xv,
                                                     const double* __restrict__ p,
                                                     double* __restrict__ r,
                                                     const double* __restrict__ q,
-                                                    const double* __restrict__ scal, double* part) {
-    __shared__ double lds[kThreads / kWave];
+                                                    const double* __restrict__ scal, double* part,
+                                                    float* __restrict__ r32) {
+    __shared__ double lds[kMThreads / kWave];
     const double alpha = scal[S_ALPHA];
     const bool ok = scal[S_PQ] > 0.0 && scal[S_RHO] > 0.0 && isfinite(alpha);
     double acc = 0.0;
-    l0_march<double, false, false>(v, [&](long) { return 0.0; }, [&](long i, double, double, int, int, int) {
-        double ri = r[i];
-        if (ok) {
-            xv[i] += alpha * p[i];
-            ri -= alpha * q[i];
-            r[i] = ri;
-        }
-        acc += ri * ri;
-    });
+    l0_march<double, false, false>(
+        v, [&](long) { return 0.0; },
+        [&](long i, int, int, int, bool, int) { return Vals<double, 4>{{xv[i], p[i], r[i], q[i]}}; },
+        [&](long i, Vals<double, 4> f, double, double, int, int, int, bool, int) {
+            double ri = f.v[2];
+            if (ok) {
+                xv[i] = f.v[0] + alpha * f.v[1];
+                ri -= alpha * f.v[3];
+                r[i] = ri;
+                if (r32) r32[i] = (float)ri;
+            }
+            acc += ri * ri;
+        });
     double sb = block_sum(acc, lds);
     if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
 void cg_xr(const FineLevel& L, double* x, const double* p, double* r, const double* q,
-           const double* scal, double* partials, hipStream_t s) {
-    KTimer kt_(T_CG_XR, s, L.n_unknowns * 48L);
-    hipLaunchKernelGGL(k_cg_xr, l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), x, p, r,
-                       q, scal, partials);
+           const double* scal, double* partials, float* r32, hipStream_t s) {
+    KTimer kt_(T_CG_XR, s, L.n_unknowns * (48L + (r32 ? 4 : 0)));
+    hipLaunchKernelGGL(k_cg_xr, l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), x, p, r,
+                       q, scal, partials, r32);
     HIPCHECK(hipGetLastError());
 }
 
@@ -834,33 +942,41 @@ void cg_unscale(const FineLevel& L, const double* x, double* out, hipStream_t s)
     HIPCHECK(hipGetLastError());
 }
 
-__global__ void __launch_bounds__(kThreads) k_mask_copy(L0View<double> v, const double* __restrict__ a,
-                                                        double* __restrict__ b) {
-    l0_march<double, false, false>(v, [&](long) { return 0.0; },
-                                   [&](long i, double, double, int, int, int) { b[i] = a[i]; });
+__global__ void __launch_bounds__(kMThreads) k_mask_copy(L0View<double> v, const double* __restrict__ a,
+                                                        double* __restrict__ b, float* __restrict__ b32) {
+    l0_march<double, false, false>(
+        v, [&](long) { return 0.0; },
+        [&](long i, int, int, int, bool, int) { return Vals<double, 1>{{a[i]}}; },
+        [&](long i, Vals<double, 1> f, double, double, int, int, int, bool, int) {
+            b[i] = f.v[0];
+            if (b32) b32[i] = (float)f.v[0];
+        });
 }
 
-void cg_mask_copy(const FineLevel& L, const double* in, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_mask_copy, l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), in,
-                       out);
+void cg_mask_copy(const FineLevel& L, const double* in, double* out, float* out32, hipStream_t s) {
+    hipLaunchKernelGGL(k_mask_copy, l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), in,
+                       out, out32);
     HIPCHECK(hipGetLastError());
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_l0_dot(L0View<double> v, const double* __restrict__ a,
+__global__ void __launch_bounds__(kMThreads) k_l0_dot(L0View<double> v, const double* __restrict__ a,
                                                      const T* __restrict__ b, double* part) {
-    __shared__ double lds[kThreads / kWave];
+    __shared__ double lds[kMThreads / kWave];
     double acc = 0.0;
-    l0_march<double, false, false>(v, [&](long) { return 0.0; }, [&](long i, double, double, int, int, int) {
-        acc += a[i] * (double)b[i];
-    });
+    l0_march<double, false, false>(
+        v, [&](long) { return 0.0; },
+        [&](long i, int, int, int, bool, int) { return Vals<double, 2>{{a[i], (double)b[i]}}; },
+        [&](long, Vals<double, 2> f, double, double, int, int, int, bool, int) {
+            acc += f.v[0] * f.v[1];
+        });
     double sb = block_sum(acc, lds);
     if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
 template <typename T>
 void l0_dot(const FineLevel& L, const double* a, const T* b, double* partials, hipStream_t s) {
-    hipLaunchKernelGGL((k_l0_dot<T>), l0_mgrid(L), dim3(kWave, kBlockY), 0, s, L.view<double>(), a,
+    hipLaunchKernelGGL((k_l0_dot<T>), l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), a,
                        b, partials);
     HIPCHECK(hipGetLastError());
 }

@@ -38,9 +38,11 @@ void l0_apply(const FineLevel& L, bool trans, const T* x, T* y, hipStream_t s);
 void l0_power_start(const FineLevel& L, double* v, hipStream_t s);
 void l0_power_step(const FineLevel& L, const double* v, const double* scal, double* w,
                    double* partials, hipStream_t s);
+// fdot: fp64 operand of the fused dot (partials of fdot . xout), used when dot is set
 template <typename TF, typename T>
 void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* din, T* xout,
-             T* dout, double c1, double c2, double c2_0, double* dot_partials, hipStream_t s);
+             T* dout, double c1, double c2, double c2_0, const double* fdot, double* dot_partials,
+             hipStream_t s);
 template <typename TF, typename T>
 void l0_residual(const FineLevel& L, const TF* f, const T* x, T* r, hipStream_t s);
 // fc = P^T r in two passes; y is a level-0 scratch vector (zero off the unknowns)
@@ -54,16 +56,17 @@ void l0_prolong(const FineLevel& L, const CoarseLevel& C, const T* v, T* x, doub
 // ---- level 0: CG (fp64)
 void cg_init(const FineLevel& L, const double* b, const double* x0, double* bs, double* x,
              hipStream_t s);
+// r32 (nullable): fp32 copy of the residual for the fp32 V-cycle
 void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
-              hipStream_t s);
+              float* r32, hipStream_t s);
 template <typename TZ>
-void cg_pq(const FineLevel& L, const TZ* z, const double* pold, double* pnew, double* q,
-           const double* scal, double* partials, hipStream_t s);
+void cg_pq(const FineLevel& L, const TZ* z, double* p, double* q, const double* scal,
+           double* partials, hipStream_t s);
 void cg_xr(const FineLevel& L, double* x, const double* p, double* r, const double* q,
-           const double* scal, double* partials, hipStream_t s);
+           const double* scal, double* partials, float* r32, hipStream_t s);
 void cg_unscale(const FineLevel& L, const double* x, double* out, hipStream_t s);
 // out = in on the unknowns (out untouched elsewhere)
-void cg_mask_copy(const FineLevel& L, const double* in, double* out, hipStream_t s);
+void cg_mask_copy(const FineLevel& L, const double* in, double* out, float* out32, hipStream_t s);
 // partial sums of a . b over level-0 unknowns (one per block of l0_blocks)
 template <typename T>
 void l0_dot(const FineLevel& L, const double* a, const T* b, double* partials, hipStream_t s);

@@ -100,27 +100,28 @@ struct VBuf {
 };
 
 template <typename T>
-static void chebstep(const saamg_hierarchy* H, int l, int mode, const double* f0, const T* fl,
+static void chebstep(const saamg_hierarchy* H, int l, int mode, const T* f0, const T* fl,
                      const T* xin, const T* din, T* xout, T* dout, double c1, double c2, double c20,
-                     double* dot, hipStream_t s) {
+                     const double* fdot, double* dot, hipStream_t s) {
     if (l == 0)
-        l0_cheb<double, T>(H->l0, mode, f0, xin, din, xout, dout, c1, c2, c20, dot, s);
+        l0_cheb<T, T>(H->l0, mode, f0, xin, din, xout, dout, c1, c2, c20, fdot, dot, s);
     else
         lc_cheb<T>(H->lc[l - 1], mode, fl, xin, din, xout, dout, c1, c2, c20, s);
 }
 
 // Algorithm 1 on level l with a zero initial guess; returns the buffer holding x_l.  On
-// level 0 the right-hand side is the fp64 PCG residual f0 and the result goes to `out`,
-// with partial sums of f0 . out in `dot` (nullable).
+// level 0 the right-hand side is the PCG residual f0 in the working precision and the
+// result goes to `out`, with partial sums of fdot . out in `dot` (nullable; fdot is the
+// fp64 residual).
 template <typename T>
-static T* vcycle(const saamg_hierarchy* H, VBuf<T>& B, int l, const double* f0, T* out,
-                 double* dot, hipStream_t s) {
+static T* vcycle(const saamg_hierarchy* H, VBuf<T>& B, int l, const T* f0, T* out,
+                 const double* fdot, double* dot, hipStream_t s) {
     const bool fine = (l == 0);
     if (l == H->n_levels - 1) {
         T* x = fine ? out : B.xa[l];
         if (fine) {
-            coarse_solve<double, T>(H->Ainv, H->cidx, H->nL, f0, x, s);
-            if (dot) l0_dot<T>(H->l0, f0, x, dot, s);
+            coarse_solve<T, T>(H->Ainv, H->cidx, H->nL, f0, x, s);
+            if (dot) l0_dot<T>(H->l0, fdot, x, dot, s);
         } else {
             coarse_solve<T, T>(H->Ainv, H->cidx, H->nL, B.f[l], x, s);
         }
@@ -135,25 +136,25 @@ static T* vcycle(const saamg_hierarchy* H, VBuf<T>& B, int l, const double* f0, 
     // pre-smoothing from a zero guess
     if (c.degree == 1) {
         chebstep<T>(H, l, CHEB_ZERO1, f0, fl, nullptr, nullptr, x, nullptr, 0, 0, c.c2[0],
-                    nullptr, s);
+                    nullptr, nullptr, s);
     } else {
         chebstep<T>(H, l, CHEB_ZERO2, f0, fl, nullptr, nullptr, x, c.degree > 2 ? d : nullptr,
-                    c.c1[1], c.c2[1], c.c2[0], nullptr, s);
+                    c.c1[1], c.c2[1], c.c2[0], nullptr, nullptr, s);
         for (int k = 2; k < c.degree; ++k) {
             chebstep<T>(H, l, CHEB_NEXT, f0, fl, x, d, other, d, c.c1[k], c.c2[k], c.c2[0],
-                        nullptr, s);
+                        nullptr, nullptr, s);
             std::swap(x, other);
         }
     }
     // residual and restriction
     if (fine) {
-        l0_residual<double, T>(H->l0, f0, x, other, s);
+        l0_residual<T, T>(H->l0, f0, x, other, s);
         l0_restrict<T>(H->l0, H->lc[0], other, d, B.f[1], P.omega, s);
     } else {
         lc_residual<T>(H->lc[l - 1], fl, x, other, s);
         lc_restrict<T>(H->lc[l - 1], H->lc[l], other, d, B.f[l + 1], P.omega, s);
     }
-    T* v = vcycle<T>(H, B, l + 1, nullptr, nullptr, nullptr, s);
+    T* v = vcycle<T>(H, B, l + 1, nullptr, nullptr, nullptr, nullptr, s);
     // coarse-grid correction
     if (fine)
         l0_prolong<T>(H->l0, H->lc[0], v, x, P.omega, s);
@@ -164,7 +165,7 @@ static T* vcycle(const saamg_hierarchy* H, VBuf<T>& B, int l, const double* f0, 
         const bool last = (k == c.degree - 1);
         T* dst = (last && fine) ? out : other;
         chebstep<T>(H, l, k == 0 ? CHEB_FIRST : CHEB_NEXT, f0, fl, x, d, dst, last ? nullptr : d,
-                    c.c1[k], c.c2[k], c.c2[0], (last && fine) ? dot : nullptr, s);
+                    c.c1[k], c.c2[k], c.c2[0], fdot, (last && fine) ? dot : nullptr, s);
         other = x;
         x = dst;
     }
@@ -183,9 +184,9 @@ struct saamg_state {
     double tol = 1e-8;
     int max_iter = 0;
     bool mixed = false;
-    double *x = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *bs = nullptr;
+    double *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *bs = nullptr;
+    float* r32 = nullptr;  // fp32 copy of r (mixed precision)
     void* z = nullptr;
-    int pcur = 0;
     VBuf<float> vf;
     VBuf<double> vd;
     double* part = nullptr;
@@ -208,12 +209,12 @@ static void state_alloc(saamg_state* S, saamg_hierarchy* H) {
     const long n = H->l0.nbox;
     S->x = (double*)dmalloc(8 * n);
     S->r = (double*)dmalloc(8 * n);
-    S->p[0] = (double*)dmalloc(8 * n);
-    S->p[1] = (double*)dmalloc(8 * n);
+    S->p = (double*)dmalloc(8 * n);
     S->q = (double*)dmalloc(8 * n);
     S->bs = (double*)dmalloc(8 * n);
     S->z = dmalloc((S->mixed ? 4 : 8) * n);
-    S->bytes = 48L * n + (S->mixed ? 4 : 8) * n;
+    if (S->mixed) S->r32 = (float*)dmalloc(4 * n);
+    S->bytes = 40L * n + (S->mixed ? 8 : 8) * n;
     if (S->mixed) {
         S->vf.alloc(H);
         S->bytes += S->vf.bytes(H);
@@ -229,15 +230,17 @@ static void state_alloc(saamg_state* S, saamg_hierarchy* H) {
 }
 
 static void state_release(saamg_state* S) {
-    for (double* p : {S->x, S->r, S->p[0], S->p[1], S->q, S->bs}) dfree(p);
+    for (double* p : {S->x, S->r, S->p, S->q, S->bs}) dfree(p);
     dfree(S->z);
+    dfree(S->r32);
+    S->r32 = nullptr;
     S->vf.release();
     S->vd.release();
     dfree(S->part);
     dfree(S->scal);
     if (S->hscal) (void)hipHostFree(S->hscal);
     if (S->ev) (void)hipEventDestroy(S->ev);
-    S->x = S->r = S->p[0] = S->p[1] = S->q = S->bs = nullptr;
+    S->x = S->r = S->p = S->q = S->bs = nullptr;
     S->z = nullptr;
     S->part = S->scal = S->hscal = nullptr;
     S->ev = nullptr;
@@ -252,14 +255,14 @@ static void read_scal(saamg_state* S) {
 static void precond(saamg_state* S) {
     const saamg_hierarchy* H = S->H;
     if (S->mixed)
-        vcycle<float>(H, S->vf, 0, S->r, (float*)S->z, S->part, S->s);
+        vcycle<float>(H, S->vf, 0, S->r32, (float*)S->z, S->r, S->part, S->s);
     else
-        vcycle<double>(H, S->vd, 0, S->r, (double*)S->z, S->part, S->s);
+        vcycle<double>(H, S->vd, 0, S->r, (double*)S->z, S->r, S->part, S->s);
 }
 
 // True residual b - A x into `dst`; returns ||dst||^2.
 static double true_residual(saamg_state* S, double* dst) {
-    cg_resid(S->H->l0, S->bs, S->x, dst, S->part, S->s);
+    cg_resid(S->H->l0, S->bs, S->x, dst, S->part, dst == S->r ? S->r32 : nullptr, S->s);
     finalize(S->part, l0_blocks(S->H->l0), 2, S->scal, FIN_STORE, S_RT, S->s);
     read_scal(S);
     return S->hscal[S_RT];
@@ -271,12 +274,12 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
     S->status = SAAMG_OK;
     S->done = 0;
     S->repl = 0;
-    S->pcur = 0;
     S->t0 = std::chrono::steady_clock::now();
     cg_init(H->l0, b, x0, S->bs, S->x, S->s);
-    cg_resid(H->l0, S->bs, S->x, S->r, S->part, S->s);
+    cg_resid(H->l0, S->bs, S->x, S->r, S->part, S->r32, S->s);
     finalize(S->part, l0_blocks(H->l0), 2, S->scal, FIN_STORE, S_RR, S->s);
-    HIPCHECK(hipMemsetAsync(S->p[0], 0, 8 * H->l0.nbox, S->s));
+    HIPCHECK(hipMemsetAsync(S->p, 0, 8 * H->l0.nbox, S->s));
+    HIPCHECK(hipMemsetAsync(S->q, 0, 8 * H->l0.nbox, S->s));
     read_scal(S);
     const double rr = S->hscal[S_RR], bb = S->hscal[S_BB];
     S->bnorm = std::sqrt(bb);
@@ -311,19 +314,16 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
 static void state_enqueue(saamg_state* S) {
     const saamg_hierarchy* H = S->H;
     const long nb = l0_blocks(H->l0);
-    double* pold = S->p[S->pcur];
-    double* pnew = S->p[1 - S->pcur];
     if (S->mixed)
-        cg_pq<float>(H->l0, (const float*)S->z, pold, pnew, S->q, S->scal, S->part, S->s);
+        cg_pq<float>(H->l0, (const float*)S->z, S->p, S->q, S->scal, S->part, S->s);
     else
-        cg_pq<double>(H->l0, (const double*)S->z, pold, pnew, S->q, S->scal, S->part, S->s);
+        cg_pq<double>(H->l0, (const double*)S->z, S->p, S->q, S->scal, S->part, S->s);
     finalize(S->part, nb, 1, S->scal, FIN_ALPHA, 0, S->s);
-    cg_xr(H->l0, S->x, pnew, S->r, S->q, S->scal, S->part, S->s);
+    cg_xr(H->l0, S->x, S->p, S->r, S->q, S->scal, S->part, S->r32, S->s);
     finalize(S->part, nb, 1, S->scal, FIN_STORE, S_RR, S->s);
     HIPCHECK(hipMemcpyAsync(S->hscal, S->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
                             S->s));
     HIPCHECK(hipEventRecord(S->ev, S->s));
-    S->pcur = 1 - S->pcur;
     precond(S);
     finalize(S->part, nb, 1, S->scal, FIN_RHO, 0, S->s);
 }
@@ -771,7 +771,8 @@ static void level_apply_impl(saamg_hierarchy* H, int l, int op, const double* hi
             T* d = (T*)dmalloc(sizeof(T) * level_nstore(H, l));
             auto step = [&](int mode, const T* xi, const T* di, T* xo, T* dd, double c1, double c2) {
                 if (l == 0)
-                    l0_cheb<T, T>(H->l0, mode, din, xi, di, xo, dd, c1, c2, c.c2[0], nullptr, s);
+                    l0_cheb<T, T>(H->l0, mode, din, xi, di, xo, dd, c1, c2, c.c2[0], nullptr,
+                                  nullptr, s);
                 else
                     lc_cheb<T>(H->lc[l - 1], mode, din, xi, di, xo, dd, c1, c2, c.c2[0], s);
             };
@@ -1085,7 +1086,7 @@ int saamg_precond_apply(saamg_hierarchy* H, const double* d_r, double* d_z, void
         saamg_state& S = *workspace(H);
         S.s = (hipStream_t)stream;
         // the residual buffer must stay zero off the unknowns: copy via the scaled mask
-        cg_mask_copy(H->l0, d_r, S.r, S.s);
+        cg_mask_copy(H->l0, d_r, S.r, S.r32, S.s);
         precond(&S);
         if (S.mixed)
             f2d_copy((const float*)S.z, d_z, H->l0.nbox, S.s);
