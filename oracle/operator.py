@@ -135,6 +135,28 @@ def assemble(dom: Domain, variant: int) -> System:
     return System(dom, variant, A, idx, sigma, As)
 
 
+def diagonal(dom: Domain, variant: int):
+    """Diagonal of A at every unknown (box-lexicographic order) without assembling A.
+
+    Same per-axis rule as ``assemble``; used to scale right-hand sides of grids too large
+    to assemble in a test.  Returns (box indices of the unknowns, diagonal).
+    """
+    nx, ny = dom.nx, dom.ny
+    ks, js, is_ = np.nonzero(dom.mask)
+    diag = np.zeros(ks.size)
+    for axis in range(3):
+        step = [0, 0, 0]
+        step[axis] = 1
+        dx, dy, dz = step
+        in_m = dom.mask[ks - dz, js - dy, is_ - dx]
+        in_p = dom.mask[ks + dz, js + dy, is_ + dx]
+        s_m = dom.frac[2 * axis, ks, js, is_]
+        s_p = dom.frac[2 * axis + 1, ks, js, is_]
+        c_self, _, _ = _axis_terms(variant, in_m, in_p, s_m, s_p)
+        diag += c_self / (dom.h[axis] * dom.h[axis])
+    return (is_ + nx * (js + ny * ks)).astype(np.int64), diag
+
+
 def scaled_rhs(sys_: System, b_box: np.ndarray) -> np.ndarray:
     """D^-1/2 b over the unknowns."""
     return sys_.sigma * sys_.gather(b_box)

@@ -232,3 +232,12 @@ def test_mms_against_paper_tables(variant, name):
         assert 1.8 < rate < 2.3
     assert 0.75 < l2_64 / g["h64"]["l2"] < 1.33
     assert 0.75 < li_64 / g["h64"]["linf"] < 1.33
+
+
+def test_diagonal_helper_matches_assembly():
+    dom = _dom(W.Shape.ellipse(1.0, 0.6, 2.0), 21, 19)
+    for v in (0, 1, 2):
+        s = operator.assemble(dom, v)
+        idx, dg = operator.diagonal(dom, v)
+        assert np.array_equal(idx, s.idx)
+        assert np.max(np.abs(dg - s.A.diagonal())) <= 1e-14 * dg.max()
