@@ -45,7 +45,100 @@ def parse():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="served-stream mode: Poisson arrivals of mixed pipe requests")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--pic", action="store_true",
+                    help="PIC sequence: moving bunch, one hierarchy, warm-started solves")
+    ap.add_argument("--pic-steps", type=int, default=20)
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="open-loop arrival rate as a fraction of the closed-loop solves/s")
     return ap.parse_args()
+
+
+def pic_bench(args) -> dict:
+    """Successive solves on the 192x192x1024 cylinder (L = 8) as a 2M-particle bunch moves
+    0.02 along z per step: the hierarchy is built once and each solve starts from the
+    previous solution (Section 4: previous time step as initial guess; Section 5: reuse of
+    the preconditioner).  Deposition runs on the host between steps and is not timed."""
+    import torch
+
+    import paper_0907_4863_amd as sa
+    import workloads as W
+
+    w = W.c5_cylinder192(sa.MIXED)
+    dev = torch.device("cuda:0")
+    dom = sa.domain_for(w.shape, w.nx, w.ny, w.nz)
+    parts = W.draw_particles(w.bunch)
+    t0 = time.perf_counter()
+    H = sa.setup(dom, w.variant, sa.default_options(precision=sa.MIXED))
+    torch.cuda.synchronize()
+    setup_ms = 1e3 * (time.perf_counter() - t0)
+    xa = torch.zeros(w.box_nodes, dtype=torch.float64, device=dev)
+    xb = torch.zeros_like(xa)
+    steps = []
+    for k in range(args.pic_steps):
+        b = torch.from_numpy(W.rhs(w, shift_z=W.pic_shift(k), particles=parts).reshape(-1)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = sa.solve(H, b, xb, x0=(xa if k > 0 else None), tol=w.tol)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0)
+        steps.append((res["iterations"], ms, res["rel_res_true"]))
+        xa, xb = xb, xa
+        print(f"[bench] pic step {k}: {res['iterations']} it, {ms:.1f} ms", file=sys.stderr, flush=True)
+    sa.destroy(H)
+    later = steps[1:] if len(steps) > 1 else steps
+    it_l = sum(s[0] for s in later)
+    ms_l = sum(s[1] for s in later)
+    return {"workload": "cylinder R=1 L=8 192x192x1024, linear wall rule, mixed",
+            "dof": dom.n_unknowns, "setup_ms": setup_ms, "steps": len(steps),
+            "first_step": {"iterations": steps[0][0], "ms": steps[0][1]},
+            "warm_steps_mean_iterations": it_l / len(later),
+            "warm_steps_mean_ms": ms_l / len(later),
+            "warm_dof_iter_per_s": dom.n_unknowns * it_l / (ms_l * 1e-3),
+            "max_rel_res": max(s[2] for s in steps)}
+
+
+def serve_bench(args) -> dict:
+    """Continuous batching over a seeded stream of pipe solves (cylinder, ellipse and
+    box-with-bore; cross-section edge 32..160; length ratio 1..4).  Pass 1 admits every
+    request at t = 0 (closed loop) to measure capacity; pass 2 replays Poisson arrivals at
+    serve_load x that rate in mixed precision, pass 3 the same arrivals in fp64."""
+    import dataclasses as dc
+
+    import paper_0907_4863_amd as sa
+    import workloads as W
+    from paper_0907_4863_amd import serve
+
+    reqs = W.serving_stream(n_requests=args.serve_requests, qps=1.0, seed=4)
+    print(f"[bench] serve: generating {len(reqs)} right-hand sides", file=sys.stderr, flush=True)
+    rhs = {r.rid: W.rhs(r.workload) for r in reqs}
+    dof_total = 0
+    out = {}
+
+    def run(tag, arrivals, precision):
+        rs = [W.Request(r.rid, t, dc.replace(r.workload, precision=precision))
+              for r, t in zip(reqs, arrivals)]
+        srv = serve.Server(serve.ServeConfig(precision=precision, max_active=16,
+                                             hbm_budget_bytes=200 << 30), serve.GpuEngine())
+        recs = srv.run(rs, rhs_of=lambda q: rhs[q.rid])
+        srv.close()
+        summ = serve.summarize(recs)
+        summ["max_concurrent"] = srv.max_concurrent
+        summ["peak_device_bytes"] = srv.peak_used
+        print(f"[bench] serve {tag}: {summ}", file=sys.stderr, flush=True)
+        return summ
+
+    closed = run("closed-loop mixed", [0.0] * len(reqs), sa.MIXED)
+    qps = args.serve_load * closed["solves_per_s"]
+    gaps = np.random.default_rng(4).exponential(1.0 / qps, size=len(reqs))
+    arr = list(np.cumsum(gaps) - gaps[0])
+    out["closed_loop_mixed"] = closed
+    out["open_loop_mixed"] = run("open-loop mixed", arr, sa.MIXED)
+    out["open_loop_fp64"] = run("open-loop fp64", arr, sa.FP64)
+    out["qps"] = qps
+    return out
 
 
 def cpu_baseline(w, planes: int) -> dict:
@@ -130,6 +223,33 @@ def main():
 
     import paper_0907_4863_amd as sa
     import workloads as W
+
+    if args.pic:
+        res = pic_bench(args)
+        print(json.dumps({
+            "metric": "DOF*iter/s of warm-started PIC solves at rel-res 1e-8",
+            "value": res["warm_dof_iter_per_s"], "unit": "DOF*iter/s", "n_gpus": 1,
+            "steps": res["steps"], "warmup": 0, "ms_per_step": res["warm_steps_mean_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64", "data": "synthetic (seeded 2M-particle bunch, cloud-in-cell)",
+            "config": {"workload": res["workload"], "dof": res["dof"]}, "pic": res}), flush=True)
+        return
+    if args.serve:
+        res = serve_bench(args)
+        m, f = res["open_loop_mixed"], res["open_loop_fp64"]
+        print(json.dumps({
+            "metric": "served solves/s and p50/p99 latency at rel-res 1e-8 (Poisson arrivals)",
+            "value": m["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+            "steps": args.serve_requests, "warmup": 0, "ms_per_step": 1e3 / m["solves_per_s"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64", "data": "synthetic (seeded Gaussian bunches, cloud-in-cell)",
+            "config": {"workload": f"served stream of {args.serve_requests} pipe solves "
+                                   f"(cylinder/ellipse/box-with-bore, edge 32..160, ratio 1..4), "
+                                   f"Poisson arrivals at {res['qps']:.2f}/s"},
+            "p50_latency_ms": m["p50_latency_ms"], "p99_latency_ms": m["p99_latency_ms"],
+            "fp64": f, "closed_loop_mixed": res["closed_loop_mixed"], "open_loop_mixed": m,
+        }), flush=True)
+        return
 
     w = W.by_name(args.workload)
     dev = torch.device("cuda:0")

@@ -1,0 +1,248 @@
+"""Continuous-batching solve server on one GPU.
+
+Requests (a pipe geometry, a lattice, a right-hand side) arrive over time.  The loop
+admits a request as soon as a slot is free and its device footprint fits the HBM budget,
+reuses hierarchies cached per geometry (the paper's reuse of the preconditioner across
+solves, Section 5, ML variations), and advances every admitted solve by one PCG step per
+round through ``saamg_batch_step``.  Each active solve owns a stream, so the rounds of
+different requests overlap on the device; finished solves retire at once and free their
+memory for queued requests.  Latency is completion minus arrival.
+
+The device work goes through an engine object (``GpuEngine`` below) so that the
+scheduling logic can be exercised without a GPU.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from collections import OrderedDict
+from typing import Any, Callable, Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import capi
+
+
+@dataclasses.dataclass
+class ServeConfig:
+    hbm_budget_bytes: int = 64 << 30
+    max_active: int = 16
+    precision: int = capi.MIXED
+    tol: float = 1e-8
+    max_iter: int = 500
+    cache_hierarchies: bool = True
+
+
+@dataclasses.dataclass
+class Record:
+    rid: int
+    arrival_s: float
+    admit_s: float = float("nan")
+    done_s: float = float("nan")
+    iterations: int = 0
+    status: int = -1
+    rel_res: float = float("nan")
+    setup_ms: float = 0.0
+    cache_hit: bool = False
+    dof: int = 0
+    x: Any = None
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+class GpuEngine:
+    """Device side of the server: hierarchies, states and steps through the C interface."""
+
+    def __init__(self, device: int = 0, keep_solutions: bool = False):
+        import torch
+        self.torch = torch
+        self.dev = torch.device(f"cuda:{device}")
+        self.keep = keep_solutions
+        self._streams: List[Any] = []
+
+    def key(self, w) -> Tuple:
+        s = w.shape
+        return (s.kind, s.a, s.b, s.length, s.bore_r, s.cavity_half_len, w.nx, w.ny, w.nz, w.variant)
+
+    def footprint(self, w, precision: int) -> Tuple[int, int]:
+        return capi.footprint_bytes(w.nx, w.ny, w.nz, w.variant, precision)
+
+    def setup(self, w, precision: int):
+        dom = capi.domain_for(w.shape, w.nx, w.ny, w.nz)
+        H = capi.setup(dom, w.variant, capi.default_options(precision=precision))
+        info = capi.hierarchy_info(H)
+        return H, info["device_bytes"], dom.n_unknowns
+
+    def release_hierarchy(self, H) -> None:
+        capi.destroy(H)
+
+    def _stream(self):
+        if self._streams:
+            return self._streams.pop()
+        return self.torch.cuda.Stream(device=self.dev)  # default priority
+
+    def start(self, H, b_host: np.ndarray, tol: float, max_iter: int):
+        torch = self.torch
+        b = torch.from_numpy(np.ascontiguousarray(b_host, dtype=np.float64).reshape(-1)).to(self.dev)
+        torch.cuda.synchronize(self.dev)  # the upload is complete before another stream reads b
+        st = self._stream()
+        S = capi.state_create(H, b, tol=tol, max_iter=max_iter, stream=st.cuda_stream)
+        return {"S": S, "b": b, "stream": st, "H": H}
+
+    def step(self, handles: Sequence[dict]) -> None:
+        capi.batch_step([h["S"] for h in handles])
+
+    def query(self, h) -> Tuple[bool, dict]:
+        return capi.state_query(h["S"])
+
+    def finish(self, h):
+        x = None
+        if self.keep:
+            x = self.torch.zeros(h["b"].numel(), dtype=self.torch.float64, device=self.dev)
+            capi.state_finish(h["S"], x)
+            x = x.cpu().numpy()
+        capi.state_destroy(h["S"])
+        self._streams.append(h["stream"])
+        return x
+
+
+class Server:
+    def __init__(self, cfg: ServeConfig, engine, clock: Callable[[], float] = time.perf_counter,
+                 sleep: Callable[[float], None] = time.sleep):
+        self.cfg = cfg
+        self.eng = engine
+        self.clock = clock
+        self.sleep = sleep
+        self.cache: "OrderedDict[Tuple, dict]" = OrderedDict()  # key -> {H, bytes, refs, dof}
+        self.used = 0
+        self.peak_used = 0
+        self.max_concurrent = 0
+        self.rounds = 0
+        self.rejected: List[int] = []
+
+    # -------------------------------------------------------------- memory accounting
+    def _evict_for(self, need: int) -> None:
+        for key in list(self.cache.keys()):
+            if self.used + need <= self.cfg.hbm_budget_bytes:
+                return
+            e = self.cache[key]
+            if e["refs"] == 0:
+                self.eng.release_hierarchy(e["H"])
+                self.used -= e["bytes"]
+                del self.cache[key]
+
+    def _admit(self, req, rhs: np.ndarray, now: float, active: List[dict]) -> Optional[dict]:
+        w = req.workload
+        key = self.eng.key(w)
+        hier_est, state_bytes = self.eng.footprint(w, self.cfg.precision)
+        cached = key in self.cache
+        need = state_bytes + (0 if cached else hier_est)
+        if self.used + need > self.cfg.hbm_budget_bytes:
+            self._evict_for(need)
+        if self.used + need > self.cfg.hbm_budget_bytes:
+            return None
+        rec = Record(req.rid, req.arrival_s, admit_s=now)
+        if cached:
+            e = self.cache.pop(key)
+            self.cache[key] = e  # most recently used
+            rec.cache_hit = True
+        else:
+            t0 = self.clock()
+            H, hbytes, dof = self.eng.setup(w, self.cfg.precision)
+            rec.setup_ms = 1e3 * (self.clock() - t0)
+            e = {"H": H, "bytes": hbytes, "refs": 0, "dof": dof}
+            self.cache[key] = e
+            self.used += hbytes
+        e["refs"] += 1
+        rec.dof = e["dof"]
+        h = self.eng.start(e["H"], rhs, self.cfg.tol, self.cfg.max_iter)
+        self.used += state_bytes
+        self.peak_used = max(self.peak_used, self.used)
+        return {"rec": rec, "h": h, "key": key, "state_bytes": state_bytes}
+
+    def _retire(self, a: dict, now: float) -> Record:
+        done, res = self.eng.query(a["h"])
+        rec = a["rec"]
+        rec.done_s = now
+        rec.iterations = res["iterations"]
+        rec.status = res["status"]
+        rec.rel_res = res["rel_res_true"]
+        rec.x = self.eng.finish(a["h"])
+        self.used -= a["state_bytes"]
+        e = self.cache[a["key"]]
+        e["refs"] -= 1
+        if not self.cfg.cache_hierarchies and e["refs"] == 0:
+            self.eng.release_hierarchy(e["H"])
+            self.used -= e["bytes"]
+            del self.cache[a["key"]]
+        return rec
+
+    # -------------------------------------------------------------- main loop
+    def run(self, requests: Sequence, rhs_of: Callable[[Any], np.ndarray]) -> List[Record]:
+        """Serve requests (objects with rid, arrival_s, workload) in arrival order."""
+        queue = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
+        t0 = self.clock()
+        active: List[dict] = []
+        out: List[Record] = []
+        qi = 0
+        while qi < len(queue) or active:
+            now = self.clock() - t0
+            while qi < len(queue) and queue[qi].arrival_s <= now and len(active) < self.cfg.max_active:
+                req = queue[qi]
+                a = self._admit(req, rhs_of(req), self.clock() - t0, active)
+                if a is None:
+                    if not active:
+                        # can never fit: reject instead of waiting forever
+                        r = Record(req.rid, req.arrival_s, status=capi.NOMEM)
+                        r.done_s = self.clock() - t0
+                        out.append(r)
+                        self.rejected.append(req.rid)
+                        qi += 1
+                        continue
+                    break
+                active.append(a)
+                qi += 1
+            self.max_concurrent = max(self.max_concurrent, len(active))
+            if not active:
+                if qi < len(queue):
+                    self.sleep(max(0.0, queue[qi].arrival_s - (self.clock() - t0)))
+                continue
+            self.eng.step([a["h"] for a in active])
+            self.rounds += 1
+            keep = []
+            for a in active:
+                done, _ = self.eng.query(a["h"])
+                if done:
+                    out.append(self._retire(a, self.clock() - t0))
+                else:
+                    keep.append(a)
+            active = keep
+        return out
+
+    def close(self) -> None:
+        for e in self.cache.values():
+            self.eng.release_hierarchy(e["H"])
+        self.cache.clear()
+        self.used = 0
+
+
+def summarize(records: Sequence[Record]) -> Dict[str, float]:
+    ok = [r for r in records if r.status == capi.OK]
+    lat = np.array([r.latency_s for r in ok]) if ok else np.array([np.nan])
+    t_first = min(r.arrival_s for r in records)
+    t_last = max(r.done_s for r in records)
+    span = max(t_last - t_first, 1e-9)
+    return {
+        "requests": len(records),
+        "completed": len(ok),
+        "rejected": sum(1 for r in records if r.status == capi.NOMEM),
+        "solves_per_s": len(ok) / span,
+        "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+        "mean_iterations": float(np.mean([r.iterations for r in ok])) if ok else float("nan"),
+        "dof_iter_per_s": sum(r.dof * r.iterations for r in ok) / span,
+        "cache_hits": sum(1 for r in ok if r.cache_hit),
+        "max_rel_res": float(max((r.rel_res for r in ok), default=float("nan"))),
+    }
