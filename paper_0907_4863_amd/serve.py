@@ -101,6 +101,7 @@ class GpuEngine:
         x = None
         if self.keep:
             x = self.torch.zeros(h["b"].numel(), dtype=self.torch.float64, device=self.dev)
+            self.torch.cuda.synchronize(self.dev)  # the fill is done before the state's stream writes x
             capi.state_finish(h["S"], x)
             x = x.cpu().numpy()
         capi.state_destroy(h["S"])
