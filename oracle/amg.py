@@ -18,9 +18,15 @@ Readings where the paper is silent (listed in the design doc):
 * aggregates are the index blocks [3I, 3I+3) x [3J, 3J+3) x [3K, 3K+3) of the level's
   logical box; a block's unknowns form one aggregate, partial blocks are kept; the
   coarse level's logical box has ceil(n/3) points per axis;
-* lambda_hat of D^-1 A comes from ``eig_iters`` = 15 power steps started from
-  v_i = ((i * 2654435761) mod 2^32) / 2^32 - 1/2 (i = logical box index), followed by
-  the D-weighted Rayleigh quotient u^T A u / u^T D u of the last normalised iterate;
+* the smoother paragraph asks for a bound on the spectrum without naming a routine.
+  lambda_hat is the largest Ritz value of ``eig_iters`` = 15 Lanczos steps on the
+  symmetric part S = (A + A^T)/2 in the D inner product (S = A for the symmetric
+  variant; for the quadratic rule the largest eigenvalue of D^-1 S bounds the real parts
+  of the spectrum of D^-1 A from above).  The start vector holds, at an unknown with
+  logical box index i, the SplitMix64 output for counter i (Steele, Lea and Flood,
+  "Fast splittable pseudorandom number generators", OOPSLA 2014) mapped to [-1/2, 1/2);
+  the recurrence stops early when beta_k <= 1e-12 * max_j |alpha_j|, and at most n
+  steps run on a level with n unknowns;
 * omega = (4/3) / lambda_hat; the Chebyshev interval is [lambda_hi / 10, lambda_hi]
   with lambda_hi = 1.1 * lambda_hat, degree 2;
 * the Chebyshev recurrence is the classical three-term Chebyshev acceleration
@@ -75,22 +81,51 @@ class Hierarchy:
         return [lv.n for lv in self.levels]
 
 
+_U64 = np.uint64
+
+
 def start_vector(lin: np.ndarray) -> np.ndarray:
-    """Deterministic power-iteration start vector (integer hash of the box index)."""
-    h = (lin.astype(np.uint64) * np.uint64(2654435761)) % np.uint64(1 << 32)
-    return h.astype(np.float64) / 4294967296.0 - 0.5
+    """Lanczos start vector: SplitMix64 of the logical box index, as a double in [-1/2, 1/2).
+
+    SplitMix64 value number i: z = (i + 1) * 0x9E3779B97F4A7C15 (mod 2^64), then
+    z ^= z >> 30; z *= 0xBF58476D1CE4E5B9; z ^= z >> 27; z *= 0x94D049BB133111EB;
+    z ^= z >> 31.  The top 53 bits scaled by 2^-53 give a value in [0, 1).
+    """
+    with np.errstate(over="ignore"):
+        z = (lin.astype(_U64) + _U64(1)) * _U64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> _U64(30))) * _U64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> _U64(27))) * _U64(0x94D049BB133111EB)
+        z = z ^ (z >> _U64(31))
+    return (z >> _U64(11)).astype(np.float64) / 2.0 ** 53 - 0.5
 
 
-def power_lambda(A: sp.csr_matrix, D: np.ndarray, lin: np.ndarray, iters: int) -> float:
-    """Largest-eigenvalue estimate of D^-1 A by the power method."""
-    v = start_vector(lin)
-    u = v
-    w = v
-    for _ in range(iters):
-        u = v / np.linalg.norm(v)
-        w = (A @ u) / D
-        v = w
-    return float(np.dot(u, D * w) / np.dot(u, D * u))
+def lanczos_lambda(A: sp.csr_matrix, D: np.ndarray, lin: np.ndarray, steps: int) -> float:
+    """Estimate of the top of the spectrum of D^-1 A by Lanczos on its symmetric part.
+
+    D^-1 S with S = (A + A^T)/2 is self-adjoint in <u, w>_D = u^T D w, so the textbook
+    three-term Lanczos recurrence in that inner product builds a tridiagonal T whose
+    largest eigenvalue approaches lambda_max(D^-1 S) from below.
+    """
+    S = ((A + A.T) * 0.5).tocsr()
+    dot = lambda u, w: float(np.dot(u, D * w))
+    q = start_vector(lin)
+    q = q / np.sqrt(dot(q, q))
+    q_prev = np.zeros_like(q)
+    beta_prev = 0.0
+    alpha, beta = [], []
+    for _ in range(min(steps, lin.size)):
+        w = (S @ q) / D
+        a = dot(q, w)
+        w = w - a * q - beta_prev * q_prev
+        b = np.sqrt(dot(w, w))
+        alpha.append(a)
+        beta.append(b)
+        if b <= 1e-12 * max(abs(x) for x in alpha):
+            break
+        q_prev, q, beta_prev = q, w / b, b
+    m = len(alpha)
+    T = np.diag(alpha) + np.diag(beta[:m - 1], 1) + np.diag(beta[:m - 1], -1)
+    return float(np.linalg.eigvalsh(T)[-1])
 
 
 def aggregate(lin: np.ndarray, dims: Tuple[int, int, int]):
@@ -149,7 +184,7 @@ def setup(A0: sp.csr_matrix, dims0: Tuple[int, int, int], lin0: np.ndarray,
         agg, clin, cdims = aggregate(lv.lin, lv.dims)
         if clin.size >= lv.n:
             break
-        lv.lam = power_lambda(lv.A, lv.D, lv.lin, opts.eig_iters)
+        lv.lam = lanczos_lambda(lv.A, lv.D, lv.lin, opts.eig_iters)
         lv.lam_hi = opts.cheb_boost * lv.lam
         lv.omega = opts.omega_scale / lv.lam
         lv.Ptent = tentative_prolongator(agg, clin.size)
