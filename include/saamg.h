@@ -85,8 +85,8 @@ typedef struct {
     int32_t max_coarse;    /* stop coarsening at <= this many unknowns (Table 1) default 1000 */
     int32_t cheb_degree;   /* Chebyshev polynomial degree, 1..8                default 2    */
     double cheb_ratio;     /* smoothing interval [lambda_hi/ratio, lambda_hi]  default 10   */
-    double cheb_boost;     /* lambda_hi = boost * power-method estimate        default 1.1  */
-    int32_t eig_iters;     /* power-method steps per level                     default 15   */
+    double cheb_boost;     /* lambda_hi = boost * spectral estimate            default 1.1  */
+    int32_t eig_iters;     /* Lanczos steps per level (spectral estimate)      default 15   */
     double omega_scale;    /* prolongator damping omega = scale / lambda_est   default 4/3  */
 } saamg_options;
 
@@ -108,7 +108,7 @@ typedef struct {
     int32_t precision;
     int32_t dims[SAAMG_MAX_LEVELS][3];    /* logical box of each level (level 0 = lattice) */
     int64_t n_unknowns[SAAMG_MAX_LEVELS];
-    double lambda_est[SAAMG_MAX_LEVELS];  /* power-method estimate of lambda_max(D^-1 A) */
+    double lambda_est[SAAMG_MAX_LEVELS];  /* Lanczos estimate of lambda_max(D^-1 (A+A^T)/2) */
     double omega[SAAMG_MAX_LEVELS];
     int64_t n_irregular;                  /* level-0 rows with a non-constant stencil */
     int64_t device_bytes;                 /* device memory held by the hierarchy */

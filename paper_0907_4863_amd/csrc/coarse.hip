@@ -69,59 +69,93 @@ void lc_apply(const CoarseLevel& C, bool trans, const T* x, T* y, hipStream_t s)
 template void lc_apply<double>(const CoarseLevel&, bool, const double*, double*, hipStream_t);
 template void lc_apply<float>(const CoarseLevel&, bool, const float*, float*, hipStream_t);
 
-__global__ void __launch_bounds__(kThreads) k_lc_power_start(LCView<double> c, double* w) {
+// Lanczos in the D inner product (see the level-0 version for the storage of vectors).
+
+// v = start vector at the unknowns; partials of v.(D v).
+__global__ void __launch_bounds__(kThreads) k_lc_lz_start(LCView<double> c, double* w,
+                                                         double* part) {
+    __shared__ double lds[kThreads / kWave];
     LC_PROLOGUE
-    if (!inb) return;
-    const long lin = X + (long)c.mx * (Y + (long)c.my * Z);
-    w[i] = c.invD[i] != 0.0 ? start_value(lin) : 0.0;
+    double a0 = 0.0;
+    if (inb) {
+        const long lin = X + (long)c.mx * (Y + (long)c.my * Z);
+        const double id = c.invD[i];
+        const double sv = id != 0.0 ? start_value(lin) : 0.0;
+        w[i] = sv;
+        if (id != 0.0) a0 = sv * sv / id;
+    }
+    const double s0 = block_sum(a0, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = s0;
 }
 
-void lc_power_start(const CoarseLevel& C, double* v, hipStream_t s) {
-    hipLaunchKernelGGL(k_lc_power_start, lc_grid(C), dim3(kThreads), 0, s,
-                       C.view<double>(), v);
+void lc_lz_start(const CoarseLevel& C, double* v, double* partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_lc_lz_start, lc_grid(C), dim3(kThreads), 0, s, C.view<double>(), v,
+                       partials);
     HIPCHECK(hipGetLastError());
 }
 
-// w = D^-1 A u, u = v * scal[S_INVN]; partials of w.w, u.(A u), u.(D u).
+// u = S q, q = vin * scal[S_LZ_S], S = (A + A^T)/2; partials of q.u.
 template <bool SYM>
-__global__ void __launch_bounds__(kThreads) k_lc_power_step(LCView<double> c,
-                                                            const double* __restrict__ vin,
-                                                            const double* __restrict__ scal,
-                                                            double* __restrict__ w, double* part) {
+__global__ void __launch_bounds__(kThreads) k_lc_lz_apply(LCView<double> c,
+                                                         const double* __restrict__ vin,
+                                                         const double* __restrict__ scal,
+                                                         double* __restrict__ u, double* part) {
     __shared__ double lds[kThreads / kWave];
-    const double sc = scal[S_INVN];
+    const double sc = scal[S_LZ_S];
     LC_PROLOGUE
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    double a0 = 0.0;
     if (inb) {
-        const double id = c.invD[i];
         double o = 0.0;
-        if (id != 0.0) {
-            const double au = lc_stencil<double, SYM, false>(c, i, [&](long j) { return vin[j] * sc; });
-            const double u = vin[i] * sc;
-            o = id * au;
-            a0 = o * o;
-            a1 = u * au;
-            a2 = u * u / id;
+        if (c.invD[i] != 0.0) {
+            auto ld = [&](long j) { return vin[j] * sc; };
+            o = lc_stencil<double, SYM, false>(c, i, ld);
+            if (!SYM) o = 0.5 * (o + lc_stencil<double, false, true>(c, i, ld));
+            a0 = vin[i] * sc * o;
         }
-        w[i] = o;
+        u[i] = o;
     }
-    const long bid = block_linear_id(), nb = grid_blocks();
-    double s0 = block_sum(a0, lds), s1 = block_sum(a1, lds), s2 = block_sum(a2, lds);
-    if (threadIdx.x == 0 && threadIdx.y == 0) {
-        part[bid] = s0;
-        part[nb + bid] = s1;
-        part[2 * nb + bid] = s2;
-    }
+    const double s0 = block_sum(a0, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = s0;
 }
 
-void lc_power_step(const CoarseLevel& C, const double* v, const double* scal, double* w,
-                   double* partials, hipStream_t s) {
+void lc_lz_apply(const CoarseLevel& C, const double* v, const double* scal, double* u,
+                 double* partials, hipStream_t s) {
     if (C.sym)
-        hipLaunchKernelGGL((k_lc_power_step<true>), lc_grid(C), dim3(kThreads), 0, s,
-                           C.view<double>(), v, scal, w, partials);
+        hipLaunchKernelGGL((k_lc_lz_apply<true>), lc_grid(C), dim3(kThreads), 0, s,
+                           C.view<double>(), v, scal, u, partials);
     else
-        hipLaunchKernelGGL((k_lc_power_step<false>), lc_grid(C), dim3(kThreads), 0, s,
-                           C.view<double>(), v, scal, w, partials);
+        hipLaunchKernelGGL((k_lc_lz_apply<false>), lc_grid(C), dim3(kThreads), 0, s,
+                           C.view<double>(), v, scal, u, partials);
+    HIPCHECK(hipGetLastError());
+}
+
+// prev <- w = D^-1 u - alpha_k s_k cur - beta_{k-1} s_{k-1} prev; partials of w.(D w).
+__global__ void __launch_bounds__(kThreads) k_lc_lz_update(LCView<double> c,
+                                                          const double* __restrict__ u,
+                                                          const double* __restrict__ cur,
+                                                          double* __restrict__ prev,
+                                                          const double* __restrict__ scal,
+                                                          double* part) {
+    __shared__ double lds[kThreads / kWave];
+    const double ac = scal[S_ALPHA] * scal[S_LZ_S], bp = scal[S_LZ_B] * scal[S_LZ_SP];
+    LC_PROLOGUE
+    double a0 = 0.0;
+    if (inb) {
+        const double id = c.invD[i];
+        if (id != 0.0) {
+            const double w = id * u[i] - ac * cur[i] - bp * prev[i];
+            prev[i] = w;
+            a0 = w * w / id;
+        }
+    }
+    const double s0 = block_sum(a0, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = s0;
+}
+
+void lc_lz_update(const CoarseLevel& C, const double* u, const double* cur, double* prev,
+                  const double* scal, double* partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_lc_lz_update, lc_grid(C), dim3(kThreads), 0, s, C.view<double>(), u,
+                       cur, prev, scal, partials);
     HIPCHECK(hipGetLastError());
 }
 

@@ -90,10 +90,14 @@ __device__ inline long block_linear_id() {
 
 __device__ inline long grid_blocks() { return (long)gridDim.x * gridDim.y * gridDim.z; }
 
-// Deterministic power-method start value of a logical box index.
+// Lanczos start value of a logical box index: output number lin of SplitMix64 from
+// state 0 (Steele, Lea, Flood, OOPSLA 2014), its top 53 bits mapped to [-1/2, 1/2).
 __host__ __device__ inline double start_value(long lin) {
-    uint64_t h = ((uint64_t)lin * 2654435761ull) & 0xffffffffull;
-    return (double)h / 4294967296.0 - 0.5;
+    uint64_t z = ((uint64_t)lin + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1.0p-53 - 0.5;
 }
 
 // ---------------------------------------------------------------- host side

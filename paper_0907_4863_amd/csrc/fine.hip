@@ -261,12 +261,22 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(const double* __restri
             scal[S_RHO_PREV] = scal[S_RHO];
             scal[S_RHO] = sums[0];
             break;
-        case FIN_POWER:
-            scal[S_INVN] = 1.0 / sqrt(sums[0]);
-            scal[S_LAM] = sums[1] / sums[2];
+        case FIN_LZ_ALPHA:  // alpha_k of the Lanczos recurrence, recorded at scal[dst]
+            scal[S_ALPHA] = sums[0];
+            scal[dst] = sums[0];
             break;
-        case FIN_NORM:
-            scal[S_INVN] = 1.0 / sqrt(sums[0]);
+        case FIN_LZ_BETA: {  // beta_k = ||w||_D; the next vector is w / beta_k
+            const double b = sqrt(sums[0]);
+            scal[dst] = b;
+            scal[S_LZ_SP] = scal[S_LZ_S];
+            scal[S_LZ_S] = b > 0.0 ? 1.0 / b : 0.0;
+            scal[S_LZ_B] = b;
+            break;
+        }
+        case FIN_NORM:  // first Lanczos vector = start / ||start||_D
+            scal[S_LZ_S] = 1.0 / sqrt(sums[0]);
+            scal[S_LZ_SP] = 0.0;
+            scal[S_LZ_B] = 0.0;
             break;
         case FIN_RESTORE_RHO:
             scal[S_RHO] = scal[S_RHO_PREV];
@@ -538,47 +548,94 @@ void l0_apply(const FineLevel& L, bool trans, const T* x, T* y, hipStream_t s) {
 template void l0_apply<double>(const FineLevel&, bool, const double*, double*, hipStream_t);
 template void l0_apply<float>(const FineLevel&, bool, const float*, float*, hipStream_t);
 
-__global__ void __launch_bounds__(kMThreads) k_l0_power_start(L0View<double> v, double* w) {
+// Lanczos estimate of the top of the spectrum (D = I on the scaled level 0).  Each
+// vector v_k is stored unnormalised as s_k * buf with s_k in scal[S_LZ_S].
+
+// v = start vector at the unknowns; partials of v.v.
+__global__ void __launch_bounds__(kMThreads) k_l0_lz_start(L0View<double> v, double* w,
+                                                          double* part) {
+    __shared__ double lds[kMThreads / kWave];
+    double a0 = 0.0;
     l0_march<double, false, false>(v, [&](long) { return 0.0; }, NOFETCH,
                                    [&](long i, NoVals, double, double, int, int, int, bool, int) {
-                                       w[i] = start_value(i);
+                                       const double sv = start_value(i);
+                                       w[i] = sv;
+                                       a0 += sv * sv;
                                    });
+    const double s0 = block_sum(a0, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = s0;
 }
 
-void l0_power_start(const FineLevel& L, double* v, hipStream_t s) {
-    hipLaunchKernelGGL(k_l0_power_start, l0_mgrid(L), dim3(kWave, kMY), 0, s,
-                       L.view<double>(), v);
+void l0_lz_start(const FineLevel& L, double* v, double* partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_l0_lz_start, l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), v,
+                       partials);
     HIPCHECK(hipGetLastError());
 }
 
-// w = A u with u = v * scal[S_INVN] (D = I at level 0); partials of w.w, u.Au, u.u.
-__global__ void __launch_bounds__(kMThreads) k_l0_power_step(L0View<double> v,
-                                                            const double* __restrict__ vin,
-                                                            const double* __restrict__ scal,
-                                                            double* __restrict__ w, double* part) {
+// u = S q with q = vin * scal[S_LZ_S] and S the symmetric part (A + A^T)/2; partials of q.u.
+// Regular rows have equal row and column (their neighbours carry the interior
+// stencil), so only irregular rows add the transposed table.
+template <bool SYM>
+__global__ void __launch_bounds__(kMThreads) k_l0_lz_apply(L0View<double> v,
+                                                          const double* __restrict__ vin,
+                                                          const double* __restrict__ scal,
+                                                          double* __restrict__ u, double* part) {
     __shared__ double lds[kMThreads / kWave];
-    const double sc = scal[S_INVN];
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    l0_march<double, true, false>(v, [&](long j) { return vin[j] * sc; }, NOFETCH,
-                                  [&](long i, NoVals, double u, double au, int, int, int, bool, int) {
-                                      w[i] = au;
-                                      a0 += au * au;
-                                      a1 += u * au;
-                                      a2 += u * u;
-                                  });
-    const long bid = blockIdx.x, nb = gridDim.x;
-    double s0 = block_sum(a0, lds), s1 = block_sum(a1, lds), s2 = block_sum(a2, lds);
-    if (threadIdx.x == 0 && threadIdx.y == 0) {
-        part[bid] = s0;
-        part[nb + bid] = s1;
-        part[2 * nb + bid] = s2;
-    }
+    const double sc = scal[S_LZ_S];
+    const long nx = v.nx, nxy = v.nxy;
+    double a0 = 0.0;
+    l0_march<double, true, false>(
+        v, [&](long j) { return vin[j] * sc; }, NOFETCH,
+        [&](long i, NoVals, double q, double aq, int, int, int, bool irr, int r) {
+            double o = aq;
+            if (!SYM && irr) {
+                const double at = q + sc * (v.tabT[0][r] * vin[i - 1] + v.tabT[1][r] * vin[i + 1] +
+                                            v.tabT[2][r] * vin[i - nx] + v.tabT[3][r] * vin[i + nx] +
+                                            v.tabT[4][r] * vin[i - nxy] + v.tabT[5][r] * vin[i + nxy]);
+                o = 0.5 * (aq + at);
+            }
+            u[i] = o;
+            a0 += q * o;
+        });
+    const double s0 = block_sum(a0, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = s0;
 }
 
-void l0_power_step(const FineLevel& L, const double* v, const double* scal, double* w,
-                   double* partials, hipStream_t s) {
-    hipLaunchKernelGGL(k_l0_power_step, l0_mgrid(L), dim3(kWave, kMY), 0, s,
-                       L.view<double>(), v, scal, w, partials);
+void l0_lz_apply(const FineLevel& L, bool sym, const double* v, const double* scal, double* u,
+                 double* partials, hipStream_t s) {
+    if (sym)
+        hipLaunchKernelGGL(k_l0_lz_apply<true>, l0_mgrid(L), dim3(kWave, kMY), 0, s,
+                           L.view<double>(), v, scal, u, partials);
+    else
+        hipLaunchKernelGGL(k_l0_lz_apply<false>, l0_mgrid(L), dim3(kWave, kMY), 0, s,
+                           L.view<double>(), v, scal, u, partials);
+    HIPCHECK(hipGetLastError());
+}
+
+// prev <- w = u - alpha_k s_k cur - beta_{k-1} s_{k-1} prev; partials of w.w.
+__global__ void __launch_bounds__(kMThreads) k_l0_lz_update(L0View<double> v,
+                                                           const double* __restrict__ u,
+                                                           const double* __restrict__ cur,
+                                                           double* __restrict__ prev,
+                                                           const double* __restrict__ scal,
+                                                           double* part) {
+    __shared__ double lds[kMThreads / kWave];
+    const double ac = scal[S_ALPHA] * scal[S_LZ_S], bp = scal[S_LZ_B] * scal[S_LZ_SP];
+    double a0 = 0.0;
+    l0_march<double, false, false>(v, [&](long) { return 0.0; }, NOFETCH,
+                                   [&](long i, NoVals, double, double, int, int, int, bool, int) {
+                                       const double w = u[i] - ac * cur[i] - bp * prev[i];
+                                       prev[i] = w;
+                                       a0 += w * w;
+                                   });
+    const double s0 = block_sum(a0, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = s0;
+}
+
+void l0_lz_update(const FineLevel& L, const double* u, const double* cur, double* prev,
+                  const double* scal, double* partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_l0_lz_update, l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), u,
+                       cur, prev, scal, partials);
     HIPCHECK(hipGetLastError());
 }
 

@@ -8,10 +8,10 @@ namespace saamg {
 // Scalar slots in the per-solve device array `scal`.
 enum Slot {
     S_RHO = 0, S_RHO_PREV, S_ALPHA, S_BETA, S_PQ, S_RR, S_BB, S_R0,
-    S_INVN, S_LAM, S_RT, S_NSLOTS = 16
+    S_INVN, S_LAM, S_RT, S_LZ_S, S_LZ_SP, S_LZ_B, S_NSLOTS = 16
 };
 // Finalisation ops: how the summed partials update `scal`.
-enum FinOp { FIN_STORE = 0, FIN_ALPHA, FIN_RHO_INIT, FIN_RHO, FIN_POWER, FIN_NORM, FIN_RESTORE_RHO };
+enum FinOp { FIN_STORE = 0, FIN_ALPHA, FIN_RHO_INIT, FIN_RHO, FIN_LZ_ALPHA, FIN_LZ_BETA, FIN_NORM, FIN_RESTORE_RHO };
 // Chebyshev step kinds.
 enum ChebMode { CHEB_ZERO1 = 0, CHEB_ZERO2, CHEB_FIRST, CHEB_NEXT };
 
@@ -35,9 +35,11 @@ void l0_unknown_list(const FineLevel& L, long* out, hipStream_t s);  // requires
 // ---- level 0: operators
 template <typename T>
 void l0_apply(const FineLevel& L, bool trans, const T* x, T* y, hipStream_t s);
-void l0_power_start(const FineLevel& L, double* v, hipStream_t s);
-void l0_power_step(const FineLevel& L, const double* v, const double* scal, double* w,
-                   double* partials, hipStream_t s);
+void l0_lz_start(const FineLevel& L, double* v, double* partials, hipStream_t s);
+void l0_lz_apply(const FineLevel& L, bool sym, const double* v, const double* scal, double* u,
+                 double* partials, hipStream_t s);
+void l0_lz_update(const FineLevel& L, const double* u, const double* cur, double* prev,
+                  const double* scal, double* partials, hipStream_t s);
 // fdot: fp64 operand of the fused dot (partials of fdot . xout), used when dot is set
 template <typename TF, typename T>
 void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* din, T* xout,
@@ -74,9 +76,11 @@ void l0_dot(const FineLevel& L, const double* a, const T* b, double* partials, h
 // ---- levels >= 1
 template <typename T>
 void lc_apply(const CoarseLevel& C, bool trans, const T* x, T* y, hipStream_t s);
-void lc_power_start(const CoarseLevel& C, double* v, hipStream_t s);
-void lc_power_step(const CoarseLevel& C, const double* v, const double* scal, double* w,
-                   double* partials, hipStream_t s);
+void lc_lz_start(const CoarseLevel& C, double* v, double* partials, hipStream_t s);
+void lc_lz_apply(const CoarseLevel& C, const double* v, const double* scal, double* u,
+                 double* partials, hipStream_t s);
+void lc_lz_update(const CoarseLevel& C, const double* u, const double* cur, double* prev,
+                  const double* scal, double* partials, hipStream_t s);
 template <typename T>
 void lc_cheb(const CoarseLevel& C, int mode, const T* f, const T* xin, const T* din, T* xout,
              T* dout, double c1, double c2, double c2_0, hipStream_t s);

@@ -387,35 +387,86 @@ static void state_fill_result(const saamg_state* S, saamg_result* res) {
 
 static long seg_count(int nx, int ny, int nz) { return (long)((nx + 63) / 64) * ny * nz; }
 
-static void power_lambda(saamg_hierarchy* H, int l, hipStream_t s, double* out_lam) {
+// Largest eigenvalue of the symmetric tridiagonal matrix with diagonal a[0..m-1] and
+// off-diagonal b[0..m-2], by bisection on Sturm sequence counts.
+static double tridiag_max_eig(const double* a, const double* b, int m) {
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    // number of eigenvalues below x = number of negative pivots of T - x I
+    auto below = [&](double x) {
+        int cnt = 0;
+        double d = 1.0;
+        for (int i = 0; i < m; ++i) {
+            d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0.0) ++cnt;
+        }
+        return cnt;
+    };
+    for (int it = 0; it < 200 && hi - lo > 2e-16 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (below(mid) == m)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Upper end of the spectrum of D^-1 A on level l (the bound that the Chebyshev and the
+// prolongator smoothers need, Section 3.2): the largest Ritz value of Lanczos steps in
+// the D inner product on the symmetric part (A + A^T)/2, started from the SplitMix64
+// vector of the box index.  The recurrence ends early when beta_k <= 1e-12 max|alpha|,
+// and runs at most n steps on a level with n unknowns.
+static double lanczos_lambda(saamg_hierarchy* H, int l, hipStream_t s) {
     const long n = (l == 0) ? H->l0.nbox : H->lc[l - 1].nstore;
     const long nb = (l == 0) ? l0_blocks(H->l0) : lc_blocks(H->lc[l - 1]);
-    double* v = (double*)dmalloc(8 * n);
-    double* w = (double*)dmalloc(8 * n);
-    double* part = (double*)dmalloc(sizeof(double) * 3 * nb);
-    double* scal = (double*)dmalloc(sizeof(double) * S_NSLOTS);
-    const double one = 1.0;
-    HIPCHECK(hipMemcpy(scal + S_INVN, &one, sizeof(double), hipMemcpyHostToDevice));
+    const long n_unk = (l == 0) ? H->l0.n_unknowns : H->lc[l - 1].n_unknowns;
+    const int K = (int)std::min<long>(H->opt.eig_iters, n_unk);
+    double* cur = (double*)dmalloc(8 * n);
+    double* prev = (double*)dmalloc(8 * n);
+    double* u = (double*)dmalloc(8 * n);
+    double* part = (double*)dmalloc(sizeof(double) * nb);
+    double* scal = (double*)dmalloc(sizeof(double) * (S_NSLOTS + 2 * K));
     if (l == 0)
-        l0_power_start(H->l0, v, s);
+        l0_lz_start(H->l0, cur, part, s);
     else
-        lc_power_start(H->lc[l - 1], v, s);
-    for (int it = 0; it < H->opt.eig_iters; ++it) {
+        lc_lz_start(H->lc[l - 1], cur, part, s);
+    finalize(part, nb, 1, scal, FIN_NORM, 0, s);
+    for (int k = 0; k < K; ++k) {
         if (l == 0)
-            l0_power_step(H->l0, v, scal, w, part, s);
+            l0_lz_apply(H->l0, H->sym, cur, scal, u, part, s);
         else
-            lc_power_step(H->lc[l - 1], v, scal, w, part, s);
-        finalize(part, nb, 3, scal, FIN_POWER, 0, s);
-        std::swap(v, w);
+            lc_lz_apply(H->lc[l - 1], cur, scal, u, part, s);
+        finalize(part, nb, 1, scal, FIN_LZ_ALPHA, S_NSLOTS + k, s);
+        if (l == 0)
+            l0_lz_update(H->l0, u, cur, prev, scal, part, s);
+        else
+            lc_lz_update(H->lc[l - 1], u, cur, prev, scal, part, s);
+        finalize(part, nb, 1, scal, FIN_LZ_BETA, S_NSLOTS + K + k, s);
+        std::swap(cur, prev);
     }
-    double lam = 0;
-    HIPCHECK(hipMemcpyAsync(&lam, scal + S_LAM, sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> ab(2 * K);
+    HIPCHECK(hipMemcpyAsync(ab.data(), scal + S_NSLOTS, sizeof(double) * 2 * K,
+                            hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
-    dfree(v);
-    dfree(w);
-    dfree(part);
-    dfree(scal);
-    *out_lam = lam;
+    for (void* p : {(void*)cur, (void*)prev, (void*)u, (void*)part, (void*)scal}) dfree(p);
+    const double* alpha = ab.data();
+    const double* beta = ab.data() + K;
+    int m = 0;
+    double amax = 0.0;
+    while (m < K) {
+        amax = std::max(amax, std::fabs(alpha[m]));
+        ++m;
+        if (beta[m - 1] <= 1e-12 * amax) break;
+    }
+    for (int k = 0; k < m; ++k)
+        if (!std::isfinite(alpha[k]) || !std::isfinite(beta[k])) return NAN;
+    return tridiag_max_eig(alpha, beta, m);
 }
 
 static CoarseLevel make_coarse(int fmx, int fmy, int fmz, int sym) {
@@ -599,9 +650,9 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
         while (n_cur > o.max_coarse && H->n_levels < o.max_levels) {
             const int l = H->n_levels - 1;
             LevelParams P;
-            power_lambda(H, l, s, &P.lam);
+            P.lam = lanczos_lambda(H, l, s);
             if (!(P.lam > 0) || !std::isfinite(P.lam))
-                throw ApiError{SAAMG_HIP_ERROR, "power iteration failed on level " + std::to_string(l)};
+                throw ApiError{SAAMG_HIP_ERROR, "spectral estimate failed on level " + std::to_string(l)};
             P.lam_hi = o.cheb_boost * P.lam;
             P.omega = o.omega_scale / P.lam;
             P.cheb = cheb_coefficients(P.lam_hi, o.cheb_ratio, o.cheb_degree);
