@@ -28,7 +28,7 @@ namespace saamg {
 constexpr int kWave = 64;
 constexpr int kBlockY = 4;          // 64 x 4 threads per block for box kernels
 constexpr int kThreads = kWave * kBlockY;
-constexpr int kMY = 4;              // lines per block of the level-0 solve-time kernels
+constexpr int kMY = 4;              // wavefronts per block of the level-0 solve-time kernels
 constexpr int kMThreads = kWave * kMY;
 constexpr int kFinThreads = 1024;   // single-block finalisation of partial sums
 
@@ -40,7 +40,8 @@ __host__ __device__ constexpr int dir_to_k(int d) {
 template <typename T>
 struct L0View {
     int nx, ny, nz, nsegx;
-    int gy, zb;         // solve-time tiling: line groups of 4, planes per block
+    int tx, gx, gy, zb; // solve-time tiling: segments per block along x, block columns,
+                        // block rows (kMY / tx lines each), planes per block
     long nxy;
     const uint64_t* unk;
     const uint64_t* irr;
@@ -199,11 +200,17 @@ struct saamg_hierarchy {
 };
 
 namespace saamg {
+// Segments of one line that a block of the level-0 solve-time kernels covers (its other
+// wavefronts take the next lines): whole 256-node lines where the box is wide enough.
+inline int l0_tile_x(int nsegx) { return nsegx >= kMY ? kMY : (nsegx >= 2 ? 2 : 1); }
+
 template <typename T>
 inline L0View<T> FineLevel::view() const {
     L0View<T> v;
     v.nx = nx; v.ny = ny; v.nz = nz; v.nsegx = nsegx; v.nxy = nxy;
-    v.gy = (ny + kMY - 1) / kMY;
+    v.tx = l0_tile_x(nsegx);
+    v.gx = (nsegx + v.tx - 1) / v.tx;
+    v.gy = (ny + kMY / v.tx - 1) / (kMY / v.tx);
     v.zb = zb;
     v.unk = unk; v.irr = irr; v.base = base;
     for (int d = 0; d < 6; ++d) {

@@ -1,15 +1,16 @@
 // Level-0 (lattice) kernels: operator build, stencils, Chebyshev steps, transfer
 // operators to level 1, and the fused fp64 CG vector kernels.
 //
-// Solve-time kernels use one mapping: a block of 64 x 4 threads owns a tile of one
-// 64-node x-segment by 4 lines and marches along z through `zb` planes.  One wavefront
-// is one segment row, so segment masks are wave-uniform (scalar loads) and empty
-// segments are skipped.  Along z each lane carries its column (z-1, z, z+1) in
-// registers; x-neighbours come from adjacent lanes, y-neighbours from L1/L2.  Block
-// numbers are remapped so that the blocks dispatched to one XCD form a contiguous
-// z-slab of tiles (the chip hands out blocks round-robin over its 8 XCDs, each with its
-// own L2).  Kernels write only unknown nodes; every level-0 work vector is zero at
-// the other nodes from allocation on.
+// Solve-time kernels use one mapping: every wavefront owns one 64-node x-segment of one
+// line and marches along z through `zb` planes.  A block of 4 wavefronts takes 4
+// consecutive segments of one line (the whole 256-node line of the large grids; 2 x 2
+// or 1 x 4 on narrow boxes), so each plane of a block is one contiguous run of memory.
+// Segment masks are wave-uniform (scalar values) and empty segments are skipped.  Along
+// z each lane carries its column (z-1, z, z+1) in registers; x-neighbours come from
+// adjacent lanes, y-neighbours from L1/L2.  Block numbers are remapped so that the
+// blocks dispatched to one XCD form a contiguous z-slab of tiles (the chip hands out
+// blocks round-robin over its 8 XCDs, each with its own L2).  Kernels write only
+// unknown nodes; every level-0 work vector is zero at the other nodes from allocation on.
 #include "launch.h"
 
 namespace saamg {
@@ -28,17 +29,20 @@ static inline long l0_meta_bytes(const FineLevel& L, int wsize, bool trans_too) 
 }
 
 // Planes per block for the solve-time kernels: long z-marches, but enough blocks to
-// fill the chip.
+// fill the chip a few times over.
+constexpr long kMinBlocks = 8192;
 int l0_choose_zb(int nsegx, int ny, int nz) {
-    const long tiles = (long)nsegx * ((ny + kMY - 1) / kMY);
+    const int tx = l0_tile_x(nsegx), ty = kMY / tx;
+    const long tiles = (long)((nsegx + tx - 1) / tx) * ((ny + ty - 1) / ty);
     int zb = 32;
-    while (zb > 2 && tiles * ((nz + zb - 1) / zb) < 8192) zb /= 2;
+    while (zb > 2 && tiles * ((nz + zb - 1) / zb) < kMinBlocks) zb /= 2;
     return zb;
 }
 
 long l0_blocks(const FineLevel& L) {
-    const long gy = (L.ny + kMY - 1) / kMY;
-    return (long)L.nsegx * gy * ((L.nz + L.zb - 1) / L.zb);
+    const int tx = l0_tile_x(L.nsegx), ty = kMY / tx;
+    const long gx = (L.nsegx + tx - 1) / tx, gy = (L.ny + ty - 1) / ty;
+    return gx * gy * ((L.nz + L.zb - 1) / L.zb);
 }
 
 static inline dim3 l0_mgrid(const FineLevel& L) { return dim3((unsigned)l0_blocks(L)); }
@@ -83,15 +87,17 @@ __device__ inline L0Node l0_node(const L0View<T>& v, int x, int y, int z) {
 
 // ---------------------------------------------------------------- solve-time engine
 
-// Tile of this block after the XCD-aware remap.
+// Segment, line and z-slab of this wavefront: the block's tile (after the XCD-aware
+// remap) holds tx consecutive segments of kMY / tx consecutive lines.
 template <typename T>
-__device__ inline void l0_tile(const L0View<T>& v, int* bx, int* by, int* bz) {
+__device__ inline void l0_tile(const L0View<T>& v, int* seg, int* y, int* bz) {
     const long b = blockIdx.x, nb = gridDim.x;
     const long q = nb >> 3;
     const long lb = (b < 8 * q) ? (b & 7) * q + (b >> 3) : b;
-    *bx = (int)(lb % v.nsegx);
-    const long t = lb / v.nsegx;
-    *by = (int)(t % v.gy);
+    const int w = threadIdx.y;
+    const long t = lb / v.gx;
+    *seg = (int)(lb % v.gx) * v.tx + w % v.tx;
+    *y = (int)(t % v.gy) * (kMY / v.tx) + w / v.tx;
     *bz = (int)(t / v.gy);
 }
 
@@ -102,37 +108,54 @@ __device__ inline uint64_t lane_u64(uint64_t v, int k) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// March over this block's tile.  For every unknown node the march calls
-//   fv = fetch(i, x, y, z, irr, rk)            (issued one plane ahead)
+// March over this block's tile.  One wavefront owns one 64-node segment row and walks
+// it along z.  For every unknown node the march calls
+//   fv = fetch(i, x, y, z, irr, rk)            (loads, issued one plane ahead)
 //   body(i, fv, c, ax, x, y, z, irr, rk)       (arithmetic and stores)
 // with the box index i, coordinates, irregular flag and table slot, the input value
-// c = X(i) and, when STENCIL, ax = (A X)_i (TR: A^T X) of the scaled operator.  X(j)
-// must be zero at nodes that are not unknowns, so a segment row without unknowns
-// contributes zeros without being read.  The segment words of planes z0-1 .. z1 are
-// fetched up front (one plane per lane) and broadcast per step.  The loads of plane z+1
-// are issued before the arithmetic of plane z (software pipelining), which doubles the
-// bytes each wavefront keeps in flight at little register cost.
-template <typename T, class FV>
+// c = X(i) and, when STENCIL, ax = (A X)_i (TR: A^T X) of the scaled operator, computed
+// in T from the values X returns (X may return a narrower type).  X must be zero at
+// nodes that are not unknowns.  The segment words of planes z0-1 .. z1 are fetched up
+// front (one plane per lane) and broadcast per step; a row without unknowns in the tile
+// exits at once.
+//
+// Every load of a plane is issued unconditionally, so the loads of plane z+1 are all in
+// flight while plane z is computed and a wavefront waits for one memory round trip per
+// plane.  To keep those loads from touching lines the row does not need, a lane outside
+// the span [first, last unknown] of its row in that plane reads at the nearest end of
+// the span instead (fetch then sees that node's index and coordinates); such values are
+// never used by the lane itself and are replaced by zero before they serve as a
+// neighbour's x- or z-neighbour.  x-neighbours come from adjacent lanes (the two edge
+// lanes read theirs with the same load instruction), z-neighbours from registers,
+// y-neighbours from L1/L2.
+template <typename T, typename TX, class FV>
 struct PlaneLoads {
     uint64_t u;   // unknown bits of the segment row
     bool irr;
+    bool ins1;    // lane inside the row's unknown span in plane z+1
     int rk;
-    T nxt, ym, yp, edge;  // X at (x, y, z+1), (x, y-1, z), (x, y+1, z), lane-edge x-neighbour
+    TX nxt, ym, yp, edge;  // X at (x, y, z+1), (x, y-1, z), (x, y+1, z), lane-edge x-neighbour
+    T t[6];                // table row of an irregular node
     FV fv;
 };
 
+// Lane clamped to the span of the set bits of u (u == 0: lane 0).
+__device__ inline int span_lane(uint64_t u, int lane) {
+    const int lo = u ? (int)__builtin_ctzll(u) : 0;
+    const int hi = u ? 63 - (int)__builtin_clzll(u) : 0;
+    return min(max(lane, lo), hi);
+}
+
 template <typename T, bool STENCIL, bool TR, class Load, class Fetch, class Body>
 __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch, Body body) {
-    // fp64 kernels carry twice the register payload per plane; they run unpipelined
-    constexpr bool kPipe = sizeof(T) == 4;
     using FV = decltype(fetch(0L, 0, 0, 0, false, 0));
-    int bx, by, bz;
-    l0_tile(v, &bx, &by, &bz);
+    using TX = decltype(X(0L));
+    int bx, y, bz;
+    l0_tile(v, &bx, &y, &bz);
     const int lane = threadIdx.x;
-    const int x = bx * kWave + lane;
-    const int y = __builtin_amdgcn_readfirstlane(by * kMY + (int)threadIdx.y);
-    if (y < 1 || y > v.ny - 2) return;
-    const bool inx = x < v.nx;
+    bx = __builtin_amdgcn_readfirstlane(bx);
+    y = __builtin_amdgcn_readfirstlane(y);
+    if (y < 1 || y > v.ny - 2 || bx >= v.nsegx) return;
     const int z0 = max(bz * v.zb, 1), z1 = min(bz * v.zb + v.zb, v.nz - 1);
     if (z0 >= z1) return;
     const long nx = v.nx, nxy = v.nxy;
@@ -146,40 +169,54 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
         wr = v.irr[sg];
         wb = v.base[sg];
     }
-    const long ib = x + nx * y;  // box index of this lane at plane 0
+    if (__ballot(wu != 0) == 0) return;
+    const int x0 = bx * kWave;
+    const long rb = x0 + nx * y;  // box index of lane 0 at plane 0
+    const long eo = lane == 0 ? -1 : (lane == kWave - 1 ? 1 : 0);
+    // X of this lane in plane q (k = q - (z0 - 1)), read inside the plane's span
+    auto load_x = [&](int k, long q) {
+        return X(rb + nxy * q + span_lane(lane_u64(wu, k), lane));
+    };
     auto load_plane = [&](int q) {
-        PlaneLoads<T, FV> P;
+        PlaneLoads<T, TX, FV> P;
         const int k = q - (z0 - 1);
         P.u = lane_u64(wu, k);
         const uint64_t r = lane_u64(wr, k);
+        const int lc = span_lane(P.u, lane);
+        const bool ins = lc == lane;
+        P.ins1 = span_lane(lane_u64(wu, k + 1), lane) == lane;
         P.irr = (r >> lane) & 1ull;
         P.rk = P.irr ? __builtin_amdgcn_readlane(wb, k) + __popcll(r & ((1ull << lane) - 1ull)) : 0;
-        P.nxt = P.ym = P.yp = P.edge = T(0);
-        const long i = ib + nxy * q;
-        const bool unk = (P.u >> lane) & 1ull;
-        if (unk) P.fv = fetch(i, x, y, q, P.irr, P.rk);
+        const long i = rb + nxy * q + lc;
+        P.fv = fetch(i, x0 + lc, y, q, P.irr, P.rk);
         if (STENCIL) {
-            if (inx && lane_u64(wu, k + 1) != 0) P.nxt = X(i + nxy);
-            if (unk) {
-                P.ym = X(i - nx);
-                P.yp = X(i + nx);
-                if (lane == 0) P.edge = X(i - 1);
-                if (lane == kWave - 1) P.edge = X(i + 1);
+            P.nxt = load_x(k + 1, q + 1);
+            P.ym = X(i - nx);
+            P.yp = X(i + nx);
+            P.edge = X(i + (ins ? eo : 0));
+            // rows with an irregular node: every lane reads a table row (slot 0 if regular)
+            if (r != 0) {
+#pragma unroll
+                for (int d = 0; d < 6; ++d) P.t[d] = tb[d][P.rk];
             }
         }
         return P;
     };
-    T zm = 0, c = 0;
-    if (STENCIL && inx) {
-        if (lane_u64(wu, 0) != 0) zm = X(ib + nxy * (z0 - 1));
-        if (lane_u64(wu, 1) != 0) c = X(ib + nxy * z0);
+    TX zm = TX(0), c = TX(0);
+    if (STENCIL) {
+        zm = load_x(0, z0 - 1);
+        c = load_x(1, z0);
+        if (span_lane(lane_u64(wu, 0), lane) != lane) zm = TX(0);
+        if (span_lane(lane_u64(wu, 1), lane) != lane) c = TX(0);
     }
-    PlaneLoads<T, FV> cur = load_plane(z0);
+    PlaneLoads<T, TX, FV> cur = load_plane(z0);
     for (int z = z0; z < z1; ++z) {
-        PlaneLoads<T, FV> nxtp;
-        if (kPipe && z + 1 < z1) nxtp = load_plane(z + 1);
+        // the last step reloads its own plane instead of reading past the tile
+        const PlaneLoads<T, TX, FV> nxtp = load_plane(z + 1 < z1 ? z + 1 : z);
+        // X at (x, y, z+1); zero where that plane's span does not reach
+        const TX zp = (STENCIL && cur.ins1) ? cur.nxt : TX(0);
         if (cur.u != 0) {
-            T xm = T(0), xp = T(0);
+            TX xm = TX(0), xp = TX(0);
             if (STENCIL) {
                 xm = __shfl_up(c, 1, kWave);
                 xp = __shfl_down(c, 1, kWave);
@@ -187,29 +224,26 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
                 if (lane == kWave - 1) xp = cur.edge;
             }
             if ((cur.u >> lane) & 1ull) {
-                const long i = ib + nxy * z;
+                const long i = rb + nxy * z + lane;
                 const int r = cur.rk;
                 T ax = T(0);
                 if (STENCIL) {
                     if (!cur.irr) {
-                        ax = c + v.c[0] * (xm + xp) + v.c[1] * (cur.ym + cur.yp) +
-                             v.c[2] * (zm + cur.nxt);
+                        ax = T(c) + v.c[0] * (T(xm) + T(xp)) + v.c[1] * (T(cur.ym) + T(cur.yp)) +
+                             v.c[2] * (T(zm) + T(zp));
                     } else {
-                        ax = c + tb[0][r] * xm + tb[1][r] * xp + tb[2][r] * cur.ym +
-                             tb[3][r] * cur.yp + tb[4][r] * zm + tb[5][r] * cur.nxt;
+                        ax = T(c) + cur.t[0] * T(xm) + cur.t[1] * T(xp) + cur.t[2] * T(cur.ym) +
+                             cur.t[3] * T(cur.yp) + cur.t[4] * T(zm) + cur.t[5] * T(zp);
                     }
                 }
-                body(i, cur.fv, c, ax, x, y, z, cur.irr, r);
+                body(i, cur.fv, T(c), ax, x0 + lane, y, z, cur.irr, r);
             }
         }
         if (STENCIL) {
             zm = c;
-            c = cur.nxt;
+            c = zp;
         }
-        if (kPipe)
-            cur = nxtp;
-        else if (z + 1 < z1)
-            cur = load_plane(z + 1);
+        cur = nxtp;
     }
 }
 
@@ -585,8 +619,9 @@ __global__ void __launch_bounds__(kMThreads) k_l0_lz_apply(L0View<double> v,
     const long nx = v.nx, nxy = v.nxy;
     double a0 = 0.0;
     l0_march<double, true, false>(
-        v, [&](long j) { return vin[j] * sc; }, NOFETCH,
-        [&](long i, NoVals, double q, double aq, int, int, int, bool irr, int r) {
+        v, [&](long j) { return vin[j]; }, NOFETCH,
+        [&](long i, NoVals, double qr, double aqr, int, int, int, bool irr, int r) {
+            const double q = sc * qr, aq = sc * aqr;
             double o = aq;
             if (!SYM && irr) {
                 const double at = q + sc * (v.tabT[0][r] * vin[i - 1] + v.tabT[1][r] * vin[i + 1] +
@@ -655,7 +690,7 @@ __global__ void __launch_bounds__(kMThreads) k_l0_cheb(L0View<T> v, const TF* __
     double acc = 0.0;
     auto fetch = [&](long i, int, int, int, bool, int) {
         Vals<T, 2> a;
-        a.v[0] = (T)f[i];
+        a.v[0] = (MODE == CHEB_FIRST || MODE == CHEB_NEXT || MODE == CHEB_ZERO1) ? (T)f[i] : T(0);
         a.v[1] = (MODE == CHEB_NEXT) ? din[i] : T(0);
         Vals<double, 1> b;
         b.v[0] = DOT ? fdot[i] : 0.0;
@@ -671,9 +706,10 @@ __global__ void __launch_bounds__(kMThreads) k_l0_cheb(L0View<T> v, const TF* __
         if (MODE == CHEB_ZERO1) {
             xo = c20 * fi;
             dn = xo;
-        } else if (MODE == CHEB_ZERO2) {
-            dn = c1 * cv + c2 * (fi - ax);
-            xo = cv + dn;
+        } else if (MODE == CHEB_ZERO2) {  // cv = f_i, ax = (A f)_i
+            const T x1 = c20 * cv;
+            dn = c1 * x1 + c2 * (cv - c20 * ax);
+            xo = x1 + dn;
         } else {
             const T r = fi - ax;
             dn = (MODE == CHEB_FIRST) ? c20 * r : c1 * fv.a.v[1] + c2 * r;
@@ -686,7 +722,7 @@ __global__ void __launch_bounds__(kMThreads) k_l0_cheb(L0View<T> v, const TF* __
     if (MODE == CHEB_ZERO1)
         l0_march<T, false, false>(v, [&](long) { return T(0); }, fetch, body);
     else if (MODE == CHEB_ZERO2)
-        l0_march<T, true, false>(v, [&](long j) { return c20 * (T)f[j]; }, fetch, body);
+        l0_march<T, true, false>(v, [&](long j) { return (T)f[j]; }, fetch, body);
     else
         l0_march<T, true, false>(v, [&](long j) { return xin[j]; }, fetch, body);
     if (DOT) {
@@ -921,7 +957,7 @@ __global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ*
     const double beta = scal[S_BETA];
     double acc = 0.0;
     l0_march<double, true, false>(
-        v, [&](long j) { return (double)zv[j]; },
+        v, [&](long j) { return zv[j]; },
         [&](long i, int, int, int, bool, int) { return Vals<double, 2>{{p[i], q[i]}}; },
         [&](long i, Vals<double, 2> f, double zi, double az, int, int, int, bool, int) {
             const double pi = zi + beta * f.v[0];

@@ -103,6 +103,7 @@ class GpuEngine:
             x = self.torch.zeros(h["b"].numel(), dtype=self.torch.float64, device=self.dev)
             self.torch.cuda.synchronize(self.dev)  # the fill is done before the state's stream writes x
             capi.state_finish(h["S"], x)
+            self.torch.cuda.synchronize(self.dev)  # the finish ran on the state's stream
             x = x.cpu().numpy()
         capi.state_destroy(h["S"])
         self._streams.append(h["stream"])

@@ -268,6 +268,8 @@ def test_batched_states_equal_alone():
         done, res = sa.state_query(st)
         assert done and res["status"] == 0
         x = torch.zeros(np.prod(c.dims), dtype=torch.float64, device=_dev())
+        torch.cuda.synchronize()  # the fill runs on torch's stream, the finish on the state's
         sa.state_finish(st, x)
+        torch.cuda.synchronize()
         assert np.array_equal(x.cpu().numpy().reshape(c.dims[::-1]), xa)
         sa.state_destroy(st)
