@@ -13,7 +13,7 @@ Paper, Section 3.2 and Table 1:
 * the coarsest level (at most ``max_coarse`` = 1000 unknowns) is solved directly;
 * the cycle is the V-cycle of Algorithm 1.
 
-Readings where the paper is silent (listed in the design doc):
+Readings where the paper is silent:
 
 * aggregates are the index blocks [3I, 3I+3) x [3J, 3J+3) x [3K, 3K+3) of the level's
   logical box; a block's unknowns form one aggregate, partial blocks are kept; the

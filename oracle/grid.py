@@ -6,7 +6,7 @@ domain.  For a point x next to the curved wall, the wall point between x and its
 outside neighbour x' = x - h e_i is x* = x - s h e_i with 0 < s <= 1 (Figure
 "boundary"); s = 1 means x' itself lies on the wall.
 
-Readings (listed in DESIGN.md):
+Readings where the paper leaves a choice open:
 * the lattice spans the bounding box of the pipe with n nodes per axis, both ends
   included, so h = extent / (n - 1); node i of an axis of half-extent a sits at
   a * (2 i - (n - 1)) / (n - 1);

@@ -5,7 +5,7 @@ nonsymmetric matrix of the quadratic wall rule; Section 3.2: preconditioned by o
 AMG V-cycle per step; Section 5 (solver comparison): stop when
 ||r||_2 <= eps ||b||_2.
 
-Readings (listed in the design doc): the residual and right-hand side in the stopping test
+Readings where the paper leaves a choice open: the residual and right-hand side in the stopping test
 are those of the scaled system; beta is the Fletcher-Reeves / Hestenes-Stiefel ratio
 (r_new . z_new) / (r . z); when the recursively updated residual passes the test the
 true residual b - A x is formed, and the iteration stops only if it passes too,

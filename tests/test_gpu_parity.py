@@ -1,12 +1,14 @@
 """GPU parity: every step of the HIP path against the CPU oracle, through the C-ABI.
 
-Tolerances (derivations in the design doc):
+Tolerances:
 * fp64 components (operator, Galerkin coefficients, smoother, transfers, V-cycle):
-  1e-12 relative (only the summation order differs);
+  1e-12 relative (only the summation order differs, over at most a few hundred terms
+  of bounded size);
 * fp64 PCG solution: 1e-8 relative to the oracle's solution of the same algorithm, and
   the same iteration count +-1;
-* mixed precision (fp32 hierarchy and V-cycle): components 1e-4 relative, full solve
-  1e-6 relative to the oracle's solution driven to 1e-13.
+* mixed precision (fp32 hierarchy and V-cycle): components 1e-4 relative (fp32 unit
+  roundoff 6e-8 times the operator's condition growth over a few chained products),
+  full solve 1e-6 relative to the oracle's solution driven to 1e-13.
 """
 import numpy as np
 import pytest

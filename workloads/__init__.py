@@ -189,8 +189,8 @@ def rhs(w: Workload, shift_z: float = 0.0, particles: Optional[np.ndarray] = Non
 
 
 # ----------------------------------------------------------------------------------
-# Named workloads.  Sizes follow the problem statements they stand for; see the design doc
-# for how each recipe was read.
+# Named workloads.  Sizes follow the problem statements they stand for; each
+# docstring gives the recipe.
 # ----------------------------------------------------------------------------------
 
 def c1_cylinder33() -> Workload:
