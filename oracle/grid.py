@@ -27,6 +27,7 @@ import numpy as np
 
 CYLINDER, ELLIPSE, BOXBORE = 0, 1, 2
 S_SNAP = 1e-12
+ON_WALL = 1e-12  # a point inside only by this relative margin lies on the wall
 
 # Direction order used for wall fractions: -x, +x, -y, +y, -z, +z.
 DIRS = ((-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1))
@@ -60,10 +61,14 @@ def coords(half: float, n: int) -> np.ndarray:
 
 def _inside_xy(kind: int, a: float, b: float, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
     if kind == CYLINDER:
-        return X * X + Y * Y < a * a
+        return X * X + Y * Y < a * a * (1.0 - ON_WALL)
     if kind == ELLIPSE:
-        return (X / a) ** 2 + (Y / b) ** 2 < 1.0
+        return (X / a) ** 2 + (Y / b) ** 2 < 1.0 - ON_WALL
     raise ValueError(kind)
+
+
+def _in_bore(X: np.ndarray, Y: np.ndarray, r: float) -> np.ndarray:
+    return X * X + Y * Y < r * r * (1.0 - ON_WALL)
 
 
 def build(kind: int, a: float, b: float, length: float, nx: int, ny: int, nz: int,
@@ -79,8 +84,9 @@ def build(kind: int, a: float, b: float, length: float, nx: int, ny: int, nz: in
     if kind in (CYLINDER, ELLIPSE):
         mask = _inside_xy(kind, a, b, X, Y) & interior_idx
     elif kind == BOXBORE:
-        cav = (np.abs(X) < a) & (np.abs(Y) < b) & (np.abs(Z) < cavity_half_len)
-        bore = X * X + Y * Y < bore_r * bore_r
+        keep = 1.0 - ON_WALL
+        cav = (np.abs(X) < a * keep) & (np.abs(Y) < b * keep) & (np.abs(Z) < cavity_half_len * keep)
+        bore = _in_bore(X, Y, bore_r)
         mask = (cav | bore) & interior_idx
     else:
         raise ValueError(kind)
@@ -115,9 +121,9 @@ def _wall_fraction(kind, a, b, length, bore_r, cav_half, xs, ys, zs, h, d) -> np
         else:
             end = b * np.sqrt(np.maximum(1.0 - (xs / a) ** 2, 0.0))
     else:  # BOXBORE
-        in_cavity_z = np.abs(zs) < cav_half
+        in_cavity_z = np.abs(zs) < cav_half * (1.0 - ON_WALL)
         if axis == 2:
-            in_bore = xs * xs + ys * ys < bore_r * bore_r
+            in_bore = _in_bore(xs, ys, bore_r)
             end = np.where(in_bore, 0.5 * length, cav_half)
         else:
             other = ys if axis == 0 else xs

@@ -39,6 +39,7 @@ def test_default_options_follow_table1():
     (W.Shape.ellipse(1.0, 0.6, 4.0), 64, 96),
     (W.Shape.boxbore(0.8, 4.0, 0.5), 47, 93),
     (W.Shape.cylinder(0.5, 1.0), 65, 65),
+    (W.Shape.cylinder(1.0, 6.0), 83, 9),  # lattice points exactly on the wall
 ])
 def test_domain_builder_matches_oracle(shape, n, nz):
     d = sa.domain_for(shape, n, n, nz)

@@ -25,6 +25,18 @@ def test_paper_dof_counts_cross_section():
     assert grid.cross_section_count(0, 1.0, 1.0, 166, 166) * 256 == g["mesh_166x166x256"]
 
 
+def test_lattice_point_on_the_wall_is_not_an_unknown():
+    """On 83 nodes per axis of the unit disc, (9/41, 40/41) lies exactly on r = 1 (a
+    Pythagorean triple); it is a wall point, not an unknown, and every neighbouring unknown
+    has a positive wall fraction."""
+    from fractions import Fraction
+    xi, yj = Fraction(2 * 50 - 82, 82), Fraction(2 * 81 - 82, 82)
+    assert xi * xi + yj * yj == 1
+    dom = grid.from_shape(W.Shape.cylinder(1.0, 6.0), 83, 83, 9)
+    assert not dom.mask[4, 81, 50] and not dom.mask[4, 50, 81]
+    assert dom.mask[4, 80, 50] and np.all(dom.frac[:, dom.mask] > 0.0)
+
+
 def test_cylinder33_unknowns():
     w = W.c1_cylinder33()
     assert grid.from_shape(w.shape, 33, 33, 33).n_unknowns == 24583
