@@ -12,22 +12,29 @@
 
 namespace {
 
-constexpr double kSnap = 1e-12;  // fractions within kSnap of 1 are taken as 1
+constexpr double kSnap = 1e-12;    // fractions within kSnap of 1 are taken as 1
+constexpr double kOnWall = 1e-12;  // a point inside only by this relative margin is on the wall
 
 struct Pipe {
     int kind;
     double a, b, len, bore_r, cav;
 
-    // strict interior test of the continuous pipe (the caps at |z| = len/2 excluded)
+    bool in_bore(double x, double y) const { return x * x + y * y < bore_r * bore_r * (1.0 - kOnWall); }
+    bool in_cavity_z(double z) const { return std::fabs(z) < cav * (1.0 - kOnWall); }
+
+    // strict interior test of the continuous pipe (the caps at |z| = len/2 excluded); a
+    // point that passes only by rounding lies on the wall and is outside
     bool inside(double x, double y, double z) const {
+        const double keep = 1.0 - kOnWall;
         switch (kind) {
             case SAAMG_SHAPE_CYLINDER:
-                return x * x + y * y < a * a;
+                return x * x + y * y < a * a * keep;
             case SAAMG_SHAPE_ELLIPSE:
-                return (x / a) * (x / a) + (y / b) * (y / b) < 1.0;
+                return (x / a) * (x / a) + (y / b) * (y / b) < keep;
             default: {
-                const bool cavity = std::fabs(x) < a && std::fabs(y) < b && std::fabs(z) < cav;
-                return cavity || x * x + y * y < bore_r * bore_r;
+                const bool cavity =
+                    std::fabs(x) < a * keep && std::fabs(y) < b * keep && in_cavity_z(z);
+                return cavity || in_bore(x, y);
             }
         }
     }
@@ -36,8 +43,8 @@ struct Pipe {
     // along `axis` (the interval is symmetric about the pipe axis).
     double half_interval(int axis, double x, double y, double z) const {
         if (kind == SAAMG_SHAPE_BOXBORE) {
-            if (axis == 2) return (x * x + y * y < bore_r * bore_r) ? 0.5 * len : cav;
-            if (std::fabs(z) < cav) return axis == 0 ? a : b;
+            if (axis == 2) return in_bore(x, y) ? 0.5 * len : cav;
+            if (in_cavity_z(z)) return axis == 0 ? a : b;
             const double o = axis == 0 ? y : x;
             return std::sqrt(std::fmax(bore_r * bore_r - o * o, 0.0));
         }
