@@ -7,8 +7,14 @@ preconditioner" mode), on the 256 x 256 x 768 elliptic pipe (semi-axes 1.0 x 0.6
 length 4, 39.1M unknowns, quadratic wall rule) with a seeded 1M-particle Gaussian
 bunch deposited by cloud-in-cell.  The headline value is DOF*iter/s of the mixed
 path (fp32 hierarchy / fp64 CG); the all-fp64 path is run on the same right-hand side
-and reported beside it.  Setup time is reported separately (the paper's
-"construction").
+and reported beside it, and a short served stream of mixed pipe requests (Poisson
+arrivals) gives p50/p99 latency for both precisions.  Setup time is reported
+separately (the paper's "construction").
+
+The roofline figure is for the kernel class with the largest share of solve time: a
+breakdown pass times every class, then the timed solves run with HIP events on that
+class only.  Its HBM traffic comes from the committed rocprofv3 counter summary when
+that summary was taken on the current kernel sources.
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -51,6 +57,10 @@ def parse():
     ap.add_argument("--pic", action="store_true",
                     help="PIC sequence: moving bunch, one hierarchy, warm-started solves")
     ap.add_argument("--pic-steps", type=int, default=20)
+    ap.add_argument("--no-serve", action="store_true",
+                    help="headline mode: skip the short served-stream leg (p50/p99 latency)")
+    ap.add_argument("--line-serve-requests", type=int, default=32,
+                    help="requests in the headline mode's served-stream leg")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="open-loop arrival rate as a fraction of the closed-loop solves/s")
     return ap.parse_args()
@@ -100,7 +110,7 @@ def pic_bench(args) -> dict:
             "max_rel_res": max(s[2] for s in steps)}
 
 
-def serve_bench(args) -> dict:
+def serve_bench(args, n_requests=None) -> dict:
     """Continuous batching over a seeded stream of pipe solves (cylinder, ellipse and
     box-with-bore; cross-section edge 32..160; length ratio 1..4).  Pass 1 admits every
     request at t = 0 (closed loop) to measure capacity; pass 2 replays Poisson arrivals at
@@ -111,7 +121,7 @@ def serve_bench(args) -> dict:
     import workloads as W
     from paper_0907_4863_amd import serve
 
-    reqs = W.serving_stream(n_requests=args.serve_requests, qps=1.0, seed=4)
+    reqs = W.serving_stream(n_requests=n_requests or args.serve_requests, qps=1.0, seed=4)
     print(f"[bench] serve: generating {len(reqs)} right-hand sides", file=sys.stderr, flush=True)
     rhs = {r.rid: W.rhs(r.workload) for r in reqs}
     dof_total = 0
@@ -139,6 +149,36 @@ def serve_bench(args) -> dict:
     out["open_loop_fp64"] = run("open-loop fp64", arr, sa.FP64)
     out["qps"] = qps
     return out
+
+
+def _kernel_sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("fine.hip", "coarse.hip", "common.h", "launch.h"):
+        with open(os.path.join(ROOT, "paper_0907_4863_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None when no summary
+    exists or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for ln in fh:
+            parts = ln.split()
+            if len(parts) == 2 and not ln.startswith("#"):
+                rec[parts[0]] = parts[1]
+    if rec.get("sources_sha256") != _kernel_sources_digest():
+        return None
+    try:
+        return float(rec["fetch_bytes_per_launch"]) + float(rec["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(w, planes: int) -> dict:
@@ -177,40 +217,57 @@ def cpu_baseline(w, planes: int) -> dict:
 
 
 def run_solves(sa, torch, H, b, nbox, steps, warmup, dev, timers: bool):
+    """Warm-up, then (timers) a per-kernel-class breakdown pass, then the timed solves.
+
+    The timed region runs with HIP-event timing on the dominant kernel class only, so its
+    average launch duration is measured live while the other launches carry no events."""
     x = torch.zeros(nbox, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         sa.solve(H, b, x, tol=1e-8, max_iter=500)
     torch.cuda.synchronize()
+
+    def read_timers(kinds):
+        out = {}
+        for k in kinds:
+            ms, n, byts = sa.capi.timer_read(k)
+            if n:
+                out[k] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / n,
+                          "alg_bytes_per_launch": byts / n,
+                          "achieved_GBs": byts / (ms * 1e-3) / 1e9 if ms > 0 else None}
+        return out
+
+    kern, dom_k = {}, None
     if timers:
         sa.capi.timer_reset()
         for k in sa.capi.TIMER_KINDS:
             sa.capi.timer_enable(k, True)
+        for _ in range(2):
+            sa.solve(H, b, x, tol=1e-8, max_iter=500)
+        torch.cuda.synchronize()
+        for k in sa.capi.TIMER_KINDS:
+            sa.capi.timer_enable(k, False)
+        kern = read_timers(sa.capi.TIMER_KINDS)
+        sa.capi.timer_reset()
+        dom_k = max(kern, key=lambda k: kern[k]["total_ms"])
+        sa.capi.timer_enable(dom_k, True)
     iters = []
     res = None
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record(stream)
     for _ in range(steps):
         res = sa.solve(H, b, x, tol=1e-8, max_iter=500)
         iters.append(res["iterations"])
-    stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern = {}
+    live = None
     if timers:
-        for k in sa.capi.TIMER_KINDS:
-            sa.capi.timer_enable(k, False)
-        for k in sa.capi.TIMER_KINDS:
-            ms, n, byts = sa.capi.timer_read(k)
-            if n:
-                kern[k] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / n,
-                           "alg_bytes_per_launch": byts / n,
-                           "achieved_GBs": byts / (ms * 1e-3) / 1e9 if ms > 0 else None}
+        sa.capi.timer_enable(dom_k, False)
+        live = read_timers([dom_k]).get(dom_k)
+        if live is not None:
+            live["kernel"] = dom_k
         sa.capi.timer_reset()
-    return x, iters, wall, res, kern
+    return x, iters, wall, res, kern, live
 
 
 def main():
@@ -283,9 +340,9 @@ def main():
         info = sa.hierarchy_info(H)
         print(f"[bench] {tag}: setup {setup_s:.3f} s levels {info['n_unknowns']}",
               file=sys.stderr, flush=True)
-        x, iters, wall, res, kern = run_solves(sa, torch, H, b, nbox, steps, args.warmup, dev,
-                                               timers=not args.no_timers)
-        out[tag] = {"x": x, "iters": iters, "wall": wall, "res": res, "kern": kern,
+        x, iters, wall, res, kern, live = run_solves(sa, torch, H, b, nbox, steps, args.warmup,
+                                                     dev, timers=not args.no_timers)
+        out[tag] = {"x": x, "iters": iters, "wall": wall, "res": res, "kern": kern, "live": live,
                     "setup_s": setup_s, "info": info, "steps": steps}
         print(f"[bench] {tag}: {steps} solves in {wall:.3f} s, iterations {iters}",
               file=sys.stderr, flush=True)
@@ -295,7 +352,7 @@ def main():
     total_iters = sum(head["iters"])
     value = dof * total_iters / head["wall"]
     line = {
-        "metric": "DOF*iter/s at rel-res 1e-8 (fp32-AMG/fp64-CG vs fp64)",
+        "metric": "DOF\u00b7iter/s and solves/s at rel-res 1e-8 (FP32-AMG vs FP64); p50/p99 latency",
         "value": value,
         "unit": "DOF*iter/s",
         "n_gpus": 1,
@@ -329,23 +386,36 @@ def main():
             "rel_res_true": f["res"]["rel_res_true"],
         }
         line["mixed_vs_fp64_rel_err"] = float(torch.linalg.norm(xm - xf) / torch.linalg.norm(xf))
-    kern = head["kern"]
-    if kern:
-        dom_k = max(kern, key=lambda k: kern[k]["total_ms"])
-        kd = kern[dom_k]
+    kern, live = head["kern"], head["live"]
+    if live:
+        dom_k = live["kernel"]
         line["roofline"] = {
             "kernel": dom_k,
             "bound": "hbm",
-            "achieved": kd["achieved_GBs"],
+            "achieved": live["achieved_GBs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": kd["achieved_GBs"] / HBM_PEAK_GBS,
-            "traffic": None,
-            "avg_launch_us": kd["avg_us"],
-            "alg_bytes_per_launch": kd["alg_bytes_per_launch"],
+            "frac": live["achieved_GBs"] / HBM_PEAK_GBS,
+            "traffic": measured_traffic(dom_k, w.name),
+            "avg_launch_us": live["avg_us"],
+            "launches": live["launches"],
+            "alg_bytes_per_launch": live["alg_bytes_per_launch"],
         }
         line["kernels"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                                for kk, vv in v.items()} for k, v in kern.items()}
+    if not args.no_serve:
+        sv = serve_bench(args, n_requests=args.line_serve_requests)
+        m, f = sv["open_loop_mixed"], sv["open_loop_fp64"]
+        keep = ("requests", "completed", "solves_per_s", "p50_latency_ms", "p99_latency_ms",
+                "mean_iterations", "max_concurrent")
+        line["p50_latency_ms"] = m["p50_latency_ms"]
+        line["p99_latency_ms"] = m["p99_latency_ms"]
+        line["serving"] = {
+            "workload": f"served stream of {m['requests']} pipe solves (cylinder/ellipse/"
+                        f"box-with-bore, edge 32..160, ratio 1..4, linear rule), Poisson "
+                        f"arrivals at {sv['qps']:.2f}/s = {args.serve_load} x closed-loop capacity",
+            "closed_loop_mixed_solves_per_s": sv["closed_loop_mixed"]["solves_per_s"],
+            "mixed": {k: m[k] for k in keep}, "fp64": {k: f[k] for k in keep}}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_planes)

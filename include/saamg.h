@@ -186,9 +186,9 @@ int saamg_state_create(saamg_hierarchy* H, const double* d_b, const double* d_x0
 int saamg_batch_step(saamg_state* const* states, int n, int* n_done_out);
 /* done = 1 when the state has finished (any status); res as for saamg_solve. */
 int saamg_state_query(const saamg_state* S, int* done, saamg_result* res);
-/* Write the (unscaled) current iterate to the device box vector d_x, queued on the
- * state's stream: the caller orders any earlier writes of d_x on other streams before
- * the call, and synchronises that stream before reading d_x elsewhere. */
+/* Write the (unscaled) current iterate to the device box vector d_x on the state's
+ * stream; returns after the write is complete.  Earlier writes of d_x on other streams
+ * must be complete before the call. */
 int saamg_state_finish(saamg_state* S, double* d_x);
 int saamg_state_destroy(saamg_state* S);
 
