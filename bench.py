@@ -397,6 +397,7 @@ def main():
             "unit": "GB/s",
             "frac": live["achieved_GBs"] / HBM_PEAK_GBS,
             "traffic": measured_traffic(dom_k, w.name),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_us": live["avg_us"],
             "launches": live["launches"],
             "alg_bytes_per_launch": live["alg_bytes_per_launch"],
