@@ -209,41 +209,49 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
         if (span_lane(lane_u64(wu, 0), lane) != lane) zm = TX(0);
         if (span_lane(lane_u64(wu, 1), lane) != lane) c = TX(0);
     }
-    PlaneLoads<T, TX, FV> cur = load_plane(z0);
-    for (int z = z0; z < z1; ++z) {
-        // the last step reloads its own plane instead of reading past the tile
-        const PlaneLoads<T, TX, FV> nxtp = load_plane(z + 1 < z1 ? z + 1 : z);
+    // Arithmetic of plane z from its loads P.
+    auto step = [&](const PlaneLoads<T, TX, FV>& P, int z) {
         // X at (x, y, z+1); zero where that plane's span does not reach
-        const TX zp = (STENCIL && cur.ins1) ? cur.nxt : TX(0);
-        if (cur.u != 0) {
+        const TX zp = (STENCIL && P.ins1) ? P.nxt : TX(0);
+        if (P.u != 0) {
             TX xm = TX(0), xp = TX(0);
             if (STENCIL) {
                 xm = __shfl_up(c, 1, kWave);
                 xp = __shfl_down(c, 1, kWave);
-                if (lane == 0) xm = cur.edge;
-                if (lane == kWave - 1) xp = cur.edge;
+                if (lane == 0) xm = P.edge;
+                if (lane == kWave - 1) xp = P.edge;
             }
-            if ((cur.u >> lane) & 1ull) {
+            if ((P.u >> lane) & 1ull) {
                 const long i = rb + nxy * z + lane;
-                const int r = cur.rk;
+                const int r = P.rk;
                 T ax = T(0);
                 if (STENCIL) {
-                    if (!cur.irr) {
-                        ax = T(c) + v.c[0] * (T(xm) + T(xp)) + v.c[1] * (T(cur.ym) + T(cur.yp)) +
+                    if (!P.irr) {
+                        ax = T(c) + v.c[0] * (T(xm) + T(xp)) + v.c[1] * (T(P.ym) + T(P.yp)) +
                              v.c[2] * (T(zm) + T(zp));
                     } else {
-                        ax = T(c) + cur.t[0] * T(xm) + cur.t[1] * T(xp) + cur.t[2] * T(cur.ym) +
-                             cur.t[3] * T(cur.yp) + cur.t[4] * T(zm) + cur.t[5] * T(zp);
+                        ax = T(c) + P.t[0] * T(xm) + P.t[1] * T(xp) + P.t[2] * T(P.ym) +
+                             P.t[3] * T(P.yp) + P.t[4] * T(zm) + P.t[5] * T(zp);
                     }
                 }
-                body(i, cur.fv, T(c), ax, x0 + lane, y, z, cur.irr, r);
+                body(i, P.fv, T(c), ax, x0 + lane, y, z, P.irr, r);
             }
         }
         if (STENCIL) {
             zm = c;
             c = zp;
         }
-        cur = nxtp;
+    };
+    // Two register sets take turns: while one plane is computed the next one's loads are
+    // in flight, and no copy between the sets forces an early wait.  The last steps
+    // reload their own plane instead of reading past the tile.
+    PlaneLoads<T, TX, FV> pa = load_plane(z0);
+    for (int z = z0; z < z1; z += 2) {
+        PlaneLoads<T, TX, FV> pb = load_plane(z + 1 < z1 ? z + 1 : z);
+        step(pa, z);
+        if (z + 1 >= z1) break;
+        pa = load_plane(z + 2 < z1 ? z + 2 : z + 1);
+        step(pb, z + 1);
     }
 }
 
