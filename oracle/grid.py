@@ -48,6 +48,7 @@ class Domain:
     h: Tuple[float, float, float]
     mask: np.ndarray
     frac: np.ndarray  # (6, nz, ny, nx)
+    robin_d: float = 0.0  # > 0: open ends (Robin), the box carries one ghost plane per end
 
     @property
     def n_unknowns(self) -> int:
@@ -72,8 +73,47 @@ def _in_bore(X: np.ndarray, Y: np.ndarray, r: float) -> np.ndarray:
 
 
 def build(kind: int, a: float, b: float, length: float, nx: int, ny: int, nz: int,
-          bore_r: float = 0.0, cavity_half_len: float = 0.0) -> Domain:
-    """Classify every box node and compute wall fractions (vectorised where simple)."""
+          bore_r: float = 0.0, cavity_half_len: float = 0.0, robin: bool = False) -> Domain:
+    """Classify every box node and compute wall fractions (vectorised where simple).
+
+    With ``robin`` the two end planes z = -L/2 and z = +L/2 of the lattice are open
+    boundary (Section 2, the Robin condition on Gamma_2): their nodes inside the
+    cross-section are unknowns, and the box gains one empty ghost plane beyond each end, so
+    the returned domain has nz + 2 planes with the lattice's plane k at box plane k + 1.
+    """
+    if robin:
+        inner = build(kind, a, b, length, nx, ny, nz, bore_r, cavity_half_len)
+        z = coords(0.5 * length, nz)
+        Y, X = np.meshgrid(coords(b, ny), coords(a, nx), indexing="ij")
+        ends = np.zeros((ny, nx), dtype=bool)
+        ends[1:-1, 1:-1] = True
+        if kind in (CYLINDER, ELLIPSE):
+            ends &= _inside_xy(kind, a, b, X, Y)
+        else:  # the bore, and the cavity if it reaches the ends
+            keep = 1.0 - ON_WALL
+            cav = (np.abs(X) < a * keep) & (np.abs(Y) < b * keep) & (0.5 * length < cavity_half_len * keep)
+            ends &= cav | _in_bore(X, Y, bore_r)
+        mask = np.zeros((nz + 2, ny, nx), dtype=bool)
+        mask[1:-1] = inner.mask
+        mask[1] = mask[-2] = ends
+        frac = np.ones((6, nz + 2, ny, nx))
+        frac[:, 1:-1] = inner.frac
+        # wall fractions of the end-plane nodes in x and y (z: the open boundary)
+        for kb, zv in ((1, z[0]), (nz, z[-1])):
+            js, is_ = np.nonzero(ends)
+            for d in range(4):
+                dy, dx = DIRS[d][1], DIRS[d][0]
+                sel = np.nonzero(~ends[js + dy, is_ + dx])[0]
+                if sel.size:
+                    j, i = js[sel], is_[sel]
+                    frac[d, kb, j, i] = _wall_fraction(
+                        kind, a, b, length, bore_r, cavity_half_len, coords(a, nx)[i],
+                        coords(b, ny)[j], np.full(sel.size, zv), inner.h, d)
+            frac[4:, kb] = 1.0
+        # the planes next to the ends now have unknown neighbours there (no wall)
+        frac[4, 2][mask[1]] = 1.0
+        frac[5, nz - 1][mask[nz]] = 1.0
+        return Domain(nx, ny, nz + 2, inner.h, mask, frac, 0.5 * length)
     x = coords(a, nx)
     y = coords(b, ny)
     z = coords(0.5 * length, nz)
@@ -137,10 +177,10 @@ def _wall_fraction(kind, a, b, length, bore_r, cav_half, xs, ys, zs, h, d) -> np
     return s
 
 
-def from_shape(shape, nx: int, ny: int, nz: int) -> Domain:
+def from_shape(shape, nx: int, ny: int, nz: int, robin: bool = False) -> Domain:
     """Build from a ``workloads.Shape``-like object (kind, a, b, length, ...)."""
     return build(shape.kind, shape.a, shape.b, shape.length, nx, ny, nz,
-                 getattr(shape, "bore_r", 0.0), getattr(shape, "cavity_half_len", 0.0))
+                 getattr(shape, "bore_r", 0.0), getattr(shape, "cavity_half_len", 0.0), robin)
 
 
 def cross_section_count(kind: int, a: float, b: float, nx: int, ny: int) -> int:

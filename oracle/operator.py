@@ -17,6 +17,13 @@ rules in every direction in which the point is near the wall).  The substitution
 carried out literally below, term by term, so that a reader can match it against the
 equations; the resulting per-axis rows are what the tests pin against closed forms.
 
+Open ends (Section 2, eq. inlet): on a domain with Robin ends, a node x on an end plane
+has its outside z-neighbour x' replaced by u(x') = u(x'') - (2 h_z / d) u(x), with x''
+the inside z-neighbour and d half the length of the pipe.  Reading: the rows of the end
+planes are divided by 2 (and so is their right-hand side).  This leaves the solution
+unchanged and keeps the constant and linear rules symmetric, as Section 2 states they
+are.
+
 Scaling (end of Section 2): with D = diag(A) the system A x = b is replaced by
 (D^-1/2 A D^-1/2) y = D^-1/2 b, x = D^-1/2 y.
 """
@@ -39,10 +46,11 @@ class System:
 
     dom: Domain
     variant: int
-    A: sp.csr_matrix          # unscaled matrix
+    A: sp.csr_matrix          # unscaled matrix (end-plane rows of open ends halved)
     idx: np.ndarray           # box-linear index of each unknown
     sigma: np.ndarray         # D^-1/2
     As: sp.csr_matrix         # scaled matrix D^-1/2 A D^-1/2
+    rho: np.ndarray = None    # row factor applied to A and b (1/2 on open-end rows)
 
     @property
     def n(self) -> int:
@@ -93,6 +101,27 @@ def _axis_terms(variant: int, in_m: np.ndarray, in_p: np.ndarray, s_m: np.ndarra
     return c_self, c_m, c_p
 
 
+def _robin_sides(dom: Domain, ks: np.ndarray):
+    """Open-end sides of each unknown: its -z / +z neighbour is the ghost plane."""
+    if dom.robin_d <= 0.0:
+        z = np.zeros(ks.shape, dtype=bool)
+        return z, z
+    return ks - 1 == 0, ks + 1 == dom.nz - 1
+
+
+def _robin_z_terms(h: float, d: float, out_m: np.ndarray, out_p: np.ndarray, c_self, c_m, c_p):
+    """z-coefficients (times h^2) of end-plane rows, eq. inlet substituted into
+    -u(x') + 2 u(x) - u(x''):  (2 + 2h/d) u(x) - 2 u(x'')."""
+    if not np.any(out_m | out_p):
+        return c_self, c_m, c_p
+    if np.any(out_m & out_p):
+        raise ValueError("an open end needs an unknown z-neighbour on the other side")
+    c_self = np.where(out_m | out_p, 2.0 + 2.0 * h / d, c_self)
+    c_p = np.where(out_m, -2.0, c_p)
+    c_m = np.where(out_p, -2.0, c_m)
+    return c_self, c_m, c_p
+
+
 def assemble(dom: Domain, variant: int) -> System:
     """Unscaled and scaled matrices of the discrete Poisson problem."""
     nx, ny, nz = dom.nx, dom.ny, dom.nz
@@ -102,6 +131,8 @@ def assemble(dom: Domain, variant: int) -> System:
     n = idx.size
     compact = np.full(nx * ny * nz, -1, dtype=np.int64)
     compact[idx] = np.arange(n)
+    rob_m, rob_p = _robin_sides(dom, ks)
+    rho = np.where(rob_m | rob_p, 0.5, 1.0)
     rows, cols, vals = [np.arange(n)], [np.arange(n)], []
     diag = np.zeros(n)
     for axis in range(3):
@@ -114,14 +145,17 @@ def assemble(dom: Domain, variant: int) -> System:
         s_m = dom.frac[d_m, ks, js, is_]
         s_p = dom.frac[d_p, ks, js, is_]
         c_self, c_m, c_p = _axis_terms(variant, in_m, in_p, s_m, s_p)
+        if axis == 2:
+            c_self, c_m, c_p = _robin_z_terms(dom.h[2], dom.robin_d, rob_m, rob_p,
+                                              c_self, c_m, c_p)
         inv_h2 = 1.0 / (dom.h[axis] * dom.h[axis])
-        diag += c_self * inv_h2
+        diag += rho * c_self * inv_h2
         lin_step = dx + nx * (dy + ny * dz)
         for c, sgn, inside in ((c_m, -1, in_m), (c_p, 1, in_p)):
             sel = np.nonzero(inside)[0]
             rows.append(sel)
             cols.append(compact[idx[sel] + sgn * lin_step])
-            vals.append(c[sel] * inv_h2)
+            vals.append(rho[sel] * c[sel] * inv_h2)
     vals.insert(0, diag)
     A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(n, n))
@@ -132,7 +166,7 @@ def assemble(dom: Domain, variant: int) -> System:
     S = sp.diags(sigma)
     As = (S @ A @ S).tocsr()
     As.sort_indices()
-    return System(dom, variant, A, idx, sigma, As)
+    return System(dom, variant, A, idx, sigma, As, rho)
 
 
 def diagonal(dom: Domain, variant: int):
@@ -144,6 +178,8 @@ def diagonal(dom: Domain, variant: int):
     nx, ny = dom.nx, dom.ny
     ks, js, is_ = np.nonzero(dom.mask)
     diag = np.zeros(ks.size)
+    rob_m, rob_p = _robin_sides(dom, ks)
+    rho = np.where(rob_m | rob_p, 0.5, 1.0)
     for axis in range(3):
         step = [0, 0, 0]
         step[axis] = 1
@@ -152,14 +188,16 @@ def diagonal(dom: Domain, variant: int):
         in_p = dom.mask[ks + dz, js + dy, is_ + dx]
         s_m = dom.frac[2 * axis, ks, js, is_]
         s_p = dom.frac[2 * axis + 1, ks, js, is_]
-        c_self, _, _ = _axis_terms(variant, in_m, in_p, s_m, s_p)
-        diag += c_self / (dom.h[axis] * dom.h[axis])
+        c_self, c_m, c_p = _axis_terms(variant, in_m, in_p, s_m, s_p)
+        if axis == 2:
+            c_self, _, _ = _robin_z_terms(dom.h[2], dom.robin_d, rob_m, rob_p, c_self, c_m, c_p)
+        diag += rho * c_self / (dom.h[axis] * dom.h[axis])
     return (is_ + nx * (js + ny * ks)).astype(np.int64), diag
 
 
 def scaled_rhs(sys_: System, b_box: np.ndarray) -> np.ndarray:
-    """D^-1/2 b over the unknowns."""
-    return sys_.sigma * sys_.gather(b_box)
+    """D^-1/2 b over the unknowns (b of the open-end rows halved with the rows)."""
+    return sys_.sigma * sys_.rho * sys_.gather(b_box)
 
 
 def unscale(sys_: System, y: np.ndarray) -> np.ndarray:

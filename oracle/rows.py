@@ -17,9 +17,13 @@ CONST, LIN, QUAD = 0, 1, 2
 
 
 def row(dom: Domain, variant: int, i: int, j: int, k: int):
-    """(diag, [(di, dj, dk, coef), ...]) of the unscaled row at unknown (i, j, k)."""
+    """(diag, [(di, dj, dk, coef), ...], rho) of the unscaled row at unknown (i, j, k).
+
+    On an open end (Robin, eq. inlet) the outside z-neighbour is u(x'') - (2 h / d) u(x),
+    and the row, already multiplied by rho = 1/2 there, is returned with that factor."""
     diag = 0.0
     offs = []
+    rob = dom.robin_d > 0.0 and (k - 1 == 0 or k + 1 == dom.nz - 1)
     for axis in range(3):
         e = [0, 0, 0]
         e[axis] = 1
@@ -30,6 +34,13 @@ def row(dom: Domain, variant: int, i: int, j: int, k: int):
         s = float(dom.frac[2 * axis, k, j, i])
         t = float(dom.frac[2 * axis + 1, k, j, i])
         ih2 = 1.0 / (dom.h[axis] ** 2)
+        if axis == 2 and rob:
+            if not (in_m or in_p):
+                raise ValueError("an open end needs an unknown z-neighbour")
+            diag += (2.0 + 2.0 * dom.h[2] / dom.robin_d) * ih2
+            sgn = 1 if in_p else -1
+            offs.append((0, 0, sgn, -2.0 * ih2))
+            continue
         if in_m and in_p:
             diag += 2.0 * ih2
             offs += [(-e[0], -e[1], -e[2], -ih2), (e[0], e[1], e[2], -ih2)]
@@ -55,7 +66,8 @@ def row(dom: Domain, variant: int, i: int, j: int, k: int):
             else:
                 diag += 2.0 / t * ih2
                 offs.append((-e[0], -e[1], -e[2], -2.0 / (t + 1.0) * ih2))
-    return diag, offs
+    rho = 0.5 if rob else 1.0
+    return rho * diag, [(a, b, c, rho * v) for a, b, c, v in offs], rho
 
 
 def scaled_residual_rows(dom: Domain, variant: int, x_box: np.ndarray, b_box: np.ndarray,
@@ -67,9 +79,9 @@ def scaled_residual_rows(dom: Domain, variant: int, x_box: np.ndarray, b_box: np
     out = np.empty(len(nodes))
     for t, n in enumerate(nodes):
         i, j, k = n % nx, (n // nx) % ny, n // (nx * ny)
-        diag, offs = row(dom, variant, i, j, k)
+        diag, offs, rho = row(dom, variant, i, j, k)
         ax = diag * xf[n]
         for di, dj, dk, c in offs:
             ax += c * xf[n + di + nx * (dj + ny * dk)]
-        out[t] = (bf[n] - ax) / np.sqrt(diag)
+        out[t] = (rho * bf[n] - ax) / np.sqrt(diag)
     return out

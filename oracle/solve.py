@@ -24,10 +24,11 @@ class OracleSolve:
 
 
 def build(shape, nx: int, ny: int, nz: int, variant: int,
-          opts: Optional[amg.Options] = None):
-    dom = grid.from_shape(shape, nx, ny, nz)
+          opts: Optional[amg.Options] = None, robin: bool = False):
+    """System and hierarchy; with ``robin`` the ends are open and the box has nz + 2 planes."""
+    dom = grid.from_shape(shape, nx, ny, nz, robin)
     sys_ = operator.assemble(dom, variant)
-    H = amg.setup(sys_.As, (nx, ny, nz), sys_.idx, opts)
+    H = amg.setup(sys_.As, (dom.nx, dom.ny, dom.nz), sys_.idx, opts)
     return sys_, H
 
 
@@ -41,9 +42,9 @@ def solve(sys_: operator.System, H: amg.Hierarchy, b_box: np.ndarray,
 
 
 def run(shape, nx, ny, nz, variant, b_box, x0_box=None, tol=1e-8, max_iter=500,
-        opts=None) -> OracleSolve:
+        opts=None, robin: bool = False) -> OracleSolve:
     t0 = time.perf_counter()
-    sys_, H = build(shape, nx, ny, nz, variant, opts)
+    sys_, H = build(shape, nx, ny, nz, variant, opts, robin)
     t1 = time.perf_counter()
     res = solve(sys_, H, b_box, x0_box, tol, max_iter)
     t2 = time.perf_counter()

@@ -4,6 +4,7 @@ import os
 
 import numpy as np
 import pytest
+import scipy.sparse.linalg as spla
 
 import workloads as W
 from oracle import amg, grid, operator, pcg, rows
@@ -124,7 +125,7 @@ def test_quadratic_rule_is_shortley_weller_1d():
             if dom.frac[1 - d, kk, jj, ii] < 1.0:
                 continue
             s = dom.frac[d, kk, jj, ii]
-            _, offs = rows.row(dom, operator.QUAD, ii, jj, kk)
+            _, offs, _ = rows.row(dom, operator.QUAD, ii, jj, kk)
             x_off = [o for o in offs if o[0] != 0]
             assert len(x_off) == 1 and x_off[0][0] == (1 if d == 0 else -1)
             hl, hr = s * h, h
@@ -173,24 +174,25 @@ def test_linear_rule_double_wall_row():
     dom.mask[k, j, i] = True
     dom.frac[:] = 1.0
     dom.frac[0, k, j, i], dom.frac[1, k, j, i] = 0.3, 0.6
-    diag, offs = rows.row(dom, operator.LIN, i, j, k)
+    diag, offs, _ = rows.row(dom, operator.LIN, i, j, k)
     hx = dom.h[0]
     want = (1 / 0.3 + 1 / 0.6) / hx ** 2 + 2 / dom.h[1] ** 2 + 2 / dom.h[2] ** 2
     assert abs(diag - want) < 1e-12 * want and offs == []
-    dq, _ = rows.row(dom, operator.QUAD, i, j, k)
+    dq, _, _ = rows.row(dom, operator.QUAD, i, j, k)
     wantq = 2 / (0.3 * 0.6) / hx ** 2 + 2 / dom.h[1] ** 2 + 2 / dom.h[2] ** 2
     assert abs(dq - wantq) < 1e-12 * wantq
     s = operator.assemble(dom, operator.QUAD)
     assert abs(s.A[0, 0] - wantq) < 1e-12 * wantq
 
 
-def test_rows_match_assembly():
-    dom = _dom(W.Shape.ellipse(1.0, 0.6, 2.0), 17, 13)
+@pytest.mark.parametrize("robin", [False, True])
+def test_rows_match_assembly(robin):
+    dom = grid.from_shape(W.Shape.ellipse(1.0, 0.6, 2.0), 17, 17, 13 - 2 * robin, robin=robin)
     for v in (0, 1, 2):
         s = operator.assemble(dom, v)
         xb = W.random_box_vector((17, 17, 13), 3) * dom.mask
         bb = W.random_box_vector((17, 17, 13), 4)
-        want = s.sigma * (s.gather(bb) - s.A @ s.gather(xb))
+        want = s.sigma * (s.rho * s.gather(bb) - s.A @ s.gather(xb))
         sel = s.idx[::7]
         got = rows.scaled_residual_rows(dom, v, xb, bb, sel)
         assert np.allclose(got, want[::7], rtol=1e-12, atol=1e-12)
@@ -253,3 +255,69 @@ def test_diagonal_helper_matches_assembly():
         idx, dg = operator.diagonal(dom, v)
         assert np.array_equal(idx, s.idx)
         assert np.max(np.abs(dg - s.A.diagonal())) <= 1e-14 * dg.max()
+
+
+# --------------------------------------------------------------------------- open ends
+
+def test_robin_dof_count_matches_paper_tubes():
+    """With open ends every z-plane of the lattice holds unknowns: the solver-comparison
+    tubes count 256 full planes."""
+    g = GOLD["dof_counts"]
+    dom = grid.from_shape(W.Shape.cylinder(1.0, 2.0), 128, 128, 256, robin=True)
+    assert dom.nz == 258 and not dom.mask[0].any() and not dom.mask[-1].any()
+    assert dom.n_unknowns == g["mesh_128x128x256"]
+
+
+def _robin_box(n=(9, 8, 11)):
+    nx, ny, nz = n
+    shape = W.Shape(W.BOXBORE, 1.0, 0.7, 2.0, 0.1, 2.0)  # cavity longer than the pipe
+    return grid.from_shape(shape, nx, ny, nz, robin=True), shape
+
+
+@pytest.mark.parametrize("variant", [operator.CONST, operator.LIN, operator.QUAD])
+def test_robin_exact_for_quadratic_profile(variant):
+    """u = (a^2 - x^2)(b^2 - y^2)(z^2 - 3 d^2) vanishes on the box walls and satisfies
+    du/dn + u/d = 0 on both ends; second differences and the central Robin difference are
+    exact for it, so the discrete solution equals u at every unknown."""
+    dom, shape = _robin_box()
+    s = operator.assemble(dom, variant)
+    a, b, d = shape.a, shape.b, 0.5 * shape.length
+    x = grid.coords(a, dom.nx)[None, None, :]
+    y = grid.coords(b, dom.ny)[None, :, None]
+    zc = grid.coords(d, dom.nz - 2)
+    z = np.concatenate([[0.0], zc, [0.0]])[:, None, None]
+    X2, Y2, Z2 = a * a - x * x, b * b - y * y, z * z - 3 * d * d
+    u = X2 * Y2 * Z2
+    f = 2 * Y2 * Z2 + 2 * X2 * Z2 - 2 * X2 * Y2
+    bs = operator.scaled_rhs(s, f)
+    yv = spla.spsolve(s.As.tocsc(), bs)
+    xv = operator.unscale(s, yv)
+    ue = s.gather(u)
+    assert np.max(np.abs(xv - ue)) <= 1e-10 * np.max(np.abs(ue))
+
+
+def test_robin_rows_symmetric_for_linear_rule():
+    dom = grid.from_shape(W.Shape.cylinder(1.0, 2.0), 13, 13, 9, robin=True)
+    s = operator.assemble(dom, operator.LIN)
+    assert abs(s.A - s.A.T).max() <= 1e-12 * abs(s.A).max()
+    assert np.linalg.eigvalsh(s.As.toarray()).min() > 0.0
+    q = operator.assemble(dom, operator.QUAD)
+    assert abs(q.A - q.A.T).max() > 1e-6 * abs(q.A).max()
+
+
+def test_robin_end_row_is_eq_inlet_halved():
+    """End-plane row of a node with all in-plane neighbours inside:
+    (1/2) [ (2 + 2h/d) u - 2 u'' ] / h_z^2 + (1/2) 7-point x,y part."""
+    dom, shape = _robin_box((9, 8, 11))
+    s = operator.assemble(dom, operator.LIN)
+    k, j, i = 1, 4, 4
+    n = i + dom.nx * (j + dom.ny * k)
+    r = int(np.searchsorted(s.idx, n))
+    hx, hy, hz = dom.h
+    d = 0.5 * shape.length
+    want_diag = 0.5 * ((2 + 2 * hz / d) / hz ** 2 + 2 / hx ** 2 + 2 / hy ** 2)
+    assert abs(s.A[r, r] - want_diag) < 1e-12 * want_diag
+    r2 = int(np.searchsorted(s.idx, n + dom.nx * dom.ny))
+    assert abs(s.A[r, r2] + 1.0 / hz ** 2) < 1e-12 / hz ** 2
+    rx = int(np.searchsorted(s.idx, n + 1))
+    assert abs(s.A[r, rx] + 0.5 / hx ** 2) < 1e-12 / hx ** 2

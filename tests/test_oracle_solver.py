@@ -259,3 +259,17 @@ def test_scaling_leaves_unscaled_solution_unchanged():
     x = operator.unscale(s, res.x)
     r = s.gather(b) - s.A @ x
     assert np.linalg.norm(r) < 1e-9 * np.linalg.norm(s.gather(b))
+
+
+@pytest.mark.parametrize("variant", [W.VARIANT_LIN, W.VARIANT_QUAD])
+def test_pcg_robin_matches_direct_solve(variant):
+    """Open ends: the AMG-PCG solution equals a sparse direct solve of the same system."""
+    shape = W.Shape.cylinder(1.0, 2.0)
+    sys_, H = solve.build(shape, 21, 21, 17, variant, amg.Options(), robin=True)
+    assert sys_.dom.nz == 19
+    b = W.rhs(W.small(shape, 21, 21, 17, variant, robin=True))
+    assert b.shape == (19, 21, 21)
+    res = solve.solve(sys_, H, b, tol=1e-12)
+    assert res.status == 0
+    y = spla.spsolve(sys_.As.tocsc(), operator.scaled_rhs(sys_, b))
+    assert np.linalg.norm(res.x - y) <= 1e-9 * np.linalg.norm(y)

@@ -107,14 +107,17 @@ class Workload:
     tol: float = 1e-8
     gauss_sigma: Optional[float] = None   # analytic Gaussian density
     bunch: Optional[Bunch] = None         # CIC-deposited particle bunch
+    robin: bool = False                   # open ends: the box has a ghost plane per end
 
     @property
     def dims(self) -> Tuple[int, int, int]:
-        return (self.nx, self.ny, self.nz)
+        """Box of the discrete domain (nx, ny, nz of the lattice, plus 2 planes if open)."""
+        return (self.nx, self.ny, self.nz + 2 * int(self.robin))
 
     @property
     def box_nodes(self) -> int:
-        return self.nx * self.ny * self.nz
+        nx, ny, nz = self.dims
+        return nx * ny * nz
 
 
 def spacing(shape: Shape, nx: int, ny: int, nz: int) -> Tuple[float, float, float]:
@@ -177,15 +180,25 @@ def cic_deposit(shape: Shape, nx: int, ny: int, nz: int, particles: np.ndarray,
     return rho.reshape(nz, ny, nx)
 
 
+def pad_ends(lattice_box: np.ndarray) -> np.ndarray:
+    """Lattice array (nz, ny, nx) placed in a box with one empty plane before and after."""
+    out = np.zeros((lattice_box.shape[0] + 2,) + lattice_box.shape[1:], dtype=lattice_box.dtype)
+    out[1:-1] = lattice_box
+    return out
+
+
 def rhs(w: Workload, shift_z: float = 0.0, particles: Optional[np.ndarray] = None) -> np.ndarray:
-    """Right-hand side (charge density) of a workload on its full box, (nz, ny, nx) fp64."""
+    """Right-hand side (charge density) of a workload on its full box, fp64, shaped like
+    ``w.dims`` reversed (open-ended workloads get their ghost planes)."""
     if w.gauss_sigma is not None:
-        return gaussian_density(w.shape, w.nx, w.ny, w.nz, w.gauss_sigma)
-    if w.bunch is None:
+        out = gaussian_density(w.shape, w.nx, w.ny, w.nz, w.gauss_sigma)
+    elif w.bunch is None:
         raise ValueError("workload has no right-hand-side recipe")
-    if particles is None:
-        particles = draw_particles(w.bunch)
-    return cic_deposit(w.shape, w.nx, w.ny, w.nz, particles, shift_z)
+    else:
+        if particles is None:
+            particles = draw_particles(w.bunch)
+        out = cic_deposit(w.shape, w.nx, w.ny, w.nz, particles, shift_z)
+    return pad_ends(out) if w.robin else out
 
 
 # ----------------------------------------------------------------------------------
@@ -291,11 +304,11 @@ def by_name(name: str) -> Workload:
 
 
 def small(shape: Shape, nx: int, ny: int, nz: int, variant: int, precision: int = PREC_FP64,
-          seed: int = 7, n_particles: int = 20_000) -> Workload:
+          seed: int = 7, n_particles: int = 20_000, robin: bool = False) -> Workload:
     """Small bunch workload for parity tests (seeded)."""
     sig = (0.15 * shape.a, 0.15 * shape.b, 0.15 * shape.length)
     return Workload(f"small_{shape.name}_{nx}x{ny}x{nz}", shape, nx, ny, nz, variant, precision,
-                    bunch=Bunch(n_particles, sig, seed))
+                    bunch=Bunch(n_particles, sig, seed), robin=robin)
 
 
 def random_box_vector(dims: Tuple[int, int, int], seed: int) -> np.ndarray:
