@@ -66,6 +66,13 @@ enum { SAAMG_SHAPE_CYLINDER = 0, SAAMG_SHAPE_ELLIPSE = 1, SAAMG_SHAPE_BOXBORE = 
  *              an unknown, the wall sits at fraction wall_s in (0, 1] of the spacing.
  *              An outside neighbour without an entry means s = 1 (the neighbour is on
  *              the wall).  Entries may come in any order; duplicates are an error.
+ *   robin_d    0: every outside neighbour is a Dirichlet wall (phi = 0).  > 0: open ends
+ *              (eq. poisson, Robin condition dphi/dn + phi/d = 0 on Gamma_2, discretised
+ *              by eq. inlet) with d = robin_d: the box planes z = 0 and z = nz-1 are ghost
+ *              planes, and every unknown on planes 1 and nz-2 takes its outside z-neighbour
+ *              from eq. inlet (its inner z-neighbour must be an unknown).  Those rows and
+ *              their right-hand side are divided by 2, which leaves the solution unchanged
+ *              and keeps the constant and linear rules symmetric.
  * The library copies what it needs; the caller keeps ownership.
  */
 typedef struct {
@@ -76,6 +83,7 @@ typedef struct {
     const int64_t* wall_node;
     const uint8_t* wall_dir;
     const double* wall_s;
+    double robin_d;
 } saamg_domain;
 
 /* Preconditioner and solver options; saamg_default_options fills the defaults. */
@@ -129,16 +137,21 @@ void saamg_default_options(saamg_options* opt);
  *   kind          SAAMG_SHAPE_*; a, b: half-extents of the box along x and y (radius,
  *                 semi-axes, or cavity half-width); length: extent along z; bore_r and
  *                 cavity_half_len: BOXBORE only (ignored otherwise).
- *   mask_out      host, nx*ny*nz bytes, written.
+ *   nx, ny, nz    lattice nodes per axis, end points included.
+ *   open_ends     0: the end planes are Dirichlet walls and the box is the lattice.
+ *                 1: the end planes hold unknowns (set robin_d = length/2 in the domain)
+ *                 and the box has nz + 2 planes, the lattice's plane k at box plane k + 1.
+ *   mask_out      host, nx*ny*(box planes) bytes, written.
  *   wall_cap      capacity of the three wall_* output arrays (host); may be 0 to query.
- *   n_wall_out    number of entries with s < 1; if it exceeds wall_cap nothing is
- *                 written to the wall arrays and SAAMG_INVALID_ARG is returned.
- * Node coordinates are a*(2i-(n-1))/(n-1) per axis; unknowns lie strictly inside.
+ *   n_wall_out    number of entries with s < 1.  If it exceeds a nonzero wall_cap the
+ *                 first wall_cap entries are written and SAAMG_INVALID_ARG is returned.
+ * Node coordinates are a*(2i-(n-1))/(n-1) per axis; unknowns lie strictly inside (a node
+ * inside only within a relative 1e-12 of the wall counts as on the wall).
  */
 int saamg_domain_from_shape(int kind, double a, double b, double length, double bore_r,
-                            double cavity_half_len, int nx, int ny, int nz, uint8_t* mask_out,
-                            int64_t wall_cap, int64_t* wall_node, uint8_t* wall_dir,
-                            double* wall_s, int64_t* n_wall_out);
+                            double cavity_half_len, int nx, int ny, int nz, int open_ends,
+                            uint8_t* mask_out, int64_t wall_cap, int64_t* wall_node,
+                            uint8_t* wall_dir, double* wall_s, int64_t* n_wall_out);
 
 /*
  * Build the scaled operator and the SA-AMG hierarchy on the current device.

@@ -31,7 +31,7 @@ class Domain(C.Structure):
                 ("hx", C.c_double), ("hy", C.c_double), ("hz", C.c_double),
                 ("mask", C.POINTER(C.c_uint8)), ("n_wall", C.c_int64),
                 ("wall_node", C.POINTER(C.c_int64)), ("wall_dir", C.POINTER(C.c_uint8)),
-                ("wall_s", C.POINTER(C.c_double))]
+                ("wall_s", C.POINTER(C.c_double)), ("robin_d", C.c_double)]
 
 
 class Options(C.Structure):
@@ -81,7 +81,7 @@ def lib() -> C.CDLL:
     L.saamg_last_error.restype = C.c_char_p
     L.saamg_default_options.argtypes = [C.POINTER(Options)]
     L.saamg_domain_from_shape.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
-                                          C.c_double, C.c_int, C.c_int, C.c_int,
+                                          C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
                                           C.POINTER(C.c_uint8), C.c_int64, C.POINTER(C.c_int64),
                                           C.POINTER(C.c_uint8), _DP, C.POINTER(C.c_int64)]
     L.saamg_setup.argtypes = [C.POINTER(Domain), C.c_int, C.POINTER(Options), _P, C.POINTER(_P)]
@@ -131,7 +131,8 @@ class HostDomain:
     """Host arrays describing a discrete domain (the argument of setup)."""
 
     def __init__(self, mask: np.ndarray, h: Tuple[float, float, float], wall_node: np.ndarray,
-                 wall_dir: np.ndarray, wall_s: np.ndarray):
+                 wall_dir: np.ndarray, wall_s: np.ndarray, robin_d: float = 0.0):
+        self.robin_d = float(robin_d)
         self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
         self.nz, self.ny, self.nx = self.mask.shape
         self.h = tuple(float(v) for v in h)
@@ -148,6 +149,7 @@ class HostDomain:
         d.wall_node = self.wall_node.ctypes.data_as(C.POINTER(C.c_int64))
         d.wall_dir = self.wall_dir.ctypes.data_as(C.POINTER(C.c_uint8))
         d.wall_s = self.wall_s.ctypes.data_as(_DP)
+        d.robin_d = self.robin_d
         return d
 
     @property
@@ -156,29 +158,33 @@ class HostDomain:
 
 
 def domain_from_shape(kind: int, a: float, b: float, length: float, nx: int, ny: int, nz: int,
-                      bore_r: float = 0.0, cavity_half_len: float = 0.0) -> HostDomain:
+                      bore_r: float = 0.0, cavity_half_len: float = 0.0,
+                      open_ends: bool = False) -> HostDomain:
+    """Domain of an analytic pipe; with ``open_ends`` the end planes hold unknowns (Robin,
+    d = length / 2) and the box has nz + 2 planes."""
     L = lib()
-    mask = np.zeros((nz, ny, nx), dtype=np.uint8)
+    mask = np.zeros((nz + 2 * int(open_ends), ny, nx), dtype=np.uint8)
     n = C.c_int64(0)
     mp = mask.ctypes.data_as(C.POINTER(C.c_uint8))
-    _check(L.saamg_domain_from_shape(kind, a, b, length, bore_r, cavity_half_len, nx, ny, nz, mp,
-                                     0, None, None, None, C.byref(n)))
+    oe = int(bool(open_ends))
+    _check(L.saamg_domain_from_shape(kind, a, b, length, bore_r, cavity_half_len, nx, ny, nz, oe,
+                                     mp, 0, None, None, None, C.byref(n)))
     cnt = n.value
     node = np.zeros(max(cnt, 1), dtype=np.int64)
     dr = np.zeros(max(cnt, 1), dtype=np.uint8)
     s = np.zeros(max(cnt, 1), dtype=np.float64)
-    _check(L.saamg_domain_from_shape(kind, a, b, length, bore_r, cavity_half_len, nx, ny, nz, mp,
-                                     max(cnt, 1), node.ctypes.data_as(C.POINTER(C.c_int64)),
+    _check(L.saamg_domain_from_shape(kind, a, b, length, bore_r, cavity_half_len, nx, ny, nz, oe,
+                                     mp, max(cnt, 1), node.ctypes.data_as(C.POINTER(C.c_int64)),
                                      dr.ctypes.data_as(C.POINTER(C.c_uint8)),
                                      s.ctypes.data_as(_DP), C.byref(n)))
     h = (2.0 * a / (nx - 1), 2.0 * b / (ny - 1), length / (nz - 1))
-    return HostDomain(mask, h, node[:cnt], dr[:cnt], s[:cnt])
+    return HostDomain(mask, h, node[:cnt], dr[:cnt], s[:cnt], 0.5 * length if open_ends else 0.0)
 
 
-def domain_for(shape, nx: int, ny: int, nz: int) -> HostDomain:
-    """Domain of a ``workloads.Shape``."""
+def domain_for(shape, nx: int, ny: int, nz: int, open_ends: bool = False) -> HostDomain:
+    """Domain of a ``workloads.Shape`` (nx, ny, nz: lattice nodes)."""
     return domain_from_shape(shape.kind, shape.a, shape.b, shape.length, nx, ny, nz,
-                             shape.bore_r, shape.cavity_half_len)
+                             shape.bore_r, shape.cavity_half_len, open_ends)
 
 
 # --------------------------------------------------------------------------- device glue

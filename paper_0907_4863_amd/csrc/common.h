@@ -49,6 +49,7 @@ struct L0View {
     const T* tab[6];    // scaled off-diagonals of irregular rows, per direction
     const T* tabT[6];   // the same rows of the transpose
     T c[3];             // interior off-diagonal per axis
+    double rho_end;     // factor of the end-plane rows (1/2 with open ends, else 1)
 };
 
 template <typename T>
@@ -151,6 +152,7 @@ struct FineLevel {
     double* tab64 = nullptr;    // [12][n_irr]: 6 forward then 6 transpose
     float* tab32 = nullptr;
     double c64[3];
+    double robin_d = 0.0;       // open ends (Robin parameter d); 0: closed ends
     double* sigma = nullptr;    // box, D^-1/2 at unknowns
     long n_unknowns = 0;
 
@@ -223,6 +225,7 @@ inline L0View<T> FineLevel::view() const {
         }
     }
     for (int a = 0; a < 3; ++a) v.c[a] = (T)c64[a];
+    v.rho_end = robin_d > 0.0 ? 0.5 : 1.0;
     return v;
 }
 

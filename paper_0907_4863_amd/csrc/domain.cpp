@@ -66,10 +66,12 @@ inline double coord(double half, int i, int n) {
 
 extern "C" int saamg_domain_from_shape(int kind, double a, double b, double length, double bore_r,
                                        double cavity_half_len, int nx, int ny, int nz,
-                                       uint8_t* mask_out, int64_t wall_cap, int64_t* wall_node,
-                                       uint8_t* wall_dir, double* wall_s, int64_t* n_wall_out) {
+                                       int open_ends, uint8_t* mask_out, int64_t wall_cap,
+                                       int64_t* wall_node, uint8_t* wall_dir, double* wall_s,
+                                       int64_t* n_wall_out) {
     if (kind < SAAMG_SHAPE_CYLINDER || kind > SAAMG_SHAPE_BOXBORE) return SAAMG_INVALID_ARG;
     if (nx < 3 || ny < 3 || nz < 3 || !mask_out || !n_wall_out) return SAAMG_INVALID_ARG;
+    if (open_ends != 0 && open_ends != 1) return SAAMG_INVALID_ARG;
     if (!(a > 0) || !(b > 0) || !(length > 0)) return SAAMG_INVALID_ARG;
     if (kind == SAAMG_SHAPE_BOXBORE && (!(bore_r > 0) || !(cavity_half_len > 0)))
         return SAAMG_INVALID_ARG;
@@ -77,28 +79,35 @@ extern "C" int saamg_domain_from_shape(int kind, double a, double b, double leng
     const Pipe p{kind, a, b, length, bore_r, cavity_half_len};
     const long nxy = (long)nx * ny;
     const double h[3] = {2.0 * a / (nx - 1), 2.0 * b / (ny - 1), length / (nz - 1)};
+    // box planes: the lattice's plane k sits at box plane k + open_ends; with open ends the
+    // lattice's end planes hold unknowns and the box gains one ghost plane at each end
+    const int nzb = nz + 2 * open_ends;
+    auto lattice_plane = [&](int kb) { return kb - open_ends; };
+    auto unknown_plane = [&](int k) { return open_ends ? (k >= 0 && k < nz) : (k > 0 && k < nz - 1); };
 
-    for (int k = 0; k < nz; ++k) {
+    for (int kb = 0; kb < nzb; ++kb) {
+        const int k = lattice_plane(kb);
         const double z = coord(0.5 * length, k, nz);
         for (int j = 0; j < ny; ++j) {
             const double y = coord(b, j, ny);
             for (int i = 0; i < nx; ++i) {
                 const double x = coord(a, i, nx);
                 const bool interior_index =
-                    i > 0 && j > 0 && k > 0 && i < nx - 1 && j < ny - 1 && k < nz - 1;
-                mask_out[i + nx * (long)j + nxy * k] = (interior_index && p.inside(x, y, z)) ? 1 : 0;
+                    i > 0 && j > 0 && i < nx - 1 && j < ny - 1 && unknown_plane(k);
+                mask_out[i + nx * (long)j + nxy * kb] = (interior_index && p.inside(x, y, z)) ? 1 : 0;
             }
         }
     }
 
     int64_t count = 0;
     const long step[3] = {1, (long)nx, nxy};
-    for (int k = 1; k < nz - 1; ++k) {
+    for (int kb = 1; kb < nzb - 1; ++kb) {
+        const int k = lattice_plane(kb);
         const double z = coord(0.5 * length, k, nz);
         for (int j = 1; j < ny - 1; ++j) {
             const double y = coord(b, j, ny);
             for (int i = 1; i < nx - 1; ++i) {
-                const long idx = i + nx * (long)j + nxy * k;
+                const long idx = i + nx * (long)j + nxy * kb;
                 if (!mask_out[idx]) continue;
                 const double x = coord(a, i, nx);
                 const double pos[3] = {x, y, z};
@@ -106,6 +115,10 @@ extern "C" int saamg_domain_from_shape(int kind, double a, double b, double leng
                     const int axis = d / 2;
                     const long nb = (d & 1) ? idx + step[axis] : idx - step[axis];
                     if (mask_out[nb]) continue;
+                    // the ghost planes beyond open ends are not walls
+                    if (open_ends && axis == 2 && (kb + ((d & 1) ? 1 : -1) == 0 ||
+                                                   kb + ((d & 1) ? 1 : -1) == nzb - 1))
+                        continue;
                     const double end = p.half_interval(axis, x, y, z);
                     const double wall = (d & 1) ? end : -end;
                     double s = std::fabs(wall - pos[axis]) / h[axis];

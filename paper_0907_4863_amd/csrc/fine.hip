@@ -461,9 +461,14 @@ __device__ inline void axis_rule(int variant, bool in_m, bool in_p, double s, do
     }
 }
 
+// Rule of the row at box index i.  Rows without a near-wall entry have the interior
+// stencil.  On a domain with open ends (rob = 2 h_z / d > 0) the unknowns of planes 1
+// and nz-2 are end-plane rows: their outside z-neighbour is u(x'') - (2 h_z / d) u(x)
+// (eq. inlet), and the whole row is halved, which keeps the constant and linear rules
+// symmetric.
 __device__ inline RowRule row_rule(long i, const uint8_t* mask, const int32_t* nwidx,
                                    const double* nwfrac, int variant, double sigma0,
-                                   const double ih2[3], const long step[3]) {
+                                   const double ih2[3], const long step[3], int nz, double rob) {
     RowRule r;
     const int k = nwidx[i];
     if (k < 0) {
@@ -471,15 +476,26 @@ __device__ inline RowRule row_rule(long i, const uint8_t* mask, const int32_t* n
         r.f[0] = r.f[1] = r.f[2] = 1.0;
         return r;
     }
+    const long zp = i / step[2];
+    const bool end = rob > 0.0 && (zp == 1 || zp == nz - 2);
     double D = 0.0;
     for (int a = 0; a < 3; ++a) {
         const bool in_m = mask[i - step[a]] != 0;
         const bool in_p = mask[i + step[a]] != 0;
         double dg, f;
-        axis_rule(variant, in_m, in_p, nwfrac[6L * k + 2 * a], nwfrac[6L * k + 2 * a + 1], &dg,
-                  &f);
+        if (a == 2 && end) {
+            dg = 2.0 + rob;
+            f = 2.0;
+        } else {
+            axis_rule(variant, in_m, in_p, nwfrac[6L * k + 2 * a], nwfrac[6L * k + 2 * a + 1], &dg,
+                      &f);
+        }
         D += dg * ih2[a];
         r.f[a] = f;
+    }
+    if (end) {
+        D *= 0.5;
+        for (int a = 0; a < 3; ++a) r.f[a] *= 0.5;
     }
     r.sigma = 1.0 / sqrt(D);
     return r;
@@ -494,7 +510,7 @@ __device__ inline double scaled_off(const RowRule& row, const RowRule& col, int 
 __global__ void __launch_bounds__(kThreads) k_build_table(
     L0View<double> v, const uint8_t* __restrict__ mask, const int32_t* __restrict__ nwidx,
     const double* __restrict__ nwfrac, int variant, double sigma0, double ihx2, double ihy2,
-    double ihz2, long n_irr, double* tab, float* tab32, double* sigma) {
+    double ihz2, double rob, long n_irr, double* tab, float* tab32, double* sigma) {
     const double ih2[3] = {ihx2, ihy2, ihz2};
     const long step[3] = {1, (long)v.nx, v.nxy};
     L0_LOOP_BEGIN
@@ -502,7 +518,8 @@ __global__ void __launch_bounds__(kThreads) k_build_table(
         if (!n.unk) {
             sigma[n.i] = 0.0;
         } else {
-            const RowRule me = row_rule(n.i, mask, nwidx, nwfrac, variant, sigma0, ih2, step);
+            const RowRule me =
+                row_rule(n.i, mask, nwidx, nwfrac, variant, sigma0, ih2, step, v.nz, rob);
             sigma[n.i] = me.sigma;
             if (n.irr) {
                 for (int d = 0; d < 6; ++d) {
@@ -510,7 +527,8 @@ __global__ void __launch_bounds__(kThreads) k_build_table(
                     const long j = n.i + ((d & 1) ? step[a] : -step[a]);
                     double fw = 0.0, bw = 0.0;
                     if (mask[j]) {
-                        const RowRule nb = row_rule(j, mask, nwidx, nwfrac, variant, sigma0, ih2, step);
+                        const RowRule nb =
+                            row_rule(j, mask, nwidx, nwfrac, variant, sigma0, ih2, step, v.nz, rob);
                         fw = scaled_off(me, nb, a, ih2);
                         bw = scaled_off(nb, me, a, ih2);
                     }
@@ -530,7 +548,8 @@ void l0_build_table(FineLevel& L, const uint8_t* mask, const int32_t* nwidx, con
     L0View<double> v = L.view<double>();
     hipLaunchKernelGGL(k_build_table, l0_grid(L), dim3(kWave, kBlockY), 0, s, v, mask, nwidx,
                        nwfrac, variant, sigma0, 1.0 / (L.h[0] * L.h[0]), 1.0 / (L.h[1] * L.h[1]),
-                       1.0 / (L.h[2] * L.h[2]), L.n_irr, L.tab64, L.tab32, L.sigma);
+                       1.0 / (L.h[2] * L.h[2]), L.robin_d > 0.0 ? 2.0 * L.h[2] / L.robin_d : 0.0,
+                       L.n_irr, L.tab64, L.tab32, L.sigma);
     HIPCHECK(hipGetLastError());
 }
 
@@ -908,8 +927,10 @@ __global__ void __launch_bounds__(kMThreads) k_cg_init(L0View<double> v, const d
         [&](long i, int, int, int, bool, int) {
             return Vals<double, 3>{{sigma[i], b[i], x0 ? x0[i] : 0.0}};
         },
-        [&](long i, Vals<double, 3> f, double, double, int, int, int, bool, int) {
-            bs[i] = f.v[0] * f.v[1];
+        [&](long i, Vals<double, 3> f, double, double, int, int, int z, bool, int) {
+            // end-plane rows of open ends are halved, and so is their right-hand side
+            const double rho = (z == 1 || z == v.nz - 2) ? v.rho_end : 1.0;
+            bs[i] = f.v[0] * rho * f.v[1];
             xv[i] = x0 ? f.v[2] / f.v[0] : 0.0;
         });
 }

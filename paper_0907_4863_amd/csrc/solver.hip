@@ -3,6 +3,8 @@
 // Paper: Section 2 (operator and scaling), Section 3 (PCG with an SA-AMG V-cycle,
 // Algorithm 1), Table 1 (coarse size limit 1000), Section 5 (relative-residual stop).
 #include <algorithm>
+#include <array>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -553,9 +555,26 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
             }
     if (n_unk == 0) throw ApiError{SAAMG_INVALID_ARG, "the domain has no unknowns"};
 
-    // wall fractions below 1, grouped per node (the constant rule ignores them)
-    std::vector<std::pair<int64_t, int>> ent;
+    const bool open = dom->robin_d > 0.0;
+    if (dom->robin_d < 0.0 || !std::isfinite(dom->robin_d))
+        throw ApiError{SAAMG_INVALID_ARG, "robin_d must be 0 (closed ends) or positive"};
+    if (open) {
+        if (nz < 4) throw ApiError{SAAMG_INVALID_ARG, "open ends need at least 4 box planes"};
+        // end-plane unknowns (planes 1 and nz-2) need an unknown on the inner side
+        for (long j = 0; j < ny; ++j)
+            for (long i = 0; i < nx; ++i) {
+                const long a = i + nx * j + nxy, b = i + nx * j + nxy * (nz - 2);
+                if ((m[a] && !m[a + nxy]) || (m[b] && !m[b - nxy]))
+                    throw ApiError{SAAMG_INVALID_ARG,
+                                   "an open-end unknown has no unknown z-neighbour inside"};
+            }
+    }
+
+    // Near-wall rows: wall fractions below 1 (the constant rule ignores them) and, with
+    // open ends, every end-plane unknown; six fractions per row, 1 where no wall is cut.
+    std::map<int64_t, std::array<double, 6>> nw;
     const long step[6] = {-1, 1, -(long)nx, (long)nx, -nxy, nxy};
+    std::vector<int64_t> seen;
     for (int64_t e = 0; e < dom->n_wall; ++e) {
         const int64_t node = dom->wall_node[e];
         const int d = dom->wall_dir[e];
@@ -567,21 +586,30 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
                            "wall entry must name an unknown whose neighbour is not an unknown"};
         if (!(sv > 1e-12) || !(sv <= 1.0))
             throw ApiError{SAAMG_INVALID_ARG, "wall fraction must lie in (1e-12, 1]"};
-        if (sv < 1.0 && variant != SAAMG_VARIANT_CONST) ent.push_back({node * 8 + d, (int)e});
+        seen.push_back(node * 8 + d);
+        if (sv < 1.0 && variant != SAAMG_VARIANT_CONST) {
+            auto it = nw.find(node);
+            if (it == nw.end()) it = nw.emplace(node, std::array<double, 6>{1, 1, 1, 1, 1, 1}).first;
+            it->second[d] = sv;
+        }
     }
-    std::sort(ent.begin(), ent.end());
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+        throw ApiError{SAAMG_INVALID_ARG, "duplicate wall entry"};
+    if (open)
+        for (long k : {1L, (long)nz - 2})
+            for (long j = 0; j < ny; ++j)
+                for (long i = 0; i < nx; ++i) {
+                    const long idx = i + nx * j + nxy * k;
+                    if (m[idx]) nw.emplace(idx, std::array<double, 6>{1, 1, 1, 1, 1, 1});
+                }
     std::vector<int64_t> nw_nodes;
     std::vector<double> nw_frac;
-    for (size_t t = 0; t < ent.size(); ++t) {
-        if (t > 0 && ent[t].first == ent[t - 1].first)
-            throw ApiError{SAAMG_INVALID_ARG, "duplicate wall entry"};
-        const int64_t node = ent[t].first / 8;
-        const int d = (int)(ent[t].first % 8);
-        if (nw_nodes.empty() || nw_nodes.back() != node) {
-            nw_nodes.push_back(node);
-            for (int q = 0; q < 6; ++q) nw_frac.push_back(1.0);
-        }
-        nw_frac[6 * (nw_nodes.size() - 1) + d] = dom->wall_s[ent[t].second];
+    nw_nodes.reserve(nw.size());
+    nw_frac.reserve(6 * nw.size());
+    for (const auto& kv : nw) {
+        nw_nodes.push_back(kv.first);
+        for (int q = 0; q < 6; ++q) nw_frac.push_back(kv.second[q]);
     }
 
     saamg_hierarchy* H = new saamg_hierarchy();
@@ -602,6 +630,7 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
         L.h[0] = dom->hx;
         L.h[1] = dom->hy;
         L.h[2] = dom->hz;
+        L.robin_d = dom->robin_d;
         L.unk = (uint64_t*)dmalloc(8 * L.nseg);
         L.irr = (uint64_t*)dmalloc(8 * L.nseg);
         L.base = (int32_t*)dmalloc(4 * L.nseg);

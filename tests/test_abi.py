@@ -51,6 +51,28 @@ def test_domain_builder_matches_oracle(shape, n, nz):
     assert np.max(np.abs(d.wall_s - we["s"]), initial=0.0) <= 1e-14
 
 
+@pytest.mark.parametrize("shape,n,nz", [
+    (W.Shape.cylinder(1.0, 2.0), 33, 21),
+    (W.Shape.ellipse(1.0, 0.6, 4.0), 40, 30),
+    (W.Shape.boxbore(0.8, 4.0, 0.5), 31, 45),
+    (W.Shape(W.BOXBORE, 1.0, 0.7, 2.0, 0.1, 2.0), 9, 11),  # cavity through the ends
+])
+def test_domain_builder_open_ends_matches_oracle(shape, n, nz):
+    d = sa.domain_for(shape, n, n, nz, open_ends=True)
+    o = grid.from_shape(shape, n, n, nz, robin=True)
+    assert d.mask.shape == (nz + 2, n, n) and d.robin_d == 0.5 * shape.length == o.robin_d
+    assert np.array_equal(d.mask.astype(bool), o.mask)
+    we = grid.wall_entries(o)
+    assert np.array_equal(d.wall_node, we["node"])
+    assert np.array_equal(d.wall_dir, we["dir"])
+    assert np.max(np.abs(d.wall_s - we["s"]), initial=0.0) <= 1e-14
+
+
+def test_domain_builder_open_ends_paper_dof_count():
+    d = sa.domain_from_shape(sa.capi.SHAPE_CYLINDER, 1.0, 1.0, 2.0, 128, 128, 256, open_ends=True)
+    assert d.n_unknowns == 3236864
+
+
 def test_domain_builder_paper_dof_count():
     d = sa.domain_from_shape(sa.capi.SHAPE_CYLINDER, 1.0, 1.0, 2.0, 33, 33, 33)
     assert d.n_unknowns == 24583
@@ -84,6 +106,16 @@ def test_setup_rejects_invalid_domains_before_touching_the_gpu():
     with pytest.raises(sa.SaamgError, match="cheb_degree"):
         sa.setup(_dom(m3), sa.VARIANT_LIN, sa.default_options(cheb_degree=0))
     assert "cheb_degree" in sa.capi.last_error()
+    bad = _dom(m3)
+    bad.robin_d = -1.0
+    with pytest.raises(sa.SaamgError, match="robin_d"):
+        sa.setup(bad, sa.VARIANT_LIN)
+    lonely = m.copy()
+    lonely[1, 2, 2] = 1  # end-plane unknown with nothing inside
+    op = _dom(lonely)
+    op.robin_d = 1.0
+    with pytest.raises(sa.SaamgError, match="open-end"):
+        sa.setup(op, sa.VARIANT_LIN)
 
 
 def test_footprint_grows_with_box_and_precision():

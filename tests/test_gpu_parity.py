@@ -27,6 +27,9 @@ CASES = {
     "ell70_quad": (W.Shape.ellipse(1.0, 0.6, 4.0), 70, 45, 66, W.VARIANT_QUAD),
     "boxbore_lin": (W.Shape.boxbore(0.8, 4.0, 0.5), 41, 41, 83, W.VARIANT_LIN),
     "cyl_const": (W.Shape.cylinder(1.0, 2.0), 29, 29, 35, W.VARIANT_CONST),
+    # open (Robin) ends: lattice nz planes, box nz + 2
+    "cyl_robin_lin": (W.Shape.cylinder(1.0, 2.0), 27, 27, 25, W.VARIANT_LIN, True),
+    "ell_robin_quad": (W.Shape.ellipse(1.0, 0.6, 4.0), 40, 26, 44, W.VARIANT_QUAD, True),
 }
 
 
@@ -36,18 +39,21 @@ def _dev():
 
 class Case:
     def __init__(self, name, precision=W.PREC_FP64, opts=None):
-        shape, nx, ny, nz, variant = CASES[name]
-        self.name, self.shape, self.dims, self.variant = name, shape, (nx, ny, nz), variant
+        shape, nx, ny, nz, variant = CASES[name][:5]
+        robin = len(CASES[name]) > 5 and CASES[name][5]
+        self.name, self.shape, self.variant = name, shape, variant
+        self.dims = (nx, ny, nz + 2 * int(robin))  # box
         self.precision = precision
-        print(f"[case] {name} {nx}x{ny}x{nz} variant={variant} prec={precision}", flush=True)
-        self.sys, self.H = solve.build(shape, nx, ny, nz, variant, opts)
-        dom = sa.domain_for(shape, nx, ny, nz)
+        print(f"[case] {name} {nx}x{ny}x{nz} variant={variant} robin={robin} prec={precision}",
+              flush=True)
+        self.sys, self.H = solve.build(shape, nx, ny, nz, variant, opts, robin=robin)
+        dom = sa.domain_for(shape, nx, ny, nz, open_ends=robin)
         o = sa.default_options(precision=precision)
         if opts is not None:
             o.max_coarse, o.cheb_degree = opts.max_coarse, opts.cheb_degree
         self.G = sa.setup(dom, variant, o)
         self.info = sa.hierarchy_info(self.G)
-        self.b = W.rhs(W.small(shape, nx, ny, nz, variant))
+        self.b = W.rhs(W.small(shape, nx, ny, nz, variant, robin=robin))
 
     def to_dev(self, box):
         return torch.from_numpy(np.ascontiguousarray(box, dtype=np.float64).reshape(-1)).to(_dev())
