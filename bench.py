@@ -61,6 +61,10 @@ def parse():
                     help="headline mode: skip the short served-stream leg (p50/p99 latency)")
     ap.add_argument("--line-serve-requests", type=int, default=32,
                     help="requests in the headline mode's served-stream leg")
+    ap.add_argument("--paper-tubes", action="store_true",
+                    help="the paper's tube problems (Tables 7-9) with open ends, one GPU")
+    ap.add_argument("--tube-sizes", default="256,512,1024")
+    ap.add_argument("--tube-reps", type=int, default=2)
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="open-loop arrival rate as a fraction of the closed-loop solves/s")
     return ap.parse_args()
@@ -108,6 +112,80 @@ def pic_bench(args) -> dict:
             "warm_steps_mean_ms": ms_l / len(later),
             "warm_dof_iter_per_s": dom.n_unknowns * it_l / (ms_l * 1e-3),
             "max_rel_res": max(s[2] for s in steps)}
+
+
+# The paper's tube problems (Section 5.3, Tables 7-9): a circular tube inscribed in an n^3
+# lattice with open (Robin) ends, all n planes unknown.  "paper" holds the fastest
+# solution and construction times printed for each, on the Cray XT4/XT3 (Opteron 2.6 GHz).
+PAPER_TUBES = [
+    {"n": 256, "variant": "lin", "table": "Table 7",
+     "paper": {"cores": 512, "solution_s": 0.71, "construction_s": 0.83}},
+    {"n": 512, "variant": "const", "table": "Table 8",
+     "paper": {"cores": 2048, "solution_s": 2.54, "construction_s": 7.58}},
+    {"n": 1024, "variant": "lin", "table": "Table 9",
+     "paper": {"cores": 2048, "solution_s": 10.93, "construction_s": 6.68}},
+]
+
+
+def tube_bench(args) -> dict:
+    """Setup and solve of each tube on one GPU, mixed and fp64 (x0 = 0, rel-res 1e-8)."""
+    import torch
+
+    import paper_0907_4863_amd as sa
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    sizes = [int(v) for v in args.tube_sizes.split(",")]
+    out = []
+    for spec in PAPER_TUBES:
+        n = spec["n"]
+        if n not in sizes:
+            continue
+        variant = {"const": W.VARIANT_CONST, "lin": W.VARIANT_LIN}[spec["variant"]]
+        shape = W.Shape.cylinder(1.0, 2.0)
+        w = W.Workload(f"tube{n}", shape, n, n, n, variant, W.PREC_MIXED,
+                       bunch=W.Bunch(1_000_000, (0.1, 0.1, 0.3), seed=7), robin=True)
+        t0 = time.perf_counter()
+        dom = sa.domain_for(shape, n, n, n, open_ends=True)
+        t_dom = time.perf_counter() - t0
+        print(f"[bench] tube {n}^3: domain built in {t_dom:.1f} s, depositing the bunch",
+              file=sys.stderr, flush=True)
+        b_host = W.rhs(w)
+        b = torch.from_numpy(b_host.reshape(-1)).to(dev)
+        del b_host
+        print(f"[bench] tube {n}^3: {dom.n_unknowns} unknowns, host domain {t_dom:.1f} s",
+              file=sys.stderr, flush=True)
+        rec = {"table": spec["table"], "grid": f"{n}^3", "wall_rule": spec["variant"],
+               "unknowns": dom.n_unknowns, "host_domain_s": t_dom, "paper": spec["paper"]}
+        for tag, prec in (("mixed", sa.MIXED), ("fp64", sa.FP64)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H = sa.setup(dom, variant, sa.default_options(precision=prec))
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
+            x = torch.zeros(w.box_nodes, dtype=torch.float64, device=dev)
+            res = sa.solve(H, b, x, tol=1e-8, max_iter=500)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = args.tube_reps
+            for _ in range(reps):
+                res = sa.solve(H, b, x, tol=1e-8, max_iter=500)
+            torch.cuda.synchronize()
+            t_solve = (time.perf_counter() - t0) / reps
+            info = sa.hierarchy_info(H)
+            rec[tag] = {"setup_s": t_setup, "solve_s": t_solve, "iterations": res["iterations"],
+                        "status": res["status"], "rel_res_true": res["rel_res_true"],
+                        "dof_iter_per_s": dom.n_unknowns * res["iterations"] / t_solve,
+                        "levels": info["n_unknowns"], "device_bytes": info["device_bytes"]}
+            print(f"[bench] tube {n}^3 {tag}: setup {t_setup:.2f} s, solve {t_solve:.3f} s, "
+                  f"{res['iterations']} it, status {res['status']}", file=sys.stderr, flush=True)
+            sa.destroy(H)
+            del x
+            torch.cuda.empty_cache()
+        del b
+        torch.cuda.empty_cache()
+        out.append(rec)
+    return {"tubes": out}
 
 
 def serve_bench(args, n_requests=None) -> dict:
@@ -290,6 +368,20 @@ def main():
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32+f64", "data": "synthetic (seeded 2M-particle bunch, cloud-in-cell)",
             "config": {"workload": res["workload"], "dof": res["dof"]}, "pic": res}), flush=True)
+        return
+    if args.paper_tubes:
+        res = tube_bench(args)
+        big = res["tubes"][-1]
+        print(json.dumps({
+            "metric": "solution time of the paper's open-ended tube problems on one GPU "
+                      "(rel-res 1e-8, x0 = 0, preconditioner built once)",
+            "value": big["mixed"]["solve_s"], "unit": "s", "n_gpus": 1,
+            "steps": args.tube_reps, "warmup": 1, "ms_per_step": 1e3 * big["mixed"]["solve_s"],
+            "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+            "dtype": "f32+f64", "data": "synthetic (seeded 1M-particle Gaussian bunch, cloud-in-cell)",
+            "config": {"workload": f"tube {big['grid']}, {big['wall_rule']} wall rule, open ends, "
+                                   f"{big['unknowns']} unknowns"},
+            **res}), flush=True)
         return
     if args.serve:
         res = serve_bench(args)

@@ -7,6 +7,8 @@
   the oracle's solver in a test, so the oracle evaluates the true residual row by row at
   sampled unknowns (from the wall rule, independently of the GPU operator) and checks
   |r_i| <= tol * ||D^-1/2 b|| for each, which every row of a converged solve satisfies.
+* The tube of the paper's Table 7 (circular tube in a 256^3 lattice, linear rule, open
+  ends, 13,066,240 unknowns): the same row-by-row check, with samples on the end planes.
 """
 import numpy as np
 import pytest
@@ -22,13 +24,13 @@ pytestmark = pytest.mark.gpu
 
 def _solve(w, precision, b):
     dev = torch.device("cuda:0")
-    dom = sa.domain_for(w.shape, w.nx, w.ny, w.nz)
+    dom = sa.domain_for(w.shape, w.nx, w.ny, w.nz, open_ends=w.robin)
     H = sa.setup(dom, w.variant, sa.default_options(precision=precision))
     x = torch.zeros(w.box_nodes, dtype=torch.float64, device=dev)
     res = sa.solve(H, torch.from_numpy(b.reshape(-1)).to(dev), x, tol=w.tol)
     info = sa.hierarchy_info(H)
     sa.destroy(H)
-    return x.cpu().numpy().reshape(w.nz, w.ny, w.nx), res, info
+    return x.cpu().numpy().reshape(w.dims[::-1]), res, info
 
 
 def test_ellipse128_fp64_and_mixed_against_oracle():
@@ -64,6 +66,31 @@ def test_large_grids_sampled_true_residual(name):
     rng = np.random.default_rng(17)
     near = idx[np.nonzero((dom.frac.reshape(6, -1)[:, idx] < 1.0).any(axis=0))[0]]
     sample = np.concatenate([rng.choice(idx, 1500, replace=False), rng.choice(near, 500, replace=False)])
+    r = rows.scaled_residual_rows(dom, w.variant, xg, b, sample)
+    ratio = np.abs(r).max() / (w.tol * bnorm)
+    print(f"iters={res['iterations']} max|r_i|/(tol*||b||)={ratio:.3f}", flush=True)
+    assert ratio <= 1.0
+    assert np.all(xg.reshape(-1)[~dom.mask.reshape(-1)] == 0)
+
+
+def test_paper_tube256_open_ends_sampled_true_residual():
+    n = 256
+    shape = W.Shape.cylinder(1.0, 2.0)
+    w = W.Workload("tube256", shape, n, n, n, W.VARIANT_LIN, W.PREC_MIXED,
+                   bunch=W.Bunch(1_000_000, (0.1, 0.1, 0.3), seed=7), robin=True)
+    print(f"[case] {w.name} open ends", flush=True)
+    b = W.rhs(w)
+    xg, res, info = _solve(w, sa.MIXED, b)
+    assert res["status"] == 0 and res["rel_res_true"] <= w.tol
+    assert info["n_unknowns"][0] == 13066240
+    dom = grid.from_shape(shape, n, n, n, robin=True)
+    idx, diag = operator.diagonal(dom, w.variant)
+    kz = idx // (dom.nx * dom.ny)
+    rho = np.where((kz == 1) | (kz == dom.nz - 2), 0.5, 1.0)
+    bnorm = np.linalg.norm(rho * b.reshape(-1)[idx] / np.sqrt(diag))
+    rng = np.random.default_rng(19)
+    ends = idx[(kz == 1) | (kz == dom.nz - 2)]
+    sample = np.concatenate([rng.choice(idx, 1500, replace=False), rng.choice(ends, 500, replace=False)])
     r = rows.scaled_residual_rows(dom, w.variant, xg, b, sample)
     ratio = np.abs(r).max() / (w.tol * bnorm)
     print(f"iters={res['iterations']} max|r_i|/(tol*||b||)={ratio:.3f}", flush=True)
