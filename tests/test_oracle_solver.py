@@ -273,3 +273,37 @@ def test_pcg_robin_matches_direct_solve(variant):
     assert res.status == 0
     y = spla.spsolve(sys_.As.tocsc(), operator.scaled_rhs(sys_, b))
     assert np.linalg.norm(res.x - y) <= 1e-9 * np.linalg.norm(y)
+
+
+def test_colored_gauss_seidel_is_sequential_gauss_seidel():
+    """The colour-by-colour sweep equals the textbook sweep x <- (D + L)^-1 (b - U x) in the
+    same order (a triangular solve of the permuted matrix)."""
+    import scipy.sparse as sp
+    shape = W.Shape.ellipse(1.0, 0.6, 4.0)
+    sys_, H = solve.build(shape, 45, 30, 60, W.VARIANT_QUAD, amg.Options())
+    lv = H.levels[-1]
+    assert 27 >= np.diff(lv.A.indptr).max() > 7 and lv.n > 50
+    b = np.random.default_rng(3).standard_normal(lv.n)
+    order = np.argsort(amg.gs_colours(lv.lin, lv.dims), kind="stable")
+    Ap = lv.A[order][:, order].tocsr()
+    L = sp.tril(Ap, format="csr")
+    U = sp.triu(Ap, k=1, format="csr")
+    x = np.zeros(lv.n)
+    for _ in range(3):
+        x = spla.spsolve_triangular(L, b[order] - U @ x, lower=True)
+    want = np.empty(lv.n)
+    want[order] = x
+    got = amg.gauss_seidel(lv, b, 3)
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
+
+
+def test_pcg_with_gauss_seidel_coarse_solver_converges():
+    shape = W.Shape.cylinder(1.0, 2.0)
+    for variant in (W.VARIANT_LIN, W.VARIANT_QUAD):
+        o = amg.Options(coarse_solver="gs")
+        sys_, H = solve.build(shape, 33, 33, 33, variant, o)
+        b = W.rhs(W.small(shape, 33, 33, 33, variant))
+        res = solve.solve(sys_, H, b, tol=1e-10)
+        ref = solve.solve(*solve.build(shape, 33, 33, 33, variant), b, tol=1e-10)
+        assert res.status == 0 and res.iterations <= ref.iterations + 3
+        assert np.linalg.norm(res.x - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
