@@ -54,6 +54,8 @@ enum { SAAMG_VARIANT_CONST = 0, SAAMG_VARIANT_LIN = 1, SAAMG_VARIANT_QUAD = 2 };
 /* Precision policy: all fp64, or fp32 hierarchy / V-cycle with fp64 outer CG,
  * dot products, true residual and coarse direct solve. */
 enum { SAAMG_FP64 = 0, SAAMG_MIXED = 1 };
+/* Coarsest-level solver (Section 3.2): dense direct solve, or Gauss-Seidel sweeps. */
+enum { SAAMG_COARSE_DIRECT = 0, SAAMG_COARSE_GS = 1 };
 /* Analytic pipe shapes for saamg_domain_from_shape. */
 enum { SAAMG_SHAPE_CYLINDER = 0, SAAMG_SHAPE_ELLIPSE = 1, SAAMG_SHAPE_BOXBORE = 2 };
 
@@ -96,6 +98,12 @@ typedef struct {
     double cheb_boost;     /* lambda_hi = boost * spectral estimate            default 1.1  */
     int32_t eig_iters;     /* Lanczos steps per level (spectral estimate)      default 15   */
     double omega_scale;    /* prolongator damping omega = scale / lambda_est   default 4/3  */
+    int32_t coarse_solver; /* SAAMG_COARSE_DIRECT: dense fp64 inverse of the coarsest operator;
+                              SAAMG_COARSE_GS: coarse_sweeps Gauss-Seidel sweeps from 0, in fp64,
+                              unknowns visited by colour (parities of the logical coordinates;
+                              multilevel hierarchies; the level's box with its ghost layer must
+                              hold at most 8192 nodes)                         default DIRECT */
+    int32_t coarse_sweeps; /* Gauss-Seidel sweeps (Section 3.2 uses 3)         default 3    */
 } saamg_options;
 
 /* Outcome of one solve. rel_res_* are ||r||/||b|| of the scaled system. */

@@ -6,7 +6,7 @@ small serving loop built on the incremental-solve entry points.
 """
 from . import capi  # noqa: F401
 from .capi import (  # noqa: F401
-    FP64, MIXED, VARIANT_CONST, VARIANT_LIN, VARIANT_QUAD, SaamgError, batch_step,
+    COARSE_DIRECT, COARSE_GS, FP64, MIXED, VARIANT_CONST, VARIANT_LIN, VARIANT_QUAD, SaamgError, batch_step,
     default_options, destroy, domain_for, domain_from_shape, footprint_bytes, hierarchy_info,
     level_apply, level_coefficients, operator_apply, precond_apply, scaling, setup, solve,
     state_create, state_destroy, state_finish, state_query,

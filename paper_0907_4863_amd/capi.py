@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "NOMEM", 3: "HIP_ERROR", 4: "NOT_C
                 5: "BREAKDOWN", 6: "NONFINITE"}
 VARIANT_CONST, VARIANT_LIN, VARIANT_QUAD = 0, 1, 2
 FP64, MIXED = 0, 1
+COARSE_DIRECT, COARSE_GS = 0, 1
 SHAPE_CYLINDER, SHAPE_ELLIPSE, SHAPE_BOXBORE = 0, 1, 2
 OP_APPLY, OP_APPLY_T, OP_PRESMOOTH, OP_RESTRICT, OP_PROLONG = range(5)
 MAX_LEVELS = 16
@@ -38,7 +39,8 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_levels", C.c_int32), ("max_coarse", C.c_int32),
                 ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("cheb_boost", C.c_double), ("eig_iters", C.c_int32),
-                ("omega_scale", C.c_double)]
+                ("omega_scale", C.c_double), ("coarse_solver", C.c_int32),
+                ("coarse_sweeps", C.c_int32)]
 
 
 class Result(C.Structure):

@@ -701,6 +701,50 @@ void dense_invert(double* A, int n, hipStream_t s) {
     HIPCHECK(hipGetLastError());
 }
 
+// Gauss-Seidel sweeps on the coarsest level from x = 0 (the iterative coarse level
+// solver of Section 3.2), in fp64 with the level's fp64 coefficients.  Unknowns are
+// visited colour by colour, colour = parities of the logical coordinates; the 27-point
+// stencil never couples two unknowns of one colour, so each colour is updated in parallel
+// and the result is the sequential sweep in that order.  One workgroup; the iterate lives
+// in LDS (storage size at most kGsMax).
+template <typename TF, typename T, bool SYM>
+__global__ void __launch_bounds__(1024) k_coarse_gs(LCView<double> c, const TF* __restrict__ f,
+                                                    T* __restrict__ x, int sweeps) {
+    __shared__ double xs[kGsMax];
+    const long n = (long)c.sx * c.sy * (c.mz + 2);
+    for (long i = threadIdx.x; i < n; i += blockDim.x) xs[i] = 0.0;
+    __syncthreads();
+    for (int sw = 0; sw < sweeps; ++sw) {
+        for (int col = 0; col < 8; ++col) {
+            for (long i = threadIdx.x; i < n; i += blockDim.x) {
+                const double id = c.invD[i];
+                if (id == 0.0) continue;
+                const long X = i % c.sx - 1, Y = (i / c.sx) % c.sy - 1, Z = i / c.sxy - 1;
+                if ((int)((X & 1) + 2 * (Y & 1) + 4 * (Z & 1)) != col) continue;
+                const double ax = lc_stencil<double, SYM, false>(c, i, [&](long j) { return xs[j]; });
+                xs[i] += id * ((double)f[i] - ax);
+            }
+            __syncthreads();
+        }
+    }
+    for (long i = threadIdx.x; i < n; i += blockDim.x)
+        if (c.invD[i] != 0.0) x[i] = (T)xs[i];
+}
+
+template <typename TF, typename T>
+void coarse_gs(const CoarseLevel& C, const TF* f, T* x, int sweeps, hipStream_t s) {
+    KTimer kt_(T_COARSE, s, C.n_unknowns * (long)(8 * ((C.sym ? 14 : 27) + 1) + sizeof(TF) + sizeof(T)));
+    if (C.sym)
+        hipLaunchKernelGGL((k_coarse_gs<TF, T, true>), dim3(1), dim3(1024), 0, s, C.view<double>(),
+                           f, x, sweeps);
+    else
+        hipLaunchKernelGGL((k_coarse_gs<TF, T, false>), dim3(1), dim3(1024), 0, s, C.view<double>(),
+                           f, x, sweeps);
+    HIPCHECK(hipGetLastError());
+}
+template void coarse_gs<double, double>(const CoarseLevel&, const double*, double*, int, hipStream_t);
+template void coarse_gs<float, float>(const CoarseLevel&, const float*, float*, int, hipStream_t);
+
 // x[cidx[i]] = sum_j Ainv[i][j] f[cidx[j]] in fp64; one wavefront per row.
 template <typename TF, typename T>
 __global__ void __launch_bounds__(256) k_coarse_solve(const double* __restrict__ Ainv,

@@ -28,6 +28,7 @@ namespace saamg {
 constexpr int kWave = 64;
 constexpr int kBlockY = 4;          // 64 x 4 threads per block for box kernels
 constexpr int kThreads = kWave * kBlockY;
+constexpr long kGsMax = 8192;     // coarsest-level storage for the Gauss-Seidel solver (LDS)
 constexpr int kMY = 4;              // wavefronts per block of the level-0 solve-time kernels
 constexpr int kMThreads = kWave * kMY;
 constexpr int kFinThreads = 1024;   // single-block finalisation of partial sums

@@ -110,6 +110,8 @@ void dense_invert(double* A, int n, hipStream_t s);
 void fill_cmap(int32_t* cmap, const long* cidx, int nL, hipStream_t s);
 template <typename TF, typename T>
 void coarse_solve(const double* Ainv, const long* cidx, int nL, const TF* f, T* x, hipStream_t s);
+template <typename TF, typename T>
+void coarse_gs(const CoarseLevel& C, const TF* f, T* x, int sweeps, hipStream_t s);
 void f2d_copy(const float* a, double* b, long n, hipStream_t s);
 
 // ---- reporting helpers

@@ -124,6 +124,8 @@ static T* vcycle(const saamg_hierarchy* H, VBuf<T>& B, int l, const T* f0, T* ou
         if (fine) {
             coarse_solve<T, T>(H->Ainv, H->cidx, H->nL, f0, x, s);
             if (dot) l0_dot<T>(H->l0, fdot, x, dot, s);
+        } else if (H->opt.coarse_solver == SAAMG_COARSE_GS) {
+            coarse_gs<T, T>(H->lc[l - 1], B.f[l], x, H->opt.coarse_sweeps, s);
         } else {
             coarse_solve<T, T>(H->Ainv, H->cidx, H->nL, B.f[l], x, s);
         }
@@ -519,6 +521,10 @@ static void validate_options(const saamg_options& o) {
         throw ApiError{SAAMG_INVALID_ARG, "cheb_ratio must exceed 1; boost and omega_scale > 0"};
     if (o.eig_iters < 1 || o.eig_iters > 1000)
         throw ApiError{SAAMG_INVALID_ARG, "eig_iters must be in 1..1000"};
+    if (o.coarse_solver != SAAMG_COARSE_DIRECT && o.coarse_solver != SAAMG_COARSE_GS)
+        throw ApiError{SAAMG_INVALID_ARG, "coarse_solver must be SAAMG_COARSE_DIRECT or _GS"};
+    if (o.coarse_sweeps < 1 || o.coarse_sweeps > 100)
+        throw ApiError{SAAMG_INVALID_ARG, "coarse_sweeps must be in 1..100"};
 }
 
 static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const saamg_options* opt,
@@ -729,21 +735,30 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
             H->cidx = (long*)dmalloc(8 * H->nL);
             l0_unknown_list(L, H->cidx, s);
         }
-        // dense inverse of the coarsest operator (fp64)
-        const int nL = H->nL;
-        const long nstore = (H->n_levels == 1) ? L.nbox : H->lc.back().nstore;
-        int32_t* cmap = (int32_t*)dmalloc(4 * nstore);
-        HIPCHECK(hipMemset(cmap, 0xff, 4 * nstore));
-        fill_cmap(cmap, H->cidx, nL, s);
-        H->Ainv = (double*)dmalloc(8L * nL * nL);
-        if (H->n_levels == 1)
-            dense_from_l0(L, H->cidx, cmap, nL, H->Ainv, s);
-        else
-            dense_from_lc(H->lc.back(), H->cidx, cmap, nL, H->Ainv, s);
-        dense_invert(H->Ainv, nL, s);
-        HIPCHECK(hipStreamSynchronize(s));
-        dfree(cmap);
-        H->bytes += 8L * nL * nL + 8L * nL;
+        // coarsest level: Gauss-Seidel sweeps on the stored operator (multilevel
+        // hierarchies only), else the dense inverse of the operator (fp64)
+        if (o.coarse_solver == SAAMG_COARSE_GS && H->n_levels == 1)
+            H->opt.coarse_solver = SAAMG_COARSE_DIRECT;
+        if (H->opt.coarse_solver == SAAMG_COARSE_GS) {
+            if (H->lc.back().nstore > kGsMax)
+                throw ApiError{SAAMG_INVALID_ARG,
+                               "coarsest level too large for the Gauss-Seidel solver; lower max_coarse"};
+        } else {
+            const int nL = H->nL;
+            const long nstore = (H->n_levels == 1) ? L.nbox : H->lc.back().nstore;
+            int32_t* cmap = (int32_t*)dmalloc(4 * nstore);
+            HIPCHECK(hipMemset(cmap, 0xff, 4 * nstore));
+            fill_cmap(cmap, H->cidx, nL, s);
+            H->Ainv = (double*)dmalloc(8L * nL * nL);
+            if (H->n_levels == 1)
+                dense_from_l0(L, H->cidx, cmap, nL, H->Ainv, s);
+            else
+                dense_from_lc(H->lc.back(), H->cidx, cmap, nL, H->Ainv, s);
+            dense_invert(H->Ainv, nL, s);
+            HIPCHECK(hipStreamSynchronize(s));
+            dfree(cmap);
+            H->bytes += 8L * nL * nL + 8L * nL;
+        }
         if (o.precision == SAAMG_MIXED) {
             for (auto& C : H->lc) {
                 for (int k = 0; k < 27; ++k)
@@ -908,6 +923,8 @@ void saamg_default_options(saamg_options* o) {
     o->cheb_boost = 1.1;
     o->eig_iters = 15;
     o->omega_scale = 4.0 / 3.0;
+    o->coarse_solver = SAAMG_COARSE_DIRECT;
+    o->coarse_sweeps = 3;
 }
 
 int saamg_setup(const saamg_domain* dom, int variant, const saamg_options* opt, void* stream,

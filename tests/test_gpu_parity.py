@@ -38,7 +38,7 @@ def _dev():
 
 
 class Case:
-    def __init__(self, name, precision=W.PREC_FP64, opts=None):
+    def __init__(self, name, precision=W.PREC_FP64, opts=None, gs=False):
         shape, nx, ny, nz, variant = CASES[name][:5]
         robin = len(CASES[name]) > 5 and CASES[name][5]
         self.name, self.shape, self.variant = name, shape, variant
@@ -46,11 +46,15 @@ class Case:
         self.precision = precision
         print(f"[case] {name} {nx}x{ny}x{nz} variant={variant} robin={robin} prec={precision}",
               flush=True)
+        if gs:
+            opts = amg.Options(coarse_solver="gs")
         self.sys, self.H = solve.build(shape, nx, ny, nz, variant, opts, robin=robin)
         dom = sa.domain_for(shape, nx, ny, nz, open_ends=robin)
         o = sa.default_options(precision=precision)
         if opts is not None:
             o.max_coarse, o.cheb_degree = opts.max_coarse, opts.cheb_degree
+            o.coarse_solver = sa.COARSE_GS if opts.coarse_solver == "gs" else sa.COARSE_DIRECT
+            o.coarse_sweeps = opts.coarse_sweeps
         self.G = sa.setup(dom, variant, o)
         self.info = sa.hierarchy_info(self.G)
         self.b = W.rhs(W.small(shape, nx, ny, nz, variant, robin=robin))
@@ -72,10 +76,10 @@ class Case:
 _cache = {}
 
 
-def case(name, precision=W.PREC_FP64):
-    key = (name, precision)
+def case(name, precision=W.PREC_FP64, gs=False):
+    key = (name, precision, gs)
     if key not in _cache:
-        _cache[key] = Case(name, precision)
+        _cache[key] = Case(name, precision, gs=gs)
     return _cache[key]
 
 
@@ -281,3 +285,28 @@ def test_batched_states_equal_alone():
         torch.cuda.synchronize()
         assert np.array_equal(x.cpu().numpy().reshape(c.dims[::-1]), xa)
         sa.state_destroy(st)
+
+
+# ------------------------------------------------------------------ Gauss-Seidel coarse solver
+
+
+@pytest.mark.parametrize("name", ["ell70_quad", "cyl_robin_lin"])
+def test_gauss_seidel_coarse_solver(name):
+    """The iterative coarse level solver (three coloured Gauss-Seidel sweeps): one V-cycle
+    and the full fp64 solve against the oracle with the same option."""
+    c = case(name, gs=True)
+    assert c.info["n_levels"] > 1
+    r = W.random_box_vector(c.dims, 6) * c.sys.dom.mask
+    want = amg.vcycle(c.H, c.sys.gather(r))
+    z = torch.zeros(np.prod(c.dims), dtype=torch.float64, device=_dev())
+    sa.precond_apply(c.G, c.to_dev(r), z)
+    assert rel(c.sys.gather(z.cpu().numpy()), want) <= 1e-11
+    o = solve.solve(c.sys, c.H, c.b, tol=1e-8)
+    xo = operator.unscale(c.sys, o.x)
+    xg, res = gpu_solve(c, c.b)
+    print(f"[{name} gs] oracle it={o.iterations} gpu it={res['iterations']}")
+    assert res["status"] == 0 and abs(res["iterations"] - o.iterations) <= 1
+    assert rel(c.sys.gather(xg), xo) <= 1e-8
+    cm = case(name, W.PREC_MIXED, gs=True)
+    xm, resm = gpu_solve(cm, cm.b)
+    assert resm["status"] == 0 and rel(cm.sys.gather(xm), xo) <= 1e-6
