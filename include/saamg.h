@@ -237,6 +237,50 @@ int saamg_operator_apply(saamg_hierarchy* H, const double* d_x, double* d_y, voi
 /* D^-1/2 as a device box vector (0 at non-unknowns), fp64. */
 int saamg_scaling(saamg_hierarchy* H, double* d_sigma, void* stream);
 
+/* ---- particle coupling (Section 1 and Section 4: charge to the grid, field back) -------
+ * A grid is the box of a discrete domain (nx, ny, nz), the box plane of the lattice's
+ * plane 0 (1 with open ends, else 0), the coordinates of lattice node (0, 0, 0), the
+ * spacings, and robin_d (> 0: open ends, as in saamg_domain).  The lattice has nx, ny and
+ * nz - 2*z_offset nodes; its cells are [i, i+1) x [j, j+1) x [k, k+1).
+ */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t z_offset;
+    double origin[3];
+    double h[3];
+    double robin_d;
+} saamg_grid;
+
+typedef struct saamg_pic saamg_pic;
+
+/*
+ * Context for up to max_particles particles on grid g (copied).  mask: host, nx*ny*nz
+ * bytes, nonzero = unknown (the domain's mask), or NULL for "every node".  Allocates the
+ * sort buffers on the current device once.
+ */
+int saamg_pic_create(const saamg_grid* g, const uint8_t* mask, int64_t max_particles,
+                     saamg_pic** out);
+/*
+ * Cloud-in-cell deposition: d_pos is device (n, 3) fp64 positions (x, y, z interleaved),
+ * each particle carries charge q; d_rho (device, box vector, fp64) receives the density
+ * nodal charge / (hx hy hz) at every box node (0 where no particle contributes).
+ * Particles outside every lattice cell are dropped.  Deterministic: each node sums its
+ * adjacent cells' particles in a fixed order (cells by index, particles by cell after a
+ * stable sort), so repeated calls give bitwise equal results.  Queued on stream.
+ */
+int saamg_pic_deposit(saamg_pic* P, const double* d_pos, int64_t n, double q, double* d_rho,
+                      void* stream);
+/*
+ * Field gather: d_E (device, (n, 3) fp64) receives E = -grad(phi) at the particles, the
+ * trilinear interpolation of central differences of phi (device box vector, e.g. a
+ * solution of saamg_solve) at the eight corners of each particle's cell.  phi counts as 0
+ * off the domain and beyond the box; beyond an open end it is eq. inlet's
+ * u(x'') - (2 h_z / d) u(x).  Particles outside every cell get E = 0.  Queued on stream.
+ */
+int saamg_pic_gather(saamg_pic* P, const double* d_phi, const double* d_pos, int64_t n,
+                     double* d_E, void* stream);
+int saamg_pic_destroy(saamg_pic* P);
+
 /* ---- kernel timing (diagnostics) ----------------------------------------------------
  * When enabled for a kernel class, every launch of that class records a pair of HIP
  * events on its own stream; saamg_timer_read synchronises on them and returns the

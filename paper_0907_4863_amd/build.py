@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsaamg.so")
-SOURCES = ["fine.hip", "coarse.hip", "solver.hip", "timer.hip", "domain.cpp"]
+SOURCES = ["fine.hip", "coarse.hip", "solver.hip", "pic.hip", "timer.hip", "domain.cpp"]
 ARCH = os.environ.get("SAAMG_ARCH", "gfx950")
 
 # Packed fp32 instructions are disabled for all device code.

@@ -43,6 +43,11 @@ class Options(C.Structure):
                 ("coarse_sweeps", C.c_int32)]
 
 
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("z_offset", C.c_int32),
+                ("origin", C.c_double * 3), ("h", C.c_double * 3), ("robin_d", C.c_double)]
+
+
 class Result(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("status", C.c_int32), ("replacements", C.c_int32),
                 ("rel_res_true", C.c_double), ("rel_res_recursive", C.c_double),
@@ -88,6 +93,10 @@ def lib() -> C.CDLL:
                                           C.POINTER(C.c_uint8), _DP, C.POINTER(C.c_int64)]
     L.saamg_setup.argtypes = [C.POINTER(Domain), C.c_int, C.POINTER(Options), _P, C.POINTER(_P)]
     L.saamg_solve.argtypes = [_P, _P, _P, _P, C.c_double, C.c_int, _P, C.POINTER(Result)]
+    L.saamg_pic_create.argtypes = [C.POINTER(Grid), C.POINTER(C.c_uint8), C.c_int64, C.POINTER(_P)]
+    L.saamg_pic_deposit.argtypes = [_P, _P, C.c_int64, C.c_double, _P, _P]
+    L.saamg_pic_gather.argtypes = [_P, _P, _P, C.c_int64, _P, _P]
+    L.saamg_pic_destroy.argtypes = [_P]
     L.saamg_destroy.argtypes = [_P]
     L.saamg_hierarchy_info.argtypes = [_P, C.POINTER(Info)]
     L.saamg_footprint_bytes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
@@ -319,6 +328,58 @@ def state_destroy(S: State) -> None:
     if S.handle:
         lib().saamg_state_destroy(S.handle)
         S.handle = 0
+
+
+# --------------------------------------------------------------------------- particles
+
+
+class Pic:
+    """Particle-coupling context (saamg_pic) on the grid of a discrete domain."""
+
+    def __init__(self, handle: int, nbox: int):
+        self.handle = handle
+        self.nbox = nbox
+
+    def __del__(self):
+        pic_destroy(self)
+
+
+def pic_create(dom: HostDomain, origin, max_particles: int, use_mask: bool = True) -> Pic:
+    """Context for ``dom``'s box; ``origin`` = coordinates of lattice node (0, 0, 0)."""
+    g = Grid()
+    g.nx, g.ny, g.nz = dom.nx, dom.ny, dom.nz
+    g.z_offset = 1 if dom.robin_d > 0.0 else 0
+    for a in range(3):
+        g.origin[a] = float(origin[a])
+        g.h[a] = dom.h[a]
+    g.robin_d = dom.robin_d
+    mp = dom.mask.ctypes.data_as(C.POINTER(C.c_uint8)) if use_mask else None
+    h = _P()
+    _check(lib().saamg_pic_create(C.byref(g), mp, int(max_particles), C.byref(h)))
+    return Pic(h.value, dom.nx * dom.ny * dom.nz)
+
+
+def _pptr(t, n: int) -> int:
+    """Device pointer of a contiguous float64 (n, 3) particle array."""
+    return _dptr(t, 3 * n)
+
+
+def pic_deposit(P: Pic, pos, q: float, rho, stream=None) -> None:
+    n = pos.shape[0] if pos.dim() == 2 else pos.numel() // 3
+    _check(lib().saamg_pic_deposit(P.handle, _pptr(pos, n) if n else None, n, float(q),
+                                   _dptr(rho, P.nbox), _stream(stream)))
+
+
+def pic_gather(P: Pic, phi, pos, E, stream=None) -> None:
+    n = pos.shape[0] if pos.dim() == 2 else pos.numel() // 3
+    _check(lib().saamg_pic_gather(P.handle, _dptr(phi, P.nbox), _pptr(pos, n) if n else None, n,
+                                  _pptr(E, n) if n else None, _stream(stream)))
+
+
+def pic_destroy(P: Pic) -> None:
+    if getattr(P, "handle", 0):
+        lib().saamg_pic_destroy(P.handle)
+        P.handle = 0
 
 
 # --------------------------------------------------------------------------- components

@@ -3,6 +3,22 @@
 
 #include "common.h"
 
+// Particle-coupling context (grid copy, device mask, sort buffers).
+struct saamg_pic {
+    int device = 0;
+    saamg_grid g{};
+    int nxl = 0, nyl = 0, nzl = 0;  // lattice nodes per axis
+    long ncell = 0;                 // lattice cells
+    int key_bits = 1;
+    int64_t cap = 0;                // particle capacity
+    uint8_t* mask = nullptr;        // box, nonzero = unknown
+    uint32_t *key = nullptr, *key_s = nullptr;
+    int32_t *idx = nullptr, *idx_s = nullptr;
+    int32_t *cstart = nullptr, *cend = nullptr;
+    void* tmp = nullptr;
+    size_t tmp_bytes = 0;
+};
+
 namespace saamg {
 
 // Scalar slots in the per-solve device array `scal`.
@@ -14,6 +30,10 @@ enum Slot {
 enum FinOp { FIN_STORE = 0, FIN_ALPHA, FIN_RHO_INIT, FIN_RHO, FIN_LZ_ALPHA, FIN_LZ_BETA, FIN_NORM, FIN_RESTORE_RHO };
 // Chebyshev step kinds.
 enum ChebMode { CHEB_ZERO1 = 0, CHEB_ZERO2, CHEB_FIRST, CHEB_NEXT };
+
+void pic_deposit(saamg_pic* P, const double* pos, long n, double q, double* rho, hipStream_t s);
+void pic_gather(saamg_pic* P, const double* phi, const double* pos, long n, double* E, hipStream_t s);
+size_t pic_sort_bytes(long n, int bits);
 
 // Number of partial sums (blocks) written by the level-0 reduction kernels.
 long l0_blocks(const FineLevel& L);

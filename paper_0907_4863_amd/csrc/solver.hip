@@ -1216,3 +1216,89 @@ int saamg_scaling(saamg_hierarchy* H, double* d_sigma, void* stream) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ particle coupling
+
+int saamg_pic_create(const saamg_grid* g, const uint8_t* mask, int64_t max_particles,
+                     saamg_pic** out) {
+    return guarded([&] {
+        if (!g || !out) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        *out = nullptr;
+        if (g->z_offset != 0 && g->z_offset != 1)
+            throw ApiError{SAAMG_INVALID_ARG, "z_offset must be 0 or 1"};
+        const int nzl = g->nz - 2 * g->z_offset;
+        if (g->nx < 2 || g->ny < 2 || nzl < 2) throw ApiError{SAAMG_INVALID_ARG, "grid too small"};
+        if (!(g->h[0] > 0) || !(g->h[1] > 0) || !(g->h[2] > 0) || g->robin_d < 0.0)
+            throw ApiError{SAAMG_INVALID_ARG, "spacings must be positive, robin_d >= 0"};
+        if (max_particles < 0 || max_particles > 2000000000L)
+            throw ApiError{SAAMG_INVALID_ARG, "max_particles must be in 0..2e9"};
+        const long ncell = (long)(g->nx - 1) * (g->ny - 1) * (nzl - 1);
+        if (ncell >= 4000000000L) throw ApiError{SAAMG_INVALID_ARG, "too many lattice cells"};
+        const long nbox = (long)g->nx * g->ny * g->nz;
+        saamg_pic* P = new saamg_pic();
+        try {
+            HIPCHECK(hipGetDevice(&P->device));
+            P->g = *g;
+            P->nxl = g->nx;
+            P->nyl = g->ny;
+            P->nzl = nzl;
+            P->ncell = ncell;
+            P->cap = max_particles;
+            while ((1L << P->key_bits) <= ncell) ++P->key_bits;
+            P->mask = (uint8_t*)dmalloc(nbox);
+            if (mask) {
+                HIPCHECK(hipMemcpy(P->mask, mask, nbox, hipMemcpyHostToDevice));
+            } else {
+                HIPCHECK(hipMemset(P->mask, 1, nbox));
+            }
+            const long c = std::max<long>(max_particles, 1);
+            P->key = (uint32_t*)dmalloc(4 * c);
+            P->key_s = (uint32_t*)dmalloc(4 * c);
+            P->idx = (int32_t*)dmalloc(4 * c);
+            P->idx_s = (int32_t*)dmalloc(4 * c);
+            P->cstart = (int32_t*)dmalloc(4 * ncell);
+            P->cend = (int32_t*)dmalloc(4 * ncell);
+            P->tmp_bytes = pic_sort_bytes(c, P->key_bits);
+            P->tmp = dmalloc(std::max<size_t>(P->tmp_bytes, 16));
+        } catch (...) {
+            saamg_pic_destroy(P);
+            throw;
+        }
+        *out = P;
+        return (int)SAAMG_OK;
+    });
+}
+
+int saamg_pic_deposit(saamg_pic* P, const double* d_pos, int64_t n, double q, double* d_rho,
+                      void* stream) {
+    return guarded([&] {
+        if (!P || !d_rho || (n > 0 && !d_pos)) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        if (n < 0 || n > P->cap) throw ApiError{SAAMG_INVALID_ARG, "n exceeds the context's capacity"};
+        HIPCHECK(hipSetDevice(P->device));
+        pic_deposit(P, d_pos, (long)n, q, d_rho, (hipStream_t)stream);
+        return (int)SAAMG_OK;
+    });
+}
+
+int saamg_pic_gather(saamg_pic* P, const double* d_phi, const double* d_pos, int64_t n,
+                     double* d_E, void* stream) {
+    return guarded([&] {
+        if (!P || !d_phi || (n > 0 && (!d_pos || !d_E)))
+            throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        if (n < 0) throw ApiError{SAAMG_INVALID_ARG, "negative particle count"};
+        HIPCHECK(hipSetDevice(P->device));
+        pic_gather(P, d_phi, d_pos, (long)n, d_E, (hipStream_t)stream);
+        return (int)SAAMG_OK;
+    });
+}
+
+int saamg_pic_destroy(saamg_pic* P) {
+    return guarded([&] {
+        if (!P) return (int)SAAMG_OK;
+        for (void* p : {(void*)P->mask, (void*)P->key, (void*)P->key_s, (void*)P->idx,
+                        (void*)P->idx_s, (void*)P->cstart, (void*)P->cend, P->tmp})
+            if (p) dfree(p);
+        delete P;
+        return (int)SAAMG_OK;
+    });
+}
