@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--pic", action="store_true",
                     help="PIC sequence: moving bunch, one hierarchy, warm-started solves")
     ap.add_argument("--pic-steps", type=int, default=20)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="headline mode: skip the Gauss-Seidel coarse-solver leg")
     ap.add_argument("--no-serve", action="store_true",
                     help="headline mode: skip the short served-stream leg (p50/p99 latency)")
     ap.add_argument("--line-serve-requests", type=int, default=32,
@@ -71,10 +73,12 @@ def parse():
 
 
 def pic_bench(args) -> dict:
-    """Successive solves on the 192x192x1024 cylinder (L = 8) as a 2M-particle bunch moves
-    0.02 along z per step: the hierarchy is built once and each solve starts from the
-    previous solution (Section 4: previous time step as initial guess; Section 5: reuse of
-    the preconditioner).  Deposition runs on the host between steps and is not timed."""
+    """Successive PIC steps on the 192x192x1024 cylinder (L = 8) as a 2M-particle bunch moves
+    0.02 along z per step.  Each step deposits the bunch on the GPU (cloud-in-cell), solves
+    with the hierarchy built once, starting from the previous solution (Section 4: previous
+    time step as initial guess; Section 5: reuse of the preconditioner), and gathers
+    E = -grad(phi) back to the particles.  The rigid shift of the bunch stands in for the
+    particle push and is not timed."""
     import torch
 
     import paper_0907_4863_amd as sa
@@ -83,34 +87,52 @@ def pic_bench(args) -> dict:
     w = W.c5_cylinder192(sa.MIXED)
     dev = torch.device("cuda:0")
     dom = sa.domain_for(w.shape, w.nx, w.ny, w.nz)
-    parts = W.draw_particles(w.bunch)
+    base = torch.from_numpy(W.draw_particles(w.bunch)).to(dev)
+    n = base.shape[0]
+    origin = (-w.shape.a, -w.shape.b, -0.5 * w.shape.length)
     t0 = time.perf_counter()
     H = sa.setup(dom, w.variant, sa.default_options(precision=sa.MIXED))
+    P = sa.pic_create(dom, origin, n)
     torch.cuda.synchronize()
     setup_ms = 1e3 * (time.perf_counter() - t0)
     xa = torch.zeros(w.box_nodes, dtype=torch.float64, device=dev)
     xb = torch.zeros_like(xa)
+    rho = torch.zeros_like(xa)
+    E = torch.empty_like(base)
     steps = []
     for k in range(args.pic_steps):
-        b = torch.from_numpy(W.rhs(w, shift_z=W.pic_shift(k), particles=parts).reshape(-1)).to(dev)
+        pos = base.clone()
+        pos[:, 2] += W.pic_shift(k)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = sa.solve(H, b, xb, x0=(xa if k > 0 else None), tol=w.tol)
+        sa.pic_deposit(P, pos, 1.0 / n, rho)
         torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0)
-        steps.append((res["iterations"], ms, res["rel_res_true"]))
+        t1 = time.perf_counter()
+        res = sa.solve(H, rho, xb, x0=(xa if k > 0 else None), tol=w.tol)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        sa.pic_gather(P, xb, pos, E)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        steps.append((res["iterations"], 1e3 * (t2 - t1), res["rel_res_true"], 1e3 * (t1 - t0),
+                      1e3 * (t3 - t2)))
         xa, xb = xb, xa
-        print(f"[bench] pic step {k}: {res['iterations']} it, {ms:.1f} ms", file=sys.stderr, flush=True)
+        print(f"[bench] pic step {k}: deposit {1e3 * (t1 - t0):.2f} ms, solve {res['iterations']} it "
+              f"{1e3 * (t2 - t1):.1f} ms, gather {1e3 * (t3 - t2):.2f} ms", file=sys.stderr, flush=True)
+    sa.pic_destroy(P)
     sa.destroy(H)
     later = steps[1:] if len(steps) > 1 else steps
     it_l = sum(s[0] for s in later)
     ms_l = sum(s[1] for s in later)
-    return {"workload": "cylinder R=1 L=8 192x192x1024, linear wall rule, mixed",
-            "dof": dom.n_unknowns, "setup_ms": setup_ms, "steps": len(steps),
+    return {"workload": "cylinder R=1 L=8 192x192x1024, linear wall rule, mixed, 2M particles",
+            "dof": dom.n_unknowns, "particles": n, "setup_ms": setup_ms, "steps": len(steps),
             "first_step": {"iterations": steps[0][0], "ms": steps[0][1]},
             "warm_steps_mean_iterations": it_l / len(later),
             "warm_steps_mean_ms": ms_l / len(later),
             "warm_dof_iter_per_s": dom.n_unknowns * it_l / (ms_l * 1e-3),
+            "deposit_ms_mean": sum(s[3] for s in steps) / len(steps),
+            "gather_ms_mean": sum(s[4] for s in steps) / len(steps),
+            "pic_step_ms_mean": sum(s[1] + s[3] + s[4] for s in later) / len(later),
             "max_rel_res": max(s[2] for s in steps)}
 
 
@@ -496,6 +518,31 @@ def main():
         }
         line["kernels"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                                for kk, vv in v.items()} for k, v in kern.items()}
+    if not args.no_variants and "mixed" in out:
+        # the paper's iterative coarse level solver (3 Gauss-Seidel sweeps) on the same b
+        t0 = time.perf_counter()
+        H = sa.setup(dom, w.variant, sa.default_options(precision=sa.MIXED,
+                                                         coarse_solver=sa.COARSE_GS))
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        x = torch.zeros(nbox, dtype=torch.float64, device=dev)
+        sa.solve(H, b, x, tol=1e-8, max_iter=500)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            rg = sa.solve(H, b, x, tol=1e-8, max_iter=500)
+        torch.cuda.synchronize()
+        t_solve = (time.perf_counter() - t0) / reps
+        sa.destroy(H)
+        line["coarse_gauss_seidel"] = {
+            "coarse_solver": "3 Gauss-Seidel sweeps (mixed path; direct solve is the default)",
+            "setup_ms": 1e3 * t_setup, "ms_per_step": 1e3 * t_solve,
+            "iterations": rg["iterations"], "rel_res_true": rg["rel_res_true"],
+            "value": dof * rg["iterations"] / t_solve}
+        print(f"[bench] coarse Gauss-Seidel: setup {1e3 * t_setup:.1f} ms, "
+              f"{1e3 * t_solve:.2f} ms per solve, {rg['iterations']} it", file=sys.stderr, flush=True)
+        del x
     if not args.no_serve:
         sv = serve_bench(args, n_requests=args.line_serve_requests)
         m, f = sv["open_loop_mixed"], sv["open_loop_fp64"]
