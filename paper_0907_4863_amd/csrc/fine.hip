@@ -101,6 +101,21 @@ __device__ inline void l0_tile(const L0View<T>& v, int* seg, int* y, int* bz) {
     *bz = (int)(t / v.gy);
 }
 
+// Box index of a lane's node, split into a wave-uniform part and the lane's offset, so
+// that an access through at() addresses memory as a scalar base plus a 32-bit vector
+// offset and needs no 64-bit vector address arithmetic.
+struct Idx {
+    long b;      // wave-uniform
+    unsigned o;  // per lane
+    __device__ operator long() const { return b + (long)o; }
+};
+template <class E>
+__device__ __forceinline__ E& at(E* a, Idx k) {
+    // the byte offset is formed in 32 bits (lane offsets are small)
+    using C = std::conditional_t<std::is_const<E>::value, const char, char>;
+    return *reinterpret_cast<E*>(reinterpret_cast<C*>(a + k.b) + k.o * (unsigned)sizeof(E));
+}
+
 // 64-bit value of lane k of a wavefront, as a wave-uniform (scalar) value.
 __device__ inline uint64_t lane_u64(uint64_t v, int k) {
     const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, k);
@@ -134,10 +149,27 @@ struct PlaneLoads {
     bool irr;
     bool ins1;    // lane inside the row's unknown span in plane z+1
     int rk;
+    bool tab;     // the row has irregular nodes: t holds table rows
     TX nxt, ym, yp, edge;  // X at (x, y, z+1), (x, y-1, z), (x, y+1, z), lane-edge x-neighbour
     T t[6];                // table row of an irregular node
     FV fv;
 };
+
+// An empty use of every 32-bit word of a loaded record.  The march calls it at the start
+// of each plane step so that, on every path through the step (including the ones that
+// skip the plane's arithmetic), the plane's loads have landed before the loop goes round.
+// Without it a load can still be in flight at the loop back-edge, and the compiler must
+// wait for all outstanding loads, the next plane's included, before it reuses that
+// load's registers, which serialises the two-plane pipeline.
+template <class R>
+__device__ __forceinline__ void settle(const R& r) {
+    if constexpr (sizeof(R) >= 4) {
+        uint32_t w[sizeof(R) / 4];
+        __builtin_memcpy(w, &r, sizeof(w));
+#pragma unroll
+        for (unsigned k = 0; k < sizeof(R) / 4; ++k) asm volatile("" ::"v"(w[k]));
+    }
+}
 
 // Lane clamped to the span of the set bits of u (u == 0: lane 0).
 __device__ inline int span_lane(uint64_t u, int lane) {
@@ -148,8 +180,8 @@ __device__ inline int span_lane(uint64_t u, int lane) {
 
 template <typename T, bool STENCIL, bool TR, class Load, class Fetch, class Body>
 __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch, Body body) {
-    using FV = decltype(fetch(0L, 0, 0, 0, false, 0));
-    using TX = decltype(X(0L));
+    using FV = decltype(fetch(Idx{0, 0u}, 0, 0, 0, false, 0));
+    using TX = decltype(X(Idx{0, 0u}));
     int bx, y, bz;
     l0_tile(v, &bx, &y, &bz);
     const int lane = threadIdx.x;
@@ -172,10 +204,10 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
     if (__ballot(wu != 0) == 0) return;
     const int x0 = bx * kWave;
     const long rb = x0 + nx * y;  // box index of lane 0 at plane 0
-    const long eo = lane == 0 ? -1 : (lane == kWave - 1 ? 1 : 0);
+    const int eo = lane == 0 ? -1 : (lane == kWave - 1 ? 1 : 0);
     // X of this lane in plane q (k = q - (z0 - 1)), read inside the plane's span
     auto load_x = [&](int k, long q) {
-        return X(rb + nxy * q + span_lane(lane_u64(wu, k), lane));
+        return X(Idx{rb + nxy * q, (unsigned)span_lane(lane_u64(wu, k), lane)});
     };
     auto load_plane = [&](int q) {
         PlaneLoads<T, TX, FV> P;
@@ -186,18 +218,28 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
         const bool ins = lc == lane;
         P.ins1 = span_lane(lane_u64(wu, k + 1), lane) == lane;
         P.irr = (r >> lane) & 1ull;
-        P.rk = P.irr ? __builtin_amdgcn_readlane(wb, k) + __popcll(r & ((1ull << lane) - 1ull)) : 0;
-        const long i = rb + nxy * q + lc;
-        P.fv = fetch(i, x0 + lc, y, q, P.irr, P.rk);
+        const int rbase = __builtin_amdgcn_readlane(wb, k);
+        const unsigned rofs = __popcll(r & ((1ull << lane) - 1ull));
+        P.rk = P.irr ? rbase + (int)rofs : 0;
+        const long ib = rb + nxy * q;
+        P.fv = fetch(Idx{ib, (unsigned)lc}, x0 + lc, y, q, P.irr, P.rk);
         if (STENCIL) {
             P.nxt = load_x(k + 1, q + 1);
-            P.ym = X(i - nx);
-            P.yp = X(i + nx);
-            P.edge = X(i + (ins ? eo : 0));
-            // rows with an irregular node: every lane reads a table row (slot 0 if regular)
-            if (r != 0) {
+            P.ym = X(Idx{ib - nx, (unsigned)lc});
+            P.yp = X(Idx{ib + nx, (unsigned)lc});
+            // the edge lanes' outer x-neighbours (from a base one node lower, so that the
+            // offset stays non-negative)
+            P.edge = X(Idx{ib - 1, (unsigned)(lc + 1 + (ins ? eo : 0))});
+            // rows with an irregular node: every lane reads a table row (its own slot if
+            // irregular, else the row's first)
+            P.tab = r != 0;
+            if (P.tab) {
+                const Idx ti{rbase, P.irr ? rofs : 0u};
 #pragma unroll
-                for (int d = 0; d < 6; ++d) P.t[d] = tb[d][P.rk];
+                for (int d = 0; d < 6; ++d) P.t[d] = at(tb[d], ti);
+            } else {
+#pragma unroll
+                for (int d = 0; d < 6; ++d) P.t[d] = T(0);
             }
         }
         return P;
@@ -209,8 +251,21 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
         if (span_lane(lane_u64(wu, 0), lane) != lane) zm = TX(0);
         if (span_lane(lane_u64(wu, 1), lane) != lane) c = TX(0);
     }
-    // Arithmetic of plane z from its loads P.
+    auto settle_plane = [&](const PlaneLoads<T, TX, FV>& P) {
+        if (STENCIL) {
+            settle(P.nxt);
+            settle(P.ym);
+            settle(P.yp);
+            settle(P.edge);
+            settle(P.t);
+        }
+        settle(P.fv);
+    };
+    // Arithmetic of plane z from its loads P (only the settling when the plane is past the
+    // tile).
     auto step = [&](const PlaneLoads<T, TX, FV>& P, int z) {
+        settle_plane(P);
+        if (z >= z1) return;
         // X at (x, y, z+1); zero where that plane's span does not reach
         const TX zp = (STENCIL && P.ins1) ? P.nxt : TX(0);
         if (P.u != 0) {
@@ -222,7 +277,7 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
                 if (lane == kWave - 1) xp = P.edge;
             }
             if ((P.u >> lane) & 1ull) {
-                const long i = rb + nxy * z + lane;
+                const Idx i{rb + nxy * z, (unsigned)lane};
                 const int r = P.rk;
                 T ax = T(0);
                 if (STENCIL) {
@@ -243,14 +298,14 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
         }
     };
     // Two register sets take turns: while one plane is computed the next one's loads are
-    // in flight, and no copy between the sets forces an early wait.  The last steps
-    // reload their own plane instead of reading past the tile.
+    // in flight, and no copy between the sets forces an early wait.  Loads past the tile
+    // re-read its last plane; the loop has no early exit, so that no path reaches the
+    // loop head with a plane's loads unsettled.
     PlaneLoads<T, TX, FV> pa = load_plane(z0);
     for (int z = z0; z < z1; z += 2) {
-        PlaneLoads<T, TX, FV> pb = load_plane(z + 1 < z1 ? z + 1 : z);
+        PlaneLoads<T, TX, FV> pb = load_plane(min(z + 1, z1 - 1));
         step(pa, z);
-        if (z + 1 >= z1) break;
-        pa = load_plane(z + 2 < z1 ? z + 2 : z + 1);
+        pa = load_plane(min(z + 2, z1 - 1));
         step(pb, z + 1);
     }
 }
@@ -592,8 +647,8 @@ void l0_unknown_list(const FineLevel& L, long* out, hipStream_t s) {
 template <typename T, bool TR>
 __global__ void __launch_bounds__(kMThreads) k_l0_apply(L0View<T> v, const T* __restrict__ xv,
                                                        T* __restrict__ yv) {
-    l0_march<T, true, TR>(v, [&](long j) { return xv[j]; }, NOFETCH,
-                          [&](long i, NoVals, T, T ax, int, int, int, bool, int) { yv[i] = ax; });
+    l0_march<T, true, TR>(v, [&](Idx j) { return at(xv, j); }, NOFETCH,
+                          [&](Idx i, NoVals, T, T ax, int, int, int, bool, int) { at(yv, i) = ax; });
 }
 
 template <typename T>
@@ -618,9 +673,9 @@ __global__ void __launch_bounds__(kMThreads) k_l0_lz_start(L0View<double> v, dou
     __shared__ double lds[kMThreads / kWave];
     double a0 = 0.0;
     l0_march<double, false, false>(v, [&](long) { return 0.0; }, NOFETCH,
-                                   [&](long i, NoVals, double, double, int, int, int, bool, int) {
+                                   [&](Idx i, NoVals, double, double, int, int, int, bool, int) {
                                        const double sv = start_value(i);
-                                       w[i] = sv;
+                                       at(w, i) = sv;
                                        a0 += sv * sv;
                                    });
     const double s0 = block_sum(a0, lds);
@@ -646,8 +701,8 @@ __global__ void __launch_bounds__(kMThreads) k_l0_lz_apply(L0View<double> v,
     const long nx = v.nx, nxy = v.nxy;
     double a0 = 0.0;
     l0_march<double, true, false>(
-        v, [&](long j) { return vin[j]; }, NOFETCH,
-        [&](long i, NoVals, double qr, double aqr, int, int, int, bool irr, int r) {
+        v, [&](Idx j) { return at(vin, j); }, NOFETCH,
+        [&](Idx i, NoVals, double qr, double aqr, int, int, int, bool irr, int r) {
             const double q = sc * qr, aq = sc * aqr;
             double o = aq;
             if (!SYM && irr) {
@@ -656,7 +711,7 @@ __global__ void __launch_bounds__(kMThreads) k_l0_lz_apply(L0View<double> v,
                                             v.tabT[4][r] * vin[i - nxy] + v.tabT[5][r] * vin[i + nxy]);
                 o = 0.5 * (aq + at);
             }
-            u[i] = o;
+            at(u, i) = o;
             a0 += q * o;
         });
     const double s0 = block_sum(a0, lds);
@@ -685,9 +740,9 @@ __global__ void __launch_bounds__(kMThreads) k_l0_lz_update(L0View<double> v,
     const double ac = scal[S_ALPHA] * scal[S_LZ_S], bp = scal[S_LZ_B] * scal[S_LZ_SP];
     double a0 = 0.0;
     l0_march<double, false, false>(v, [&](long) { return 0.0; }, NOFETCH,
-                                   [&](long i, NoVals, double, double, int, int, int, bool, int) {
-                                       const double w = u[i] - ac * cur[i] - bp * prev[i];
-                                       prev[i] = w;
+                                   [&](Idx i, NoVals, double, double, int, int, int, bool, int) {
+                                       const double w = at(u, i) - ac * at(cur, i) - bp * at(prev, i);
+                                       at(prev, i) = w;
                                        a0 += w * w;
                                    });
     const double s0 = block_sum(a0, lds);
@@ -715,19 +770,19 @@ __global__ void __launch_bounds__(kMThreads) k_l0_cheb(L0View<T> v, const TF* __
                                                       const double* __restrict__ fdot, double* part) {
     __shared__ double lds[kMThreads / kWave];
     double acc = 0.0;
-    auto fetch = [&](long i, int, int, int, bool, int) {
+    auto fetch = [&](Idx i, int, int, int, bool, int) {
         Vals<T, 2> a;
-        a.v[0] = (MODE == CHEB_FIRST || MODE == CHEB_NEXT || MODE == CHEB_ZERO1) ? (T)f[i] : T(0);
-        a.v[1] = (MODE == CHEB_NEXT) ? din[i] : T(0);
+        a.v[0] = (MODE == CHEB_FIRST || MODE == CHEB_NEXT || MODE == CHEB_ZERO1) ? (T)at(f, i) : T(0);
+        a.v[1] = (MODE == CHEB_NEXT) ? at(din, i) : T(0);
         Vals<double, 1> b;
-        b.v[0] = DOT ? fdot[i] : 0.0;
+        b.v[0] = DOT ? at(fdot, i) : 0.0;
         struct R {
             Vals<T, 2> a;
             Vals<double, 1> b;
         };
         return R{a, b};
     };
-    auto body = [&](long i, auto fv, T cv, T ax, int, int, int, bool, int) {
+    auto body = [&](Idx i, auto fv, T cv, T ax, int, int, int, bool, int) {
         const T fi = fv.a.v[0];
         T xo, dn;
         if (MODE == CHEB_ZERO1) {
@@ -742,16 +797,16 @@ __global__ void __launch_bounds__(kMThreads) k_l0_cheb(L0View<T> v, const TF* __
             dn = (MODE == CHEB_FIRST) ? c20 * r : c1 * fv.a.v[1] + c2 * r;
             xo = cv + dn;
         }
-        xout[i] = xo;
-        if (dout) dout[i] = dn;
+        at(xout, i) = xo;
+        if (dout) at(dout, i) = dn;
         if (DOT) acc += fv.b.v[0] * (double)xo;
     };
     if (MODE == CHEB_ZERO1)
         l0_march<T, false, false>(v, [&](long) { return T(0); }, fetch, body);
     else if (MODE == CHEB_ZERO2)
-        l0_march<T, true, false>(v, [&](long j) { return (T)f[j]; }, fetch, body);
+        l0_march<T, true, false>(v, [&](Idx j) { return (T)at(f, j); }, fetch, body);
     else
-        l0_march<T, true, false>(v, [&](long j) { return xin[j]; }, fetch, body);
+        l0_march<T, true, false>(v, [&](Idx j) { return at(xin, j); }, fetch, body);
     if (DOT) {
         double sb = block_sum(acc, lds);
         if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
@@ -796,9 +851,9 @@ __global__ void __launch_bounds__(kMThreads) k_l0_residual(L0View<T> v, const TF
                                                           const T* __restrict__ xv,
                                                           T* __restrict__ r) {
     l0_march<T, true, false>(
-        v, [&](long j) { return xv[j]; },
-        [&](long i, int, int, int, bool, int) { return Vals<T, 1>{{(T)f[i]}}; },
-        [&](long i, Vals<T, 1> fv, T, T ax, int, int, int, bool, int) { r[i] = fv.v[0] - ax; });
+        v, [&](Idx j) { return at(xv, j); },
+        [&](Idx i, int, int, int, bool, int) { return Vals<T, 1>{{(T)at(f, i)}}; },
+        [&](Idx i, Vals<T, 1> fv, T, T ax, int, int, int, bool, int) { at(r, i) = fv.v[0] - ax; });
 }
 
 template <typename TF, typename T>
@@ -819,9 +874,9 @@ template void l0_residual<float, float>(const FineLevel&, const float*, const fl
 template <typename T>
 __global__ void __launch_bounds__(kMThreads) k_l0_restrict_y(L0View<T> v, const T* __restrict__ r,
                                                             T* __restrict__ yv, T omega) {
-    l0_march<T, true, true>(v, [&](long j) { return r[j]; }, NOFETCH,
-                            [&](long i, NoVals, T ri, T atr, int, int, int, bool, int) {
-                                yv[i] = ri - omega * atr;
+    l0_march<T, true, true>(v, [&](Idx j) { return at(r, j); }, NOFETCH,
+                            [&](Idx i, NoVals, T ri, T atr, int, int, int, bool, int) {
+                                at(yv, i) = ri - omega * atr;
                             });
 }
 
@@ -874,31 +929,41 @@ template <typename T>
 __global__ void __launch_bounds__(kMThreads) k_l0_prolong(L0View<T> v, LCView<T> c,
                                                          const T* __restrict__ vc,
                                                          T* __restrict__ xv, T omega) {
-    auto fetch = [&](long i, int x, int y, int z, bool, int) {
+    // the coarse values of the node's aggregate and of the neighbours' aggregates, the
+    // current x, and (irregular nodes) the row's table coefficients, all issued a plane
+    // ahead
+    struct R {
+        Vals<T, 8> f;
+        Vals<T, 6> t;
+    };
+    auto fetch = [&](Idx i, int x, int y, int z, bool irr, int rk) {
         const int qx = x / 3, qy = y / 3, qz = z / 3;
         const long a = (qx + 1) + (long)c.sx * (qy + 1) + c.sxy * (qz + 1);
-        Vals<T, 8> f;
-        f.v[0] = vc[a];
-        f.v[1] = vc[a - (x - 3 * qx == 0)];
-        f.v[2] = vc[a + (x - 3 * qx == 2)];
-        f.v[3] = vc[a - (y - 3 * qy == 0 ? c.sx : 0)];
-        f.v[4] = vc[a + (y - 3 * qy == 2 ? c.sx : 0)];
-        f.v[5] = vc[a - (z - 3 * qz == 0 ? c.sxy : 0)];
-        f.v[6] = vc[a + (z - 3 * qz == 2 ? c.sxy : 0)];
-        f.v[7] = xv[i];
-        return f;
+        R r;
+        r.f.v[0] = vc[a];
+        r.f.v[1] = vc[a - (x - 3 * qx == 0)];
+        r.f.v[2] = vc[a + (x - 3 * qx == 2)];
+        r.f.v[3] = vc[a - (y - 3 * qy == 0 ? c.sx : 0)];
+        r.f.v[4] = vc[a + (y - 3 * qy == 2 ? c.sx : 0)];
+        r.f.v[5] = vc[a - (z - 3 * qz == 0 ? c.sxy : 0)];
+        r.f.v[6] = vc[a + (z - 3 * qz == 2 ? c.sxy : 0)];
+        r.f.v[7] = at(xv, i);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) r.t.v[d] = irr ? v.tab[d][rk] : T(0);
+        return r;
     };
     l0_march<T, false, false>(v, [&](long) { return T(0); }, fetch,
-                              [&](long i, Vals<T, 8> f, T, T, int, int, int, bool irrow, int rk) {
+                              [&](Idx i, R r, T, T, int, int, int, bool irrow, int) {
+        const Vals<T, 8>& f = r.f;
         T apv;
         if (!irrow) {
             apv = f.v[0] + v.c[0] * (f.v[1] + f.v[2]) + v.c[1] * (f.v[3] + f.v[4]) +
                   v.c[2] * (f.v[5] + f.v[6]);
         } else {
-            apv = f.v[0] + v.tab[0][rk] * f.v[1] + v.tab[1][rk] * f.v[2] + v.tab[2][rk] * f.v[3] +
-                  v.tab[3][rk] * f.v[4] + v.tab[4][rk] * f.v[5] + v.tab[5][rk] * f.v[6];
+            apv = f.v[0] + r.t.v[0] * f.v[1] + r.t.v[1] * f.v[2] + r.t.v[2] * f.v[3] +
+                  r.t.v[3] * f.v[4] + r.t.v[4] * f.v[5] + r.t.v[5] * f.v[6];
         }
-        xv[i] = f.v[7] + (f.v[0] - omega * apv);
+        at(xv, i) = f.v[7] + (f.v[0] - omega * apv);
     });
 }
 
@@ -924,14 +989,14 @@ __global__ void __launch_bounds__(kMThreads) k_cg_init(L0View<double> v, const d
                                                       double* __restrict__ bs, double* __restrict__ xv) {
     l0_march<double, false, false>(
         v, [&](long) { return 0.0; },
-        [&](long i, int, int, int, bool, int) {
-            return Vals<double, 3>{{sigma[i], b[i], x0 ? x0[i] : 0.0}};
+        [&](Idx i, int, int, int, bool, int) {
+            return Vals<double, 3>{{at(sigma, i), at(b, i), x0 ? at(x0, i) : 0.0}};
         },
-        [&](long i, Vals<double, 3> f, double, double, int, int, int z, bool, int) {
+        [&](Idx i, Vals<double, 3> f, double, double, int, int, int z, bool, int) {
             // end-plane rows of open ends are halved, and so is their right-hand side
             const double rho = (z == 1 || z == v.nz - 2) ? v.rho_end : 1.0;
-            bs[i] = f.v[0] * rho * f.v[1];
-            xv[i] = x0 ? f.v[2] / f.v[0] : 0.0;
+            at(bs, i) = f.v[0] * rho * f.v[1];
+            at(xv, i) = x0 ? f.v[2] / f.v[0] : 0.0;
         });
 }
 
@@ -950,13 +1015,13 @@ __global__ void __launch_bounds__(kMThreads) k_cg_resid(L0View<double> v, const 
     __shared__ double lds[kMThreads / kWave];
     double a0 = 0.0, a1 = 0.0;
     l0_march<double, true, false>(
-        v, [&](long j) { return xv[j]; },
-        [&](long i, int, int, int, bool, int) { return Vals<double, 1>{{bs[i]}}; },
-        [&](long i, Vals<double, 1> f, double, double ax, int, int, int, bool, int) {
+        v, [&](Idx j) { return at(xv, j); },
+        [&](Idx i, int, int, int, bool, int) { return Vals<double, 1>{{at(bs, i)}}; },
+        [&](Idx i, Vals<double, 1> f, double, double ax, int, int, int, bool, int) {
             const double bi = f.v[0];
             const double o = bi - ax;
-            r[i] = o;
-            if (r32) r32[i] = (float)o;
+            at(r, i) = o;
+            if (r32) at(r32, i) = (float)o;
             a0 += o * o;
             a1 += bi * bi;
         });
@@ -986,13 +1051,13 @@ __global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ*
     const double beta = scal[S_BETA];
     double acc = 0.0;
     l0_march<double, true, false>(
-        v, [&](long j) { return zv[j]; },
-        [&](long i, int, int, int, bool, int) { return Vals<double, 2>{{p[i], q[i]}}; },
-        [&](long i, Vals<double, 2> f, double zi, double az, int, int, int, bool, int) {
+        v, [&](Idx j) { return at(zv, j); },
+        [&](Idx i, int, int, int, bool, int) { return Vals<double, 2>{{at(p, i), at(q, i)}}; },
+        [&](Idx i, Vals<double, 2> f, double zi, double az, int, int, int, bool, int) {
             const double pi = zi + beta * f.v[0];
             const double qi = az + beta * f.v[1];
-            p[i] = pi;
-            q[i] = qi;
+            at(p, i) = pi;
+            at(q, i) = qi;
             acc += pi * qi;
         });
     double sb = block_sum(acc, lds);
@@ -1026,14 +1091,14 @@ __global__ void __launch_bounds__(kMThreads) k_cg_xr(L0View<double> v, double* _
     double acc = 0.0;
     l0_march<double, false, false>(
         v, [&](long) { return 0.0; },
-        [&](long i, int, int, int, bool, int) { return Vals<double, 4>{{xv[i], p[i], r[i], q[i]}}; },
-        [&](long i, Vals<double, 4> f, double, double, int, int, int, bool, int) {
+        [&](Idx i, int, int, int, bool, int) { return Vals<double, 4>{{at(xv, i), at(p, i), at(r, i), at(q, i)}}; },
+        [&](Idx i, Vals<double, 4> f, double, double, int, int, int, bool, int) {
             double ri = f.v[2];
             if (ok) {
-                xv[i] = f.v[0] + alpha * f.v[1];
+                at(xv, i) = f.v[0] + alpha * f.v[1];
                 ri -= alpha * f.v[3];
-                r[i] = ri;
-                if (r32) r32[i] = (float)ri;
+                at(r, i) = ri;
+                if (r32) at(r32, i) = (float)ri;
             }
             acc += ri * ri;
         });
@@ -1068,10 +1133,10 @@ __global__ void __launch_bounds__(kMThreads) k_mask_copy(L0View<double> v, const
                                                         double* __restrict__ b, float* __restrict__ b32) {
     l0_march<double, false, false>(
         v, [&](long) { return 0.0; },
-        [&](long i, int, int, int, bool, int) { return Vals<double, 1>{{a[i]}}; },
-        [&](long i, Vals<double, 1> f, double, double, int, int, int, bool, int) {
-            b[i] = f.v[0];
-            if (b32) b32[i] = (float)f.v[0];
+        [&](Idx i, int, int, int, bool, int) { return Vals<double, 1>{{at(a, i)}}; },
+        [&](Idx i, Vals<double, 1> f, double, double, int, int, int, bool, int) {
+            at(b, i) = f.v[0];
+            if (b32) at(b32, i) = (float)f.v[0];
         });
 }
 
@@ -1088,7 +1153,7 @@ __global__ void __launch_bounds__(kMThreads) k_l0_dot(L0View<double> v, const do
     double acc = 0.0;
     l0_march<double, false, false>(
         v, [&](long) { return 0.0; },
-        [&](long i, int, int, int, bool, int) { return Vals<double, 2>{{a[i], (double)b[i]}}; },
+        [&](Idx i, int, int, int, bool, int) { return Vals<double, 2>{{at(a, i), (double)at(b, i)}}; },
         [&](long, Vals<double, 2> f, double, double, int, int, int, bool, int) {
             acc += f.v[0] * f.v[1];
         });
