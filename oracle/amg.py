@@ -200,6 +200,36 @@ def setup(A0: sp.csr_matrix, dims0: Tuple[int, int, int], lin0: np.ndarray,
     return H
 
 
+def refresh(H: Hierarchy, A0: sp.csr_matrix) -> Hierarchy:
+    """Reuse of the aggregation hierarchy (Section 5.2): keep every level's logical box,
+    unknowns and tentative prolongator from ``H``, and recompute from the new level-0
+    operator ``A0`` what depends on the numbers -- the smoother's spectral bound, the
+    smoothed prolongators, the Galerkin operators and the coarse solver.
+
+    ``A0`` must act on H's level-0 unknowns (same order).
+    """
+    old = H.levels
+    if A0.shape[0] != old[0].n:
+        raise ValueError("the new operator does not act on the hierarchy's unknowns")
+    opts = H.opts
+    A = A0.tocsr()
+    levels = [Level(A, A.diagonal().copy(), old[0].dims, old[0].lin)]
+    for k in range(len(old) - 1):
+        lv = levels[-1]
+        lv.Ptent = old[k].Ptent
+        lv.lam = lanczos_lambda(lv.A, lv.D, lv.lin, opts.eig_iters)
+        lv.lam_hi = opts.cheb_boost * lv.lam
+        lv.omega = opts.omega_scale / lv.lam
+        Dinv = sp.diags(1.0 / lv.D)
+        lv.P = (lv.Ptent - lv.omega * (Dinv @ (lv.A @ lv.Ptent))).tocsr()
+        Ac = (lv.P.T @ (lv.A @ lv.P)).tocsr()
+        Ac.sort_indices()
+        levels.append(Level(Ac, Ac.diagonal().copy(), old[k + 1].dims, old[k + 1].lin))
+    R = Hierarchy(levels, opts)
+    R.coarse_lu = sla.lu_factor(levels[-1].A.toarray())
+    return R
+
+
 def gs_colours(lin: np.ndarray, dims: Tuple[int, int, int]) -> np.ndarray:
     """Colour 0..7 of each unknown from the parities of its logical box coordinates."""
     mx, my, _ = dims

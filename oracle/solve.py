@@ -32,6 +32,17 @@ def build(shape, nx: int, ny: int, nz: int, variant: int,
     return sys_, H
 
 
+def refresh(shape, nx: int, ny: int, nz: int, variant: int, H: amg.Hierarchy,
+            robin: bool = False):
+    """System of a new geometry on the same lattice, and H refreshed for it
+    (amg.refresh); the new domain must have H's unknowns."""
+    dom = grid.from_shape(shape, nx, ny, nz, robin)
+    sys_ = operator.assemble(dom, variant)
+    if not np.array_equal(sys_.idx, H.levels[0].lin):
+        raise ValueError("the domain's unknowns differ from the hierarchy's")
+    return sys_, amg.refresh(H, sys_.As)
+
+
 def solve(sys_: operator.System, H: amg.Hierarchy, b_box: np.ndarray,
           x0_box: Optional[np.ndarray] = None, tol: float = 1e-8,
           max_iter: int = 500) -> pcg.Result:

@@ -307,3 +307,52 @@ def test_pcg_with_gauss_seidel_coarse_solver_converges():
         ref = solve.solve(*solve.build(shape, 33, 33, 33, variant), b, tol=1e-10)
         assert res.status == 0 and res.iterations <= ref.iterations + 3
         assert np.linalg.norm(res.x - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
+
+
+# ------------------------------------------------------------------ hierarchy reuse
+
+
+@pytest.mark.parametrize("variant,shape1,shape2", [
+    # a bunch that elongates: same lattice and unknowns, larger h_z
+    (W.VARIANT_LIN, W.Shape.cylinder(1.0, 2.0), W.Shape.cylinder(1.0, 2.6)),
+    # a flatter ellipse: the lattice spans the bounding box, so only h_y changes
+    (W.VARIANT_QUAD, W.Shape.ellipse(1.0, 0.6, 4.0), W.Shape.ellipse(1.0, 0.45, 4.0)),
+])
+def test_refresh_equals_fresh_setup(variant, shape1, shape2):
+    """Reuse of the aggregation hierarchy (Section 5.2): the aggregates depend on the
+    unknowns only, so refreshing a hierarchy for a new geometry with the same unknowns
+    gives, level by level, the hierarchy that a fresh setup builds; the numbers do change."""
+    n = (33, 29, 31)
+    _, H1 = solve.build(shape1, *n, variant)
+    s2, R = solve.refresh(shape2, *n, variant, H1)
+    _, F = solve.build(shape2, *n, variant)
+    assert R.sizes == F.sizes == H1.sizes
+    for a, b, old in zip(R.levels, F.levels, H1.levels):
+        scale = abs(b.A).max()
+        assert abs(a.A - b.A).max() <= 1e-15 * scale
+        assert abs(a.A - old.A).max() > 1e-6 * scale
+        if b.P is not None:
+            assert abs(a.lam - b.lam) <= 1e-15 * b.lam and a.lam != old.lam
+            assert abs(a.P - b.P).max() <= 1e-15 * abs(b.P).max()
+    r = np.random.default_rng(3).standard_normal(s2.n)
+    zr, zf = amg.vcycle(R, r), amg.vcycle(F, r)
+    assert np.abs(zr - zf).max() <= 1e-13 * np.abs(zf).max()
+
+
+def test_refresh_rejects_other_unknowns():
+    # the bore radius relative to the cavity changes which lattice nodes are inside
+    _, H = solve.build(W.Shape.boxbore(0.8, 4.0, 0.5), 31, 31, 45, W.VARIANT_LIN)
+    with pytest.raises(ValueError):
+        solve.refresh(W.Shape.boxbore(0.8, 4.0, 0.4), 31, 31, 45, W.VARIANT_LIN, H)
+
+
+def test_elongating_cylinder_keeps_its_unknowns():
+    """The workload of the hierarchy reuse: the lattice spans the bounding box and the
+    cylinder does not vary along z, so every length gives the same unknowns and wall
+    fractions (only h_z changes)."""
+    ref = grid.from_shape(W.Shape.cylinder(1.0, 2.0), 25, 25, 19)
+    for L in (2.2, 3.0, 7.5):
+        d = grid.from_shape(W.Shape.cylinder(1.0, L), 25, 25, 19)
+        assert np.array_equal(d.mask, ref.mask)
+        assert np.array_equal(d.frac, ref.frac)
+        assert d.h[2] == pytest.approx(L / 18) and d.h[0] == ref.h[0]
