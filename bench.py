@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--line-serve-requests", type=int, default=32,
                     help="requests in the headline mode's served-stream leg")
     ap.add_argument("--paper-tubes", action="store_true",
-                    help="the paper's tube problems (Tables 7-9) with open ends, one GPU")
+                    help="the paper's tube problems (Tables 8-10) with open ends, one GPU")
     ap.add_argument("--tube-sizes", default="256,512,1024")
     ap.add_argument("--tube-reps", type=int, default=2)
     ap.add_argument("--serve-load", type=float, default=0.7,
@@ -136,15 +136,15 @@ def pic_bench(args) -> dict:
             "max_rel_res": max(s[2] for s in steps)}
 
 
-# The paper's tube problems (Section 5.3, Tables 7-9): a circular tube inscribed in an n^3
+# The paper's tube problems (Section 5.3, Tables 8-10): a circular tube inscribed in an n^3
 # lattice with open (Robin) ends, all n planes unknown.  "paper" holds the fastest
 # solution and construction times printed for each, on the Cray XT4/XT3 (Opteron 2.6 GHz).
 PAPER_TUBES = [
-    {"n": 256, "variant": "lin", "table": "Table 7",
+    {"n": 256, "variant": "lin", "table": "Table 8",
      "paper": {"cores": 512, "solution_s": 0.71, "construction_s": 0.83}},
-    {"n": 512, "variant": "const", "table": "Table 8",
+    {"n": 512, "variant": "const", "table": "Table 9",
      "paper": {"cores": 2048, "solution_s": 2.54, "construction_s": 7.58}},
-    {"n": 1024, "variant": "lin", "table": "Table 9",
+    {"n": 1024, "variant": "lin", "table": "Table 10",
      "paper": {"cores": 2048, "solution_s": 10.93, "construction_s": 6.68}},
 ]
 

@@ -129,6 +129,7 @@ typedef struct {
     int64_t n_irregular;                  /* level-0 rows with a non-constant stencil */
     int64_t device_bytes;                 /* device memory held by the hierarchy */
     double t_setup_ms;
+    double t_refresh_ms;                  /* last saamg_refresh (host wall time), 0 if none */
 } saamg_info;
 
 typedef struct saamg_hierarchy saamg_hierarchy;
@@ -181,6 +182,25 @@ int saamg_setup(const saamg_domain* dom, int variant, const saamg_options* opt, 
  */
 int saamg_solve(saamg_hierarchy* H, const double* d_b, const double* d_x0, double* d_x,
                 double tol, int max_iter, void* stream, saamg_result* res);
+
+/*
+ * Numeric-only re-setup reusing the aggregation hierarchy (Section 5.2, reuse of the
+ * aggregation hierarchy; Table 6 times it): keeps H's aggregates (the tentative
+ * prolongators), storage and buffers, and recomputes every number from dom: level-0
+ * stencil weights and scaling, spectral estimates, smoothed prolongators, Galerkin
+ * operators, Chebyshev coefficients and the coarsest-level solver.  The result equals a
+ * fresh saamg_setup of dom with H's variant and options.  Typical use: a bunch that
+ * elongates, so that the spacings change while the lattice does not.
+ *   dom     host domain as for saamg_setup; it must have H's box, the same unknowns and
+ *           near-wall rows (nodes with a cut wall, plus the end planes with open ends)
+ *           and the same end condition kind; spacings, wall fractions and robin_d may
+ *           differ.
+ *   stream  work is queued on it; the call returns when H is complete.
+ * Errors: SAAMG_INVALID_ARG when dom fails those checks or a solve state created on H
+ * still exists (H unchanged).  A failure after the checks (HIP error) leaves H unusable:
+ * destroy it.
+ */
+int saamg_refresh(saamg_hierarchy* H, const saamg_domain* dom, void* stream);
 
 /* Free the hierarchy (NULL is accepted). */
 int saamg_destroy(saamg_hierarchy* H);

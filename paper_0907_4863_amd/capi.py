@@ -63,7 +63,7 @@ class Info(C.Structure):
                 ("n_unknowns", C.c_int64 * MAX_LEVELS),
                 ("lambda_est", C.c_double * MAX_LEVELS), ("omega", C.c_double * MAX_LEVELS),
                 ("n_irregular", C.c_int64), ("device_bytes", C.c_int64),
-                ("t_setup_ms", C.c_double)]
+                ("t_setup_ms", C.c_double), ("t_refresh_ms", C.c_double)]
 
 
 class SaamgError(RuntimeError):
@@ -92,6 +92,7 @@ def lib() -> C.CDLL:
                                           C.POINTER(C.c_uint8), C.c_int64, C.POINTER(C.c_int64),
                                           C.POINTER(C.c_uint8), _DP, C.POINTER(C.c_int64)]
     L.saamg_setup.argtypes = [C.POINTER(Domain), C.c_int, C.POINTER(Options), _P, C.POINTER(_P)]
+    L.saamg_refresh.argtypes = [_P, C.POINTER(Domain), _P]
     L.saamg_solve.argtypes = [_P, _P, _P, _P, C.c_double, C.c_int, _P, C.POINTER(Result)]
     L.saamg_pic_create.argtypes = [C.POINTER(Grid), C.POINTER(C.c_uint8), C.c_int64, C.POINTER(_P)]
     L.saamg_pic_deposit.argtypes = [_P, _P, C.c_int64, C.c_double, _P, _P]
@@ -248,6 +249,12 @@ def setup(dom: HostDomain, variant: int, options: Optional[Options] = None,
     return Hierarchy(h.value, (dom.nx, dom.ny, dom.nz))
 
 
+def refresh(H: Hierarchy, dom: HostDomain, stream=None) -> None:
+    """Recompute every number of H for ``dom`` on H's aggregates (saamg_refresh)."""
+    ds = dom.struct()
+    _check(lib().saamg_refresh(H.handle, C.byref(ds), _stream(stream)))
+
+
 def destroy(H: Hierarchy) -> None:
     if H.handle:
         lib().saamg_destroy(H.handle)
@@ -275,7 +282,7 @@ def hierarchy_info(H: Hierarchy) -> dict:
         "lambda_est": [info.lambda_est[l] for l in range(n)],
         "omega": [info.omega[l] for l in range(n)],
         "n_irregular": info.n_irregular, "device_bytes": info.device_bytes,
-        "t_setup_ms": info.t_setup_ms,
+        "t_setup_ms": info.t_setup_ms, "t_refresh_ms": info.t_refresh_ms,
     }
 
 

@@ -197,6 +197,8 @@ struct saamg_hierarchy {
     double* Ainv = nullptr;
     long* cidx = nullptr;     // storage index of each coarsest-level unknown
     double t_setup_ms = 0;
+    double t_refresh_ms = 0;  // last saamg_refresh, 0 if none
+    int live_states = 0;      // saamg_state objects created on H and not yet destroyed
     int64_t bytes = 0;
     // work vectors of saamg_solve / saamg_precond_apply, allocated on first use
     saamg_state* ws = nullptr;

@@ -447,6 +447,26 @@ void l0_build_masks(FineLevel& L, const uint8_t* mask, const int32_t* nwidx, int
     HIPCHECK(hipGetLastError());
 }
 
+__global__ void k_mask_diff(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+                            const uint64_t* __restrict__ c, const uint64_t* __restrict__ d, long n,
+                            int* __restrict__ flag) {
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n && (a[t] != b[t] || c[t] != d[t])) *flag = 1;
+}
+
+bool l0_same_masks(const FineLevel& L, const uint64_t* unk, const uint64_t* irr, hipStream_t s) {
+    int* flag = (int*)dmalloc(sizeof(int));
+    hipLaunchKernelGGL(k_mask_diff, dim3((unsigned)((L.nseg + 255) / 256)), dim3(256), 0, s, L.unk,
+                       unk, L.irr, irr, L.nseg, flag);
+    int h = 1;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dfree(flag);
+    HIPCHECK(e);
+    return h == 0;
+}
+
 // Single-block exclusive scan of int32 counts (setup only).
 __global__ void __launch_bounds__(1024) k_scan(const int32_t* in, int32_t* out, long n,
                                                int64_t* total) {

@@ -47,6 +47,8 @@ void finalize(const double* partials, long nblk, int nq, double* scal, int op, i
 void l0_scatter_nwidx(int32_t* nwidx, const int64_t* nodes, long n, hipStream_t s);
 void l0_build_masks(FineLevel& L, const uint8_t* mask, const int32_t* nwidx, int32_t* cnt_irr,
                     int32_t* cnt_unk, hipStream_t s);
+// true when the segment masks unk/irr equal L's
+bool l0_same_masks(const FineLevel& L, const uint64_t* unk, const uint64_t* irr, hipStream_t s);
 void exclusive_scan(const int32_t* in, int32_t* out, long n, int64_t* total, hipStream_t s);
 void l0_build_table(FineLevel& L, const uint8_t* mask, const int32_t* nwidx, const double* nwfrac,
                     int variant, double sigma0, hipStream_t s);

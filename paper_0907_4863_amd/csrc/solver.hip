@@ -527,9 +527,16 @@ static void validate_options(const saamg_options& o) {
         throw ApiError{SAAMG_INVALID_ARG, "coarse_sweeps must be in 1..100"};
 }
 
-static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const saamg_options* opt,
-                                   hipStream_t s) {
-    auto t0 = std::chrono::steady_clock::now();
+// Host-side checks of a domain and its near-wall rows: wall fractions below 1 (the
+// constant rule ignores them) and, with open ends, every end-plane unknown; six fractions
+// per row, 1 where no wall is cut.
+struct DomainPrep {
+    long n_unk = 0;
+    std::vector<int64_t> nw_nodes;
+    std::vector<double> nw_frac;
+};
+
+static DomainPrep prepare_domain(const saamg_domain* dom, int variant) {
     if (!dom || !dom->mask) throw ApiError{SAAMG_INVALID_ARG, "domain or mask is NULL"};
     const int nx = dom->nx, ny = dom->ny, nz = dom->nz;
     if (nx < 3 || ny < 3 || nz < 3) throw ApiError{SAAMG_INVALID_ARG, "box must be at least 3^3"};
@@ -540,16 +547,10 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
         throw ApiError{SAAMG_INVALID_ARG, "unknown boundary variant"};
     if (dom->n_wall < 0 || (dom->n_wall > 0 && (!dom->wall_node || !dom->wall_dir || !dom->wall_s)))
         throw ApiError{SAAMG_INVALID_ARG, "wall arrays are NULL"};
-    saamg_options o;
-    if (opt)
-        o = *opt;
-    else
-        saamg_default_options(&o);
-    validate_options(o);
 
+    DomainPrep D;
     const long nxy = (long)nx * ny, nbox = nxy * nz;
     const uint8_t* m = dom->mask;
-    long n_unk = 0;
     for (long k = 0; k < nz; ++k)
         for (long j = 0; j < ny; ++j)
             for (long i = 0; i < nx; ++i) {
@@ -557,9 +558,9 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
                 if (!m[idx]) continue;
                 if (i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1)
                     throw ApiError{SAAMG_INVALID_ARG, "an unknown lies on a face of the box"};
-                ++n_unk;
+                ++D.n_unk;
             }
-    if (n_unk == 0) throw ApiError{SAAMG_INVALID_ARG, "the domain has no unknowns"};
+    if (D.n_unk == 0) throw ApiError{SAAMG_INVALID_ARG, "the domain has no unknowns"};
 
     const bool open = dom->robin_d > 0.0;
     if (dom->robin_d < 0.0 || !std::isfinite(dom->robin_d))
@@ -576,8 +577,6 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
             }
     }
 
-    // Near-wall rows: wall fractions below 1 (the constant rule ignores them) and, with
-    // open ends, every end-plane unknown; six fractions per row, 1 where no wall is cut.
     std::map<int64_t, std::array<double, 6>> nw;
     const long step[6] = {-1, 1, -(long)nx, (long)nx, -nxy, nxy};
     std::vector<int64_t> seen;
@@ -609,14 +608,166 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
                     const long idx = i + nx * j + nxy * k;
                     if (m[idx]) nw.emplace(idx, std::array<double, 6>{1, 1, 1, 1, 1, 1});
                 }
-    std::vector<int64_t> nw_nodes;
-    std::vector<double> nw_frac;
-    nw_nodes.reserve(nw.size());
-    nw_frac.reserve(6 * nw.size());
+    D.nw_nodes.reserve(nw.size());
+    D.nw_frac.reserve(6 * nw.size());
     for (const auto& kv : nw) {
-        nw_nodes.push_back(kv.first);
-        for (int q = 0; q < 6; ++q) nw_frac.push_back(kv.second[q]);
+        D.nw_nodes.push_back(kv.first);
+        for (int q = 0; q < 6; ++q) D.nw_frac.push_back(kv.second[q]);
     }
+    return D;
+}
+
+// The domain on the device: mask, near-wall row index per box node (-1 elsewhere) and
+// the near-wall rows' fractions.
+struct DeviceDomain {
+    uint8_t* mask = nullptr;
+    int32_t* nwidx = nullptr;
+    int64_t* nwnodes = nullptr;
+    double* nwfrac = nullptr;
+    DeviceDomain(const saamg_domain* dom, const DomainPrep& D, long nbox, hipStream_t s) {
+        try {
+            mask = (uint8_t*)dmalloc(nbox);
+            nwidx = (int32_t*)dmalloc(4 * nbox);
+            nwnodes = (int64_t*)dmalloc(8 * std::max<size_t>(D.nw_nodes.size(), 1));
+            nwfrac = (double*)dmalloc(8 * std::max<size_t>(D.nw_frac.size(), 1));
+            HIPCHECK(hipMemcpy(mask, dom->mask, nbox, hipMemcpyHostToDevice));
+            HIPCHECK(hipMemset(nwidx, 0xff, 4 * nbox));
+            if (!D.nw_nodes.empty()) {
+                HIPCHECK(hipMemcpy(nwnodes, D.nw_nodes.data(), 8 * D.nw_nodes.size(),
+                                   hipMemcpyHostToDevice));
+                HIPCHECK(hipMemcpy(nwfrac, D.nw_frac.data(), 8 * D.nw_frac.size(),
+                                   hipMemcpyHostToDevice));
+            }
+            l0_scatter_nwidx(nwidx, nwnodes, (long)D.nw_nodes.size(), s);
+        } catch (...) {
+            release();
+            throw;
+        }
+    }
+    void release() {
+        for (void* p : {(void*)mask, (void*)nwidx, (void*)nwnodes, (void*)nwfrac}) dfree(p);
+        mask = nullptr;
+        nwidx = nullptr;
+        nwnodes = nullptr;
+        nwfrac = nullptr;
+    }
+    ~DeviceDomain() { release(); }
+};
+
+// Level-0 numbers from the spacings, the Robin parameter and the near-wall fractions:
+// stencil weights of regular rows, the irregular rows' table and the scaling sigma.
+static void fine_numbers(FineLevel& L, const saamg_domain* dom, const DeviceDomain& dd, int variant,
+                         hipStream_t s) {
+    L.h[0] = dom->hx;
+    L.h[1] = dom->hy;
+    L.h[2] = dom->hz;
+    L.robin_d = dom->robin_d;
+    const double ih2[3] = {1.0 / (L.h[0] * L.h[0]), 1.0 / (L.h[1] * L.h[1]),
+                           1.0 / (L.h[2] * L.h[2])};
+    const double sigma0 = 1.0 / std::sqrt(2.0 * ih2[0] + 2.0 * ih2[1] + 2.0 * ih2[2]);
+    for (int a = 0; a < 3; ++a) L.c64[a] = -(sigma0 * (1.0 * ih2[a])) * sigma0;
+    l0_build_table(L, dd.mask, dd.nwidx, dd.nwfrac, variant, sigma0, s);
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+// Smoother and transfer parameters of level l from its operator (Section 3.2).
+static LevelParams level_params(saamg_hierarchy* H, int l, hipStream_t s) {
+    const saamg_options& o = H->opt;
+    LevelParams P;
+    P.lam = lanczos_lambda(H, l, s);
+    if (!(P.lam > 0) || !std::isfinite(P.lam))
+        throw ApiError{SAAMG_HIP_ERROR, "spectral estimate failed on level " + std::to_string(l)};
+    P.lam_hi = o.cheb_boost * P.lam;
+    P.omega = o.omega_scale / P.lam;
+    P.cheb = cheb_coefficients(P.lam_hi, o.cheb_ratio, o.cheb_degree);
+    return P;
+}
+
+// Galerkin operator of level l+1 into C, its inverse diagonal, and the number of coarse
+// unknowns (aggregates holding at least one unknown); `cnt_out` (nullable) receives the
+// per-64 counts, which the caller frees.
+static int64_t galerkin(saamg_hierarchy* H, int l, CoarseLevel& C, double omega,
+                        int32_t** cnt_out, hipStream_t s) {
+    if (l == 0)
+        rap_from_l0(H->l0, C, omega, s);
+    else
+        rap_from_lc(H->lc[l - 1], C, omega, s);
+    const long nb = (C.nstore + 255) / 256;
+    int32_t* cnt = (int32_t*)dmalloc(4 * 4 * nb);
+    lc_finish(C, cnt, s);
+    int64_t* tot = (int64_t*)dmalloc(8);
+    exclusive_scan(cnt, nullptr, 4 * nb, tot, s);
+    int64_t nc = 0;
+    HIPCHECK(hipMemcpyAsync(&nc, tot, 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    dfree(tot);
+    if (cnt_out)
+        *cnt_out = cnt;
+    else
+        dfree(cnt);
+    return nc;
+}
+
+// Coarsest-level solver: Gauss-Seidel sweeps need nothing beyond the stored operator;
+// the direct solver holds the explicit fp64 inverse (allocated on first use).
+static void build_coarse_solver(saamg_hierarchy* H, hipStream_t s) {
+    if (H->opt.coarse_solver == SAAMG_COARSE_GS) {
+        if (H->lc.back().nstore > kGsMax)
+            throw ApiError{SAAMG_INVALID_ARG,
+                           "coarsest level too large for the Gauss-Seidel solver; lower max_coarse"};
+        return;
+    }
+    const int nL = H->nL;
+    const long nstore = (H->n_levels == 1) ? H->l0.nbox : H->lc.back().nstore;
+    int32_t* cmap = (int32_t*)dmalloc(4 * nstore);
+    try {
+        HIPCHECK(hipMemset(cmap, 0xff, 4 * nstore));
+        fill_cmap(cmap, H->cidx, nL, s);
+        if (!H->Ainv) {
+            H->Ainv = (double*)dmalloc(8L * nL * nL);
+            H->bytes += 8L * nL * nL + 8L * nL;
+        } else {
+            // the assembly writes the nonzero couplings only
+            HIPCHECK(hipMemsetAsync(H->Ainv, 0, 8L * nL * nL, s));
+        }
+        if (H->n_levels == 1)
+            dense_from_l0(H->l0, H->cidx, cmap, nL, H->Ainv, s);
+        else
+            dense_from_lc(H->lc.back(), H->cidx, cmap, nL, H->Ainv, s);
+        dense_invert(H->Ainv, nL, s);
+        HIPCHECK(hipStreamSynchronize(s));
+    } catch (...) {
+        dfree(cmap);
+        throw;
+    }
+    dfree(cmap);
+}
+
+// fp32 copies of the coarse operators for the mixed-precision V-cycle (allocated on
+// first use).
+static void coarse_fp32(saamg_hierarchy* H, hipStream_t s) {
+    if (H->opt.precision != SAAMG_MIXED) return;
+    for (auto& C : H->lc) {
+        for (int k = 0; k < 27; ++k)
+            if (C.coef64[k] && !C.coef32[k]) C.coef32[k] = (float*)dmalloc(4 * C.nstore);
+        if (!C.invD32) C.invD32 = (float*)dmalloc(4 * C.nstore);
+        lc_to_fp32(C, s);
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const saamg_options* opt,
+                                   hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    const DomainPrep D = prepare_domain(dom, variant);
+    saamg_options o;
+    if (opt)
+        o = *opt;
+    else
+        saamg_default_options(&o);
+    validate_options(o);
+    const int nx = dom->nx, ny = dom->ny, nz = dom->nz;
+    const long nxy = (long)nx * ny, nbox = nxy * nz;
 
     saamg_hierarchy* H = new saamg_hierarchy();
     try {
@@ -633,49 +784,30 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
         L.nbox = nbox;
         L.nseg = seg_count(nx, ny, nz);
         L.zb = l0_choose_zb(L.nsegx, ny, nz);
-        L.h[0] = dom->hx;
-        L.h[1] = dom->hy;
-        L.h[2] = dom->hz;
-        L.robin_d = dom->robin_d;
         L.unk = (uint64_t*)dmalloc(8 * L.nseg);
         L.irr = (uint64_t*)dmalloc(8 * L.nseg);
         L.base = (int32_t*)dmalloc(4 * L.nseg);
         L.sigma = (double*)dmalloc(8 * nbox);
 
-        uint8_t* d_mask = (uint8_t*)dmalloc(nbox);
-        int32_t* d_nwidx = (int32_t*)dmalloc(4 * nbox);
-        int64_t* d_nwnodes = (int64_t*)dmalloc(8 * std::max<size_t>(nw_nodes.size(), 1));
-        double* d_nwfrac = (double*)dmalloc(8 * std::max<size_t>(nw_frac.size(), 1));
+        // segment masks of unknowns and irregular rows, table slots
+        DeviceDomain dd(dom, D, nbox, s);
         int32_t* cnt_irr = (int32_t*)dmalloc(4 * L.nseg);
         int32_t* cnt_unk = (int32_t*)dmalloc(4 * L.nseg);
         int64_t* d_tot = (int64_t*)dmalloc(16);
-        HIPCHECK(hipMemcpy(d_mask, m, nbox, hipMemcpyHostToDevice));
-        HIPCHECK(hipMemset(d_nwidx, 0xff, 4 * nbox));
-        if (!nw_nodes.empty()) {
-            HIPCHECK(hipMemcpy(d_nwnodes, nw_nodes.data(), 8 * nw_nodes.size(), hipMemcpyHostToDevice));
-            HIPCHECK(hipMemcpy(d_nwfrac, nw_frac.data(), 8 * nw_frac.size(), hipMemcpyHostToDevice));
-        }
-        l0_scatter_nwidx(d_nwidx, d_nwnodes, (long)nw_nodes.size(), s);
-        l0_build_masks(L, d_mask, d_nwidx, cnt_irr, cnt_unk, s);
+        l0_build_masks(L, dd.mask, dd.nwidx, cnt_irr, cnt_unk, s);
         exclusive_scan(cnt_irr, L.base, L.nseg, d_tot, s);
         exclusive_scan(cnt_unk, nullptr, L.nseg, d_tot + 1, s);
         int64_t tots[2];
         HIPCHECK(hipMemcpyAsync(tots, d_tot, 16, hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
+        for (void* p : {(void*)cnt_irr, (void*)cnt_unk, (void*)d_tot}) dfree(p);
         L.n_irr = tots[0];
         L.n_unknowns = tots[1];
-        if (L.n_unknowns != n_unk) throw ApiError{SAAMG_HIP_ERROR, "unknown count mismatch"};
+        if (L.n_unknowns != D.n_unk) throw ApiError{SAAMG_HIP_ERROR, "unknown count mismatch"};
         L.tab64 = (double*)dmalloc(8 * 12 * std::max<long>(L.n_irr, 1));
         L.tab32 = (float*)dmalloc(4 * 12 * std::max<long>(L.n_irr, 1));
-        const double ih2[3] = {1.0 / (L.h[0] * L.h[0]), 1.0 / (L.h[1] * L.h[1]),
-                               1.0 / (L.h[2] * L.h[2])};
-        const double sigma0 = 1.0 / std::sqrt(2.0 * ih2[0] + 2.0 * ih2[1] + 2.0 * ih2[2]);
-        for (int a = 0; a < 3; ++a) L.c64[a] = -(sigma0 * (1.0 * ih2[a])) * sigma0;
-        l0_build_table(L, d_mask, d_nwidx, d_nwfrac, variant, sigma0, s);
-        HIPCHECK(hipStreamSynchronize(s));
-        for (void* p : {(void*)d_mask, (void*)d_nwidx, (void*)d_nwnodes, (void*)d_nwfrac,
-                        (void*)cnt_irr, (void*)cnt_unk, (void*)d_tot})
-            dfree(p);
+        fine_numbers(L, dom, dd, variant, s);
+        dd.release();
         H->bytes = 20L * L.nseg + 8L * nbox + 12L * 12 * L.n_irr;
 
         // hierarchy (Section 3.2): coarsen until at most max_coarse unknowns
@@ -684,27 +816,16 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
         H->n_levels = 1;
         while (n_cur > o.max_coarse && H->n_levels < o.max_levels) {
             const int l = H->n_levels - 1;
-            LevelParams P;
-            P.lam = lanczos_lambda(H, l, s);
-            if (!(P.lam > 0) || !std::isfinite(P.lam))
-                throw ApiError{SAAMG_HIP_ERROR, "spectral estimate failed on level " + std::to_string(l)};
-            P.lam_hi = o.cheb_boost * P.lam;
-            P.omega = o.omega_scale / P.lam;
-            P.cheb = cheb_coefficients(P.lam_hi, o.cheb_ratio, o.cheb_degree);
+            const LevelParams P = level_params(H, l, s);
             CoarseLevel C = make_coarse(fmx, fmy, fmz, H->sym);
-            if (l == 0)
-                rap_from_l0(L, C, P.omega, s);
-            else
-                rap_from_lc(H->lc[l - 1], C, P.omega, s);
-            const long nb = (C.nstore + 255) / 256;
-            int32_t* cnt = (int32_t*)dmalloc(4 * 4 * nb);
-            lc_finish(C, cnt, s);
-            int64_t* tot = (int64_t*)dmalloc(8);
-            exclusive_scan(cnt, nullptr, 4 * nb, tot, s);
+            int32_t* cnt = nullptr;
             int64_t nc = 0;
-            HIPCHECK(hipMemcpyAsync(&nc, tot, 8, hipMemcpyDeviceToHost, s));
-            HIPCHECK(hipStreamSynchronize(s));
-            dfree(tot);
+            try {
+                nc = galerkin(H, l, C, P.omega, &cnt, s);
+            } catch (...) {
+                free_coarse(C);
+                throw;
+            }
             if (nc >= n_cur) {
                 dfree(cnt);
                 free_coarse(C);
@@ -713,8 +834,12 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
             C.n_unknowns = nc;
             if (nc <= o.max_coarse || H->n_levels + 1 == o.max_levels) {
                 // coarsest level: collect its unknowns
+                if (nc > 8000) {
+                    dfree(cnt);
+                    free_coarse(C);
+                    throw ApiError{SAAMG_INVALID_ARG, "coarsest level too large"};
+                }
                 H->nL = (int)nc;
-                if (nc > 8000) throw ApiError{SAAMG_INVALID_ARG, "coarsest level too large"};
                 H->cidx = (long*)dmalloc(8 * nc);
                 lc_unknown_list(C, H->cidx, cnt, s);
             }
@@ -735,45 +860,70 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
             H->cidx = (long*)dmalloc(8 * H->nL);
             l0_unknown_list(L, H->cidx, s);
         }
-        // coarsest level: Gauss-Seidel sweeps on the stored operator (multilevel
-        // hierarchies only), else the dense inverse of the operator (fp64)
+        // Gauss-Seidel coarse solves need a coarse level to run on
         if (o.coarse_solver == SAAMG_COARSE_GS && H->n_levels == 1)
             H->opt.coarse_solver = SAAMG_COARSE_DIRECT;
-        if (H->opt.coarse_solver == SAAMG_COARSE_GS) {
-            if (H->lc.back().nstore > kGsMax)
-                throw ApiError{SAAMG_INVALID_ARG,
-                               "coarsest level too large for the Gauss-Seidel solver; lower max_coarse"};
-        } else {
-            const int nL = H->nL;
-            const long nstore = (H->n_levels == 1) ? L.nbox : H->lc.back().nstore;
-            int32_t* cmap = (int32_t*)dmalloc(4 * nstore);
-            HIPCHECK(hipMemset(cmap, 0xff, 4 * nstore));
-            fill_cmap(cmap, H->cidx, nL, s);
-            H->Ainv = (double*)dmalloc(8L * nL * nL);
-            if (H->n_levels == 1)
-                dense_from_l0(L, H->cidx, cmap, nL, H->Ainv, s);
-            else
-                dense_from_lc(H->lc.back(), H->cidx, cmap, nL, H->Ainv, s);
-            dense_invert(H->Ainv, nL, s);
-            HIPCHECK(hipStreamSynchronize(s));
-            dfree(cmap);
-            H->bytes += 8L * nL * nL + 8L * nL;
-        }
-        if (o.precision == SAAMG_MIXED) {
-            for (auto& C : H->lc) {
-                for (int k = 0; k < 27; ++k)
-                    if (C.coef64[k]) C.coef32[k] = (float*)dmalloc(4 * C.nstore);
-                C.invD32 = (float*)dmalloc(4 * C.nstore);
-                lc_to_fp32(C, s);
-            }
-        }
-        HIPCHECK(hipStreamSynchronize(s));
+        build_coarse_solver(H, s);
+        coarse_fp32(H, s);
     } catch (...) {
         saamg_destroy(H);
         throw;
     }
     H->t_setup_ms = ms_since(t0);
     return H;
+}
+
+// Numeric-only re-setup on the aggregates, storage and buffers of H (Section 5.2, reuse of
+// the aggregation hierarchy): the domain must have H's box, unknowns, near-wall rows and
+// end condition kind; every number is recomputed.  H is unchanged when a check fails.
+static void refresh_impl(saamg_hierarchy* H, const saamg_domain* dom, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    FineLevel& L = H->l0;
+    const DomainPrep D = prepare_domain(dom, H->variant);
+    if (dom->nx != L.nx || dom->ny != L.ny || dom->nz != L.nz)
+        throw ApiError{SAAMG_INVALID_ARG, "the domain's box differs from the hierarchy's"};
+    if ((dom->robin_d > 0.0) != (L.robin_d > 0.0))
+        throw ApiError{SAAMG_INVALID_ARG, "the end condition kind (open or closed) differs"};
+    if (D.n_unk != L.n_unknowns)
+        throw ApiError{SAAMG_INVALID_ARG, "the domain's unknowns differ from the hierarchy's"};
+    if (H->live_states > 0)
+        throw ApiError{SAAMG_INVALID_ARG, "solve states of this hierarchy still exist"};
+
+    DeviceDomain dd(dom, D, L.nbox, s);
+    {
+        // the new segment masks must equal the hierarchy's
+        FineLevel T = L;
+        T.unk = (uint64_t*)dmalloc(8 * L.nseg);
+        T.irr = (uint64_t*)dmalloc(8 * L.nseg);
+        int32_t* c1 = (int32_t*)dmalloc(4 * L.nseg);
+        int32_t* c2 = (int32_t*)dmalloc(4 * L.nseg);
+        bool same = false;
+        try {
+            l0_build_masks(T, dd.mask, dd.nwidx, c1, c2, s);
+            same = l0_same_masks(L, T.unk, T.irr, s);
+        } catch (...) {
+            for (void* p : {(void*)T.unk, (void*)T.irr, (void*)c1, (void*)c2}) dfree(p);
+            throw;
+        }
+        for (void* p : {(void*)T.unk, (void*)T.irr, (void*)c1, (void*)c2}) dfree(p);
+        if (!same)
+            throw ApiError{SAAMG_INVALID_ARG,
+                           "the domain's unknowns or near-wall rows differ from the hierarchy's"};
+    }
+    // from here on H changes; a failure leaves it unusable (destroy it)
+    fine_numbers(L, dom, dd, H->variant, s);
+    dd.release();
+    for (int l = 0; l + 1 < H->n_levels; ++l) {
+        H->par[l] = level_params(H, l, s);
+        CoarseLevel& C = H->lc[l];
+        const int64_t nc = galerkin(H, l, C, H->par[l].omega, nullptr, s);
+        if (nc != C.n_unknowns)
+            throw ApiError{SAAMG_HIP_ERROR, "coarse level " + std::to_string(l + 1) +
+                                                " changed its unknowns; destroy the hierarchy"};
+    }
+    build_coarse_solver(H, s);
+    coarse_fp32(H, s);
+    H->t_refresh_ms = ms_since(t0);
 }
 
 template <class F>
@@ -937,6 +1087,15 @@ int saamg_setup(const saamg_domain* dom, int variant, const saamg_options* opt, 
     });
 }
 
+int saamg_refresh(saamg_hierarchy* H, const saamg_domain* dom, void* stream) {
+    return guarded([&] {
+        if (!H) throw ApiError{SAAMG_INVALID_ARG, "hierarchy is NULL"};
+        HIPCHECK(hipSetDevice(H->device));
+        refresh_impl(H, dom, (hipStream_t)stream);
+        return (int)SAAMG_OK;
+    });
+}
+
 int saamg_destroy(saamg_hierarchy* H) {
     if (!H) return SAAMG_OK;
     FineLevel& L = H->l0;
@@ -975,6 +1134,7 @@ int saamg_hierarchy_info(const saamg_hierarchy* H, saamg_info* info) {
         info->n_irregular = H->l0.n_irr;
         info->device_bytes = H->bytes;
         info->t_setup_ms = H->t_setup_ms;
+        info->t_refresh_ms = H->t_refresh_ms;
         return (int)SAAMG_OK;
     });
 }
@@ -1057,6 +1217,7 @@ int saamg_state_create(saamg_hierarchy* H, const double* d_b, const double* d_x0
         state_alloc(S, H);
         state_start(S, d_b, d_x0);
         *out = S;
+        H->live_states += 1;
         return (int)SAAMG_OK;
     });
     if (rc != SAAMG_OK && S) {
@@ -1115,6 +1276,7 @@ int saamg_state_finish(saamg_state* S, double* d_x) {
 int saamg_state_destroy(saamg_state* S) {
     if (!S) return SAAMG_OK;
     (void)hipStreamSynchronize(S->s);
+    if (S->H) S->H->live_states -= 1;
     state_release(S);
     delete S;
     return SAAMG_OK;

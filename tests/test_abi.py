@@ -124,3 +124,11 @@ def test_footprint_grows_with_box_and_precision():
     h2, s2 = sa.footprint_bytes(256, 256, 768, sa.VARIANT_QUAD, sa.MIXED)
     assert s64 > sm > 0 and h2 > hm and s2 > sm
     assert s64 >= 48 * 128 * 128 * 256
+
+
+def test_refresh_rejects_a_null_hierarchy_before_touching_the_gpu():
+    m = np.zeros((5, 5, 5), np.uint8)
+    m[2, 2, 2] = 1
+    H = sa.capi.Hierarchy(0, (5, 5, 5))
+    with pytest.raises(sa.SaamgError, match="hierarchy is NULL"):
+        sa.refresh(H, _dom(m))

@@ -7,7 +7,7 @@
   the oracle's solver in a test, so the oracle evaluates the true residual row by row at
   sampled unknowns (from the wall rule, independently of the GPU operator) and checks
   |r_i| <= tol * ||D^-1/2 b|| for each, which every row of a converged solve satisfies.
-* The tube of the paper's Table 7 (circular tube in a 256^3 lattice, linear rule, open
+* The tube of the paper's Table 8 (circular tube in a 256^3 lattice, linear rule, open
   ends, 13,066,240 unknowns): the same row-by-row check, with samples on the end planes.
 """
 import numpy as np

@@ -1,0 +1,138 @@
+"""GPU: numeric-only re-setup reusing the aggregation hierarchy (saamg_refresh).
+
+* A refreshed hierarchy equals a fresh setup of the new domain: the same level
+  coefficients, spectral estimates and damping factors bit for bit (the same kernels run
+  on the same numbers), and the same solve, iterate for iterate.
+* It matches the oracle's refresh (amg.refresh): estimates to 1e-10 relative and the fp64
+  solution to 1e-8, as in the parity tests.
+* A domain with other unknowns, or an existing solve state, is rejected and the
+  hierarchy keeps working as before.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import operator, solve
+
+torch = pytest.importorskip("torch")
+sa = pytest.importorskip("paper_0907_4863_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    return torch.device("cuda:0")
+
+
+def _to_dev(box):
+    return torch.from_numpy(np.ascontiguousarray(box, dtype=np.float64).reshape(-1)).to(_dev())
+
+
+def _opts(precision, gs):
+    o = sa.default_options(precision=precision)
+    if gs:
+        o.coarse_solver = sa.COARSE_GS
+    return o
+
+
+REFRESH_CASES = {
+    # name: (shape before, shape after, lattice, variant, precision, open ends, GS coarse)
+    "cyl_elongates_lin_fp64": (W.Shape.cylinder(1.0, 2.0), W.Shape.cylinder(1.0, 2.8),
+                               (33, 33, 41), W.VARIANT_LIN, W.PREC_FP64, False, False),
+    "ell_flattens_quad_mixed": (W.Shape.ellipse(1.0, 0.6, 4.0), W.Shape.ellipse(1.0, 0.45, 4.0),
+                                (48, 40, 52), W.VARIANT_QUAD, W.PREC_MIXED, False, False),
+    "cyl_open_ends_lin_mixed": (W.Shape.cylinder(1.0, 2.0), W.Shape.cylinder(1.0, 3.1),
+                                (27, 27, 37), W.VARIANT_LIN, W.PREC_MIXED, True, False),
+    "cyl_elongates_gs_coarse": (W.Shape.cylinder(1.0, 2.0), W.Shape.cylinder(1.0, 2.4),
+                                (35, 35, 35), W.VARIANT_QUAD, W.PREC_FP64, False, True),
+}
+
+
+@pytest.mark.parametrize("name", list(REFRESH_CASES))
+def test_refresh_equals_fresh_setup(name):
+    s1, s2, (nx, ny, nz), variant, prec, robin, gs = REFRESH_CASES[name]
+    print(f"[case] refresh {name} {nx}x{ny}x{nz}", flush=True)
+    o = _opts(prec, gs)
+    d1 = sa.domain_for(s1, nx, ny, nz, open_ends=robin)
+    d2 = sa.domain_for(s2, nx, ny, nz, open_ends=robin)
+    assert np.array_equal(d1.mask, d2.mask) and np.array_equal(d1.wall_node, d2.wall_node)
+    G = sa.setup(d1, variant, o)
+    before = sa.hierarchy_info(G)
+    sa.refresh(G, d2)
+    F = sa.setup(d2, variant, o)
+    gi, fi = sa.hierarchy_info(G), sa.hierarchy_info(F)
+    assert gi["t_refresh_ms"] > 0.0 and fi["t_refresh_ms"] == 0.0
+    assert gi["n_unknowns"] == fi["n_unknowns"] == before["n_unknowns"]
+    assert gi["lambda_est"] == fi["lambda_est"] and gi["omega"] == fi["omega"]
+    assert gi["lambda_est"][0] != before["lambda_est"][0]
+    for l in range(gi["n_levels"]):
+        dims = gi["dims"][l]
+        assert np.array_equal(sa.level_coefficients(G, l, dims), sa.level_coefficients(F, l, dims))
+    b = _to_dev(W.rhs(W.small(s2, nx, ny, nz, variant, robin=robin)))
+    xg = torch.zeros_like(b)
+    xf = torch.zeros_like(b)
+    rg = sa.solve(G, b, xg, tol=1e-9)
+    rf = sa.solve(F, b, xf, tol=1e-9)
+    torch.cuda.synchronize()
+    assert rg["status"] == 0 and rg["iterations"] == rf["iterations"]
+    assert torch.equal(xg, xf)
+
+
+def test_refresh_matches_oracle():
+    s1, s2 = W.Shape.cylinder(1.0, 2.0), W.Shape.cylinder(1.0, 2.7)
+    n = (33, 33, 33)
+    print("[case] refresh vs oracle cyl 33^3", flush=True)
+    _, H1 = solve.build(s1, *n, W.VARIANT_LIN)
+    sys2, R = solve.refresh(s2, *n, W.VARIANT_LIN, H1)
+    G = sa.setup(sa.domain_for(s1, *n), W.VARIANT_LIN)
+    sa.refresh(G, sa.domain_for(s2, *n))
+    info = sa.hierarchy_info(G)
+    assert info["n_unknowns"] == R.sizes
+    for l, lv in enumerate(R.levels[:-1]):
+        assert abs(info["lambda_est"][l] - lv.lam) <= 1e-10 * lv.lam
+        assert abs(info["omega"][l] - lv.omega) <= 1e-10 * lv.omega
+    b_box = W.rhs(W.small(s2, *n, W.VARIANT_LIN))
+    ref = solve.solve(sys2, R, b_box, tol=1e-10)
+    x_ref = sys2.scatter(operator.unscale(sys2, ref.x))
+    b = _to_dev(b_box)
+    x = torch.zeros_like(b)
+    res = sa.solve(G, b, x, tol=1e-10)
+    got = x.cpu().numpy().reshape(x_ref.shape)
+    assert abs(res["iterations"] - ref.iterations) <= 1
+    assert np.linalg.norm(got - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+
+
+def test_refresh_rejects_other_unknowns_and_keeps_the_hierarchy():
+    n = (31, 31, 45)
+    s1, s2 = W.Shape.boxbore(0.8, 4.0, 0.5), W.Shape.boxbore(0.8, 4.0, 0.4)
+    print("[case] refresh rejected: boxbore bore 0.5 -> 0.4", flush=True)
+    d1, d2 = sa.domain_for(s1, *n), sa.domain_for(s2, *n)
+    assert not np.array_equal(d1.mask, d2.mask)
+    G = sa.setup(d1, W.VARIANT_LIN)
+    b = _to_dev(W.rhs(W.small(s1, *n, W.VARIANT_LIN)))
+    x0 = torch.zeros_like(b)
+    r0 = sa.solve(G, b, x0)
+    with pytest.raises(sa.SaamgError, match="unknowns"):
+        sa.refresh(G, d2)
+    # a box of another size is rejected too
+    with pytest.raises(sa.SaamgError, match="box"):
+        sa.refresh(G, sa.domain_for(s1, 31, 31, 47))
+    x1 = torch.zeros_like(b)
+    r1 = sa.solve(G, b, x1)
+    torch.cuda.synchronize()
+    assert r1["iterations"] == r0["iterations"] and torch.equal(x0, x1)
+
+
+def test_refresh_rejected_while_a_state_exists():
+    s1, s2 = W.Shape.cylinder(1.0, 2.0), W.Shape.cylinder(1.0, 2.5)
+    n = (25, 25, 25)
+    print("[case] refresh with a live state", flush=True)
+    G = sa.setup(sa.domain_for(s1, *n), W.VARIANT_LIN)
+    b = _to_dev(W.rhs(W.small(s1, *n, W.VARIANT_LIN)))
+    S = sa.state_create(G, b)
+    with pytest.raises(sa.SaamgError, match="states"):
+        sa.refresh(G, sa.domain_for(s2, *n))
+    sa.state_destroy(S)
+    sa.refresh(G, sa.domain_for(s2, *n))
+    x = torch.zeros_like(b)
+    assert sa.solve(G, b, x)["status"] == 0
