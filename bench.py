@@ -543,6 +543,40 @@ def main():
         print(f"[bench] coarse Gauss-Seidel: setup {1e3 * t_setup:.1f} ms, "
               f"{1e3 * t_solve:.2f} ms per solve, {rg['iterations']} it", file=sys.stderr, flush=True)
         del x
+        # reuse of the aggregation hierarchy (Section 5.2): the bunch elongates, so h_z
+        # grows while the lattice and its unknowns stay; numeric-only re-setups of one
+        # hierarchy against fresh setups of the same domains
+        import dataclasses
+        H = sa.setup(dom, w.variant, sa.default_options(precision=sa.MIXED))
+        t_refresh, t_fresh, it_refresh, it_fresh = [], [], [], []
+        x = torch.zeros(nbox, dtype=torch.float64, device=dev)
+        for grow in (1.05, 1.10, 1.15):
+            d2 = sa.domain_for(dataclasses.replace(w.shape, length=w.shape.length * grow),
+                               w.nx, w.ny, w.nz)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sa.refresh(H, d2)
+            torch.cuda.synchronize()
+            t_refresh.append(time.perf_counter() - t0)
+            it_refresh.append(sa.solve(H, b, x, tol=w.tol, max_iter=500)["iterations"])
+            t0 = time.perf_counter()
+            F = sa.setup(d2, w.variant, sa.default_options(precision=sa.MIXED))
+            torch.cuda.synchronize()
+            t_fresh.append(time.perf_counter() - t0)
+            it_fresh.append(sa.solve(F, b, x, tol=w.tol, max_iter=500)["iterations"])
+            sa.destroy(F)
+        torch.cuda.synchronize()
+        sa.destroy(H)
+        del x
+        line["hierarchy_reuse"] = {
+            "workload": f"{w.name} with the length grown by 5, 10 and 15 % (h_z changes, "
+                        f"same unknowns), mixed precision",
+            "refresh_ms": [round(1e3 * t, 1) for t in t_refresh],
+            "fresh_setup_ms": [round(1e3 * t, 1) for t in t_fresh],
+            "refresh_over_setup": sum(t_refresh) / sum(t_fresh),
+            "iterations_refreshed": it_refresh, "iterations_fresh": it_fresh}
+        print(f"[bench] hierarchy reuse: refresh {[round(1e3 * t) for t in t_refresh]} ms vs "
+              f"fresh setup {[round(1e3 * t) for t in t_fresh]} ms", file=sys.stderr, flush=True)
     if not args.no_serve:
         sv = serve_bench(args, n_requests=args.line_serve_requests)
         m, f = sv["open_loop_mixed"], sv["open_loop_fp64"]

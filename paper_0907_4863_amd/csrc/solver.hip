@@ -4,7 +4,6 @@
 // Algorithm 1), Table 1 (coarse size limit 1000), Section 5 (relative-residual stop).
 #include <algorithm>
 #include <array>
-#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -536,7 +535,9 @@ struct DomainPrep {
     std::vector<double> nw_frac;
 };
 
-static DomainPrep prepare_domain(const saamg_domain* dom, int variant) {
+// scan_mask = false skips the mask's own checks (count, faces, open ends): a refresh
+// compares the mask with the hierarchy's, which passed them.
+static DomainPrep prepare_domain(const saamg_domain* dom, int variant, bool scan_mask = true) {
     if (!dom || !dom->mask) throw ApiError{SAAMG_INVALID_ARG, "domain or mask is NULL"};
     const int nx = dom->nx, ny = dom->ny, nz = dom->nz;
     if (nx < 3 || ny < 3 || nz < 3) throw ApiError{SAAMG_INVALID_ARG, "box must be at least 3^3"};
@@ -551,21 +552,25 @@ static DomainPrep prepare_domain(const saamg_domain* dom, int variant) {
     DomainPrep D;
     const long nxy = (long)nx * ny, nbox = nxy * nz;
     const uint8_t* m = dom->mask;
-    for (long k = 0; k < nz; ++k)
-        for (long j = 0; j < ny; ++j)
-            for (long i = 0; i < nx; ++i) {
-                const long idx = i + nx * j + nxy * k;
-                if (!m[idx]) continue;
-                if (i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1)
-                    throw ApiError{SAAMG_INVALID_ARG, "an unknown lies on a face of the box"};
-                ++D.n_unk;
-            }
-    if (D.n_unk == 0) throw ApiError{SAAMG_INVALID_ARG, "the domain has no unknowns"};
+    // unknowns: their number, and none on a face of the box
+    if (scan_mask) {
+        for (long t = 0; t < nbox; ++t) D.n_unk += m[t] != 0;
+        if (D.n_unk == 0) throw ApiError{SAAMG_INVALID_ARG, "the domain has no unknowns"};
+        bool on_face = false;
+        for (long t = 0; t < nxy && !on_face; ++t) on_face = m[t] || m[t + nxy * (nz - 1)];
+        for (long k = 0; k < nz && !on_face; ++k)
+            for (long i = 0; i < nx; ++i)
+                on_face = on_face || m[i + nxy * k] || m[i + nx * (ny - 1) + nxy * k];
+        for (long k = 0; k < nz && !on_face; ++k)
+            for (long j = 0; j < ny; ++j)
+                on_face = on_face || m[nx * j + nxy * k] || m[nx - 1 + nx * j + nxy * k];
+        if (on_face) throw ApiError{SAAMG_INVALID_ARG, "an unknown lies on a face of the box"};
+    }
 
     const bool open = dom->robin_d > 0.0;
     if (dom->robin_d < 0.0 || !std::isfinite(dom->robin_d))
         throw ApiError{SAAMG_INVALID_ARG, "robin_d must be 0 (closed ends) or positive"};
-    if (open) {
+    if (open && scan_mask) {
         if (nz < 4) throw ApiError{SAAMG_INVALID_ARG, "open ends need at least 4 box planes"};
         // end-plane unknowns (planes 1 and nz-2) need an unknown on the inner side
         for (long j = 0; j < ny; ++j)
@@ -577,10 +582,12 @@ static DomainPrep prepare_domain(const saamg_domain* dom, int variant) {
             }
     }
 
-    std::map<int64_t, std::array<double, 6>> nw;
+    // wall entries, checked and ordered by (node, direction); the domain builder emits
+    // them in that order already, so the sort is usually skipped
+    const int64_t nw_in = dom->n_wall;
     const long step[6] = {-1, 1, -(long)nx, (long)nx, -nxy, nxy};
-    std::vector<int64_t> seen;
-    for (int64_t e = 0; e < dom->n_wall; ++e) {
+    std::vector<int64_t> key(nw_in);
+    for (int64_t e = 0; e < nw_in; ++e) {
         const int64_t node = dom->wall_node[e];
         const int d = dom->wall_dir[e];
         const double sv = dom->wall_s[e];
@@ -591,29 +598,43 @@ static DomainPrep prepare_domain(const saamg_domain* dom, int variant) {
                            "wall entry must name an unknown whose neighbour is not an unknown"};
         if (!(sv > 1e-12) || !(sv <= 1.0))
             throw ApiError{SAAMG_INVALID_ARG, "wall fraction must lie in (1e-12, 1]"};
-        seen.push_back(node * 8 + d);
-        if (sv < 1.0 && variant != SAAMG_VARIANT_CONST) {
-            auto it = nw.find(node);
-            if (it == nw.end()) it = nw.emplace(node, std::array<double, 6>{1, 1, 1, 1, 1, 1}).first;
-            it->second[d] = sv;
-        }
+        key[e] = node * 8 + d;
     }
-    std::sort(seen.begin(), seen.end());
-    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
-        throw ApiError{SAAMG_INVALID_ARG, "duplicate wall entry"};
+    std::vector<int64_t> order;
+    const bool sorted = std::is_sorted(key.begin(), key.end());
+    if (!sorted) {
+        order.resize(nw_in);
+        for (int64_t e = 0; e < nw_in; ++e) order[e] = e;
+        std::sort(order.begin(), order.end(), [&](int64_t p, int64_t q) { return key[p] < key[q]; });
+    }
+    auto at = [&](int64_t r) { return sorted ? r : order[r]; };
+    for (int64_t r = 1; r < nw_in; ++r)
+        if (key[at(r)] == key[at(r - 1)]) throw ApiError{SAAMG_INVALID_ARG, "duplicate wall entry"};
+
+    // near-wall rows in node order: the cut entries (not for the constant rule) merged
+    // with the open-end planes' unknowns
+    std::vector<int64_t> ends;
     if (open)
         for (long k : {1L, (long)nz - 2})
-            for (long j = 0; j < ny; ++j)
-                for (long i = 0; i < nx; ++i) {
-                    const long idx = i + nx * j + nxy * k;
-                    if (m[idx]) nw.emplace(idx, std::array<double, 6>{1, 1, 1, 1, 1, 1});
-                }
-    D.nw_nodes.reserve(nw.size());
-    D.nw_frac.reserve(6 * nw.size());
-    for (const auto& kv : nw) {
-        D.nw_nodes.push_back(kv.first);
-        for (int q = 0; q < 6; ++q) D.nw_frac.push_back(kv.second[q]);
+            for (long t = 0; t < nxy; ++t)
+                if (m[t + nxy * k]) ends.push_back(t + nxy * k);
+    auto add_row = [&](int64_t node) {
+        D.nw_nodes.push_back(node);
+        for (int q = 0; q < 6; ++q) D.nw_frac.push_back(1.0);
+    };
+    size_t ei = 0;
+    const bool cuts = variant != SAAMG_VARIANT_CONST;
+    for (int64_t r = 0; r < nw_in; ++r) {
+        const int64_t e = at(r);
+        const double sv = dom->wall_s[e];
+        if (!cuts || !(sv < 1.0)) continue;
+        const int64_t node = key[e] >> 3;
+        while (ei < ends.size() && ends[ei] < node) add_row(ends[ei++]);
+        if (ei < ends.size() && ends[ei] == node) ++ei;
+        if (D.nw_nodes.empty() || D.nw_nodes.back() != node) add_row(node);
+        D.nw_frac[D.nw_frac.size() - 6 + (key[e] & 7)] = sv;
     }
+    while (ei < ends.size()) add_row(ends[ei++]);
     return D;
 }
 
@@ -879,13 +900,11 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
 static void refresh_impl(saamg_hierarchy* H, const saamg_domain* dom, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
     FineLevel& L = H->l0;
-    const DomainPrep D = prepare_domain(dom, H->variant);
-    if (dom->nx != L.nx || dom->ny != L.ny || dom->nz != L.nz)
+    if (dom && dom->mask && (dom->nx != L.nx || dom->ny != L.ny || dom->nz != L.nz))
         throw ApiError{SAAMG_INVALID_ARG, "the domain's box differs from the hierarchy's"};
+    const DomainPrep D = prepare_domain(dom, H->variant, false);
     if ((dom->robin_d > 0.0) != (L.robin_d > 0.0))
         throw ApiError{SAAMG_INVALID_ARG, "the end condition kind (open or closed) differs"};
-    if (D.n_unk != L.n_unknowns)
-        throw ApiError{SAAMG_INVALID_ARG, "the domain's unknowns differ from the hierarchy's"};
     if (H->live_states > 0)
         throw ApiError{SAAMG_INVALID_ARG, "solve states of this hierarchy still exist"};
 
