@@ -178,6 +178,27 @@ __device__ inline int span_lane(uint64_t u, int lane) {
     return min(max(lane, lo), hi);
 }
 
+// Whole-wavefront shift by one lane (DPP wave_shr:1 / wave_shl:1): lane l receives
+// lane l-1 (UP) or l+1 (down); the lane without a source keeps `edge`.
+template <bool UP, class V>
+__device__ __forceinline__ V wave_shift(V src, V edge) {
+    constexpr int ctrl = UP ? 0x138 : 0x130;
+    if constexpr (sizeof(V) == 4) {
+        return __builtin_bit_cast(V, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, src), ctrl,
+                                                                 0xf, 0xf, false));
+    } else {
+        static_assert(sizeof(V) == 8, "4- or 8-byte values");
+        const uint64_t s = __builtin_bit_cast(uint64_t, src), e = __builtin_bit_cast(uint64_t, edge);
+        const uint32_t lo = __builtin_amdgcn_update_dpp((int)(uint32_t)e, (int)(uint32_t)s, ctrl,
+                                                        0xf, 0xf, false);
+        const uint32_t hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(e >> 32),
+                                                        (int)(uint32_t)(s >> 32), ctrl, 0xf, 0xf,
+                                                        false);
+        return __builtin_bit_cast(V, ((uint64_t)hi << 32) | lo);
+    }
+}
+
 template <typename T, bool STENCIL, bool TR, class Load, class Fetch, class Body>
 __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch, Body body) {
     using FV = decltype(fetch(Idx{0, 0u}, 0, 0, 0, false, 0));
@@ -271,10 +292,8 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
         if (P.u != 0) {
             TX xm = TX(0), xp = TX(0);
             if (STENCIL) {
-                xm = __shfl_up(c, 1, kWave);
-                xp = __shfl_down(c, 1, kWave);
-                if (lane == 0) xm = P.edge;
-                if (lane == kWave - 1) xp = P.edge;
+                xm = wave_shift<true>(c, P.edge);
+                xp = wave_shift<false>(c, P.edge);
             }
             if ((P.u >> lane) & 1ull) {
                 const Idx i{rb + nxy * z, (unsigned)lane};
@@ -344,14 +363,22 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(const double* __restri
         case FIN_STORE:
             for (int q = 0; q < nq; ++q) scal[dst + q] = sums[q];
             break;
-        case FIN_ALPHA:
+        case FIN_ALPHA: {
+            // the step is taken only when p.q > 0, r.z > 0 and alpha is finite
+            const double a = scal[S_RHO] / sums[0];
             scal[S_PQ] = sums[0];
-            scal[S_ALPHA] = scal[S_RHO] / sums[0];
+            scal[S_ALPHA] = a;
+            scal[S_XA] = (sums[0] > 0.0 && scal[S_RHO] > 0.0 && isfinite(a)) ? a : 0.0;
             break;
+        }
         case FIN_RHO_INIT:
             scal[S_RHO] = sums[0];
             scal[S_RHO_PREV] = sums[0];
             scal[S_BETA] = 0.0;
+            scal[S_XA] = 0.0;
+            break;
+        case FIN_XA_CLEAR:
+            scal[S_XA] = 0.0;
             break;
         case FIN_RHO:
             scal[S_BETA] = sums[0] / scal[S_RHO];
@@ -1062,20 +1089,26 @@ void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, 
 
 // Direction update with the product by A carried along:  p <- z + beta p and
 // q <- A z + beta q, which equals A p_new because q held A p_old.  The stencil runs on z
-// (fp32 in mixed precision), the sums in fp64; partials of p . q.
+// (fp32 in mixed precision), the sums in fp64; partials of p . q.  The previous step's
+// x += alpha p, deferred to here, is applied with the old p as it is read.
 template <typename TZ>
 __global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ* __restrict__ zv,
+                                                    double* __restrict__ xv,
                                                     double* __restrict__ p, double* __restrict__ q,
                                                     const double* __restrict__ scal, double* part) {
     __shared__ double lds[kMThreads / kWave];
     const double beta = scal[S_BETA];
+    const double xa = scal[S_XA];
     double acc = 0.0;
     l0_march<double, true, false>(
         v, [&](Idx j) { return at(zv, j); },
-        [&](Idx i, int, int, int, bool, int) { return Vals<double, 2>{{at(p, i), at(q, i)}}; },
-        [&](Idx i, Vals<double, 2> f, double zi, double az, int, int, int, bool, int) {
+        [&](Idx i, int, int, int, bool, int) {
+            return Vals<double, 3>{{at(p, i), at(q, i), at(xv, i)}};
+        },
+        [&](Idx i, Vals<double, 3> f, double zi, double az, int, int, int, bool, int) {
             const double pi = zi + beta * f.v[0];
             const double qi = az + beta * f.v[1];
+            at(xv, i) = f.v[2] + xa * f.v[0];
             at(p, i) = pi;
             at(q, i) = qi;
             acc += pi * qi;
@@ -1085,38 +1118,35 @@ __global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ*
 }
 
 template <typename TZ>
-void cg_pq(const FineLevel& L, const TZ* z, double* p, double* q, const double* scal,
+void cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
            double* partials, hipStream_t s) {
-    KTimer kt_(T_CG_PQ, s, L.n_unknowns * (long)(sizeof(TZ) + 32) + l0_meta_bytes(L, 8, false));
+    KTimer kt_(T_CG_PQ, s, L.n_unknowns * (long)(sizeof(TZ) + 48) + l0_meta_bytes(L, 8, false));
     hipLaunchKernelGGL((k_cg_pq<TZ>), l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), z,
-                       p, q, scal, partials);
+                       x, p, q, scal, partials);
     HIPCHECK(hipGetLastError());
 }
-template void cg_pq<double>(const FineLevel&, const double*, double*, double*, const double*,
-                            double*, hipStream_t);
-template void cg_pq<float>(const FineLevel&, const float*, double*, double*, const double*,
-                           double*, hipStream_t);
+template void cg_pq<double>(const FineLevel&, const double*, double*, double*, double*,
+                            const double*, double*, hipStream_t);
+template void cg_pq<float>(const FineLevel&, const float*, double*, double*, double*,
+                           const double*, double*, hipStream_t);
 
-// x += alpha p; r -= alpha q; partials of r.r.  Skipped (x, r untouched) when the step
-// broke down: p.q <= 0, r.z <= 0 or a non-finite alpha.
-__global__ void __launch_bounds__(kMThreads) k_cg_xr(L0View<double> v, double* __restrict__ xv,
-                                                    const double* __restrict__ p,
-                                                    double* __restrict__ r,
+// r -= alpha q (alpha = S_XA) and partials of r.r; r untouched when the step broke down
+// (S_XA = 0).  x receives alpha p later (the next k_cg_pq or k_cg_xflush).
+__global__ void __launch_bounds__(kMThreads) k_cg_xr(L0View<double> v, double* __restrict__ r,
                                                     const double* __restrict__ q,
                                                     const double* __restrict__ scal, double* part,
                                                     float* __restrict__ r32) {
     __shared__ double lds[kMThreads / kWave];
-    const double alpha = scal[S_ALPHA];
-    const bool ok = scal[S_PQ] > 0.0 && scal[S_RHO] > 0.0 && isfinite(alpha);
+    const double alpha = scal[S_XA];
+    const bool ok = alpha != 0.0;
     double acc = 0.0;
     l0_march<double, false, false>(
-        v, [&](long) { return 0.0; },
-        [&](Idx i, int, int, int, bool, int) { return Vals<double, 4>{{at(xv, i), at(p, i), at(r, i), at(q, i)}}; },
-        [&](Idx i, Vals<double, 4> f, double, double, int, int, int, bool, int) {
-            double ri = f.v[2];
+        v, [&](Idx) { return 0.0; },
+        [&](Idx i, int, int, int, bool, int) { return Vals<double, 2>{{at(r, i), at(q, i)}}; },
+        [&](Idx i, Vals<double, 2> f, double, double, int, int, int, bool, int) {
+            double ri = f.v[0];
             if (ok) {
-                at(xv, i) = f.v[0] + alpha * f.v[1];
-                ri -= alpha * f.v[3];
+                ri -= alpha * f.v[1];
                 at(r, i) = ri;
                 if (r32) at(r32, i) = (float)ri;
             }
@@ -1126,11 +1156,29 @@ __global__ void __launch_bounds__(kMThreads) k_cg_xr(L0View<double> v, double* _
     if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
-void cg_xr(const FineLevel& L, double* x, const double* p, double* r, const double* q,
-           const double* scal, double* partials, float* r32, hipStream_t s) {
-    KTimer kt_(T_CG_XR, s, L.n_unknowns * (48L + (r32 ? 4 : 0)));
-    hipLaunchKernelGGL(k_cg_xr, l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), x, p, r,
-                       q, scal, partials, r32);
+void cg_xr(const FineLevel& L, double* r, const double* q, const double* scal, double* partials,
+           float* r32, hipStream_t s) {
+    KTimer kt_(T_CG_XR, s, L.n_unknowns * (24L + (r32 ? 4 : 0)));
+    hipLaunchKernelGGL(k_cg_xr, l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), r, q, scal,
+                       partials, r32);
+    HIPCHECK(hipGetLastError());
+}
+
+__global__ void __launch_bounds__(kMThreads) k_cg_xflush(L0View<double> v, double* __restrict__ xv,
+                                                        const double* __restrict__ p,
+                                                        const double* __restrict__ scal) {
+    const double xa = scal[S_XA];
+    l0_march<double, false, false>(
+        v, [&](Idx) { return 0.0; },
+        [&](Idx i, int, int, int, bool, int) { return Vals<double, 2>{{at(xv, i), at(p, i)}}; },
+        [&](Idx i, Vals<double, 2> f, double, double, int, int, int, bool, int) {
+            at(xv, i) = f.v[0] + xa * f.v[1];
+        });
+}
+
+void cg_xflush(const FineLevel& L, double* x, const double* p, const double* scal, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_xflush, l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), x, p,
+                       scal);
     HIPCHECK(hipGetLastError());
 }
 

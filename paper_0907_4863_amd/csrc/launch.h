@@ -24,10 +24,13 @@ namespace saamg {
 // Scalar slots in the per-solve device array `scal`.
 enum Slot {
     S_RHO = 0, S_RHO_PREV, S_ALPHA, S_BETA, S_PQ, S_RR, S_BB, S_R0,
-    S_INVN, S_LAM, S_RT, S_LZ_S, S_LZ_SP, S_LZ_B, S_NSLOTS = 16
+    S_INVN, S_LAM, S_RT, S_LZ_S, S_LZ_SP, S_LZ_B,
+    S_XA,  // step length still owed to x (x += S_XA p); 0 after a broken-down step
+    S_NSLOTS = 16
 };
 // Finalisation ops: how the summed partials update `scal`.
-enum FinOp { FIN_STORE = 0, FIN_ALPHA, FIN_RHO_INIT, FIN_RHO, FIN_LZ_ALPHA, FIN_LZ_BETA, FIN_NORM, FIN_RESTORE_RHO };
+enum FinOp { FIN_STORE = 0, FIN_ALPHA, FIN_RHO_INIT, FIN_RHO, FIN_LZ_ALPHA, FIN_LZ_BETA, FIN_NORM,
+             FIN_RESTORE_RHO, FIN_XA_CLEAR };
 // Chebyshev step kinds.
 enum ChebMode { CHEB_ZERO1 = 0, CHEB_ZERO2, CHEB_FIRST, CHEB_NEXT };
 
@@ -84,10 +87,12 @@ void cg_init(const FineLevel& L, const double* b, const double* x0, double* bs, 
 void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
               float* r32, hipStream_t s);
 template <typename TZ>
-void cg_pq(const FineLevel& L, const TZ* z, double* p, double* q, const double* scal,
+void cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
            double* partials, hipStream_t s);
-void cg_xr(const FineLevel& L, double* x, const double* p, double* r, const double* q,
-           const double* scal, double* partials, float* r32, hipStream_t s);
+void cg_xr(const FineLevel& L, double* r, const double* q, const double* scal, double* partials,
+           float* r32, hipStream_t s);
+// x += S_XA p: the update the last step still owes x
+void cg_xflush(const FineLevel& L, double* x, const double* p, const double* scal, hipStream_t s);
 void cg_unscale(const FineLevel& L, const double* x, double* out, hipStream_t s);
 // out = in on the unknowns (out untouched elsewhere)
 void cg_mask_copy(const FineLevel& L, const double* in, double* out, float* out32, hipStream_t s);

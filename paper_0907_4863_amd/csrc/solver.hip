@@ -318,11 +318,11 @@ static void state_enqueue(saamg_state* S) {
     const saamg_hierarchy* H = S->H;
     const long nb = l0_blocks(H->l0);
     if (S->mixed)
-        cg_pq<float>(H->l0, (const float*)S->z, S->p, S->q, S->scal, S->part, S->s);
+        cg_pq<float>(H->l0, (const float*)S->z, S->x, S->p, S->q, S->scal, S->part, S->s);
     else
-        cg_pq<double>(H->l0, (const double*)S->z, S->p, S->q, S->scal, S->part, S->s);
+        cg_pq<double>(H->l0, (const double*)S->z, S->x, S->p, S->q, S->scal, S->part, S->s);
     finalize(S->part, nb, 1, S->scal, FIN_ALPHA, 0, S->s);
-    cg_xr(H->l0, S->x, S->p, S->r, S->q, S->scal, S->part, S->r32, S->s);
+    cg_xr(H->l0, S->r, S->q, S->scal, S->part, S->r32, S->s);
     finalize(S->part, nb, 1, S->scal, FIN_STORE, S_RR, S->s);
     HIPCHECK(hipMemcpyAsync(S->hscal, S->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
                             S->s));
@@ -331,24 +331,34 @@ static void state_enqueue(saamg_state* S) {
     finalize(S->part, nb, 1, S->scal, FIN_RHO, 0, S->s);
 }
 
+// The step length a step still owes x (each step's x += alpha p is applied by the next
+// step's direction update): apply it now and clear it.  Needed before x is read.
+static void flush_x(saamg_state* S) {
+    cg_xflush(S->H->l0, S->x, S->p, S->scal, S->s);
+    finalize(S->part, 1, 0, S->scal, FIN_XA_CLEAR, 0, S->s);
+}
+
 static void state_complete(saamg_state* S) {
     HIPCHECK(hipEventSynchronize(S->ev));
     S->iter += 1;
     const double pq = S->hscal[S_PQ], rho = S->hscal[S_RHO], rr = S->hscal[S_RR];
     const double alpha = S->hscal[S_ALPHA];
     if (!std::isfinite(pq) || !std::isfinite(rho) || !std::isfinite(alpha)) {
+        flush_x(S);
         S->status = SAAMG_NONFINITE;
         S->done = 1;
         S->rel_true = S->rel_rec = NAN;
         return;
     }
     if (pq <= 0.0 || rho <= 0.0) {
+        flush_x(S);
         S->status = SAAMG_BREAKDOWN;
         S->done = 1;
         S->rel_true = std::sqrt(true_residual(S, S->q)) / S->bnorm;
         return;
     }
     if (!std::isfinite(rr)) {
+        flush_x(S);
         S->status = SAAMG_NONFINITE;
         S->done = 1;
         S->rel_true = S->rel_rec = NAN;
@@ -356,6 +366,7 @@ static void state_complete(saamg_state* S) {
     }
     S->rel_rec = std::sqrt(rr) / S->bnorm;
     if (S->rel_rec <= S->tol) {
+        flush_x(S);
         const double rt = true_residual(S, S->r);
         S->rel_true = std::sqrt(rt) / S->bnorm;
         if (S->rel_true <= S->tol) {
@@ -370,6 +381,7 @@ static void state_complete(saamg_state* S) {
         finalize(S->part, nb, 1, S->scal, FIN_RHO, 0, S->s);
     }
     if (S->iter >= S->max_iter) {
+        flush_x(S);
         S->status = SAAMG_NOT_CONVERGED;
         S->done = 1;
         S->rel_true = std::sqrt(true_residual(S, S->q)) / S->bnorm;
@@ -1286,6 +1298,7 @@ int saamg_state_finish(saamg_state* S, double* d_x) {
     return guarded([&] {
         if (!S || !d_x) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
         HIPCHECK(hipSetDevice(S->H->device));
+        if (!S->done) flush_x(S);  // an unfinished state's iterate, with its last step
         cg_unscale(S->H->l0, S->x, d_x, S->s);
         HIPCHECK(hipStreamSynchronize(S->s));
         return (int)SAAMG_OK;
