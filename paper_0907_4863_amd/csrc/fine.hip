@@ -134,15 +134,15 @@ __device__ inline uint64_t lane_u64(uint64_t v, int k) {
 // front (one plane per lane) and broadcast per step; a row without unknowns in the tile
 // exits at once.
 //
-// Every load of a plane is issued unconditionally, so the loads of plane z+1 are all in
-// flight while plane z is computed and a wavefront waits for one memory round trip per
-// plane.  To keep those loads from touching lines the row does not need, a lane outside
-// the span [first, last unknown] of its row in that plane reads at the nearest end of
-// the span instead (fetch then sees that node's index and coordinates); such values are
-// never used by the lane itself and are replaced by zero before they serve as a
-// neighbour's x- or z-neighbour.  x-neighbours come from adjacent lanes (the two edge
-// lanes read theirs with the same load instruction), z-neighbours from registers,
-// y-neighbours from L1/L2.
+// The loads of a plane are issued one plane ahead, without waiting on anything of the
+// current plane, so the loads of plane z+1 are all in flight while plane z is computed
+// and a wavefront waits for one memory round trip per plane.  To keep those loads from
+// touching lines the row does not need, a lane outside the span [first, last unknown] of
+// its row in that plane reads at the nearest end of the span instead (fetch then sees
+// that node's index and coordinates); such values are never used by the lane itself and
+// are replaced by zero before they serve as a neighbour's x- or z-neighbour.
+// x-neighbours come from adjacent lanes (the two edge lanes load theirs), z-neighbours
+// from registers, y-neighbours from L1/L2; table rows are loaded by the irregular lanes.
 template <typename T, typename TX, class FV>
 struct PlaneLoads {
     uint64_t u;   // unknown bits of the segment row
@@ -249,15 +249,20 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
             P.ym = X(Idx{ib - nx, (unsigned)lc});
             P.yp = X(Idx{ib + nx, (unsigned)lc});
             // the edge lanes' outer x-neighbours (from a base one node lower, so that the
-            // offset stays non-negative)
-            P.edge = X(Idx{ib - 1, (unsigned)(lc + 1 + (ins ? eo : 0))});
-            // rows with an irregular node: every lane reads a table row (its own slot if
-            // irregular, else the row's first)
+            // offset stays non-negative); only those two lanes load
+            P.edge = TX(0);
+            if (lane == 0 || lane == kWave - 1)
+                P.edge = X(Idx{ib - 1, (unsigned)(lc + 1 + (ins ? eo : 0))});
+            // rows with an irregular node: the irregular lanes read their table row
             P.tab = r != 0;
             if (P.tab) {
-                const Idx ti{rbase, P.irr ? rofs : 0u};
+                const Idx ti{rbase, rofs};
 #pragma unroll
-                for (int d = 0; d < 6; ++d) P.t[d] = at(tb[d], ti);
+                for (int d = 0; d < 6; ++d) P.t[d] = T(0);
+                if (P.irr) {
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) P.t[d] = at(tb[d], ti);
+                }
             } else {
 #pragma unroll
                 for (int d = 0; d < 6; ++d) P.t[d] = T(0);
