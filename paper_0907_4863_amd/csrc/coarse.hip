@@ -4,28 +4,46 @@
 
 namespace saamg {
 
+// Coefficient k of the row with slot s (compressed operator).
+template <typename T>
+__device__ inline T lc_row(const LCView<T>& c, int s, int k) {
+    return s >= 0 ? c.tab[k][s] : (s == -1 ? c.cst[k] : T(0));
+}
 // Coefficient A(i, k) of a 27-point level.
 template <typename T, bool SYM>
 __device__ inline T lc_a(const LCView<T>& c, long i, int k) {
-    if (SYM && k < 13) return c.coef[26 - k][i + c.off[k]];
-    return c.coef[k][i];
+    return lc_row(c, c.slot[i], k);
 }
 // Coefficient of the transpose: A^T(i, k) = A(i + off(k), 26 - k).
 template <typename T, bool SYM>
 __device__ inline T lc_at(const LCView<T>& c, long i, int k) {
     if (SYM) return lc_a<T, true>(c, i, k);
-    return c.coef[26 - k][i + c.off[k]];
+    return lc_row(c, c.slot[i + c.off[k]], 26 - k);
 }
 
+// sum_k A(i, k) X(i + off_k) (TR: A^T), offsets in order k = 0..26.
 template <typename T, bool SYM, bool TR, class F>
 __device__ inline T lc_stencil(const LCView<T>& c, long i, F X) {
     T acc = 0;
+    if (!TR || SYM) {
+        const int s = c.slot[i];
+        if (s == -1) {
 #pragma unroll
-    for (int k = 0; k < 27; ++k) {
-        const T a = TR ? lc_at<T, SYM>(c, i, k) : lc_a<T, SYM>(c, i, k);
-        acc += a * X(i + c.off[k]);
+            for (int k = 0; k < 27; ++k) acc += c.cst[k] * X(i + c.off[k]);
+        } else if (s >= 0) {
+#pragma unroll
+            for (int k = 0; k < 27; ++k) acc += c.tab[k][s] * X(i + c.off[k]);
+        }
+        return acc;
     }
+#pragma unroll
+    for (int k = 0; k < 27; ++k) acc += lc_at<T, false>(c, i, k) * X(i + c.off[k]);
     return acc;
+}
+
+// A(i, k) from the full fp64 arrays (setup).
+__device__ inline double lc_full(const LCView<double>& c, long i, int k) {
+    return (c.sym && k < 13) ? c.coef[26 - k][i + c.off[k]] : c.coef[k][i];
 }
 
 static inline dim3 lc_grid(const CoarseLevel& C) {
@@ -191,10 +209,10 @@ __global__ void __launch_bounds__(kThreads) k_lc_cheb(LCView<T> c, const T* __re
     if (dout) dout[i] = dn;
 }
 
-// Algorithmic bytes of one coarse-level stencil sweep: coefficient arrays, 1/diag and
-// `nvec` vectors over the level's unknowns.
+// Algorithmic bytes of one coarse-level stencil sweep: slots, 1/diag and `nvec` vectors
+// over the level's unknowns, plus the table rows.
 static inline long lc_bytes(const CoarseLevel& C, int wsize, int nvec) {
-    return C.n_unknowns * (long)wsize * ((C.sym ? 14 : 27) + 1 + nvec);
+    return C.n_unknowns * (4L + (long)wsize * (1 + nvec)) + C.n_tab * 27L * wsize;
 }
 
 template <typename T>
@@ -323,10 +341,11 @@ __global__ void __launch_bounds__(kThreads) k_lc_prolong(LCView<T> c, LCView<T> 
         return ax + (long)cc.sx * ay + cc.sxy * az;
     };
     T apv = 0;
+    const int s = c.slot[i];
 #pragma unroll
     for (int k = 0; k < 27; ++k) {
         const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
-        apv += lc_a<T, SYM>(c, i, k) * vc[agg(X + dx, Y + dy, Z + dz)];
+        apv += lc_row(c, s, k) * vc[agg(X + dx, Y + dy, Z + dz)];
     }
     const T pv = vc[agg(X, Y, Z)];
     xv[i] += pv - omega * id * apv;
@@ -417,13 +436,8 @@ struct AccLC {
         if (c.invD[i] == 0.0) return;
         *unk = true;
         for (int k = 0; k < 27; ++k) {
-            if (c.sym) {
-                a[k] = (k < 13) ? c.coef[26 - k][i + c.off[k]] : c.coef[k][i];
-                at[k] = a[k];
-            } else {
-                a[k] = c.coef[k][i];
-                at[k] = c.coef[26 - k][i + c.off[k]];
-            }
+            a[k] = lc_full(c, i, k);
+            at[k] = c.sym ? a[k] : lc_full(c, i + c.off[k], 26 - k);
         }
     }
     __device__ double invd(int x, int y, int z) const {
@@ -573,12 +587,101 @@ __global__ void k_d2f(const double* a, float* b, long n) {
 
 void lc_to_fp32(CoarseLevel& C, hipStream_t s) {
     const long nb = (C.nstore + 255) / 256;
-    for (int k = 0; k < 27; ++k) {
-        if (!C.coef64[k]) continue;
-        hipLaunchKernelGGL(k_d2f, dim3(nb), dim3(256), 0, s, C.coef64[k], C.coef32[k], C.nstore);
-    }
+    const long nt = 27 * C.tab_cap;
+    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, C.tab64, C.tab32,
+                       nt);
     hipLaunchKernelGGL(k_d2f, dim3(nb), dim3(256), 0, s, C.invD64, C.invD32, C.nstore);
     HIPCHECK(hipGetLastError());
+}
+
+// Compression of a level's operator (after lc_finish).  Pass 1: slot -2 at nodes that are
+// not unknowns, -1 where the row equals the reference row `ref` bit for bit (ref < 0:
+// none does), else irregular; per-64 counts of irregular rows.  Pass 2: table slots in
+// storage order and the table rows.
+__global__ void k_lc_classify(LCView<double> c, long n, long ref, int32_t* __restrict__ slot,
+                              int32_t* __restrict__ cnt) {
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    bool irr = false;
+    if (t < n) {
+        int sv = -2;
+        if (c.invD[t] != 0.0) {
+            bool same = ref >= 0;
+            for (int k = 0; k < 27 && same; ++k) same = lc_full(c, t, k) == lc_full(c, ref, k);
+            sv = same ? -1 : 0;
+            irr = !same;
+        }
+        slot[t] = sv;
+    }
+    const uint64_t bal = __ballot(irr);
+    if ((threadIdx.x & 63) == 0 && t < n) cnt[t >> 6] = __popcll(bal);
+}
+
+__global__ void k_lc_fill(LCView<double> c, long n, const int32_t* __restrict__ base, long cap,
+                          int32_t* __restrict__ slot, double* __restrict__ tab) {
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const bool irr = t < n && slot[t] == 0;  // the classification's mark
+    const uint64_t bal = __ballot(irr);
+    if (!irr) return;
+    const int lane = threadIdx.x & 63;
+    const int s = base[t >> 6] + __popcll(bal & ((1ull << lane) - 1ull));
+    slot[t] = s;
+    for (int k = 0; k < 27; ++k) tab[k * cap + s] = lc_full(c, t, k);
+}
+
+__global__ void k_lc_ref_row(LCView<double> c, long ref, double* out) {
+    const int k = threadIdx.x;
+    if (k < 27) out[k] = lc_full(c, ref, k);
+}
+
+void lc_compress(CoarseLevel& C, hipStream_t s) {
+    const long n = C.nstore, nw = (n + 63) / 64;
+    // reference row: the node at the centre of the box, if it is an unknown
+    long ref = (C.mx / 2 + 1) + (long)C.sx * (C.my / 2 + 1) + C.sxy * (C.mz / 2 + 1);
+    double dref = 0.0;
+    HIPCHECK(hipMemcpyAsync(&dref, C.invD64 + ref, 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (dref == 0.0) ref = -1;
+    if (!C.slot) C.slot = (int32_t*)dmalloc(4 * n);
+    int32_t* cnt = (int32_t*)dmalloc(4 * nw);
+    int32_t* base = (int32_t*)dmalloc(4 * nw);
+    int64_t* tot = (int64_t*)dmalloc(8);
+    double* row = (double*)dmalloc(8 * 27);
+    try {
+        LCView<double> v = C.view<double>();
+        hipLaunchKernelGGL(k_lc_classify, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n,
+                           ref, C.slot, cnt);
+        HIPCHECK(hipGetLastError());
+        exclusive_scan(cnt, base, nw, tot, s);
+        int64_t nt = 0;
+        HIPCHECK(hipMemcpyAsync(&nt, tot, 8, hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        if (nt > C.tab_cap) {  // (re)allocate; the fp32 copy follows in lc_to_fp32's caller
+            dfree(C.tab64);
+            dfree(C.tab32);
+            C.tab32 = nullptr;
+            C.tab_cap = std::max<long>(nt, 1);
+            C.tab64 = (double*)dmalloc(8 * 27 * C.tab_cap);
+        }
+        if (!C.tab64) {
+            C.tab_cap = 1;
+            C.tab64 = (double*)dmalloc(8 * 27);
+        }
+        C.n_tab = nt;
+        hipLaunchKernelGGL(k_lc_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n, base,
+                           C.tab_cap, C.slot, C.tab64);
+        HIPCHECK(hipGetLastError());
+        for (int k = 0; k < 27; ++k) C.cst64[k] = 0.0;
+        if (ref >= 0) {
+            hipLaunchKernelGGL(k_lc_ref_row, dim3(1), dim3(64), 0, s, v, ref, row);
+            HIPCHECK(hipGetLastError());
+            HIPCHECK(hipMemcpyAsync(C.cst64, row, 8 * 27, hipMemcpyDeviceToHost, s));
+        }
+        HIPCHECK(hipStreamSynchronize(s));
+    } catch (...) {
+        for (void* p : {(void*)cnt, (void*)base, (void*)tot, (void*)row}) dfree(p);
+        throw;
+    }
+    for (void* p : {(void*)cnt, (void*)base, (void*)tot, (void*)row}) dfree(p);
 }
 
 // Storage indices of the existing nodes of a coarse level, in increasing order.
@@ -643,8 +746,7 @@ __global__ void k_dense_lc(LCView<double> c, const long* cidx, const int32_t* cm
     if (i >= nL) return;
     const long m = cidx[i];
     for (int k = 0; k < 27; ++k) {
-        const double a = c.sym ? ((k < 13) ? c.coef[26 - k][m + c.off[k]] : c.coef[k][m])
-                               : c.coef[k][m];
+        const double a = lc_full(c, m, k);
         if (a == 0.0) continue;
         const int j = cmap[m + c.off[k]];
         if (j >= 0) A[(long)i * nL + j] = a;

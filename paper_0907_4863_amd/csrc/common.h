@@ -53,15 +53,22 @@ struct L0View {
     double rho_end;     // factor of the end-plane rows (1/2 with open ends, else 1)
 };
 
+// A level >= 1 operator.  The solve kernels read it compressed: a node's row is the
+// level's interior stencil (slot -1), zero (slot -2: not an unknown or a ghost), or row
+// `slot` of the table.  The full per-offset arrays (fp64 views only) serve setup and
+// diagnostics.
 template <typename T>
 struct LCView {
     int mx, my, mz;     // logical box
     int sx, sy;         // storage pitch (mx+2, my+2)
     long sxy;
     long off[27];
-    const T* coef[27];  // storage layout; for symmetric operators coef[k<13] = nullptr
+    const T* coef[27];  // full fp64 arrays, storage layout; symmetric: coef[k<13] = nullptr
     const T* invD;      // 1/diag, 0 at nodes that are not unknowns and in the ghost layer
     int sym;
+    const int32_t* slot;  // per storage node
+    const T* tab[27];     // table rows: tab[k][s] = A(i, i + off[k]) for the node of slot s
+    T cst[27];            // the interior stencil
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -167,10 +174,15 @@ struct CoarseLevel {
     long sxy, nstore;
     int sym;
     double* coef64[27] = {};
-    float* coef32[27] = {};
     double* invD64 = nullptr;
     float* invD32 = nullptr;
     long n_unknowns = 0;
+    // compressed operator: slot per storage node, interior stencil, table [27][tab_cap]
+    int32_t* slot = nullptr;
+    double cst64[27] = {};
+    long n_tab = 0, tab_cap = 0;
+    double* tab64 = nullptr;
+    float* tab32 = nullptr;
 
     template <typename T>
     LCView<T> view() const;
@@ -236,11 +248,18 @@ template <typename T>
 inline LCView<T> CoarseLevel::view() const {
     LCView<T> v;
     v.mx = mx; v.my = my; v.mz = mz; v.sx = sx; v.sy = sy; v.sxy = sxy; v.sym = sym;
+    v.slot = slot;
     for (int k = 0; k < 27; ++k) {
         int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
         v.off[k] = dx + (long)sx * dy + sxy * dz;
-        if constexpr (sizeof(T) == 8) v.coef[k] = coef64[k];
-        else v.coef[k] = coef32[k];
+        v.cst[k] = (T)cst64[k];
+        if constexpr (sizeof(T) == 8) {
+            v.coef[k] = coef64[k];
+            v.tab[k] = tab64 ? tab64 + k * tab_cap : nullptr;
+        } else {
+            v.coef[k] = nullptr;
+            v.tab[k] = tab32 ? tab32 + k * tab_cap : nullptr;
+        }
     }
     if constexpr (sizeof(T) == 8) v.invD = invD64;
     else v.invD = invD32;

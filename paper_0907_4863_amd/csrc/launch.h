@@ -125,6 +125,8 @@ void rap_from_l0(const FineLevel& L, const CoarseLevel& C, double omega, hipStre
 void rap_from_lc(const CoarseLevel& F, const CoarseLevel& C, double omega, hipStream_t s);
 void lc_finish(CoarseLevel& C, int32_t* counts, hipStream_t s);    // invD and unknown count
 void lc_to_fp32(CoarseLevel& C, hipStream_t s);
+// compressed operator (slots, interior stencil, table) from the full fp64 arrays
+void lc_compress(CoarseLevel& C, hipStream_t s);
 void l0_to_fp32(FineLevel& L, hipStream_t s);
 void lc_unknown_list(const CoarseLevel& C, long* out, int32_t* counter, hipStream_t s);
 

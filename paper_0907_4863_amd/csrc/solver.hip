@@ -504,19 +504,22 @@ static CoarseLevel make_coarse(int fmx, int fmy, int fmz, int sym) {
 static void free_coarse(CoarseLevel& C) {
     for (int k = 0; k < 27; ++k) {
         dfree(C.coef64[k]);
-        dfree(C.coef32[k]);
         C.coef64[k] = nullptr;
-        C.coef32[k] = nullptr;
     }
-    dfree(C.invD64);
-    dfree(C.invD32);
+    for (void* p : {(void*)C.invD64, (void*)C.invD32, (void*)C.slot, (void*)C.tab64, (void*)C.tab32})
+        dfree(p);
     C.invD64 = nullptr;
     C.invD32 = nullptr;
+    C.slot = nullptr;
+    C.tab64 = nullptr;
+    C.tab32 = nullptr;
+    C.tab_cap = C.n_tab = 0;
 }
 
 static int64_t coarse_bytes(const CoarseLevel& C, bool mixed) {
     const int na = C.sym ? 14 : 27;
-    return (int64_t)(na + 1) * C.nstore * (mixed ? 12 : 8);
+    return (int64_t)(na + 1) * C.nstore * 8 + 4L * C.nstore + (mixed ? 4L * C.nstore : 0) +
+           27L * C.tab_cap * (mixed ? 12 : 8);
 }
 
 static void validate_options(const saamg_options& o) {
@@ -728,6 +731,7 @@ static int64_t galerkin(saamg_hierarchy* H, int l, CoarseLevel& C, double omega,
     const long nb = (C.nstore + 255) / 256;
     int32_t* cnt = (int32_t*)dmalloc(4 * 4 * nb);
     lc_finish(C, cnt, s);
+    lc_compress(C, s);
     int64_t* tot = (int64_t*)dmalloc(8);
     exclusive_scan(cnt, nullptr, 4 * nb, tot, s);
     int64_t nc = 0;
@@ -781,8 +785,7 @@ static void build_coarse_solver(saamg_hierarchy* H, hipStream_t s) {
 static void coarse_fp32(saamg_hierarchy* H, hipStream_t s) {
     if (H->opt.precision != SAAMG_MIXED) return;
     for (auto& C : H->lc) {
-        for (int k = 0; k < 27; ++k)
-            if (C.coef64[k] && !C.coef32[k]) C.coef32[k] = (float*)dmalloc(4 * C.nstore);
+        if (!C.tab32) C.tab32 = (float*)dmalloc(4 * 27 * C.tab_cap);
         if (!C.invD32) C.invD32 = (float*)dmalloc(4 * C.nstore);
         lc_to_fp32(C, s);
     }
@@ -947,7 +950,9 @@ static void refresh_impl(saamg_hierarchy* H, const saamg_domain* dom, hipStream_
     for (int l = 0; l + 1 < H->n_levels; ++l) {
         H->par[l] = level_params(H, l, s);
         CoarseLevel& C = H->lc[l];
+        H->bytes -= coarse_bytes(C, H->opt.precision == SAAMG_MIXED);
         const int64_t nc = galerkin(H, l, C, H->par[l].omega, nullptr, s);
+        H->bytes += coarse_bytes(C, H->opt.precision == SAAMG_MIXED);
         if (nc != C.n_unknowns)
             throw ApiError{SAAMG_HIP_ERROR, "coarse level " + std::to_string(l + 1) +
                                                 " changed its unknowns; destroy the hierarchy"};
@@ -1224,7 +1229,8 @@ int saamg_footprint_bytes(int nx, int ny, int nz, int variant, int precision, in
         for (int l = 1; l < 10 && m > 27; ++l) {
             m = (std::ceil(std::cbrt(m) / 3.0) + 2) * (std::ceil(std::cbrt(m) / 3.0) + 2) *
                 (std::ceil(std::cbrt(m) / 3.0) + 2);
-            h += (na + 1) * m * (mixed ? 12 : 8);
+            // full fp64 arrays and 1/diag, slots, fp32 1/diag, table (at most every row)
+            h += ((na + 1) * 8 + 4 + (mixed ? 4 : 0) + 27 * (mixed ? 12 : 8)) * m;
             st += 4 * w * m;
         }
         h += 8.0 * 1000 * 1000;
