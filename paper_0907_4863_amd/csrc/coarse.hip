@@ -14,11 +14,15 @@ template <typename T, bool SYM>
 __device__ inline T lc_a(const LCView<T>& c, long i, int k) {
     return lc_row(c, c.slot[i], k);
 }
-// Coefficient of the transpose: A^T(i, k) = A(i + off(k), 26 - k).
+// Coefficient k of the transpose row with slot s: A^T(i, k) = A(i + off(k), 26 - k).
+template <typename T>
+__device__ inline T lc_rowT(const LCView<T>& c, int s, int k) {
+    return s >= 0 ? c.tabT[k][s] : (s == -1 ? c.cst[26 - k] : T(0));
+}
 template <typename T, bool SYM>
 __device__ inline T lc_at(const LCView<T>& c, long i, int k) {
     if (SYM) return lc_a<T, true>(c, i, k);
-    return lc_row(c, c.slot[i + c.off[k]], 26 - k);
+    return lc_rowT(c, c.slotT[i], k);
 }
 
 // sum_k A(i, k) X(i + off_k) (TR: A^T), offsets in order k = 0..26.
@@ -36,8 +40,14 @@ __device__ inline T lc_stencil(const LCView<T>& c, long i, F X) {
         }
         return acc;
     }
+    const int s = c.slotT[i];
+    if (s == -1) {
 #pragma unroll
-    for (int k = 0; k < 27; ++k) acc += lc_at<T, false>(c, i, k) * X(i + c.off[k]);
+        for (int k = 0; k < 27; ++k) acc += c.cst[26 - k] * X(i + c.off[k]);
+    } else if (s >= 0) {
+#pragma unroll
+        for (int k = 0; k < 27; ++k) acc += c.tabT[k][s] * X(i + c.off[k]);
+    }
     return acc;
 }
 
@@ -590,6 +600,11 @@ void lc_to_fp32(CoarseLevel& C, hipStream_t s) {
     const long nt = 27 * C.tab_cap;
     hipLaunchKernelGGL(k_d2f, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, C.tab64, C.tab32,
                        nt);
+    if (C.tabT64) {
+        const long ntt = 27 * C.tabT_cap;
+        hipLaunchKernelGGL(k_d2f, dim3((unsigned)((ntt + 255) / 256)), dim3(256), 0, s, C.tabT64,
+                           C.tabT32, ntt);
+    }
     hipLaunchKernelGGL(k_d2f, dim3(nb), dim3(256), 0, s, C.invD64, C.invD32, C.nstore);
     HIPCHECK(hipGetLastError());
 }
@@ -626,6 +641,38 @@ __global__ void k_lc_fill(LCView<double> c, long n, const int32_t* __restrict__ 
     const int s = base[t >> 6] + __popcll(bal & ((1ull << lane) - 1ull));
     slot[t] = s;
     for (int k = 0; k < 27; ++k) tab[k * cap + s] = lc_full(c, t, k);
+}
+
+// Transpose rows: slot -2 where every coupling is zero (not an unknown), -1 where the node
+// and its 26 neighbours all have the interior row, else irregular (marked 0).
+__global__ void k_lc_classifyT(LCView<double> c, long n, int32_t* __restrict__ slotT,
+                               int32_t* __restrict__ cnt) {
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    bool irr = false;
+    if (t < n) {
+        int sv = -2;
+        if (c.invD[t] != 0.0) {
+            bool reg = true;
+            for (int k = 0; k < 27 && reg; ++k) reg = c.slot[t + c.off[k]] == -1;
+            sv = reg ? -1 : 0;
+            irr = !reg;
+        }
+        slotT[t] = sv;
+    }
+    const uint64_t bal = __ballot(irr);
+    if ((threadIdx.x & 63) == 0 && t < n) cnt[t >> 6] = __popcll(bal);
+}
+
+__global__ void k_lc_fillT(LCView<double> c, long n, const int32_t* __restrict__ base, long cap,
+                           int32_t* __restrict__ slotT, double* __restrict__ tab) {
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const bool irr = t < n && slotT[t] == 0;  // the classification's mark
+    const uint64_t bal = __ballot(irr);
+    if (!irr) return;
+    const int lane = threadIdx.x & 63;
+    const int s = base[t >> 6] + __popcll(bal & ((1ull << lane) - 1ull));
+    slotT[t] = s;
+    for (int k = 0; k < 27; ++k) tab[k * cap + s] = lc_full(c, t + c.off[k], 26 - k);
 }
 
 __global__ void k_lc_ref_row(LCView<double> c, long ref, double* out) {
@@ -677,6 +724,30 @@ void lc_compress(CoarseLevel& C, hipStream_t s) {
             HIPCHECK(hipMemcpyAsync(C.cst64, row, 8 * 27, hipMemcpyDeviceToHost, s));
         }
         HIPCHECK(hipStreamSynchronize(s));
+        if (!C.sym) {
+            // the transpose, from the slots just built
+            if (!C.slotT) C.slotT = (int32_t*)dmalloc(4 * n);
+            v = C.view<double>();
+            hipLaunchKernelGGL(k_lc_classifyT, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v,
+                               n, C.slotT, cnt);
+            HIPCHECK(hipGetLastError());
+            exclusive_scan(cnt, base, nw, tot, s);
+            int64_t ntt = 0;
+            HIPCHECK(hipMemcpyAsync(&ntt, tot, 8, hipMemcpyDeviceToHost, s));
+            HIPCHECK(hipStreamSynchronize(s));
+            if (ntt > C.tabT_cap || !C.tabT64) {
+                dfree(C.tabT64);
+                dfree(C.tabT32);
+                C.tabT32 = nullptr;
+                C.tabT_cap = std::max<long>(ntt, 1);
+                C.tabT64 = (double*)dmalloc(8 * 27 * C.tabT_cap);
+            }
+            C.n_tabT = ntt;
+            hipLaunchKernelGGL(k_lc_fillT, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n,
+                               base, C.tabT_cap, C.slotT, C.tabT64);
+            HIPCHECK(hipGetLastError());
+            HIPCHECK(hipStreamSynchronize(s));
+        }
     } catch (...) {
         for (void* p : {(void*)cnt, (void*)base, (void*)tot, (void*)row}) dfree(p);
         throw;

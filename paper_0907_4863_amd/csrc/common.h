@@ -69,6 +69,10 @@ struct LCView {
     const int32_t* slot;  // per storage node
     const T* tab[27];     // table rows: tab[k][s] = A(i, i + off[k]) for the node of slot s
     T cst[27];            // the interior stencil
+    // nonsymmetric levels: the transpose, compressed the same way (slot -1: the node and
+    // its 26 neighbours all have the interior row, so A^T(i, k) = cst[26 - k])
+    const int32_t* slotT;
+    const T* tabT[27];
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -183,6 +187,11 @@ struct CoarseLevel {
     long n_tab = 0, tab_cap = 0;
     double* tab64 = nullptr;
     float* tab32 = nullptr;
+    // transpose (nonsymmetric levels only)
+    int32_t* slotT = nullptr;
+    long n_tabT = 0, tabT_cap = 0;
+    double* tabT64 = nullptr;
+    float* tabT32 = nullptr;
 
     template <typename T>
     LCView<T> view() const;
@@ -249,6 +258,7 @@ inline LCView<T> CoarseLevel::view() const {
     LCView<T> v;
     v.mx = mx; v.my = my; v.mz = mz; v.sx = sx; v.sy = sy; v.sxy = sxy; v.sym = sym;
     v.slot = slot;
+    v.slotT = slotT;
     for (int k = 0; k < 27; ++k) {
         int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
         v.off[k] = dx + (long)sx * dy + sxy * dz;
@@ -256,9 +266,11 @@ inline LCView<T> CoarseLevel::view() const {
         if constexpr (sizeof(T) == 8) {
             v.coef[k] = coef64[k];
             v.tab[k] = tab64 ? tab64 + k * tab_cap : nullptr;
+            v.tabT[k] = tabT64 ? tabT64 + k * tabT_cap : nullptr;
         } else {
             v.coef[k] = nullptr;
             v.tab[k] = tab32 ? tab32 + k * tab_cap : nullptr;
+            v.tabT[k] = tabT32 ? tabT32 + k * tabT_cap : nullptr;
         }
     }
     if constexpr (sizeof(T) == 8) v.invD = invD64;

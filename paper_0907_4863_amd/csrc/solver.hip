@@ -506,20 +506,21 @@ static void free_coarse(CoarseLevel& C) {
         dfree(C.coef64[k]);
         C.coef64[k] = nullptr;
     }
-    for (void* p : {(void*)C.invD64, (void*)C.invD32, (void*)C.slot, (void*)C.tab64, (void*)C.tab32})
+    for (void* p : {(void*)C.invD64, (void*)C.invD32, (void*)C.slot, (void*)C.tab64, (void*)C.tab32,
+                    (void*)C.slotT, (void*)C.tabT64, (void*)C.tabT32})
         dfree(p);
     C.invD64 = nullptr;
     C.invD32 = nullptr;
-    C.slot = nullptr;
-    C.tab64 = nullptr;
-    C.tab32 = nullptr;
-    C.tab_cap = C.n_tab = 0;
+    C.slot = C.slotT = nullptr;
+    C.tab64 = C.tabT64 = nullptr;
+    C.tab32 = C.tabT32 = nullptr;
+    C.tab_cap = C.n_tab = C.tabT_cap = C.n_tabT = 0;
 }
 
 static int64_t coarse_bytes(const CoarseLevel& C, bool mixed) {
     const int na = C.sym ? 14 : 27;
-    return (int64_t)(na + 1) * C.nstore * 8 + 4L * C.nstore + (mixed ? 4L * C.nstore : 0) +
-           27L * C.tab_cap * (mixed ? 12 : 8);
+    return (int64_t)(na + 1) * C.nstore * 8 + 4L * C.nstore * (C.sym ? 1 : 2) +
+           (mixed ? 4L * C.nstore : 0) + 27L * (C.tab_cap + C.tabT_cap) * (mixed ? 12 : 8);
 }
 
 static void validate_options(const saamg_options& o) {
@@ -786,6 +787,7 @@ static void coarse_fp32(saamg_hierarchy* H, hipStream_t s) {
     if (H->opt.precision != SAAMG_MIXED) return;
     for (auto& C : H->lc) {
         if (!C.tab32) C.tab32 = (float*)dmalloc(4 * 27 * C.tab_cap);
+        if (C.tabT64 && !C.tabT32) C.tabT32 = (float*)dmalloc(4 * 27 * C.tabT_cap);
         if (!C.invD32) C.invD32 = (float*)dmalloc(4 * C.nstore);
         lc_to_fp32(C, s);
     }
@@ -1230,7 +1232,8 @@ int saamg_footprint_bytes(int nx, int ny, int nz, int variant, int precision, in
             m = (std::ceil(std::cbrt(m) / 3.0) + 2) * (std::ceil(std::cbrt(m) / 3.0) + 2) *
                 (std::ceil(std::cbrt(m) / 3.0) + 2);
             // full fp64 arrays and 1/diag, slots, fp32 1/diag, table (at most every row)
-            h += ((na + 1) * 8 + 4 + (mixed ? 4 : 0) + 27 * (mixed ? 12 : 8)) * m;
+            h += ((na + 1) * 8 + (na == 27 ? 8 : 4) + (mixed ? 4 : 0) +
+                  (na == 27 ? 2 : 1) * 27 * (mixed ? 12 : 8)) * m;
             st += 4 * w * m;
         }
         h += 8.0 * 1000 * 1000;
