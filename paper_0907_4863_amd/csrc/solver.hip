@@ -1010,10 +1010,20 @@ static T* upload_level(const saamg_hierarchy* H, int l, const double* h) {
     int mx, my, mz;
     level_dims(H, l, &mx, &my, &mz);
     std::vector<T> buf(level_nstore(H, l), (T)0);
+    // level 0: entries at nodes that are not unknowns are ignored (the kernels expect 0)
+    std::vector<uint64_t> unk;
+    if (l == 0) {
+        unk.resize(H->l0.nseg);
+        HIPCHECK(hipMemcpy(unk.data(), H->l0.unk, 8 * H->l0.nseg, hipMemcpyDeviceToHost));
+    }
     for (int z = 0; z < mz; ++z)
         for (int y = 0; y < my; ++y)
-            for (int x = 0; x < mx; ++x)
+            for (int x = 0; x < mx; ++x) {
+                if (l == 0 &&
+                    !((unk[((long)z * my + y) * H->l0.nsegx + (x >> 6)] >> (x & 63)) & 1ull))
+                    continue;
                 buf[storage_index(H, l, x, y, z)] = (T)h[x + (long)mx * (y + (long)my * z)];
+            }
     T* d = (T*)dmalloc(sizeof(T) * buf.size());
     HIPCHECK(hipMemcpy(d, buf.data(), sizeof(T) * buf.size(), hipMemcpyHostToDevice));
     return d;
