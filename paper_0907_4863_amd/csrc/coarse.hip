@@ -1,5 +1,7 @@
 // Kernels of levels >= 1 (27-point Galerkin operators on ghost-padded boxes), the
-// structured Galerkin product that builds them, and the dense coarsest-level solve.
+// structured Galerkin product that builds them, the compression the solve kernels read
+// them in (interior stencil, per-node slot, table of the other rows; also for the
+// transpose of nonsymmetric levels), and the coarsest-level solvers.
 #include "launch.h"
 
 namespace saamg {

@@ -1,7 +1,9 @@
-// Host driver: hierarchy setup, V-cycle, PCG state machine and the C interface.
+// Host driver: hierarchy setup and numeric re-setup, V-cycle, PCG state machine and the
+// C interface.
 //
 // Paper: Section 2 (operator and scaling), Section 3 (PCG with an SA-AMG V-cycle,
-// Algorithm 1), Table 1 (coarse size limit 1000), Section 5 (relative-residual stop).
+// Algorithm 1), Table 1 (coarse size limit 1000), Section 5 (relative-residual stop),
+// Section 5.2 (reuse of the aggregation hierarchy, Gauss-Seidel coarse level solver).
 #include <algorithm>
 #include <array>
 #include <chrono>
