@@ -132,3 +132,16 @@ def test_refresh_rejects_a_null_hierarchy_before_touching_the_gpu():
     H = sa.capi.Hierarchy(0, (5, 5, 5))
     with pytest.raises(sa.SaamgError, match="hierarchy is NULL"):
         sa.refresh(H, _dom(m))
+
+
+def test_wall_entries_in_any_order_are_checked_for_duplicates():
+    m = np.zeros((5, 5, 5), np.uint8)
+    m[2, 2, 2] = 1
+    with pytest.raises(sa.SaamgError, match="duplicate"):
+        sa.setup(_dom(m, [62, 62, 62], [1, 0, 1], [0.5, 0.5, 0.5]), sa.VARIANT_QUAD)
+    # unsorted and distinct: the host checks pass (without a GPU the call then fails later)
+    try:
+        H = sa.setup(_dom(m, [62, 62], [1, 0], [0.5, 0.5]), sa.VARIANT_QUAD)
+        sa.destroy(H)
+    except sa.SaamgError as e:
+        assert "duplicate" not in str(e) and "wall" not in str(e)
