@@ -813,7 +813,8 @@ void l0_lz_update(const FineLevel& L, const double* u, const double* cur, double
 //   ZERO2: x1 = c2_0 f on the fly; r1 = f - A x1; d1 = c1 x1 + c2 r1; x2 = x1 + d1
 //   FIRST: r = f - A xin; d = c2_0 r; xout = xin + d
 //   NEXT : r = f - A xin; d = c1 din + c2 r; xout = xin + d
-// Optional partial sums of fdot . xout (the PCG's r . z when this is the last step).
+// Optional partial sums of fdot . xout (the PCG's r . z when this is the last step); with
+// fdot NULL the dot is taken with f itself (promoted to fp64).
 template <typename TF, typename T, int MODE, bool DOT>
 __global__ void __launch_bounds__(kMThreads) k_l0_cheb(L0View<T> v, const TF* __restrict__ f,
                                                       const T* __restrict__ xin,
@@ -827,7 +828,7 @@ __global__ void __launch_bounds__(kMThreads) k_l0_cheb(L0View<T> v, const TF* __
         a.v[0] = (MODE == CHEB_FIRST || MODE == CHEB_NEXT || MODE == CHEB_ZERO1) ? (T)at(f, i) : T(0);
         a.v[1] = (MODE == CHEB_NEXT) ? at(din, i) : T(0);
         Vals<double, 1> b;
-        b.v[0] = DOT ? at(fdot, i) : 0.0;
+        b.v[0] = (DOT && fdot) ? at(fdot, i) : 0.0;
         struct R {
             Vals<T, 2> a;
             Vals<double, 1> b;
@@ -851,7 +852,7 @@ __global__ void __launch_bounds__(kMThreads) k_l0_cheb(L0View<T> v, const TF* __
         }
         at(xout, i) = xo;
         if (dout) at(dout, i) = dn;
-        if (DOT) acc += fv.b.v[0] * (double)xo;
+        if (DOT) acc += (fdot ? fv.b.v[0] : (double)fi) * (double)xo;
     };
     if (MODE == CHEB_ZERO1)
         l0_march<T, false, false>(v, [&](long) { return T(0); }, fetch, body);

@@ -257,12 +257,16 @@ static void read_scal(saamg_state* S) {
     HIPCHECK(hipStreamSynchronize(S->s));
 }
 
+// z = M r and the partials of r . z.  The dot is taken with the residual the V-cycle
+// reads (the fp32 copy in mixed precision, so r . z is the quadratic form of the applied
+// preconditioner); a one-level hierarchy takes it with the fp64 residual.
 static void precond(saamg_state* S) {
     const saamg_hierarchy* H = S->H;
+    const double* fdot = H->n_levels == 1 ? S->r : nullptr;
     if (S->mixed)
-        vcycle<float>(H, S->vf, 0, S->r32, (float*)S->z, S->r, S->part, S->s);
+        vcycle<float>(H, S->vf, 0, S->r32, (float*)S->z, fdot, S->part, S->s);
     else
-        vcycle<double>(H, S->vd, 0, S->r, (double*)S->z, S->r, S->part, S->s);
+        vcycle<double>(H, S->vd, 0, S->r, (double*)S->z, fdot, S->part, S->s);
 }
 
 // True residual b - A x into `dst`; returns ||dst||^2.

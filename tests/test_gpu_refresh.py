@@ -136,3 +136,21 @@ def test_refresh_rejected_while_a_state_exists():
     sa.refresh(G, sa.domain_for(s2, *n))
     x = torch.zeros_like(b)
     assert sa.solve(G, b, x)["status"] == 0
+
+
+def test_wall_entries_in_any_order_give_the_same_hierarchy():
+    """The interface takes wall entries in any order: shuffled entries (with open ends, so
+    that the end-plane rows are merged in as well) give the same operator and estimates."""
+    shape, n = W.Shape.ellipse(1.0, 0.6, 4.0), (40, 26, 44)
+    print("[case] shuffled wall entries", flush=True)
+    d = sa.domain_for(shape, *n, open_ends=True)
+    perm = np.random.default_rng(12).permutation(d.wall_node.size)
+    s = sa.capi.HostDomain(d.mask, d.h, d.wall_node[perm], d.wall_dir[perm], d.wall_s[perm],
+                           d.robin_d)
+    G = sa.setup(d, W.VARIANT_QUAD)
+    S = sa.setup(s, W.VARIANT_QUAD)
+    gi, si = sa.hierarchy_info(G), sa.hierarchy_info(S)
+    assert gi["lambda_est"] == si["lambda_est"] and gi["n_irregular"] == si["n_irregular"]
+    for l in range(gi["n_levels"]):
+        dims = gi["dims"][l]
+        assert np.array_equal(sa.level_coefficients(G, l, dims), sa.level_coefficients(S, l, dims))
