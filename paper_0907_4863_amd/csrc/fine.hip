@@ -873,7 +873,7 @@ void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* d
     const long wf = sizeof(TF), w = sizeof(T), n = L.n_unknowns;
     const long vec = (mode == CHEB_ZERO1 || mode == CHEB_ZERO2) ? wf + w
                      : (mode == CHEB_FIRST) ? wf + 2 * w : wf + 3 * w;
-    KTimer kt_(T_L0_CHEB, s, n * (vec + (dout ? w : 0) + (dot ? 8 : 0)) + l0_meta_bytes(L, w, false));
+    KTimer kt_(T_L0_CHEB, s, n * (vec + (dout ? w : 0) + (dot && fdot ? 8 : 0)) + l0_meta_bytes(L, w, false));
     L0View<T> v = L.view<T>();
     dim3 g = l0_mgrid(L), b(kWave, kMY);
 #define CHEB_LAUNCH(M)                                                                         \
