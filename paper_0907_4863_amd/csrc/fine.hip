@@ -199,8 +199,15 @@ __device__ __forceinline__ V wave_shift(V src, V edge) {
     }
 }
 
-template <typename T, bool STENCIL, bool TR, class Load, class Fetch, class Body>
-__device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch, Body body) {
+// Optional per-plane hook of the march: end(z, last, x, y) after plane z's arithmetic, on
+// every lane (x = its node's x, y = the row; last: the tile's final plane).
+struct NoEnd {
+    __device__ void operator()(int, bool, int, int) const {}
+};
+
+template <typename T, bool STENCIL, bool TR, class Load, class Fetch, class Body, class End = NoEnd>
+__device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch, Body body,
+                                         End end = End{}) {
     using FV = decltype(fetch(Idx{0, 0u}, 0, 0, 0, false, 0));
     using TX = decltype(X(Idx{0, 0u}));
     int bx, y, bz;
@@ -320,6 +327,7 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
             zm = c;
             c = zp;
         }
+        end(z, z == z1 - 1, x0 + lane, y);
     };
     // Two register sets take turns: while one plane is computed the next one's loads are
     // in flight, and no copy between the sets forces an early wait.  Loads past the tile
@@ -923,14 +931,23 @@ template void l0_residual<float, float>(const FineLevel&, const float*, const fl
                                         hipStream_t);
 
 // Restriction to level 1, P^T r with P = (I - w A) P_tent (D = I at level 0), in two
-// passes: y = r - w A^T r on every fine unknown, then the sum of y over each aggregate.
+// passes.  Pass 1 forms y = r - w A^T r on every fine unknown and sums each lane's column
+// over the three planes of an aggregate (the z-slabs start at multiples of 3), writing one
+// value per (x, y, aggregate plane) into yz; pass 2 sums yz over the aggregate's 3 x 3
+// (x, y) nodes.  Entries of yz that no unknown reaches stay 0 from allocation on.
 template <typename T>
 __global__ void __launch_bounds__(kMThreads) k_l0_restrict_y(L0View<T> v, const T* __restrict__ r,
-                                                            T* __restrict__ yv, T omega) {
-    l0_march<T, true, true>(v, [&](Idx j) { return at(r, j); }, NOFETCH,
-                            [&](Idx i, NoVals, T ri, T atr, int, int, int, bool, int) {
-                                at(yv, i) = ri - omega * atr;
-                            });
+                                                            T* __restrict__ yz, T omega) {
+    T acc = T(0);
+    l0_march<T, true, true>(
+        v, [&](Idx j) { return at(r, j); }, NOFETCH,
+        [&](Idx, NoVals, T ri, T atr, int, int, int, bool, int) { acc += ri - omega * atr; },
+        [&](int z, bool last, int x, int y) {
+            if (z % 3 == 2 || last) {
+                if (x < v.nx) yz[x + (long)v.nx * y + v.nxy * (z / 3)] = acc;
+                acc = T(0);
+            }
+        });
 }
 
 template <typename T>
@@ -942,17 +959,13 @@ __global__ void __launch_bounds__(256) k_l0_restrict_sum(int nx, int ny, int nz,
     const int X = (int)(t % c.mx), Y = (int)(t / c.mx), Z = blockIdx.y;
     const long nxy = (long)nx * ny;
     T acc = 0;
-    for (int dz = 0; dz < 3; ++dz) {
-        const int z = 3 * Z + dz;
-        if (z >= nz) break;
-        for (int dy = 0; dy < 3; ++dy) {
-            const int y = 3 * Y + dy;
-            if (y >= ny) break;
-            const long row = (long)nx * y + nxy * z;
-            for (int dx = 0; dx < 3; ++dx) {
-                const int x = 3 * X + dx;
-                if (x < nx) acc += yv[row + x];
-            }
+    for (int dy = 0; dy < 3; ++dy) {
+        const int y = 3 * Y + dy;
+        if (y >= ny) break;
+        const long row = (long)nx * y + nxy * Z;
+        for (int dx = 0; dx < 3; ++dx) {
+            const int x = 3 * X + dx;
+            if (x < nx) acc += yv[row + x];
         }
     }
     fc[(X + 1) + (long)c.sx * (Y + 1) + c.sxy * (Z + 1)] = acc;
@@ -961,10 +974,14 @@ __global__ void __launch_bounds__(256) k_l0_restrict_sum(int nx, int ny, int nz,
 template <typename T>
 void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* fc, double omega,
                  hipStream_t s) {
-    KTimer kt_(T_L0_RESTRICT, s, (L.n_unknowns * 3 + C.n_unknowns) * (long)sizeof(T) +
+    KTimer kt_(T_L0_RESTRICT, s, (L.n_unknowns * 5 / 3 + C.n_unknowns) * (long)sizeof(T) +
                                     l0_meta_bytes(L, sizeof(T), true));
-    hipLaunchKernelGGL((k_l0_restrict_y<T>), l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<T>(),
-                       r, y, (T)omega);
+    // z-slabs of a multiple of 3 planes, so that no aggregate plane is split between tiles
+    L0View<T> v = L.view<T>();
+    v.zb = std::max(3, L.zb / 3 * 3);
+    const long blocks = (long)v.gx * v.gy * ((L.nz + v.zb - 1) / v.zb);
+    hipLaunchKernelGGL((k_l0_restrict_y<T>), dim3((unsigned)blocks), dim3(kWave, kMY), 0, s, v, r,
+                       y, (T)omega);
     dim3 g((unsigned)(((long)C.mx * C.my + 255) / 256), C.mz);
     hipLaunchKernelGGL((k_l0_restrict_sum<T>), g, dim3(256), 0, s, L.nx, L.ny, L.nz, C.view<T>(),
                        y, fc);

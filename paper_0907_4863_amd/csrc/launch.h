@@ -72,7 +72,8 @@ void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* d
              hipStream_t s);
 template <typename TF, typename T>
 void l0_residual(const FineLevel& L, const TF* f, const T* x, T* r, hipStream_t s);
-// fc = P^T r in two passes; y is a level-0 scratch vector (zero off the unknowns)
+// fc = P^T r in two passes; y: scratch of at least nx*ny*ceil(nz/3) entries, zero from
+// allocation on and used by no other kernel (entries that no unknown reaches are read as 0)
 template <typename T>
 void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* fc, double omega,
                  hipStream_t s);

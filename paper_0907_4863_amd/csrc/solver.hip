@@ -67,6 +67,10 @@ static double ms_since(std::chrono::steady_clock::time_point t0) {
 template <typename T>
 struct VBuf {
     std::vector<T*> f, xa, xb, d;  // per level; level 0 has no f (the PCG residual is read)
+    T* yz = nullptr;               // level-0 restriction scratch (aggregate-plane sums)
+    static long yz_size(const saamg_hierarchy* H) {
+        return H->l0.nxy * ((H->l0.nz + 2) / 3);
+    }
     void alloc(const saamg_hierarchy* H) {
         const int L = H->n_levels;
         f.assign(L, nullptr);
@@ -82,10 +86,13 @@ struct VBuf {
             }
             if (l > 0) f[l] = (T*)dmalloc(sizeof(T) * n);
         }
+        if (L > 1) yz = (T*)dmalloc(sizeof(T) * yz_size(H));
     }
     void release() {
         for (auto* v : {&f, &xa, &xb, &d})
             for (T* p : *v) dfree(p);
+        dfree(yz);
+        yz = nullptr;
         f.clear();
         xa.clear();
         xb.clear();
@@ -98,6 +105,7 @@ struct VBuf {
             int cnt = 1 + (l < H->n_levels - 1 ? 2 : 0) + (l > 0 ? 1 : 0);
             b += (int64_t)cnt * n * sizeof(T);
         }
+        if (H->n_levels > 1) b += (int64_t)yz_size(H) * sizeof(T);
         return b;
     }
 };
@@ -154,7 +162,7 @@ static T* vcycle(const saamg_hierarchy* H, VBuf<T>& B, int l, const T* f0, T* ou
     // residual and restriction
     if (fine) {
         l0_residual<T, T>(H->l0, f0, x, other, s);
-        l0_restrict<T>(H->l0, H->lc[0], other, d, B.f[1], P.omega, s);
+        l0_restrict<T>(H->l0, H->lc[0], other, B.yz, B.f[1], P.omega, s);
     } else {
         lc_residual<T>(H->lc[l - 1], fl, x, other, s);
         lc_restrict<T>(H->lc[l - 1], H->lc[l], other, d, B.f[l + 1], P.omega, s);
@@ -1242,7 +1250,7 @@ int saamg_footprint_bytes(int nx, int ny, int nz, int variant, int precision, in
         double h = 8.0 * nbox + 20.0 * nbox / 64 + 0.2 * nbox * 12 * 12;  // sigma, masks, table
         double st = 48.0 * nbox + (mixed ? 4 : 8) * nbox;
         double w = mixed ? 4 : 8;
-        st += 3 * w * nbox;
+        st += 3 * w * nbox + w * nbox / 3;  // level-0 V-cycle vectors and restriction sums
         double m = nbox;
         for (int l = 1; l < 10 && m > 27; ++l) {
             m = (std::ceil(std::cbrt(m) / 3.0) + 2) * (std::ceil(std::cbrt(m) / 3.0) + 2) *
