@@ -302,9 +302,10 @@ int saamg_pic_gather(saamg_pic* P, const double* d_phi, const double* d_pos, int
 int saamg_pic_destroy(saamg_pic* P);
 
 /* ---- kernel timing (diagnostics) ----------------------------------------------------
- * When enabled for a kernel class, every launch of that class records a pair of HIP
- * events on its own stream; saamg_timer_read synchronises on them and returns the
- * summed event-to-event time, the launch count and the algorithmic bytes moved (each
+ * When enabled for a kernel class, every call that launches kernels of that class binds
+ * a pair of HIP events to its first and last kernel dispatch on its own stream (no marker
+ * is inserted between kernels); saamg_timer_read synchronises on them and returns the
+ * summed start-to-end time, the launch count and the algorithmic bytes moved (each
  * array the kernel must read or write counted once over the unknowns it covers).
  * Classes: 0 level-0 Chebyshev steps, 1 level-0 residual, 2 restriction to level 1,
  * 3 prolongation from level 1, 4 CG direction update + product with A, 5 CG x/r update,

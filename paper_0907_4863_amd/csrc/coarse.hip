@@ -234,8 +234,8 @@ void lc_cheb(const CoarseLevel& C, int mode, const T* f, const T* xin, const T* 
     LCView<T> c = C.view<T>();
     dim3 g = lc_grid(C), b(kThreads);
 #define LC_CHEB(SYMV, M)                                                                       \
-    hipLaunchKernelGGL((k_lc_cheb<T, SYMV, M>), g, b, 0, s, c, f, xin, din, xout, dout, (T)c1, \
-                       (T)c2, (T)c2_0);
+    klaunch(kt_, true, (k_lc_cheb<T, SYMV, M>), g, b, c, f, xin, din, xout, dout, (T)c1,       \
+            (T)c2, (T)c2_0);
 #define LC_CHEB_MODES(SYMV)                                 \
     switch (mode) {                                         \
         case CHEB_ZERO1: LC_CHEB(SYMV, CHEB_ZERO1) break;   \
@@ -272,11 +272,11 @@ template <typename T>
 void lc_residual(const CoarseLevel& C, const T* f, const T* x, T* r, hipStream_t s) {
     KTimer kt_(T_COARSE, s, lc_bytes(C, sizeof(T), 3));
     if (C.sym)
-        hipLaunchKernelGGL((k_lc_residual<T, true>), lc_grid(C), dim3(kThreads), 0, s,
-                           C.view<T>(), f, x, r);
+        klaunch(kt_, true, (k_lc_residual<T, true>), lc_grid(C), dim3(kThreads), C.view<T>(), f, x,
+                r);
     else
-        hipLaunchKernelGGL((k_lc_residual<T, false>), lc_grid(C), dim3(kThreads), 0, s,
-                           C.view<T>(), f, x, r);
+        klaunch(kt_, true, (k_lc_residual<T, false>), lc_grid(C), dim3(kThreads), C.view<T>(), f,
+                x, r);
     HIPCHECK(hipGetLastError());
 }
 template void lc_residual<double>(const CoarseLevel&, const double*, const double*, double*,
@@ -323,13 +323,13 @@ void lc_restrict(const CoarseLevel& F, const CoarseLevel& C, const T* r, T* y, T
                  hipStream_t s) {
     KTimer kt_(T_COARSE, s, lc_bytes(F, sizeof(T), 3) + C.n_unknowns * (long)sizeof(T));
     if (F.sym)
-        hipLaunchKernelGGL((k_lc_restrict_y<T, true>), lc_grid(F), dim3(kThreads), 0, s,
-                           F.view<T>(), r, y, (T)omega);
+        klaunch(kt_, false, (k_lc_restrict_y<T, true>), lc_grid(F), dim3(kThreads), F.view<T>(), r,
+                y, (T)omega);
     else
-        hipLaunchKernelGGL((k_lc_restrict_y<T, false>), lc_grid(F), dim3(kThreads), 0, s,
-                           F.view<T>(), r, y, (T)omega);
-    hipLaunchKernelGGL((k_lc_restrict_sum<T>), lc_grid(C), dim3(kThreads), 0, s, F.view<T>(),
-                       C.view<T>(), y, fc);
+        klaunch(kt_, false, (k_lc_restrict_y<T, false>), lc_grid(F), dim3(kThreads), F.view<T>(),
+                r, y, (T)omega);
+    klaunch(kt_, true, (k_lc_restrict_sum<T>), lc_grid(C), dim3(kThreads), F.view<T>(),
+            C.view<T>(), y, fc);
     HIPCHECK(hipGetLastError());
 }
 template void lc_restrict<double>(const CoarseLevel&, const CoarseLevel&, const double*, double*,
@@ -368,11 +368,11 @@ void lc_prolong(const CoarseLevel& F, const CoarseLevel& C, const T* vc, T* x, d
                 hipStream_t s) {
     KTimer kt_(T_COARSE, s, lc_bytes(F, sizeof(T), 2) + C.n_unknowns * (long)sizeof(T));
     if (F.sym)
-        hipLaunchKernelGGL((k_lc_prolong<T, true>), lc_grid(F), dim3(kThreads), 0, s,
-                           F.view<T>(), C.view<T>(), vc, x, (T)omega);
+        klaunch(kt_, true, (k_lc_prolong<T, true>), lc_grid(F), dim3(kThreads), F.view<T>(),
+                C.view<T>(), vc, x, (T)omega);
     else
-        hipLaunchKernelGGL((k_lc_prolong<T, false>), lc_grid(F), dim3(kThreads), 0, s,
-                           F.view<T>(), C.view<T>(), vc, x, (T)omega);
+        klaunch(kt_, true, (k_lc_prolong<T, false>), lc_grid(F), dim3(kThreads), F.view<T>(),
+                C.view<T>(), vc, x, (T)omega);
     HIPCHECK(hipGetLastError());
 }
 template void lc_prolong<double>(const CoarseLevel&, const CoarseLevel&, const double*, double*,
@@ -910,11 +910,11 @@ template <typename TF, typename T>
 void coarse_gs(const CoarseLevel& C, const TF* f, T* x, int sweeps, hipStream_t s) {
     KTimer kt_(T_COARSE, s, C.n_unknowns * (long)(8 * ((C.sym ? 14 : 27) + 1) + sizeof(TF) + sizeof(T)));
     if (C.sym)
-        hipLaunchKernelGGL((k_coarse_gs<TF, T, true>), dim3(1), dim3(1024), 0, s, C.view<double>(),
-                           f, x, sweeps);
+        klaunch(kt_, true, (k_coarse_gs<TF, T, true>), dim3(1), dim3(1024), C.view<double>(), f, x,
+                sweeps);
     else
-        hipLaunchKernelGGL((k_coarse_gs<TF, T, false>), dim3(1), dim3(1024), 0, s, C.view<double>(),
-                           f, x, sweeps);
+        klaunch(kt_, true, (k_coarse_gs<TF, T, false>), dim3(1), dim3(1024), C.view<double>(), f,
+                x, sweeps);
     HIPCHECK(hipGetLastError());
 }
 template void coarse_gs<double, double>(const CoarseLevel&, const double*, double*, int, hipStream_t);
@@ -937,8 +937,8 @@ __global__ void __launch_bounds__(256) k_coarse_solve(const double* __restrict__
 template <typename TF, typename T>
 void coarse_solve(const double* Ainv, const long* cidx, int nL, const TF* f, T* x, hipStream_t s) {
     KTimer kt_(T_COARSE, s, 8L * nL * nL + nL * (long)(sizeof(TF) + sizeof(T) + 8));
-    hipLaunchKernelGGL((k_coarse_solve<TF, T>), dim3((nL + 3) / 4), dim3(256), 0, s, Ainv, cidx, nL,
-                       f, x);
+    klaunch(kt_, true, (k_coarse_solve<TF, T>), dim3((nL + 3) / 4), dim3(256), Ainv, cidx, nL, f,
+            x);
     HIPCHECK(hipGetLastError());
 }
 template void coarse_solve<double, double>(const double*, const long*, int, const double*, double*,

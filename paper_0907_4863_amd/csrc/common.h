@@ -15,6 +15,7 @@
 //   operator stores only k >= 13 and reads A(i, k<13) as A(i+off(k), 26-k).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -131,8 +132,10 @@ void hip_check(hipError_t e, const char* what);
 void* dmalloc(size_t bytes);            // throws ApiError(NOMEM) on failure, zero-filled
 void dfree(void* p);
 
-// Opt-in kernel timing: HIP events recorded on the launching stream around every
-// launch of one kernel class (see saamg_timer_* in the C interface).
+// Opt-in kernel timing of one kernel class (see saamg_timer_* in the C interface).  A
+// timer spans one launch function: its first launch carries the start event and its last
+// the stop event, so the timestamps are those of the kernel dispatches themselves and no
+// marker is added to the stream between kernels.
 enum TimerKind {
     T_L0_CHEB = 0, T_L0_RESID, T_L0_RESTRICT, T_L0_PROLONG, T_CG_PQ, T_CG_XR, T_COARSE,
     T_FINALIZE, T_NKIND
@@ -141,9 +144,19 @@ struct KTimer {
     int slot = -1;
     int kind;
     hipStream_t s;
+    bool started = false, stopped = false;
     KTimer(int kind, hipStream_t s, long units);
-    ~KTimer();
+    hipEvent_t start();  // the start event for the first launch (null when off or taken)
+    hipEvent_t stop();   // the stop event (null when off)
+    ~KTimer();           // records the events that no launch carried
 };
+
+// Launches kernel f on the timer's stream; `last` marks the timer's final launch.
+template <typename F, typename... Args>
+inline void klaunch(KTimer& kt, bool last, F f, dim3 grid, dim3 block, Args... args) {
+    hipExtLaunchKernelGGL(f, grid, block, 0, kt.s, kt.start(), last ? kt.stop() : nullptr, 0,
+                          args...);
+}
 
 struct ChebCoef {
     int degree;

@@ -424,8 +424,7 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(const double* __restri
 void finalize(const double* partials, long nblk, int nq, double* scal, int op, int dst,
               hipStream_t s) {
     KTimer kt_(T_FINALIZE, s, nblk * 8L * nq);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, partials, nblk, nq, scal, op,
-                       dst);
+    klaunch(kt_, true, k_finalize, dim3(1), dim3(kFinThreads), partials, nblk, nq, scal, op, dst);
     HIPCHECK(hipGetLastError());
 }
 
@@ -886,11 +885,11 @@ void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* d
     dim3 g = l0_mgrid(L), b(kWave, kMY);
 #define CHEB_LAUNCH(M)                                                                         \
     if (dot)                                                                                   \
-        hipLaunchKernelGGL((k_l0_cheb<TF, T, M, true>), g, b, 0, s, v, f, xin, din, xout, dout, \
-                           (T)c1, (T)c2, (T)c2_0, fdot, dot);                                  \
+        klaunch(kt_, true, (k_l0_cheb<TF, T, M, true>), g, b, v, f, xin, din, xout, dout,      \
+                (T)c1, (T)c2, (T)c2_0, fdot, dot);                                             \
     else                                                                                       \
-        hipLaunchKernelGGL((k_l0_cheb<TF, T, M, false>), g, b, 0, s, v, f, xin, din, xout,      \
-                           dout, (T)c1, (T)c2, (T)c2_0, fdot, dot);
+        klaunch(kt_, true, (k_l0_cheb<TF, T, M, false>), g, b, v, f, xin, din, xout, dout,     \
+                (T)c1, (T)c2, (T)c2_0, fdot, dot);
     switch (mode) {
         case CHEB_ZERO1: CHEB_LAUNCH(CHEB_ZERO1) break;
         case CHEB_ZERO2: CHEB_LAUNCH(CHEB_ZERO2) break;
@@ -921,8 +920,8 @@ template <typename TF, typename T>
 void l0_residual(const FineLevel& L, const TF* f, const T* x, T* r, hipStream_t s) {
     KTimer kt_(T_L0_RESID, s, L.n_unknowns * (long)(sizeof(TF) + 2 * sizeof(T)) +
                                  l0_meta_bytes(L, sizeof(T), false));
-    hipLaunchKernelGGL((k_l0_residual<TF, T>), l0_mgrid(L), dim3(kWave, kMY), 0, s,
-                       L.view<T>(), f, x, r);
+    klaunch(kt_, true, (k_l0_residual<TF, T>), l0_mgrid(L), dim3(kWave, kMY), L.view<T>(), f, x,
+            r);
     HIPCHECK(hipGetLastError());
 }
 template void l0_residual<double, double>(const FineLevel&, const double*, const double*,
@@ -980,11 +979,10 @@ void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* 
     L0View<T> v = L.view<T>();
     v.zb = std::max(3, L.zb / 3 * 3);
     const long blocks = (long)v.gx * v.gy * ((L.nz + v.zb - 1) / v.zb);
-    hipLaunchKernelGGL((k_l0_restrict_y<T>), dim3((unsigned)blocks), dim3(kWave, kMY), 0, s, v, r,
-                       y, (T)omega);
+    klaunch(kt_, false, (k_l0_restrict_y<T>), dim3((unsigned)blocks), dim3(kWave, kMY), v, r, y,
+            (T)omega);
     dim3 g((unsigned)(((long)C.mx * C.my + 255) / 256), C.mz);
-    hipLaunchKernelGGL((k_l0_restrict_sum<T>), g, dim3(256), 0, s, L.nx, L.ny, L.nz, C.view<T>(),
-                       y, fc);
+    klaunch(kt_, true, (k_l0_restrict_sum<T>), g, dim3(256), L.nx, L.ny, L.nz, C.view<T>(), y, fc);
     HIPCHECK(hipGetLastError());
 }
 template void l0_restrict<double>(const FineLevel&, const CoarseLevel&, const double*, double*,
@@ -1042,8 +1040,8 @@ void l0_prolong(const FineLevel& L, const CoarseLevel& C, const T* vc, T* x, dou
                 hipStream_t s) {
     KTimer kt_(T_L0_PROLONG, s, (2 * L.n_unknowns + C.n_unknowns) * (long)sizeof(T) +
                                    l0_meta_bytes(L, sizeof(T), false));
-    hipLaunchKernelGGL((k_l0_prolong<T>), l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<T>(),
-                       C.view<T>(), vc, x, (T)omega);
+    klaunch(kt_, true, (k_l0_prolong<T>), l0_mgrid(L), dim3(kWave, kMY), L.view<T>(), C.view<T>(),
+            vc, x, (T)omega);
     HIPCHECK(hipGetLastError());
 }
 template void l0_prolong<double>(const FineLevel&, const CoarseLevel&, const double*, double*,
@@ -1144,8 +1142,8 @@ template <typename TZ>
 void cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
            double* partials, hipStream_t s) {
     KTimer kt_(T_CG_PQ, s, L.n_unknowns * (long)(sizeof(TZ) + 48) + l0_meta_bytes(L, 8, false));
-    hipLaunchKernelGGL((k_cg_pq<TZ>), l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), z,
-                       x, p, q, scal, partials);
+    klaunch(kt_, true, (k_cg_pq<TZ>), l0_mgrid(L), dim3(kWave, kMY), L.view<double>(), z, x, p, q,
+            scal, partials);
     HIPCHECK(hipGetLastError());
 }
 template void cg_pq<double>(const FineLevel&, const double*, double*, double*, double*,
@@ -1182,8 +1180,8 @@ __global__ void __launch_bounds__(kMThreads) k_cg_xr(L0View<double> v, double* _
 void cg_xr(const FineLevel& L, double* r, const double* q, const double* scal, double* partials,
            float* r32, hipStream_t s) {
     KTimer kt_(T_CG_XR, s, L.n_unknowns * (24L + (r32 ? 4 : 0)));
-    hipLaunchKernelGGL(k_cg_xr, l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), r, q, scal,
-                       partials, r32);
+    klaunch(kt_, true, k_cg_xr, l0_mgrid(L), dim3(kWave, kMY), L.view<double>(), r, q, scal,
+            partials, r32);
     HIPCHECK(hipGetLastError());
 }
 

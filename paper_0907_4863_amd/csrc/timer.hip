@@ -1,4 +1,4 @@
-// Opt-in per-class kernel timing with HIP events on the launching stream.
+// Opt-in per-class kernel timing with HIP events bound to the timed kernel dispatches.
 #include <mutex>
 #include <vector>
 
@@ -42,12 +42,25 @@ KTimer::KTimer(int k, hipStream_t st, long units) : kind(k), s(st) {
     slot = T.used++;
     T.slots[slot].kind = k;
     T.slots[slot].units = units;
-    (void)hipEventRecord(T.slots[slot].a, s);
+}
+
+hipEvent_t KTimer::start() {
+    if (slot < 0 || started) return nullptr;
+    started = true;
+    return timers().slots[slot].a;
+}
+
+hipEvent_t KTimer::stop() {
+    if (slot < 0) return nullptr;
+    stopped = true;
+    return timers().slots[slot].b;
 }
 
 KTimer::~KTimer() {
     if (slot < 0) return;
-    (void)hipEventRecord(timers().slots[slot].b, s);
+    // a scope that launched nothing reads as zero time
+    if (!started) (void)hipEventRecord(timers().slots[slot].a, s);
+    if (!stopped) (void)hipEventRecord(timers().slots[slot].b, s);
 }
 
 }  // namespace saamg
