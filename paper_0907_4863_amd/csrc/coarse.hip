@@ -9,7 +9,7 @@ namespace saamg {
 // Coefficient k of the row with slot s (compressed operator).
 template <typename T>
 __device__ inline T lc_row(const LCView<T>& c, int s, int k) {
-    return s >= 0 ? c.tab[k][s] : (s == -1 ? c.cst[k] : T(0));
+    return s >= 0 ? c.tb[k * c.tcap + s] : (s == -1 ? c.cst[k] : T(0));
 }
 // Coefficient A(i, k) of a 27-point level.
 template <typename T, bool SYM>
@@ -19,7 +19,7 @@ __device__ inline T lc_a(const LCView<T>& c, long i, int k) {
 // Coefficient k of the transpose row with slot s: A^T(i, k) = A(i + off(k), 26 - k).
 template <typename T>
 __device__ inline T lc_rowT(const LCView<T>& c, int s, int k) {
-    return s >= 0 ? c.tabT[k][s] : (s == -1 ? c.cst[26 - k] : T(0));
+    return s >= 0 ? c.tbT[k * c.tTcap + s] : (s == -1 ? c.cst[26 - k] : T(0));
 }
 template <typename T, bool SYM>
 __device__ inline T lc_at(const LCView<T>& c, long i, int k) {
@@ -27,28 +27,34 @@ __device__ inline T lc_at(const LCView<T>& c, long i, int k) {
     return lc_rowT(c, c.slotT[i], k);
 }
 
-// sum_k A(i, k) X(i + off_k) (TR: A^T), offsets in order k = 0..26.
+// Storage offset of neighbour k, from the pitches (the unrolled loops fold the constants).
+template <typename T>
+__device__ inline long lc_off(const LCView<T>& c, int k) {
+    return (k % 3 - 1) + (long)c.sx * ((k / 3) % 3 - 1) + c.sxy * (k / 9 - 1);
+}
+
+// sum_k A(i, k) X(i + off_k) (TR: A^T), offsets in order k = 0..26.  A wavefront whose
+// lanes are all interior rows takes the stencil from registers; one that holds any table
+// row runs a single loop that picks each lane's coefficient, so the neighbour values are
+// loaded once per offset whatever the mix of rows in the wavefront.
 template <typename T, bool SYM, bool TR, class F>
 __device__ inline T lc_stencil(const LCView<T>& c, long i, F X) {
+    constexpr bool kT = TR && !SYM;
+    const int s = kT ? c.slotT[i] : c.slot[i];
+    if (s == -2) return T(0);
     T acc = 0;
-    if (!TR || SYM) {
-        const int s = c.slot[i];
-        if (s == -1) {
+    if (__ballot(s >= 0) == 0) {
 #pragma unroll
-            for (int k = 0; k < 27; ++k) acc += c.cst[k] * X(i + c.off[k]);
-        } else if (s >= 0) {
-#pragma unroll
-            for (int k = 0; k < 27; ++k) acc += c.tab[k][s] * X(i + c.off[k]);
-        }
+        for (int k = 0; k < 27; ++k) acc += c.cst[kT ? 26 - k : k] * X(i + lc_off(c, k));
         return acc;
     }
-    const int s = c.slotT[i];
-    if (s == -1) {
+    const T* tb = kT ? c.tbT : c.tb;
+    const long cap = kT ? c.tTcap : c.tcap;
+    const int sc = s < 0 ? 0 : s;  // a valid table row for the interior lanes' (unused) load
 #pragma unroll
-        for (int k = 0; k < 27; ++k) acc += c.cst[26 - k] * X(i + c.off[k]);
-    } else if (s >= 0) {
-#pragma unroll
-        for (int k = 0; k < 27; ++k) acc += c.tabT[k][s] * X(i + c.off[k]);
+    for (int k = 0; k < 27; ++k) {
+        const T t = tb[k * cap + sc];
+        acc += (s >= 0 ? t : c.cst[kT ? 26 - k : k]) * X(i + lc_off(c, k));
     }
     return acc;
 }

@@ -74,6 +74,11 @@ struct LCView {
     // its 26 neighbours all have the interior row, so A^T(i, k) = cst[26 - k])
     const int32_t* slotT;
     const T* tabT[27];
+    // the same tables as one base and a per-offset stride (tab[k] = tb + k * tcap), which
+    // the solve kernels index so that no per-offset pointer has to stay in registers
+    const T* tb;
+    const T* tbT;
+    long tcap, tTcap;
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -286,8 +291,17 @@ inline LCView<T> CoarseLevel::view() const {
             v.tabT[k] = tabT32 ? tabT32 + k * tabT_cap : nullptr;
         }
     }
-    if constexpr (sizeof(T) == 8) v.invD = invD64;
-    else v.invD = invD32;
+    if constexpr (sizeof(T) == 8) {
+        v.invD = invD64;
+        v.tb = tab64;
+        v.tbT = tabT64;
+    } else {
+        v.invD = invD32;
+        v.tb = tab32;
+        v.tbT = tabT32;
+    }
+    v.tcap = tab_cap;
+    v.tTcap = tabT_cap;
     return v;
 }
 }  // namespace saamg
