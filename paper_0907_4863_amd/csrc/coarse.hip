@@ -195,7 +195,9 @@ void lc_lz_update(const CoarseLevel& C, const double* u, const double* cur, doub
     HIPCHECK(hipGetLastError());
 }
 
-// Chebyshev step with D^-1 (see the level-0 version for the modes).
+// Chebyshev step with D^-1 (see the level-0 version for the modes).  CHEB_ZERO2 takes
+// D^-1 f in xin (written by the restriction that produced f), so that each neighbour
+// costs one load.
 template <typename T, bool SYM, int MODE>
 __global__ void __launch_bounds__(kThreads) k_lc_cheb(LCView<T> c, const T* __restrict__ f,
                                                       const T* __restrict__ xin,
@@ -212,7 +214,7 @@ __global__ void __launch_bounds__(kThreads) k_lc_cheb(LCView<T> c, const T* __re
             xo = c20 * id * fi;
             dn = xo;
         } else if (MODE == CHEB_ZERO2) {
-            const T ax = lc_stencil<T, SYM, false>(c, i, [&](long j) { return c20 * c.invD[j] * f[j]; });
+            const T ax = c20 * lc_stencil<T, SYM, false>(c, i, [&](long j) { return xin[j]; });
             const T x1 = c20 * id * fi;
             dn = c1 * x1 + c2 * id * (fi - ax);
             xo = x1 + dn;
@@ -236,7 +238,8 @@ static inline long lc_bytes(const CoarseLevel& C, int wsize, int nvec) {
 template <typename T>
 void lc_cheb(const CoarseLevel& C, int mode, const T* f, const T* xin, const T* din, T* xout,
              T* dout, double c1, double c2, double c2_0, hipStream_t s) {
-    KTimer kt_(T_COARSE, s, lc_bytes(C, sizeof(T), (mode == CHEB_NEXT ? 4 : 3) + (dout ? 1 : 0)));
+    const int nvec = mode == CHEB_ZERO1 ? 2 : mode == CHEB_NEXT ? 4 : 3;
+    KTimer kt_(T_COARSE, s, lc_bytes(C, sizeof(T), nvec + (dout ? 1 : 0)));
     LCView<T> c = C.view<T>();
     dim3 g = lc_grid(C), b(kThreads);
 #define LC_CHEB(SYMV, M)                                                                       \
@@ -263,48 +266,75 @@ template void lc_cheb<double>(const CoarseLevel&, int, const double*, const doub
 template void lc_cheb<float>(const CoarseLevel&, int, const float*, const float*, const float*,
                              float*, float*, double, double, double, hipStream_t);
 
+// r = f - A x and (rd non-null) rd = D^-1 r, the restriction's input.
 template <typename T, bool SYM>
 __global__ void __launch_bounds__(kThreads) k_lc_residual(LCView<T> c, const T* __restrict__ f,
                                                           const T* __restrict__ xv,
-                                                          T* __restrict__ r) {
+                                                          T* __restrict__ r, T* __restrict__ rd) {
     LC_PROLOGUE
     if (!inb) return;
+    const T id = c.invD[i];
     T o = 0;
-    if (c.invD[i] != (T)0) o = f[i] - lc_stencil<T, SYM, false>(c, i, [&](long j) { return xv[j]; });
+    if (id != (T)0) o = f[i] - lc_stencil<T, SYM, false>(c, i, [&](long j) { return xv[j]; });
     r[i] = o;
+    if (rd) rd[i] = id * o;
 }
 
 template <typename T>
-void lc_residual(const CoarseLevel& C, const T* f, const T* x, T* r, hipStream_t s) {
-    KTimer kt_(T_COARSE, s, lc_bytes(C, sizeof(T), 3));
+void lc_residual(const CoarseLevel& C, const T* f, const T* x, T* r, T* rd, hipStream_t s) {
+    KTimer kt_(T_COARSE, s, lc_bytes(C, sizeof(T), rd ? 4 : 3));
     if (C.sym)
         klaunch(kt_, true, (k_lc_residual<T, true>), lc_grid(C), dim3(kThreads), C.view<T>(), f, x,
-                r);
+                r, rd);
     else
         klaunch(kt_, true, (k_lc_residual<T, false>), lc_grid(C), dim3(kThreads), C.view<T>(), f,
-                x, r);
+                x, r, rd);
     HIPCHECK(hipGetLastError());
 }
 template void lc_residual<double>(const CoarseLevel&, const double*, const double*, double*,
-                                  hipStream_t);
-template void lc_residual<float>(const CoarseLevel&, const float*, const float*, float*,
+                                  double*, hipStream_t);
+template void lc_residual<float>(const CoarseLevel&, const float*, const float*, float*, float*,
                                  hipStream_t);
 
-// P^T r with P = (I - w D^-1 A) P_tent in two passes: y = r - w A^T D^-1 r on every fine
-// node (one thread per node), then fc(I) = sum of y over aggregate I.
+// out = D^-1 in on every storage node (0 off the unknowns and on the ghost layer).
+template <typename T>
+__global__ void __launch_bounds__(256) k_lc_dscale(const T* __restrict__ invD,
+                                                   const T* __restrict__ in, T* __restrict__ out,
+                                                   long n) {
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = invD[i] * in[i];
+}
+
+template <typename T>
+void lc_dscale(const CoarseLevel& C, const T* in, T* out, hipStream_t s) {
+    const T* invD;
+    if constexpr (sizeof(T) == 8) invD = C.invD64;
+    else invD = C.invD32;
+    hipLaunchKernelGGL((k_lc_dscale<T>), dim3((unsigned)((C.nstore + 255) / 256)), dim3(256), 0, s,
+                       invD, in, out, C.nstore);
+    HIPCHECK(hipGetLastError());
+}
+template void lc_dscale<double>(const CoarseLevel&, const double*, double*, hipStream_t);
+template void lc_dscale<float>(const CoarseLevel&, const float*, float*, hipStream_t);
+
+// P^T r with P = (I - w D^-1 A) P_tent in two passes: y = r - w A^T (D^-1 r) on every fine
+// node (one thread per node; y overwrites r in place, each thread reading only its own r),
+// then fc(I) = sum of y over aggregate I, and (fd non-null) fd = D_c^-1 fc for the coarse
+// level's first smoothing step.
 template <typename T, bool SYM>
-__global__ void __launch_bounds__(kThreads) k_lc_restrict_y(LCView<T> c, const T* __restrict__ r,
-                                                            T* __restrict__ yv, T omega) {
+__global__ void __launch_bounds__(kThreads) k_lc_restrict_y(LCView<T> c, T* ry,
+                                                            const T* __restrict__ rd, T omega) {
     LC_PROLOGUE
     if (!inb) return;
-    const T atr = lc_stencil<T, SYM, true>(c, i, [&](long j) { return c.invD[j] * r[j]; });
-    yv[i] = r[i] - omega * atr;
+    const T atr = lc_stencil<T, SYM, true>(c, i, [&](long j) { return rd[j]; });
+    ry[i] = ry[i] - omega * atr;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_lc_restrict_sum(LCView<T> f, LCView<T> c,
                                                               const T* __restrict__ yv,
-                                                              T* __restrict__ fc) {
+                                                              T* __restrict__ fc,
+                                                              T* __restrict__ fd) {
     LC_PROLOGUE
     if (!inb) return;
     T acc = 0;
@@ -322,26 +352,28 @@ __global__ void __launch_bounds__(kThreads) k_lc_restrict_sum(LCView<T> f, LCVie
         }
     }
     fc[i] = acc;
+    if (fd) fd[i] = c.invD[i] * acc;
 }
 
 template <typename T>
-void lc_restrict(const CoarseLevel& F, const CoarseLevel& C, const T* r, T* y, T* fc, double omega,
-                 hipStream_t s) {
-    KTimer kt_(T_COARSE, s, lc_bytes(F, sizeof(T), 3) + C.n_unknowns * (long)sizeof(T));
+void lc_restrict(const CoarseLevel& F, const CoarseLevel& C, T* r, const T* rd, T* fc, T* fd,
+                 double omega, hipStream_t s) {
+    KTimer kt_(T_COARSE, s, lc_bytes(F, sizeof(T), 3) +
+                                C.n_unknowns * (long)sizeof(T) * (fd ? 3 : 1));
     if (F.sym)
         klaunch(kt_, false, (k_lc_restrict_y<T, true>), lc_grid(F), dim3(kThreads), F.view<T>(), r,
-                y, (T)omega);
+                rd, (T)omega);
     else
         klaunch(kt_, false, (k_lc_restrict_y<T, false>), lc_grid(F), dim3(kThreads), F.view<T>(),
-                r, y, (T)omega);
+                r, rd, (T)omega);
     klaunch(kt_, true, (k_lc_restrict_sum<T>), lc_grid(C), dim3(kThreads), F.view<T>(),
-            C.view<T>(), y, fc);
+            C.view<T>(), (const T*)r, fc, fd);
     HIPCHECK(hipGetLastError());
 }
-template void lc_restrict<double>(const CoarseLevel&, const CoarseLevel&, const double*, double*,
-                                  double*, double, hipStream_t);
-template void lc_restrict<float>(const CoarseLevel&, const CoarseLevel&, const float*, float*,
-                                 float*, double, hipStream_t);
+template void lc_restrict<double>(const CoarseLevel&, const CoarseLevel&, double*, const double*,
+                                  double*, double*, double, hipStream_t);
+template void lc_restrict<float>(const CoarseLevel&, const CoarseLevel&, float*, const float*,
+                                 float*, float*, double, hipStream_t);
 
 // x += P v = P_tent v - w D^-1 A P_tent v on the fine level's unknowns.
 template <typename T, bool SYM>

@@ -952,7 +952,7 @@ __global__ void __launch_bounds__(kMThreads) k_l0_restrict_y(L0View<T> v, const 
 template <typename T>
 __global__ void __launch_bounds__(256) k_l0_restrict_sum(int nx, int ny, int nz, LCView<T> c,
                                                          const T* __restrict__ yv,
-                                                         T* __restrict__ fc) {
+                                                         T* __restrict__ fc, T* __restrict__ fd) {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t >= (long)c.mx * c.my) return;
     const int X = (int)(t % c.mx), Y = (int)(t / c.mx), Z = blockIdx.y;
@@ -967,14 +967,16 @@ __global__ void __launch_bounds__(256) k_l0_restrict_sum(int nx, int ny, int nz,
             if (x < nx) acc += yv[row + x];
         }
     }
-    fc[(X + 1) + (long)c.sx * (Y + 1) + c.sxy * (Z + 1)] = acc;
+    const long i = (X + 1) + (long)c.sx * (Y + 1) + c.sxy * (Z + 1);
+    fc[i] = acc;
+    if (fd) fd[i] = c.invD[i] * acc;
 }
 
 template <typename T>
-void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* fc, double omega,
-                 hipStream_t s) {
-    KTimer kt_(T_L0_RESTRICT, s, (L.n_unknowns * 5 / 3 + C.n_unknowns) * (long)sizeof(T) +
-                                    l0_meta_bytes(L, sizeof(T), true));
+void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* fc, T* fd,
+                 double omega, hipStream_t s) {
+    KTimer kt_(T_L0_RESTRICT, s, (L.n_unknowns * 5 / 3 + C.n_unknowns * (fd ? 3 : 1)) *
+                                        (long)sizeof(T) + l0_meta_bytes(L, sizeof(T), true));
     // z-slabs of a multiple of 3 planes, so that no aggregate plane is split between tiles
     L0View<T> v = L.view<T>();
     v.zb = std::max(3, L.zb / 3 * 3);
@@ -982,13 +984,14 @@ void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* 
     klaunch(kt_, false, (k_l0_restrict_y<T>), dim3((unsigned)blocks), dim3(kWave, kMY), v, r, y,
             (T)omega);
     dim3 g((unsigned)(((long)C.mx * C.my + 255) / 256), C.mz);
-    klaunch(kt_, true, (k_l0_restrict_sum<T>), g, dim3(256), L.nx, L.ny, L.nz, C.view<T>(), y, fc);
+    klaunch(kt_, true, (k_l0_restrict_sum<T>), g, dim3(256), L.nx, L.ny, L.nz, C.view<T>(),
+            (const T*)y, fc, fd);
     HIPCHECK(hipGetLastError());
 }
 template void l0_restrict<double>(const FineLevel&, const CoarseLevel&, const double*, double*,
-                                  double*, double, hipStream_t);
+                                  double*, double*, double, hipStream_t);
 template void l0_restrict<float>(const FineLevel&, const CoarseLevel&, const float*, float*, float*,
-                                 double, hipStream_t);
+                                 float*, double, hipStream_t);
 
 // Prolongation from level 1: x += P v = P_tent v - w A (P_tent v).  A node's aggregate
 // is (x/3, y/3, z/3); a neighbour's differs by one coarse step exactly when the node sits

@@ -73,10 +73,11 @@ void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* d
 template <typename TF, typename T>
 void l0_residual(const FineLevel& L, const TF* f, const T* x, T* r, hipStream_t s);
 // fc = P^T r in two passes; y: scratch of at least nx*ny*ceil(nz/3) entries, zero from
-// allocation on and used by no other kernel (entries that no unknown reaches are read as 0)
+// allocation on and used by no other kernel (entries that no unknown reaches are read as 0);
+// fd (nullable): D^-1 fc of level 1
 template <typename T>
-void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* fc, double omega,
-                 hipStream_t s);
+void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* fc, T* fd,
+                 double omega, hipStream_t s);
 template <typename T>
 void l0_prolong(const FineLevel& L, const CoarseLevel& C, const T* v, T* x, double omega,
                 hipStream_t s);
@@ -109,14 +110,20 @@ void lc_lz_apply(const CoarseLevel& C, const double* v, const double* scal, doub
                  double* partials, hipStream_t s);
 void lc_lz_update(const CoarseLevel& C, const double* u, const double* cur, double* prev,
                   const double* scal, double* partials, hipStream_t s);
+// CHEB_ZERO2 reads D^-1 f from xin
 template <typename T>
 void lc_cheb(const CoarseLevel& C, int mode, const T* f, const T* xin, const T* din, T* xout,
              T* dout, double c1, double c2, double c2_0, hipStream_t s);
+// r = f - A x; rd (nullable) = D^-1 r
 template <typename T>
-void lc_residual(const CoarseLevel& C, const T* f, const T* x, T* r, hipStream_t s);
+void lc_residual(const CoarseLevel& C, const T* f, const T* x, T* r, T* rd, hipStream_t s);
+// out = D^-1 in on every storage node
 template <typename T>
-void lc_restrict(const CoarseLevel& F, const CoarseLevel& C, const T* r, T* y, T* fc, double omega,
-                 hipStream_t s);
+void lc_dscale(const CoarseLevel& C, const T* in, T* out, hipStream_t s);
+// fc = P^T r from r and rd = D_F^-1 r; r is overwritten; fd (nullable) = D_C^-1 fc
+template <typename T>
+void lc_restrict(const CoarseLevel& F, const CoarseLevel& C, T* r, const T* rd, T* fc, T* fd,
+                 double omega, hipStream_t s);
 template <typename T>
 void lc_prolong(const CoarseLevel& F, const CoarseLevel& C, const T* v, T* x, double omega,
                 hipStream_t s);

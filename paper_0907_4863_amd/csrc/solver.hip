@@ -151,21 +151,24 @@ static T* vcycle(const saamg_hierarchy* H, VBuf<T>& B, int l, const T* f0, T* ou
         chebstep<T>(H, l, CHEB_ZERO1, f0, fl, nullptr, nullptr, x, nullptr, 0, 0, c.c2[0],
                     nullptr, nullptr, s);
     } else {
-        chebstep<T>(H, l, CHEB_ZERO2, f0, fl, nullptr, nullptr, x, c.degree > 2 ? d : nullptr,
-                    c.c1[1], c.c2[1], c.c2[0], nullptr, nullptr, s);
+        // on levels >= 1 the restriction left D^-1 f in `other`
+        chebstep<T>(H, l, CHEB_ZERO2, f0, fl, fine ? nullptr : other, nullptr, x,
+                    c.degree > 2 ? d : nullptr, c.c1[1], c.c2[1], c.c2[0], nullptr, nullptr, s);
         for (int k = 2; k < c.degree; ++k) {
             chebstep<T>(H, l, CHEB_NEXT, f0, fl, x, d, other, d, c.c1[k], c.c2[k], c.c2[0],
                         nullptr, nullptr, s);
             std::swap(x, other);
         }
     }
-    // residual and restriction
+    // residual and restriction; D^-1 f of level l+1 goes to its `other` buffer (the
+    // coarsest level has none and needs none)
+    T* fd = (l + 1 < H->n_levels - 1) ? B.xb[l + 1] : nullptr;
     if (fine) {
         l0_residual<T, T>(H->l0, f0, x, other, s);
-        l0_restrict<T>(H->l0, H->lc[0], other, B.yz, B.f[1], P.omega, s);
+        l0_restrict<T>(H->l0, H->lc[0], other, B.yz, B.f[1], fd, P.omega, s);
     } else {
-        lc_residual<T>(H->lc[l - 1], fl, x, other, s);
-        lc_restrict<T>(H->lc[l - 1], H->lc[l], other, d, B.f[l + 1], P.omega, s);
+        lc_residual<T>(H->lc[l - 1], fl, x, other, d, s);
+        lc_restrict<T>(H->lc[l - 1], H->lc[l], other, d, B.f[l + 1], fd, P.omega, s);
     }
     T* v = vcycle<T>(H, B, l + 1, nullptr, nullptr, nullptr, nullptr, s);
     // coarse-grid correction
@@ -1086,7 +1089,8 @@ static void level_apply_impl(saamg_hierarchy* H, int l, int op, const double* hi
             if (c.degree == 1) {
                 step(CHEB_ZERO1, nullptr, nullptr, x, nullptr, 0, 0);
             } else {
-                step(CHEB_ZERO2, nullptr, nullptr, x, d, c.c1[1], c.c2[1]);
+                if (l > 0) lc_dscale<T>(H->lc[l - 1], din, other, s);  // D^-1 f
+                step(CHEB_ZERO2, l > 0 ? other : nullptr, nullptr, x, d, c.c1[1], c.c2[1]);
                 for (int k = 2; k < c.degree; ++k) {
                     step(CHEB_NEXT, x, d, other, d, c.c1[k], c.c2[k]);
                     std::swap(x, other);
@@ -1098,10 +1102,13 @@ static void level_apply_impl(saamg_hierarchy* H, int l, int op, const double* hi
             break;
         }
         case SAAMG_OP_RESTRICT:
-            if (l == 0)
-                l0_restrict<T>(H->l0, H->lc[0], din, tmp, dout, H->par[0].omega, s);
-            else
-                lc_restrict<T>(H->lc[l - 1], H->lc[l], din, tmp, dout, H->par[l].omega, s);
+            if (l == 0) {
+                l0_restrict<T>(H->l0, H->lc[0], din, tmp, dout, nullptr, H->par[0].omega, s);
+            } else {
+                lc_dscale<T>(H->lc[l - 1], din, tmp, s);
+                lc_restrict<T>(H->lc[l - 1], H->lc[l], din, tmp, dout, nullptr, H->par[l].omega,
+                               s);
+            }
             break;
         case SAAMG_OP_PROLONG:
             if (l == 0)
