@@ -91,14 +91,16 @@ __device__ inline L0Node l0_node(const L0View<T>& v, int x, int y, int z) {
 // remap) holds tx consecutive segments of kMY / tx consecutive lines.
 template <typename T>
 __device__ inline void l0_tile(const L0View<T>& v, int* seg, int* y, int* bz) {
-    const long b = blockIdx.x, nb = gridDim.x;
-    const long q = nb >> 3;
-    const long lb = (b < 8 * q) ? (b & 7) * q + (b >> 3) : b;
+    // block counts fit in 32 bits: unsigned arithmetic keeps the divisions short
+    const unsigned b = blockIdx.x, nb = gridDim.x;
+    const unsigned q = nb >> 3;
+    const unsigned lb = (b < 8 * q) ? (b & 7) * q + (b >> 3) : b;
     const int w = threadIdx.y;
-    const long t = lb / v.gx;
-    *seg = (int)(lb % v.gx) * v.tx + w % v.tx;
-    *y = (int)(t % v.gy) * (kMY / v.tx) + w / v.tx;
-    *bz = (int)(t / v.gy);
+    const unsigned gx = (unsigned)v.gx, gy = (unsigned)v.gy;
+    const unsigned t = lb / gx;
+    *seg = (int)(lb % gx) * v.tx + w % v.tx;
+    *y = (int)(t % gy) * (kMY / v.tx) + w / v.tx;
+    *bz = (int)(t / gy);
 }
 
 // Box index of a lane's node, split into a wave-uniform part and the lane's offset, so
@@ -150,6 +152,7 @@ struct PlaneLoads {
     bool ins1;    // lane inside the row's unknown span in plane z+1
     int rk;
     bool tab;     // the row has irregular nodes: t holds table rows
+    long ib;      // box index of lane 0 of the row in this plane (wave-uniform)
     TX nxt, ym, yp, edge;  // X at (x, y, z+1), (x, y-1, z), (x, y+1, z), lane-edge x-neighbour
     T t[6];                // table row of an irregular node
     FV fv;
@@ -232,13 +235,17 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
     if (__ballot(wu != 0) == 0) return;
     const int x0 = bx * kWave;
     const long rb = x0 + nx * y;  // box index of lane 0 at plane 0
+    const long ib_last = rb + nxy * (z1 - 1);
     const int eo = lane == 0 ? -1 : (lane == kWave - 1 ? 1 : 0);
-    // X of this lane in plane q (k = q - (z0 - 1)), read inside the plane's span
-    auto load_x = [&](int k, long q) {
-        return X(Idx{rb + nxy * q, (unsigned)span_lane(lane_u64(wu, k), lane)});
+    // X of this lane in the plane with row base ibq (k = plane - (z0 - 1)), read inside the
+    // plane's span
+    auto load_x = [&](int k, long ibq) {
+        return X(Idx{ibq, (unsigned)span_lane(lane_u64(wu, k), lane)});
     };
-    auto load_plane = [&](int q) {
+    // loads of plane q, whose row base ib = rb + nxy * q the caller carries along
+    auto load_plane = [&](int q, long ib) {
         PlaneLoads<T, TX, FV> P;
+        P.ib = ib;
         const int k = q - (z0 - 1);
         P.u = lane_u64(wu, k);
         const uint64_t r = lane_u64(wr, k);
@@ -249,10 +256,9 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
         const int rbase = __builtin_amdgcn_readlane(wb, k);
         const unsigned rofs = __popcll(r & ((1ull << lane) - 1ull));
         P.rk = P.irr ? rbase + (int)rofs : 0;
-        const long ib = rb + nxy * q;
         P.fv = fetch(Idx{ib, (unsigned)lc}, x0 + lc, y, q, P.irr, P.rk);
         if (STENCIL) {
-            P.nxt = load_x(k + 1, q + 1);
+            P.nxt = load_x(k + 1, ib + nxy);
             P.ym = X(Idx{ib - nx, (unsigned)lc});
             P.yp = X(Idx{ib + nx, (unsigned)lc});
             // the edge lanes' outer x-neighbours (from a base one node lower, so that the
@@ -279,8 +285,8 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
     };
     TX zm = TX(0), c = TX(0);
     if (STENCIL) {
-        zm = load_x(0, z0 - 1);
-        c = load_x(1, z0);
+        zm = load_x(0, rb + nxy * (z0 - 1));
+        c = load_x(1, rb + nxy * z0);
         if (span_lane(lane_u64(wu, 0), lane) != lane) zm = TX(0);
         if (span_lane(lane_u64(wu, 1), lane) != lane) c = TX(0);
     }
@@ -308,7 +314,7 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
                 xp = wave_shift<false>(c, P.edge);
             }
             if ((P.u >> lane) & 1ull) {
-                const Idx i{rb + nxy * z, (unsigned)lane};
+                const Idx i{P.ib, (unsigned)lane};
                 const int r = P.rk;
                 T ax = T(0);
                 if (STENCIL) {
@@ -333,11 +339,16 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
     // in flight, and no copy between the sets forces an early wait.  Loads past the tile
     // re-read its last plane; the loop has no early exit, so that no path reaches the
     // loop head with a plane's loads unsettled.
-    PlaneLoads<T, TX, FV> pa = load_plane(z0);
+    // The row base advances by one plane per step (no per-plane multiply); past the tile it
+    // stays at the last plane's.
+    long ibz = rb + nxy * z0;
+    PlaneLoads<T, TX, FV> pa = load_plane(z0, ibz);
     for (int z = z0; z < z1; z += 2) {
-        PlaneLoads<T, TX, FV> pb = load_plane(min(z + 1, z1 - 1));
+        const long ib1 = ibz + nxy;
+        PlaneLoads<T, TX, FV> pb = load_plane(min(z + 1, z1 - 1), ib1 < ib_last ? ib1 : ib_last);
         step(pa, z);
-        pa = load_plane(min(z + 2, z1 - 1));
+        ibz += 2 * nxy;
+        pa = load_plane(min(z + 2, z1 - 1), ibz < ib_last ? ibz : ib_last);
         step(pb, z + 1);
     }
 }
