@@ -9,8 +9,10 @@
 // z each lane carries its column (z-1, z, z+1) in registers; x-neighbours come from
 // adjacent lanes, y-neighbours from L1/L2.  Block numbers are remapped so that the
 // blocks dispatched to one XCD form a contiguous z-slab of tiles (the chip hands out
-// blocks round-robin over its 8 XCDs, each with its own L2).  Kernels write only
-// unknown nodes; every level-0 work vector is zero at the other nodes from allocation on.
+// blocks round-robin over its 8 XCDs, each with its own L2).  Every level-0 work vector
+// is zero at the nodes that are not unknowns from allocation on; kernels write only
+// unknown nodes, except that in mixed precision the kernels write whole rows (the zero
+// written back at the non-unknowns of the rows they store; kFullRows).
 #include "launch.h"
 
 namespace saamg {
@@ -27,6 +29,17 @@ static inline dim3 l0_grid(const FineLevel& L) {
 static inline long l0_meta_bytes(const FineLevel& L, int wsize, bool trans_too) {
     return L.nseg * 20 + L.n_irr * 6L * wsize * (trans_too ? 2 : 1);
 }
+
+// Whole-row stores.  A march kernel that stores whole rows writes every in-box lane of a
+// row (segment) with unknowns, the extra lanes writing the zero their node already holds,
+// so that each store instruction covers whole cache lines instead of being masked to the
+// unknowns.  Measured on the 256 x 256 x 768 elliptic pipe: when every level-0 kernel of
+// the mixed-precision solve stores whole rows, the CG kernels that read those vectors run
+// faster (k_cg_xr -15%, the solve -2%), while in fp64 the wider writes cost the writers
+// more than they save (the fp64 V-cycle kernels +1%, k_cg_pq +3%), so fp64 keeps masked
+// stores.
+template <typename T>
+constexpr bool kFullRows = sizeof(T) == 4;
 
 // Planes per block for the solve-time kernels: long z-marches, but enough blocks to
 // fill the chip a few times over.
@@ -143,6 +156,9 @@ __device__ inline uint64_t lane_u64(uint64_t v, int k) {
 // its row in that plane reads at the nearest end of the span instead (fetch then sees
 // that node's index and coordinates); such values are never used by the lane itself and
 // are replaced by zero before they serve as a neighbour's x- or z-neighbour.
+// With FULL the body also runs on the lanes of a row with unknowns whose node is in the
+// box but not an unknown, with table slot -1, so that a kernel can store every lane of
+// the row (zero at those nodes) in one full-width write.
 // x-neighbours come from adjacent lanes (the two edge lanes load theirs), z-neighbours
 // from registers, y-neighbours from L1/L2; table rows are loaded by the irregular lanes.
 template <typename T, typename TX, class FV>
@@ -208,7 +224,8 @@ struct NoEnd {
     __device__ void operator()(int, bool, int, int) const {}
 };
 
-template <typename T, bool STENCIL, bool TR, class Load, class Fetch, class Body, class End = NoEnd>
+template <typename T, bool STENCIL, bool TR, bool FULL = false, class Load, class Fetch, class Body,
+          class End = NoEnd>
 __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch, Body body,
                                          End end = End{}) {
     using FV = decltype(fetch(Idx{0, 0u}, 0, 0, 0, false, 0));
@@ -313,7 +330,8 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
                 xm = wave_shift<true>(c, P.edge);
                 xp = wave_shift<false>(c, P.edge);
             }
-            if ((P.u >> lane) & 1ull) {
+            const bool unk = (P.u >> lane) & 1ull;
+            if (FULL ? (x0 + lane < v.nx) : unk) {
                 const Idx i{P.ib, (unsigned)lane};
                 const int r = P.rk;
                 T ax = T(0);
@@ -326,7 +344,7 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
                              P.t[3] * T(P.yp) + P.t[4] * T(zm) + P.t[5] * T(zp);
                     }
                 }
-                body(i, P.fv, T(c), ax, x0 + lane, y, z, P.irr, r);
+                body(i, P.fv, T(c), ax, x0 + lane, y, z, P.irr, (FULL && !unk) ? -1 : r);
             }
         }
         if (STENCIL) {
@@ -853,7 +871,8 @@ __global__ void __launch_bounds__(kMThreads) k_l0_cheb(L0View<T> v, const TF* __
         };
         return R{a, b};
     };
-    auto body = [&](Idx i, auto fv, T cv, T ax, int, int, int, bool, int) {
+    auto body = [&](Idx i, auto fv, T cv, T ax, int, int, int, bool, int rk) {
+        const bool u = rk >= 0;  // false only on the extra lanes of a full-row store
         const T fi = fv.a.v[0];
         T xo, dn;
         if (MODE == CHEB_ZERO1) {
@@ -868,16 +887,16 @@ __global__ void __launch_bounds__(kMThreads) k_l0_cheb(L0View<T> v, const TF* __
             dn = (MODE == CHEB_FIRST) ? c20 * r : c1 * fv.a.v[1] + c2 * r;
             xo = cv + dn;
         }
-        at(xout, i) = xo;
-        if (dout) at(dout, i) = dn;
-        if (DOT) acc += (fdot ? fv.b.v[0] : (double)fi) * (double)xo;
+        at(xout, i) = u ? xo : T(0);
+        if (dout) at(dout, i) = u ? dn : T(0);
+        if (DOT && u) acc += (fdot ? fv.b.v[0] : (double)fi) * (double)xo;
     };
     if (MODE == CHEB_ZERO1)
         l0_march<T, false, false>(v, [&](long) { return T(0); }, fetch, body);
     else if (MODE == CHEB_ZERO2)
-        l0_march<T, true, false>(v, [&](Idx j) { return (T)at(f, j); }, fetch, body);
+        l0_march<T, true, false, kFullRows<T>>(v, [&](Idx j) { return (T)at(f, j); }, fetch, body);
     else
-        l0_march<T, true, false>(v, [&](Idx j) { return at(xin, j); }, fetch, body);
+        l0_march<T, true, false, kFullRows<T>>(v, [&](Idx j) { return at(xin, j); }, fetch, body);
     if (DOT) {
         double sb = block_sum(acc, lds);
         if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
@@ -921,10 +940,12 @@ template <typename TF, typename T>
 __global__ void __launch_bounds__(kMThreads) k_l0_residual(L0View<T> v, const TF* __restrict__ f,
                                                           const T* __restrict__ xv,
                                                           T* __restrict__ r) {
-    l0_march<T, true, false>(
+    l0_march<T, true, false, kFullRows<T>>(
         v, [&](Idx j) { return at(xv, j); },
         [&](Idx i, int, int, int, bool, int) { return Vals<T, 1>{{(T)at(f, i)}}; },
-        [&](Idx i, Vals<T, 1> fv, T, T ax, int, int, int, bool, int) { at(r, i) = fv.v[0] - ax; });
+        [&](Idx i, Vals<T, 1> fv, T, T ax, int, int, int, bool, int rk) {
+            at(r, i) = rk >= 0 ? fv.v[0] - ax : T(0);
+        });
 }
 
 template <typename TF, typename T>
@@ -1034,8 +1055,8 @@ __global__ void __launch_bounds__(kMThreads) k_l0_prolong(L0View<T> v, LCView<T>
         for (int d = 0; d < 6; ++d) r.t.v[d] = irr ? v.tab[d][rk] : T(0);
         return r;
     };
-    l0_march<T, false, false>(v, [&](long) { return T(0); }, fetch,
-                              [&](Idx i, R r, T, T, int, int, int, bool irrow, int) {
+    l0_march<T, false, false, kFullRows<T>>(v, [&](long) { return T(0); }, fetch,
+                              [&](Idx i, R r, T, T, int, int, int, bool irrow, int rk) {
         const Vals<T, 8>& f = r.f;
         T apv;
         if (!irrow) {
@@ -1045,7 +1066,7 @@ __global__ void __launch_bounds__(kMThreads) k_l0_prolong(L0View<T> v, LCView<T>
             apv = f.v[0] + r.t.v[0] * f.v[1] + r.t.v[1] * f.v[2] + r.t.v[2] * f.v[3] +
                   r.t.v[3] * f.v[4] + r.t.v[4] * f.v[5] + r.t.v[5] * f.v[6];
         }
-        at(xv, i) = f.v[7] + (f.v[0] - omega * apv);
+        at(xv, i) = rk >= 0 ? f.v[7] + (f.v[0] - omega * apv) : T(0);
     });
 }
 
@@ -1125,7 +1146,8 @@ void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, 
 // Direction update with the product by A carried along:  p <- z + beta p and
 // q <- A z + beta q, which equals A p_new because q held A p_old.  The stencil runs on z
 // (fp32 in mixed precision), the sums in fp64; partials of p . q.  The previous step's
-// x += alpha p, deferred to here, is applied with the old p as it is read.
+// x += alpha p, deferred to here, is applied with the old p as it is read.  With an fp32 z
+// (mixed precision) it stores whole rows.
 template <typename TZ>
 __global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ* __restrict__ zv,
                                                     double* __restrict__ xv,
@@ -1135,15 +1157,16 @@ __global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ*
     const double beta = scal[S_BETA];
     const double xa = scal[S_XA];
     double acc = 0.0;
-    l0_march<double, true, false>(
+    l0_march<double, true, false, kFullRows<TZ>>(
         v, [&](Idx j) { return at(zv, j); },
         [&](Idx i, int, int, int, bool, int) {
             return Vals<double, 3>{{at(p, i), at(q, i), at(xv, i)}};
         },
-        [&](Idx i, Vals<double, 3> f, double zi, double az, int, int, int, bool, int) {
-            const double pi = zi + beta * f.v[0];
-            const double qi = az + beta * f.v[1];
-            at(xv, i) = f.v[2] + xa * f.v[0];
+        [&](Idx i, Vals<double, 3> f, double zi, double az, int, int, int, bool, int rk) {
+            const bool u = rk >= 0;
+            const double pi = u ? zi + beta * f.v[0] : 0.0;
+            const double qi = u ? az + beta * f.v[1] : 0.0;
+            at(xv, i) = u ? f.v[2] + xa * f.v[0] : 0.0;
             at(p, i) = pi;
             at(q, i) = qi;
             acc += pi * qi;
@@ -1166,7 +1189,9 @@ template void cg_pq<float>(const FineLevel&, const float*, double*, double*, dou
                            const double*, double*, hipStream_t);
 
 // r -= alpha q (alpha = S_XA) and partials of r.r; r untouched when the step broke down
-// (S_XA = 0).  x receives alpha p later (the next k_cg_pq or k_cg_xflush).
+// (S_XA = 0).  x receives alpha p later (the next k_cg_pq or k_cg_xflush).  With the fp32
+// copy (mixed precision) it stores whole rows (FULL).
+template <bool FULL>
 __global__ void __launch_bounds__(kMThreads) k_cg_xr(L0View<double> v, double* __restrict__ r,
                                                     const double* __restrict__ q,
                                                     const double* __restrict__ scal, double* part,
@@ -1175,13 +1200,14 @@ __global__ void __launch_bounds__(kMThreads) k_cg_xr(L0View<double> v, double* _
     const double alpha = scal[S_XA];
     const bool ok = alpha != 0.0;
     double acc = 0.0;
-    l0_march<double, false, false>(
+    l0_march<double, false, false, FULL>(
         v, [&](Idx) { return 0.0; },
         [&](Idx i, int, int, int, bool, int) { return Vals<double, 2>{{at(r, i), at(q, i)}}; },
-        [&](Idx i, Vals<double, 2> f, double, double, int, int, int, bool, int) {
-            double ri = f.v[0];
+        [&](Idx i, Vals<double, 2> f, double, double, int, int, int, bool, int rk) {
+            const bool u = rk >= 0;
+            double ri = u ? f.v[0] : 0.0;
             if (ok) {
-                ri -= alpha * f.v[1];
+                ri = u ? ri - alpha * f.v[1] : 0.0;
                 at(r, i) = ri;
                 if (r32) at(r32, i) = (float)ri;
             }
@@ -1194,8 +1220,12 @@ __global__ void __launch_bounds__(kMThreads) k_cg_xr(L0View<double> v, double* _
 void cg_xr(const FineLevel& L, double* r, const double* q, const double* scal, double* partials,
            float* r32, hipStream_t s) {
     KTimer kt_(T_CG_XR, s, L.n_unknowns * (24L + (r32 ? 4 : 0)));
-    klaunch(kt_, true, k_cg_xr, l0_mgrid(L), dim3(kWave, kMY), L.view<double>(), r, q, scal,
-            partials, r32);
+    if (r32)
+        klaunch(kt_, true, k_cg_xr<true>, l0_mgrid(L), dim3(kWave, kMY), L.view<double>(), r, q,
+                scal, partials, r32);
+    else
+        klaunch(kt_, true, k_cg_xr<false>, l0_mgrid(L), dim3(kWave, kMY), L.view<double>(), r, q,
+                scal, partials, r32);
     HIPCHECK(hipGetLastError());
 }
 
