@@ -223,7 +223,11 @@ def serve_bench(args, n_requests=None) -> dict:
 
     reqs = W.serving_stream(n_requests=n_requests or args.serve_requests, qps=1.0, seed=4)
     print(f"[bench] serve: generating {len(reqs)} right-hand sides", file=sys.stderr, flush=True)
-    rhs = {r.rid: W.rhs(r.workload) for r in reqs}
+    rhs = {}
+    for k, r in enumerate(reqs):
+        rhs[r.rid] = W.rhs(r.workload)
+        if (k + 1) % 64 == 0:
+            print(f"[bench] serve: {k + 1} right-hand sides", file=sys.stderr, flush=True)
     dof_total = 0
     out = {}
 
