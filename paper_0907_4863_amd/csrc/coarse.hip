@@ -460,8 +460,8 @@ struct AccL0 {
         a[13] = at[13] = 1.0;
         for (int d = 0; d < 6; ++d) {
             const int k = dir_to_k(d);
-            a[k] = n.irr ? v.tab[d][n.rank] : v.c[d >> 1];
-            at[k] = n.irr ? v.tabT[d][n.rank] : v.c[d >> 1];
+            a[k] = n.irr ? v.tcoef(d, n.rank) : v.c[d >> 1];
+            at[k] = n.irr ? v.tcoefT(d, n.rank) : v.c[d >> 1];
         }
     }
     __device__ double invd(int x, int y, int z) const {

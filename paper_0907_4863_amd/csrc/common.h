@@ -48,8 +48,14 @@ struct L0View {
     const uint64_t* unk;
     const uint64_t* irr;
     const int32_t* base;
-    const T* tab[6];    // scaled off-diagonals of irregular rows, per direction
-    const T* tabT[6];   // the same rows of the transpose
+    // scaled off-diagonals of the irregular rows: table slot r holds 8 values, the 6
+    // directions and 2 of padding, so that a row is read with two 16-byte loads (fp32) or
+    // three (fp64) instead of one load per direction; tabT holds the same rows of the
+    // transpose
+    const T* tab;
+    const T* tabT;
+    __host__ __device__ T tcoef(int d, long r) const { return tab[8 * r + d]; }
+    __host__ __device__ T tcoefT(int d, long r) const { return tabT[8 * r + d]; }
     T c[3];             // interior off-diagonal per axis
     double rho_end;     // factor of the end-plane rows (1/2 with open ends, else 1)
 };
@@ -179,7 +185,7 @@ struct FineLevel {
     uint64_t* irr = nullptr;
     int32_t* base = nullptr;
     long n_irr = 0;
-    double* tab64 = nullptr;    // [12][n_irr]: 6 forward then 6 transpose
+    double* tab64 = nullptr;    // [2][n_irr][8]: rows of the operator, then of its transpose
     float* tab32 = nullptr;
     double c64[3];
     double robin_d = 0.0;       // open ends (Robin parameter d); 0: closed ends
@@ -257,14 +263,12 @@ inline L0View<T> FineLevel::view() const {
     v.gy = (ny + kMY / v.tx - 1) / (kMY / v.tx);
     v.zb = zb;
     v.unk = unk; v.irr = irr; v.base = base;
-    for (int d = 0; d < 6; ++d) {
-        if constexpr (sizeof(T) == 8) {
-            v.tab[d] = (const T*)(tab64 ? tab64 + (long)d * n_irr : nullptr);
-            v.tabT[d] = (const T*)(tab64 ? tab64 + (long)(6 + d) * n_irr : nullptr);
-        } else {
-            v.tab[d] = (const T*)(tab32 ? tab32 + (long)d * n_irr : nullptr);
-            v.tabT[d] = (const T*)(tab32 ? tab32 + (long)(6 + d) * n_irr : nullptr);
-        }
+    if constexpr (sizeof(T) == 8) {
+        v.tab = (const T*)tab64;
+        v.tabT = (const T*)(tab64 ? tab64 + 8 * n_irr : nullptr);
+    } else {
+        v.tab = (const T*)tab32;
+        v.tabT = (const T*)(tab32 ? tab32 + 8 * n_irr : nullptr);
     }
     for (int a = 0; a < 3; ++a) v.c[a] = (T)c64[a];
     v.rho_end = robin_d > 0.0 ? 0.5 : 1.0;

@@ -190,6 +190,23 @@ __device__ __forceinline__ void settle(const R& r) {
     }
 }
 
+// Table row b + o (b wave-uniform, o per lane) of an 8-wide coefficient table: its 6
+// values in two 16-byte loads (fp32; the second narrowed to 8 bytes) or three (fp64).
+template <typename T>
+__device__ __forceinline__ void load_row6(const T* tb, long b, unsigned o, T t[6]) {
+    const char* p = reinterpret_cast<const char*>(tb + 8 * b) + (size_t)o * (8 * sizeof(T));
+    if constexpr (sizeof(T) == 4) {
+        const float4 a = *reinterpret_cast<const float4*>(p);
+        const float2 c = *reinterpret_cast<const float2*>(p + 16);
+        t[0] = a.x; t[1] = a.y; t[2] = a.z; t[3] = a.w; t[4] = c.x; t[5] = c.y;
+    } else {
+        const double2 a = *reinterpret_cast<const double2*>(p);
+        const double2 c = *reinterpret_cast<const double2*>(p + 16);
+        const double2 e = *reinterpret_cast<const double2*>(p + 32);
+        t[0] = a.x; t[1] = a.y; t[2] = c.x; t[3] = c.y; t[4] = e.x; t[5] = e.y;
+    }
+}
+
 // Lane clamped to the span of the set bits of u (u == 0: lane 0).
 __device__ inline int span_lane(uint64_t u, int lane) {
     const int lo = u ? (int)__builtin_ctzll(u) : 0;
@@ -239,7 +256,7 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
     const int z0 = max(bz * v.zb, 1), z1 = min(bz * v.zb + v.zb, v.nz - 1);
     if (z0 >= z1) return;
     const long nx = v.nx, nxy = v.nxy;
-    const T* const* tb = TR ? v.tabT : v.tab;
+    const T* tb = TR ? v.tabT : v.tab;
     // words of planes q = z0-1+lane, lane < z1-z0+2 (at most zb+2 <= 34 planes)
     uint64_t wu = 0, wr = 0;
     int wb = 0;
@@ -286,13 +303,9 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
             // rows with an irregular node: the irregular lanes read their table row
             P.tab = r != 0;
             if (P.tab) {
-                const Idx ti{rbase, rofs};
 #pragma unroll
                 for (int d = 0; d < 6; ++d) P.t[d] = T(0);
-                if (P.irr) {
-#pragma unroll
-                    for (int d = 0; d < 6; ++d) P.t[d] = at(tb[d], ti);
-                }
+                if (P.irr) load_row6(tb, rbase, rofs, P.t);
             } else {
 #pragma unroll
                 for (int d = 0; d < 6; ++d) P.t[d] = T(0);
@@ -675,10 +688,16 @@ __global__ void __launch_bounds__(kThreads) k_build_table(
                         fw = scaled_off(me, nb, a, ih2);
                         bw = scaled_off(nb, me, a, ih2);
                     }
-                    tab[(long)d * n_irr + n.rank] = fw;
-                    tab[(long)(6 + d) * n_irr + n.rank] = bw;
-                    tab32[(long)d * n_irr + n.rank] = (float)fw;
-                    tab32[(long)(6 + d) * n_irr + n.rank] = (float)bw;
+                    tab[8 * n.rank + d] = fw;
+                    tab[8 * (n_irr + n.rank) + d] = bw;
+                    tab32[8 * n.rank + d] = (float)fw;
+                    tab32[8 * (n_irr + n.rank) + d] = (float)bw;
+                }
+                for (int d = 6; d < 8; ++d) {  // padding
+                    tab[8 * n.rank + d] = 0.0;
+                    tab[8 * (n_irr + n.rank) + d] = 0.0;
+                    tab32[8 * n.rank + d] = 0.0f;
+                    tab32[8 * (n_irr + n.rank) + d] = 0.0f;
                 }
             }
         }
@@ -794,9 +813,11 @@ __global__ void __launch_bounds__(kMThreads) k_l0_lz_apply(L0View<double> v,
             const double q = sc * qr, aq = sc * aqr;
             double o = aq;
             if (!SYM && irr) {
-                const double at = q + sc * (v.tabT[0][r] * vin[i - 1] + v.tabT[1][r] * vin[i + 1] +
-                                            v.tabT[2][r] * vin[i - nx] + v.tabT[3][r] * vin[i + nx] +
-                                            v.tabT[4][r] * vin[i - nxy] + v.tabT[5][r] * vin[i + nxy]);
+                double t[6];
+                load_row6(v.tabT, (long)r, 0u, t);
+                const double at = q + sc * (t[0] * vin[i - 1] + t[1] * vin[i + 1] +
+                                            t[2] * vin[i - nx] + t[3] * vin[i + nx] +
+                                            t[4] * vin[i - nxy] + t[5] * vin[i + nxy]);
                 o = 0.5 * (aq + at);
             }
             at(u, i) = o;
@@ -1052,7 +1073,8 @@ __global__ void __launch_bounds__(kMThreads) k_l0_prolong(L0View<T> v, LCView<T>
         r.f.v[6] = vc[a + (z - 3 * qz == 2 ? c.sxy : 0)];
         r.f.v[7] = at(xv, i);
 #pragma unroll
-        for (int d = 0; d < 6; ++d) r.t.v[d] = irr ? v.tab[d][rk] : T(0);
+        for (int d = 0; d < 6; ++d) r.t.v[d] = T(0);
+        if (irr) load_row6(v.tab, (long)rk, 0u, r.t.v);
         return r;
     };
     l0_march<T, false, false, kFullRows<T>>(v, [&](long) { return T(0); }, fetch,
@@ -1312,7 +1334,7 @@ __global__ void __launch_bounds__(kThreads) k_l0_export(L0View<double> v, double
         double dg = 0.0;
         if (n.unk) {
             dg = 1.0;
-            for (int d = 0; d < 6; ++d) cf[d] = n.irr ? v.tab[d][n.rank] : v.c[d >> 1];
+            for (int d = 0; d < 6; ++d) cf[d] = n.irr ? v.tcoef(d, n.rank) : v.c[d >> 1];
         }
         out[13 * nbox + n.i] = dg;
         for (int d = 0; d < 6; ++d) out[(long)dir_to_k(d) * nbox + n.i] = cf[d];

@@ -859,11 +859,11 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
         L.n_irr = tots[0];
         L.n_unknowns = tots[1];
         if (L.n_unknowns != D.n_unk) throw ApiError{SAAMG_HIP_ERROR, "unknown count mismatch"};
-        L.tab64 = (double*)dmalloc(8 * 12 * std::max<long>(L.n_irr, 1));
-        L.tab32 = (float*)dmalloc(4 * 12 * std::max<long>(L.n_irr, 1));
+        L.tab64 = (double*)dmalloc(8 * 16 * std::max<long>(L.n_irr, 1));
+        L.tab32 = (float*)dmalloc(4 * 16 * std::max<long>(L.n_irr, 1));
         fine_numbers(L, dom, dd, variant, s);
         dd.release();
-        H->bytes = 20L * L.nseg + 8L * nbox + 12L * 12 * L.n_irr;
+        H->bytes = 20L * L.nseg + 8L * nbox + 12L * 16 * L.n_irr;
 
         // hierarchy (Section 3.2): coarsen until at most max_coarse unknowns
         long n_cur = L.n_unknowns;
@@ -1254,7 +1254,7 @@ int saamg_footprint_bytes(int nx, int ny, int nz, int variant, int precision, in
         const double nbox = (double)nx * ny * nz;
         const bool mixed = precision == SAAMG_MIXED;
         const int na = variant == SAAMG_VARIANT_QUAD ? 27 : 14;
-        double h = 8.0 * nbox + 20.0 * nbox / 64 + 0.2 * nbox * 12 * 12;  // sigma, masks, table
+        double h = 8.0 * nbox + 20.0 * nbox / 64 + 0.2 * nbox * 12 * 16;  // sigma, masks, table
         double st = 48.0 * nbox + (mixed ? 4 : 8) * nbox;
         double w = mixed ? 4 : 8;
         st += 3 * w * nbox + w * nbox / 3;  // level-0 V-cycle vectors and restriction sums
