@@ -1055,22 +1055,38 @@ __global__ void __launch_bounds__(kMThreads) k_l0_prolong(L0View<T> v, LCView<T>
                                                          T* __restrict__ xv, T omega) {
     // the coarse values of the node's aggregate and of the neighbours' aggregates, the
     // current x, and (irregular nodes) the row's table coefficients, all issued a plane
-    // ahead
+    // ahead.  The three planes of an aggregate layer share the node's own, x- and
+    // y-neighbour aggregates: those five values are loaded on the layer's first plane in
+    // the tile and kept, and only the z-neighbour on a face plane is loaded per plane.
+    // They are taken at the lane's own node (x clamped to the box), not at the
+    // span-clamped node the other loads use, so that they hold for every plane.
     struct R {
         Vals<T, 8> f;
         Vals<T, 6> t;
     };
-    auto fetch = [&](Idx i, int x, int y, int z, bool irr, int rk) {
+    int cqz = -1;
+    T c0 = T(0), cxm = T(0), cxp = T(0), cym = T(0), cyp = T(0);
+    auto fetch = [&](Idx i, int xs, int y, int z, bool irr, int rk) {
+        const int x = min(xs - (int)i.o + (int)threadIdx.x, v.nx - 1);
         const int qx = x / 3, qy = y / 3, qz = z / 3;
         const long a = (qx + 1) + (long)c.sx * (qy + 1) + c.sxy * (qz + 1);
+        if (qz != cqz) {  // wave-uniform
+            cqz = qz;
+            c0 = vc[a];
+            cxm = vc[a - (x - 3 * qx == 0)];
+            cxp = vc[a + (x - 3 * qx == 2)];
+            cym = vc[a - (y - 3 * qy == 0 ? c.sx : 0)];
+            cyp = vc[a + (y - 3 * qy == 2 ? c.sx : 0)];
+        }
+        const int zr = z - 3 * qz;
         R r;
-        r.f.v[0] = vc[a];
-        r.f.v[1] = vc[a - (x - 3 * qx == 0)];
-        r.f.v[2] = vc[a + (x - 3 * qx == 2)];
-        r.f.v[3] = vc[a - (y - 3 * qy == 0 ? c.sx : 0)];
-        r.f.v[4] = vc[a + (y - 3 * qy == 2 ? c.sx : 0)];
-        r.f.v[5] = vc[a - (z - 3 * qz == 0 ? c.sxy : 0)];
-        r.f.v[6] = vc[a + (z - 3 * qz == 2 ? c.sxy : 0)];
+        r.f.v[0] = c0;
+        r.f.v[1] = cxm;
+        r.f.v[2] = cxp;
+        r.f.v[3] = cym;
+        r.f.v[4] = cyp;
+        r.f.v[5] = zr == 0 ? vc[a - c.sxy] : c0;
+        r.f.v[6] = zr == 2 ? vc[a + c.sxy] : c0;
         r.f.v[7] = at(xv, i);
 #pragma unroll
         for (int d = 0; d < 6; ++d) r.t.v[d] = T(0);
