@@ -9,7 +9,7 @@ namespace saamg {
 // Coefficient k of the row with slot s (compressed operator).
 template <typename T>
 __device__ inline T lc_row(const LCView<T>& c, int s, int k) {
-    return s >= 0 ? c.tb[k * c.tcap + s] : (s == -1 ? c.cst[k] : T(0));
+    return s >= 0 ? c.tb[(long)kLcRow * s + k] : (s == -1 ? c.cst[k] : T(0));
 }
 // Coefficient A(i, k) of a 27-point level.
 template <typename T, bool SYM>
@@ -19,12 +19,36 @@ __device__ inline T lc_a(const LCView<T>& c, long i, int k) {
 // Coefficient k of the transpose row with slot s: A^T(i, k) = A(i + off(k), 26 - k).
 template <typename T>
 __device__ inline T lc_rowT(const LCView<T>& c, int s, int k) {
-    return s >= 0 ? c.tbT[k * c.tTcap + s] : (s == -1 ? c.cst[26 - k] : T(0));
+    return s >= 0 ? c.tbT[(long)kLcRow * s + k] : (s == -1 ? c.cst[26 - k] : T(0));
 }
 template <typename T, bool SYM>
 __device__ inline T lc_at(const LCView<T>& c, long i, int k) {
     if (SYM) return lc_a<T, true>(c, i, k);
     return lc_rowT(c, c.slotT[i], k);
+}
+
+// Row s of a coefficient table into t: 7 (fp32) or 14 (fp64) 16-byte loads.
+template <typename T>
+__device__ __forceinline__ void lc_load_row(const T* tb, int s, T (&t)[kLcRow]) {
+    if constexpr (sizeof(T) == 4) {
+        const float4* p = reinterpret_cast<const float4*>(tb + (long)kLcRow * s);
+#pragma unroll
+        for (int q = 0; q < kLcRow / 4; ++q) {
+            const float4 v = p[q];
+            t[4 * q] = v.x;
+            t[4 * q + 1] = v.y;
+            t[4 * q + 2] = v.z;
+            t[4 * q + 3] = v.w;
+        }
+    } else {
+        const double2* p = reinterpret_cast<const double2*>(tb + (long)kLcRow * s);
+#pragma unroll
+        for (int q = 0; q < kLcRow / 2; ++q) {
+            const double2 v = p[q];
+            t[2 * q] = v.x;
+            t[2 * q + 1] = v.y;
+        }
+    }
 }
 
 // Storage offset of neighbour k, from the pitches (the unrolled loops fold the constants).
@@ -48,14 +72,11 @@ __device__ inline T lc_stencil(const LCView<T>& c, long i, F X) {
         for (int k = 0; k < 27; ++k) acc += c.cst[kT ? 26 - k : k] * X(i + lc_off(c, k));
         return acc;
     }
-    const T* tb = kT ? c.tbT : c.tb;
-    const long cap = kT ? c.tTcap : c.tcap;
     const int sc = s < 0 ? 0 : s;  // a valid table row for the interior lanes' (unused) load
+    T t[kLcRow];
+    lc_load_row(kT ? c.tbT : c.tb, sc, t);
 #pragma unroll
-    for (int k = 0; k < 27; ++k) {
-        const T t = tb[k * cap + sc];
-        acc += (s >= 0 ? t : c.cst[kT ? 26 - k : k]) * X(i + lc_off(c, k));
-    }
+    for (int k = 0; k < 27; ++k) acc += (s >= 0 ? t[k] : c.cst[kT ? 26 - k : k]) * X(i + lc_off(c, k));
     return acc;
 }
 
@@ -391,11 +412,18 @@ __global__ void __launch_bounds__(kThreads) k_lc_prolong(LCView<T> c, LCView<T> 
         return ax + (long)cc.sx * ay + cc.sxy * az;
     };
     T apv = 0;
-    const int s = c.slot[i];
+    const int s = c.slot[i];  // -1 or a table row (the node is an unknown)
+    T t[kLcRow];
+    if (s >= 0) {
+        lc_load_row(c.tb, s, t);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 27; ++k) t[k] = c.cst[k];
+    }
 #pragma unroll
     for (int k = 0; k < 27; ++k) {
         const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
-        apv += lc_row(c, s, k) * vc[agg(X + dx, Y + dy, Z + dz)];
+        apv += t[k] * vc[agg(X + dx, Y + dy, Z + dz)];
     }
     const T pv = vc[agg(X, Y, Z)];
     xv[i] += pv - omega * id * apv;
@@ -637,11 +665,11 @@ __global__ void k_d2f(const double* a, float* b, long n) {
 
 void lc_to_fp32(CoarseLevel& C, hipStream_t s) {
     const long nb = (C.nstore + 255) / 256;
-    const long nt = 27 * C.tab_cap;
+    const long nt = kLcRow * C.tab_cap;
     hipLaunchKernelGGL(k_d2f, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, C.tab64, C.tab32,
                        nt);
     if (C.tabT64) {
-        const long ntt = 27 * C.tabT_cap;
+        const long ntt = kLcRow * C.tabT_cap;
         hipLaunchKernelGGL(k_d2f, dim3((unsigned)((ntt + 255) / 256)), dim3(256), 0, s, C.tabT64,
                            C.tabT32, ntt);
     }
@@ -680,7 +708,8 @@ __global__ void k_lc_fill(LCView<double> c, long n, const int32_t* __restrict__ 
     const int lane = threadIdx.x & 63;
     const int s = base[t >> 6] + __popcll(bal & ((1ull << lane) - 1ull));
     slot[t] = s;
-    for (int k = 0; k < 27; ++k) tab[k * cap + s] = lc_full(c, t, k);
+    for (int k = 0; k < 27; ++k) tab[(long)kLcRow * s + k] = lc_full(c, t, k);
+    tab[(long)kLcRow * s + 27] = 0.0;
 }
 
 // Transpose rows: slot -2 where every coupling is zero (not an unknown), -1 where the node
@@ -712,7 +741,8 @@ __global__ void k_lc_fillT(LCView<double> c, long n, const int32_t* __restrict__
     const int lane = threadIdx.x & 63;
     const int s = base[t >> 6] + __popcll(bal & ((1ull << lane) - 1ull));
     slotT[t] = s;
-    for (int k = 0; k < 27; ++k) tab[k * cap + s] = lc_full(c, t + c.off[k], 26 - k);
+    for (int k = 0; k < 27; ++k) tab[(long)kLcRow * s + k] = lc_full(c, t + c.off[k], 26 - k);
+    tab[(long)kLcRow * s + 27] = 0.0;
 }
 
 __global__ void k_lc_ref_row(LCView<double> c, long ref, double* out) {
@@ -747,11 +777,11 @@ void lc_compress(CoarseLevel& C, hipStream_t s) {
             dfree(C.tab32);
             C.tab32 = nullptr;
             C.tab_cap = std::max<long>(nt, 1);
-            C.tab64 = (double*)dmalloc(8 * 27 * C.tab_cap);
+            C.tab64 = (double*)dmalloc(8 * kLcRow * C.tab_cap);
         }
         if (!C.tab64) {
             C.tab_cap = 1;
-            C.tab64 = (double*)dmalloc(8 * 27);
+            C.tab64 = (double*)dmalloc(8 * kLcRow);
         }
         C.n_tab = nt;
         hipLaunchKernelGGL(k_lc_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n, base,
@@ -780,7 +810,7 @@ void lc_compress(CoarseLevel& C, hipStream_t s) {
                 dfree(C.tabT32);
                 C.tabT32 = nullptr;
                 C.tabT_cap = std::max<long>(ntt, 1);
-                C.tabT64 = (double*)dmalloc(8 * 27 * C.tabT_cap);
+                C.tabT64 = (double*)dmalloc(8 * kLcRow * C.tabT_cap);
             }
             C.n_tabT = ntt;
             hipLaunchKernelGGL(k_lc_fillT, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n,

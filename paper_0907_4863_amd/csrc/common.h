@@ -60,6 +60,9 @@ struct L0View {
     double rho_end;     // factor of the end-plane rows (1/2 with open ends, else 1)
 };
 
+// Values per row of a level >= 1 coefficient table (27 and 1 of padding).
+constexpr int kLcRow = 28;
+
 // A level >= 1 operator.  The solve kernels read it compressed: a node's row is the
 // level's interior stencil (slot -1), zero (slot -2: not an unknown or a ghost), or row
 // `slot` of the table.  The full per-offset arrays (fp64 views only) serve setup and
@@ -74,17 +77,16 @@ struct LCView {
     const T* invD;      // 1/diag, 0 at nodes that are not unknowns and in the ghost layer
     int sym;
     const int32_t* slot;  // per storage node
-    const T* tab[27];     // table rows: tab[k][s] = A(i, i + off[k]) for the node of slot s
     T cst[27];            // the interior stencil
     // nonsymmetric levels: the transpose, compressed the same way (slot -1: the node and
     // its 26 neighbours all have the interior row, so A^T(i, k) = cst[26 - k])
     const int32_t* slotT;
-    const T* tabT[27];
-    // the same tables as one base and a per-offset stride (tab[k] = tb + k * tcap), which
-    // the solve kernels index so that no per-offset pointer has to stay in registers
+    // table rows: tb[kLcRow * s + k] = A(i, i + off[k]) for the node of slot s (tbT: the
+    // transpose); kLcRow = 28 values per row (27 and 1 of padding), so that a row is read
+    // with 16-byte loads
     const T* tb;
     const T* tbT;
-    long tcap, tTcap;
+    long tcap, tTcap;     // rows allocated
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -205,7 +207,7 @@ struct CoarseLevel {
     double* invD64 = nullptr;
     float* invD32 = nullptr;
     long n_unknowns = 0;
-    // compressed operator: slot per storage node, interior stencil, table [27][tab_cap]
+    // compressed operator: slot per storage node, interior stencil, table [tab_cap][kLcRow]
     int32_t* slot = nullptr;
     double cst64[27] = {};
     long n_tab = 0, tab_cap = 0;
@@ -285,15 +287,7 @@ inline LCView<T> CoarseLevel::view() const {
         int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
         v.off[k] = dx + (long)sx * dy + sxy * dz;
         v.cst[k] = (T)cst64[k];
-        if constexpr (sizeof(T) == 8) {
-            v.coef[k] = coef64[k];
-            v.tab[k] = tab64 ? tab64 + k * tab_cap : nullptr;
-            v.tabT[k] = tabT64 ? tabT64 + k * tabT_cap : nullptr;
-        } else {
-            v.coef[k] = nullptr;
-            v.tab[k] = tab32 ? tab32 + k * tab_cap : nullptr;
-            v.tabT[k] = tabT32 ? tabT32 + k * tabT_cap : nullptr;
-        }
+        v.coef[k] = sizeof(T) == 8 ? (const T*)coef64[k] : nullptr;
     }
     if constexpr (sizeof(T) == 8) {
         v.invD = invD64;

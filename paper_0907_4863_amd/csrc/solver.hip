@@ -537,7 +537,7 @@ static void free_coarse(CoarseLevel& C) {
 static int64_t coarse_bytes(const CoarseLevel& C, bool mixed) {
     const int na = C.sym ? 14 : 27;
     return (int64_t)(na + 1) * C.nstore * 8 + 4L * C.nstore * (C.sym ? 1 : 2) +
-           (mixed ? 4L * C.nstore : 0) + 27L * (C.tab_cap + C.tabT_cap) * (mixed ? 12 : 8);
+           (mixed ? 4L * C.nstore : 0) + (long)kLcRow * (C.tab_cap + C.tabT_cap) * (mixed ? 12 : 8);
 }
 
 static void validate_options(const saamg_options& o) {
@@ -803,8 +803,8 @@ static void build_coarse_solver(saamg_hierarchy* H, hipStream_t s) {
 static void coarse_fp32(saamg_hierarchy* H, hipStream_t s) {
     if (H->opt.precision != SAAMG_MIXED) return;
     for (auto& C : H->lc) {
-        if (!C.tab32) C.tab32 = (float*)dmalloc(4 * 27 * C.tab_cap);
-        if (C.tabT64 && !C.tabT32) C.tabT32 = (float*)dmalloc(4 * 27 * C.tabT_cap);
+        if (!C.tab32) C.tab32 = (float*)dmalloc(4 * kLcRow * C.tab_cap);
+        if (C.tabT64 && !C.tabT32) C.tabT32 = (float*)dmalloc(4 * kLcRow * C.tabT_cap);
         if (!C.invD32) C.invD32 = (float*)dmalloc(4 * C.nstore);
         lc_to_fp32(C, s);
     }
@@ -1264,7 +1264,7 @@ int saamg_footprint_bytes(int nx, int ny, int nz, int variant, int precision, in
                 (std::ceil(std::cbrt(m) / 3.0) + 2);
             // full fp64 arrays and 1/diag, slots, fp32 1/diag, table (at most every row)
             h += ((na + 1) * 8 + (na == 27 ? 8 : 4) + (mixed ? 4 : 0) +
-                  (na == 27 ? 2 : 1) * 27 * (mixed ? 12 : 8)) * m;
+                  (na == 27 ? 2 : 1) * kLcRow * (mixed ? 12 : 8)) * m;
             st += 4 * w * m;
         }
         h += 8.0 * 1000 * 1000;
