@@ -870,6 +870,8 @@ void l0_lz_update(const FineLevel& L, const double* u, const double* cur, double
 //   ZERO2: x1 = c2_0 f on the fly; r1 = f - A x1; d1 = c1 x1 + c2 r1; x2 = x1 + d1
 //   FIRST: r = f - A xin; d = c2_0 r; xout = xin + d
 //   NEXT : r = f - A xin; d = c1 din + c2 r; xout = xin + d
+//   NEXT_X: as NEXT with the previous iterate in din: d = c1 (xin - din) + c2 r, so that
+//           the step before it need not store its direction
 // Optional partial sums of fdot . xout (the PCG's r . z when this is the last step); with
 // fdot NULL the dot is taken with f itself (promoted to fp64).
 template <typename TF, typename T, int MODE, bool DOT>
@@ -882,8 +884,11 @@ __global__ void __launch_bounds__(kMThreads) k_l0_cheb(L0View<T> v, const TF* __
     double acc = 0.0;
     auto fetch = [&](Idx i, int, int, int, bool, int) {
         Vals<T, 2> a;
-        a.v[0] = (MODE == CHEB_FIRST || MODE == CHEB_NEXT || MODE == CHEB_ZERO1) ? (T)at(f, i) : T(0);
-        a.v[1] = (MODE == CHEB_NEXT) ? at(din, i) : T(0);
+        a.v[0] = (MODE == CHEB_FIRST || MODE == CHEB_NEXT || MODE == CHEB_NEXT_X ||
+                  MODE == CHEB_ZERO1)
+                     ? (T)at(f, i)
+                     : T(0);
+        a.v[1] = (MODE == CHEB_NEXT || MODE == CHEB_NEXT_X) ? at(din, i) : T(0);
         Vals<double, 1> b;
         b.v[0] = (DOT && fdot) ? at(fdot, i) : 0.0;
         struct R {
@@ -905,7 +910,8 @@ __global__ void __launch_bounds__(kMThreads) k_l0_cheb(L0View<T> v, const TF* __
             xo = x1 + dn;
         } else {
             const T r = fi - ax;
-            dn = (MODE == CHEB_FIRST) ? c20 * r : c1 * fv.a.v[1] + c2 * r;
+            const T dprev = (MODE == CHEB_NEXT_X) ? cv - fv.a.v[1] : fv.a.v[1];
+            dn = (MODE == CHEB_FIRST) ? c20 * r : c1 * dprev + c2 * r;
             xo = cv + dn;
         }
         at(xout, i) = u ? xo : T(0);
@@ -945,6 +951,7 @@ void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* d
         case CHEB_ZERO1: CHEB_LAUNCH(CHEB_ZERO1) break;
         case CHEB_ZERO2: CHEB_LAUNCH(CHEB_ZERO2) break;
         case CHEB_FIRST: CHEB_LAUNCH(CHEB_FIRST) break;
+        case CHEB_NEXT_X: CHEB_LAUNCH(CHEB_NEXT_X) break;
         default: CHEB_LAUNCH(CHEB_NEXT) break;
     }
 #undef CHEB_LAUNCH

@@ -31,8 +31,9 @@ enum Slot {
 // Finalisation ops: how the summed partials update `scal`.
 enum FinOp { FIN_STORE = 0, FIN_ALPHA, FIN_RHO_INIT, FIN_RHO, FIN_LZ_ALPHA, FIN_LZ_BETA, FIN_NORM,
              FIN_RESTORE_RHO, FIN_XA_CLEAR };
-// Chebyshev step kinds.
-enum ChebMode { CHEB_ZERO1 = 0, CHEB_ZERO2, CHEB_FIRST, CHEB_NEXT };
+// Chebyshev step kinds.  CHEB_NEXT_X (level 0 only) is CHEB_NEXT with the previous
+// iterate in place of the previous direction (d = xin - din).
+enum ChebMode { CHEB_ZERO1 = 0, CHEB_ZERO2, CHEB_FIRST, CHEB_NEXT, CHEB_NEXT_X };
 
 void pic_deposit(saamg_pic* P, const double* pos, long n, double q, double* rho, hipStream_t s);
 void pic_gather(saamg_pic* P, const double* phi, const double* pos, long n, double* E, hipStream_t s);

@@ -176,12 +176,19 @@ static T* vcycle(const saamg_hierarchy* H, VBuf<T>& B, int l, const T* f0, T* ou
         l0_prolong<T>(H->l0, H->lc[0], v, x, P.omega, s);
     else
         lc_prolong<T>(H->lc[l - 1], H->lc[l], v, x, P.omega, s);
-    // post-smoothing
+    // post-smoothing.  Degree 2 on level 0: the second step takes its previous direction as
+    // the difference of the two iterates (both still held), so the first stores none.
+    const bool xdiff = fine && c.degree == 2;
     for (int k = 0; k < c.degree; ++k) {
         const bool last = (k == c.degree - 1);
         T* dst = (last && fine) ? out : other;
-        chebstep<T>(H, l, k == 0 ? CHEB_FIRST : CHEB_NEXT, f0, fl, x, d, dst, last ? nullptr : d,
-                    c.c1[k], c.c2[k], c.c2[0], fdot, (last && fine) ? dot : nullptr, s);
+        if (xdiff && k == 1)
+            chebstep<T>(H, l, CHEB_NEXT_X, f0, fl, x, other, dst, nullptr, c.c1[k], c.c2[k],
+                        c.c2[0], fdot, dot, s);
+        else
+            chebstep<T>(H, l, k == 0 ? CHEB_FIRST : CHEB_NEXT, f0, fl, x, d, dst,
+                        (last || xdiff) ? nullptr : d, c.c1[k], c.c2[k], c.c2[0], fdot,
+                        (last && fine) ? dot : nullptr, s);
         other = x;
         x = dst;
     }
