@@ -139,6 +139,13 @@ __device__ __forceinline__ void nts(E* a, Idx k, V v) {
     __builtin_nontemporal_store((E)v, &at(a, k));
 }
 
+// Load of an operand a solve kernel reads once per node (not a stencil operand): a
+// nontemporal load, for the same reason.  k_cg_pq keeps ordinary loads (slower there).
+template <class E>
+__device__ __forceinline__ std::remove_const_t<E> ntl(E* a, Idx k) {
+    return __builtin_nontemporal_load(&at(a, k));
+}
+
 // 64-bit value of lane k of a wavefront, as a wave-uniform (scalar) value.
 __device__ inline uint64_t lane_u64(uint64_t v, int k) {
     const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, k);
@@ -894,11 +901,11 @@ __global__ void __launch_bounds__(kMThreads) k_l0_cheb(L0View<T> v, const TF* __
         Vals<T, 2> a;
         a.v[0] = (MODE == CHEB_FIRST || MODE == CHEB_NEXT || MODE == CHEB_NEXT_X ||
                   MODE == CHEB_ZERO1)
-                     ? (T)at(f, i)
+                     ? (T)ntl(f, i)
                      : T(0);
-        a.v[1] = (MODE == CHEB_NEXT || MODE == CHEB_NEXT_X) ? at(din, i) : T(0);
+        a.v[1] = (MODE == CHEB_NEXT || MODE == CHEB_NEXT_X) ? ntl(din, i) : T(0);
         Vals<double, 1> b;
-        b.v[0] = (DOT && fdot) ? at(fdot, i) : 0.0;
+        b.v[0] = (DOT && fdot) ? ntl(fdot, i) : 0.0;
         struct R {
             Vals<T, 2> a;
             Vals<double, 1> b;
@@ -978,7 +985,7 @@ __global__ void __launch_bounds__(kMThreads) k_l0_residual(L0View<T> v, const TF
                                                           T* __restrict__ r) {
     l0_march<T, true, false, kFullRows<T>>(
         v, [&](Idx j) { return at(xv, j); },
-        [&](Idx i, int, int, int, bool, int) { return Vals<T, 1>{{(T)at(f, i)}}; },
+        [&](Idx i, int, int, int, bool, int) { return Vals<T, 1>{{(T)ntl(f, i)}}; },
         [&](Idx i, Vals<T, 1> fv, T, T ax, int, int, int, bool, int rk) {
             nts(r, i, rk >= 0 ? fv.v[0] - ax : T(0));
         });
@@ -1102,7 +1109,7 @@ __global__ void __launch_bounds__(kMThreads) k_l0_prolong(L0View<T> v, LCView<T>
         r.f.v[4] = cyp;
         r.f.v[5] = zr == 0 ? vc[a - c.sxy] : c0;
         r.f.v[6] = zr == 2 ? vc[a + c.sxy] : c0;
-        r.f.v[7] = at(xv, i);
+        r.f.v[7] = ntl(xv, i);
 #pragma unroll
         for (int d = 0; d < 6; ++d) r.t.v[d] = T(0);
         if (irr) load_row6(v.tab, (long)rk, 0u, r.t.v);
@@ -1146,7 +1153,7 @@ __global__ void __launch_bounds__(kMThreads) k_cg_init(L0View<double> v, const d
     l0_march<double, false, false>(
         v, [&](long) { return 0.0; },
         [&](Idx i, int, int, int, bool, int) {
-            return Vals<double, 3>{{at(sigma, i), at(b, i), x0 ? at(x0, i) : 0.0}};
+            return Vals<double, 3>{{ntl(sigma, i), ntl(b, i), x0 ? ntl(x0, i) : 0.0}};
         },
         [&](Idx i, Vals<double, 3> f, double, double, int, int, int z, bool, int) {
             // end-plane rows of open ends are halved, and so is their right-hand side
@@ -1172,7 +1179,7 @@ __global__ void __launch_bounds__(kMThreads) k_cg_resid(L0View<double> v, const 
     double a0 = 0.0, a1 = 0.0;
     l0_march<double, true, false>(
         v, [&](Idx j) { return at(xv, j); },
-        [&](Idx i, int, int, int, bool, int) { return Vals<double, 1>{{at(bs, i)}}; },
+        [&](Idx i, int, int, int, bool, int) { return Vals<double, 1>{{ntl(bs, i)}}; },
         [&](Idx i, Vals<double, 1> f, double, double ax, int, int, int, bool, int) {
             const double bi = f.v[0];
             const double o = bi - ax;
@@ -1255,7 +1262,7 @@ __global__ void __launch_bounds__(kMThreads) k_cg_xr(L0View<double> v, double* _
     double acc = 0.0;
     l0_march<double, false, false, FULL>(
         v, [&](Idx) { return 0.0; },
-        [&](Idx i, int, int, int, bool, int) { return Vals<double, 2>{{at(r, i), at(q, i)}}; },
+        [&](Idx i, int, int, int, bool, int) { return Vals<double, 2>{{ntl(r, i), ntl(q, i)}}; },
         [&](Idx i, Vals<double, 2> f, double, double, int, int, int, bool, int rk) {
             const bool u = rk >= 0;
             double ri = u ? f.v[0] : 0.0;
