@@ -175,22 +175,31 @@ def domain_from_shape(kind: int, a: float, b: float, length: float, nx: int, ny:
     """Domain of an analytic pipe; with ``open_ends`` the end planes hold unknowns (Robin,
     d = length / 2) and the box has nz + 2 planes."""
     L = lib()
-    mask = np.zeros((nz + 2 * int(open_ends), ny, nx), dtype=np.uint8)
+    nzb = nz + 2 * int(open_ends)
+    mask = np.empty((nzb, ny, nx), dtype=np.uint8)
     n = C.c_int64(0)
     mp = mask.ctypes.data_as(C.POINTER(C.c_uint8))
     oe = int(bool(open_ends))
-    _check(L.saamg_domain_from_shape(kind, a, b, length, bore_r, cavity_half_len, nx, ny, nz, oe,
-                                     mp, 0, None, None, None, C.byref(n)))
+    # one call with room for the wall entries of a surface-sized set of nodes (the entries
+    # are written in node order up to the capacity); a second call only if they do not fit
+    cap = max(8 * (nx * ny + nx * nzb + ny * nzb), 1)
+    while True:
+        node = np.empty(cap, dtype=np.int64)
+        dr = np.empty(cap, dtype=np.uint8)
+        s = np.empty(cap, dtype=np.float64)
+        rc = L.saamg_domain_from_shape(kind, a, b, length, bore_r, cavity_half_len, nx, ny, nz,
+                                       oe, mp, cap, node.ctypes.data_as(C.POINTER(C.c_int64)),
+                                       dr.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                       s.ctypes.data_as(_DP), C.byref(n))
+        if rc != OK and n.value > cap:
+            cap = n.value
+            continue
+        _check(rc)
+        break
     cnt = n.value
-    node = np.zeros(max(cnt, 1), dtype=np.int64)
-    dr = np.zeros(max(cnt, 1), dtype=np.uint8)
-    s = np.zeros(max(cnt, 1), dtype=np.float64)
-    _check(L.saamg_domain_from_shape(kind, a, b, length, bore_r, cavity_half_len, nx, ny, nz, oe,
-                                     mp, max(cnt, 1), node.ctypes.data_as(C.POINTER(C.c_int64)),
-                                     dr.ctypes.data_as(C.POINTER(C.c_uint8)),
-                                     s.ctypes.data_as(_DP), C.byref(n)))
     h = (2.0 * a / (nx - 1), 2.0 * b / (ny - 1), length / (nz - 1))
-    return HostDomain(mask, h, node[:cnt], dr[:cnt], s[:cnt], 0.5 * length if open_ends else 0.0)
+    return HostDomain(mask, h, node[:cnt].copy(), dr[:cnt].copy(), s[:cnt].copy(),
+                      0.5 * length if open_ends else 0.0)
 
 
 def domain_for(shape, nx: int, ny: int, nz: int, open_ends: bool = False) -> HostDomain:

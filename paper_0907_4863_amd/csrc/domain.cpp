@@ -5,8 +5,11 @@
 // wall point is the interval end on the side of the outside neighbour.
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
+#include <vector>
 
 #include "../../include/saamg.h"
 
@@ -62,6 +65,30 @@ inline double coord(double half, int i, int n) {
     return half * (double)(2 * i - (n - 1)) / (double)(n - 1);
 }
 
+struct WallEntry {
+    int64_t node;
+    uint8_t dir;
+    double s;
+};
+
+// Runs f(lo, hi) over [0, n) split into contiguous ranges, one per thread (at most 16
+// threads, at least `grain` items each); the ranges are in order.
+template <class F>
+void parallel_ranges(int n, int grain, F f) {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nt = std::max(1, std::min({(int)std::min(hw, 16u), n / std::max(grain, 1)}));
+    if (nt <= 1) {
+        f(0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) {
+        const int lo = (int)((long)n * t / nt), hi = (int)((long)n * (t + 1) / nt);
+        th.emplace_back([=, &f] { f(lo, hi, t); });
+    }
+    for (auto& x : th) x.join();
+}
+
 }  // namespace
 
 extern "C" int saamg_domain_from_shape(int kind, double a, double b, double length, double bore_r,
@@ -85,55 +112,75 @@ extern "C" int saamg_domain_from_shape(int kind, double a, double b, double leng
     auto lattice_plane = [&](int kb) { return kb - open_ends; };
     auto unknown_plane = [&](int k) { return open_ends ? (k >= 0 && k < nz) : (k > 0 && k < nz - 1); };
 
-    for (int kb = 0; kb < nzb; ++kb) {
-        const int k = lattice_plane(kb);
-        const double z = coord(0.5 * length, k, nz);
-        for (int j = 0; j < ny; ++j) {
-            const double y = coord(b, j, ny);
-            for (int i = 0; i < nx; ++i) {
-                const double x = coord(a, i, nx);
-                const bool interior_index =
-                    i > 0 && j > 0 && i < nx - 1 && j < ny - 1 && unknown_plane(k);
-                mask_out[i + nx * (long)j + nxy * kb] = (interior_index && p.inside(x, y, z)) ? 1 : 0;
+    // The box planes are split into contiguous ranges over threads: first the mask, then
+    // (after every plane's mask is known) the wall entries of each range in node order,
+    // concatenated in range order.
+    parallel_ranges(nzb, 4, [&](int kb0, int kb1, int) {
+        for (int kb = kb0; kb < kb1; ++kb) {
+            const int k = lattice_plane(kb);
+            const double z = coord(0.5 * length, k, nz);
+            for (int j = 0; j < ny; ++j) {
+                const double y = coord(b, j, ny);
+                for (int i = 0; i < nx; ++i) {
+                    const double x = coord(a, i, nx);
+                    const bool interior_index =
+                        i > 0 && j > 0 && i < nx - 1 && j < ny - 1 && unknown_plane(k);
+                    mask_out[i + nx * (long)j + nxy * kb] =
+                        (interior_index && p.inside(x, y, z)) ? 1 : 0;
+                }
             }
         }
-    }
+    });
 
-    int64_t count = 0;
     const long step[3] = {1, (long)nx, nxy};
-    for (int kb = 1; kb < nzb - 1; ++kb) {
-        const int k = lattice_plane(kb);
-        const double z = coord(0.5 * length, k, nz);
-        for (int j = 1; j < ny - 1; ++j) {
-            const double y = coord(b, j, ny);
-            for (int i = 1; i < nx - 1; ++i) {
-                const long idx = i + nx * (long)j + nxy * kb;
-                if (!mask_out[idx]) continue;
-                const double x = coord(a, i, nx);
-                const double pos[3] = {x, y, z};
-                for (int d = 0; d < 6; ++d) {
-                    const int axis = d / 2;
-                    const long nb = (d & 1) ? idx + step[axis] : idx - step[axis];
-                    if (mask_out[nb]) continue;
-                    // the ghost planes beyond open ends are not walls
-                    if (open_ends && axis == 2 && (kb + ((d & 1) ? 1 : -1) == 0 ||
-                                                   kb + ((d & 1) ? 1 : -1) == nzb - 1))
-                        continue;
-                    const double end = p.half_interval(axis, x, y, z);
-                    const double wall = (d & 1) ? end : -end;
-                    double s = std::fabs(wall - pos[axis]) / h[axis];
-                    if (s > 1.0 - kSnap) s = 1.0;
-                    if (!(s > 0.0)) return SAAMG_INVALID_ARG;
-                    if (s < 1.0) {
-                        if (count < wall_cap) {
-                            wall_node[count] = idx;
-                            wall_dir[count] = (uint8_t)d;
-                            wall_s[count] = s;
+    std::vector<std::vector<WallEntry>> parts(16);
+    std::vector<int> bad(16, 0);
+    const int nin = std::max(nzb - 2, 0);  // planes 1 .. nzb-2
+    parallel_ranges(nin, 4, [&](int r0, int r1, int t) {
+        std::vector<WallEntry>& out = parts[t];
+        for (int kb = 1 + r0; kb < 1 + r1; ++kb) {
+            const int k = lattice_plane(kb);
+            const double z = coord(0.5 * length, k, nz);
+            for (int j = 1; j < ny - 1; ++j) {
+                const double y = coord(b, j, ny);
+                for (int i = 1; i < nx - 1; ++i) {
+                    const long idx = i + nx * (long)j + nxy * kb;
+                    if (!mask_out[idx]) continue;
+                    const double x = coord(a, i, nx);
+                    const double pos[3] = {x, y, z};
+                    for (int d = 0; d < 6; ++d) {
+                        const int axis = d / 2;
+                        const long nb = (d & 1) ? idx + step[axis] : idx - step[axis];
+                        if (mask_out[nb]) continue;
+                        // the ghost planes beyond open ends are not walls
+                        if (open_ends && axis == 2 && (kb + ((d & 1) ? 1 : -1) == 0 ||
+                                                       kb + ((d & 1) ? 1 : -1) == nzb - 1))
+                            continue;
+                        const double end = p.half_interval(axis, x, y, z);
+                        const double wall = (d & 1) ? end : -end;
+                        double sv = std::fabs(wall - pos[axis]) / h[axis];
+                        if (sv > 1.0 - kSnap) sv = 1.0;
+                        if (!(sv > 0.0)) {
+                            bad[t] = 1;
+                            return;
                         }
-                        ++count;
+                        if (sv < 1.0) out.push_back({idx, (uint8_t)d, sv});
                     }
                 }
             }
+        }
+    });
+    for (int t = 0; t < 16; ++t)
+        if (bad[t]) return SAAMG_INVALID_ARG;
+    int64_t count = 0;
+    for (const auto& part : parts) {
+        for (const WallEntry& e : part) {
+            if (count < wall_cap) {
+                wall_node[count] = e.node;
+                wall_dir[count] = e.dir;
+                wall_s[count] = e.s;
+            }
+            ++count;
         }
     }
     *n_wall_out = count;
