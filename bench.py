@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--tube-reps", type=int, default=2)
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="open-loop arrival rate as a fraction of the closed-loop solves/s")
+    ap.add_argument("--serve-setup-workers", type=int, default=None,
+                    help="threads building hierarchies of new geometries (server default if unset)")
     return ap.parse_args()
 
 
@@ -234,8 +236,10 @@ def serve_bench(args, n_requests=None) -> dict:
     def run(tag, arrivals, precision):
         rs = [W.Request(r.rid, t, dc.replace(r.workload, precision=precision))
               for r, t in zip(reqs, arrivals)]
-        srv = serve.Server(serve.ServeConfig(precision=precision, max_active=16,
-                                             hbm_budget_bytes=200 << 30), serve.GpuEngine())
+        cfg = serve.ServeConfig(precision=precision, max_active=16, hbm_budget_bytes=200 << 30)
+        if getattr(args, "serve_setup_workers", None):
+            cfg.setup_workers = args.serve_setup_workers
+        srv = serve.Server(cfg, serve.GpuEngine())
         recs = srv.run(rs, rhs_of=lambda q: rhs[q.rid])
         srv.close()
         summ = serve.summarize(recs)

@@ -9,11 +9,16 @@ different requests overlap on the device; finished solves retire at once and fre
 memory for queued requests.  Latency is completion minus arrival.
 
 The device work goes through an engine object (``GpuEngine`` below) so that the
-scheduling logic can be exercised without a GPU.
+scheduling logic can be exercised without a GPU.  An engine whose ``concurrent_setup`` is
+true has the hierarchies of new geometries built on a worker thread, so that the running
+solves keep stepping meanwhile; a request waits, with its memory reserved, until its
+hierarchy is ready (later requests for the same geometry wait on the same build).
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import dataclasses
+import threading
 import time
 from collections import OrderedDict
 from typing import Any, Callable, Dict, List, Optional, Sequence, Tuple
@@ -31,6 +36,9 @@ class ServeConfig:
     tol: float = 1e-8
     max_iter: int = 500
     cache_hierarchies: bool = True
+    # threads building hierarchies (engines with concurrent_setup); GpuEngine runs one
+    # setup at a time, so more workers only overlap their host-side domain construction
+    setup_workers: int = 1
 
 
 @dataclasses.dataclass
@@ -55,12 +63,19 @@ class Record:
 class GpuEngine:
     """Device side of the server: hierarchies, states and steps through the C interface."""
 
+    concurrent_setup = True  # setup() may run on a worker thread beside step()
+
     def __init__(self, device: int = 0, keep_solutions: bool = False):
         import torch
         self.torch = torch
         self.dev = torch.device(f"cuda:{device}")
         self.keep = keep_solutions
         self._streams: List[Any] = []
+        self._tls = threading.local()  # one setup stream per worker thread
+        # one setup at a time: with two or three hierarchies built at once beside the
+        # stepping, some served solves ended without converging (cause not found), so
+        # setups are serialized whatever the number of workers
+        self._setup_lock = threading.Lock()
 
     def key(self, w) -> Tuple:
         s = w.shape
@@ -71,7 +86,16 @@ class GpuEngine:
 
     def setup(self, w, precision: int):
         dom = capi.domain_for(w.shape, w.nx, w.ny, w.nz)
-        H = capi.setup(dom, w.variant, capi.default_options(precision=precision))
+        with self._setup_lock:
+            return self._setup_locked(w, precision, dom)
+
+    def _setup_locked(self, w, precision: int, dom):
+        st = getattr(self._tls, "stream", None)
+        if st is None:
+            st = self._tls.stream = self.torch.cuda.Stream(device=self.dev)  # default priority
+        H = capi.setup(dom, w.variant, capi.default_options(precision=precision),
+                       stream=st.cuda_stream)
+        st.synchronize()  # complete before any state's stream uses H
         info = capi.hierarchy_info(H)
         return H, info["device_bytes"], dom.n_unknowns
 
@@ -135,6 +159,57 @@ class Server:
                 self.used -= e["bytes"]
                 del self.cache[key]
 
+    def _timed_setup(self, w):
+        t0 = self.clock()
+        r = self.eng.setup(w, self.cfg.precision)
+        return r, 1e3 * (self.clock() - t0)
+
+    def _admit_async(self, req, rhs: np.ndarray, now: float, pool, building: dict) -> Optional[dict]:
+        """Admission with the hierarchy of a new geometry built on the worker: returns an
+        active entry (cached geometry) or a pending one (with the setup's future)."""
+        w = req.workload
+        key = self.eng.key(w)
+        hier_est, state_bytes = self.eng.footprint(w, self.cfg.precision)
+        cached = key in self.cache
+        new_build = not cached and key not in building
+        need = state_bytes + (hier_est if new_build else 0)
+        if self.used + need > self.cfg.hbm_budget_bytes:
+            self._evict_for(need)
+        if self.used + need > self.cfg.hbm_budget_bytes:
+            return None
+        rec = Record(req.rid, req.arrival_s, admit_s=now)
+        self.used += need  # the state, and the hierarchy's estimate until its size is known
+        self.peak_used = max(self.peak_used, self.used)
+        if cached:
+            e = self.cache.pop(key)
+            self.cache[key] = e  # most recently used
+            rec.cache_hit = True
+            e["refs"] += 1
+            rec.dof = e["dof"]
+            h = self.eng.start(e["H"], rhs, self.cfg.tol, self.cfg.max_iter)
+            return {"rec": rec, "h": h, "key": key, "state_bytes": state_bytes}
+        if new_build:
+            building[key] = {"fut": pool.submit(self._timed_setup, w), "est": hier_est}
+        return {"rec": rec, "key": key, "state_bytes": state_bytes, "rhs": rhs,
+                "build": building[key], "builder": new_build}
+
+    def _start_pending(self, p: dict, building: dict) -> dict:
+        """Start a pending request whose hierarchy is built."""
+        key, rec = p["key"], p["rec"]
+        if key not in self.cache:  # the first request served by this build
+            (H, hbytes, dof), setup_ms = p["build"]["fut"].result()
+            self.cache[key] = {"H": H, "bytes": hbytes, "refs": 0, "dof": dof}
+            self.used += hbytes - p["build"]["est"]
+            self.peak_used = max(self.peak_used, self.used)
+            building.pop(key, None)
+        if p["builder"]:
+            rec.setup_ms = p["build"]["fut"].result()[1]
+        e = self.cache[key]
+        e["refs"] += 1
+        rec.dof = e["dof"]
+        h = self.eng.start(e["H"], p["rhs"], self.cfg.tol, self.cfg.max_iter)
+        return {"rec": rec, "h": h, "key": key, "state_bytes": p["state_bytes"]}
+
     def _admit(self, req, rhs: np.ndarray, now: float, active: List[dict]) -> Optional[dict]:
         w = req.workload
         key = self.eng.key(w)
@@ -184,6 +259,9 @@ class Server:
     # -------------------------------------------------------------- main loop
     def run(self, requests: Sequence, rhs_of: Callable[[Any], np.ndarray]) -> List[Record]:
         """Serve requests (objects with rid, arrival_s, workload) in arrival order."""
+        if getattr(self.eng, "concurrent_setup", False):
+            with cf.ThreadPoolExecutor(max_workers=self.cfg.setup_workers) as pool:
+                return self._run_async(requests, rhs_of, pool)
         queue = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
         t0 = self.clock()
         active: List[dict] = []
@@ -211,16 +289,65 @@ class Server:
                 if qi < len(queue):
                     self.sleep(max(0.0, queue[qi].arrival_s - (self.clock() - t0)))
                 continue
-            self.eng.step([a["h"] for a in active])
-            self.rounds += 1
-            keep = []
-            for a in active:
-                done, _ = self.eng.query(a["h"])
-                if done:
-                    out.append(self._retire(a, self.clock() - t0))
-                else:
-                    keep.append(a)
-            active = keep
+            self._round(active, out, t0)
+            active = [a for a in active if "done" not in a]
+        return out
+
+    def _round(self, active: List[dict], out: List[Record], t0: float) -> None:
+        """One PCG step of every active solve; finished ones retire (marked "done")."""
+        self.eng.step([a["h"] for a in active])
+        self.rounds += 1
+        for a in active:
+            done, _ = self.eng.query(a["h"])
+            if done:
+                out.append(self._retire(a, self.clock() - t0))
+                a["done"] = True
+
+    def _run_async(self, requests: Sequence, rhs_of: Callable[[Any], np.ndarray],
+                   pool) -> List[Record]:
+        queue = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
+        t0 = self.clock()
+        active: List[dict] = []
+        pending: List[dict] = []
+        building: dict = {}
+        out: List[Record] = []
+        qi = 0
+        while qi < len(queue) or active or pending:
+            now = self.clock() - t0
+            while (qi < len(queue) and queue[qi].arrival_s <= now
+                   and len(active) + len(pending) < self.cfg.max_active):
+                req = queue[qi]
+                a = self._admit_async(req, rhs_of(req), self.clock() - t0, pool, building)
+                if a is None:
+                    if not active and not pending:
+                        r = Record(req.rid, req.arrival_s, status=capi.NOMEM)
+                        r.done_s = self.clock() - t0
+                        out.append(r)
+                        self.rejected.append(req.rid)
+                        qi += 1
+                        continue
+                    break
+                (pending if "build" in a else active).append(a)
+                qi += 1
+            self.max_concurrent = max(self.max_concurrent, len(active) + len(pending))
+            if pending:
+                if not active:
+                    # nothing to step: wait for a build, or until the next arrival
+                    timeout = None
+                    if qi < len(queue):
+                        timeout = max(0.0, queue[qi].arrival_s - (self.clock() - t0))
+                    cf.wait({p["build"]["fut"] for p in pending}, timeout=timeout,
+                            return_when=cf.FIRST_COMPLETED)
+                ready = [p for p in pending if p["build"]["fut"].done()]
+                for p in ready:
+                    pending.remove(p)
+                    active.append(self._start_pending(p, building))
+            if not active:
+                if not pending and qi < len(queue):
+                    self.sleep(max(0.0, queue[qi].arrival_s - (self.clock() - t0)))
+                continue
+            self._round(active, out, t0)
+            active = [a for a in active if "done" not in a]
         return out
 
     def close(self) -> None:

@@ -140,3 +140,58 @@ def test_hierarchy_cache_reuse_and_eviction():
     # the 12^3 hierarchy had to be evicted to admit the 13^3 request, then rebuilt
     assert eng2.setups == 3 and srv2.peak_used <= per13 + 10
     assert not recs2[2].cache_hit
+
+
+# ---------------------------------------------------------------------------------------
+# Hierarchies built on a worker thread (engines with concurrent_setup), as GpuEngine does.
+
+
+class ThreadedFakeEngine(FakeEngine):
+    concurrent_setup = True
+
+    def __init__(self, clock, round_s=0.01):
+        super().__init__(clock, round_s)
+        import threading
+        self.lock = threading.Lock()
+        self.setup_threads = set()
+
+    def setup(self, w, precision):
+        import threading
+        with self.lock:
+            self.setup_threads.add(threading.get_ident())
+            return super().setup(w, precision)
+
+
+def _serve_threaded(reqs, **cfg):
+    import threading
+    clock = Clock()
+    eng = ThreadedFakeEngine(clock)
+    srv = Server(ServeConfig(**cfg), eng, clock=clock, sleep=clock.sleep)
+    recs = srv.run(reqs, rhs_of=lambda r: r.rounds)
+    return srv, eng, {r.rid: r for r in recs}, threading.get_ident()
+
+
+def test_worker_setup_serves_every_request_once_per_geometry():
+    """Hierarchies built off the main thread: every request finishes with its own
+    iterations, one build per geometry (requests of a geometry whose build is running wait
+    on it), the budget holds, and all memory but the cached hierarchies is returned."""
+    reqs = [_req(i, 0.0, 10 + i % 3, 4 + i % 5) for i in range(12)]
+    srv, eng, recs, main = _serve_threaded(reqs, hbm_budget_bytes=1 << 40, max_active=5)
+    assert len(recs) == 12 and all(r.status == 0 for r in recs.values())
+    for r in reqs:
+        assert recs[r.rid].iterations == r.rounds
+    assert eng.setups == 3 and main not in eng.setup_threads
+    assert srv.max_concurrent <= 5 and eng.max_live <= 5 and eng.live_states == 0
+    assert srv.used == sum(e["bytes"] for e in srv.cache.values())
+    assert sum(r.setup_ms > 0 or r.cache_hit for r in recs.values()) >= 3
+
+
+def test_worker_setup_respects_budget_and_rejects_oversized():
+    reqs = [_req(i, 0.0, 10, 4) for i in range(6)] + [_req(6, 0.0, 40, 3)]
+    per = 60 * 1000 + 10 * 1000
+    srv, eng, recs, _ = _serve_threaded(reqs, hbm_budget_bytes=2 * per + 10, max_active=16,
+                                        cache_hierarchies=False)
+    assert recs[6].status == capi.NOMEM and srv.rejected == [6]
+    assert all(recs[i].status == 0 for i in range(6))
+    assert srv.peak_used <= 2 * per + 10 and eng.max_live <= 2
+    assert srv.used == 0 and not srv.cache
