@@ -155,7 +155,9 @@ void saamg_default_options(saamg_options* opt);
  *   n_wall_out    number of entries with s < 1.  If it exceeds a nonzero wall_cap the
  *                 first wall_cap entries are written and SAAMG_INVALID_ARG is returned.
  * Node coordinates are a*(2i-(n-1))/(n-1) per axis; unknowns lie strictly inside (a node
- * inside only within a relative 1e-12 of the wall counts as on the wall).
+ * inside only within a relative 1e-12 of the wall counts as on the wall).  The entries
+ * are written in node order; the work is split over up to 16 host threads.  Host-only and
+ * reentrant.
  */
 int saamg_domain_from_shape(int kind, double a, double b, double length, double bore_r,
                             double cavity_half_len, int nx, int ny, int nz, int open_ends,
@@ -167,6 +169,9 @@ int saamg_domain_from_shape(int kind, double a, double b, double length, double 
  *   variant   SAAMG_VARIANT_*; opt may be NULL (defaults).  Work is queued on stream;
  *   the call returns after the hierarchy is complete.  *out owns all device memory of
  *   the hierarchy until saamg_destroy.
+ * A setup may run on one thread while other threads solve or step states of other
+ * hierarchies on their own streams.  Two setups must not run at the same time on one
+ * device: in a test with two or three at once, some later solves did not converge.
  */
 int saamg_setup(const saamg_domain* dom, int variant, const saamg_options* opt, void* stream,
                 saamg_hierarchy** out);
