@@ -911,37 +911,43 @@ void dense_from_lc(const CoarseLevel& C, const long* cidx, const int32_t* cmap, 
 // In-place Gauss-Jordan inversion without pivoting (the coarsest operator is positive
 // definite, or has a positive definite symmetric part).  Step k: scale pivot row k, then
 // eliminate column k from every other row; one block per row.
-__global__ void k_gj_pivot(double* A, int n, int k) {
-    __shared__ double piv;
-    if (threadIdx.x == 0) piv = 1.0 / A[(long)k * n + k];
-    __syncthreads();
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const long o = (long)k * n + j;
-        A[o] = (j == k) ? piv : A[o] * piv;
-    }
-}
-
-__global__ void k_gj_elim(double* A, int n, int k) {
+// One Gauss-Jordan step (pivot k, no pivoting) of the in-place inversion, from src to
+// dst: the pivot row is scaled by 1/a_kk (its diagonal becomes 1/a_kk) and every other row
+// i loses a_ik times the scaled pivot row (its column k becomes -a_ik/a_kk).  Reading one
+// buffer and writing the other lets one launch do both halves of the step; the values
+// are those of the two-pass form (the scaled pivot entry is rounded before it is used).
+__global__ void k_gj_step(const double* __restrict__ src, double* __restrict__ dst, int n,
+                          int k) {
     const int i = blockIdx.x;
-    if (i == k) return;
-    __shared__ double f;
-    if (threadIdx.x == 0) f = A[(long)i * n + k];
-    __syncthreads();
+    const double piv = 1.0 / src[(long)k * n + k];
+    const double f = src[(long)i * n + k];
+    const double* rk = src + (long)k * n;
+    const double* ri = src + (long)i * n;
+    double* di = dst + (long)i * n;
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const long o = (long)i * n + j;
-        if (j == k)
-            A[o] = -f * A[(long)k * n + k];
+        const double pk = rk[j] * piv;  // scaled pivot row
+        if (i == k)
+            di[j] = (j == k) ? piv : pk;
         else
-            A[o] -= f * A[(long)k * n + j];
+            di[j] = (j == k) ? -f * piv : ri[j] - f * pk;
     }
 }
 
+// In-place inverse of the n x n matrix A (row-major, fp64) by Gauss-Jordan without
+// pivoting, one launch per pivot alternating between A and a scratch copy.
 void dense_invert(double* A, int n, hipStream_t s) {
+    double* B = (double*)dmalloc(sizeof(double) * (size_t)n * n);
+    double* src = A;
+    double* dst = B;
     for (int k = 0; k < n; ++k) {
-        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, A, n, k);
-        hipLaunchKernelGGL(k_gj_elim, dim3(n), dim3(256), 0, s, A, n, k);
+        hipLaunchKernelGGL(k_gj_step, dim3(n), dim3(256), 0, s, (const double*)src, dst, n, k);
+        std::swap(src, dst);
     }
     HIPCHECK(hipGetLastError());
+    if (src != A)
+        HIPCHECK(hipMemcpyAsync(A, src, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    dfree(B);
 }
 
 // Gauss-Seidel sweeps on the coarsest level from x = 0 (the iterative coarse level
