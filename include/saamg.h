@@ -104,6 +104,23 @@ typedef struct {
                               multilevel hierarchies; the level's box with its ghost layer must
                               hold at most 8192 nodes)                         default DIRECT */
     int32_t coarse_sweeps; /* Gauss-Seidel sweeps (Section 3.2 uses 3)         default 3    */
+    /* Level-0 launch shape of the solve-time kernels (the results do not depend on it):
+       planes per block along z (0 = automatic; else a power of two 1..64) and 64-node
+       segments per block along x (0 = automatic; else 1, 2 or 4, at most the segments of
+       a line).                                                          default 0, 0 */
+    int32_t l0_planes;
+    int32_t l0_tile_x;
+    /* Device memory.  Every buffer of the hierarchy, of the solve states created on it
+       and of the library's temporaries comes from alloc(alloc_ctx, bytes, stream), which
+       returns memory of the current device (NULL: failure, reported as SAAMG_NOMEM) that
+       may be used in stream order on `stream` (a hipStream_t; NULL = the default stream),
+       and goes back through free(alloc_ctx, ptr, stream) once no queued work uses it.
+       Both NULL: hipMalloc and hipFree.  The library zero-fills new buffers on the
+       stream itself (stream-ordered, no host synchronisation).  Both callbacks may be
+       called from any thread that calls into the library with this hierarchy. */
+    void* (*alloc)(void* alloc_ctx, size_t bytes, void* stream);
+    void (*free)(void* alloc_ctx, void* ptr, void* stream);
+    void* alloc_ctx;
 } saamg_options;
 
 /* Outcome of one solve. rel_res_* are ||r||/||b|| of the scaled system. */
@@ -154,6 +171,9 @@ void saamg_default_options(saamg_options* opt);
  *   wall_cap      capacity of the three wall_* output arrays (host); may be 0 to query.
  *   n_wall_out    number of entries with s < 1.  If it exceeds a nonzero wall_cap the
  *                 first wall_cap entries are written and SAAMG_INVALID_ARG is returned.
+ *   h_out         (nullable) host, 4 doubles: the spacings hx = 2a/(nx-1), hy = 2b/(ny-1),
+ *                 hz = length/(nz-1) and the Robin parameter d of the domain (length/2
+ *                 with open ends, else 0), i.e. the saamg_domain fields hx, hy, hz, robin_d.
  * Node coordinates are a*(2i-(n-1))/(n-1) per axis; unknowns lie strictly inside (a node
  * inside only within a relative 1e-12 of the wall counts as on the wall).  The entries
  * are written in node order; the work is split over up to 16 host threads.  Host-only and
@@ -162,28 +182,47 @@ void saamg_default_options(saamg_options* opt);
 int saamg_domain_from_shape(int kind, double a, double b, double length, double bore_r,
                             double cavity_half_len, int nx, int ny, int nz, int open_ends,
                             uint8_t* mask_out, int64_t wall_cap, int64_t* wall_node,
-                            uint8_t* wall_dir, double* wall_s, int64_t* n_wall_out);
+                            uint8_t* wall_dir, double* wall_s, int64_t* n_wall_out,
+                            double* h_out);
 
 /*
  * Build the scaled operator and the SA-AMG hierarchy on the current device.
- *   variant   SAAMG_VARIANT_*; opt may be NULL (defaults).  Work is queued on stream;
- *   the call returns after the hierarchy is complete.  *out owns all device memory of
- *   the hierarchy until saamg_destroy.
- * A setup may run on one thread while other threads solve or step states of other
- * hierarchies on their own streams.  Two setups must not run at the same time on one
- * device: in a test with two or three at once, some later solves did not converge.
+ *   Section 2: the 7-point operator with the wall rule of `variant` (SAAMG_VARIANT_*:
+ *   eq. const_extrapol, eq. lin_extrapol, eqs. quad_extrapol / quad_extrapol1) and its
+ *   scaling to unit diagonal; Section 3.2 and Table 1: 3^3 cube aggregates, one
+ *   damped-Jacobi step on the tentative prolongator, Galerkin coarse operators
+ *   A_{l+1} = P^T A_l P, a Chebyshev smoother per level, coarsening until at most
+ *   max_coarse unknowns, and a direct (or Gauss-Seidel) solver on the coarsest level.
+ *   A level whose aggregates would not reduce the number of unknowns ends the
+ *   coarsening and becomes the coarsest level.
+ *   dom       host domain (copied; the caller keeps ownership).
+ *   opt       may be NULL (defaults).  Its allocator, if any, serves every later call on
+ *             the hierarchy and on the states created on it.
+ *   stream    work is queued on it (hipStream_t, NULL = default stream); the call
+ *             returns after the hierarchy is complete.
+ *   *out      owns all device memory of the hierarchy until saamg_destroy.
+ * Errors: SAAMG_INVALID_ARG for a bad domain or option (nothing allocated),
+ * SAAMG_NOMEM, SAAMG_HIP_ERROR.  Setups, solves and steps of other hierarchies may run
+ * at the same time on other threads and streams of the device.
  */
 int saamg_setup(const saamg_domain* dom, int variant, const saamg_options* opt, void* stream,
                 saamg_hierarchy** out);
 
 /*
- * Solve A x = b with PCG + one V-cycle per step.
+ * Solve A x = b with preconditioned CG (Section 3.1, also for the nonsymmetric quadratic
+ * rule), one V-cycle of Algorithm 1 per step as the preconditioner (Section 3.2), on the
+ * scaled system of Section 2; stop when ||r||_2 <= tol ||b||_2 of the scaled system
+ * (Section 5), confirmed by a true residual b - A x recomputed in fp64.  A previous
+ * solution as x0 is the warm start of Section 4.
  *   d_b    device, box vector of rho (unscaled right-hand side), fp64.
  *   d_x0   device box vector of the initial guess (unscaled), fp64, or NULL for 0.
  *   d_x    device box vector, fp64, receives the solution (may alias d_x0).
- *   tol    relative residual of the scaled system; max_iter >= 0.
- * Returns after completion; res (nullable) receives the outcome.  Status 4..6 still
- * write the last iterate to d_x.
+ *   tol    relative residual of the scaled system (> 0); max_iter >= 0.
+ *   stream work is queued on it; the call returns after completion.
+ * res (nullable) receives the outcome.  The work vectors are allocated on the first
+ * solve of H (with H's allocator) and kept with H.  Errors: SAAMG_INVALID_ARG (NULL or
+ * bad argument), SAAMG_NOMEM, SAAMG_HIP_ERROR; SAAMG_NOT_CONVERGED, SAAMG_BREAKDOWN
+ * and SAAMG_NONFINITE still write the last iterate to d_x.
  */
 int saamg_solve(saamg_hierarchy* H, const double* d_b, const double* d_x0, double* d_x,
                 double tol, int max_iter, void* stream, saamg_result* res);

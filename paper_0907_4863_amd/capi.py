@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import threading
 from typing import Optional, Sequence, Tuple
 
 import numpy as np
@@ -35,12 +36,19 @@ class Domain(C.Structure):
                 ("wall_s", C.POINTER(C.c_double)), ("robin_d", C.c_double)]
 
 
+# saamg_options' allocator callbacks: alloc(ctx, bytes, stream) -> ptr, free(ctx, ptr, stream)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_levels", C.c_int32), ("max_coarse", C.c_int32),
                 ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("cheb_boost", C.c_double), ("eig_iters", C.c_int32),
                 ("omega_scale", C.c_double), ("coarse_solver", C.c_int32),
-                ("coarse_sweeps", C.c_int32)]
+                ("coarse_sweeps", C.c_int32), ("l0_planes", C.c_int32),
+                ("l0_tile_x", C.c_int32), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_ctx", C.c_void_p)]
 
 
 class Grid(C.Structure):
@@ -90,7 +98,7 @@ def lib() -> C.CDLL:
     L.saamg_domain_from_shape.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                                           C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
                                           C.POINTER(C.c_uint8), C.c_int64, C.POINTER(C.c_int64),
-                                          C.POINTER(C.c_uint8), _DP, C.POINTER(C.c_int64)]
+                                          C.POINTER(C.c_uint8), _DP, C.POINTER(C.c_int64), _DP]
     L.saamg_setup.argtypes = [C.POINTER(Domain), C.c_int, C.POINTER(Options), _P, C.POINTER(_P)]
     L.saamg_refresh.argtypes = [_P, C.POINTER(Domain), _P]
     L.saamg_solve.argtypes = [_P, _P, _P, _P, C.c_double, C.c_int, _P, C.POINTER(Result)]
@@ -128,9 +136,67 @@ def last_error() -> str:
     return lib().saamg_last_error().decode()
 
 
-def default_options(**kw) -> Options:
+class TorchAllocator:
+    """saamg_options allocator callbacks backed by torch's caching allocator, so that the
+    library's device memory comes from (and returns to) torch's pool: no hipMalloc per
+    buffer, and frees are stream-ordered instead of device-synchronising.  Counts the
+    calls (tests read them)."""
+
+    def __init__(self):
+        self.n_alloc = 0
+        self.n_free = 0
+        self.outstanding = {}  # ptr -> bytes
+        self._lock = threading.Lock()
+        self.alloc_fn = ALLOC_FN(self._alloc)
+        self.free_fn = FREE_FN(self._free)
+
+    def _alloc(self, ctx, nbytes, stream):
+        try:
+            import torch
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                   int(stream or 0))
+        except Exception:
+            return None  # reported by the library as SAAMG_NOMEM
+        with self._lock:
+            self.n_alloc += 1
+            self.outstanding[p] = int(nbytes)
+        return p
+
+    def _free(self, ctx, ptr, stream):
+        import torch
+        with self._lock:
+            self.n_free += 1
+            self.outstanding.pop(ptr, None)
+        torch.cuda.caching_allocator_delete(ptr)
+
+    @property
+    def outstanding_bytes(self) -> int:
+        with self._lock:
+            return sum(self.outstanding.values())
+
+
+_torch_allocator: Optional[TorchAllocator] = None
+
+
+def torch_allocator() -> TorchAllocator:
+    """The process-wide TorchAllocator (its callbacks must outlive every hierarchy)."""
+    global _torch_allocator
+    if _torch_allocator is None:
+        _torch_allocator = TorchAllocator()
+    return _torch_allocator
+
+
+def default_options(allocator="torch", **kw) -> Options:
+    """Library defaults (Table 1 and the documented readings) with ``kw`` applied.
+    ``allocator``: "torch" (torch's caching allocator, the default), None (the library's
+    hipMalloc / hipFree) or a TorchAllocator-like object with alloc_fn / free_fn."""
     o = Options()
     lib().saamg_default_options(C.byref(o))
+    if allocator == "torch":
+        allocator = torch_allocator()
+    if allocator is not None:
+        o.alloc = allocator.alloc_fn
+        o.free = allocator.free_fn
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -187,19 +253,19 @@ def domain_from_shape(kind: int, a: float, b: float, length: float, nx: int, ny:
         node = np.empty(cap, dtype=np.int64)
         dr = np.empty(cap, dtype=np.uint8)
         s = np.empty(cap, dtype=np.float64)
+        hd = (C.c_double * 4)()
         rc = L.saamg_domain_from_shape(kind, a, b, length, bore_r, cavity_half_len, nx, ny, nz,
                                        oe, mp, cap, node.ctypes.data_as(C.POINTER(C.c_int64)),
                                        dr.ctypes.data_as(C.POINTER(C.c_uint8)),
-                                       s.ctypes.data_as(_DP), C.byref(n))
+                                       s.ctypes.data_as(_DP), C.byref(n), hd)
         if rc != OK and n.value > cap:
             cap = n.value
             continue
         _check(rc)
         break
     cnt = n.value
-    h = (2.0 * a / (nx - 1), 2.0 * b / (ny - 1), length / (nz - 1))
-    return HostDomain(mask, h, node[:cnt].copy(), dr[:cnt].copy(), s[:cnt].copy(),
-                      0.5 * length if open_ends else 0.0)
+    return HostDomain(mask, (hd[0], hd[1], hd[2]), node[:cnt].copy(), dr[:cnt].copy(),
+                      s[:cnt].copy(), hd[3])
 
 
 def domain_for(shape, nx: int, ny: int, nz: int, open_ends: bool = False) -> HostDomain:
@@ -251,10 +317,13 @@ class Hierarchy:
 
 def setup(dom: HostDomain, variant: int, options: Optional[Options] = None,
           stream=None) -> Hierarchy:
+    """saamg_setup; without ``options`` the defaults with torch's caching allocator."""
     h = _P()
     ds = dom.struct()
-    _check(lib().saamg_setup(C.byref(ds), variant, C.byref(options) if options else None,
-                             _stream(stream), C.byref(h)))
+    if options is None:
+        options = default_options()
+    _check(lib().saamg_setup(C.byref(ds), variant, C.byref(options), _stream(stream),
+                             C.byref(h)))
     return Hierarchy(h.value, (dom.nx, dom.ny, dom.nz))
 
 

@@ -140,10 +140,43 @@ struct ApiError {
 };
 
 void hip_check(hipError_t e, const char* what);
+
+// Device allocator of a hierarchy (the options' callbacks; both null: hipMalloc / hipFree)
+// and the stream on which an entry point queues its work.
+struct MemCtx {
+    void* (*alloc)(void*, size_t, void*) = nullptr;
+    void (*free)(void*, void*, void*) = nullptr;
+    void* ctx = nullptr;
+    hipStream_t s = nullptr;
+};
+// Makes (m, s) the allocator and fill stream of dmalloc / dfree on the calling thread for
+// the scope's lifetime.
+struct MemScope {
+    MemCtx saved;
+    MemScope(const MemCtx& m, hipStream_t s);
+    ~MemScope();
+    MemScope(const MemScope&) = delete;
+    MemScope& operator=(const MemScope&) = delete;
+};
 #define HIPCHECK(x) ::saamg::hip_check((x), #x)
 
-void* dmalloc(size_t bytes);            // throws ApiError(NOMEM) on failure, zero-filled
+// Allocates through the thread's MemScope and zero-fills on its stream (stream-ordered);
+// throws ApiError(NOMEM) on failure.
+void* dmalloc(size_t bytes);
 void dfree(void* p);
+
+// A temporary device buffer of one step, returned to the allocator when the step's scope
+// ends, also when an exception leaves it.  The step synchronises its stream before a
+// normal exit; an allocator's stream-ordered reuse covers the exceptional one.
+struct Tmp {
+    void* p = nullptr;
+    explicit Tmp(size_t bytes) : p(dmalloc(bytes)) {}
+    ~Tmp() { dfree(p); }
+    Tmp(const Tmp&) = delete;
+    Tmp& operator=(const Tmp&) = delete;
+    template <typename T>
+    T* as() const { return (T*)p; }
+};
 
 // Opt-in kernel timing of one kernel class (see saamg_timer_* in the C interface).  A
 // timer spans one launch function: its first launch carries the start event and its last
@@ -181,6 +214,7 @@ ChebCoef cheb_coefficients(double lam_hi, double ratio, int degree);
 struct FineLevel {
     int nx, ny, nz, nsegx;
     int zb = 4;                 // planes per block of the solve-time kernels
+    int tx = 1;                 // segments per block along x of the solve-time kernels
     long nxy, nbox, nseg;
     double h[3];
     uint64_t* unk = nullptr;
@@ -232,6 +266,7 @@ struct LevelParams {
 
 struct saamg_hierarchy {
     int device = 0;
+    saamg::MemCtx mem;        // allocator of every buffer of the hierarchy and its states
     int variant = 1;
     saamg_options opt{};
     int sym = 1;
@@ -253,14 +288,15 @@ struct saamg_hierarchy {
 
 namespace saamg {
 // Segments of one line that a block of the level-0 solve-time kernels covers (its other
-// wavefronts take the next lines): whole 256-node lines where the box is wide enough.
+// wavefronts take the next lines): whole 256-node lines where the box is wide enough
+// (the automatic choice; an option may ask for fewer).
 inline int l0_tile_x(int nsegx) { return nsegx >= kMY ? kMY : (nsegx >= 2 ? 2 : 1); }
 
 template <typename T>
 inline L0View<T> FineLevel::view() const {
     L0View<T> v;
     v.nx = nx; v.ny = ny; v.nz = nz; v.nsegx = nsegx; v.nxy = nxy;
-    v.tx = l0_tile_x(nsegx);
+    v.tx = tx;
     v.gx = (nsegx + v.tx - 1) / v.tx;
     v.gy = (ny + kMY / v.tx - 1) / (kMY / v.tx);
     v.zb = zb;

@@ -95,7 +95,7 @@ extern "C" int saamg_domain_from_shape(int kind, double a, double b, double leng
                                        double cavity_half_len, int nx, int ny, int nz,
                                        int open_ends, uint8_t* mask_out, int64_t wall_cap,
                                        int64_t* wall_node, uint8_t* wall_dir, double* wall_s,
-                                       int64_t* n_wall_out) {
+                                       int64_t* n_wall_out, double* h_out) {
     if (kind < SAAMG_SHAPE_CYLINDER || kind > SAAMG_SHAPE_BOXBORE) return SAAMG_INVALID_ARG;
     if (nx < 3 || ny < 3 || nz < 3 || !mask_out || !n_wall_out) return SAAMG_INVALID_ARG;
     if (open_ends != 0 && open_ends != 1) return SAAMG_INVALID_ARG;
@@ -106,6 +106,10 @@ extern "C" int saamg_domain_from_shape(int kind, double a, double b, double leng
     const Pipe p{kind, a, b, length, bore_r, cavity_half_len};
     const long nxy = (long)nx * ny;
     const double h[3] = {2.0 * a / (nx - 1), 2.0 * b / (ny - 1), length / (nz - 1)};
+    if (h_out) {
+        for (int q = 0; q < 3; ++q) h_out[q] = h[q];
+        h_out[3] = open_ends ? 0.5 * length : 0.0;  // eq. inlet: d = half the pipe length
+    }
     // box planes: the lattice's plane k sits at box plane k + open_ends; with open ends the
     // lattice's end planes hold unknowns and the box gains one ghost plane at each end
     const int nzb = nz + 2 * open_ends;

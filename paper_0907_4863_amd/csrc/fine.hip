@@ -44,8 +44,8 @@ constexpr bool kFullRows = sizeof(T) == 4;
 // Planes per block for the solve-time kernels: long z-marches, but enough blocks to
 // fill the chip a few times over.
 constexpr long kMinBlocks = 8192;
-int l0_choose_zb(int nsegx, int ny, int nz) {
-    const int tx = l0_tile_x(nsegx), ty = kMY / tx;
+int l0_choose_zb(int tx, int nsegx, int ny, int nz) {
+    const int ty = kMY / tx;
     const long tiles = (long)((nsegx + tx - 1) / tx) * ((ny + ty - 1) / ty);
     int zb = 32;
     while (zb > 2 && tiles * ((nz + zb - 1) / zb) < kMinBlocks) zb /= 2;
@@ -53,7 +53,7 @@ int l0_choose_zb(int nsegx, int ny, int nz) {
 }
 
 long l0_blocks(const FineLevel& L) {
-    const int tx = l0_tile_x(L.nsegx), ty = kMY / tx;
+    const int tx = L.tx, ty = kMY / tx;
     const long gx = (L.nsegx + tx - 1) / tx, gy = (L.ny + ty - 1) / ty;
     return gx * gy * ((L.nz + L.zb - 1) / L.zb);
 }
@@ -551,15 +551,13 @@ __global__ void k_mask_diff(const uint64_t* __restrict__ a, const uint64_t* __re
 }
 
 bool l0_same_masks(const FineLevel& L, const uint64_t* unk, const uint64_t* irr, hipStream_t s) {
-    int* flag = (int*)dmalloc(sizeof(int));
+    Tmp flag(sizeof(int));
     hipLaunchKernelGGL(k_mask_diff, dim3((unsigned)((L.nseg + 255) / 256)), dim3(256), 0, s, L.unk,
-                       unk, L.irr, irr, L.nseg, flag);
+                       unk, L.irr, irr, L.nseg, flag.as<int>());
     int h = 1;
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    dfree(flag);
-    HIPCHECK(e);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
     return h == 0;
 }
 
@@ -744,9 +742,10 @@ __global__ void __launch_bounds__(kThreads) k_unknown_list(L0View<double> v, con
 
 void l0_unknown_list(const FineLevel& L, long* out, hipStream_t s) {
     // rank of unknowns by segment: scan the per-segment unknown counts
-    int32_t* cnt = (int32_t*)dmalloc(sizeof(int32_t) * L.nseg);
-    int32_t* base = (int32_t*)dmalloc(sizeof(int32_t) * L.nseg);
-    int64_t* tot = (int64_t*)dmalloc(sizeof(int64_t));
+    Tmp t_cnt(sizeof(int32_t) * L.nseg), t_base(sizeof(int32_t) * L.nseg), t_tot(sizeof(int64_t));
+    int32_t* cnt = t_cnt.as<int32_t>();
+    int32_t* base = t_base.as<int32_t>();
+    int64_t* tot = t_tot.as<int64_t>();
     std::vector<uint64_t> hu(L.nseg);
     HIPCHECK(hipMemcpyAsync(hu.data(), L.unk, sizeof(uint64_t) * L.nseg, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
@@ -758,9 +757,6 @@ void l0_unknown_list(const FineLevel& L, long* out, hipStream_t s) {
                        base, out);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(s));
-    dfree(cnt);
-    dfree(base);
-    dfree(tot);
 }
 
 // ================================================================ operators

@@ -41,7 +41,7 @@ size_t pic_sort_bytes(long n, int bits);
 
 // Number of partial sums (blocks) written by the level-0 reduction kernels.
 long l0_blocks(const FineLevel& L);
-int l0_choose_zb(int nsegx, int ny, int nz);
+int l0_choose_zb(int tx, int nsegx, int ny, int nz);
 long lc_blocks(const CoarseLevel& C);
 
 void finalize(const double* partials, long nblk, int nq, double* scal, int op, int dst,

@@ -23,21 +23,50 @@ void hip_check(hipError_t e, const char* what) {
     if (e != hipSuccess) throw HipError{e, what};
 }
 
+// Device memory of the running entry point: the hierarchy's allocator (the options'
+// callbacks, else hipMalloc / hipFree) and the stream its work is queued on.  Set for the
+// duration of each entry point by MemScope.
+static thread_local MemCtx g_mem{};
+
+MemScope::MemScope(const MemCtx& m, hipStream_t s) : saved(g_mem) {
+    g_mem = m;
+    g_mem.s = s;
+}
+MemScope::~MemScope() { g_mem = saved; }
+
+// New buffers are zero-filled on the entry point's stream, in stream order with the work
+// that follows (a null-stream fill would not be ordered with a non-blocking stream).
 void* dmalloc(size_t bytes) {
     void* p = nullptr;
     if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        throw ApiError{SAAMG_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    if (g_mem.alloc) {
+        p = g_mem.alloc(g_mem.ctx, bytes, (void*)g_mem.s);
+        if (!p)
+            throw ApiError{SAAMG_NOMEM, "the allocator returned NULL for " + std::to_string(bytes) +
+                                            " bytes"};
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw ApiError{SAAMG_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+        }
     }
-    HIPCHECK(hipMemset(p, 0, bytes));
-    HIPCHECK(hipStreamSynchronize(nullptr));  // zero-filled before any stream uses it
+    hipError_t e = hipMemsetAsync(p, 0, bytes, g_mem.s);
+    if (e != hipSuccess) {
+        dfree(p);
+        throw HipError{e, "hipMemsetAsync (zero fill of a new buffer)"};
+    }
     return p;
 }
 
+// The caller guarantees that no queued work still uses p (the library synchronises the
+// stream before it frees a temporary).
 void dfree(void* p) {
-    if (p) (void)hipFree(p);
+    if (!p) return;
+    if (g_mem.free)
+        g_mem.free(g_mem.ctx, p, (void*)g_mem.s);
+    else
+        (void)hipFree(p);
 }
 
 ChebCoef cheb_coefficients(double lam_hi, double ratio, int degree) {
@@ -466,11 +495,13 @@ static double lanczos_lambda(saamg_hierarchy* H, int l, hipStream_t s) {
     const long nb = (l == 0) ? l0_blocks(H->l0) : lc_blocks(H->lc[l - 1]);
     const long n_unk = (l == 0) ? H->l0.n_unknowns : H->lc[l - 1].n_unknowns;
     const int K = (int)std::min<long>(H->opt.eig_iters, n_unk);
-    double* cur = (double*)dmalloc(8 * n);
-    double* prev = (double*)dmalloc(8 * n);
-    double* u = (double*)dmalloc(8 * n);
-    double* part = (double*)dmalloc(sizeof(double) * nb);
-    double* scal = (double*)dmalloc(sizeof(double) * (S_NSLOTS + 2 * K));
+    Tmp t_cur(8 * n), t_prev(8 * n), t_u(8 * n), t_part(sizeof(double) * nb),
+        t_scal(sizeof(double) * (S_NSLOTS + 2 * K));
+    double* cur = t_cur.as<double>();
+    double* prev = t_prev.as<double>();
+    double* u = t_u.as<double>();
+    double* part = t_part.as<double>();
+    double* scal = t_scal.as<double>();
     if (l == 0)
         l0_lz_start(H->l0, cur, part, s);
     else
@@ -493,7 +524,6 @@ static double lanczos_lambda(saamg_hierarchy* H, int l, hipStream_t s) {
     HIPCHECK(hipMemcpyAsync(ab.data(), scal + S_NSLOTS, sizeof(double) * 2 * K,
                             hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
-    for (void* p : {(void*)cur, (void*)prev, (void*)u, (void*)part, (void*)scal}) dfree(p);
     const double* alpha = ab.data();
     const double* beta = ab.data() + K;
     int m = 0;
@@ -508,6 +538,8 @@ static double lanczos_lambda(saamg_hierarchy* H, int l, hipStream_t s) {
     return tridiag_max_eig(alpha, beta, m);
 }
 
+static void free_coarse(CoarseLevel& C);
+
 static CoarseLevel make_coarse(int fmx, int fmy, int fmz, int sym) {
     CoarseLevel C;
     C.mx = (fmx + 2) / 3;
@@ -519,9 +551,14 @@ static CoarseLevel make_coarse(int fmx, int fmy, int fmz, int sym) {
     C.sxy = (long)C.sx * C.sy;
     C.nstore = C.sxy * C.sz;
     C.sym = sym;
-    for (int k = 0; k < 27; ++k)
-        if (!sym || k >= 13) C.coef64[k] = (double*)dmalloc(8 * C.nstore);
-    C.invD64 = (double*)dmalloc(8 * C.nstore);
+    try {
+        for (int k = 0; k < 27; ++k)
+            if (!sym || k >= 13) C.coef64[k] = (double*)dmalloc(8 * C.nstore);
+        C.invD64 = (double*)dmalloc(8 * C.nstore);
+    } catch (...) {
+        free_coarse(C);
+        throw;
+    }
     return C;
 }
 
@@ -564,6 +601,14 @@ static void validate_options(const saamg_options& o) {
         throw ApiError{SAAMG_INVALID_ARG, "coarse_solver must be SAAMG_COARSE_DIRECT or _GS"};
     if (o.coarse_sweeps < 1 || o.coarse_sweeps > 100)
         throw ApiError{SAAMG_INVALID_ARG, "coarse_sweeps must be in 1..100"};
+    // the march loads one mask word per plane of a block and its two halo planes into
+    // the lanes of a wavefront, so a block holds at most 32 planes
+    if (o.l0_planes != 0 && (o.l0_planes < 2 || o.l0_planes > 32 || (o.l0_planes & (o.l0_planes - 1))))
+        throw ApiError{SAAMG_INVALID_ARG, "l0_planes must be 0 or a power of two in 2..32"};
+    if (o.l0_tile_x != 0 && o.l0_tile_x != 1 && o.l0_tile_x != 2 && o.l0_tile_x != 4)
+        throw ApiError{SAAMG_INVALID_ARG, "l0_tile_x must be 0, 1, 2 or 4"};
+    if ((o.alloc == nullptr) != (o.free == nullptr))
+        throw ApiError{SAAMG_INVALID_ARG, "alloc and free must both be set or both be NULL"};
 }
 
 // Host-side checks of a domain and its near-wall rows: wall fractions below 1 (the
@@ -691,15 +736,18 @@ struct DeviceDomain {
             nwidx = (int32_t*)dmalloc(4 * nbox);
             nwnodes = (int64_t*)dmalloc(8 * std::max<size_t>(D.nw_nodes.size(), 1));
             nwfrac = (double*)dmalloc(8 * std::max<size_t>(D.nw_frac.size(), 1));
-            HIPCHECK(hipMemcpy(mask, dom->mask, nbox, hipMemcpyHostToDevice));
-            HIPCHECK(hipMemset(nwidx, 0xff, 4 * nbox));
+            // uploads and the fill are queued on s, ordered before the kernels that read
+            // them; the host arrays outlive the setup's next synchronisation of s
+            HIPCHECK(hipMemcpyAsync(mask, dom->mask, nbox, hipMemcpyHostToDevice, s));
+            HIPCHECK(hipMemsetAsync(nwidx, 0xff, 4 * nbox, s));
             if (!D.nw_nodes.empty()) {
-                HIPCHECK(hipMemcpy(nwnodes, D.nw_nodes.data(), 8 * D.nw_nodes.size(),
-                                   hipMemcpyHostToDevice));
-                HIPCHECK(hipMemcpy(nwfrac, D.nw_frac.data(), 8 * D.nw_frac.size(),
-                                   hipMemcpyHostToDevice));
+                HIPCHECK(hipMemcpyAsync(nwnodes, D.nw_nodes.data(), 8 * D.nw_nodes.size(),
+                                        hipMemcpyHostToDevice, s));
+                HIPCHECK(hipMemcpyAsync(nwfrac, D.nw_frac.data(), 8 * D.nw_frac.size(),
+                                        hipMemcpyHostToDevice, s));
             }
             l0_scatter_nwidx(nwidx, nwnodes, (long)D.nw_nodes.size(), s);
+            HIPCHECK(hipStreamSynchronize(s));
         } catch (...) {
             release();
             throw;
@@ -755,14 +803,19 @@ static int64_t galerkin(saamg_hierarchy* H, int l, CoarseLevel& C, double omega,
         rap_from_lc(H->lc[l - 1], C, omega, s);
     const long nb = (C.nstore + 255) / 256;
     int32_t* cnt = (int32_t*)dmalloc(4 * 4 * nb);
-    lc_finish(C, cnt, s);
-    lc_compress(C, s);
-    int64_t* tot = (int64_t*)dmalloc(8);
-    exclusive_scan(cnt, nullptr, 4 * nb, tot, s);
     int64_t nc = 0;
-    HIPCHECK(hipMemcpyAsync(&nc, tot, 8, hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    dfree(tot);
+    try {
+        lc_finish(C, cnt, s);
+        lc_compress(C, s);
+        Tmp tot(8);
+        exclusive_scan(cnt, nullptr, 4 * nb, tot.as<int64_t>(), s);
+        HIPCHECK(hipMemcpyAsync(&nc, tot.p, 8, hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        dfree(cnt);
+        throw;
+    }
     if (cnt_out)
         *cnt_out = cnt;
     else
@@ -783,7 +836,7 @@ static void build_coarse_solver(saamg_hierarchy* H, hipStream_t s) {
     const long nstore = (H->n_levels == 1) ? H->l0.nbox : H->lc.back().nstore;
     int32_t* cmap = (int32_t*)dmalloc(4 * nstore);
     try {
-        HIPCHECK(hipMemset(cmap, 0xff, 4 * nstore));
+        HIPCHECK(hipMemsetAsync(cmap, 0xff, 4 * nstore, s));
         fill_cmap(cmap, H->cidx, nL, s);
         if (!H->Ainv) {
             H->Ainv = (double*)dmalloc(8L * nL * nL);
@@ -832,6 +885,9 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
     const long nxy = (long)nx * ny, nbox = nxy * nz;
 
     saamg_hierarchy* H = new saamg_hierarchy();
+    H->mem.alloc = o.alloc;
+    H->mem.free = o.free;
+    H->mem.ctx = o.alloc_ctx;
     try {
         HIPCHECK(hipGetDevice(&H->device));
         H->variant = variant;
@@ -845,7 +901,10 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
         L.nxy = nxy;
         L.nbox = nbox;
         L.nseg = seg_count(nx, ny, nz);
-        L.zb = l0_choose_zb(L.nsegx, ny, nz);
+        if (o.l0_tile_x > L.nsegx)
+            throw ApiError{SAAMG_INVALID_ARG, "l0_tile_x exceeds the 64-node segments of a line"};
+        L.tx = o.l0_tile_x ? o.l0_tile_x : l0_tile_x(L.nsegx);
+        L.zb = o.l0_planes ? o.l0_planes : l0_choose_zb(L.tx, L.nsegx, ny, nz);
         L.unk = (uint64_t*)dmalloc(8 * L.nseg);
         L.irr = (uint64_t*)dmalloc(8 * L.nseg);
         L.base = (int32_t*)dmalloc(4 * L.nseg);
@@ -853,16 +912,15 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
 
         // segment masks of unknowns and irregular rows, table slots
         DeviceDomain dd(dom, D, nbox, s);
-        int32_t* cnt_irr = (int32_t*)dmalloc(4 * L.nseg);
-        int32_t* cnt_unk = (int32_t*)dmalloc(4 * L.nseg);
-        int64_t* d_tot = (int64_t*)dmalloc(16);
-        l0_build_masks(L, dd.mask, dd.nwidx, cnt_irr, cnt_unk, s);
-        exclusive_scan(cnt_irr, L.base, L.nseg, d_tot, s);
-        exclusive_scan(cnt_unk, nullptr, L.nseg, d_tot + 1, s);
         int64_t tots[2];
-        HIPCHECK(hipMemcpyAsync(tots, d_tot, 16, hipMemcpyDeviceToHost, s));
-        HIPCHECK(hipStreamSynchronize(s));
-        for (void* p : {(void*)cnt_irr, (void*)cnt_unk, (void*)d_tot}) dfree(p);
+        {
+            Tmp cnt_irr(4 * L.nseg), cnt_unk(4 * L.nseg), d_tot(16);
+            l0_build_masks(L, dd.mask, dd.nwidx, cnt_irr.as<int32_t>(), cnt_unk.as<int32_t>(), s);
+            exclusive_scan(cnt_irr.as<int32_t>(), L.base, L.nseg, d_tot.as<int64_t>(), s);
+            exclusive_scan(cnt_unk.as<int32_t>(), nullptr, L.nseg, d_tot.as<int64_t>() + 1, s);
+            HIPCHECK(hipMemcpyAsync(tots, d_tot.p, 16, hipMemcpyDeviceToHost, s));
+            HIPCHECK(hipStreamSynchronize(s));
+        }
         L.n_irr = tots[0];
         L.n_unknowns = tots[1];
         if (L.n_unknowns != D.n_unk) throw ApiError{SAAMG_HIP_ERROR, "unknown count mismatch"};
@@ -889,6 +947,8 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
                 throw;
             }
             if (nc >= n_cur) {
+                // the aggregates no longer reduce the unknowns: the level built last is
+                // the coarsest (as the oracle's setup does)
                 dfree(cnt);
                 free_coarse(C);
                 break;
@@ -921,6 +981,19 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
             H->nL = (int)L.n_unknowns;
             H->cidx = (long*)dmalloc(8 * H->nL);
             l0_unknown_list(L, H->cidx, s);
+        } else if (!H->cidx) {
+            // coarsening stopped on a level that was not marked coarsest when it was built
+            CoarseLevel& C = H->lc.back();
+            if (C.n_unknowns > 8000)
+                throw ApiError{SAAMG_INVALID_ARG,
+                               "coarsening stalled above 8000 unknowns; the coarsest level is too "
+                               "large for a direct solve"};
+            const long nb = (C.nstore + 255) / 256;
+            Tmp cnt(4 * 4 * nb);
+            lc_finish(C, cnt.as<int32_t>(), s);  // recomputes 1/diag (same values) and the counts
+            H->nL = (int)C.n_unknowns;
+            H->cidx = (long*)dmalloc(8 * H->nL);
+            lc_unknown_list(C, H->cidx, cnt.as<int32_t>(), s);
         }
         // Gauss-Seidel coarse solves need a coarse level to run on
         if (o.coarse_solver == SAAMG_COARSE_GS && H->n_levels == 1)
@@ -1151,6 +1224,11 @@ void saamg_default_options(saamg_options* o) {
     o->omega_scale = 4.0 / 3.0;
     o->coarse_solver = SAAMG_COARSE_DIRECT;
     o->coarse_sweeps = 3;
+    o->l0_planes = 0;
+    o->l0_tile_x = 0;
+    o->alloc = nullptr;
+    o->free = nullptr;
+    o->alloc_ctx = nullptr;
 }
 
 int saamg_setup(const saamg_domain* dom, int variant, const saamg_options* opt, void* stream,
@@ -1158,6 +1236,13 @@ int saamg_setup(const saamg_domain* dom, int variant, const saamg_options* opt, 
     return guarded([&] {
         if (!out) throw ApiError{SAAMG_INVALID_ARG, "out is NULL"};
         *out = nullptr;
+        MemCtx m;
+        if (opt) {
+            m.alloc = opt->alloc;
+            m.free = opt->free;
+            m.ctx = opt->alloc_ctx;
+        }
+        MemScope ms(m, (hipStream_t)stream);
         *out = setup_impl(dom, variant, opt, (hipStream_t)stream);
         return (int)SAAMG_OK;
     });
@@ -1167,6 +1252,7 @@ int saamg_refresh(saamg_hierarchy* H, const saamg_domain* dom, void* stream) {
     return guarded([&] {
         if (!H) throw ApiError{SAAMG_INVALID_ARG, "hierarchy is NULL"};
         HIPCHECK(hipSetDevice(H->device));
+        MemScope ms(H->mem, (hipStream_t)stream);
         refresh_impl(H, dom, (hipStream_t)stream);
         return (int)SAAMG_OK;
     });
@@ -1174,13 +1260,14 @@ int saamg_refresh(saamg_hierarchy* H, const saamg_domain* dom, void* stream) {
 
 int saamg_destroy(saamg_hierarchy* H) {
     if (!H) return SAAMG_OK;
+    // no queued work uses H any more (solves return complete, states are destroyed first)
+    MemScope ms(H->mem, nullptr);
     FineLevel& L = H->l0;
     for (void* p : {(void*)L.unk, (void*)L.irr, (void*)L.base, (void*)L.tab64, (void*)L.tab32,
                     (void*)L.sigma, (void*)H->Ainv, (void*)H->cidx})
         dfree(p);
     for (auto& C : H->lc) free_coarse(C);
     if (H->ws) {
-        (void)hipStreamSynchronize(H->ws->s);
         state_release(H->ws);
         delete H->ws;
     }
@@ -1237,6 +1324,7 @@ int saamg_solve(saamg_hierarchy* H, const double* d_b, const double* d_x0, doubl
         if (!(tol > 0) || max_iter < 0) throw ApiError{SAAMG_INVALID_ARG, "tol > 0, max_iter >= 0"};
         HIPCHECK(hipSetDevice(H->device));
         auto t0 = std::chrono::steady_clock::now();
+        MemScope ms(H->mem, (hipStream_t)stream);
         saamg_state& S = *workspace(H);
         S.s = (hipStream_t)stream;
         S.tol = tol;
@@ -1248,6 +1336,7 @@ int saamg_solve(saamg_hierarchy* H, const double* d_b, const double* d_x0, doubl
         }
         cg_unscale(H->l0, S.x, d_x, S.s);
         HIPCHECK(hipStreamSynchronize(S.s));
+        S.s = nullptr;  // the caller's stream is not kept beyond the call
         S.t_ms = ms_since(t0);
         state_fill_result(&S, res);
         return S.status;
@@ -1288,6 +1377,7 @@ int saamg_state_create(saamg_hierarchy* H, const double* d_b, const double* d_x0
         if (!H || !d_b || !out) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
         if (!(tol > 0) || max_iter < 0) throw ApiError{SAAMG_INVALID_ARG, "tol > 0, max_iter >= 0"};
         HIPCHECK(hipSetDevice(H->device));
+        MemScope ms(H->mem, (hipStream_t)stream);
         S = new saamg_state();
         S->s = (hipStream_t)stream;
         S->tol = tol;
@@ -1299,6 +1389,8 @@ int saamg_state_create(saamg_hierarchy* H, const double* d_b, const double* d_x0
         return (int)SAAMG_OK;
     });
     if (rc != SAAMG_OK && S) {
+        MemScope ms(H->mem, S->s);
+        (void)hipStreamSynchronize(S->s);
         state_release(S);
         delete S;
         if (out) *out = nullptr;
@@ -1356,6 +1448,7 @@ int saamg_state_destroy(saamg_state* S) {
     if (!S) return SAAMG_OK;
     (void)hipStreamSynchronize(S->s);
     if (S->H) S->H->live_states -= 1;
+    MemScope ms(S->H ? S->H->mem : MemCtx{}, S->s);
     state_release(S);
     delete S;
     return SAAMG_OK;
@@ -1372,6 +1465,7 @@ int saamg_level_apply(saamg_hierarchy* H, int level, int op, int precision, cons
         if (precision == SAAMG_MIXED && H->opt.precision != SAAMG_MIXED)
             throw ApiError{SAAMG_INVALID_ARG, "fp32 data exist only for a MIXED hierarchy"};
         HIPCHECK(hipSetDevice(H->device));
+        MemScope ms(H->mem, nullptr);
         if (precision == SAAMG_MIXED)
             level_apply_impl<float>(H, level, op, h_in, h_out);
         else
@@ -1385,6 +1479,7 @@ int saamg_level_coefficients(saamg_hierarchy* H, int level, double* h_out) {
         if (!H || !h_out) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
         if (level < 0 || level >= H->n_levels) throw ApiError{SAAMG_INVALID_ARG, "bad level"};
         HIPCHECK(hipSetDevice(H->device));
+        MemScope ms(H->mem, nullptr);
         int mx, my, mz;
         level_dims(H, level, &mx, &my, &mz);
         const long nlog = (long)mx * my * mz;
@@ -1421,6 +1516,7 @@ int saamg_precond_apply(saamg_hierarchy* H, const double* d_r, double* d_z, void
     return guarded([&] {
         if (!H || !d_r || !d_z) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
         HIPCHECK(hipSetDevice(H->device));
+        MemScope ms(H->mem, (hipStream_t)stream);
         saamg_state& S = *workspace(H);
         S.s = (hipStream_t)stream;
         // the residual buffer must stay zero off the unknowns: copy via the scaled mask
@@ -1431,6 +1527,7 @@ int saamg_precond_apply(saamg_hierarchy* H, const double* d_r, double* d_z, void
         else
             HIPCHECK(hipMemcpyAsync(d_z, S.z, 8 * H->l0.nbox, hipMemcpyDeviceToDevice, S.s));
         HIPCHECK(hipStreamSynchronize(S.s));
+        S.s = nullptr;
         return (int)SAAMG_OK;
     });
 }
@@ -1476,6 +1573,7 @@ int saamg_pic_create(const saamg_grid* g, const uint8_t* mask, int64_t max_parti
         const long ncell = (long)(g->nx - 1) * (g->ny - 1) * (nzl - 1);
         if (ncell >= 4000000000L) throw ApiError{SAAMG_INVALID_ARG, "too many lattice cells"};
         const long nbox = (long)g->nx * g->ny * g->nz;
+        MemScope ms(MemCtx{}, nullptr);
         saamg_pic* P = new saamg_pic();
         try {
             HIPCHECK(hipGetDevice(&P->device));
@@ -1501,6 +1599,9 @@ int saamg_pic_create(const saamg_grid* g, const uint8_t* mask, int64_t max_parti
             P->cend = (int32_t*)dmalloc(4 * ncell);
             P->tmp_bytes = pic_sort_bytes(c, P->key_bits);
             P->tmp = dmalloc(std::max<size_t>(P->tmp_bytes, 16));
+            // the fills and the mask upload ran on the null stream: complete them before
+            // any stream of the caller uses the context
+            HIPCHECK(hipDeviceSynchronize());
         } catch (...) {
             saamg_pic_destroy(P);
             throw;
@@ -1536,6 +1637,7 @@ int saamg_pic_gather(saamg_pic* P, const double* d_phi, const double* d_pos, int
 int saamg_pic_destroy(saamg_pic* P) {
     return guarded([&] {
         if (!P) return (int)SAAMG_OK;
+        MemScope ms(MemCtx{}, nullptr);
         for (void* p : {(void*)P->mask, (void*)P->key, (void*)P->key_s, (void*)P->idx,
                         (void*)P->idx_s, (void*)P->cstart, (void*)P->cend, P->tmp})
             if (p) dfree(p);

@@ -36,9 +36,8 @@ class ServeConfig:
     tol: float = 1e-8
     max_iter: int = 500
     cache_hierarchies: bool = True
-    # threads building hierarchies (engines with concurrent_setup); GpuEngine runs one
-    # setup at a time, so more workers only overlap their host-side domain construction
-    setup_workers: int = 1
+    # threads building hierarchies (engines with concurrent_setup), each on its own stream
+    setup_workers: int = 2
 
 
 @dataclasses.dataclass
@@ -72,10 +71,6 @@ class GpuEngine:
         self.keep = keep_solutions
         self._streams: List[Any] = []
         self._tls = threading.local()  # one setup stream per worker thread
-        # one setup at a time: with two or three hierarchies built at once beside the
-        # stepping, some served solves ended without converging (cause not found), so
-        # setups are serialized whatever the number of workers
-        self._setup_lock = threading.Lock()
 
     def key(self, w) -> Tuple:
         s = w.shape
@@ -86,10 +81,6 @@ class GpuEngine:
 
     def setup(self, w, precision: int):
         dom = capi.domain_for(w.shape, w.nx, w.ny, w.nz)
-        with self._setup_lock:
-            return self._setup_locked(w, precision, dom)
-
-    def _setup_locked(self, w, precision: int, dom):
         st = getattr(self._tls, "stream", None)
         if st is None:
             st = self._tls.stream = self.torch.cuda.Stream(device=self.dev)  # default priority

@@ -33,7 +33,8 @@ def test_served_results_equal_alone():
     reqs = _stream()
     rhs = {r.rid: W.rhs(r.workload) for r in reqs}
     eng = serve.GpuEngine(keep_solutions=True)
-    srv = serve.Server(serve.ServeConfig(max_active=6, precision=sa.MIXED), eng)
+    # three hierarchies built at once on worker threads beside the stepping
+    srv = serve.Server(serve.ServeConfig(max_active=6, precision=sa.MIXED, setup_workers=3), eng)
     recs = {r.rid: r for r in srv.run(reqs, rhs_of=lambda q: rhs[q.rid])}
     srv.close()
     print(serve.summarize(list(recs.values())), "max concurrent", srv.max_concurrent, flush=True)
