@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timers", action="store_true",
                     help="time without per-kernel HIP events (roofline omitted)")
-    ap.add_argument("--cpu-sample-planes", type=int, default=48)
+    ap.add_argument("--cpu-sample-planes", type=int, default=160)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     ap.add_argument("--skip-fp64", action="store_true")
@@ -249,6 +249,7 @@ def serve_bench(args, n_requests=None) -> dict:
         return summ
 
     closed = run("closed-loop mixed", [0.0] * len(reqs), sa.MIXED)
+    out["closed_loop_fp64"] = run("closed-loop fp64", [0.0] * len(reqs), sa.FP64)
     qps = args.serve_load * closed["solves_per_s"]
     gaps = np.random.default_rng(4).exponential(1.0 / qps, size=len(reqs))
     arr = list(np.cumsum(gaps) - gaps[0])
@@ -289,6 +290,36 @@ def measured_traffic(kernel: str, workload: str):
         return None
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def oracle_check(w, solutions: dict) -> dict:
+    """Each GPU solution against the oracle: the scaled true residual D^-1/2 (b - A x) that
+    the oracle's own operator gives on every row (matrix-free, fp64), relative to ||b~||;
+    the stopping rule asks for <= tol.  The oracle cannot solve this size in a bench."""
+    import workloads as W
+    from oracle import grid, operator
+
+    t0 = time.perf_counter()
+    dom = grid.from_shape(w.shape, w.nx, w.ny, w.nz)
+    b = W.rhs(w)
+    out = {}
+    for tag, x in solutions.items():
+        r, bn = operator.scaled_residual(dom, w.variant, x, b)
+        out[tag] = float(np.linalg.norm(r) / bn)
+    out["rows"] = int(dom.n_unknowns)
+    out["check_s"] = time.perf_counter() - t0
+    return out
+
+
 def cpu_baseline(w, planes: int) -> dict:
     """The oracle, single-threaded, on a z-slab of the same pipe cross-section and spacing."""
     from threadpoolctl import threadpool_limits
@@ -319,7 +350,7 @@ def cpu_baseline(w, planes: int) -> dict:
         "setup_s": t1 - t0,
         "solve_s": t2 - t1,
         "iterations": res.iterations,
-        "host_cpu": platform.processor() or platform.machine(),
+        "host_cpu": _cpu_model(),
         "host_threads": os.cpu_count(),
     }
 
@@ -426,7 +457,8 @@ def main():
                                    f"(cylinder/ellipse/box-with-bore, edge 32..160, ratio 1..4), "
                                    f"Poisson arrivals at {res['qps']:.2f}/s"},
             "p50_latency_ms": m["p50_latency_ms"], "p99_latency_ms": m["p99_latency_ms"],
-            "fp64": f, "closed_loop_mixed": res["closed_loop_mixed"], "open_loop_mixed": m,
+            "fp64": f, "closed_loop_mixed": res["closed_loop_mixed"],
+            "closed_loop_fp64": res["closed_loop_fp64"], "open_loop_mixed": m,
         }), flush=True)
         return
 
@@ -589,7 +621,8 @@ def main():
         sv = serve_bench(args, n_requests=args.line_serve_requests)
         m, f = sv["open_loop_mixed"], sv["open_loop_fp64"]
         keep = ("requests", "completed", "solves_per_s", "p50_latency_ms", "p99_latency_ms",
-                "mean_iterations", "max_concurrent")
+                "mean_iterations", "max_concurrent", "cache_hits", "warm_starts",
+                "mean_iterations_warm", "mean_iterations_cold")
         line["p50_latency_ms"] = m["p50_latency_ms"]
         line["p99_latency_ms"] = m["p99_latency_ms"]
         line["serving"] = {
@@ -597,10 +630,19 @@ def main():
                         f"box-with-bore, edge 32..160, ratio 1..4, linear rule), Poisson "
                         f"arrivals at {sv['qps']:.2f}/s = {args.serve_load} x closed-loop capacity",
             "closed_loop_mixed_solves_per_s": sv["closed_loop_mixed"]["solves_per_s"],
+            "closed_loop_fp64_solves_per_s": sv["closed_loop_fp64"]["solves_per_s"],
             "mixed": {k: m[k] for k in keep}, "fp64": {k: f[k] for k in keep}}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_planes)
+        print("[bench] oracle residual of the GPU solutions ...", file=sys.stderr, flush=True)
+        sols = {tag: out[tag]["x"].cpu().numpy() for tag in out}
+        chk = oracle_check(w, sols)
+        line["oracle_rel_res_true"] = {
+            **{tag: chk[tag] for tag in sols},
+            "definition": "||D^-1/2 (b - A x)|| / ||D^-1/2 b|| of each GPU solution with the "
+                          "oracle's operator, over all rows (the stopping rule's quantity)",
+            "rows": chk["rows"], "check_s": round(chk["check_s"], 1)}
     print(json.dumps(line), flush=True)
 
 

@@ -147,6 +147,8 @@ typedef struct {
     int64_t device_bytes;                 /* device memory held by the hierarchy */
     double t_setup_ms;
     double t_refresh_ms;                  /* last saamg_refresh (host wall time), 0 if none */
+    int32_t l0_planes;                    /* level-0 launch shape in use: planes per block, */
+    int32_t l0_tile_x;                    /* 64-node segments per block along x            */
 } saamg_info;
 
 typedef struct saamg_hierarchy saamg_hierarchy;
@@ -269,6 +271,16 @@ int saamg_state_create(saamg_hierarchy* H, const double* d_b, const double* d_x0
                        int max_iter, void* stream, saamg_state** out);
 /* n states; *n_done_out (nullable) receives how many are finished after the step. */
 int saamg_batch_step(saamg_state* const* states, int n, int* n_done_out);
+/*
+ * The same step machine without waiting: every unfinished state whose step has completed
+ * on the device is taken through its host-side test (and finished, or given its next
+ * step), and every unfinished state with no step queued gets one.  Returns at once, so a
+ * caller that polls it lets each state advance at its own pace: a small solve is never
+ * held back by a large one in the same batch.  The host-side test can still wait briefly
+ * where it recomputes a true residual (at convergence).  *n_done_out: finished states;
+ * *n_stepped_out: states that completed a step in this call (both nullable).
+ */
+int saamg_batch_advance(saamg_state* const* states, int n, int* n_done_out, int* n_stepped_out);
 /* done = 1 when the state has finished (any status); res as for saamg_solve. */
 int saamg_state_query(const saamg_state* S, int* done, saamg_result* res);
 /* Write the (unscaled) current iterate to the device box vector d_x on the state's

@@ -6,9 +6,9 @@ small serving loop built on the incremental-solve entry points.
 """
 from . import capi  # noqa: F401
 from .capi import (  # noqa: F401
-    COARSE_DIRECT, COARSE_GS, FP64, MIXED, VARIANT_CONST, VARIANT_LIN, VARIANT_QUAD, SaamgError, batch_step,
-    default_options, destroy, domain_for, domain_from_shape, footprint_bytes, hierarchy_info,
-    level_apply, level_coefficients, operator_apply, pic_create, pic_deposit, pic_destroy,
-    pic_gather, precond_apply, refresh, scaling, setup, solve,
-    state_create, state_destroy, state_finish, state_query,
+    COARSE_DIRECT, COARSE_GS, FP64, MIXED, VARIANT_CONST, VARIANT_LIN, VARIANT_QUAD, HostDomain,
+    SaamgError, TorchAllocator, batch_advance, batch_step, default_options, destroy, domain_for,
+    domain_from_shape, footprint_bytes, hierarchy_info, level_apply, level_coefficients,
+    operator_apply, pic_create, pic_deposit, pic_destroy, pic_gather, precond_apply, refresh,
+    scaling, setup, solve, state_create, state_destroy, state_finish, state_query,
 )

@@ -71,7 +71,8 @@ class Info(C.Structure):
                 ("n_unknowns", C.c_int64 * MAX_LEVELS),
                 ("lambda_est", C.c_double * MAX_LEVELS), ("omega", C.c_double * MAX_LEVELS),
                 ("n_irregular", C.c_int64), ("device_bytes", C.c_int64),
-                ("t_setup_ms", C.c_double), ("t_refresh_ms", C.c_double)]
+                ("t_setup_ms", C.c_double), ("t_refresh_ms", C.c_double),
+                ("l0_planes", C.c_int32), ("l0_tile_x", C.c_int32)]
 
 
 class SaamgError(RuntimeError):
@@ -112,6 +113,8 @@ def lib() -> C.CDLL:
                                         C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.saamg_state_create.argtypes = [_P, _P, _P, C.c_double, C.c_int, _P, C.POINTER(_P)]
     L.saamg_batch_step.argtypes = [C.POINTER(_P), C.c_int, C.POINTER(C.c_int)]
+    L.saamg_batch_advance.argtypes = [C.POINTER(_P), C.c_int, C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int)]
     L.saamg_state_query.argtypes = [_P, C.POINTER(C.c_int), C.POINTER(Result)]
     L.saamg_state_finish.argtypes = [_P, _P]
     L.saamg_state_destroy.argtypes = [_P]
@@ -147,14 +150,17 @@ class TorchAllocator:
         self.n_free = 0
         self.outstanding = {}  # ptr -> bytes
         self._lock = threading.Lock()
+        self._torch = None
         self.alloc_fn = ALLOC_FN(self._alloc)
         self.free_fn = FREE_FN(self._free)
 
     def _alloc(self, ctx, nbytes, stream):
         try:
-            import torch
-            p = torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
-                                                   int(stream or 0))
+            if self._torch is None:
+                import torch
+                self._torch = torch
+            cuda = self._torch.cuda
+            p = cuda.caching_allocator_alloc(int(nbytes), cuda.current_device(), int(stream or 0))
         except Exception:
             return None  # reported by the library as SAAMG_NOMEM
         with self._lock:
@@ -163,11 +169,13 @@ class TorchAllocator:
         return p
 
     def _free(self, ctx, ptr, stream):
-        import torch
         with self._lock:
             self.n_free += 1
             self.outstanding.pop(ptr, None)
-        torch.cuda.caching_allocator_delete(ptr)
+        try:
+            self._torch.cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass  # interpreter shutdown: the process's memory goes with it
 
     @property
     def outstanding_bytes(self) -> int:
@@ -361,6 +369,7 @@ def hierarchy_info(H: Hierarchy) -> dict:
         "omega": [info.omega[l] for l in range(n)],
         "n_irregular": info.n_irregular, "device_bytes": info.device_bytes,
         "t_setup_ms": info.t_setup_ms, "t_refresh_ms": info.t_refresh_ms,
+        "l0_planes": info.l0_planes, "l0_tile_x": info.l0_tile_x,
     }
 
 
@@ -396,6 +405,14 @@ def batch_step(states: Sequence[State]) -> int:
     nd = C.c_int(0)
     _check(lib().saamg_batch_step(arr, len(states), C.byref(nd)))
     return nd.value
+
+
+def batch_advance(states: Sequence[State]) -> Tuple[int, int]:
+    """saamg_batch_advance: (finished states, states that completed a step); never waits."""
+    arr = (_P * max(len(states), 1))(*[s.handle for s in states])
+    nd, ns = C.c_int(0), C.c_int(0)
+    _check(lib().saamg_batch_advance(arr, len(states), C.byref(nd), C.byref(ns)))
+    return nd.value, ns.value
 
 
 def state_query(S: State) -> Tuple[bool, dict]:

@@ -247,6 +247,7 @@ struct saamg_state {
     double* hscal = nullptr;  // pinned
     hipEvent_t ev = nullptr;
     int iter = 0, status = SAAMG_OK, done = 0, repl = 0;
+    bool inflight = false;  // a step is queued whose scalars the host has not read yet
     double bnorm = 0, rel_true = 0, rel_rec = 0;
     double t_ms = 0;
     std::chrono::steady_clock::time_point t0;
@@ -380,6 +381,7 @@ static void state_enqueue(saamg_state* S) {
     HIPCHECK(hipMemcpyAsync(S->hscal, S->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
                             S->s));
     HIPCHECK(hipEventRecord(S->ev, S->s));
+    S->inflight = true;
     precond(S);
     finalize(S->part, nb, 1, S->scal, FIN_RHO, 0, S->s);
 }
@@ -393,6 +395,7 @@ static void flush_x(saamg_state* S) {
 
 static void state_complete(saamg_state* S) {
     HIPCHECK(hipEventSynchronize(S->ev));
+    S->inflight = false;
     S->iter += 1;
     const double pq = S->hscal[S_PQ], rho = S->hscal[S_RHO], rr = S->hscal[S_RR];
     const double alpha = S->hscal[S_ALPHA];
@@ -1298,6 +1301,8 @@ int saamg_hierarchy_info(const saamg_hierarchy* H, saamg_info* info) {
         info->device_bytes = H->bytes;
         info->t_setup_ms = H->t_setup_ms;
         info->t_refresh_ms = H->t_refresh_ms;
+        info->l0_planes = H->l0.zb;
+        info->l0_tile_x = H->l0.tx;
         return (int)SAAMG_OK;
     });
 }
@@ -1403,12 +1408,13 @@ int saamg_batch_step(saamg_state* const* states, int n, int* n_done_out) {
         if (n < 0 || (n > 0 && !states)) throw ApiError{SAAMG_INVALID_ARG, "bad state list"};
         for (int i = 0; i < n; ++i)
             if (!states[i]) throw ApiError{SAAMG_INVALID_ARG, "NULL state"};
-        // queue every unfinished state's step on its own stream, then collect
+        // queue every unfinished state's step on its own stream (a step that
+        // saamg_batch_advance queued is already on its way), then collect
         std::vector<saamg_state*> live;
         for (int i = 0; i < n; ++i)
             if (!states[i]->done) {
                 auto t0 = std::chrono::steady_clock::now();
-                state_enqueue(states[i]);
+                if (!states[i]->inflight) state_enqueue(states[i]);
                 states[i]->t_ms += ms_since(t0);
                 live.push_back(states[i]);
             }
@@ -1420,6 +1426,34 @@ int saamg_batch_step(saamg_state* const* states, int n, int* n_done_out) {
         int nd = 0;
         for (int i = 0; i < n; ++i) nd += states[i]->done;
         if (n_done_out) *n_done_out = nd;
+        return (int)SAAMG_OK;
+    });
+}
+
+int saamg_batch_advance(saamg_state* const* states, int n, int* n_done_out, int* n_stepped_out) {
+    return guarded([&] {
+        if (n < 0 || (n > 0 && !states)) throw ApiError{SAAMG_INVALID_ARG, "bad state list"};
+        for (int i = 0; i < n; ++i)
+            if (!states[i]) throw ApiError{SAAMG_INVALID_ARG, "NULL state"};
+        int stepped = 0;
+        for (int i = 0; i < n; ++i) {
+            saamg_state* S = states[i];
+            if (S->done) continue;
+            auto t0 = std::chrono::steady_clock::now();
+            if (S->inflight) {
+                const hipError_t e = hipEventQuery(S->ev);
+                if (e == hipErrorNotReady) continue;
+                HIPCHECK(e);
+                state_complete(S);  // the event has fired: no wait
+                stepped += 1;
+            }
+            if (!S->done) state_enqueue(S);
+            S->t_ms += ms_since(t0);
+        }
+        int nd = 0;
+        for (int i = 0; i < n; ++i) nd += states[i]->done;
+        if (n_done_out) *n_done_out = nd;
+        if (n_stepped_out) *n_stepped_out = stepped;
         return (int)SAAMG_OK;
     });
 }

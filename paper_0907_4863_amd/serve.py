@@ -3,10 +3,12 @@
 Requests (a pipe geometry, a lattice, a right-hand side) arrive over time.  The loop
 admits a request as soon as a slot is free and its device footprint fits the HBM budget,
 reuses hierarchies cached per geometry (the paper's reuse of the preconditioner across
-solves, Section 5, ML variations), and advances every admitted solve by one PCG step per
-round through ``saamg_batch_step``.  Each active solve owns a stream, so the rounds of
-different requests overlap on the device; finished solves retire at once and free their
-memory for queued requests.  Latency is completion minus arrival.
+solves, Section 5, ML variations), keeps the last solution of each cached geometry on the
+device and starts the next request of that geometry from it (the warm start of Section 4),
+and advances the admitted solves through ``saamg_batch_advance``, which never waits: each
+solve owns a stream and steps at its own pace, so a small solve is not held back by a large
+one.  Finished solves retire at once and free their memory for queued requests.  Latency
+is completion minus arrival.
 
 The device work goes through an engine object (``GpuEngine`` below) so that the
 scheduling logic can be exercised without a GPU.  An engine whose ``concurrent_setup`` is
@@ -38,6 +40,11 @@ class ServeConfig:
     cache_hierarchies: bool = True
     # threads building hierarchies (engines with concurrent_setup), each on its own stream
     setup_workers: int = 2
+    # keep the last solution of each cached geometry resident and start the next request
+    # of that geometry from it (counted in the budget, evicted with the hierarchy)
+    warm_start: bool = True
+    # host wait between polls when no solve completed a step
+    poll_s: float = 50e-6
 
 
 @dataclasses.dataclass
@@ -51,6 +58,7 @@ class Record:
     rel_res: float = float("nan")
     setup_ms: float = 0.0
     cache_hit: bool = False
+    warm_from: int = -1       # rid of the solution this request started from (-1: x0 = 0)
     dof: int = 0
     x: Any = None
 
@@ -98,31 +106,48 @@ class GpuEngine:
             return self._streams.pop()
         return self.torch.cuda.Stream(device=self.dev)  # default priority
 
-    def start(self, H, b_host: np.ndarray, tol: float, max_iter: int):
+    def warm_bytes(self, w) -> int:
+        """Device bytes of a resident solution of workload w."""
+        return 8 * w.nx * w.ny * w.nz
+
+    def start(self, H, b_host: np.ndarray, tol: float, max_iter: int, x0=None):
+        """Queue a solve on a stream of its own: the upload of b, the initial residual and
+        the first preconditioner are ordered on that stream (no device-wide wait)."""
         torch = self.torch
-        b = torch.from_numpy(np.ascontiguousarray(b_host, dtype=np.float64).reshape(-1)).to(self.dev)
-        torch.cuda.synchronize(self.dev)  # the upload is complete before another stream reads b
         st = self._stream()
-        S = capi.state_create(H, b, tol=tol, max_iter=max_iter, stream=st.cuda_stream)
+        with torch.cuda.stream(st):
+            b = torch.from_numpy(np.ascontiguousarray(b_host, dtype=np.float64).reshape(-1)).to(self.dev)
+        if x0 is not None:
+            x0.record_stream(st)  # a resident solution read on this stream
+        S = capi.state_create(H, b, x0=x0, tol=tol, max_iter=max_iter, stream=st.cuda_stream)
         return {"S": S, "b": b, "stream": st, "H": H}
 
-    def step(self, handles: Sequence[dict]) -> None:
-        capi.batch_step([h["S"] for h in handles])
+    def step(self, handles: Sequence[dict]) -> int:
+        """Advance without waiting; returns how many solves completed a step."""
+        return capi.batch_advance([h["S"] for h in handles])[1]
 
     def query(self, h) -> Tuple[bool, dict]:
         return capi.state_query(h["S"])
 
-    def finish(self, h):
-        x = None
-        if self.keep:
-            x = self.torch.zeros(h["b"].numel(), dtype=self.torch.float64, device=self.dev)
-            self.torch.cuda.synchronize(self.dev)  # the fill is done before the state's stream writes x
-            capi.state_finish(h["S"], x)
-            self.torch.cuda.synchronize(self.dev)  # the finish ran on the state's stream
-            x = x.cpu().numpy()
+    def finish(self, h, keep_warm: bool = False):
+        """Retire a solve: (host copy of x or None, device x kept for a warm start or None)."""
+        torch = self.torch
+        x_host = x_dev = None
+        if self.keep or keep_warm:
+            st = h["stream"]
+            with torch.cuda.stream(st):
+                x = torch.empty(h["b"].numel(), dtype=torch.float64, device=self.dev)
+            capi.state_finish(h["S"], x)  # writes every entry on st and waits for it
+            if self.keep:
+                x_host = x.cpu().numpy()
+            if keep_warm:
+                x_dev = x
         capi.state_destroy(h["S"])
         self._streams.append(h["stream"])
-        return x
+        return x_host, x_dev
+
+    def release_warm(self, x) -> None:
+        pass  # a torch tensor: its memory returns to the caching allocator when dropped
 
 
 class Server:
@@ -132,7 +157,8 @@ class Server:
         self.eng = engine
         self.clock = clock
         self.sleep = sleep
-        self.cache: "OrderedDict[Tuple, dict]" = OrderedDict()  # key -> {H, bytes, refs, dof}
+        # key -> {H, bytes, refs, dof, warm: (device x, rid) or None, warm_bytes}
+        self.cache: "OrderedDict[Tuple, dict]" = OrderedDict()
         self.used = 0
         self.peak_used = 0
         self.max_concurrent = 0
@@ -146,9 +172,40 @@ class Server:
                 return
             e = self.cache[key]
             if e["refs"] == 0:
-                self.eng.release_hierarchy(e["H"])
-                self.used -= e["bytes"]
-                del self.cache[key]
+                self._drop(key)
+
+    def _drop(self, key) -> None:
+        """Release a cached geometry: its hierarchy and its resident solution."""
+        e = self.cache.pop(key)
+        self._set_warm(e, None)
+        self.eng.release_hierarchy(e["H"])
+        self.used -= e["bytes"]
+
+    def _set_warm(self, e: dict, warm) -> None:
+        """Replace the resident solution of a cache entry (None: drop it)."""
+        if e.get("warm") is not None:
+            self.eng.release_warm(e["warm"][0])
+            self.used -= e["warm_bytes"]
+        e["warm"] = None
+        if warm is not None and self.used + e["warm_bytes"] <= self.cfg.hbm_budget_bytes:
+            e["warm"] = warm
+            self.used += e["warm_bytes"]
+            self.peak_used = max(self.peak_used, self.used)
+        elif warm is not None:
+            self.eng.release_warm(warm[0])
+
+    def _new_entry(self, w, H, hbytes: int, dof: int) -> dict:
+        wb = self.eng.warm_bytes(w) if hasattr(self.eng, "warm_bytes") else 0
+        return {"H": H, "bytes": hbytes, "refs": 0, "dof": dof, "warm": None, "warm_bytes": wb}
+
+    def _start(self, e: dict, rec: Record, rhs: np.ndarray):
+        """Start a request on a cached hierarchy, from its resident solution if any."""
+        x0 = None
+        if self.cfg.warm_start and e.get("warm") is not None:
+            x0, rec.warm_from = e["warm"]
+        if x0 is None:
+            return self.eng.start(e["H"], rhs, self.cfg.tol, self.cfg.max_iter)
+        return self.eng.start(e["H"], rhs, self.cfg.tol, self.cfg.max_iter, x0=x0)
 
     def _timed_setup(self, w):
         t0 = self.clock()
@@ -177,19 +234,19 @@ class Server:
             rec.cache_hit = True
             e["refs"] += 1
             rec.dof = e["dof"]
-            h = self.eng.start(e["H"], rhs, self.cfg.tol, self.cfg.max_iter)
+            h = self._start(e, rec, rhs)
             return {"rec": rec, "h": h, "key": key, "state_bytes": state_bytes}
         if new_build:
             building[key] = {"fut": pool.submit(self._timed_setup, w), "est": hier_est}
         return {"rec": rec, "key": key, "state_bytes": state_bytes, "rhs": rhs,
-                "build": building[key], "builder": new_build}
+                "build": building[key], "builder": new_build, "rec_w": w}
 
     def _start_pending(self, p: dict, building: dict) -> dict:
         """Start a pending request whose hierarchy is built."""
         key, rec = p["key"], p["rec"]
         if key not in self.cache:  # the first request served by this build
             (H, hbytes, dof), setup_ms = p["build"]["fut"].result()
-            self.cache[key] = {"H": H, "bytes": hbytes, "refs": 0, "dof": dof}
+            self.cache[key] = self._new_entry(p["rec_w"], H, hbytes, dof)
             self.used += hbytes - p["build"]["est"]
             self.peak_used = max(self.peak_used, self.used)
             building.pop(key, None)
@@ -198,7 +255,7 @@ class Server:
         e = self.cache[key]
         e["refs"] += 1
         rec.dof = e["dof"]
-        h = self.eng.start(e["H"], p["rhs"], self.cfg.tol, self.cfg.max_iter)
+        h = self._start(e, rec, p["rhs"])
         return {"rec": rec, "h": h, "key": key, "state_bytes": p["state_bytes"]}
 
     def _admit(self, req, rhs: np.ndarray, now: float, active: List[dict]) -> Optional[dict]:
@@ -220,12 +277,12 @@ class Server:
             t0 = self.clock()
             H, hbytes, dof = self.eng.setup(w, self.cfg.precision)
             rec.setup_ms = 1e3 * (self.clock() - t0)
-            e = {"H": H, "bytes": hbytes, "refs": 0, "dof": dof}
+            e = self._new_entry(w, H, hbytes, dof)
             self.cache[key] = e
             self.used += hbytes
         e["refs"] += 1
         rec.dof = e["dof"]
-        h = self.eng.start(e["H"], rhs, self.cfg.tol, self.cfg.max_iter)
+        h = self._start(e, rec, rhs)
         self.used += state_bytes
         self.peak_used = max(self.peak_used, self.used)
         return {"rec": rec, "h": h, "key": key, "state_bytes": state_bytes}
@@ -237,14 +294,15 @@ class Server:
         rec.iterations = res["iterations"]
         rec.status = res["status"]
         rec.rel_res = res["rel_res_true"]
-        rec.x = self.eng.finish(a["h"])
+        keep_warm = (self.cfg.warm_start and self.cfg.cache_hierarchies and rec.status == capi.OK)
+        rec.x, x_dev = self.eng.finish(a["h"], keep_warm)
         self.used -= a["state_bytes"]
         e = self.cache[a["key"]]
         e["refs"] -= 1
+        if x_dev is not None:
+            self._set_warm(e, (x_dev, rec.rid))
         if not self.cfg.cache_hierarchies and e["refs"] == 0:
-            self.eng.release_hierarchy(e["H"])
-            self.used -= e["bytes"]
-            del self.cache[a["key"]]
+            self._drop(a["key"])
         return rec
 
     # -------------------------------------------------------------- main loop
@@ -285,14 +343,18 @@ class Server:
         return out
 
     def _round(self, active: List[dict], out: List[Record], t0: float) -> None:
-        """One PCG step of every active solve; finished ones retire (marked "done")."""
-        self.eng.step([a["h"] for a in active])
+        """Advance the active solves (an engine step that returns 0 made no progress: the
+        device is still busy, so the loop yields briefly); finished ones retire (marked
+        "done")."""
+        stepped = self.eng.step([a["h"] for a in active])
         self.rounds += 1
         for a in active:
             done, _ = self.eng.query(a["h"])
             if done:
                 out.append(self._retire(a, self.clock() - t0))
                 a["done"] = True
+        if stepped == 0:
+            self.sleep(self.cfg.poll_s)
 
     def _run_async(self, requests: Sequence, rhs_of: Callable[[Any], np.ndarray],
                    pool) -> List[Record]:
@@ -342,9 +404,8 @@ class Server:
         return out
 
     def close(self) -> None:
-        for e in self.cache.values():
-            self.eng.release_hierarchy(e["H"])
-        self.cache.clear()
+        for key in list(self.cache.keys()):
+            self._drop(key)
         self.used = 0
 
 
@@ -364,5 +425,10 @@ def summarize(records: Sequence[Record]) -> Dict[str, float]:
         "mean_iterations": float(np.mean([r.iterations for r in ok])) if ok else float("nan"),
         "dof_iter_per_s": sum(r.dof * r.iterations for r in ok) / span,
         "cache_hits": sum(1 for r in ok if r.cache_hit),
+        "warm_starts": sum(1 for r in ok if r.warm_from >= 0),
+        "mean_iterations_warm": (float(np.mean([r.iterations for r in ok if r.warm_from >= 0]))
+                                 if any(r.warm_from >= 0 for r in ok) else float("nan")),
+        "mean_iterations_cold": (float(np.mean([r.iterations for r in ok if r.warm_from < 0]))
+                                 if any(r.warm_from < 0 for r in ok) else float("nan")),
         "max_rel_res": float(max((r.rel_res for r in ok), default=float("nan"))),
     }

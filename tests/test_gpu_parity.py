@@ -6,9 +6,12 @@ Tolerances:
   of bounded size);
 * fp64 PCG solution: 1e-8 relative to the oracle's solution of the same algorithm, and
   the same iteration count +-1;
-* mixed precision (fp32 hierarchy and V-cycle): components 1e-4 relative (fp32 unit
-  roundoff 6e-8 times the operator's condition growth over a few chained products),
+* mixed precision (fp32 hierarchy and V-cycle): single products and transfers 2e-5,
+  the two-step smoother and the V-cycle 1e-4 (fp32 unit roundoff 6e-8 times a few dozen
+  bounded terms per output, carried through a few chained products and every level),
   full solve 1e-6 relative to the oracle's solution driven to 1e-13.
+
+Component checks are element by element: max |got - want| over max |want|.
 """
 import numpy as np
 import pytest
@@ -87,6 +90,11 @@ def rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
+def emax(a, b):
+    """Element-wise error: max |a - b| over max |b|."""
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
 def oracle_coef(lv):
     mx, my, mz = lv.dims
     c = amg.coarse_box_coords(lv)
@@ -140,7 +148,9 @@ def test_scaling_vector():
 @pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
 def test_level_operations(name, precision):
     c = case(name, precision)
-    tol = 1e-12 if precision == W.PREC_FP64 else 1e-4
+    fp64 = precision == W.PREC_FP64
+    tol = 1e-12 if fp64 else 2e-5
+    tol_smooth = 1e-12 if fp64 else 1e-4
     rng = np.random.default_rng(11)
     nl = len(c.H.levels)
     for l in range(nl):
@@ -150,18 +160,18 @@ def test_level_operations(name, precision):
         xb = c.lv_box(l, x)
         for op, want in ((sa.capi.OP_APPLY, lv.A @ x), (sa.capi.OP_APPLY_T, lv.A.T @ x)):
             got = c.lv_vec(l, sa.level_apply(c.G, l, op, xb, (mz, my, mx), precision))
-            assert rel(got, want) <= tol, (name, l, op)
+            assert emax(got, want) <= tol, (name, l, op, emax(got, want))
         if l == nl - 1:
             continue
         got = c.lv_vec(l, sa.level_apply(c.G, l, sa.capi.OP_PRESMOOTH, xb, (mz, my, mx), precision))
         want = amg.chebyshev(lv, x, None, c.H.opts.cheb_degree, c.H.opts.cheb_ratio)
-        assert rel(got, want) <= tol, (name, l, "presmooth")
+        assert emax(got, want) <= tol_smooth, (name, l, "presmooth", emax(got, want))
         nx_, ny_, nz_ = c.H.levels[l + 1].dims
         got = c.lv_vec(l + 1, sa.level_apply(c.G, l, sa.capi.OP_RESTRICT, xb, (nz_, ny_, nx_), precision))
-        assert rel(got, lv.P.T @ x) <= tol, (name, l, "restrict")
+        assert emax(got, lv.P.T @ x) <= tol, (name, l, "restrict", emax(got, lv.P.T @ x))
         v = rng.uniform(-1, 1, c.H.levels[l + 1].n)
         got = c.lv_vec(l, sa.level_apply(c.G, l, sa.capi.OP_PROLONG, c.lv_box(l + 1, v), (mz, my, mx), precision))
-        assert rel(got, lv.P @ v) <= tol, (name, l, "prolong")
+        assert emax(got, lv.P @ v) <= tol, (name, l, "prolong", emax(got, lv.P @ v))
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -174,7 +184,8 @@ def test_vcycle(name, precision):
     sa.precond_apply(c.G, c.to_dev(r), z)
     got = c.sys.gather(z.cpu().numpy())
     tol = 1e-11 if precision == W.PREC_FP64 else 1e-4
-    assert rel(got, want) <= tol
+    print(f"[{name}] vcycle emax={emax(got, want):.2e}", flush=True)
+    assert emax(got, want) <= tol
 
 
 def test_operator_apply_device():

@@ -32,6 +32,8 @@ class FakeEngine:
         self.live_states = 0
         self.max_live = 0
         self.setups = 0
+        self.starts = []
+        self.warm_live = 0
 
     def key(self, w):
         return (w.shape.kind, w.nx, w.ny, w.nz)
@@ -50,10 +52,13 @@ class FakeEngine:
     def release_hierarchy(self, H):
         del self.hier[id(H)]
 
-    def start(self, H, b, tol, max_iter):
+    def start(self, H, b, tol, max_iter, x0=None):
         self.live_states += 1
         self.max_live = max(self.max_live, self.live_states)
-        return {"left": int(b), "it": 0}
+        self.starts.append(x0)
+        # a warm start saves one round
+        left = max(int(b) - (1 if x0 is not None else 0), 1)
+        return {"left": left, "it": 0}
 
     def step(self, hs):
         self.clock.t += self.round_s
@@ -65,9 +70,18 @@ class FakeEngine:
     def query(self, h):
         return h["left"] == 0, {"iterations": h["it"], "status": 0, "rel_res_true": 1e-9}
 
-    def finish(self, h):
+    def finish(self, h, keep_warm=False):
         self.live_states -= 1
-        return None
+        if keep_warm:
+            self.warm_live += 1
+            return None, ("x", id(h))
+        return None, None
+
+    def warm_bytes(self, w):
+        return 8 * w.nx * w.ny * w.nz
+
+    def release_warm(self, x):
+        self.warm_live -= 1
 
 
 @dataclasses.dataclass
@@ -176,7 +190,8 @@ def test_worker_setup_serves_every_request_once_per_geometry():
     iterations, one build per geometry (requests of a geometry whose build is running wait
     on it), the budget holds, and all memory but the cached hierarchies is returned."""
     reqs = [_req(i, 0.0, 10 + i % 3, 4 + i % 5) for i in range(12)]
-    srv, eng, recs, main = _serve_threaded(reqs, hbm_budget_bytes=1 << 40, max_active=5)
+    srv, eng, recs, main = _serve_threaded(reqs, hbm_budget_bytes=1 << 40, max_active=5,
+                                           warm_start=False)
     assert len(recs) == 12 and all(r.status == 0 for r in recs.values())
     for r in reqs:
         assert recs[r.rid].iterations == r.rounds
@@ -195,3 +210,36 @@ def test_worker_setup_respects_budget_and_rejects_oversized():
     assert all(recs[i].status == 0 for i in range(6))
     assert srv.peak_used <= 2 * per + 10 and eng.max_live <= 2
     assert srv.used == 0 and not srv.cache
+
+
+def test_repeat_geometry_starts_from_the_resident_solution():
+    """Section 4's warm start in the server: the second and third requests of a geometry
+    start from the solution of the one before; other geometries start from zero."""
+    reqs = [_req(0, 0.0, 20, 5), _req(1, 1.0, 20, 5), _req(2, 2.0, 24, 5), _req(3, 3.0, 20, 5)]
+    srv, eng, recs = _serve(reqs, hbm_budget_bytes=10 ** 9)
+    assert [recs[i].warm_from for i in range(4)] == [-1, 0, -1, 1]
+    assert recs[1].iterations == recs[0].iterations - 1
+    assert summarize(list(recs.values()))["warm_starts"] == 2
+    srv.close()
+    assert eng.warm_live == 0 and srv.used == 0
+
+
+def test_resident_solutions_count_in_the_budget_and_go_with_eviction():
+    reqs = [_req(0, 0.0, 20, 3), _req(1, 1.0, 30, 3), _req(2, 2.0, 20, 3)]
+    n20, n30 = 20 ** 3, 30 ** 3
+    # room for the 30^3 geometry's hierarchy and state, but not beside the 20^3 one's
+    # hierarchy and resident solution
+    budget = 10 * n30 + 60 * n30 + 1000
+    assert budget < 10 * n20 + 8 * n20 + 10 * n30 + 60 * n30
+    srv, eng, recs = _serve(reqs, hbm_budget_bytes=budget)
+    assert all(r.status == 0 for r in recs.values())
+    assert recs[2].warm_from == -1  # geometry 20 was evicted for geometry 30
+    assert srv.peak_used <= budget
+    srv.close()
+    assert eng.warm_live == 0
+
+
+def test_warm_start_off():
+    reqs = [_req(0, 0.0, 20, 5), _req(1, 1.0, 20, 5)]
+    srv, eng, recs = _serve(reqs, warm_start=False)
+    assert recs[1].warm_from == -1 and eng.starts == [None, None] and eng.warm_live == 0

@@ -315,3 +315,70 @@ def random_box_vector(dims: Tuple[int, int, int], seed: int) -> np.ndarray:
     """Seeded uniform(-1, 1) vector on the full box, (nz, ny, nx) fp64."""
     nx, ny, nz = dims
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(nz, ny, nx))
+
+
+# ------------------------------------------------------------------ hand-made domains
+#
+# Discrete domains given directly as a mask and wall fractions (the saamg_domain input),
+# for the method's edge cases that no pipe on the configurations' lattices produces.
+
+DIRS = ((-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1))
+
+
+@dataclasses.dataclass
+class MaskDomain:
+    dims: Tuple[int, int, int]           # (nx, ny, nz)
+    h: Tuple[float, float, float]
+    mask: np.ndarray                     # (nz, ny, nx) bool
+    wall_node: np.ndarray                # box-linear index of an unknown
+    wall_dir: np.ndarray                 # 0..5 = -x, +x, -y, +y, -z, +z
+    wall_s: np.ndarray                   # fraction in (0, 1)
+
+
+def _wall_entries(mask: np.ndarray, rng: np.random.Generator, lo: float, keep: float):
+    """A seeded fraction in [lo, 1) for about ``keep`` of the (unknown, direction) pairs
+    whose neighbour is not an unknown; the other pairs get no entry (fraction 1)."""
+    nz, ny, nx = mask.shape
+    ks, js, is_ = np.nonzero(mask)
+    lin = is_ + nx * (js + ny * ks)
+    nodes, dirs, fr = [], [], []
+    for d, (dx, dy, dz) in enumerate(DIRS):
+        sel = np.nonzero(~mask[ks + dz, js + dy, is_ + dx])[0]
+        s = rng.uniform(lo, 1.0, sel.size)
+        k = rng.uniform(size=sel.size) < keep
+        nodes.append(lin[sel][k])
+        dirs.append(np.full(int(k.sum()), d, dtype=np.uint8))
+        fr.append(s[k])
+    order = np.lexsort((np.concatenate(dirs), np.concatenate(nodes)))
+    return (np.concatenate(nodes)[order].astype(np.int64), np.concatenate(dirs)[order],
+            np.concatenate(fr)[order])
+
+
+def thin_lines_domain(seed: int = 12) -> MaskDomain:
+    """A box cavity, one-node-wide lines along x, y and z, and two isolated nodes, with
+    seeded wall fractions: every node of a line has both neighbours outside on the two
+    axes across it (and an isolated node on all three)."""
+    nx, ny, nz = 30, 28, 26
+    m = np.zeros((nz, ny, nx), dtype=bool)
+    m[3:12, 3:13, 3:14] = True      # cavity
+    m[8, 18, 3:25] = True           # x-line at z = 8, y = 18
+    m[17, 3:24, 20] = True          # y-line at z = 17, x = 20
+    m[3:23, 22, 8] = True           # z-line at y = 22, x = 8
+    m[20, 10, 14] = True            # isolated nodes
+    m[22, 5, 25] = True
+    node, d, s = _wall_entries(m, np.random.default_rng(seed), 0.05, 0.875)
+    return MaskDomain((nx, ny, nz), (0.05, 0.06, 0.07), m, node, d, s)
+
+
+def cluster_domain() -> MaskDomain:
+    """27 separate 3^3 clusters of unknowns, at aggregate blocks 1, 4 and 7 of each axis:
+    the first coarsening gives one isolated node per cluster, which no further
+    aggregation reduces.  Wall fractions 1 (no entries)."""
+    n = 26
+    m = np.zeros((n, n, n), dtype=bool)
+    for bz in (1, 4, 7):
+        for by in (1, 4, 7):
+            for bx in (1, 4, 7):
+                m[3 * bz:3 * bz + 3, 3 * by:3 * by + 3, 3 * bx:3 * bx + 3] = True
+    e = np.zeros(0, dtype=np.int64)
+    return MaskDomain((n, n, n), (0.1, 0.1, 0.1), m, e, e.astype(np.uint8), e.astype(np.float64))
