@@ -230,6 +230,23 @@ int saamg_solve(saamg_hierarchy* H, const double* d_b, const double* d_x0, doubl
                 double tol, int max_iter, void* stream, saamg_result* res);
 
 /*
+ * saamg_solve for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same solve, the same
+ * kernels in the same order and the same results, with every work vector (PCG vectors,
+ * the V-cycle's vectors on all levels, block partials, scalars) carved out of a static
+ * 64 MiB device array inside the library instead of allocated.  No hipMalloc, hipFree,
+ * pinned host allocation, event creation or allocator callback happens in the call; the
+ * work vectors are zero-filled by a kernel on `stream` first.  Arguments, results and
+ * errors as for saamg_solve, plus SAAMG_INVALID_ARG (nothing queued) when the hierarchy
+ * needs more than 64 MiB of work space (about a million box nodes in mixed precision;
+ * saamg_solve has no such limit).  All calls on one device share that device's array:
+ * calls that overlap on one device (other threads or streams) race and must be
+ * serialised by the caller.  Each device keeps its array until the process ends.
+ */
+int saamg_solve_noalloc(saamg_hierarchy* H, const double* d_b, const double* d_x0, double* d_x,
+                        double tol, int max_iter, void* stream, saamg_result* res);
+
+/*
  * Numeric-only re-setup reusing the aggregation hierarchy (Section 5.2, reuse of the
  * aggregation hierarchy; Table 6 times it): keeps H's aggregates (the tentative
  * prolongators), storage and buffers, and recomputes every number from dom: level-0

@@ -103,6 +103,8 @@ def lib() -> C.CDLL:
     L.saamg_setup.argtypes = [C.POINTER(Domain), C.c_int, C.POINTER(Options), _P, C.POINTER(_P)]
     L.saamg_refresh.argtypes = [_P, C.POINTER(Domain), _P]
     L.saamg_solve.argtypes = [_P, _P, _P, _P, C.c_double, C.c_int, _P, C.POINTER(Result)]
+    L.saamg_solve_noalloc.argtypes = [_P, _P, _P, _P, C.c_double, C.c_int, _P,
+                                      C.POINTER(Result)]
     L.saamg_pic_create.argtypes = [C.POINTER(Grid), C.POINTER(C.c_uint8), C.c_int64, C.POINTER(_P)]
     L.saamg_pic_deposit.argtypes = [_P, _P, C.c_int64, C.c_double, _P, _P]
     L.saamg_pic_gather.argtypes = [_P, _P, _P, C.c_int64, _P, _P]
@@ -352,6 +354,19 @@ def solve(H: Hierarchy, b, x, x0=None, tol: float = 1e-8, max_iter: int = 500,
     res = Result()
     rc = lib().saamg_solve(H.handle, _dptr(b, H.nbox), None if x0 is None else _dptr(x0, H.nbox),
                            _dptr(x, H.nbox), tol, max_iter, _stream(stream), C.byref(res))
+    allowed = (OK,) if raise_on_failure else (OK, NOT_CONVERGED, BREAKDOWN, NONFINITE)
+    _check(rc, allowed)
+    return res.as_dict()
+
+
+def solve_noalloc(H: Hierarchy, b, x, x0=None, tol: float = 1e-8, max_iter: int = 500,
+                  stream=None, raise_on_failure: bool = False) -> dict:
+    """saamg_solve_noalloc: saamg_solve with its work vectors in the library's static
+    scratch array (no device allocation during the call)."""
+    res = Result()
+    rc = lib().saamg_solve_noalloc(H.handle, _dptr(b, H.nbox),
+                                   None if x0 is None else _dptr(x0, H.nbox), _dptr(x, H.nbox),
+                                   tol, max_iter, _stream(stream), C.byref(res))
     allowed = (OK,) if raise_on_failure else (OK, NOT_CONVERGED, BREAKDOWN, NONFINITE)
     _check(rc, allowed)
     return res.as_dict()

@@ -148,6 +148,7 @@ struct MemCtx {
     void (*free)(void*, void*, void*) = nullptr;
     void* ctx = nullptr;
     hipStream_t s = nullptr;
+    bool fill = true;  // zero-fill new buffers (off only for a pass that measures sizes)
 };
 // Makes (m, s) the allocator and fill stream of dmalloc / dfree on the calling thread for
 // the scope's lifetime.

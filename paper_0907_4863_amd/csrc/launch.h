@@ -47,6 +47,9 @@ long lc_blocks(const CoarseLevel& C);
 void finalize(const double* partials, long nblk, int nq, double* scal, int op, int dst,
               hipStream_t s);
 
+// Zero `bytes` bytes at p with a kernel on stream s (no memset node, any alignment).
+void zero_fill(void* p, size_t bytes, hipStream_t s);
+
 // ---- level 0: build
 void l0_scatter_nwidx(int32_t* nwidx, const int64_t* nodes, long n, hipStream_t s);
 void l0_build_masks(FineLevel& L, const uint8_t* mask, const int32_t* nwidx, int32_t* cnt_irr,

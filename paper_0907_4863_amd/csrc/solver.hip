@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -34,8 +35,29 @@ MemScope::MemScope(const MemCtx& m, hipStream_t s) : saved(g_mem) {
 }
 MemScope::~MemScope() { g_mem = saved; }
 
+__global__ void k_zero_fill(char* __restrict__ p, size_t bytes) {
+    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    // bytes before the first 16-byte boundary, the 16-byte body, and the tail
+    const size_t head = (16 - ((uintptr_t)p & 15)) & 15;
+    const size_t h = head < bytes ? head : bytes;
+    const size_t n16 = (bytes - h) / 16;
+    if (t < n16) ((uint4*)(p + h))[t] = make_uint4(0u, 0u, 0u, 0u);
+    if (t < h) p[t] = 0;
+    const size_t tail0 = h + 16 * n16;
+    if (t < bytes - tail0) p[tail0 + t] = 0;
+}
+
+void zero_fill(void* p, size_t bytes, hipStream_t s) {
+    if (!p || bytes == 0) return;
+    const size_t threads = std::max<size_t>((bytes + 15) / 16, 16);
+    hipLaunchKernelGGL(k_zero_fill, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                       (char*)p, bytes);
+    HIPCHECK(hipGetLastError());
+}
+
 // New buffers are zero-filled on the entry point's stream, in stream order with the work
-// that follows (a null-stream fill would not be ordered with a non-blocking stream).
+// that follows (a null-stream fill would not be ordered with a non-blocking stream).  The
+// fill is a kernel, not a memset, so that no memset node enters a captured graph.
 void* dmalloc(size_t bytes) {
     void* p = nullptr;
     if (bytes == 0) bytes = 8;
@@ -51,10 +73,13 @@ void* dmalloc(size_t bytes) {
             throw ApiError{SAAMG_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
         }
     }
-    hipError_t e = hipMemsetAsync(p, 0, bytes, g_mem.s);
-    if (e != hipSuccess) {
-        dfree(p);
-        throw HipError{e, "hipMemsetAsync (zero fill of a new buffer)"};
+    if (g_mem.fill) {
+        try {
+            zero_fill(p, bytes, g_mem.s);
+        } catch (...) {
+            dfree(p);
+            throw;
+        }
     }
     return p;
 }
@@ -244,8 +269,9 @@ struct saamg_state {
     double* part = nullptr;
     long npart = 0;
     double* scal = nullptr;
-    double* hscal = nullptr;  // pinned
-    hipEvent_t ev = nullptr;
+    double* hscal = nullptr;  // pinned, or hbuf for a state that allocates nothing on the host
+    double hbuf[S_NSLOTS] = {};
+    hipEvent_t ev = nullptr;  // null: the host waits on the stream instead
     int iter = 0, status = SAAMG_OK, done = 0, repl = 0;
     bool inflight = false;  // a step is queued whose scalars the host has not read yet
     double bnorm = 0, rel_true = 0, rel_rec = 0;
@@ -256,7 +282,9 @@ struct saamg_state {
 
 namespace saamg {
 
-static void state_alloc(saamg_state* S, saamg_hierarchy* H) {
+// pinned = false: no pinned host buffer and no event (the allocation-free solve); the
+// scalars are read into the state itself and the host waits on the stream.
+static void state_alloc(saamg_state* S, saamg_hierarchy* H, bool pinned = true) {
     S->H = H;
     S->mixed = H->opt.precision == SAAMG_MIXED;
     const long n = H->l0.nbox;
@@ -278,6 +306,10 @@ static void state_alloc(saamg_state* S, saamg_hierarchy* H) {
     S->npart = std::max<long>(l0_blocks(H->l0), 1);
     S->part = (double*)dmalloc(sizeof(double) * 3 * S->npart);
     S->scal = (double*)dmalloc(sizeof(double) * S_NSLOTS);
+    if (!pinned) {
+        S->hscal = S->hbuf;
+        return;
+    }
     HIPCHECK(hipHostMalloc((void**)&S->hscal, sizeof(double) * S_NSLOTS, hipHostMallocDefault));
     HIPCHECK(hipEventCreateWithFlags(&S->ev, hipEventDisableTiming));
 }
@@ -291,7 +323,7 @@ static void state_release(saamg_state* S) {
     S->vd.release();
     dfree(S->part);
     dfree(S->scal);
-    if (S->hscal) (void)hipHostFree(S->hscal);
+    if (S->hscal && S->hscal != S->hbuf) (void)hipHostFree(S->hscal);
     if (S->ev) (void)hipEventDestroy(S->ev);
     S->x = S->r = S->p = S->q = S->bs = nullptr;
     S->z = nullptr;
@@ -335,8 +367,8 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
     cg_init(H->l0, b, x0, S->bs, S->x, S->s);
     cg_resid(H->l0, S->bs, S->x, S->r, S->part, S->r32, S->s);
     finalize(S->part, l0_blocks(H->l0), 2, S->scal, FIN_STORE, S_RR, S->s);
-    HIPCHECK(hipMemsetAsync(S->p, 0, 8 * H->l0.nbox, S->s));
-    HIPCHECK(hipMemsetAsync(S->q, 0, 8 * H->l0.nbox, S->s));
+    zero_fill(S->p, 8 * H->l0.nbox, S->s);
+    zero_fill(S->q, 8 * H->l0.nbox, S->s);
     read_scal(S);
     const double rr = S->hscal[S_RR], bb = S->hscal[S_BB];
     S->bnorm = std::sqrt(bb);
@@ -347,7 +379,7 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
         return;
     }
     if (bb == 0.0) {
-        HIPCHECK(hipMemsetAsync(S->x, 0, 8 * H->l0.nbox, S->s));
+        zero_fill(S->x, 8 * H->l0.nbox, S->s);
         S->done = 1;
         S->rel_true = S->rel_rec = 0.0;
         return;
@@ -380,7 +412,7 @@ static void state_enqueue(saamg_state* S) {
     finalize(S->part, nb, 1, S->scal, FIN_STORE, S_RR, S->s);
     HIPCHECK(hipMemcpyAsync(S->hscal, S->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
                             S->s));
-    HIPCHECK(hipEventRecord(S->ev, S->s));
+    if (S->ev) HIPCHECK(hipEventRecord(S->ev, S->s));
     S->inflight = true;
     precond(S);
     finalize(S->part, nb, 1, S->scal, FIN_RHO, 0, S->s);
@@ -394,7 +426,10 @@ static void flush_x(saamg_state* S) {
 }
 
 static void state_complete(saamg_state* S) {
-    HIPCHECK(hipEventSynchronize(S->ev));
+    if (S->ev)
+        HIPCHECK(hipEventSynchronize(S->ev));
+    else
+        HIPCHECK(hipStreamSynchronize(S->s));
     S->inflight = false;
     S->iter += 1;
     const double pq = S->hscal[S_PQ], rho = S->hscal[S_RHO], rr = S->hscal[S_RR];
@@ -1588,6 +1623,110 @@ int saamg_scaling(saamg_hierarchy* H, double* d_sigma, void* stream) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ solve without allocation
+//
+// The work vectors of saamg_solve_noalloc (the PCG vectors, the V-cycle's vectors on every
+// level, the block partials and the scalars) are carved out of one file-scope device
+// array.  Each device that runs the library holds its own copy until the process ends; in
+// host code `scratch` names only a host-side stand-in, so its device address is taken once
+// per device with hipGetSymbolAddress and only that address is used.
+
+namespace saamg {
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on `device`, which must be current.
+static char* scratch_base(int device) {
+    if (device < 0 || device >= kMaxDevices) throw ApiError{SAAMG_INVALID_ARG, "device index"};
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw ApiError{SAAMG_HIP_ERROR, "no device address for the scratch array"};
+        g_scratch_ptr[device] = (char*)p;
+    }
+    return g_scratch_ptr[device];
+}
+
+// Bump allocation from [base, base + cap), 256-byte aligned; nothing is returned.
+struct Bump {
+    char* base;
+    size_t cap, used;
+};
+static void* bump_alloc(void* ctx, size_t bytes, void*) {
+    Bump* b = (Bump*)ctx;
+    const size_t off = (b->used + 255) & ~size_t(255);
+    if (off > b->cap || bytes > b->cap - off) return nullptr;
+    b->used = off + bytes;
+    return b->base + off;
+}
+static void bump_free(void*, void*, void*) {}
+
+// Bytes the work vectors of one solve on H take in the scratch array: the allocation
+// sequence of a solve state, run against placeholder addresses (nothing is allocated,
+// filled or launched).
+static size_t noalloc_bytes(saamg_hierarchy* H) {
+    Bump probe{reinterpret_cast<char*>(uintptr_t(256)), ~size_t(0) >> 1, 0};
+    MemCtx m;
+    m.alloc = bump_alloc;
+    m.free = bump_free;
+    m.ctx = &probe;
+    m.fill = false;
+    MemScope ms(m, nullptr);
+    saamg_state S;
+    state_alloc(&S, H, false);
+    S.hscal = nullptr;
+    state_release(&S);
+    return probe.used;
+}
+
+}  // namespace saamg
+
+extern "C" int saamg_solve_noalloc(saamg_hierarchy* H, const double* d_b, const double* d_x0,
+                                   double* d_x, double tol, int max_iter, void* stream,
+                                   saamg_result* res) {
+    return guarded([&] {
+        if (!H || !d_b || !d_x) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        if (!(tol > 0) || max_iter < 0) throw ApiError{SAAMG_INVALID_ARG, "tol > 0, max_iter >= 0"};
+        HIPCHECK(hipSetDevice(H->device));
+        const size_t need = noalloc_bytes(H);
+        if (need > kScratchBytes)
+            throw ApiError{SAAMG_INVALID_ARG,
+                           "the solve needs " + std::to_string(need) + " bytes of work space; the "
+                           "scratch array of saamg_solve_noalloc holds " +
+                               std::to_string(kScratchBytes) + " bytes (use saamg_solve)"};
+        auto t0 = std::chrono::steady_clock::now();
+        Bump bump{scratch_base(H->device), kScratchBytes, 0};
+        MemCtx m;
+        m.alloc = bump_alloc;
+        m.free = bump_free;
+        m.ctx = &bump;
+        MemScope ms(m, (hipStream_t)stream);
+        saamg_state S;
+        S.s = (hipStream_t)stream;
+        S.tol = tol;
+        S.max_iter = max_iter;
+        state_alloc(&S, H, false);  // zero-filled by a kernel on the stream
+        state_start(&S, d_b, d_x0);
+        while (!S.done) {
+            state_enqueue(&S);
+            state_complete(&S);
+        }
+        cg_unscale(H->l0, S.x, d_x, S.s);
+        HIPCHECK(hipStreamSynchronize(S.s));
+        S.t_ms = ms_since(t0);
+        state_fill_result(&S, res);
+        S.hscal = nullptr;
+        state_release(&S);  // returns nothing: the vectors stay in the scratch array
+        return S.status;
+    });
+}
 
 // ------------------------------------------------------------------ particle coupling
 
