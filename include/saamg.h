@@ -115,9 +115,11 @@ typedef struct {
        returns memory of the current device (NULL: failure, reported as SAAMG_NOMEM) that
        may be used in stream order on `stream` (a hipStream_t; NULL = the default stream),
        and goes back through free(alloc_ctx, ptr, stream) once no queued work uses it.
-       Both NULL: hipMalloc and hipFree.  The library zero-fills new buffers on the
-       stream itself (stream-ordered, no host synchronisation).  Both callbacks may be
-       called from any thread that calls into the library with this hierarchy. */
+       Both NULL: the library's own pool (per device; new memory from hipMalloc, freed
+       blocks kept and reused once the work queued before their release has completed,
+       at most 16 GiB cached).  The library zero-fills new buffers on the stream itself
+       (stream-ordered, no host synchronisation).  Both callbacks may be called from any
+       thread that calls into the library with this hierarchy. */
     void* (*alloc)(void* alloc_ctx, size_t bytes, void* stream);
     void (*free)(void* alloc_ctx, void* ptr, void* stream);
     void* alloc_ctx;

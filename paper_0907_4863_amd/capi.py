@@ -196,10 +196,13 @@ def torch_allocator() -> TorchAllocator:
     return _torch_allocator
 
 
-def default_options(allocator="torch", **kw) -> Options:
+def default_options(allocator=None, **kw) -> Options:
     """Library defaults (Table 1 and the documented readings) with ``kw`` applied.
-    ``allocator``: "torch" (torch's caching allocator, the default), None (the library's
-    hipMalloc / hipFree) or a TorchAllocator-like object with alloc_fn / free_fn."""
+    ``allocator``: None (the library's own stream-safe device pool, the default), "torch"
+    (torch's caching allocator through Python callbacks) or a TorchAllocator-like object
+    with alloc_fn / free_fn.  The pool is the default because the callbacks take the GIL
+    on every allocation: with hierarchies built on worker threads beside a polling loop,
+    served throughput fell from 54 to 12-19 solves/s with them."""
     o = Options()
     lib().saamg_default_options(C.byref(o))
     if allocator == "torch":
@@ -327,7 +330,7 @@ class Hierarchy:
 
 def setup(dom: HostDomain, variant: int, options: Optional[Options] = None,
           stream=None) -> Hierarchy:
-    """saamg_setup; without ``options`` the defaults with torch's caching allocator."""
+    """saamg_setup; without ``options`` the library defaults."""
     h = _P()
     ds = dom.struct()
     if options is None:

@@ -9,9 +9,11 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "launch.h"
@@ -55,6 +57,114 @@ void zero_fill(void* p, size_t bytes, hipStream_t s) {
     HIPCHECK(hipGetLastError());
 }
 
+// The library's own device memory (no allocator callback): a pool per device.  A freed
+// block keeps an event recorded on the freeing stream after everything queued there, and
+// is handed out again (for a request of the same size class) only once that event has
+// completed, so a block is never reused while queued work may still touch it, whatever
+// stream the next user runs on.  New memory comes from hipMalloc; nothing is given back
+// to the device until the cached bytes exceed kPoolCap, so steady-state setups and solve
+// states make no hipMalloc and no device-synchronising hipFree.
+namespace {
+constexpr size_t kPoolCap = size_t(16) << 30;
+
+struct PoolBlock {
+    void* p;
+    hipEvent_t ev;
+};
+
+struct DevicePool {
+    std::multimap<size_t, PoolBlock> free_;     // by size class
+    std::unordered_map<void*, size_t> live_;    // block -> size class
+    std::vector<hipEvent_t> events_;            // spare events
+    size_t cached = 0;
+};
+
+std::mutex g_pool_mu;
+std::map<int, DevicePool> g_pools;
+
+// Size classes: multiples of 256 B below 64 KiB, above that the next of 2^k * {1, 5/4,
+// 3/2, 7/4} (at most 25% slack).
+size_t size_class(size_t b) {
+    if (b <= (size_t(64) << 10)) return (b + 255) & ~size_t(255);
+    size_t k = size_t(1) << (63 - __builtin_clzll(b));
+    for (size_t q : {k, k + k / 4, k + k / 2, k + 3 * k / 4, 2 * k})
+        if (q >= b) return q;
+    return 2 * k;
+}
+
+void* pool_alloc(size_t bytes) {
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    const size_t cls = size_class(bytes);
+    {
+        std::lock_guard<std::mutex> g(g_pool_mu);
+        DevicePool& P = g_pools[dev];
+        auto range = P.free_.equal_range(cls);
+        for (auto it = range.first; it != range.second; ++it) {
+            const hipError_t q = hipEventQuery(it->second.ev);
+            if (q == hipErrorNotReady) continue;
+            (void)hipGetLastError();
+            void* p = it->second.p;
+            P.events_.push_back(it->second.ev);
+            P.free_.erase(it);
+            P.cached -= cls;
+            P.live_[p] = cls;
+            return p;
+        }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, cls);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw ApiError{SAAMG_NOMEM, "hipMalloc of " + std::to_string(cls) + " bytes failed"};
+    }
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    g_pools[dev].live_[p] = cls;
+    return p;
+}
+
+void pool_free(void* p, hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::vector<void*> give_back;
+    {
+        std::lock_guard<std::mutex> g(g_pool_mu);
+        DevicePool& P = g_pools[dev];
+        auto it = P.live_.find(p);
+        if (it == P.live_.end()) {
+            (void)hipFree(p);  // not a pool block
+            return;
+        }
+        const size_t cls = it->second;
+        P.live_.erase(it);
+        hipEvent_t ev = nullptr;
+        if (!P.events_.empty()) {
+            ev = P.events_.back();
+            P.events_.pop_back();
+        } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            ev = nullptr;
+        }
+        if (!ev || hipEventRecord(ev, s) != hipSuccess) {
+            (void)hipGetLastError();
+            if (ev) P.events_.push_back(ev);
+            give_back.push_back(p);  // hipFree waits for the device itself
+        } else {
+            P.free_.insert({cls, PoolBlock{p, ev}});
+            P.cached += cls;
+            // over the cap: give back the largest cached blocks
+            while (P.cached > kPoolCap && !P.free_.empty()) {
+                auto last = std::prev(P.free_.end());
+                give_back.push_back(last->second.p);
+                P.events_.push_back(last->second.ev);
+                P.cached -= last->first;
+                P.free_.erase(last);
+            }
+        }
+    }
+    for (void* q : give_back) (void)hipFree(q);
+}
+}  // namespace
+
 // New buffers are zero-filled on the entry point's stream, in stream order with the work
 // that follows (a null-stream fill would not be ordered with a non-blocking stream).  The
 // fill is a kernel, not a memset, so that no memset node enters a captured graph.
@@ -67,11 +177,7 @@ void* dmalloc(size_t bytes) {
             throw ApiError{SAAMG_NOMEM, "the allocator returned NULL for " + std::to_string(bytes) +
                                             " bytes"};
     } else {
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            throw ApiError{SAAMG_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
-        }
+        p = pool_alloc(bytes);
     }
     if (g_mem.fill) {
         try {
@@ -91,7 +197,7 @@ void dfree(void* p) {
     if (g_mem.free)
         g_mem.free(g_mem.ctx, p, (void*)g_mem.s);
     else
-        (void)hipFree(p);
+        pool_free(p, g_mem.s);
 }
 
 ChebCoef cheb_coefficients(double lam_hi, double ratio, int degree) {

@@ -72,11 +72,12 @@ class GpuEngine:
 
     concurrent_setup = True  # setup() may run on a worker thread beside step()
 
-    def __init__(self, device: int = 0, keep_solutions: bool = False):
+    def __init__(self, device: int = 0, keep_solutions: bool = False, allocator=None):
         import torch
         self.torch = torch
         self.dev = torch.device(f"cuda:{device}")
         self.keep = keep_solutions
+        self.allocator = allocator  # saamg_options allocator (capi.default_options)
         self._streams: List[Any] = []
         self._tls = threading.local()  # one setup stream per worker thread
 
@@ -92,7 +93,8 @@ class GpuEngine:
         st = getattr(self._tls, "stream", None)
         if st is None:
             st = self._tls.stream = self.torch.cuda.Stream(device=self.dev)  # default priority
-        H = capi.setup(dom, w.variant, capi.default_options(precision=precision),
+        H = capi.setup(dom, w.variant,
+                       capi.default_options(allocator=self.allocator, precision=precision),
                        stream=st.cuda_stream)
         st.synchronize()  # complete before any state's stream uses H
         info = capi.hierarchy_info(H)

@@ -152,3 +152,26 @@ def test_warm_start_matches_oracle(precision):
         xs = sys_.gather(x_star)
         assert np.linalg.norm(sys_.gather(xg) - xs) <= 1e-6 * np.linalg.norm(xs)
     sa.destroy(G)
+
+
+def test_torch_allocator_option_gives_the_same_solution():
+    """saamg_options' allocator callbacks backed by torch's caching allocator: the same
+    hierarchy and solution bit for bit as with the library's own pool, and every buffer
+    is handed back when the hierarchy is destroyed."""
+    shape = W.Shape.ellipse(1.0, 0.6, 4.0)
+    nx, ny, nz = 70, 45, 66
+    print("[case] torch allocator option", flush=True)
+    dom = sa.domain_for(shape, nx, ny, nz)
+    b = W.rhs(W.small(shape, nx, ny, nz, W.VARIANT_QUAD))
+    al = sa.capi.TorchAllocator()
+    xs = []
+    for alloc in (None, al):
+        G = sa.setup(dom, W.VARIANT_QUAD, sa.default_options(allocator=alloc, precision=sa.MIXED))
+        x, res = gpu_solve(G, (nx, ny, nz), b)
+        assert res["status"] == 0
+        xs.append(x)
+        sa.destroy(G)
+    torch.cuda.synchronize()
+    print(f"torch allocator: {al.n_alloc} allocations, {al.n_free} frees", flush=True)
+    assert al.n_alloc > 50 and al.n_free == al.n_alloc and al.outstanding_bytes == 0
+    assert np.array_equal(xs[0], xs[1])

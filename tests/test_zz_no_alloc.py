@@ -37,8 +37,9 @@ def test_noalloc_matches_solve_large_then_small(precision):
     al = sa.capi.torch_allocator()
     for name, shape, nx, ny, nz, variant in CASES:
         print(f"[case] noalloc {name} precision={precision}", flush=True)
+        # the hierarchy's allocator is torch's, whose callbacks count: the call must not use it
         G = sa.setup(sa.domain_for(shape, nx, ny, nz), variant,
-                     sa.default_options(precision=precision))
+                     sa.default_options(allocator="torch", precision=precision))
         b = torch.from_numpy(W.rhs(W.small(shape, nx, ny, nz, variant)).reshape(-1)).to(_dev())
         xa = torch.zeros(nx * ny * nz, dtype=torch.float64, device=_dev())
         ra = sa.solve(G, b, xa, tol=1e-8)
