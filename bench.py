@@ -260,6 +260,24 @@ def serve_bench(args, n_requests=None) -> dict:
     return out
 
 
+def hbm_ceiling() -> dict:
+    """Best rates of the device's own streaming kernels (paper_0907_4863_amd/hbm_ceiling,
+    built by build(): 16-byte copy / read / write over 2 GiB, ordinary and nontemporal),
+    in GB/s, and the runtime's device-to-device copy.  Run as a child process."""
+    exe = os.path.join(ROOT, "paper_0907_4863_amd", "hbm_ceiling")
+    if not os.path.exists(exe):
+        return {}
+    res = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    best = {}
+    for ln in res.stdout.splitlines():
+        parts = ln.split()
+        if ln.startswith("blocks") and len(parts) >= 7:
+            best[parts[2]] = max(best.get(parts[2], 0.0), float(parts[5]))
+        elif ln.startswith("hipMemcpy"):
+            best["hipMemcpy_d2d"] = float(parts[4])
+    return {f"{k}_GBs": v for k, v in best.items()}
+
+
 def _kernel_sources_digest() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -463,6 +481,8 @@ def main():
         return
 
     w = W.by_name(args.workload)
+    ceiling = hbm_ceiling()
+    print(f"[bench] HBM streaming ceilings (GB/s): {ceiling}", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     if args.copy_mb:
         n = args.copy_mb * (1 << 20) // 8
@@ -555,6 +575,7 @@ def main():
             "avg_launch_us": live["avg_us"],
             "launches": live["launches"],
             "alg_bytes_per_launch": live["alg_bytes_per_launch"],
+            "measured_ceilings_GBs": ceiling,
         }
         line["kernels"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                                for kk, vv in v.items()} for k, v in kern.items()}

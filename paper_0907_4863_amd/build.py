@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsaamg.so")
 SOURCES = ["fine.hip", "coarse.hip", "solver.hip", "pic.hip", "timer.hip", "domain.cpp"]
+# hbm_ceiling.hip is a separate program (see _build_ceiling), not part of the library
 ARCH = os.environ.get("SAAMG_ARCH", "gfx950")
 
 # Packed fp32 instructions are disabled for all device code.
@@ -56,7 +57,22 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"linking libsaamg.so failed:\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, LIB)
+    _build_ceiling(verbose)
     return LIB
+
+
+CEILING = os.path.join(HERE, "hbm_ceiling")
+
+
+def _build_ceiling(verbose: bool) -> None:
+    """The standalone HBM streaming-ceiling program the benchmark runs."""
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-O3", "-x", "hip", *DEVICE_FLAGS,
+           os.path.join(CSRC, "hbm_ceiling.hip"), "-o", CEILING]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"compiling hbm_ceiling.hip failed:\n{res.stdout}\n{res.stderr}")
 
 
 if __name__ == "__main__":
