@@ -151,6 +151,12 @@ typedef struct {
     double t_refresh_ms;                  /* last saamg_refresh (host wall time), 0 if none */
     int32_t l0_planes;                    /* level-0 launch shape in use: planes per block, */
     int32_t l0_tile_x;                    /* 64-node segments per block along x            */
+    int64_t table_rows[SAAMG_MAX_LEVELS]; /* levels >= 1: stored coefficient rows of A_l    */
+    int64_t table_rows_t[SAAMG_MAX_LEVELS]; /* and of A_l^T (nonsymmetric levels)           */
+    /* host wall time of the setup's phases: domain checks (host), level-0 operator (masks,
+       table, scaling), spectral estimates, Galerkin products and their compression, the
+       coarsest-level solver, fp32 copies */
+    double t_setup_phase_ms[6];
 } saamg_info;
 
 typedef struct saamg_hierarchy saamg_hierarchy;

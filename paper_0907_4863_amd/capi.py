@@ -72,7 +72,9 @@ class Info(C.Structure):
                 ("lambda_est", C.c_double * MAX_LEVELS), ("omega", C.c_double * MAX_LEVELS),
                 ("n_irregular", C.c_int64), ("device_bytes", C.c_int64),
                 ("t_setup_ms", C.c_double), ("t_refresh_ms", C.c_double),
-                ("l0_planes", C.c_int32), ("l0_tile_x", C.c_int32)]
+                ("l0_planes", C.c_int32), ("l0_tile_x", C.c_int32),
+                ("table_rows", C.c_int64 * MAX_LEVELS), ("table_rows_t", C.c_int64 * MAX_LEVELS),
+                ("t_setup_phase_ms", C.c_double * 6)]
 
 
 class SaamgError(RuntimeError):
@@ -388,6 +390,10 @@ def hierarchy_info(H: Hierarchy) -> dict:
         "n_irregular": info.n_irregular, "device_bytes": info.device_bytes,
         "t_setup_ms": info.t_setup_ms, "t_refresh_ms": info.t_refresh_ms,
         "l0_planes": info.l0_planes, "l0_tile_x": info.l0_tile_x,
+        "table_rows": [info.table_rows[l] for l in range(n)],
+        "table_rows_t": [info.table_rows_t[l] for l in range(n)],
+        "t_setup_phase_ms": dict(zip(("host_checks", "level0", "spectral", "galerkin",
+                                      "coarse_solver", "fp32"), list(info.t_setup_phase_ms))),
     }
 
 

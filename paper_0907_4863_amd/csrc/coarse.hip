@@ -96,6 +96,7 @@ long lc_blocks(const CoarseLevel& C) {
 // One thread per node of a z-plane (flattened over x and y so that wavefronts stay full
 // on narrow coarse boxes), one block row per plane.
 #define LC_PROLOGUE                                                              \
+    if (c.skip && *c.skip != 0.0) return;                                        \
     const long t_ = blockIdx.x * (long)blockDim.x + threadIdx.x;                 \
     const bool inb = t_ < (long)c.mx * c.my;                                     \
     const int X = inb ? (int)(t_ % c.mx) : 0;                                    \
@@ -524,9 +525,14 @@ struct AccLC {
     }
 };
 
+// The 27 output arrays of a Galerkin product, passed by value with the launch.
+struct CoefOut {
+    double* p[27];
+};
+
 template <class Acc>
 __global__ void __launch_bounds__(256) k_rap(Acc acc, int fmx, int fmy, int fmz, LCView<double> cc,
-                                             double* const* __restrict__ out, double omega) {
+                                             CoefOut out, double omega) {
     __shared__ double sv[125], sw[343], sy[729];
     const int X = blockIdx.x, Y = blockIdx.y, Z = blockIdx.z;
     const int t = threadIdx.x;
@@ -607,7 +613,7 @@ __global__ void __launch_bounds__(256) k_rap(Acc acc, int fmx, int fmy, int fmz,
                 s += sy[px + 9 * py + 81 * pz];
             }
             const long row = (IX + 1) + (long)cc.sx * (IY + 1) + cc.sxy * (IZ + 1);
-            out[kprime][row] = s;
+            out.p[kprime][row] = s;
         }
     }
     (void)fmx;
@@ -615,30 +621,24 @@ __global__ void __launch_bounds__(256) k_rap(Acc acc, int fmx, int fmy, int fmz,
     (void)fmz;
 }
 
-static double** upload_ptrs(const CoarseLevel& C, hipStream_t s) {
-    double** d = (double**)dmalloc(sizeof(double*) * 27);
-    HIPCHECK(hipMemcpyAsync(d, C.coef64, sizeof(double*) * 27, hipMemcpyHostToDevice, s));
-    return d;
+static CoefOut coef_out(const CoarseLevel& C) {
+    CoefOut o;
+    for (int k = 0; k < 27; ++k) o.p[k] = C.coef64[k];
+    return o;
 }
 
 void rap_from_l0(const FineLevel& L, const CoarseLevel& C, double omega, hipStream_t s) {
     AccL0 acc{L.view<double>()};
-    double** d = upload_ptrs(C, s);
     hipLaunchKernelGGL((k_rap<AccL0>), dim3(C.mx, C.my, C.mz), dim3(256), 0, s, acc, L.nx, L.ny,
-                       L.nz, C.view<double>(), d, omega);
+                       L.nz, C.view<double>(), coef_out(C), omega);
     HIPCHECK(hipGetLastError());
-    HIPCHECK(hipStreamSynchronize(s));
-    dfree(d);
 }
 
 void rap_from_lc(const CoarseLevel& F, const CoarseLevel& C, double omega, hipStream_t s) {
     AccLC acc{F.view<double>()};
-    double** d = upload_ptrs(C, s);
     hipLaunchKernelGGL((k_rap<AccLC>), dim3(C.mx, C.my, C.mz), dim3(256), 0, s, acc, F.mx, F.my,
-                       F.mz, C.view<double>(), d, omega);
+                       F.mz, C.view<double>(), coef_out(C), omega);
     HIPCHECK(hipGetLastError());
-    HIPCHECK(hipStreamSynchronize(s));
-    dfree(d);
 }
 
 // invD = 1/diag at existing coarse nodes (diag != 0); per-block counts of unknowns.
@@ -679,24 +679,53 @@ void lc_to_fp32(CoarseLevel& C, hipStream_t s) {
 
 // Compression of a level's operator (after lc_finish).  Pass 1: slot -2 at nodes that are
 // not unknowns, -1 where the row equals the reference row `ref` bit for bit (ref < 0:
-// none does), else irregular; per-64 counts of irregular rows.  Pass 2: table slots in
-// storage order and the table rows.
+// none does), -3 where the row equals, bit for bit, the row of the node one plane below
+// (which then has a table row of its own or shares one further down), else a new table
+// row; per-64 counts of new rows.  Pass 2: table slots of the new rows in storage order,
+// and their table rows.  Pass 3: each column, walked up along z, gives its -3 nodes the
+// slot of the node below.  A pipe whose cross-section does not change along z repeats
+// almost every row from plane to plane, so the table holds a few rows per column of the
+// cross-section instead of one per node, and sweeps stream a small, cached table.
+__device__ inline bool same_bits(double a, double b) {
+    return __double_as_longlong(a) == __double_as_longlong(b);
+}
+
 __global__ void k_lc_classify(LCView<double> c, long n, long ref, int32_t* __restrict__ slot,
                               int32_t* __restrict__ cnt) {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    bool irr = false;
+    bool fresh = false;
     if (t < n) {
         int sv = -2;
         if (c.invD[t] != 0.0) {
             bool same = ref >= 0;
             for (int k = 0; k < 27 && same; ++k) same = lc_full(c, t, k) == lc_full(c, ref, k);
-            sv = same ? -1 : 0;
-            irr = !same;
+            if (same) {
+                sv = -1;
+            } else {
+                // only an unknown below (storage plane >= 1, so every access of its row,
+                // including the symmetric storage's neighbour reads, stays in the box)
+                bool below = t >= c.sxy && c.invD[t - c.sxy] != 0.0;
+                for (int k = 0; k < 27 && below; ++k)
+                    below = same_bits(lc_full(c, t, k), lc_full(c, t - c.sxy, k));
+                sv = below ? -3 : 0;
+                fresh = !below;
+            }
         }
         slot[t] = sv;
     }
-    const uint64_t bal = __ballot(irr);
+    const uint64_t bal = __ballot(fresh);
     if ((threadIdx.x & 63) == 0 && t < n) cnt[t >> 6] = __popcll(bal);
+}
+
+// Pass 3: nodes marked -3 take the slot of the node one plane below, column by column.
+__global__ void k_lc_zshare(int32_t* __restrict__ slot, int sx, int sy, int sz) {
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= (long)sx * sy) return;
+    const long sxy = (long)sx * sy;
+    for (int z = 1; z < sz; ++z) {
+        const long i = t + sxy * z;
+        if (slot[i] == -3) slot[i] = slot[i - sxy];
+    }
 }
 
 __global__ void k_lc_fill(LCView<double> c, long n, const int32_t* __restrict__ base, long cap,
@@ -713,22 +742,31 @@ __global__ void k_lc_fill(LCView<double> c, long n, const int32_t* __restrict__ 
 }
 
 // Transpose rows: slot -2 where every coupling is zero (not an unknown), -1 where the node
-// and its 26 neighbours all have the interior row, else irregular (marked 0).
+// and its 26 neighbours all have the interior row, -3 where the transposed row equals the
+// one of the node below bit for bit, else a new row (marked 0).
 __global__ void k_lc_classifyT(LCView<double> c, long n, int32_t* __restrict__ slotT,
                                int32_t* __restrict__ cnt) {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    bool irr = false;
+    bool fresh = false;
     if (t < n) {
         int sv = -2;
         if (c.invD[t] != 0.0) {
             bool reg = true;
             for (int k = 0; k < 27 && reg; ++k) reg = c.slot[t + c.off[k]] == -1;
-            sv = reg ? -1 : 0;
-            irr = !reg;
+            if (reg) {
+                sv = -1;
+            } else {
+                bool below = t >= c.sxy && c.invD[t - c.sxy] != 0.0;
+                for (int k = 0; k < 27 && below; ++k)
+                    below = same_bits(lc_full(c, t + c.off[k], 26 - k),
+                                      lc_full(c, t - c.sxy + c.off[k], 26 - k));
+                sv = below ? -3 : 0;
+                fresh = !below;
+            }
         }
         slotT[t] = sv;
     }
-    const uint64_t bal = __ballot(irr);
+    const uint64_t bal = __ballot(fresh);
     if ((threadIdx.x & 63) == 0 && t < n) cnt[t >> 6] = __popcll(bal);
 }
 
@@ -786,6 +824,8 @@ void lc_compress(CoarseLevel& C, hipStream_t s) {
         C.n_tab = nt;
         hipLaunchKernelGGL(k_lc_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n, base,
                            C.tab_cap, C.slot, C.tab64);
+        const dim3 gcol((unsigned)((C.sxy + 255) / 256));
+        hipLaunchKernelGGL(k_lc_zshare, gcol, dim3(256), 0, s, C.slot, C.sx, C.sy, C.sz);
         HIPCHECK(hipGetLastError());
         for (int k = 0; k < 27; ++k) C.cst64[k] = 0.0;
         if (ref >= 0) {
@@ -815,6 +855,7 @@ void lc_compress(CoarseLevel& C, hipStream_t s) {
             C.n_tabT = ntt;
             hipLaunchKernelGGL(k_lc_fillT, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n,
                                base, C.tabT_cap, C.slotT, C.tabT64);
+            hipLaunchKernelGGL(k_lc_zshare, gcol, dim3(256), 0, s, C.slotT, C.sx, C.sy, C.sz);
             HIPCHECK(hipGetLastError());
             HIPCHECK(hipStreamSynchronize(s));
         }
@@ -908,46 +949,130 @@ void dense_from_lc(const CoarseLevel& C, const long* cidx, const int32_t* cmap, 
     HIPCHECK(hipGetLastError());
 }
 
-// In-place Gauss-Jordan inversion without pivoting (the coarsest operator is positive
-// definite, or has a positive definite symmetric part).  Step k: scale pivot row k, then
-// eliminate column k from every other row; one block per row.
-// One Gauss-Jordan step (pivot k, no pivoting) of the in-place inversion, from src to
-// dst: the pivot row is scaled by 1/a_kk (its diagonal becomes 1/a_kk) and every other row
-// i loses a_ik times the scaled pivot row (its column k becomes -a_ik/a_kk).  Reading one
-// buffer and writing the other lets one launch do both halves of the step; the values
-// are those of the two-pass form (the scaled pivot entry is rounded before it is used).
-__global__ void k_gj_step(const double* __restrict__ src, double* __restrict__ dst, int n,
-                          int k) {
-    const int i = blockIdx.x;
-    const double piv = 1.0 / src[(long)k * n + k];
-    const double f = src[(long)i * n + k];
-    const double* rk = src + (long)k * n;
-    const double* ri = src + (long)i * n;
-    double* di = dst + (long)i * n;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const double pk = rk[j] * piv;  // scaled pivot row
-        if (i == k)
-            di[j] = (j == k) ? piv : pk;
+// In-place inversion of the coarsest operator A (row-major n x n, fp64) by Gauss-Jordan
+// elimination without pivoting (A is positive definite, or has a positive definite
+// symmetric part, so every pivot is positive), taken in blocks of kGjB pivots.  For the
+// block K = [k0, k0 + kb), with P = (A_KK)^-1:
+//   A_Kj <- P A_Kj (j outside K),  A_ij <- A_ij - A_iK A_Kj (new)  and  A_iK <- -A_iK P
+//   (i outside K),  A_KK <- P,
+// which is kb single-pivot steps applied at once.  Two launches per block: the first
+// inverts A_KK in LDS (every workgroup, the same arithmetic), forms the block row and
+// saves the old block column; the second does the rank-kb update.
+constexpr int kGjB = 32;
+
+// Unpivoted Gauss-Jordan inverse of the kb x kb matrix M in LDS, in place (256 threads).
+__device__ void lds_gj_invert(double (*M)[kGjB + 1], int kb) {
+    for (int p = 0; p < kb; ++p) {
+        __syncthreads();
+        const double piv = 1.0 / M[p][p];
+        double v[4];
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int r = e / kGjB, c = e % kGjB;
+            v[q] = 0.0;
+            if (r < kb && c < kb) {
+                const double pc = M[p][c] * piv;  // scaled pivot row (rounded before use)
+                if (r == p)
+                    v[q] = (c == p) ? piv : pc;
+                else
+                    v[q] = (c == p) ? -M[r][p] * piv : M[r][c] - M[r][p] * pc;
+            }
+        }
+        __syncthreads();
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int r = e / kGjB, c = e % kGjB;
+            if (r < kb && c < kb) M[r][c] = v[q];
+        }
+    }
+    __syncthreads();
+}
+
+// Block step, part 1.  Workgroup g: P into LDS; columns j = 256 g + t of the block row
+// (outside the block) become P A_Kj; rows i = 256 g + t (outside the block) copy their old
+// block-column entries to C (n x kGjB); workgroup 0 stores P.
+__global__ void __launch_bounds__(256) k_gjb_panel(double* __restrict__ A, int n, int k0, int kb,
+                                                   double* __restrict__ Pout,
+                                                   double* __restrict__ C) {
+    __shared__ double M[kGjB][kGjB + 1];
+    for (int e = threadIdx.x; e < kGjB * kGjB; e += 256) {
+        const int r = e / kGjB, c = e % kGjB;
+        M[r][c] = (r < kb && c < kb) ? A[(long)(k0 + r) * n + k0 + c] : 0.0;
+    }
+    lds_gj_invert(M, kb);
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < n && (t < k0 || t >= k0 + kb)) {
+        // fixed trip counts (guarded) keep old[] in registers
+        double old[kGjB];
+#pragma unroll
+        for (int c = 0; c < kGjB; ++c) old[c] = c < kb ? A[(long)(k0 + c) * n + t] : 0.0;
+        for (int r = 0; r < kb; ++r) {
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < kGjB; ++c)
+                if (c < kb) acc += M[r][c] * old[c];
+            A[(long)(k0 + r) * n + t] = acc;
+        }
+        for (int c = 0; c < kb; ++c) C[(long)t * kGjB + c] = A[(long)t * n + k0 + c];
+    }
+    if (blockIdx.x == 0)
+        for (int e = threadIdx.x; e < kGjB * kGjB; e += 256) Pout[e] = M[e / kGjB][e % kGjB];
+}
+
+// Block step, part 2: rows i0 .. i0 + kGjR - 1 (i0 = kGjR blockIdx.y), columns
+// j = 256 blockIdx.x + t.  The block row's column j (new, from part 1) is read once into
+// registers and serves all kGjR rows; the rows' saved block-column entries are staged in
+// LDS.
+constexpr int kGjR = 16;
+__global__ void __launch_bounds__(256) k_gjb_update(double* __restrict__ A, int n, int k0, int kb,
+                                                    const double* __restrict__ P,
+                                                    const double* __restrict__ C) {
+    __shared__ double cs[kGjR][kGjB];
+    const int i0 = blockIdx.y * kGjR;
+    for (int e = threadIdx.x; e < kGjR * kGjB; e += 256) {
+        const int r = e / kGjB, c = e % kGjB;
+        cs[r][c] = (i0 + r < n && c < kb) ? C[(long)(i0 + r) * kGjB + c] : 0.0;
+    }
+    __syncthreads();
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const bool in_j = j >= k0 && j < k0 + kb;
+    double col[kGjB];
+#pragma unroll
+    for (int c = 0; c < kGjB; ++c)
+        col[c] = c < kb ? (in_j ? P[c * kGjB + (j - k0)] : A[(long)(k0 + c) * n + j]) : 0.0;
+    for (int r = 0; r < kGjR; ++r) {
+        const int i = i0 + r;
+        if (i >= n) break;
+        if (i >= k0 && i < k0 + kb) {
+            if (in_j) A[(long)i * n + j] = P[(i - k0) * kGjB + (j - k0)];
+            continue;  // the rest of the block row was formed in part 1
+        }
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < kGjB; ++c) acc += cs[r][c] * col[c];
+        if (in_j)
+            A[(long)i * n + j] = -acc;
         else
-            di[j] = (j == k) ? -f * piv : ri[j] - f * pk;
+            A[(long)i * n + j] -= acc;
     }
 }
 
-// In-place inverse of the n x n matrix A (row-major, fp64) by Gauss-Jordan without
-// pivoting, one launch per pivot alternating between A and a scratch copy.
+// In-place inverse of the n x n matrix A (row-major, fp64): 2 launches per block of kGjB
+// pivots.
 void dense_invert(double* A, int n, hipStream_t s) {
-    double* B = (double*)dmalloc(sizeof(double) * (size_t)n * n);
-    double* src = A;
-    double* dst = B;
-    for (int k = 0; k < n; ++k) {
-        hipLaunchKernelGGL(k_gj_step, dim3(n), dim3(256), 0, s, (const double*)src, dst, n, k);
-        std::swap(src, dst);
+    Tmp P(sizeof(double) * kGjB * kGjB), C(sizeof(double) * (size_t)n * kGjB);
+    const unsigned gcol = (unsigned)((n + 255) / 256);
+    for (int k0 = 0; k0 < n; k0 += kGjB) {
+        const int kb = std::min(kGjB, n - k0);
+        hipLaunchKernelGGL(k_gjb_panel, dim3(gcol), dim3(256), 0, s, A, n, k0, kb, P.as<double>(),
+                           C.as<double>());
+        hipLaunchKernelGGL(k_gjb_update, dim3(gcol, (unsigned)((n + kGjR - 1) / kGjR)), dim3(256),
+                           0, s, A, n, k0, kb, (const double*)P.as<double>(),
+                           (const double*)C.as<double>());
     }
     HIPCHECK(hipGetLastError());
-    if (src != A)
-        HIPCHECK(hipMemcpyAsync(A, src, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
     HIPCHECK(hipStreamSynchronize(s));
-    dfree(B);
 }
 
 // Gauss-Seidel sweeps on the coarsest level from x = 0 (the iterative coarse level
@@ -960,6 +1085,7 @@ template <typename TF, typename T, bool SYM>
 __global__ void __launch_bounds__(1024) k_coarse_gs(LCView<double> c, const TF* __restrict__ f,
                                                     T* __restrict__ x, int sweeps) {
     __shared__ double xs[kGsMax];
+    if (c.skip && *c.skip != 0.0) return;  // before any barrier: the whole block returns
     const long n = (long)c.sx * c.sy * (c.mz + 2);
     for (long i = threadIdx.x; i < n; i += blockDim.x) xs[i] = 0.0;
     __syncthreads();
@@ -998,7 +1124,9 @@ template void coarse_gs<float, float>(const CoarseLevel&, const float*, float*, 
 template <typename TF, typename T>
 __global__ void __launch_bounds__(256) k_coarse_solve(const double* __restrict__ Ainv,
                                                       const long* __restrict__ cidx, int nL,
-                                                      const TF* __restrict__ f, T* __restrict__ x) {
+                                                      const TF* __restrict__ f, T* __restrict__ x,
+                                                      const double* __restrict__ skip) {
+    if (skip && *skip != 0.0) return;
     const int row = blockIdx.x * 4 + threadIdx.x / kWave;
     const int lane = threadIdx.x & 63;
     if (row >= nL) return;
@@ -1012,7 +1140,7 @@ template <typename TF, typename T>
 void coarse_solve(const double* Ainv, const long* cidx, int nL, const TF* f, T* x, hipStream_t s) {
     KTimer kt_(T_COARSE, s, 8L * nL * nL + nL * (long)(sizeof(TF) + sizeof(T) + 8));
     klaunch(kt_, true, (k_coarse_solve<TF, T>), dim3((nL + 3) / 4), dim3(256), Ainv, cidx, nL, f,
-            x);
+            x, g_vskip);
     HIPCHECK(hipGetLastError());
 }
 template void coarse_solve<double, double>(const double*, const long*, int, const double*, double*,

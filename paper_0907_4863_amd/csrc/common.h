@@ -58,6 +58,7 @@ struct L0View {
     __host__ __device__ T tcoefT(int d, long r) const { return tabT[8 * r + d]; }
     T c[3];             // interior off-diagonal per axis
     double rho_end;     // factor of the end-plane rows (1/2 with open ends, else 1)
+    const double* skip; // nonzero *skip: the kernel returns at once (see g_vskip)
 };
 
 // Values per row of a level >= 1 coefficient table (27 and 1 of padding).
@@ -87,6 +88,7 @@ struct LCView {
     const T* tb;
     const T* tbT;
     long tcap, tTcap;     // rows allocated
+    const double* skip;   // nonzero *skip: the kernel returns at once (see g_vskip)
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -160,6 +162,20 @@ struct MemScope {
     MemScope& operator=(const MemScope&) = delete;
 };
 #define HIPCHECK(x) ::saamg::hip_check((x), #x)
+
+// While a solve's preconditioner is queued, the device address of its skip flag: every
+// view built then carries it, and the V-cycle's kernels return at once when the flag is
+// nonzero.  The flag is set on the device by the test of the residual the V-cycle would
+// precondition, when that residual already passes the stopping rule (the host would
+// discard the result).  Null elsewhere (setup, diagnostics, the CG kernels).
+extern thread_local const double* g_vskip;
+struct VSkipScope {
+    const double* saved;
+    explicit VSkipScope(const double* flag) : saved(g_vskip) { g_vskip = flag; }
+    ~VSkipScope() { g_vskip = saved; }
+    VSkipScope(const VSkipScope&) = delete;
+    VSkipScope& operator=(const VSkipScope&) = delete;
+};
 
 // Allocates through the thread's MemScope and zero-fills on its stream (stream-ordered);
 // throws ApiError(NOMEM) on failure.
@@ -280,6 +296,7 @@ struct saamg_hierarchy {
     double* Ainv = nullptr;
     long* cidx = nullptr;     // storage index of each coarsest-level unknown
     double t_setup_ms = 0;
+    double t_phase_ms[6] = {};  // setup phases (see saamg_info.t_setup_phase_ms)
     double t_refresh_ms = 0;  // last saamg_refresh, 0 if none
     int live_states = 0;      // saamg_state objects created on H and not yet destroyed
     int64_t bytes = 0;
@@ -311,6 +328,7 @@ inline L0View<T> FineLevel::view() const {
     }
     for (int a = 0; a < 3; ++a) v.c[a] = (T)c64[a];
     v.rho_end = robin_d > 0.0 ? 0.5 : 1.0;
+    v.skip = g_vskip;
     return v;
 }
 
@@ -337,6 +355,7 @@ inline LCView<T> CoarseLevel::view() const {
     }
     v.tcap = tab_cap;
     v.tTcap = tabT_cap;
+    v.skip = g_vskip;
     return v;
 }
 }  // namespace saamg

@@ -262,6 +262,7 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
                                          End end = End{}) {
     using FV = decltype(fetch(Idx{0, 0u}, 0, 0, 0, false, 0));
     using TX = decltype(X(Idx{0, 0u}));
+    if (v.skip && *v.skip != 0.0) return;  // wave-uniform: the whole grid returns
     int bx, y, bz;
     l0_tile(v, &bx, &y, &bz);
     const int lane = threadIdx.x;
@@ -472,10 +473,31 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(const double* __restri
             scal[S_LZ_SP] = 0.0;
             scal[S_LZ_B] = 0.0;
             break;
-        case FIN_RESTORE_RHO:
+        case FIN_RESTORE_RHO:  // a step redone from the true residual: its V-cycle runs
             scal[S_RHO] = scal[S_RHO_PREV];
+            scal[S_SKIP] = 0.0;
             break;
+        case FIN_RR: {
+            // ||r||^2, and the skip flag of the V-cycle queued next: set when the
+            // recursive residual passes the stopping rule, by the host's own expression
+            // (sqrt(r.r) / sqrt(b.b) <= tol, same IEEE operations), or is not finite; the
+            // host then stops or recomputes the true residual, and never uses that V-cycle
+            const double rr = sums[0];
+            scal[S_RR] = rr;
+            scal[S_SKIP] = !(sqrt(rr) / sqrt(scal[S_BB]) > scal[S_TOL]) ? 1.0 : 0.0;
+            break;
+        }
     }
+}
+
+__global__ void k_scal_start(double* scal, double tol) {
+    scal[S_TOL] = tol;
+    scal[S_SKIP] = 0.0;
+}
+
+void scal_start(double* scal, double tol, hipStream_t s) {
+    hipLaunchKernelGGL(k_scal_start, dim3(1), dim3(1), 0, s, scal, tol);
+    HIPCHECK(hipGetLastError());
 }
 
 void finalize(const double* partials, long nblk, int nq, double* scal, int op, int dst,
@@ -1024,6 +1046,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_l0_restrict_sum(int nx, int ny, int nz, LCView<T> c,
                                                          const T* __restrict__ yv,
                                                          T* __restrict__ fc, T* __restrict__ fd) {
+    if (c.skip && *c.skip != 0.0) return;
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t >= (long)c.mx * c.my) return;
     const int X = (int)(t % c.mx), Y = (int)(t / c.mx), Z = blockIdx.y;
@@ -1203,7 +1226,9 @@ void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, 
 // q <- A z + beta q, which equals A p_new because q held A p_old.  The stencil runs on z
 // (fp32 in mixed precision), the sums in fp64; partials of p . q.  The previous step's
 // x += alpha p, deferred to here, is applied with the old p as it is read.  With an fp32 z
-// (mixed precision) it stores whole rows.
+// (mixed precision) it stores whole rows.  (Forming p_new at every stencil node from z and
+// the old p instead, and q = A p_new, moves 8 bytes less per unknown but needs twice the
+// stencil loads: measured slower on the 256 x 256 x 768 ellipse, 454 -> 488 us.)
 template <typename TZ>
 __global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ* __restrict__ zv,
                                                     double* __restrict__ xv,

@@ -26,11 +26,13 @@ enum Slot {
     S_RHO = 0, S_RHO_PREV, S_ALPHA, S_BETA, S_PQ, S_RR, S_BB, S_R0,
     S_INVN, S_LAM, S_RT, S_LZ_S, S_LZ_SP, S_LZ_B,
     S_XA,  // step length still owed to x (x += S_XA p); 0 after a broken-down step
-    S_NSLOTS = 16
+    S_TOL,   // the solve's tolerance
+    S_SKIP,  // nonzero: the queued V-cycle is not needed (the residual passes the test)
+    S_NSLOTS = 18
 };
 // Finalisation ops: how the summed partials update `scal`.
 enum FinOp { FIN_STORE = 0, FIN_ALPHA, FIN_RHO_INIT, FIN_RHO, FIN_LZ_ALPHA, FIN_LZ_BETA, FIN_NORM,
-             FIN_RESTORE_RHO, FIN_XA_CLEAR };
+             FIN_RESTORE_RHO, FIN_XA_CLEAR, FIN_RR };
 // Chebyshev step kinds.  CHEB_NEXT_X (level 0 only) is CHEB_NEXT with the previous
 // iterate in place of the previous direction (d = xin - din).
 enum ChebMode { CHEB_ZERO1 = 0, CHEB_ZERO2, CHEB_FIRST, CHEB_NEXT, CHEB_NEXT_X };
@@ -46,6 +48,8 @@ long lc_blocks(const CoarseLevel& C);
 
 void finalize(const double* partials, long nblk, int nq, double* scal, int op, int dst,
               hipStream_t s);
+// scal[S_TOL] = tol, scal[S_SKIP] = 0 (start of a solve)
+void scal_start(double* scal, double tol, hipStream_t s);
 
 // Zero `bytes` bytes at p with a kernel on stream s (no memset node, any alignment).
 void zero_fill(void* p, size_t bytes, hipStream_t s);

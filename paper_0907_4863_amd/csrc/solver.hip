@@ -21,6 +21,7 @@
 namespace saamg {
 
 static thread_local std::string g_err;
+thread_local const double* g_vskip = nullptr;
 
 void hip_check(hipError_t e, const char* what) {
     if (e != hipSuccess) throw HipError{e, what};
@@ -288,6 +289,9 @@ template <typename T>
 static T* vcycle(const saamg_hierarchy* H, VBuf<T>& B, int l, const T* f0, T* out,
                  const double* fdot, double* dot, hipStream_t s) {
     const bool fine = (l == 0);
+    // Levels below 1 are latency-bound: their kernels do not wait on the skip flag (a
+    // dependent load at each kernel start costs more there than the skipped work).
+    VSkipScope vs(l >= 2 ? nullptr : g_vskip);
     if (l == H->n_levels - 1) {
         T* x = fine ? out : B.xa[l];
         if (fine) {
@@ -445,9 +449,11 @@ static void read_scal(saamg_state* S) {
 
 // z = M r and the partials of r . z.  The dot is taken with the residual the V-cycle
 // reads (the fp32 copy in mixed precision, so r . z is the quadratic form of the applied
-// preconditioner); a one-level hierarchy takes it with the fp64 residual.
-static void precond(saamg_state* S) {
+// preconditioner); a one-level hierarchy takes it with the fp64 residual.  With `skippable`
+// the V-cycle's kernels honour the solve's skip flag (scal[S_SKIP]).
+static void precond(saamg_state* S, bool skippable = true) {
     const saamg_hierarchy* H = S->H;
+    VSkipScope vs(skippable ? S->scal + S_SKIP : nullptr);
     const double* fdot = H->n_levels == 1 ? S->r : nullptr;
     if (S->mixed)
         vcycle<float>(H, S->vf, 0, S->r32, (float*)S->z, fdot, S->part, S->s);
@@ -473,6 +479,7 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
     cg_init(H->l0, b, x0, S->bs, S->x, S->s);
     cg_resid(H->l0, S->bs, S->x, S->r, S->part, S->r32, S->s);
     finalize(S->part, l0_blocks(H->l0), 2, S->scal, FIN_STORE, S_RR, S->s);
+    scal_start(S->scal, S->tol, S->s);
     zero_fill(S->p, 8 * H->l0.nbox, S->s);
     zero_fill(S->q, 8 * H->l0.nbox, S->s);
     read_scal(S);
@@ -515,7 +522,7 @@ static void state_enqueue(saamg_state* S) {
         cg_pq<double>(H->l0, (const double*)S->z, S->x, S->p, S->q, S->scal, S->part, S->s);
     finalize(S->part, nb, 1, S->scal, FIN_ALPHA, 0, S->s);
     cg_xr(H->l0, S->r, S->q, S->scal, S->part, S->r32, S->s);
-    finalize(S->part, nb, 1, S->scal, FIN_STORE, S_RR, S->s);
+    finalize(S->part, nb, 1, S->scal, FIN_RR, 0, S->s);
     HIPCHECK(hipMemcpyAsync(S->hscal, S->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
                             S->s));
     if (S->ev) HIPCHECK(hipEventRecord(S->ev, S->s));
@@ -570,18 +577,30 @@ static void state_complete(saamg_state* S) {
             S->done = 1;
             return;
         }
-        // continue from the true residual: redo the preconditioner on it
+        // continue from the true residual: redo the preconditioner on it (the restore
+        // also clears the device's skip flag; the host copy follows)
         S->repl += 1;
         const long nb = l0_blocks(S->H->l0);
         finalize(S->part, nb, 0, S->scal, FIN_RESTORE_RHO, 0, S->s);
         precond(S);
         finalize(S->part, nb, 1, S->scal, FIN_RHO, 0, S->s);
+        S->hscal[S_SKIP] = 0.0;
     }
     if (S->iter >= S->max_iter) {
         flush_x(S);
         S->status = SAAMG_NOT_CONVERGED;
         S->done = 1;
         S->rel_true = std::sqrt(true_residual(S, S->q)) / S->bnorm;
+        return;
+    }
+    if (S->hscal[S_SKIP] != 0.0) {
+        // the device skipped the queued V-cycle while the host goes on (the two tests
+        // use the same expression, so only a rounding difference could cause this): redo
+        // that step's preconditioner
+        const long nb = l0_blocks(S->H->l0);
+        finalize(S->part, nb, 0, S->scal, FIN_RESTORE_RHO, 0, S->s);
+        precond(S);
+        finalize(S->part, nb, 1, S->scal, FIN_RHO, 0, S->s);
     }
 }
 
@@ -759,7 +778,6 @@ static void validate_options(const saamg_options& o) {
 // constant rule ignores them) and, with open ends, every end-plane unknown; six fractions
 // per row, 1 where no wall is cut.
 struct DomainPrep {
-    long n_unk = 0;
     std::vector<int64_t> nw_nodes;
     std::vector<double> nw_frac;
 };
@@ -783,8 +801,10 @@ static DomainPrep prepare_domain(const saamg_domain* dom, int variant, bool scan
     const uint8_t* m = dom->mask;
     // unknowns: their number, and none on a face of the box
     if (scan_mask) {
-        for (long t = 0; t < nbox; ++t) D.n_unk += m[t] != 0;
-        if (D.n_unk == 0) throw ApiError{SAAMG_INVALID_ARG, "the domain has no unknowns"};
+        // at least one unknown (the device counts them when it builds the segment masks)
+        bool any = false;
+        for (long t = 0; t < nbox && !any; ++t) any = m[t] != 0;
+        if (!any) throw ApiError{SAAMG_INVALID_ARG, "the domain has no unknowns"};
         bool on_face = false;
         for (long t = 0; t < nxy && !on_face; ++t) on_face = m[t] || m[t + nxy * (nz - 1)];
         for (long k = 0; k < nz && !on_face; ++k)
@@ -1019,6 +1039,7 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
                                    hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
     const DomainPrep D = prepare_domain(dom, variant);
+    const double t_host = ms_since(t0);
     saamg_options o;
     if (opt)
         o = *opt;
@@ -1067,12 +1088,13 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
         }
         L.n_irr = tots[0];
         L.n_unknowns = tots[1];
-        if (L.n_unknowns != D.n_unk) throw ApiError{SAAMG_HIP_ERROR, "unknown count mismatch"};
         L.tab64 = (double*)dmalloc(8 * 16 * std::max<long>(L.n_irr, 1));
         L.tab32 = (float*)dmalloc(4 * 16 * std::max<long>(L.n_irr, 1));
         fine_numbers(L, dom, dd, variant, s);
         dd.release();
         H->bytes = 20L * L.nseg + 8L * nbox + 12L * 16 * L.n_irr;
+        H->t_phase_ms[0] = t_host;
+        H->t_phase_ms[1] = ms_since(t0) - t_host;
 
         // hierarchy (Section 3.2): coarsen until at most max_coarse unknowns
         long n_cur = L.n_unknowns;
@@ -1080,12 +1102,16 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
         H->n_levels = 1;
         while (n_cur > o.max_coarse && H->n_levels < o.max_levels) {
             const int l = H->n_levels - 1;
+            auto tl = std::chrono::steady_clock::now();
             const LevelParams P = level_params(H, l, s);
+            H->t_phase_ms[2] += ms_since(tl);
+            tl = std::chrono::steady_clock::now();
             CoarseLevel C = make_coarse(fmx, fmy, fmz, H->sym);
             int32_t* cnt = nullptr;
             int64_t nc = 0;
             try {
                 nc = galerkin(H, l, C, P.omega, &cnt, s);
+                H->t_phase_ms[3] += ms_since(tl);
             } catch (...) {
                 free_coarse(C);
                 throw;
@@ -1142,8 +1168,12 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
         // Gauss-Seidel coarse solves need a coarse level to run on
         if (o.coarse_solver == SAAMG_COARSE_GS && H->n_levels == 1)
             H->opt.coarse_solver = SAAMG_COARSE_DIRECT;
+        auto tc = std::chrono::steady_clock::now();
         build_coarse_solver(H, s);
+        H->t_phase_ms[4] = ms_since(tc);
+        tc = std::chrono::steady_clock::now();
         coarse_fp32(H, s);
+        H->t_phase_ms[5] = ms_since(tc);
     } catch (...) {
         saamg_destroy(H);
         throw;
@@ -1442,8 +1472,13 @@ int saamg_hierarchy_info(const saamg_hierarchy* H, saamg_info* info) {
         info->device_bytes = H->bytes;
         info->t_setup_ms = H->t_setup_ms;
         info->t_refresh_ms = H->t_refresh_ms;
+        for (int q = 0; q < 6; ++q) info->t_setup_phase_ms[q] = H->t_phase_ms[q];
         info->l0_planes = H->l0.zb;
         info->l0_tile_x = H->l0.tx;
+        for (int l = 1; l < H->n_levels; ++l) {
+            info->table_rows[l] = H->lc[l - 1].n_tab;
+            info->table_rows_t[l] = H->lc[l - 1].sym ? 0 : H->lc[l - 1].n_tabT;
+        }
         return (int)SAAMG_OK;
     });
 }
@@ -1696,7 +1731,7 @@ int saamg_precond_apply(saamg_hierarchy* H, const double* d_r, double* d_z, void
         S.s = (hipStream_t)stream;
         // the residual buffer must stay zero off the unknowns: copy via the scaled mask
         cg_mask_copy(H->l0, d_r, S.r, S.r32, S.s);
-        precond(&S);
+        precond(&S, false);
         if (S.mixed)
             f2d_copy((const float*)S.z, d_z, H->l0.nbox, S.s);
         else
