@@ -609,7 +609,9 @@ def main():
         # hierarchy against fresh setups of the same domains
         import dataclasses
         H = sa.setup(dom, w.variant, sa.default_options(precision=sa.MIXED))
+        Hp = sa.setup(dom, w.variant, sa.default_options(precision=sa.MIXED))
         t_refresh, t_fresh, it_refresh, it_fresh = [], [], [], []
+        t_op, it_op = [], []
         x = torch.zeros(nbox, dtype=torch.float64, device=dev)
         for grow in (1.05, 1.10, 1.15):
             d2 = sa.domain_for(dataclasses.replace(w.shape, length=w.shape.length * grow),
@@ -620,6 +622,12 @@ def main():
             torch.cuda.synchronize()
             t_refresh.append(time.perf_counter() - t0)
             it_refresh.append(sa.solve(H, b, x, tol=w.tol, max_iter=500)["iterations"])
+            # reuse of the preconditioner: the original one, the new operator
+            t0 = time.perf_counter()
+            sa.set_operator(Hp, d2)
+            torch.cuda.synchronize()
+            t_op.append(time.perf_counter() - t0)
+            it_op.append(sa.solve(Hp, b, x, tol=w.tol, max_iter=500)["iterations"])
             t0 = time.perf_counter()
             F = sa.setup(d2, w.variant, sa.default_options(precision=sa.MIXED))
             torch.cuda.synchronize()
@@ -628,6 +636,7 @@ def main():
             sa.destroy(F)
         torch.cuda.synchronize()
         sa.destroy(H)
+        sa.destroy(Hp)
         del x
         line["hierarchy_reuse"] = {
             "workload": f"{w.name} with the length grown by 5, 10 and 15 % (h_z changes, "
@@ -635,7 +644,12 @@ def main():
             "refresh_ms": [round(1e3 * t, 1) for t in t_refresh],
             "fresh_setup_ms": [round(1e3 * t, 1) for t in t_fresh],
             "refresh_over_setup": sum(t_refresh) / sum(t_fresh),
-            "iterations_refreshed": it_refresh, "iterations_fresh": it_fresh}
+            "iterations_refreshed": it_refresh, "iterations_fresh": it_fresh,
+            "preconditioner_reuse": {
+                "what": "the original length's preconditioner kept, the operator of each "
+                        "longer pipe set (saamg_set_operator)",
+                "operator_update_ms": [round(1e3 * t, 1) for t in t_op],
+                "iterations": it_op}}
         print(f"[bench] hierarchy reuse: refresh {[round(1e3 * t) for t in t_refresh]} ms vs "
               f"fresh setup {[round(1e3 * t) for t in t_fresh]} ms", file=sys.stderr, flush=True)
     if not args.no_serve:

@@ -273,6 +273,25 @@ int saamg_solve_noalloc(saamg_hierarchy* H, const double* d_b, const double* d_x
  */
 int saamg_refresh(saamg_hierarchy* H, const saamg_domain* dom, void* stream);
 
+/*
+ * Reuse of the preconditioner (Section 5.2, reusing the preconditioner): later solves on H
+ * iterate with the system operator of dom (its level-0 stencil weights, wall rows and
+ * scaling D^-1/2), while the preconditioner -- every level's operator, smoother,
+ * transfer operators and the coarsest-level solver -- stays the one H was built (or last
+ * refreshed) for.  The paper keeps the first time step's preconditioner through a
+ * simulation and recomputes it only once the iteration count exceeds a threshold; the
+ * caller decides that and calls saamg_refresh(H, dom), which rebuilds the preconditioner
+ * for dom and ends the reuse.  saamg_operator_apply and saamg_scaling report the
+ * operator in use; saamg_level_apply and saamg_level_coefficients the preconditioner's
+ * levels.
+ *   dom     host domain with H's box, unknowns and near-wall rows and the same end
+ *           condition kind (as for saamg_refresh); copied.
+ *   stream  work is queued on it; the call returns when the operator is complete.
+ * Errors: SAAMG_INVALID_ARG when dom fails those checks or a solve state created on H
+ * still exists (H unchanged); SAAMG_NOMEM, SAAMG_HIP_ERROR.
+ */
+int saamg_set_operator(saamg_hierarchy* H, const saamg_domain* dom, void* stream);
+
 /* Free the hierarchy (NULL is accepted). */
 int saamg_destroy(saamg_hierarchy* H);
 

@@ -10,5 +10,6 @@ from .capi import (  # noqa: F401
     SaamgError, TorchAllocator, batch_advance, batch_step, default_options, destroy, domain_for,
     domain_from_shape, footprint_bytes, hierarchy_info, level_apply, level_coefficients,
     operator_apply, pic_create, pic_deposit, pic_destroy, pic_gather, precond_apply, refresh,
+    set_operator,
     scaling, setup, solve, solve_noalloc, state_create, state_destroy, state_finish, state_query,
 )

@@ -104,6 +104,7 @@ def lib() -> C.CDLL:
                                           C.POINTER(C.c_uint8), _DP, C.POINTER(C.c_int64), _DP]
     L.saamg_setup.argtypes = [C.POINTER(Domain), C.c_int, C.POINTER(Options), _P, C.POINTER(_P)]
     L.saamg_refresh.argtypes = [_P, C.POINTER(Domain), _P]
+    L.saamg_set_operator.argtypes = [_P, C.POINTER(Domain), _P]
     L.saamg_solve.argtypes = [_P, _P, _P, _P, C.c_double, C.c_int, _P, C.POINTER(Result)]
     L.saamg_solve_noalloc.argtypes = [_P, _P, _P, _P, C.c_double, C.c_int, _P,
                                       C.POINTER(Result)]
@@ -346,6 +347,12 @@ def refresh(H: Hierarchy, dom: HostDomain, stream=None) -> None:
     """Recompute every number of H for ``dom`` on H's aggregates (saamg_refresh)."""
     ds = dom.struct()
     _check(lib().saamg_refresh(H.handle, C.byref(ds), _stream(stream)))
+
+
+def set_operator(H: Hierarchy, dom: HostDomain, stream=None) -> None:
+    """Iterate with the operator of ``dom`` and keep H's preconditioner (saamg_set_operator)."""
+    ds = dom.struct()
+    _check(lib().saamg_set_operator(H.handle, C.byref(ds), _stream(stream)))
 
 
 def destroy(H: Hierarchy) -> None:

@@ -289,6 +289,9 @@ struct saamg_hierarchy {
     int sym = 1;
     int n_levels = 1;
     saamg::FineLevel l0{};
+    // the CG iteration's level-0 operator when it differs from the preconditioner's
+    // (saamg_set_operator): own table and scaling, the segment masks of l0; else null
+    saamg::FineLevel* op = nullptr;
     std::vector<saamg::CoarseLevel> lc;     // lc[l-1] is level l
     std::vector<saamg::LevelParams> par;    // per level except the coarsest
     // coarsest level: explicit inverse, fp64, and where its unknowns live

@@ -392,6 +392,10 @@ struct saamg_state {
 
 namespace saamg {
 
+// The level-0 operator of the CG iteration: the hierarchy's own, or the one a later
+// saamg_set_operator gave it (the preconditioner then keeps the hierarchy's).
+static const FineLevel& cg_op(const saamg_hierarchy* H) { return H->op ? *H->op : H->l0; }
+
 // pinned = false: no pinned host buffer and no event (the allocation-free solve); the
 // scalars are read into the state itself and the host waits on the stream.
 static void state_alloc(saamg_state* S, saamg_hierarchy* H, bool pinned = true) {
@@ -463,7 +467,7 @@ static void precond(saamg_state* S, bool skippable = true) {
 
 // True residual b - A x into `dst`; returns ||dst||^2.
 static double true_residual(saamg_state* S, double* dst) {
-    cg_resid(S->H->l0, S->bs, S->x, dst, S->part, dst == S->r ? S->r32 : nullptr, S->s);
+    cg_resid(cg_op(S->H), S->bs, S->x, dst, S->part, dst == S->r ? S->r32 : nullptr, S->s);
     finalize(S->part, l0_blocks(S->H->l0), 2, S->scal, FIN_STORE, S_RT, S->s);
     read_scal(S);
     return S->hscal[S_RT];
@@ -476,8 +480,8 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
     S->done = 0;
     S->repl = 0;
     S->t0 = std::chrono::steady_clock::now();
-    cg_init(H->l0, b, x0, S->bs, S->x, S->s);
-    cg_resid(H->l0, S->bs, S->x, S->r, S->part, S->r32, S->s);
+    cg_init(cg_op(H), b, x0, S->bs, S->x, S->s);
+    cg_resid(cg_op(H), S->bs, S->x, S->r, S->part, S->r32, S->s);
     finalize(S->part, l0_blocks(H->l0), 2, S->scal, FIN_STORE, S_RR, S->s);
     scal_start(S->scal, S->tol, S->s);
     zero_fill(S->p, 8 * H->l0.nbox, S->s);
@@ -517,11 +521,11 @@ static void state_enqueue(saamg_state* S) {
     const saamg_hierarchy* H = S->H;
     const long nb = l0_blocks(H->l0);
     if (S->mixed)
-        cg_pq<float>(H->l0, (const float*)S->z, S->x, S->p, S->q, S->scal, S->part, S->s);
+        cg_pq<float>(cg_op(H), (const float*)S->z, S->x, S->p, S->q, S->scal, S->part, S->s);
     else
-        cg_pq<double>(H->l0, (const double*)S->z, S->x, S->p, S->q, S->scal, S->part, S->s);
+        cg_pq<double>(cg_op(H), (const double*)S->z, S->x, S->p, S->q, S->scal, S->part, S->s);
     finalize(S->part, nb, 1, S->scal, FIN_ALPHA, 0, S->s);
-    cg_xr(H->l0, S->r, S->q, S->scal, S->part, S->r32, S->s);
+    cg_xr(cg_op(H), S->r, S->q, S->scal, S->part, S->r32, S->s);
     finalize(S->part, nb, 1, S->scal, FIN_RR, 0, S->s);
     HIPCHECK(hipMemcpyAsync(S->hscal, S->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
                             S->s));
@@ -534,7 +538,7 @@ static void state_enqueue(saamg_state* S) {
 // The step length a step still owes x (each step's x += alpha p is applied by the next
 // step's direction update): apply it now and clear it.  Needed before x is read.
 static void flush_x(saamg_state* S) {
-    cg_xflush(S->H->l0, S->x, S->p, S->scal, S->s);
+    cg_xflush(cg_op(S->H), S->x, S->p, S->scal, S->s);
     finalize(S->part, 1, 0, S->scal, FIN_XA_CLEAR, 0, S->s);
 }
 
@@ -1182,42 +1186,54 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
     return H;
 }
 
+// Checks shared by the re-setups of H for a new domain: the box, the end condition kind
+// and no live solve state.
+static DomainPrep check_resetup(const saamg_hierarchy* H, const saamg_domain* dom) {
+    const FineLevel& L = H->l0;
+    if (dom && dom->mask && (dom->nx != L.nx || dom->ny != L.ny || dom->nz != L.nz))
+        throw ApiError{SAAMG_INVALID_ARG, "the domain's box differs from the hierarchy's"};
+    DomainPrep D = prepare_domain(dom, H->variant, false);
+    if ((dom->robin_d > 0.0) != (L.robin_d > 0.0))
+        throw ApiError{SAAMG_INVALID_ARG, "the end condition kind (open or closed) differs"};
+    if (H->live_states > 0)
+        throw ApiError{SAAMG_INVALID_ARG, "solve states of this hierarchy still exist"};
+    return D;
+}
+
+// The new domain's segment masks (unknowns and near-wall rows) must equal H's.
+static void check_same_rows(const saamg_hierarchy* H, const DeviceDomain& dd, hipStream_t s) {
+    const FineLevel& L = H->l0;
+    FineLevel T = L;
+    Tmp unk(8 * L.nseg), irr(8 * L.nseg), c1(4 * L.nseg), c2(4 * L.nseg);
+    T.unk = unk.as<uint64_t>();
+    T.irr = irr.as<uint64_t>();
+    l0_build_masks(T, dd.mask, dd.nwidx, c1.as<int32_t>(), c2.as<int32_t>(), s);
+    if (!l0_same_masks(L, T.unk, T.irr, s))
+        throw ApiError{SAAMG_INVALID_ARG,
+                       "the domain's unknowns or near-wall rows differ from the hierarchy's"};
+}
+
+// End a reuse of the preconditioner: the CG iteration goes back to the hierarchy's own
+// level-0 operator.
+static void drop_operator(saamg_hierarchy* H) {
+    if (!H->op) return;
+    for (void* p : {(void*)H->op->tab64, (void*)H->op->tab32, (void*)H->op->sigma}) dfree(p);
+    H->bytes -= 8L * H->op->nbox + 12L * 16 * H->op->n_irr;
+    delete H->op;
+    H->op = nullptr;
+}
+
 // Numeric-only re-setup on the aggregates, storage and buffers of H (Section 5.2, reuse of
 // the aggregation hierarchy): the domain must have H's box, unknowns, near-wall rows and
 // end condition kind; every number is recomputed.  H is unchanged when a check fails.
 static void refresh_impl(saamg_hierarchy* H, const saamg_domain* dom, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
     FineLevel& L = H->l0;
-    if (dom && dom->mask && (dom->nx != L.nx || dom->ny != L.ny || dom->nz != L.nz))
-        throw ApiError{SAAMG_INVALID_ARG, "the domain's box differs from the hierarchy's"};
-    const DomainPrep D = prepare_domain(dom, H->variant, false);
-    if ((dom->robin_d > 0.0) != (L.robin_d > 0.0))
-        throw ApiError{SAAMG_INVALID_ARG, "the end condition kind (open or closed) differs"};
-    if (H->live_states > 0)
-        throw ApiError{SAAMG_INVALID_ARG, "solve states of this hierarchy still exist"};
-
+    const DomainPrep D = check_resetup(H, dom);
     DeviceDomain dd(dom, D, L.nbox, s);
-    {
-        // the new segment masks must equal the hierarchy's
-        FineLevel T = L;
-        T.unk = (uint64_t*)dmalloc(8 * L.nseg);
-        T.irr = (uint64_t*)dmalloc(8 * L.nseg);
-        int32_t* c1 = (int32_t*)dmalloc(4 * L.nseg);
-        int32_t* c2 = (int32_t*)dmalloc(4 * L.nseg);
-        bool same = false;
-        try {
-            l0_build_masks(T, dd.mask, dd.nwidx, c1, c2, s);
-            same = l0_same_masks(L, T.unk, T.irr, s);
-        } catch (...) {
-            for (void* p : {(void*)T.unk, (void*)T.irr, (void*)c1, (void*)c2}) dfree(p);
-            throw;
-        }
-        for (void* p : {(void*)T.unk, (void*)T.irr, (void*)c1, (void*)c2}) dfree(p);
-        if (!same)
-            throw ApiError{SAAMG_INVALID_ARG,
-                           "the domain's unknowns or near-wall rows differ from the hierarchy's"};
-    }
+    check_same_rows(H, dd, s);
     // from here on H changes; a failure leaves it unusable (destroy it)
+    drop_operator(H);
     fine_numbers(L, dom, dd, H->variant, s);
     dd.release();
     for (int l = 0; l + 1 < H->n_levels; ++l) {
@@ -1233,6 +1249,33 @@ static void refresh_impl(saamg_hierarchy* H, const saamg_domain* dom, hipStream_
     build_coarse_solver(H, s);
     coarse_fp32(H, s);
     H->t_refresh_ms = ms_since(t0);
+}
+
+// Reuse of the preconditioner (Section 5.2): the CG iteration takes the level-0 operator
+// (stencil weights, wall rows, scaling) of dom; the V-cycle keeps everything it had.
+static void set_operator_impl(saamg_hierarchy* H, const saamg_domain* dom, hipStream_t s) {
+    const FineLevel& L = H->l0;
+    const DomainPrep D = check_resetup(H, dom);
+    DeviceDomain dd(dom, D, L.nbox, s);
+    check_same_rows(H, dd, s);
+    if (!H->op) {
+        FineLevel* op = new FineLevel(L);  // shares the segment masks and slots
+        op->tab64 = nullptr;
+        op->tab32 = nullptr;
+        op->sigma = nullptr;
+        try {
+            op->tab64 = (double*)dmalloc(8 * 16 * std::max<long>(L.n_irr, 1));
+            op->tab32 = (float*)dmalloc(4 * 16 * std::max<long>(L.n_irr, 1));
+            op->sigma = (double*)dmalloc(8 * L.nbox);
+        } catch (...) {
+            for (void* p : {(void*)op->tab64, (void*)op->tab32, (void*)op->sigma}) dfree(p);
+            delete op;
+            throw;
+        }
+        H->op = op;
+        H->bytes += 8L * L.nbox + 12L * 16 * L.n_irr;
+    }
+    fine_numbers(*H->op, dom, dd, H->variant, s);
 }
 
 template <class F>
@@ -1422,6 +1465,16 @@ int saamg_setup(const saamg_domain* dom, int variant, const saamg_options* opt, 
     });
 }
 
+int saamg_set_operator(saamg_hierarchy* H, const saamg_domain* dom, void* stream) {
+    return guarded([&] {
+        if (!H) throw ApiError{SAAMG_INVALID_ARG, "hierarchy is NULL"};
+        HIPCHECK(hipSetDevice(H->device));
+        MemScope ms(H->mem, (hipStream_t)stream);
+        set_operator_impl(H, dom, (hipStream_t)stream);
+        return (int)SAAMG_OK;
+    });
+}
+
 int saamg_refresh(saamg_hierarchy* H, const saamg_domain* dom, void* stream) {
     return guarded([&] {
         if (!H) throw ApiError{SAAMG_INVALID_ARG, "hierarchy is NULL"};
@@ -1441,6 +1494,7 @@ int saamg_destroy(saamg_hierarchy* H) {
                     (void*)L.sigma, (void*)H->Ainv, (void*)H->cidx})
         dfree(p);
     for (auto& C : H->lc) free_coarse(C);
+    drop_operator(H);
     if (H->ws) {
         state_release(H->ws);
         delete H->ws;
@@ -1515,7 +1569,7 @@ int saamg_solve(saamg_hierarchy* H, const double* d_b, const double* d_x0, doubl
             state_enqueue(&S);
             state_complete(&S);
         }
-        cg_unscale(H->l0, S.x, d_x, S.s);
+        cg_unscale(cg_op(H), S.x, d_x, S.s);
         HIPCHECK(hipStreamSynchronize(S.s));
         S.s = nullptr;  // the caller's stream is not kept beyond the call
         S.t_ms = ms_since(t0);
@@ -1648,7 +1702,7 @@ int saamg_state_finish(saamg_state* S, double* d_x) {
         if (!S || !d_x) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
         HIPCHECK(hipSetDevice(S->H->device));
         if (!S->done) flush_x(S);  // an unfinished state's iterate, with its last step
-        cg_unscale(S->H->l0, S->x, d_x, S->s);
+        cg_unscale(cg_op(S->H), S->x, d_x, S->s);
         HIPCHECK(hipStreamSynchronize(S->s));
         return (int)SAAMG_OK;
     });
@@ -1746,7 +1800,7 @@ int saamg_operator_apply(saamg_hierarchy* H, const double* d_x, double* d_y, voi
     return guarded([&] {
         if (!H || !d_x || !d_y) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
         HIPCHECK(hipSetDevice(H->device));
-        l0_apply<double>(H->l0, false, d_x, d_y, (hipStream_t)stream);
+        l0_apply<double>(cg_op(H), false, d_x, d_y, (hipStream_t)stream);
         HIPCHECK(hipStreamSynchronize((hipStream_t)stream));
         return (int)SAAMG_OK;
     });
@@ -1756,7 +1810,7 @@ int saamg_scaling(saamg_hierarchy* H, double* d_sigma, void* stream) {
     return guarded([&] {
         if (!H || !d_sigma) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
         HIPCHECK(hipSetDevice(H->device));
-        HIPCHECK(hipMemcpyAsync(d_sigma, H->l0.sigma, 8 * H->l0.nbox, hipMemcpyDeviceToDevice,
+        HIPCHECK(hipMemcpyAsync(d_sigma, cg_op(H).sigma, 8 * H->l0.nbox, hipMemcpyDeviceToDevice,
                                 (hipStream_t)stream));
         HIPCHECK(hipStreamSynchronize((hipStream_t)stream));
         return (int)SAAMG_OK;
@@ -1859,7 +1913,7 @@ extern "C" int saamg_solve_noalloc(saamg_hierarchy* H, const double* d_b, const 
             state_enqueue(&S);
             state_complete(&S);
         }
-        cg_unscale(H->l0, S.x, d_x, S.s);
+        cg_unscale(cg_op(H), S.x, d_x, S.s);
         HIPCHECK(hipStreamSynchronize(S.s));
         S.t_ms = ms_since(t0);
         state_fill_result(&S, res);
