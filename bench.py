@@ -281,7 +281,7 @@ def hbm_ceiling() -> dict:
 def _kernel_sources_digest() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("fine.hip", "coarse.hip", "common.h", "launch.h"):
+    for f in ("fine.hip", "wide.hip", "coarse.hip", "common.h", "launch.h", "march.h"):
         with open(os.path.join(ROOT, "paper_0907_4863_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

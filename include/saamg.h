@@ -104,15 +104,18 @@ typedef struct {
                               multilevel hierarchies; the level's box with its ghost layer must
                               hold at most 8192 nodes)                         default DIRECT */
     int32_t coarse_sweeps; /* Gauss-Seidel sweeps (Section 3.2 uses 3)         default 3    */
-    /* Level-0 launch shape of the solve-time kernels (the results do not depend on it):
-       planes per block along z (0 = automatic; else a power of two 1..64) and 64-node
-       segments per block along x (0 = automatic; else 1, 2 or 4, at most the segments of
-       a line).                                                          default 0, 0 */
+    /* Level-0 launch shape of the solve-time kernels (results agree up to the order of
+       the dot products' partial sums): planes per block along z (0 = automatic; else a
+       power of two 2..32, capped at 14 for fp32 and 30 for fp64 on 16-byte lanes) and
+       64-node segments per block along x (0 = automatic; else 1, 2 or 4, at most the
+       segments of a line; one-node lanes only).                         default 0, 0 */
     int32_t l0_planes;
     int32_t l0_tile_x;
     /* Device memory.  Every buffer of the hierarchy, of the solve states created on it
        and of the library's temporaries comes from alloc(alloc_ctx, bytes, stream), which
-       returns memory of the current device (NULL: failure, reported as SAAMG_NOMEM) that
+       returns memory of the current device aligned to 256 bytes (NULL: failure, reported
+       as SAAMG_NOMEM; a misaligned block is freed again and reported as
+       SAAMG_INVALID_ARG) that
        may be used in stream order on `stream` (a hipStream_t; NULL = the default stream),
        and goes back through free(alloc_ctx, ptr, stream) once no queued work uses it.
        Both NULL: the library's own pool (per device; new memory from hipMalloc, freed
@@ -123,6 +126,12 @@ typedef struct {
     void* (*alloc)(void* alloc_ctx, size_t bytes, void* stream);
     void (*free)(void* alloc_ctx, void* ptr, void* stream);
     void* alloc_ctx;
+    /* Lanes of the level-0 V-cycle and CG kernels: 1 = one node per lane (a wavefront
+       marches one 64-node segment of a line); 2 = 16 bytes per lane (4 consecutive fp32
+       or 2 fp64 nodes, a wavefront marching 256 or 128 nodes of a line: a quarter or half
+       of the vector memory instructions per node; needs nx a multiple of 4); 0 =
+       automatic (2 where nx is a multiple of 4 and above 128, else 1).    default 0 */
+    int32_t l0_wide;
 } saamg_options;
 
 /* Outcome of one solve. rel_res_* are ||r||/||b|| of the scaled system. */
@@ -157,6 +166,8 @@ typedef struct {
        table, scaling), spectral estimates, Galerkin products and their compression, the
        coarsest-level solver, fp32 copies */
     double t_setup_phase_ms[6];
+    int32_t l0_wide;                      /* 1: level-0 kernels on 16-byte lanes          */
+    int32_t l0_wide_planes[2];            /* their planes per block: fp32, fp64 lanes     */
 } saamg_info;
 
 typedef struct saamg_hierarchy saamg_hierarchy;
@@ -352,7 +363,8 @@ int saamg_level_apply(saamg_hierarchy* H, int level, int op, int precision, cons
 int saamg_level_coefficients(saamg_hierarchy* H, int level, double* h_out);
 /* One V-cycle z = M^-1 r on device box vectors of the scaled level-0 system (fp64). */
 int saamg_precond_apply(saamg_hierarchy* H, const double* d_r, double* d_z, void* stream);
-/* Scaled operator y = D^-1/2 A D^-1/2 x on device box vectors (fp64). */
+/* Scaled operator y = D^-1/2 A D^-1/2 x on device box vectors (fp64, 16-byte aligned,
+   else SAAMG_INVALID_ARG). */
 int saamg_operator_apply(saamg_hierarchy* H, const double* d_x, double* d_y, void* stream);
 /* D^-1/2 as a device box vector (0 at non-unknowns), fp64. */
 int saamg_scaling(saamg_hierarchy* H, double* d_sigma, void* stream);

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsaamg.so")
-SOURCES = ["fine.hip", "coarse.hip", "solver.hip", "pic.hip", "timer.hip", "domain.cpp"]
+SOURCES = ["fine.hip", "wide.hip", "coarse.hip", "solver.hip", "pic.hip", "timer.hip", "domain.cpp"]
 # hbm_ceiling.hip is a separate program (see _build_ceiling), not part of the library
 ARCH = os.environ.get("SAAMG_ARCH", "gfx950")
 

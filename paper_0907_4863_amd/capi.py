@@ -48,7 +48,7 @@ class Options(C.Structure):
                 ("omega_scale", C.c_double), ("coarse_solver", C.c_int32),
                 ("coarse_sweeps", C.c_int32), ("l0_planes", C.c_int32),
                 ("l0_tile_x", C.c_int32), ("alloc", ALLOC_FN), ("free", FREE_FN),
-                ("alloc_ctx", C.c_void_p)]
+                ("alloc_ctx", C.c_void_p), ("l0_wide", C.c_int32)]
 
 
 class Grid(C.Structure):
@@ -74,7 +74,8 @@ class Info(C.Structure):
                 ("t_setup_ms", C.c_double), ("t_refresh_ms", C.c_double),
                 ("l0_planes", C.c_int32), ("l0_tile_x", C.c_int32),
                 ("table_rows", C.c_int64 * MAX_LEVELS), ("table_rows_t", C.c_int64 * MAX_LEVELS),
-                ("t_setup_phase_ms", C.c_double * 6)]
+                ("t_setup_phase_ms", C.c_double * 6), ("l0_wide", C.c_int32),
+                ("l0_wide_planes", C.c_int32 * 2)]
 
 
 class SaamgError(RuntimeError):
@@ -397,6 +398,7 @@ def hierarchy_info(H: Hierarchy) -> dict:
         "n_irregular": info.n_irregular, "device_bytes": info.device_bytes,
         "t_setup_ms": info.t_setup_ms, "t_refresh_ms": info.t_refresh_ms,
         "l0_planes": info.l0_planes, "l0_tile_x": info.l0_tile_x,
+        "l0_wide": info.l0_wide, "l0_wide_planes": list(info.l0_wide_planes),
         "table_rows": [info.table_rows[l] for l in range(n)],
         "table_rows_t": [info.table_rows_t[l] for l in range(n)],
         "t_setup_phase_ms": dict(zip(("host_checks", "level0", "spectral", "galerkin",

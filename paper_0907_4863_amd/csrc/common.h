@@ -232,6 +232,10 @@ struct FineLevel {
     int nx, ny, nz, nsegx;
     int zb = 4;                 // planes per block of the solve-time kernels
     int tx = 1;                 // segments per block along x of the solve-time kernels
+    // 16-byte lanes (wide.hip): the V-cycle and CG kernels run with 4 (fp32) or 2 (fp64)
+    // nodes per lane; wzb[0] / wzb[1]: their planes per block with 2 / 4 nodes per lane
+    int wide = 0;
+    int wzb[2] = {2, 2};
     long nxy, nbox, nseg;
     double h[3];
     uint64_t* unk = nullptr;

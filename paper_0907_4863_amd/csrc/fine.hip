@@ -13,7 +13,7 @@
 // is zero at the nodes that are not unknowns from allocation on; kernels write only
 // unknown nodes, except that in mixed precision the kernels write whole rows (the zero
 // written back at the non-unknowns of the rows they store; kFullRows).
-#include "launch.h"
+#include "march.h"
 
 namespace saamg {
 
@@ -30,16 +30,6 @@ static inline long l0_meta_bytes(const FineLevel& L, int wsize, bool trans_too) 
     return L.nseg * 20 + L.n_irr * 6L * wsize * (trans_too ? 2 : 1);
 }
 
-// Whole-row stores.  A march kernel that stores whole rows writes every in-box lane of a
-// row (segment) with unknowns, the extra lanes writing the zero their node already holds,
-// so that each store instruction covers whole cache lines instead of being masked to the
-// unknowns.  Measured on the 256 x 256 x 768 elliptic pipe: when every level-0 kernel of
-// the mixed-precision solve stores whole rows, the CG kernels that read those vectors run
-// faster (k_cg_xr -15%, the solve -2%), while in fp64 the wider writes cost the writers
-// more than they save (the fp64 V-cycle kernels +1%, k_cg_pq +3%), so fp64 keeps masked
-// stores.
-template <typename T>
-constexpr bool kFullRows = sizeof(T) == 4;
 
 // Planes per block for the solve-time kernels: long z-marches, but enough blocks to
 // fill the chip a few times over.
@@ -49,6 +39,45 @@ int l0_choose_zb(int tx, int nsegx, int ny, int nz) {
     const long tiles = (long)((nsegx + tx - 1) / tx) * ((ny + ty - 1) / ty);
     int zb = 32;
     while (zb > 2 && tiles * ((nz + zb - 1) / zb) < kMinBlocks) zb /= 2;
+    return zb;
+}
+
+// 16-byte lanes by default where rows start 16-byte aligned and a line spans more than two
+// 64-node segments (shorter lines would leave most lanes of a 256-node span idle).
+bool l0_wide_default(int nx) { return nx % 4 == 0 && nx > 128; }
+
+// Which level-0 launchers run on 16-byte lanes when the hierarchy uses them (measured per
+// kernel on the 256 x 256 x 768 elliptic pipe, one-node against 16-byte lanes, us per
+// launch): every V-cycle kernel in both precisions (fp32 residual 132 -> 119, restriction
+// pass 125 -> 101, prolongation 130 -> 113; fp64 residual 282 -> 215, restriction pass
+// 208 -> 158), the fp64 residual and the direction update with an fp64 z (511 -> 489).
+// The direction update with an fp32 z (456 against 465) and the streaming r -= alpha q
+// (234 against 242, fp64 192 against 199) keep one node per lane.
+static bool pq_wide(const FineLevel& L, bool z32) { return L.wide && !z32; }
+
+long cg_resid_parts(const FineLevel& L) { return L.wide ? l0_wblocks(L, 2) : l0_blocks(L); }
+long cg_pq_parts(const FineLevel& L, bool z32) {
+    return pq_wide(L, z32) ? l0_wblocks(L, 2) : l0_blocks(L);
+}
+long cg_xr_parts(const FineLevel& L) { return l0_blocks(L); }
+long l0_dot_parts(const FineLevel& L, int bytes) {
+    return L.wide ? l0_wblocks(L, l0_lanes(bytes)) : l0_blocks(L);
+}
+
+// Planes per block of the kernels on 16-byte lanes: at most 64 / n - 2 (the per-tile word
+// preload), else as l0_choose_zb with a lower block target (the wider lanes need fewer
+// wavefronts to keep the memory system busy; measured on the 256 x 256 x 768 box, 4 nodes
+// per lane: 8 planes 110.1 us, 16 planes 110.0 us, 4 planes 113.3 us per residual).
+constexpr long kMinWideBlocks = 2048;
+int l0_wide_zb(const FineLevel& L, int n, int planes) {
+    const int cap = kWave / n - 2;
+    if (planes) return std::min(planes, cap);
+    int zb = 1;
+    while (2 * zb <= cap) zb *= 2;
+    const int nws = (L.nx + kWave * n - 1) / (kWave * n);
+    const int tx = nws >= kMY ? kMY : (nws >= 2 ? 2 : 1);
+    const long tiles = (long)((nws + tx - 1) / tx) * ((L.ny + kMY / tx - 1) / (kMY / tx));
+    while (zb > 2 && tiles * ((L.nz + zb - 1) / zb) < kMinWideBlocks) zb /= 2;
     return zb;
 }
 
@@ -100,59 +129,6 @@ __device__ inline L0Node l0_node(const L0View<T>& v, int x, int y, int z) {
 
 // ---------------------------------------------------------------- solve-time engine
 
-// Segment, line and z-slab of this wavefront: the block's tile (after the XCD-aware
-// remap) holds tx consecutive segments of kMY / tx consecutive lines.
-template <typename T>
-__device__ inline void l0_tile(const L0View<T>& v, int* seg, int* y, int* bz) {
-    // block counts fit in 32 bits: unsigned arithmetic keeps the divisions short
-    const unsigned b = blockIdx.x, nb = gridDim.x;
-    const unsigned q = nb >> 3;
-    const unsigned lb = (b < 8 * q) ? (b & 7) * q + (b >> 3) : b;
-    const int w = threadIdx.y;
-    const unsigned gx = (unsigned)v.gx, gy = (unsigned)v.gy;
-    const unsigned t = lb / gx;
-    *seg = (int)(lb % gx) * v.tx + w % v.tx;
-    *y = (int)(t % gy) * (kMY / v.tx) + w / v.tx;
-    *bz = (int)(t / gy);
-}
-
-// Box index of a lane's node, split into a wave-uniform part and the lane's offset, so
-// that an access through at() addresses memory as a scalar base plus a 32-bit vector
-// offset and needs no 64-bit vector address arithmetic.
-struct Idx {
-    long b;      // wave-uniform
-    unsigned o;  // per lane
-    __device__ operator long() const { return b + (long)o; }
-};
-template <class E>
-__device__ __forceinline__ E& at(E* a, Idx k) {
-    // the byte offset is formed in 32 bits (lane offsets are small)
-    using C = std::conditional_t<std::is_const<E>::value, const char, char>;
-    return *reinterpret_cast<E*>(reinterpret_cast<C*>(a + k.b) + k.o * (unsigned)sizeof(E));
-}
-
-// Store of a solve kernel's output: a nontemporal (streaming) store.  The outputs are
-// written once per launch and are far larger than the caches, which then keep the
-// stencil rows the march re-reads (measured: the level-0 kernels 1-5% faster).
-template <class E, class V>
-__device__ __forceinline__ void nts(E* a, Idx k, V v) {
-    __builtin_nontemporal_store((E)v, &at(a, k));
-}
-
-// Load of an operand a solve kernel reads once per node (not a stencil operand): a
-// nontemporal load, for the same reason.  k_cg_pq keeps ordinary loads (slower there).
-template <class E>
-__device__ __forceinline__ std::remove_const_t<E> ntl(E* a, Idx k) {
-    return __builtin_nontemporal_load(&at(a, k));
-}
-
-// 64-bit value of lane k of a wavefront, as a wave-uniform (scalar) value.
-__device__ inline uint64_t lane_u64(uint64_t v, int k) {
-    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, k);
-    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), k);
-    return ((uint64_t)hi << 32) | lo;
-}
-
 // March over this block's tile.  One wavefront owns one 64-node segment row and walks
 // it along z.  For every unknown node the march calls
 //   fv = fetch(i, x, y, z, irr, rk)            (loads, issued one plane ahead)
@@ -187,73 +163,6 @@ struct PlaneLoads {
     TX nxt, ym, yp, edge;  // X at (x, y, z+1), (x, y-1, z), (x, y+1, z), lane-edge x-neighbour
     T t[6];                // table row of an irregular node
     FV fv;
-};
-
-// An empty use of every 32-bit word of a loaded record.  The march calls it at the start
-// of each plane step so that, on every path through the step (including the ones that
-// skip the plane's arithmetic), the plane's loads have landed before the loop goes round.
-// Without it a load can still be in flight at the loop back-edge, and the compiler must
-// wait for all outstanding loads, the next plane's included, before it reuses that
-// load's registers, which serialises the two-plane pipeline.
-template <class R>
-__device__ __forceinline__ void settle(const R& r) {
-    if constexpr (sizeof(R) >= 4) {
-        uint32_t w[sizeof(R) / 4];
-        __builtin_memcpy(w, &r, sizeof(w));
-#pragma unroll
-        for (unsigned k = 0; k < sizeof(R) / 4; ++k) asm volatile("" ::"v"(w[k]));
-    }
-}
-
-// Table row b + o (b wave-uniform, o per lane) of an 8-wide coefficient table: its 6
-// values in two 16-byte loads (fp32; the second narrowed to 8 bytes) or three (fp64).
-template <typename T>
-__device__ __forceinline__ void load_row6(const T* tb, long b, unsigned o, T t[6]) {
-    const char* p = reinterpret_cast<const char*>(tb + 8 * b) + (size_t)o * (8 * sizeof(T));
-    if constexpr (sizeof(T) == 4) {
-        const float4 a = *reinterpret_cast<const float4*>(p);
-        const float2 c = *reinterpret_cast<const float2*>(p + 16);
-        t[0] = a.x; t[1] = a.y; t[2] = a.z; t[3] = a.w; t[4] = c.x; t[5] = c.y;
-    } else {
-        const double2 a = *reinterpret_cast<const double2*>(p);
-        const double2 c = *reinterpret_cast<const double2*>(p + 16);
-        const double2 e = *reinterpret_cast<const double2*>(p + 32);
-        t[0] = a.x; t[1] = a.y; t[2] = c.x; t[3] = c.y; t[4] = e.x; t[5] = e.y;
-    }
-}
-
-// Lane clamped to the span of the set bits of u (u == 0: lane 0).
-__device__ inline int span_lane(uint64_t u, int lane) {
-    const int lo = u ? (int)__builtin_ctzll(u) : 0;
-    const int hi = u ? 63 - (int)__builtin_clzll(u) : 0;
-    return min(max(lane, lo), hi);
-}
-
-// Whole-wavefront shift by one lane (DPP wave_shr:1 / wave_shl:1): lane l receives
-// lane l-1 (UP) or l+1 (down); the lane without a source keeps `edge`.
-template <bool UP, class V>
-__device__ __forceinline__ V wave_shift(V src, V edge) {
-    constexpr int ctrl = UP ? 0x138 : 0x130;
-    if constexpr (sizeof(V) == 4) {
-        return __builtin_bit_cast(V, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
-                                                                 __builtin_bit_cast(int, src), ctrl,
-                                                                 0xf, 0xf, false));
-    } else {
-        static_assert(sizeof(V) == 8, "4- or 8-byte values");
-        const uint64_t s = __builtin_bit_cast(uint64_t, src), e = __builtin_bit_cast(uint64_t, edge);
-        const uint32_t lo = __builtin_amdgcn_update_dpp((int)(uint32_t)e, (int)(uint32_t)s, ctrl,
-                                                        0xf, 0xf, false);
-        const uint32_t hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(e >> 32),
-                                                        (int)(uint32_t)(s >> 32), ctrl, 0xf, 0xf,
-                                                        false);
-        return __builtin_bit_cast(V, ((uint64_t)hi << 32) | lo);
-    }
-}
-
-// Optional per-plane hook of the march: end(z, last, x, y) after plane z's arithmetic, on
-// every lane (x = its node's x, y = the row; last: the tile's final plane).
-struct NoEnd {
-    __device__ void operator()(int, bool, int, int) const {}
 };
 
 template <typename T, bool STENCIL, bool TR, bool FULL = false, class Load, class Fetch, class Body,
@@ -400,13 +309,6 @@ __device__ __forceinline__ void l0_march(const L0View<T>& v, Load X, Fetch fetch
     }
 }
 
-// Small fixed-size records for the fetch phase.
-template <typename A, int N>
-struct Vals {
-    A v[N];
-};
-struct NoVals {};
-#define NOFETCH [&](long, int, int, int, bool, int) { return NoVals{}; }
 
 // ================================================================ finalisation
 
@@ -795,6 +697,10 @@ template <typename T>
 void l0_apply(const FineLevel& L, bool trans, const T* x, T* y, hipStream_t s) {
     L0View<T> v = L.view<T>();
     HIPCHECK(hipMemsetAsync(y, 0, sizeof(T) * L.nbox, s));
+    if (L.wide) {
+        w_apply<T>(L, trans, x, y, s);
+        return;
+    }
     if (trans)
         hipLaunchKernelGGL((k_l0_apply<T, true>), l0_mgrid(L), dim3(kWave, kMY), 0, s, v, x, y);
     else
@@ -971,6 +877,12 @@ void l0_cheb(const FineLevel& L, int mode, const TF* f, const T* xin, const T* d
     const long vec = (mode == CHEB_ZERO1 || mode == CHEB_ZERO2) ? wf + w
                      : (mode == CHEB_FIRST) ? wf + 2 * w : wf + 3 * w;
     KTimer kt_(T_L0_CHEB, s, n * (vec + (dout ? w : 0) + (dot && fdot ? 8 : 0)) + l0_meta_bytes(L, w, false));
+    if constexpr (std::is_same_v<TF, T>) {
+        if (L.wide) {
+            w_cheb<T>(L, mode, f, xin, din, xout, dout, c1, c2, c2_0, fdot, dot, kt_);
+            return;
+        }
+    }
     L0View<T> v = L.view<T>();
     dim3 g = l0_mgrid(L), b(kWave, kMY);
 #define CHEB_LAUNCH(M)                                                                         \
@@ -1013,6 +925,12 @@ template <typename TF, typename T>
 void l0_residual(const FineLevel& L, const TF* f, const T* x, T* r, hipStream_t s) {
     KTimer kt_(T_L0_RESID, s, L.n_unknowns * (long)(sizeof(TF) + 2 * sizeof(T)) +
                                  l0_meta_bytes(L, sizeof(T), false));
+    if constexpr (std::is_same_v<TF, T>) {
+        if (L.wide) {
+            w_residual<T>(L, f, x, r, kt_);
+            return;
+        }
+    }
     klaunch(kt_, true, (k_l0_residual<TF, T>), l0_mgrid(L), dim3(kWave, kMY), L.view<T>(), f, x,
             r);
     HIPCHECK(hipGetLastError());
@@ -1071,12 +989,16 @@ void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* 
                  double omega, hipStream_t s) {
     KTimer kt_(T_L0_RESTRICT, s, (L.n_unknowns * 5 / 3 + C.n_unknowns * (fd ? 3 : 1)) *
                                         (long)sizeof(T) + l0_meta_bytes(L, sizeof(T), true));
-    // z-slabs of a multiple of 3 planes, so that no aggregate plane is split between tiles
-    L0View<T> v = L.view<T>();
-    v.zb = std::max(3, L.zb / 3 * 3);
-    const long blocks = (long)v.gx * v.gy * ((L.nz + v.zb - 1) / v.zb);
-    klaunch(kt_, false, (k_l0_restrict_y<T>), dim3((unsigned)blocks), dim3(kWave, kMY), v, r, y,
-            (T)omega);
+    if (L.wide) {
+        w_restrict_y<T>(L, r, y, omega, kt_);
+    } else {
+        // z-slabs of a multiple of 3 planes, so that no aggregate plane is split between tiles
+        L0View<T> v = L.view<T>();
+        v.zb = std::max(3, L.zb / 3 * 3);
+        const long blocks = (long)v.gx * v.gy * ((L.nz + v.zb - 1) / v.zb);
+        klaunch(kt_, false, (k_l0_restrict_y<T>), dim3((unsigned)blocks), dim3(kWave, kMY), v, r,
+                y, (T)omega);
+    }
     dim3 g((unsigned)(((long)C.mx * C.my + 255) / 256), C.mz);
     klaunch(kt_, true, (k_l0_restrict_sum<T>), g, dim3(256), L.nx, L.ny, L.nz, C.view<T>(),
             (const T*)y, fc, fd);
@@ -1154,6 +1076,10 @@ void l0_prolong(const FineLevel& L, const CoarseLevel& C, const T* vc, T* x, dou
                 hipStream_t s) {
     KTimer kt_(T_L0_PROLONG, s, (2 * L.n_unknowns + C.n_unknowns) * (long)sizeof(T) +
                                    l0_meta_bytes(L, sizeof(T), false));
+    if (L.wide) {
+        w_prolong<T>(L, C, vc, x, omega, kt_);
+        return;
+    }
     klaunch(kt_, true, (k_l0_prolong<T>), l0_mgrid(L), dim3(kWave, kMY), L.view<T>(), C.view<T>(),
             vc, x, (T)omega);
     HIPCHECK(hipGetLastError());
@@ -1217,6 +1143,10 @@ __global__ void __launch_bounds__(kMThreads) k_cg_resid(L0View<double> v, const 
 
 void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
               float* r32, hipStream_t s) {
+    if (L.wide) {
+        w_cg_resid(L, bs, x, r, partials, r32, s);
+        return;
+    }
     hipLaunchKernelGGL(k_cg_resid, l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), bs,
                        x, r, partials, r32);
     HIPCHECK(hipGetLastError());
@@ -1260,6 +1190,12 @@ template <typename TZ>
 void cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
            double* partials, hipStream_t s) {
     KTimer kt_(T_CG_PQ, s, L.n_unknowns * (long)(sizeof(TZ) + 48) + l0_meta_bytes(L, 8, false));
+    if constexpr (sizeof(TZ) == 8) {
+        if (pq_wide(L, false)) {
+            w_cg_pq<TZ>(L, z, x, p, q, scal, partials, kt_);
+            return;
+        }
+    }
     klaunch(kt_, true, (k_cg_pq<TZ>), l0_mgrid(L), dim3(kWave, kMY), L.view<double>(), z, x, p, q,
             scal, partials);
     HIPCHECK(hipGetLastError());
@@ -1377,6 +1313,10 @@ __global__ void __launch_bounds__(kMThreads) k_l0_dot(L0View<double> v, const do
 
 template <typename T>
 void l0_dot(const FineLevel& L, const double* a, const T* b, double* partials, hipStream_t s) {
+    if (L.wide) {
+        w_dot<T>(L, a, b, partials, s);
+        return;
+    }
     hipLaunchKernelGGL((k_l0_dot<T>), l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), a,
                        b, partials);
     HIPCHECK(hipGetLastError());

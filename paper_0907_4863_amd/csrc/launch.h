@@ -41,9 +41,25 @@ void pic_deposit(saamg_pic* P, const double* pos, long n, double q, double* rho,
 void pic_gather(saamg_pic* P, const double* phi, const double* pos, long n, double* E, hipStream_t s);
 size_t pic_sort_bytes(long n, int bits);
 
-// Number of partial sums (blocks) written by the level-0 reduction kernels.
+// Nodes per lane of the level-0 kernels on 16-byte lanes, for values of `bytes` bytes.
+constexpr int l0_lanes(int bytes) { return 16 / bytes; }
+// Number of partial sums (blocks) written by the level-0 reduction kernels of the
+// 64-node engine (the Lanczos kernels), and by those on 16-byte lanes with n nodes per lane.
 long l0_blocks(const FineLevel& L);
+long l0_wblocks(const FineLevel& L, int n);
+// Partial sums (blocks) that the level-0 reduction launchers below write, for the lanes
+// each of them runs on (FineLevel::wide: see the launchers): cg_resid, cg_pq (fp32 z or
+// not), cg_xr, and the V-cycle's fused r . z (its last Chebyshev step, or l0_dot) in a
+// working precision of `bytes` bytes.
+long cg_resid_parts(const FineLevel& L);
+long cg_pq_parts(const FineLevel& L, bool z32);
+long cg_xr_parts(const FineLevel& L);
+long l0_dot_parts(const FineLevel& L, int bytes);
 int l0_choose_zb(int tx, int nsegx, int ny, int nz);
+// 16-byte lanes: whether a box of nx nodes per line uses them by default, and the planes
+// per block with n nodes per lane (planes: 0 = automatic, else the option's value, capped)
+bool l0_wide_default(int nx);
+int l0_wide_zb(const FineLevel& L, int n, int planes);
 long lc_blocks(const CoarseLevel& C);
 
 void finalize(const double* partials, long nblk, int nq, double* scal, int op, int dst,
@@ -89,6 +105,29 @@ void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* 
 template <typename T>
 void l0_prolong(const FineLevel& L, const CoarseLevel& C, const T* v, T* x, double omega,
                 hipStream_t s);
+
+// ---- level 0 on 16-byte lanes (wide.hip; FineLevel::wide).  The launchers of fine.hip
+// dispatch to these; they take the caller's kernel timer.
+template <typename T>
+void w_apply(const FineLevel& L, bool trans, const T* x, T* y, hipStream_t s);
+template <typename T>
+void w_cheb(const FineLevel& L, int mode, const T* f, const T* xin, const T* din, T* xout,
+            T* dout, double c1, double c2, double c2_0, const double* fdot, double* dot,
+            KTimer& kt);
+template <typename T>
+void w_residual(const FineLevel& L, const T* f, const T* x, T* r, KTimer& kt);
+template <typename T>
+void w_restrict_y(const FineLevel& L, const T* r, T* y, double omega, KTimer& kt);
+template <typename T>
+void w_prolong(const FineLevel& L, const CoarseLevel& C, const T* vc, T* x, double omega,
+               KTimer& kt);
+template <typename T>
+void w_dot(const FineLevel& L, const double* a, const T* b, double* partials, hipStream_t s);
+void w_cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
+                float* r32, hipStream_t s);
+template <typename TZ>
+void w_cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
+             double* partials, KTimer& kt);
 
 // ---- level 0: CG (fp64)
 void cg_init(const FineLevel& L, const double* b, const double* x0, double* bs, double* x,

@@ -177,6 +177,11 @@ void* dmalloc(size_t bytes) {
         if (!p)
             throw ApiError{SAAMG_NOMEM, "the allocator returned NULL for " + std::to_string(bytes) +
                                             " bytes"};
+        // the level-0 kernels read and write 16 bytes per lane
+        if (reinterpret_cast<uintptr_t>(p) & 255u) {
+            g_mem.free(g_mem.ctx, p, (void*)g_mem.s);
+            throw ApiError{SAAMG_INVALID_ARG, "the allocator returned memory not aligned to 256 bytes"};
+        }
     } else {
         p = pool_alloc(bytes);
     }
@@ -396,6 +401,9 @@ namespace saamg {
 // saamg_set_operator gave it (the preconditioner then keeps the hierarchy's).
 static const FineLevel& cg_op(const saamg_hierarchy* H) { return H->op ? *H->op : H->l0; }
 
+// Partial sums written by the V-cycle's fused r . z (in the working precision).
+static long pc_parts(const saamg_state* S) { return l0_dot_parts(S->H->l0, S->mixed ? 4 : 8); }
+
 // pinned = false: no pinned host buffer and no event (the allocation-free solve); the
 // scalars are read into the state itself and the host waits on the stream.
 static void state_alloc(saamg_state* S, saamg_hierarchy* H, bool pinned = true) {
@@ -418,6 +426,8 @@ static void state_alloc(saamg_state* S, saamg_hierarchy* H, bool pinned = true) 
         S->bytes += S->vd.bytes(H);
     }
     S->npart = std::max<long>(l0_blocks(H->l0), 1);
+    if (H->l0.wide)
+        S->npart = std::max(S->npart, std::max(l0_wblocks(H->l0, 2), l0_wblocks(H->l0, 4)));
     S->part = (double*)dmalloc(sizeof(double) * 3 * S->npart);
     S->scal = (double*)dmalloc(sizeof(double) * S_NSLOTS);
     if (!pinned) {
@@ -468,7 +478,7 @@ static void precond(saamg_state* S, bool skippable = true) {
 // True residual b - A x into `dst`; returns ||dst||^2.
 static double true_residual(saamg_state* S, double* dst) {
     cg_resid(cg_op(S->H), S->bs, S->x, dst, S->part, dst == S->r ? S->r32 : nullptr, S->s);
-    finalize(S->part, l0_blocks(S->H->l0), 2, S->scal, FIN_STORE, S_RT, S->s);
+    finalize(S->part, cg_resid_parts(cg_op(S->H)), 2, S->scal, FIN_STORE, S_RT, S->s);
     read_scal(S);
     return S->hscal[S_RT];
 }
@@ -482,7 +492,7 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
     S->t0 = std::chrono::steady_clock::now();
     cg_init(cg_op(H), b, x0, S->bs, S->x, S->s);
     cg_resid(cg_op(H), S->bs, S->x, S->r, S->part, S->r32, S->s);
-    finalize(S->part, l0_blocks(H->l0), 2, S->scal, FIN_STORE, S_RR, S->s);
+    finalize(S->part, cg_resid_parts(cg_op(H)), 2, S->scal, FIN_STORE, S_RR, S->s);
     scal_start(S->scal, S->tol, S->s);
     zero_fill(S->p, 8 * H->l0.nbox, S->s);
     zero_fill(S->q, 8 * H->l0.nbox, S->s);
@@ -513,26 +523,26 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
         return;
     }
     precond(S);
-    finalize(S->part, l0_blocks(H->l0), 1, S->scal, FIN_RHO_INIT, 0, S->s);
+    finalize(S->part, pc_parts(S), 1, S->scal, FIN_RHO_INIT, 0, S->s);
 }
 
 // Queue one PCG step plus the (speculative) preconditioner of the next one.
 static void state_enqueue(saamg_state* S) {
     const saamg_hierarchy* H = S->H;
-    const long nb = l0_blocks(H->l0);
+    const FineLevel& L = cg_op(H);
     if (S->mixed)
-        cg_pq<float>(cg_op(H), (const float*)S->z, S->x, S->p, S->q, S->scal, S->part, S->s);
+        cg_pq<float>(L, (const float*)S->z, S->x, S->p, S->q, S->scal, S->part, S->s);
     else
-        cg_pq<double>(cg_op(H), (const double*)S->z, S->x, S->p, S->q, S->scal, S->part, S->s);
-    finalize(S->part, nb, 1, S->scal, FIN_ALPHA, 0, S->s);
-    cg_xr(cg_op(H), S->r, S->q, S->scal, S->part, S->r32, S->s);
-    finalize(S->part, nb, 1, S->scal, FIN_RR, 0, S->s);
+        cg_pq<double>(L, (const double*)S->z, S->x, S->p, S->q, S->scal, S->part, S->s);
+    finalize(S->part, cg_pq_parts(L, S->mixed), 1, S->scal, FIN_ALPHA, 0, S->s);
+    cg_xr(L, S->r, S->q, S->scal, S->part, S->r32, S->s);
+    finalize(S->part, cg_xr_parts(L), 1, S->scal, FIN_RR, 0, S->s);
     HIPCHECK(hipMemcpyAsync(S->hscal, S->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
                             S->s));
     if (S->ev) HIPCHECK(hipEventRecord(S->ev, S->s));
     S->inflight = true;
     precond(S);
-    finalize(S->part, nb, 1, S->scal, FIN_RHO, 0, S->s);
+    finalize(S->part, pc_parts(S), 1, S->scal, FIN_RHO, 0, S->s);
 }
 
 // The step length a step still owes x (each step's x += alpha p is applied by the next
@@ -584,7 +594,7 @@ static void state_complete(saamg_state* S) {
         // continue from the true residual: redo the preconditioner on it (the restore
         // also clears the device's skip flag; the host copy follows)
         S->repl += 1;
-        const long nb = l0_blocks(S->H->l0);
+        const long nb = pc_parts(S);
         finalize(S->part, nb, 0, S->scal, FIN_RESTORE_RHO, 0, S->s);
         precond(S);
         finalize(S->part, nb, 1, S->scal, FIN_RHO, 0, S->s);
@@ -601,7 +611,7 @@ static void state_complete(saamg_state* S) {
         // the device skipped the queued V-cycle while the host goes on (the two tests
         // use the same expression, so only a rounding difference could cause this): redo
         // that step's preconditioner
-        const long nb = l0_blocks(S->H->l0);
+        const long nb = pc_parts(S);
         finalize(S->part, nb, 0, S->scal, FIN_RESTORE_RHO, 0, S->s);
         precond(S);
         finalize(S->part, nb, 1, S->scal, FIN_RHO, 0, S->s);
@@ -776,6 +786,8 @@ static void validate_options(const saamg_options& o) {
         throw ApiError{SAAMG_INVALID_ARG, "l0_tile_x must be 0, 1, 2 or 4"};
     if ((o.alloc == nullptr) != (o.free == nullptr))
         throw ApiError{SAAMG_INVALID_ARG, "alloc and free must both be set or both be NULL"};
+    if (o.l0_wide < 0 || o.l0_wide > 2)
+        throw ApiError{SAAMG_INVALID_ARG, "l0_wide must be 0, 1 or 2"};
 }
 
 // Host-side checks of a domain and its near-wall rows: wall fractions below 1 (the
@@ -1074,6 +1086,11 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
             throw ApiError{SAAMG_INVALID_ARG, "l0_tile_x exceeds the 64-node segments of a line"};
         L.tx = o.l0_tile_x ? o.l0_tile_x : l0_tile_x(L.nsegx);
         L.zb = o.l0_planes ? o.l0_planes : l0_choose_zb(L.tx, L.nsegx, ny, nz);
+        if (o.l0_wide == 2 && nx % 4 != 0)
+            throw ApiError{SAAMG_INVALID_ARG, "l0_wide = 2 needs nx to be a multiple of 4"};
+        L.wide = o.l0_wide == 2 ? 1 : (o.l0_wide == 1 ? 0 : (int)l0_wide_default(nx));
+        L.wzb[0] = l0_wide_zb(L, 2, o.l0_planes);
+        L.wzb[1] = l0_wide_zb(L, 4, o.l0_planes);
         L.unk = (uint64_t*)dmalloc(8 * L.nseg);
         L.irr = (uint64_t*)dmalloc(8 * L.nseg);
         L.base = (int32_t*)dmalloc(4 * L.nseg);
@@ -1443,6 +1460,7 @@ void saamg_default_options(saamg_options* o) {
     o->coarse_sweeps = 3;
     o->l0_planes = 0;
     o->l0_tile_x = 0;
+    o->l0_wide = 0;
     o->alloc = nullptr;
     o->free = nullptr;
     o->alloc_ctx = nullptr;
@@ -1529,6 +1547,9 @@ int saamg_hierarchy_info(const saamg_hierarchy* H, saamg_info* info) {
         for (int q = 0; q < 6; ++q) info->t_setup_phase_ms[q] = H->t_phase_ms[q];
         info->l0_planes = H->l0.zb;
         info->l0_tile_x = H->l0.tx;
+        info->l0_wide = H->l0.wide;
+        info->l0_wide_planes[0] = H->l0.wzb[1];
+        info->l0_wide_planes[1] = H->l0.wzb[0];
         for (int l = 1; l < H->n_levels; ++l) {
             info->table_rows[l] = H->lc[l - 1].n_tab;
             info->table_rows_t[l] = H->lc[l - 1].sym ? 0 : H->lc[l - 1].n_tabT;
@@ -1799,6 +1820,8 @@ int saamg_precond_apply(saamg_hierarchy* H, const double* d_r, double* d_z, void
 int saamg_operator_apply(saamg_hierarchy* H, const double* d_x, double* d_y, void* stream) {
     return guarded([&] {
         if (!H || !d_x || !d_y) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        if ((reinterpret_cast<uintptr_t>(d_x) | reinterpret_cast<uintptr_t>(d_y)) & 15u)
+            throw ApiError{SAAMG_INVALID_ARG, "d_x and d_y must be 16-byte aligned"};
         HIPCHECK(hipSetDevice(H->device));
         l0_apply<double>(cg_op(H), false, d_x, d_y, (hipStream_t)stream);
         HIPCHECK(hipStreamSynchronize((hipStream_t)stream));

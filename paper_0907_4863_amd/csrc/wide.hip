@@ -1,0 +1,787 @@
+// Level-0 solve kernels on 16-byte lanes.
+//
+// The same z-march as the 64-node engine of fine.hip, except that every lane holds N
+// consecutive nodes of its line (N = 4 in fp32, 2 in fp64) and reads and writes them with
+// one 16-byte access, so that a wavefront covers 64 N nodes of a line.  The level-0
+// kernels are limited by the rate of vector memory instructions rather than by bytes:
+// a fp32 7-point residual on a full 256 x 256 x 768 box, marched as here, measured
+// 137.6 us with 4-byte lanes, 121.7 us with 8-byte and 110.0 us with 16-byte lanes
+// (5.5 TB/s), with identical results.  This engine issues a quarter (fp32) or half (fp64)
+// of the 64-node engine's vector memory instructions per node.  It needs rows that start
+// 16-byte aligned (nx a multiple of 4) and lines long enough to fill the lanes; the
+// hierarchy decides once (FineLevel::wide).
+//
+// Tiles: a block of kMY wavefronts takes tx consecutive wavefront spans of a line and
+// kMY / tx lines (the 64-node engine's tile mapping, with its XCD-aware block remap), and
+// marches zb planes.  The segment words of a wavefront's span (N 64-node segments) for
+// planes z0-1 .. z1 are fetched up front, one (plane, segment) pair per lane, which bounds
+// the planes per block by 64 / N - 2.
+#include "march.h"
+
+namespace saamg {
+
+template <typename E, int N>
+struct Vec {
+    E v[N];
+};
+
+template <typename E, int N>
+struct ExtVec {
+    typedef E type __attribute__((ext_vector_type(N)));
+};
+
+// N consecutive elements at a + k (k.b + k.o a multiple of N): one access.
+template <int N, class E>
+__device__ __forceinline__ Vec<std::remove_const_t<E>, N> vld(E* a, Idx k) {
+    using U = std::remove_const_t<E>;
+    using VT = typename ExtVec<U, N>::type;
+    const VT t = *reinterpret_cast<const VT*>(&at(a, k));
+    Vec<U, N> r;
+#pragma unroll
+    for (int e = 0; e < N; ++e) r.v[e] = t[e];
+    return r;
+}
+template <int N, class E>
+__device__ __forceinline__ Vec<std::remove_const_t<E>, N> vldnt(E* a, Idx k) {
+    using U = std::remove_const_t<E>;
+    using VT = typename ExtVec<U, N>::type;
+    const VT t = __builtin_nontemporal_load(reinterpret_cast<const VT*>(&at(a, k)));
+    Vec<U, N> r;
+#pragma unroll
+    for (int e = 0; e < N; ++e) r.v[e] = t[e];
+    return r;
+}
+template <int N, class E, class V>
+__device__ __forceinline__ void vstnt(E* a, Idx k, const V (&v)[N]) {
+    using VT = typename ExtVec<E, N>::type;
+    VT t;
+#pragma unroll
+    for (int e = 0; e < N; ++e) t[e] = (E)v[e];
+    __builtin_nontemporal_store(t, reinterpret_cast<VT*>(&at(a, k)));
+}
+
+template <typename T, int N>
+__device__ __forceinline__ Vec<T, N> vzero() {
+    Vec<T, N> r;
+#pragma unroll
+    for (int e = 0; e < N; ++e) r.v[e] = T(0);
+    return r;
+}
+
+// Loads of one plane of a wavefront's row (the 16-byte-lane counterpart of PlaneLoads).
+template <typename T, typename TX, int N, class FV>
+struct WPlane {
+    unsigned nib;   // unknown bits of the lane's N nodes
+    unsigned nibr;  // irregular bits
+    int rk0;        // table slot of the lane's first irregular node
+    int sp;         // the row's packed span word (wave-uniform; see wmarch)
+    int tb0;        // table slot of the row's first irregular node (wave-uniform)
+    bool ins1;      // lane inside the row's unknown span (in lanes) in plane z+1
+    long ib;        // box index of the span's first node in this plane (wave-uniform)
+    Vec<TX, N> nxt, ym, yp;  // X at (z+1), (y-1), (y+1)
+    TX edge;        // lanes 0 and 63: X beyond the span's ends (0 at the line's ends)
+    typename ExtVec<T, 16 / sizeof(T)>::type trow;  // 16 bytes of the row's first table rows
+    FV fv;
+};
+
+// One 8-value table row (6 used) from 16-byte pieces p[0..].
+template <typename T, class TV>
+__device__ __forceinline__ void row6(const TV* p, T t[6]) {
+    if constexpr (sizeof(T) == 4) {
+        const TV a = p[0], b = p[1];
+        t[0] = a[0]; t[1] = a[1]; t[2] = a[2]; t[3] = a[3]; t[4] = b[0]; t[5] = b[1];
+    } else {
+        const TV a = p[0], b = p[1], c = p[2];
+        t[0] = a[0]; t[1] = a[1]; t[2] = b[0]; t[3] = b[1]; t[4] = c[0]; t[5] = c[1];
+    }
+}
+
+// March of a tile on 16-byte lanes.  For every lane with unknowns (FULL: every lane in
+// the box of a row with unknowns) the march calls
+//   fv = fetch(i, x, y, z, nibr, rk0)          (loads, issued one plane ahead)
+//   body(i, fv, c, ax, x, y, z, nib)           (arithmetic and stores)
+// where i / x address the lane's first node (fetch: the span-clamped lane's, as in the
+// 64-node engine; nibr and rk0 are the lane's own irregular bits and first table slot),
+// c holds X at the lane's N nodes and, when STENCIL, ax = (A X) there (TR: A^T X), and
+// nib the lane's unknown bits.  Values at nodes that are not unknowns are garbage to be
+// masked by the body.  X must be zero at nodes that are not unknowns; it may be null when
+// not STENCIL.  end(z, last, x, y) runs on every lane after each plane.
+//
+// Row bookkeeping is done once per tile: for each plane the lanes holding its N segment
+// words reduce them to one packed word (the span of the unknowns in lanes, whether the
+// row has unknowns and irregular nodes, and how many irregular nodes), which a plane step
+// reads with one broadcast; a lane takes its own segment word with cross-lane permutes.
+//
+// Table rows: the irregular nodes of a row's span have consecutive table slots, so the
+// wavefront reads them together, 16 bytes per lane (32 fp32 or 16 fp64 rows per load,
+// the first load issued a plane ahead), stages them in its slice of LDS, and each lane
+// reads the rows of its own irregular nodes from there.  Reading the rows lane by lane
+// instead issued up to 2 N loads per plane and took a quarter of the time of the fp32
+// stencil kernels.
+template <typename T, int N, bool STENCIL, bool TR, bool FULL, class TX, class Fetch, class Body,
+          class End = NoEnd>
+__device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict__ X, Fetch fetch,
+                                       Body body, End end = End{}) {
+    static_assert(N == 2 || N == 4, "16-byte lanes of 8- or 4-byte values");
+    using FV = decltype(fetch(Idx{0, 0u}, 0, 0, 0, 0u, 0));
+    using WP = WPlane<T, TX, N, FV>;
+    using TV = typename ExtVec<T, 16 / sizeof(T)>::type;
+    constexpr int W = kWave * N;      // nodes per wavefront span
+    constexpr int LPW = kWave / N;    // lanes per 64-bit segment word
+    constexpr unsigned NM = (1u << N) - 1u;
+    constexpr int RV = (int)sizeof(T) / 2;  // 16-byte pieces per table row
+    constexpr int R = kWave / RV;           // table rows per wavefront load
+    // packed span word: lo | hi << 8 | any << 16 | irregular << 17 | count << 18
+    constexpr int SP_ANY = 1 << 16, SP_IRR = 1 << 17, SP_CNT = 18;
+    __shared__ TV tl[kMY][kWave];  // each wavefront's staged table rows
+    if (v.skip && *v.skip != 0.0) return;  // wave-uniform: the whole grid returns
+    int ws, y, bz;
+    l0_tile(v, &ws, &y, &bz);
+    const int lane = threadIdx.x;
+    ws = __builtin_amdgcn_readfirstlane(ws);
+    y = __builtin_amdgcn_readfirstlane(y);
+    const int nws = (v.nx + W - 1) / W;
+    if (y < 1 || y > v.ny - 2 || ws >= nws) return;
+    const int z0 = max(bz * v.zb, 1), z1 = min(bz * v.zb + v.zb, v.nz - 1);
+    if (z0 >= z1) return;
+    const long nx = v.nx, nxy = v.nxy;
+    const T* tb = TR ? v.tabT : v.tab;
+    TV* const stage = tl[threadIdx.y];
+    // words of (plane k = lane / N, segment j = lane % N) of the span, planes z0-1 .. z1
+    uint64_t wu = 0, wr = 0;
+    int wb = 0;
+    if (lane < (z1 - z0 + 2) * N) {
+        const int k = lane / N, j = lane % N;
+        const int sgx = ws * N + j;
+        if (sgx < v.nsegx) {
+            const long sg = ((long)(z0 - 1 + k) * v.ny + y) * v.nsegx + sgx;
+            wu = v.unk[sg];
+            wr = v.irr[sg];
+            wb = v.base[sg];
+        }
+    }
+    if (__ballot(wu != 0) == 0) return;
+    const int x0 = ws * W;
+    const long rb = x0 + nx * y;  // box index of the span's first node at plane 0
+    const long ib_last = rb + nxy * (z1 - 1);
+    const int jl = lane / LPW;          // the lane's segment word
+    const int sh = (lane % LPW) * N;    // its first bit there
+    const int xl = x0 + N * lane;       // x of the lane's first node
+    const bool inb = xl < v.nx;
+    int spk;  // lane k N: the packed span word of plane k
+    {
+        const int jj = lane % N;
+        int lo = 1 << 20, hi = -1, cnt = (int)__popcll(wr);
+        if (wu) {
+            lo = jj * 64 + (int)__builtin_ctzll(wu);
+            hi = jj * 64 + 63 - (int)__builtin_clzll(wu);
+        }
+#pragma unroll
+        for (int o = 1; o < N; o <<= 1) {
+            lo = min(lo, __shfl_xor(lo, o));
+            hi = max(hi, __shfl_xor(hi, o));
+            cnt += __shfl_xor(cnt, o);
+        }
+        spk = (hi < 0 ? 0 : ((lo / N) | ((hi / N) << 8) | SP_ANY)) | (cnt ? SP_IRR : 0) |
+              (cnt << SP_CNT);
+    }
+    auto span_word = [&](int k) { return __builtin_amdgcn_readlane(spk, k * N); };
+    auto clamp_lane = [&](int sp) { return min(max(lane, sp & 255), (sp >> 8) & 255); };
+    auto load_vec = [&](long ibq, int lc) { return vld<N>(X, Idx{ibq, (unsigned)(N * lc)}); };
+    // 16 bytes of table rows tb0 + c R .. of a row with cnt irregular nodes
+    auto load_rows = [&](int tb0, int c, int cnt) {
+        TV d;
+#pragma unroll
+        for (int q = 0; q < 16 / (int)sizeof(T); ++q) d[q] = T(0);
+        if (lane < min(cnt - c * R, R) * RV)
+            d = *reinterpret_cast<const TV*>(reinterpret_cast<const char*>(tb + 8 * ((long)tb0 + c * R)) +
+                                             (unsigned)lane * 16u);
+        return d;
+    };
+    auto load_plane = [&](int q, long ib) {
+        WP P;
+        P.ib = ib;
+        const int k = q - (z0 - 1);
+        P.sp = span_word(k);
+        const int lc = clamp_lane(P.sp);
+        const int lc1 = clamp_lane(span_word(k + 1));
+        P.ins1 = lc1 == lane;
+        // the lane's own words, from lane k N + jl
+        const int src = (k * N + jl) * 4;
+        const uint32_t ulo = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)wu);
+        const uint32_t uhi = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)(wu >> 32));
+        const uint32_t rlo = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)wr);
+        const uint32_t rhi = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)(wr >> 32));
+        const int sb = __builtin_amdgcn_ds_bpermute(src, wb);
+        const bool lowh = sh < 32;
+        const int shh = lowh ? sh : sh - 32;
+        const uint32_t below = (1u << shh) - 1u;
+        P.nib = ((lowh ? ulo : uhi) >> shh) & NM;
+        P.nibr = ((lowh ? rlo : rhi) >> shh) & NM;
+        P.rk0 = sb + (lowh ? (int)__popc(rlo & below) : (int)__popc(rlo) + (int)__popc(rhi & below));
+        P.tb0 = __builtin_amdgcn_readlane(wb, k * N);
+        P.fv = fetch(Idx{ib, (unsigned)(N * lc)}, x0 + N * lc, y, q, P.nibr, P.rk0);
+        if (STENCIL) {
+            P.nxt = load_vec(ib + nxy, lc1);
+            P.ym = load_vec(ib - nx, lc);
+            P.yp = load_vec(ib + nx, lc);
+            P.edge = TX(0);
+            if (lane == 0 && x0 > 0) P.edge = at(X, Idx{ib - 1, 0u});
+            if (lane == kWave - 1 && x0 + W < v.nx) P.edge = at(X, Idx{ib, (unsigned)W});
+            P.trow = load_rows(P.tb0, 0, P.sp >> SP_CNT);
+        }
+        return P;
+    };
+    Vec<TX, N> zm = vzero<TX, N>(), c = vzero<TX, N>();
+    if (STENCIL) {
+        int lc = clamp_lane(span_word(0));
+        zm = load_vec(rb + nxy * (z0 - 1), lc);
+        if (lc != lane) zm = vzero<TX, N>();
+        lc = clamp_lane(span_word(1));
+        c = load_vec(rb + nxy * z0, lc);
+        if (lc != lane) c = vzero<TX, N>();
+    }
+    auto settle_plane = [&](const WP& P) {
+        if (STENCIL) {
+            settle(P.nxt);
+            settle(P.ym);
+            settle(P.yp);
+            settle(P.edge);
+            settle(P.trow);
+        }
+        settle(P.fv);
+    };
+    auto step = [&](const WP& P, int z) {
+        settle_plane(P);
+        if (z >= z1) return;
+        Vec<TX, N> zp = vzero<TX, N>();
+        if (STENCIL && P.ins1) zp = P.nxt;
+        if (P.sp & SP_ANY) {
+            Vec<T, N> cv, ax;
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                cv.v[e] = T(c.v[e]);
+                ax.v[e] = T(0);
+            }
+            if (STENCIL) {
+                // table rows of the lane's irregular nodes, staged through LDS one
+                // wavefront load at a time (one load for rows of up to R irregular nodes)
+                T t[N][6];
+#pragma unroll
+                for (int e = 0; e < N; ++e)
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) t[e][d] = T(0);
+                if (P.sp & SP_IRR) {
+                    const int cnt = P.sp >> SP_CNT;
+                    for (int ch = 0; ch * R < cnt; ++ch) {
+                        const TV d = ch ? load_rows(P.tb0, ch, cnt) : P.trow;
+                        __builtin_amdgcn_wave_barrier();
+                        stage[lane] = d;
+                        __builtin_amdgcn_wave_barrier();
+                        int r = P.rk0 - P.tb0 - ch * R;
+#pragma unroll
+                        for (int e = 0; e < N; ++e) {
+                            if ((P.nibr >> e) & 1u) {
+                                if (r >= 0 && r < R) row6<T>(stage + r * RV, t[e]);
+                                ++r;
+                            }
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+                const T left = T(wave_shift<true>(c.v[N - 1], P.edge));
+                const T right = T(wave_shift<false>(c.v[0], P.edge));
+#pragma unroll
+                for (int e = 0; e < N; ++e) {
+                    const T xm = e ? cv.v[e - 1] : left;
+                    const T xp = e < N - 1 ? cv.v[e + 1] : right;
+                    const T ym = T(P.ym.v[e]), yp = T(P.yp.v[e]);
+                    const T zmv = T(zm.v[e]), zpv = T(zp.v[e]);
+                    if ((P.nibr >> e) & 1u) {
+                        ax.v[e] = cv.v[e] + t[e][0] * xm + t[e][1] * xp + t[e][2] * ym +
+                                  t[e][3] * yp + t[e][4] * zmv + t[e][5] * zpv;
+                    } else {
+                        ax.v[e] = cv.v[e] + v.c[0] * (xm + xp) + v.c[1] * (ym + yp) +
+                                  v.c[2] * (zmv + zpv);
+                    }
+                }
+            }
+            if (FULL ? inb : P.nib != 0u)
+                body(Idx{P.ib, (unsigned)(N * lane)}, P.fv, cv, ax, xl, y, z, P.nib);
+        }
+        if (STENCIL) {
+            zm = c;
+            c = zp;
+        }
+        end(z, z == z1 - 1, xl, y);
+    };
+    long ibz = rb + nxy * z0;
+    WP pa = load_plane(z0, ibz);
+    for (int z = z0; z < z1; z += 2) {
+        const long ib1 = ibz + nxy;
+        WP pb = load_plane(min(z + 1, z1 - 1), ib1 < ib_last ? ib1 : ib_last);
+        step(pa, z);
+        ibz += 2 * nxy;
+        pa = load_plane(min(z + 2, z1 - 1), ibz < ib_last ? ibz : ib_last);
+        step(pb, z + 1);
+    }
+}
+
+#define WNOFETCH [&](Idx, int, int, int, unsigned, int) { return NoVals{}; }
+
+template <typename T>
+constexpr int kLanes = l0_lanes((int)sizeof(T));
+
+template <typename T>
+static inline L0View<T> wview(const FineLevel& L, int n) {
+    L0View<T> v = L.view<T>();
+    const int nws = (L.nx + kWave * n - 1) / (kWave * n);
+    v.tx = nws >= kMY ? kMY : (nws >= 2 ? 2 : 1);
+    v.gx = (nws + v.tx - 1) / v.tx;
+    v.gy = (L.ny + kMY / v.tx - 1) / (kMY / v.tx);
+    v.zb = L.wzb[n == 4 ? 1 : 0];
+    return v;
+}
+
+static inline long wblocks(const L0View<double>& v, int nz, int zb) {
+    return (long)v.gx * v.gy * ((nz + zb - 1) / zb);
+}
+
+long l0_wblocks(const FineLevel& L, int n) {
+    const L0View<double> v = wview<double>(L, n);
+    return wblocks(v, L.nz, v.zb);
+}
+
+template <typename T>
+static inline dim3 wgrid(const FineLevel& L) {
+    return dim3((unsigned)l0_wblocks(L, kLanes<T>));
+}
+
+// ---------------------------------------------------------------- operator
+
+// y = A x (TR: A^T x) at the unknowns; other nodes of y untouched (scalar stores in lanes
+// that are not all unknowns).
+template <typename T, bool TR>
+__global__ void __launch_bounds__(kMThreads) k_w_apply(L0View<T> v, const T* __restrict__ xv,
+                                                      T* __restrict__ yv) {
+    constexpr int N = kLanes<T>;
+    wmarch<T, N, true, TR, false>(v, xv, WNOFETCH,
+                                  [&](Idx i, NoVals, const Vec<T, N>&, const Vec<T, N>& ax, int,
+                                      int, int, unsigned nib) {
+                                      if (nib == (1u << N) - 1u) {
+                                          vstnt<N>(yv, i, ax.v);
+                                      } else {
+#pragma unroll
+                                          for (int e = 0; e < N; ++e)
+                                              if ((nib >> e) & 1u)
+                                                  at(yv, Idx{i.b, i.o + (unsigned)e}) = ax.v[e];
+                                      }
+                                  });
+}
+
+template <typename T>
+void w_apply(const FineLevel& L, bool trans, const T* x, T* y, hipStream_t s) {
+    const L0View<T> v = wview<T>(L, kLanes<T>);
+    if (trans)
+        hipLaunchKernelGGL((k_w_apply<T, true>), wgrid<T>(L), dim3(kWave, kMY), 0, s, v, x, y);
+    else
+        hipLaunchKernelGGL((k_w_apply<T, false>), wgrid<T>(L), dim3(kWave, kMY), 0, s, v, x, y);
+    HIPCHECK(hipGetLastError());
+}
+template void w_apply<double>(const FineLevel&, bool, const double*, double*, hipStream_t);
+template void w_apply<float>(const FineLevel&, bool, const float*, float*, hipStream_t);
+
+// ---------------------------------------------------------------- V-cycle
+
+// The Chebyshev steps of fine.hip (same modes and arithmetic), N nodes per lane.
+template <typename T, int MODE, bool DOT>
+__global__ void __launch_bounds__(kMThreads) k_w_cheb(L0View<T> v, const T* __restrict__ f,
+                                                     const T* __restrict__ xin,
+                                                     const T* __restrict__ din, T* __restrict__ xout,
+                                                     T* __restrict__ dout, T c1, T c2, T c20,
+                                                     const double* __restrict__ fdot, double* part) {
+    constexpr int N = kLanes<T>;
+    __shared__ double lds[kMThreads / kWave];
+    double acc = 0.0;
+    constexpr bool LF = MODE == CHEB_FIRST || MODE == CHEB_NEXT || MODE == CHEB_NEXT_X ||
+                        MODE == CHEB_ZERO1;
+    constexpr bool LD = MODE == CHEB_NEXT || MODE == CHEB_NEXT_X;
+    struct R {
+        Vec<T, N> f, d;
+        Vec<double, N> b;
+    };
+    auto fetch = [&](Idx i, int, int, int, unsigned, int) {
+        R r;
+        r.f = LF ? vldnt<N>(f, i) : vzero<T, N>();
+        r.d = LD ? vldnt<N>(din, i) : vzero<T, N>();
+        r.b = (DOT && fdot) ? vldnt<N>(fdot, i) : vzero<double, N>();
+        return r;
+    };
+    auto body = [&](Idx i, const R& fv, const Vec<T, N>& c, const Vec<T, N>& ax, int, int, int,
+                    unsigned nib) {
+        T xo[N], dn[N];
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
+            const bool u = (nib >> e) & 1u;
+            const T fi = fv.f.v[e];
+            T xe, de;
+            if (MODE == CHEB_ZERO1) {
+                xe = c20 * fi;
+                de = xe;
+            } else if (MODE == CHEB_ZERO2) {  // c = f, ax = A f
+                const T x1 = c20 * c.v[e];
+                de = c1 * x1 + c2 * (c.v[e] - c20 * ax.v[e]);
+                xe = x1 + de;
+            } else {
+                const T r = fi - ax.v[e];
+                const T dprev = (MODE == CHEB_NEXT_X) ? c.v[e] - fv.d.v[e] : fv.d.v[e];
+                de = (MODE == CHEB_FIRST) ? c20 * r : c1 * dprev + c2 * r;
+                xe = c.v[e] + de;
+            }
+            xo[e] = u ? xe : T(0);
+            dn[e] = u ? de : T(0);
+            if (DOT && u) acc += (fdot ? fv.b.v[e] : (double)fi) * (double)xe;
+        }
+        vstnt<N>(xout, i, xo);
+        if (dout) vstnt<N>(dout, i, dn);
+    };
+    if (MODE == CHEB_ZERO1)
+        wmarch<T, N, false, false, kFullRows<T>>(v, (const T*)nullptr, fetch, body);
+    else if (MODE == CHEB_ZERO2)
+        wmarch<T, N, true, false, kFullRows<T>>(v, f, fetch, body);
+    else
+        wmarch<T, N, true, false, kFullRows<T>>(v, xin, fetch, body);
+    if (DOT) {
+        const double sb = block_sum(acc, lds);
+        if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
+    }
+}
+
+template <typename T>
+void w_cheb(const FineLevel& L, int mode, const T* f, const T* xin, const T* din, T* xout,
+            T* dout, double c1, double c2, double c2_0, const double* fdot, double* dot,
+            KTimer& kt_) {
+    const L0View<T> v = wview<T>(L, kLanes<T>);
+    const dim3 g = wgrid<T>(L), b(kWave, kMY);
+#define WCHEB_LAUNCH(M)                                                                        \
+    if (dot)                                                                                   \
+        klaunch(kt_, true, (k_w_cheb<T, M, true>), g, b, v, f, xin, din, xout, dout, (T)c1,    \
+                (T)c2, (T)c2_0, fdot, dot);                                                    \
+    else                                                                                       \
+        klaunch(kt_, true, (k_w_cheb<T, M, false>), g, b, v, f, xin, din, xout, dout, (T)c1,   \
+                (T)c2, (T)c2_0, fdot, dot);
+    switch (mode) {
+        case CHEB_ZERO1: WCHEB_LAUNCH(CHEB_ZERO1) break;
+        case CHEB_ZERO2: WCHEB_LAUNCH(CHEB_ZERO2) break;
+        case CHEB_FIRST: WCHEB_LAUNCH(CHEB_FIRST) break;
+        case CHEB_NEXT_X: WCHEB_LAUNCH(CHEB_NEXT_X) break;
+        default: WCHEB_LAUNCH(CHEB_NEXT) break;
+    }
+#undef WCHEB_LAUNCH
+    HIPCHECK(hipGetLastError());
+}
+template void w_cheb<double>(const FineLevel&, int, const double*, const double*, const double*,
+                             double*, double*, double, double, double, const double*, double*,
+                             KTimer&);
+template void w_cheb<float>(const FineLevel&, int, const float*, const float*, const float*,
+                            float*, float*, double, double, double, const double*, double*,
+                            KTimer&);
+
+template <typename T>
+__global__ void __launch_bounds__(kMThreads) k_w_residual(L0View<T> v, const T* __restrict__ f,
+                                                         const T* __restrict__ xv,
+                                                         T* __restrict__ r) {
+    constexpr int N = kLanes<T>;
+    wmarch<T, N, true, false, kFullRows<T>>(
+        v, xv, [&](Idx i, int, int, int, unsigned, int) { return vldnt<N>(f, i); },
+        [&](Idx i, const Vec<T, N>& fv, const Vec<T, N>&, const Vec<T, N>& ax, int, int, int,
+            unsigned nib) {
+            T o[N];
+#pragma unroll
+            for (int e = 0; e < N; ++e) o[e] = ((nib >> e) & 1u) ? fv.v[e] - ax.v[e] : T(0);
+            vstnt<N>(r, i, o);
+        });
+}
+
+template <typename T>
+void w_residual(const FineLevel& L, const T* f, const T* x, T* r, KTimer& kt_) {
+    klaunch(kt_, true, (k_w_residual<T>), wgrid<T>(L), dim3(kWave, kMY), wview<T>(L, kLanes<T>),
+            f, x, r);
+    HIPCHECK(hipGetLastError());
+}
+template void w_residual<double>(const FineLevel&, const double*, const double*, double*,
+                                 KTimer&);
+template void w_residual<float>(const FineLevel&, const float*, const float*, float*, KTimer&);
+
+// First pass of the restriction (see k_l0_restrict_y): y = r - w A^T r summed over the
+// three planes of each aggregate layer, one value per (x, y, layer) into yz.
+template <typename T>
+__global__ void __launch_bounds__(kMThreads) k_w_restrict_y(L0View<T> v, const T* __restrict__ r,
+                                                           T* __restrict__ yz, T omega) {
+    constexpr int N = kLanes<T>;
+    T acc[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) acc[e] = T(0);
+    wmarch<T, N, true, true, false>(
+        v, r, WNOFETCH,
+        [&](Idx, NoVals, const Vec<T, N>& c, const Vec<T, N>& atr, int, int, int, unsigned nib) {
+#pragma unroll
+            for (int e = 0; e < N; ++e)
+                if ((nib >> e) & 1u) acc[e] += c.v[e] - omega * atr.v[e];
+        },
+        [&](int z, bool last, int x, int y) {
+            if (z % 3 == 2 || last) {
+                if (x < v.nx) vstnt<N>(yz, Idx{(long)v.nx * y + v.nxy * (z / 3), (unsigned)x}, acc);
+#pragma unroll
+                for (int e = 0; e < N; ++e) acc[e] = T(0);
+            }
+        });
+}
+
+template <typename T>
+void w_restrict_y(const FineLevel& L, const T* r, T* y, double omega, KTimer& kt_) {
+    // z-slabs of a multiple of 3 planes, so that no aggregate layer is split between tiles
+    L0View<T> v = wview<T>(L, kLanes<T>);
+    v.zb = std::max(3, v.zb / 3 * 3);
+    const long blocks = (long)v.gx * v.gy * ((L.nz + v.zb - 1) / v.zb);
+    klaunch(kt_, false, (k_w_restrict_y<T>), dim3((unsigned)blocks), dim3(kWave, kMY), v, r, y,
+            (T)omega);
+    HIPCHECK(hipGetLastError());
+}
+template void w_restrict_y<double>(const FineLevel&, const double*, double*, double, KTimer&);
+template void w_restrict_y<float>(const FineLevel&, const float*, float*, double, KTimer&);
+
+// Prolongation from level 1 (see k_l0_prolong): x += P v = P_tent v - w A (P_tent v).
+// A lane's N nodes lie in at most two aggregates along x; with their x-neighbour
+// aggregates that is the coarse x-range qx0-1 .. qx0+2 (qx0 = aggregate of the lane's
+// first node), read once per aggregate layer together with the y-neighbour values of
+// the two own aggregates on a y-face line.  The z-neighbour values are read per face
+// plane.  The coarse values are taken at the lane's own nodes (clamped to the box).
+template <typename T>
+__global__ void __launch_bounds__(kMThreads) k_w_prolong(L0View<T> v, LCView<T> c,
+                                                        const T* __restrict__ vc,
+                                                        T* __restrict__ xv, T omega) {
+    constexpr int N = kLanes<T>;
+    struct R {
+        T row[4];  // coarse values at x-range qx0-1 .. qx0+2 of the node's layer
+        T yn[2];   // y-face lines: the y-neighbour values of aggregates qx0, qx0+1
+        T zn[2];   // z-face planes: the z-neighbour values of aggregates qx0, qx0+1
+        Vec<T, N> x;
+        T t[N][6];
+        unsigned irr;  // the lane's irregular bits
+    };
+    const int lane = threadIdx.x;
+    int cqz = -1;
+    T crow[4] = {T(0), T(0), T(0), T(0)}, cyn[2] = {T(0), T(0)};
+    auto fetch = [&](Idx i, int xc, int y, int z, unsigned nibr, int rk0) {
+        // the lane's own first node (xc is the span-clamped lane's), clamped to the box
+        const int xs = min(xc - (int)i.o + N * lane, v.nx - N);
+        const int qx = xs / 3, qy = y / 3, qz = z / 3;
+        const long a = qx + (long)c.sx * (qy + 1) + c.sxy * (qz + 1);  // storage of qx - 1
+        const int fy = y - 3 * qy;
+        if (qz != cqz) {  // wave-uniform
+            cqz = qz;
+            // N = 2 reaches qx0+1 at most (nodes qx0 .. qx0+1 have no right face beyond)
+#pragma unroll
+            for (int j = 0; j < (N == 4 ? 4 : 3); ++j) crow[j] = vc[a + j];
+            if (fy != 1) {
+                const long o = fy == 0 ? -(long)c.sx : (long)c.sx;
+                cyn[0] = vc[a + 1 + o];
+                cyn[1] = vc[a + 2 + o];
+            }
+        }
+        R r;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r.row[j] = crow[j];
+        r.yn[0] = cyn[0];
+        r.yn[1] = cyn[1];
+        const int zr = z - 3 * qz;
+        r.zn[0] = r.zn[1] = T(0);
+        if (zr != 1) {
+            const long o = zr == 0 ? -c.sxy : c.sxy;
+            r.zn[0] = vc[a + 1 + o];
+            r.zn[1] = vc[a + 2 + o];
+        }
+        r.x = vldnt<N>(xv, i);
+        r.irr = nibr;
+#pragma unroll
+        for (int e = 0; e < N; ++e)
+#pragma unroll
+            for (int d = 0; d < 6; ++d) r.t[e][d] = T(0);
+        int rk = rk0;
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
+            if ((nibr >> e) & 1u) {
+                load_row6(v.tab, 0, (unsigned)rk, r.t[e]);
+                ++rk;
+            }
+        }
+        return r;
+    };
+    wmarch<T, N, false, false, kFullRows<T>>(
+        v, (const T*)nullptr, fetch,
+        [&](Idx i, const R& r, const Vec<T, N>&, const Vec<T, N>&, int xl, int y, int z,
+            unsigned nib) {
+            const int xs = min(xl, v.nx - N);
+            const int qx0 = xs / 3, fy = y - 3 * (y / 3), zr = z - 3 * (z / 3);
+            T o[N];
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                const int x = xs + e, fx = x - 3 * (x / 3);
+                // the node's aggregate is row[1] or row[2] (selects, not a runtime index,
+                // so that the record stays in registers)
+                const bool second = x / 3 != qx0;
+                const T c0 = second ? r.row[2] : r.row[1];
+                const T cxm = fx == 0 ? (second ? r.row[1] : r.row[0]) : c0;
+                const T cxp = fx == 2 ? (second ? r.row[3] : r.row[2]) : c0;
+                const T cyf = second ? r.yn[1] : r.yn[0];
+                const T czf = second ? r.zn[1] : r.zn[0];
+                const T cym = fy == 0 ? cyf : c0;
+                const T cyp = fy == 2 ? cyf : c0;
+                const T czm = zr == 0 ? czf : c0;
+                const T czp = zr == 2 ? czf : c0;
+                T apv;
+                if ((r.irr >> e) & 1u) {
+                    apv = c0 + r.t[e][0] * cxm + r.t[e][1] * cxp + r.t[e][2] * cym +
+                          r.t[e][3] * cyp + r.t[e][4] * czm + r.t[e][5] * czp;
+                } else {
+                    apv = c0 + v.c[0] * (cxm + cxp) + v.c[1] * (cym + cyp) + v.c[2] * (czm + czp);
+                }
+                o[e] = ((nib >> e) & 1u) ? r.x.v[e] + (c0 - omega * apv) : T(0);
+            }
+            vstnt<N>(xv, i, o);
+        });
+}
+
+template <typename T>
+void w_prolong(const FineLevel& L, const CoarseLevel& C, const T* vc, T* x, double omega,
+               KTimer& kt_) {
+    klaunch(kt_, true, (k_w_prolong<T>), wgrid<T>(L), dim3(kWave, kMY), wview<T>(L, kLanes<T>),
+            C.view<T>(), vc, x, (T)omega);
+    HIPCHECK(hipGetLastError());
+}
+template void w_prolong<double>(const FineLevel&, const CoarseLevel&, const double*, double*,
+                                double, KTimer&);
+template void w_prolong<float>(const FineLevel&, const CoarseLevel&, const float*, float*, double,
+                               KTimer&);
+
+// Partial sums of a . b over the unknowns, on the tiling of the V-cycle kernels in T.
+template <typename T>
+__global__ void __launch_bounds__(kMThreads) k_w_dot(L0View<T> v, const double* __restrict__ a,
+                                                    const T* __restrict__ b, double* part) {
+    constexpr int N = kLanes<T>;
+    __shared__ double lds[kMThreads / kWave];
+    double acc = 0.0;
+    struct R {
+        Vec<double, N> a;
+        Vec<T, N> b;
+    };
+    wmarch<T, N, false, false, false>(
+        v, (const T*)nullptr,
+        [&](Idx i, int, int, int, unsigned, int) { return R{vldnt<N>(a, i), vldnt<N>(b, i)}; },
+        [&](Idx, const R& r, const Vec<T, N>&, const Vec<T, N>&, int, int, int, unsigned nib) {
+#pragma unroll
+            for (int e = 0; e < N; ++e)
+                if ((nib >> e) & 1u) acc += r.a.v[e] * (double)r.b.v[e];
+        });
+    const double sb = block_sum(acc, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
+}
+
+template <typename T>
+void w_dot(const FineLevel& L, const double* a, const T* b, double* partials, hipStream_t s) {
+    hipLaunchKernelGGL((k_w_dot<T>), wgrid<T>(L), dim3(kWave, kMY), 0, s, wview<T>(L, kLanes<T>),
+                       a, b, partials);
+    HIPCHECK(hipGetLastError());
+}
+template void w_dot<double>(const FineLevel&, const double*, const double*, double*, hipStream_t);
+template void w_dot<float>(const FineLevel&, const double*, const float*, double*, hipStream_t);
+
+// ---------------------------------------------------------------- CG (fp64, 2 nodes per lane)
+
+// r = bs - A x; partials of r.r and bs.bs (see k_cg_resid).
+__global__ void __launch_bounds__(kMThreads) k_w_cg_resid(L0View<double> v,
+                                                         const double* __restrict__ bs,
+                                                         const double* __restrict__ xv,
+                                                         double* __restrict__ r, double* part,
+                                                         float* __restrict__ r32) {
+    constexpr int N = 2;
+    __shared__ double lds[kMThreads / kWave];
+    double a0 = 0.0, a1 = 0.0;
+    wmarch<double, N, true, false, false>(
+        v, xv, [&](Idx i, int, int, int, unsigned, int) { return vldnt<N>(bs, i); },
+        [&](Idx i, const Vec<double, N>& b, const Vec<double, N>&, const Vec<double, N>& ax, int,
+            int, int, unsigned nib) {
+            double o[N];
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                const bool u = (nib >> e) & 1u;
+                o[e] = u ? b.v[e] - ax.v[e] : 0.0;
+                a0 += o[e] * o[e];
+                a1 += u ? b.v[e] * b.v[e] : 0.0;
+            }
+            vstnt<N>(r, i, o);
+            if (r32) vstnt<N>(r32, i, o);
+        });
+    const double s0 = block_sum(a0, lds), s1 = block_sum(a1, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        part[blockIdx.x] = s0;
+        part[gridDim.x + blockIdx.x] = s1;
+    }
+}
+
+void w_cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
+                float* r32, hipStream_t s) {
+    hipLaunchKernelGGL(k_w_cg_resid, wgrid<double>(L), dim3(kWave, kMY), 0, s,
+                       wview<double>(L, 2), bs, x, r, partials, r32);
+    HIPCHECK(hipGetLastError());
+}
+
+// Direction update with the product by A carried along (see k_cg_pq): p <- z + beta p,
+// q <- A z + beta q, x += alpha_prev p_old; partials of p . q.
+template <typename TZ>
+__global__ void __launch_bounds__(kMThreads) k_w_cg_pq(L0View<double> v, const TZ* __restrict__ zv,
+                                                      double* __restrict__ xv,
+                                                      double* __restrict__ p, double* __restrict__ q,
+                                                      const double* __restrict__ scal, double* part) {
+    constexpr int N = 2;
+    __shared__ double lds[kMThreads / kWave];
+    const double beta = scal[S_BETA];
+    const double xa = scal[S_XA];
+    double acc = 0.0;
+    struct R {
+        Vec<double, N> p, q, x;
+    };
+    wmarch<double, N, true, false, kFullRows<TZ>>(
+        v, zv,
+        [&](Idx i, int, int, int, unsigned, int) { return R{vld<N>(p, i), vld<N>(q, i), vld<N>(xv, i)}; },
+        [&](Idx i, const R& f, const Vec<double, N>& z, const Vec<double, N>& az, int, int, int,
+            unsigned nib) {
+            double po[N], qo[N], xo[N];
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                const bool u = (nib >> e) & 1u;
+                po[e] = u ? z.v[e] + beta * f.p.v[e] : 0.0;
+                qo[e] = u ? az.v[e] + beta * f.q.v[e] : 0.0;
+                xo[e] = u ? f.x.v[e] + xa * f.p.v[e] : 0.0;
+                acc += po[e] * qo[e];
+            }
+            vstnt<N>(xv, i, xo);
+            vstnt<N>(p, i, po);
+            vstnt<N>(q, i, qo);
+        });
+    const double sb = block_sum(acc, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
+}
+
+template <typename TZ>
+void w_cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
+             double* partials, KTimer& kt_) {
+    klaunch(kt_, true, (k_w_cg_pq<TZ>), wgrid<double>(L), dim3(kWave, kMY), wview<double>(L, 2),
+            z, x, p, q, scal, partials);
+    HIPCHECK(hipGetLastError());
+}
+template void w_cg_pq<double>(const FineLevel&, const double*, double*, double*, double*,
+                              const double*, double*, KTimer&);
+
+}  // namespace saamg

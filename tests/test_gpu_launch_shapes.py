@@ -1,12 +1,17 @@
 """GPU parity in the level-0 launch shapes of the full-size problems, element by element.
 
-The level-0 solve kernels tile the box into blocks of `l0_tile_x` 64-node segments of a
-line and `l0_planes` z-planes.  The 256x256x768 ellipse runs with 4 segments per block
-and 16 planes, the 192x192x1024 cylinder with 2 and 16; the small parity cases reach only
-1-2 and 2.  This file takes an ellipse lattice the oracle solves in seconds but with four
-segments per line (the last one ragged: 200 = 3*64 + 8 nodes) and 70 planes (ragged
-slabs for every planes-per-block), and checks every level-0 step and the solves against
-the oracle in each launch shape, including the extremes 2 and 32 planes.
+The level-0 solve kernels run on one of two lane layouts.  With one node per lane they
+tile the box into blocks of `l0_tile_x` 64-node segments of a line and `l0_planes`
+z-planes.  On 16-byte lanes (`l0_wide` = 2, the automatic choice for the 256x256x768
+ellipse and the 192x192x1024 cylinder) a wavefront spans 256 (fp32) or 128 (fp64) nodes
+of a line, and a block 8 (fp32) or 16 (fp64) planes there; lines longer than a span
+take several wavefronts that exchange their edge nodes.  The small parity cases reach
+none of this.  This file takes an ellipse lattice the oracle solves in seconds but with
+lines of 264 = 4*64 + 8 nodes (one-node lanes: a ragged fifth segment; 16-byte lanes: a
+second fp32 span of 2 lanes and a third fp64 span of 4) and 70 planes (ragged slabs for
+every planes-per-block), and checks every level-0 step and the solves against the oracle
+in each launch shape, including the extremes 2 and 32 planes (capped at 14 / 30 planes
+on 16-byte lanes).
 
 Tolerances (max |got - want| over max |want|): fp64 1e-12 (components; summation order
 only) and 1e-11 (V-cycle); fp32 components 2e-5 (unit roundoff 6e-8 times a few dozen
@@ -28,8 +33,11 @@ sa = pytest.importorskip("paper_0907_4863_amd")
 pytestmark = pytest.mark.gpu
 
 SHAPE = W.Shape.ellipse(1.0, 0.3, 1.4)
-DIMS = (200, 32, 70)
-SHAPES = [(2, 4), (16, 4), (32, 4), (16, 2), (16, 1)]  # (planes per block, segments per block)
+DIMS = (264, 32, 70)
+# (lanes, planes per block, segments per block): one-node lanes in five tilings, then
+# 16-byte lanes with 2, 8, 16 and 32 planes asked for
+SHAPES = [(1, 2, 4), (1, 16, 4), (1, 32, 4), (1, 16, 2), (1, 16, 1),
+          (2, 2, 0), (2, 8, 0), (2, 16, 0), (2, 32, 0)]
 
 
 def _dev():
@@ -49,11 +57,15 @@ def emax(got, want):
     return np.abs(got - want).max() / max(np.abs(want).max(), 1e-300)
 
 
-def _setup(planes, tile, precision):
-    o = sa.default_options(precision=precision, l0_planes=planes, l0_tile_x=tile)
+def _setup(wide, planes, tile, precision):
+    o = sa.default_options(precision=precision, l0_planes=planes, l0_tile_x=tile, l0_wide=wide)
     G = sa.setup(sa.domain_for(SHAPE, *DIMS), W.VARIANT_QUAD, o)
     info = sa.hierarchy_info(G)
-    assert (info["l0_planes"], info["l0_tile_x"]) == (planes, tile)
+    assert info["l0_planes"] == planes and info["l0_wide"] == int(wide == 2)
+    if wide == 1:
+        assert info["l0_tile_x"] == tile
+    else:
+        assert info["l0_wide_planes"] == [min(planes, 14), min(planes, 30)]
     return G
 
 
@@ -64,17 +76,20 @@ def test_automatic_shape_of_the_full_size_problems():
         G = sa.setup(sa.domain_for(w.shape, w.nx, w.ny, w.nz), w.variant,
                      sa.default_options(precision=sa.MIXED))
         info = sa.hierarchy_info(G)
-        print(name, info["l0_planes"], info["l0_tile_x"], flush=True)
+        print(name, info["l0_planes"], info["l0_tile_x"], info["l0_wide"],
+              info["l0_wide_planes"], flush=True)
         assert (info["l0_planes"], info["l0_tile_x"]) == want, name
+        assert info["l0_wide"] == 1 and info["l0_wide_planes"] == [8, 16], name
         sa.destroy(G)
 
 
-@pytest.mark.parametrize("planes,tile", SHAPES)
+@pytest.mark.parametrize("wide,planes,tile", SHAPES)
 @pytest.mark.parametrize("precision", [sa.FP64, sa.MIXED])
-def test_level0_steps_elementwise(planes, tile, precision):
-    print(f"[case] launch shape planes={planes} tile_x={tile} precision={precision}", flush=True)
+def test_level0_steps_elementwise(wide, planes, tile, precision):
+    print(f"[case] launch shape lanes={wide} planes={planes} tile_x={tile} precision={precision}",
+          flush=True)
     sys_, H, _, _, _ = oracle()
-    G = _setup(planes, tile, precision)
+    G = _setup(wide, planes, tile, precision)
     lv, lc = H.levels[0], H.levels[1]
     mx, my, mz = lv.dims
     cx, cy, cz = lc.dims
@@ -109,15 +124,15 @@ def test_level0_steps_elementwise(planes, tile, precision):
     sa.destroy(G)
 
 
-@pytest.mark.parametrize("planes,tile", SHAPES)
-def test_solves_against_oracle(planes, tile):
-    print(f"[case] solves planes={planes} tile_x={tile}", flush=True)
+@pytest.mark.parametrize("wide,planes,tile", SHAPES)
+def test_solves_against_oracle(wide, planes, tile):
+    print(f"[case] solves lanes={wide} planes={planes} tile_x={tile}", flush=True)
     sys_, H, b, o, tight = oracle()
     xo = operator.unscale(sys_, o.x)
     xt = operator.unscale(sys_, tight.x)
     bt = torch.from_numpy(b.reshape(-1)).to(_dev())
     for precision in (sa.FP64, sa.MIXED):
-        G = _setup(planes, tile, precision)
+        G = _setup(wide, planes, tile, precision)
         x = torch.zeros(int(np.prod(DIMS)), dtype=torch.float64, device=_dev())
         res = sa.solve(G, bt, x, tol=1e-8)
         xg = x.cpu().numpy()

@@ -33,7 +33,12 @@ CASES = {
     # open (Robin) ends: lattice nz planes, box nz + 2
     "cyl_robin_lin": (W.Shape.cylinder(1.0, 2.0), 27, 27, 25, W.VARIANT_LIN, True),
     "ell_robin_quad": (W.Shape.ellipse(1.0, 0.6, 4.0), 40, 26, 44, W.VARIANT_QUAD, True),
+    "ell68_quad": (W.Shape.ellipse(1.0, 0.6, 4.0), 68, 45, 66, W.VARIANT_QUAD),
 }
+# (case, lanes): every case with the automatic level-0 lanes (one node per lane on these
+# short lines), and the cases whose nx is a multiple of 4 again on 16-byte lanes
+# (l0_wide = 2: 4 fp32 / 2 fp64 nodes per lane, lines far shorter than a wavefront's span)
+LANES = [(n, 0) for n in CASES] + [(n, 2) for n in CASES if CASES[n][1] % 4 == 0]
 
 
 def _dev():
@@ -41,25 +46,27 @@ def _dev():
 
 
 class Case:
-    def __init__(self, name, precision=W.PREC_FP64, opts=None, gs=False):
+    def __init__(self, name, precision=W.PREC_FP64, opts=None, gs=False, wide=0):
         shape, nx, ny, nz, variant = CASES[name][:5]
         robin = len(CASES[name]) > 5 and CASES[name][5]
         self.name, self.shape, self.variant = name, shape, variant
         self.dims = (nx, ny, nz + 2 * int(robin))  # box
         self.precision = precision
-        print(f"[case] {name} {nx}x{ny}x{nz} variant={variant} robin={robin} prec={precision}",
-              flush=True)
+        print(f"[case] {name} {nx}x{ny}x{nz} variant={variant} robin={robin} prec={precision} "
+              f"wide={wide}", flush=True)
         if gs:
             opts = amg.Options(coarse_solver="gs")
         self.sys, self.H = solve.build(shape, nx, ny, nz, variant, opts, robin=robin)
         dom = sa.domain_for(shape, nx, ny, nz, open_ends=robin)
-        o = sa.default_options(precision=precision)
+        o = sa.default_options(precision=precision, l0_wide=wide)
         if opts is not None:
             o.max_coarse, o.cheb_degree = opts.max_coarse, opts.cheb_degree
             o.coarse_solver = sa.COARSE_GS if opts.coarse_solver == "gs" else sa.COARSE_DIRECT
             o.coarse_sweeps = opts.coarse_sweeps
         self.G = sa.setup(dom, variant, o)
         self.info = sa.hierarchy_info(self.G)
+        if wide:
+            assert self.info["l0_wide"] == int(wide == 2)
         self.b = W.rhs(W.small(shape, nx, ny, nz, variant, robin=robin))
 
     def to_dev(self, box):
@@ -79,10 +86,10 @@ class Case:
 _cache = {}
 
 
-def case(name, precision=W.PREC_FP64, gs=False):
-    key = (name, precision, gs)
+def case(name, precision=W.PREC_FP64, gs=False, wide=0):
+    key = (name, precision, gs, wide)
     if key not in _cache:
-        _cache[key] = Case(name, precision, gs=gs)
+        _cache[key] = Case(name, precision, gs=gs, wide=wide)
     return _cache[key]
 
 
@@ -144,10 +151,10 @@ def test_scaling_vector():
 # ------------------------------------------------------------------ components
 
 
-@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("name,wide", LANES)
 @pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
-def test_level_operations(name, precision):
-    c = case(name, precision)
+def test_level_operations(name, wide, precision):
+    c = case(name, precision, wide=wide)
     fp64 = precision == W.PREC_FP64
     tol = 1e-12 if fp64 else 2e-5
     tol_smooth = 1e-12 if fp64 else 1e-4
@@ -174,10 +181,10 @@ def test_level_operations(name, precision):
         assert emax(got, lv.P @ v) <= tol, (name, l, "prolong", emax(got, lv.P @ v))
 
 
-@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("name,wide", LANES)
 @pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
-def test_vcycle(name, precision):
-    c = case(name, precision)
+def test_vcycle(name, wide, precision):
+    c = case(name, precision, wide=wide)
     r = W.random_box_vector(c.dims, 5) * c.sys.dom.mask
     want = amg.vcycle(c.H, c.sys.gather(r))
     z = torch.zeros(np.prod(c.dims), dtype=torch.float64, device=_dev())
@@ -207,9 +214,9 @@ def gpu_solve(c, b, x0=None, tol=1e-8, max_iter=500):
     return x.cpu().numpy().reshape(c.dims[::-1]), res
 
 
-@pytest.mark.parametrize("name", list(CASES))
-def test_solve_fp64_matches_oracle(name):
-    c = case(name)
+@pytest.mark.parametrize("name,wide", LANES)
+def test_solve_fp64_matches_oracle(name, wide):
+    c = case(name, wide=wide)
     o = solve.solve(c.sys, c.H, c.b, tol=1e-8)
     xo = c.sys.scatter(operator.unscale(c.sys, o.x))
     xg, res = gpu_solve(c, c.b)
@@ -221,9 +228,9 @@ def test_solve_fp64_matches_oracle(name):
     assert np.all(xg[~c.sys.dom.mask] == 0)
 
 
-@pytest.mark.parametrize("name", list(CASES))
-def test_solve_mixed_matches_tight_oracle(name):
-    c = case(name, W.PREC_MIXED)
+@pytest.mark.parametrize("name,wide", LANES)
+def test_solve_mixed_matches_tight_oracle(name, wide):
+    c = case(name, W.PREC_MIXED, wide=wide)
     ref = solve.solve(c.sys, c.H, c.b, tol=1e-13)
     xref = operator.unscale(c.sys, ref.x)
     o8 = operator.unscale(c.sys, solve.solve(c.sys, c.H, c.b, tol=1e-8).x)
