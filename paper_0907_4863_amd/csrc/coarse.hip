@@ -2,7 +2,7 @@
 // structured Galerkin product that builds them, the compression the solve kernels read
 // them in (interior stencil, per-node slot, table of the other rows; also for the
 // transpose of nonsymmetric levels), and the coarsest-level solvers.
-#include "launch.h"
+#include "march.h"
 
 namespace saamg {
 
@@ -104,24 +104,179 @@ long lc_blocks(const CoarseLevel& C) {
     const int Z = blockIdx.y;                                                    \
     const long i = (X + 1) + (long)c.sx * (Y + 1) + c.sxy * (Z + 1);
 
+// ---------------------------------------------------------------- solve-time z-march
+//
+// The solve kernels of levels >= 1 march along z like the level-0 ones.  A wavefront owns
+// kLcSeg = 62 consecutive nodes of one line (storage x = 62 s + lane in segment s; lanes 0
+// and 63 are its halo, which only load), keeps X at the 3 x 3 (y, z) neighbour columns of
+// its node in registers, takes the x-neighbours from the adjacent lanes and loads 3 values
+// per plane (the next plane's rows y-1, y, y+1) where one thread per node loads 27.  The
+// plane's loads (its slot, the kernel's operands, the next plane's rows) are issued a
+// plane ahead; a row that is not the interior stencil reads its table row in the step.
+// The stencil sums its 27 terms in the order k = 0..26, as lc_stencil does.
+constexpr int kLcSeg = kWave - 2;
+
+struct LcTile {
+    int tx, gx, gy, zb;  // segments per block along x, block columns, block rows, planes
+};
+
+static LcTile lc_tiling(const CoarseLevel& C) {
+    LcTile t;
+    const int nsx = (C.mx + kLcSeg - 1) / kLcSeg;
+    t.tx = nsx >= kMY ? kMY : (nsx >= 2 ? 2 : 1);
+    t.gx = (nsx + t.tx - 1) / t.tx;
+    t.gy = (C.my + kMY / t.tx - 1) / (kMY / t.tx);
+    // long z-runs where the level is large, down to 2 planes on the small levels
+    const long tiles = (long)t.gx * t.gy;
+    t.zb = 8;
+    while (t.zb > 2 && tiles * ((C.mz + t.zb - 1) / t.zb) < 2048) t.zb /= 2;
+    return t;
+}
+static inline dim3 lc_mgrid(const CoarseLevel& C, const LcTile& t) {
+    return dim3((unsigned)((long)t.gx * t.gy * ((C.mz + t.zb - 1) / t.zb)));
+}
+
+// Segment, line and z-slab of this wavefront (the XCD-aware remap of l0_tile).
+__device__ inline void lc_tile(const LcTile& t, int* seg, int* Y, int* bz) {
+    const unsigned b = blockIdx.x, nb = gridDim.x;
+    const unsigned q = nb >> 3;
+    const unsigned lb = (b < 8 * q) ? (b & 7) * q + (b >> 3) : b;
+    const int w = threadIdx.y;
+    const unsigned tt = lb / (unsigned)t.gx;
+    *seg = (int)(lb % (unsigned)t.gx) * t.tx + w % t.tx;
+    *Y = (int)(tt % (unsigned)t.gy) * (kMY / t.tx) + w / t.tx;
+    *bz = (int)(tt / (unsigned)t.gy);
+}
+
+template <typename T, class FV>
+struct LcPlane {
+    T nxt[3];  // X at the next plane, rows y-1, y, y+1
+    int slot;  // this plane's slot (of A, or of A^T when transposed)
+    FV fv;
+};
+
+// March of a tile.  For every node of the tile the march calls
+//   fv = fetch(i)                         (loads, issued a plane ahead)
+//   body(i, fv, xc, ax, comp)             (arithmetic and stores)
+// with the storage index i, X at the node (xc) and ax = (A X)_i (TR: A^T X; 0 where the
+// slot is -2); comp is false on the halo lanes and past the box, whose i must not be
+// written.  X(i, xs, ys, zs) returns X at storage index i = xs + sx ys + sxy zs (the
+// coordinates for loaders that gather, such as the prolongation's coarse values).
+template <typename T, bool SYM, bool TR, class Load, class Fetch, class Body>
+__device__ __forceinline__ void lc_march(const LCView<T>& c, const LcTile& tl, Load X, Fetch fetch,
+                                         Body body) {
+    constexpr bool kT = TR && !SYM;
+    using FV = decltype(fetch(0L));
+    using P = LcPlane<T, FV>;
+    if (c.skip && *c.skip != 0.0) return;  // wave-uniform: the whole grid returns
+    int seg, Y, bz;
+    lc_tile(tl, &seg, &Y, &bz);
+    seg = __builtin_amdgcn_readfirstlane(seg);
+    Y = __builtin_amdgcn_readfirstlane(Y);
+    const int lane = threadIdx.x;
+    const int nsx = (c.mx + kLcSeg - 1) / kLcSeg;
+    if (Y >= c.my || seg >= nsx) return;
+    const int Z0 = bz * tl.zb, Z1 = min(Z0 + tl.zb, c.mz);
+    if (Z0 >= Z1) return;
+    const int xs = min(seg * kLcSeg + lane, c.mx + 1);  // storage x, clamped to the ghost
+    const bool comp = lane >= 1 && lane <= kLcSeg && seg * kLcSeg + lane <= c.mx;
+    const int ys = Y + 1;
+    const long sx = c.sx, sxy = c.sxy;
+    const long rb = xs + sx * ys;  // storage index of the lane's column at storage plane 0
+    const int32_t* slots = kT ? c.slotT : c.slot;
+    const T* tbl = kT ? c.tbT : c.tb;
+    auto load_plane = [&](int zs) {  // storage plane zs (the node plane)
+        P p;
+        const long i = rb + sxy * zs, n = i + sxy;
+        p.nxt[0] = X(n - sx, xs, ys - 1, zs + 1);
+        p.nxt[1] = X(n, xs, ys, zs + 1);
+        p.nxt[2] = X(n + sx, xs, ys + 1, zs + 1);
+        p.slot = slots[i];
+        p.fv = fetch(i);
+        return p;
+    };
+    T col[3][3];  // [dz][dy] at the lane's x: planes zs-1, zs, zs+1
+    {
+        const long i0 = rb + sxy * Z0;  // storage plane Z0 = the plane below the first node
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+                col[dz][dy] = X(i0 + sxy * dz + sx * (dy - 1), xs, ys + dy - 1, Z0 + dz);
+    }
+    // The lane's table row stays in registers from plane to plane and is read again only
+    // when its slot changes: table rows equal to the row one plane below share its slot, so
+    // along a pipe of constant cross-section most planes read no table row at all.
+    T t[kLcRow];
+#pragma unroll
+    for (int k = 0; k < kLcRow; ++k) t[k] = T(0);
+    int held = -1;  // slot whose row t holds
+    auto step = [&](const P& p, int Z) {
+        settle(p.nxt);
+        settle(p.slot);
+        settle(p.fv);
+        if (Z >= Z1) return;
+        const long i = rb + sxy * (Z + 1);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) col[2][dy] = p.nxt[dy];
+        const int s = p.slot;
+        const bool need = s >= 0 && s != held;
+        if (__ballot(need) != 0) {
+            if (need) {
+                lc_load_row(tbl, s, t);
+                held = s;
+            }
+        }
+        T acc = T(0);
+#pragma unroll
+        for (int k = 0; k < 27; ++k) {
+            const int dx = k % 3 - 1, dy = (k / 3) % 3, dz = k / 9;
+            const T v0 = col[dz][dy];
+            const T xv = dx == 0 ? v0 : (dx < 0 ? wave_shift<true>(v0, T(0)) : wave_shift<false>(v0, T(0)));
+            const T a = s >= 0 ? t[k] : c.cst[kT ? 26 - k : k];
+            acc += a * xv;
+        }
+        if (s == -2) acc = T(0);
+        body(i, p.fv, col[1][1], acc, comp);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            col[0][dy] = col[1][dy];
+            col[1][dy] = col[2][dy];
+        }
+    };
+    P pa = load_plane(Z0 + 1);
+    for (int Z = Z0; Z < Z1; Z += 2) {
+        P pb = load_plane(min(Z + 2, Z1));
+        step(pa, Z);
+        pa = load_plane(min(Z + 3, Z1));
+        step(pb, Z + 1);
+    }
+}
+
+// Loader of X from a storage vector.
+#define LC_LOAD(p) [&](long j, int, int, int) { return (p)[j]; }
+
 template <typename T, bool SYM, bool TR>
-__global__ void __launch_bounds__(kThreads) k_lc_apply(LCView<T> c, const T* __restrict__ xv,
-                                                       T* __restrict__ yv) {
-    LC_PROLOGUE
-    if (!inb) return;
-    yv[i] = lc_stencil<T, SYM, TR>(c, i, [&](long j) { return xv[j]; });
+__global__ void __launch_bounds__(kMThreads) k_lc_apply(LCView<T> c, LcTile tl,
+                                                        const T* __restrict__ xv,
+                                                        T* __restrict__ yv) {
+    lc_march<T, SYM, TR>(c, tl, LC_LOAD(xv), [&](long) { return 0; },
+                         [&](long i, int, T, T ax, bool comp) {
+                             if (comp) yv[i] = ax;
+                         });
 }
 
 template <typename T>
 void lc_apply(const CoarseLevel& C, bool trans, const T* x, T* y, hipStream_t s) {
     LCView<T> c = C.view<T>();
-    dim3 g = lc_grid(C), b(kThreads);
+    const LcTile tl = lc_tiling(C);
+    const dim3 g = lc_mgrid(C, tl), b(kWave, kMY);
     if (C.sym)
-        hipLaunchKernelGGL((k_lc_apply<T, true, false>), g, b, 0, s, c, x, y);
+        hipLaunchKernelGGL((k_lc_apply<T, true, false>), g, b, 0, s, c, tl, x, y);
     else if (trans)
-        hipLaunchKernelGGL((k_lc_apply<T, false, true>), g, b, 0, s, c, x, y);
+        hipLaunchKernelGGL((k_lc_apply<T, false, true>), g, b, 0, s, c, tl, x, y);
     else
-        hipLaunchKernelGGL((k_lc_apply<T, false, false>), g, b, 0, s, c, x, y);
+        hipLaunchKernelGGL((k_lc_apply<T, false, false>), g, b, 0, s, c, tl, x, y);
     HIPCHECK(hipGetLastError());
 }
 template void lc_apply<double>(const CoarseLevel&, bool, const double*, double*, hipStream_t);
@@ -221,34 +376,43 @@ void lc_lz_update(const CoarseLevel& C, const double* u, const double* cur, doub
 // D^-1 f in xin (written by the restriction that produced f), so that each neighbour
 // costs one load.
 template <typename T, bool SYM, int MODE>
-__global__ void __launch_bounds__(kThreads) k_lc_cheb(LCView<T> c, const T* __restrict__ f,
-                                                      const T* __restrict__ xin,
-                                                      const T* __restrict__ din,
-                                                      T* __restrict__ xout, T* __restrict__ dout,
-                                                      T c1, T c2, T c20) {
-    LC_PROLOGUE
-    if (!inb) return;
-    const T id = c.invD[i];
-    T xo = 0, dn = 0;
-    if (id != (T)0) {
-        const T fi = f[i];
-        if (MODE == CHEB_ZERO1) {
-            xo = c20 * id * fi;
-            dn = xo;
-        } else if (MODE == CHEB_ZERO2) {
-            const T ax = c20 * lc_stencil<T, SYM, false>(c, i, [&](long j) { return xin[j]; });
-            const T x1 = c20 * id * fi;
-            dn = c1 * x1 + c2 * id * (fi - ax);
-            xo = x1 + dn;
-        } else {
-            const T ax = lc_stencil<T, SYM, false>(c, i, [&](long j) { return xin[j]; });
-            const T r = id * (fi - ax);
-            dn = (MODE == CHEB_FIRST) ? c20 * r : c1 * din[i] + c2 * r;
-            xo = xin[i] + dn;
-        }
-    }
-    xout[i] = xo;
-    if (dout) dout[i] = dn;
+__global__ void __launch_bounds__(kMThreads) k_lc_cheb(LCView<T> c, LcTile tl,
+                                                       const T* __restrict__ f,
+                                                       const T* __restrict__ xin,
+                                                       const T* __restrict__ din,
+                                                       T* __restrict__ xout, T* __restrict__ dout,
+                                                       T c1, T c2, T c20) {
+    struct R {
+        T id, fi, di;
+    };
+    // CHEB_ZERO1 has no stencil: it marches over f (any valid vector) and ignores ax
+    const T* xs = MODE == CHEB_ZERO1 ? f : xin;
+    lc_march<T, SYM, false>(
+        c, tl, LC_LOAD(xs),
+        [&](long i) { return R{c.invD[i], f[i], MODE == CHEB_NEXT ? din[i] : T(0)}; },
+        [&](long i, const R& r, T xc, T axs, bool comp) {
+            if (!comp) return;
+            const T id = r.id;
+            T xo = 0, dn = 0;
+            if (id != (T)0) {
+                const T fi = r.fi;
+                if (MODE == CHEB_ZERO1) {
+                    xo = c20 * id * fi;
+                    dn = xo;
+                } else if (MODE == CHEB_ZERO2) {
+                    const T ax = c20 * axs;
+                    const T x1 = c20 * id * fi;
+                    dn = c1 * x1 + c2 * id * (fi - ax);
+                    xo = x1 + dn;
+                } else {
+                    const T rr = id * (fi - axs);
+                    dn = (MODE == CHEB_FIRST) ? c20 * rr : c1 * r.di + c2 * rr;
+                    xo = xc + dn;
+                }
+            }
+            xout[i] = xo;
+            if (dout) dout[i] = dn;
+        });
 }
 
 // Algorithmic bytes of one coarse-level stencil sweep: slots, 1/diag and `nvec` vectors
@@ -263,9 +427,10 @@ void lc_cheb(const CoarseLevel& C, int mode, const T* f, const T* xin, const T* 
     const int nvec = mode == CHEB_ZERO1 ? 2 : mode == CHEB_NEXT ? 4 : 3;
     KTimer kt_(T_COARSE, s, lc_bytes(C, sizeof(T), nvec + (dout ? 1 : 0)));
     LCView<T> c = C.view<T>();
-    dim3 g = lc_grid(C), b(kThreads);
+    const LcTile tl = lc_tiling(C);
+    const dim3 g = lc_mgrid(C, tl), b(kWave, kMY);
 #define LC_CHEB(SYMV, M)                                                                       \
-    klaunch(kt_, true, (k_lc_cheb<T, SYMV, M>), g, b, c, f, xin, din, xout, dout, (T)c1,       \
+    klaunch(kt_, true, (k_lc_cheb<T, SYMV, M>), g, b, c, tl, f, xin, din, xout, dout, (T)c1,   \
             (T)c2, (T)c2_0);
 #define LC_CHEB_MODES(SYMV)                                 \
     switch (mode) {                                         \
@@ -290,27 +455,32 @@ template void lc_cheb<float>(const CoarseLevel&, int, const float*, const float*
 
 // r = f - A x and (rd non-null) rd = D^-1 r, the restriction's input.
 template <typename T, bool SYM>
-__global__ void __launch_bounds__(kThreads) k_lc_residual(LCView<T> c, const T* __restrict__ f,
-                                                          const T* __restrict__ xv,
-                                                          T* __restrict__ r, T* __restrict__ rd) {
-    LC_PROLOGUE
-    if (!inb) return;
-    const T id = c.invD[i];
-    T o = 0;
-    if (id != (T)0) o = f[i] - lc_stencil<T, SYM, false>(c, i, [&](long j) { return xv[j]; });
-    r[i] = o;
-    if (rd) rd[i] = id * o;
+__global__ void __launch_bounds__(kMThreads) k_lc_residual(LCView<T> c, LcTile tl,
+                                                           const T* __restrict__ f,
+                                                           const T* __restrict__ xv,
+                                                           T* __restrict__ r, T* __restrict__ rd) {
+    struct R {
+        T id, fi;
+    };
+    lc_march<T, SYM, false>(c, tl, LC_LOAD(xv), [&](long i) { return R{c.invD[i], f[i]}; },
+                            [&](long i, const R& q, T, T ax, bool comp) {
+                                if (!comp) return;
+                                const T o = q.id != (T)0 ? q.fi - ax : T(0);
+                                r[i] = o;
+                                if (rd) rd[i] = q.id * o;
+                            });
 }
 
 template <typename T>
 void lc_residual(const CoarseLevel& C, const T* f, const T* x, T* r, T* rd, hipStream_t s) {
     KTimer kt_(T_COARSE, s, lc_bytes(C, sizeof(T), rd ? 4 : 3));
+    const LcTile tl = lc_tiling(C);
     if (C.sym)
-        klaunch(kt_, true, (k_lc_residual<T, true>), lc_grid(C), dim3(kThreads), C.view<T>(), f, x,
-                r, rd);
+        klaunch(kt_, true, (k_lc_residual<T, true>), lc_mgrid(C, tl), dim3(kWave, kMY),
+                C.view<T>(), tl, f, x, r, rd);
     else
-        klaunch(kt_, true, (k_lc_residual<T, false>), lc_grid(C), dim3(kThreads), C.view<T>(), f,
-                x, r, rd);
+        klaunch(kt_, true, (k_lc_residual<T, false>), lc_mgrid(C, tl), dim3(kWave, kMY),
+                C.view<T>(), tl, f, x, r, rd);
     HIPCHECK(hipGetLastError());
 }
 template void lc_residual<double>(const CoarseLevel&, const double*, const double*, double*,
@@ -344,12 +514,12 @@ template void lc_dscale<float>(const CoarseLevel&, const float*, float*, hipStre
 // then fc(I) = sum of y over aggregate I, and (fd non-null) fd = D_c^-1 fc for the coarse
 // level's first smoothing step.
 template <typename T, bool SYM>
-__global__ void __launch_bounds__(kThreads) k_lc_restrict_y(LCView<T> c, T* ry,
-                                                            const T* __restrict__ rd, T omega) {
-    LC_PROLOGUE
-    if (!inb) return;
-    const T atr = lc_stencil<T, SYM, true>(c, i, [&](long j) { return rd[j]; });
-    ry[i] = ry[i] - omega * atr;
+__global__ void __launch_bounds__(kMThreads) k_lc_restrict_y(LCView<T> c, LcTile tl, T* ry,
+                                                             const T* __restrict__ rd, T omega) {
+    lc_march<T, SYM, true>(c, tl, LC_LOAD(rd), [&](long i) { return ry[i]; },
+                           [&](long i, T ri, T, T atr, bool comp) {
+                               if (comp) ry[i] = ri - omega * atr;
+                           });
 }
 
 template <typename T>
@@ -382,12 +552,13 @@ void lc_restrict(const CoarseLevel& F, const CoarseLevel& C, T* r, const T* rd, 
                  double omega, hipStream_t s) {
     KTimer kt_(T_COARSE, s, lc_bytes(F, sizeof(T), 3) +
                                 C.n_unknowns * (long)sizeof(T) * (fd ? 3 : 1));
+    const LcTile tl = lc_tiling(F);
     if (F.sym)
-        klaunch(kt_, false, (k_lc_restrict_y<T, true>), lc_grid(F), dim3(kThreads), F.view<T>(), r,
-                rd, (T)omega);
+        klaunch(kt_, false, (k_lc_restrict_y<T, true>), lc_mgrid(F, tl), dim3(kWave, kMY),
+                F.view<T>(), tl, r, rd, (T)omega);
     else
-        klaunch(kt_, false, (k_lc_restrict_y<T, false>), lc_grid(F), dim3(kThreads), F.view<T>(),
-                r, rd, (T)omega);
+        klaunch(kt_, false, (k_lc_restrict_y<T, false>), lc_mgrid(F, tl), dim3(kWave, kMY),
+                F.view<T>(), tl, r, rd, (T)omega);
     klaunch(kt_, true, (k_lc_restrict_sum<T>), lc_grid(C), dim3(kThreads), F.view<T>(),
             C.view<T>(), (const T*)r, fc, fd);
     HIPCHECK(hipGetLastError());
@@ -397,49 +568,39 @@ template void lc_restrict<double>(const CoarseLevel&, const CoarseLevel&, double
 template void lc_restrict<float>(const CoarseLevel&, const CoarseLevel&, float*, const float*,
                                  float*, float*, double, hipStream_t);
 
-// x += P v = P_tent v - w D^-1 A P_tent v on the fine level's unknowns.
+// x += P v = P_tent v - w D^-1 A P_tent v on the fine level's unknowns: the stencil runs
+// on the field P_tent v, whose value at fine node (x, y, z) is v at its aggregate (floor
+// division, so that ghost neighbours (-1) map into the coarse ghost layer).
 template <typename T, bool SYM>
-__global__ void __launch_bounds__(kThreads) k_lc_prolong(LCView<T> c, LCView<T> cc,
-                                                         const T* __restrict__ vc,
-                                                         T* __restrict__ xv, T omega) {
-    LC_PROLOGUE
-    if (!inb) return;
-    const T id = c.invD[i];
-    if (id == (T)0) return;
-    // coarse storage index of the aggregate of fine logical (x, y, z); floor division so
-    // that ghost neighbours (-1) map into the coarse ghost layer
-    auto agg = [&](int x, int y, int z) -> long {
-        const int ax = (x + 3) / 3, ay = (y + 3) / 3, az = (z + 3) / 3;  // floor(x/3) + 1
-        return ax + (long)cc.sx * ay + cc.sxy * az;
+__global__ void __launch_bounds__(kMThreads) k_lc_prolong(LCView<T> c, LcTile tl, LCView<T> cc,
+                                                          const T* __restrict__ vc,
+                                                          T* __restrict__ xv, T omega) {
+    struct R {
+        T id, x;
     };
-    T apv = 0;
-    const int s = c.slot[i];  // -1 or a table row (the node is an unknown)
-    T t[kLcRow];
-    if (s >= 0) {
-        lc_load_row(c.tb, s, t);
-    } else {
-#pragma unroll
-        for (int k = 0; k < 27; ++k) t[k] = c.cst[k];
-    }
-#pragma unroll
-    for (int k = 0; k < 27; ++k) {
-        const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
-        apv += t[k] * vc[agg(X + dx, Y + dy, Z + dz)];
-    }
-    const T pv = vc[agg(X, Y, Z)];
-    xv[i] += pv - omega * id * apv;
+    lc_march<T, SYM, false>(
+        c, tl,
+        [&](long, int xs, int ys, int zs) {  // storage coordinates: logical + 1
+            const int ax = (xs + 2) / 3, ay = (ys + 2) / 3, az = (zs + 2) / 3;
+            return vc[ax + (long)cc.sx * ay + cc.sxy * az];
+        },
+        [&](long i) { return R{c.invD[i], xv[i]}; },
+        [&](long i, const R& r, T pv, T apv, bool comp) {
+            if (comp && r.id != (T)0) xv[i] = r.x + (pv - omega * r.id * apv);
+        });
 }
 
 template <typename T>
 void lc_prolong(const CoarseLevel& F, const CoarseLevel& C, const T* vc, T* x, double omega,
                 hipStream_t s) {
     KTimer kt_(T_COARSE, s, lc_bytes(F, sizeof(T), 2) + C.n_unknowns * (long)sizeof(T));
+    const LcTile tl = lc_tiling(F);
     if (F.sym)
-        klaunch(kt_, true, (k_lc_prolong<T, true>), lc_grid(F), dim3(kThreads), F.view<T>(),
-                C.view<T>(), vc, x, (T)omega);
+        klaunch(kt_, true, (k_lc_prolong<T, true>), lc_mgrid(F, tl), dim3(kWave, kMY),
+                F.view<T>(), tl, C.view<T>(), vc, x, (T)omega);
     else
-        klaunch(kt_, true, (k_lc_prolong<T, false>), lc_grid(F), dim3(kThreads), F.view<T>(),
-                C.view<T>(), vc, x, (T)omega);
+        klaunch(kt_, true, (k_lc_prolong<T, false>), lc_mgrid(F, tl), dim3(kWave, kMY),
+                F.view<T>(), tl, C.view<T>(), vc, x, (T)omega);
     HIPCHECK(hipGetLastError());
 }
 template void lc_prolong<double>(const CoarseLevel&, const CoarseLevel&, const double*, double*,
