@@ -160,7 +160,9 @@ typedef struct {
     double t_refresh_ms;                  /* last saamg_refresh (host wall time), 0 if none */
     int32_t l0_planes;                    /* level-0 launch shape in use: planes per block, */
     int32_t l0_tile_x;                    /* 64-node segments per block along x            */
-    int64_t table_rows[SAAMG_MAX_LEVELS]; /* levels >= 1: stored coefficient rows of A_l    */
+    int64_t table_rows[SAAMG_MAX_LEVELS]; /* stored coefficient rows of A_l (level 0: of   */
+                                          /* its irregular rows, lines repeating the line  */
+                                          /* below sharing rows)                           */
     int64_t table_rows_t[SAAMG_MAX_LEVELS]; /* and of A_l^T (nonsymmetric levels)           */
     /* host wall time of the setup's phases: domain checks (host), level-0 operator (masks,
        table, scaling), spectral estimates, Galerkin products and their compression, the

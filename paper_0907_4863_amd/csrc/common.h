@@ -240,9 +240,12 @@ struct FineLevel {
     double h[3];
     uint64_t* unk = nullptr;
     uint64_t* irr = nullptr;
-    int32_t* base = nullptr;
-    long n_irr = 0;
-    double* tab64 = nullptr;    // [2][n_irr][8]: rows of the operator, then of its transpose
+    int32_t* base = nullptr;    // table slot of each segment's first irregular row
+    int32_t* base_full = nullptr;  // the same before de-duplication (one row per node)
+    long n_irr = 0;             // irregular rows
+    long n_tab = 0;             // table rows: lines repeating the line one plane below share
+                                // its rows (see l0_dedup_table)
+    double* tab64 = nullptr;    // [2][n_tab][8]: rows of the operator, then of its transpose
     float* tab32 = nullptr;
     double c64[3];
     double robin_d = 0.0;       // open ends (Robin parameter d); 0: closed ends
@@ -328,10 +331,10 @@ inline L0View<T> FineLevel::view() const {
     v.unk = unk; v.irr = irr; v.base = base;
     if constexpr (sizeof(T) == 8) {
         v.tab = (const T*)tab64;
-        v.tabT = (const T*)(tab64 ? tab64 + 8 * n_irr : nullptr);
+        v.tabT = (const T*)(tab64 ? tab64 + 8 * n_tab : nullptr);
     } else {
         v.tab = (const T*)tab32;
-        v.tabT = (const T*)(tab32 ? tab32 + 8 * n_irr : nullptr);
+        v.tabT = (const T*)(tab32 ? tab32 + 8 * n_tab : nullptr);
     }
     for (int a = 0; a < 3; ++a) v.c[a] = (T)c64[a];
     v.rho_end = robin_d > 0.0 ? 0.5 : 1.0;

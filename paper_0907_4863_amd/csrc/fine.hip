@@ -27,7 +27,7 @@ static inline dim3 l0_grid(const FineLevel& L) {
 // Level-0 metadata streamed by every stencil launch: segment masks and table slots,
 // plus the irregular rows' coefficients.
 static inline long l0_meta_bytes(const FineLevel& L, int wsize, bool trans_too) {
-    return L.nseg * 20 + L.n_irr * 6L * wsize * (trans_too ? 2 : 1);
+    return L.nseg * 20 + L.n_tab * 6L * wsize * (trans_too ? 2 : 1);
 }
 
 
@@ -643,13 +643,141 @@ __global__ void __launch_bounds__(kThreads) k_build_table(
 }
 
 void l0_build_table(FineLevel& L, const uint8_t* mask, const int32_t* nwidx, const double* nwfrac,
-                    int variant, double sigma0, hipStream_t s) {
+                    int variant, double sigma0, double* tab64, float* tab32, hipStream_t s) {
     L0View<double> v = L.view<double>();
+    v.base = L.base_full;
     hipLaunchKernelGGL(k_build_table, l0_grid(L), dim3(kWave, kBlockY), 0, s, v, mask, nwidx,
                        nwfrac, variant, sigma0, 1.0 / (L.h[0] * L.h[0]), 1.0 / (L.h[1] * L.h[1]),
                        1.0 / (L.h[2] * L.h[2]), L.robin_d > 0.0 ? 2.0 * L.h[2] / L.robin_d : 0.0,
-                       L.n_irr, L.tab64, L.tab32, L.sigma);
+                       L.n_irr, tab64, tab32, L.sigma);
     HIPCHECK(hipGetLastError());
+}
+
+// ---- de-duplication of the table along z
+//
+// A line (y, z) repeats the line below it when each of its segments has the irregular mask
+// of the segment one plane below and its table rows (operator and transpose, fp64, bit for
+// bit) equal theirs in order.  Such a line's segments take the slots of the rows below, so
+// a pipe of constant cross-section stores the rows of a few planes only, and a z-march
+// reading the same slots on consecutive planes can keep the rows it has.  The rows of a
+// line stay consecutive, as the kernels on 16-byte lanes need.
+
+// One wavefront per line (line = z ny + y): its irregular rows (keep = 0 when it repeats
+// the line below) and the repeat flag.
+__global__ void __launch_bounds__(kThreads) k_l0_line_info(L0View<double> v,
+                                                           const int32_t* __restrict__ bfull,
+                                                           const double* __restrict__ full,
+                                                           long n_irr, int32_t* keep,
+                                                           int32_t* same) {
+    const long line = (long)blockIdx.x * kBlockY + threadIdx.y;
+    if (line >= (long)v.ny * v.nz) return;
+    const int lane = threadIdx.x;
+    const long z = line / v.ny;
+    const long s0 = line * v.nsegx, sb = s0 - (long)v.ny * v.nsegx;  // this line, line below
+    int cnt = 0;
+    bool diff = z < 1;
+    for (int sx = lane; sx < v.nsegx; sx += kWave) {
+        const uint64_t r = v.irr[s0 + sx];
+        cnt += (int)__popcll(r);
+        if (z >= 1 && r != v.irr[sb + sx]) diff = true;
+    }
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) cnt += __shfl_xor(cnt, o);
+    bool rep = __ballot(diff) == 0;
+    if (rep && cnt > 0) {
+        const long r0 = bfull[s0], r1 = bfull[sb];
+        bool d2 = false;
+        for (long k = lane; k < 8L * cnt; k += kWave) {
+            d2 |= __double_as_longlong(full[8 * r0 + k]) != __double_as_longlong(full[8 * r1 + k]);
+            d2 |= __double_as_longlong(full[8 * (n_irr + r0) + k]) !=
+                  __double_as_longlong(full[8 * (n_irr + r1) + k]);
+        }
+        rep = __ballot(d2) == 0;
+    }
+    if (lane == 0) {
+        keep[line] = rep ? 0 : cnt;
+        same[line] = rep;
+    }
+}
+
+// Slot of each line's first row: the compacted offset of the last line at or below it
+// (same y) that does not repeat.  One thread per y.
+__global__ void __launch_bounds__(256) k_l0_line_src(int ny, int nz, const int32_t* __restrict__ same,
+                                                     const int32_t* __restrict__ off,
+                                                     int32_t* __restrict__ nb) {
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= ny) return;
+    int m = 0;
+#pragma unroll 8
+    for (int z = 0; z < nz; ++z) {
+        const long line = (long)z * ny + y;
+        m = same[line] ? m : off[line];
+        nb[line] = m;
+    }
+}
+
+// base of every segment: its line's first slot plus its offset inside the line.
+__global__ void __launch_bounds__(256) k_l0_seg_base(long nseg, int nsegx,
+                                                     const int32_t* __restrict__ bfull,
+                                                     const int32_t* __restrict__ nb,
+                                                     int32_t* __restrict__ base) {
+    const long sg = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (sg >= nseg) return;
+    const long line = sg / nsegx;
+    base[sg] = nb[line] + (bfull[sg] - bfull[line * nsegx]);
+}
+
+// Rows of the lines that do not repeat, to their compacted slots (one wavefront per line).
+__global__ void __launch_bounds__(kThreads) k_l0_line_copy(long nlines, int nsegx, const int32_t* __restrict__ bfull,
+                                                           const int32_t* __restrict__ keep,
+                                                           const int32_t* __restrict__ off,
+                                                           long n_irr, long n_tab,
+                                                           const double* __restrict__ f64,
+                                                           const float* __restrict__ f32,
+                                                           double* __restrict__ t64,
+                                                           float* __restrict__ t32) {
+    const long line = (long)blockIdx.x * kBlockY + threadIdx.y;
+    if (line >= nlines) return;
+    const int cnt = keep[line];
+    if (cnt == 0) return;
+    const long src = bfull[line * nsegx], dst = off[line];
+    for (long k = threadIdx.x; k < 8L * cnt; k += kWave) {
+        t64[8 * dst + k] = f64[8 * src + k];
+        t64[8 * (n_tab + dst) + k] = f64[8 * (n_irr + src) + k];
+        t32[8 * dst + k] = f32[8 * src + k];
+        t32[8 * (n_tab + dst) + k] = f32[8 * (n_irr + src) + k];
+    }
+}
+
+void l0_dedup_table(FineLevel& L, const double* full64, const float* full32, hipStream_t s) {
+    const long nlines = (long)L.ny * L.nz;
+    Tmp keep(4 * nlines), same(4 * nlines), off(4 * nlines), nb(4 * nlines), tot(8);
+    const dim3 gl((unsigned)((nlines + kBlockY - 1) / kBlockY)), bl(kWave, kBlockY);
+    hipLaunchKernelGGL(k_l0_line_info, gl, bl, 0, s, L.view<double>(), (const int32_t*)L.base_full,
+                       full64, L.n_irr, keep.as<int32_t>(), same.as<int32_t>());
+    exclusive_scan(keep.as<int32_t>(), off.as<int32_t>(), nlines, tot.as<int64_t>(), s);
+    hipLaunchKernelGGL(k_l0_line_src, dim3((unsigned)((L.ny + 255) / 256)), dim3(256), 0, s, L.ny,
+                       L.nz, (const int32_t*)same.as<int32_t>(), (const int32_t*)off.as<int32_t>(),
+                       nb.as<int32_t>());
+    hipLaunchKernelGGL(k_l0_seg_base, dim3((unsigned)((L.nseg + 255) / 256)), dim3(256), 0, s,
+                       L.nseg, L.nsegx, (const int32_t*)L.base_full, (const int32_t*)nb.as<int32_t>(),
+                       L.base);
+    int64_t n_tab = 0;
+    HIPCHECK(hipMemcpyAsync(&n_tab, tot.p, 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    HIPCHECK(hipGetLastError());
+    dfree(L.tab64);
+    dfree(L.tab32);
+    L.tab64 = nullptr;
+    L.tab32 = nullptr;
+    L.n_tab = n_tab;
+    L.tab64 = (double*)dmalloc(8 * 16 * std::max<long>(n_tab, 1));
+    L.tab32 = (float*)dmalloc(4 * 16 * std::max<long>(n_tab, 1));
+    hipLaunchKernelGGL(k_l0_line_copy, gl, bl, 0, s, nlines, L.nsegx, (const int32_t*)L.base_full,
+                       (const int32_t*)keep.as<int32_t>(), (const int32_t*)off.as<int32_t>(),
+                       L.n_irr, (long)n_tab, full64, full32, L.tab64, L.tab32);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(s));
 }
 
 __global__ void __launch_bounds__(kThreads) k_unknown_list(L0View<double> v, const int32_t* ucnt_base,

@@ -77,8 +77,13 @@ void l0_build_masks(FineLevel& L, const uint8_t* mask, const int32_t* nwidx, int
 // true when the segment masks unk/irr equal L's
 bool l0_same_masks(const FineLevel& L, const uint64_t* unk, const uint64_t* irr, hipStream_t s);
 void exclusive_scan(const int32_t* in, int32_t* out, long n, int64_t* total, hipStream_t s);
+// The full table (one row per irregular node, slots from base_full) into tab64 / tab32
+// ([2][n_irr][8]) and sigma.
 void l0_build_table(FineLevel& L, const uint8_t* mask, const int32_t* nwidx, const double* nwfrac,
-                    int variant, double sigma0, hipStream_t s);
+                    int variant, double sigma0, double* tab64, float* tab32, hipStream_t s);
+// De-duplicated table of L from the full one: sets L.base, L.n_tab, L.tab64, L.tab32
+// (reallocated).  Synchronises the stream.
+void l0_dedup_table(FineLevel& L, const double* full64, const float* full32, hipStream_t s);
 void l0_unknown_list(const FineLevel& L, long* out, hipStream_t s);  // requires n_unknowns slots
 
 // ---- level 0: operators

@@ -955,8 +955,11 @@ static void fine_numbers(FineLevel& L, const saamg_domain* dom, const DeviceDoma
                            1.0 / (L.h[2] * L.h[2])};
     const double sigma0 = 1.0 / std::sqrt(2.0 * ih2[0] + 2.0 * ih2[1] + 2.0 * ih2[2]);
     for (int a = 0; a < 3; ++a) L.c64[a] = -(sigma0 * (1.0 * ih2[a])) * sigma0;
-    l0_build_table(L, dd.mask, dd.nwidx, dd.nwfrac, variant, sigma0, s);
-    HIPCHECK(hipStreamSynchronize(s));
+    const long nr = std::max<long>(L.n_irr, 1);
+    Tmp full64(8 * 16 * nr), full32(4 * 16 * nr);
+    l0_build_table(L, dd.mask, dd.nwidx, dd.nwfrac, variant, sigma0, full64.as<double>(),
+                   full32.as<float>(), s);
+    l0_dedup_table(L, full64.as<double>(), full32.as<float>(), s);
 }
 
 // Smoother and transfer parameters of level l from its operator (Section 3.2).
@@ -1094,6 +1097,7 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
         L.unk = (uint64_t*)dmalloc(8 * L.nseg);
         L.irr = (uint64_t*)dmalloc(8 * L.nseg);
         L.base = (int32_t*)dmalloc(4 * L.nseg);
+        L.base_full = (int32_t*)dmalloc(4 * L.nseg);
         L.sigma = (double*)dmalloc(8 * nbox);
 
         // segment masks of unknowns and irregular rows, table slots
@@ -1102,18 +1106,16 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
         {
             Tmp cnt_irr(4 * L.nseg), cnt_unk(4 * L.nseg), d_tot(16);
             l0_build_masks(L, dd.mask, dd.nwidx, cnt_irr.as<int32_t>(), cnt_unk.as<int32_t>(), s);
-            exclusive_scan(cnt_irr.as<int32_t>(), L.base, L.nseg, d_tot.as<int64_t>(), s);
+            exclusive_scan(cnt_irr.as<int32_t>(), L.base_full, L.nseg, d_tot.as<int64_t>(), s);
             exclusive_scan(cnt_unk.as<int32_t>(), nullptr, L.nseg, d_tot.as<int64_t>() + 1, s);
             HIPCHECK(hipMemcpyAsync(tots, d_tot.p, 16, hipMemcpyDeviceToHost, s));
             HIPCHECK(hipStreamSynchronize(s));
         }
         L.n_irr = tots[0];
         L.n_unknowns = tots[1];
-        L.tab64 = (double*)dmalloc(8 * 16 * std::max<long>(L.n_irr, 1));
-        L.tab32 = (float*)dmalloc(4 * 16 * std::max<long>(L.n_irr, 1));
         fine_numbers(L, dom, dd, variant, s);
         dd.release();
-        H->bytes = 20L * L.nseg + 8L * nbox + 12L * 16 * L.n_irr;
+        H->bytes = 24L * L.nseg + 8L * nbox + 12L * 16 * L.n_tab;
         H->t_phase_ms[0] = t_host;
         H->t_phase_ms[1] = ms_since(t0) - t_host;
 
@@ -1234,8 +1236,10 @@ static void check_same_rows(const saamg_hierarchy* H, const DeviceDomain& dd, hi
 // level-0 operator.
 static void drop_operator(saamg_hierarchy* H) {
     if (!H->op) return;
-    for (void* p : {(void*)H->op->tab64, (void*)H->op->tab32, (void*)H->op->sigma}) dfree(p);
-    H->bytes -= 8L * H->op->nbox + 12L * 16 * H->op->n_irr;
+    for (void* p : {(void*)H->op->tab64, (void*)H->op->tab32, (void*)H->op->sigma,
+                    (void*)H->op->base})
+        dfree(p);
+    H->bytes -= 8L * H->op->nbox + 4L * H->op->nseg + 12L * 16 * H->op->n_tab;
     delete H->op;
     H->op = nullptr;
 }
@@ -1251,7 +1255,9 @@ static void refresh_impl(saamg_hierarchy* H, const saamg_domain* dom, hipStream_
     check_same_rows(H, dd, s);
     // from here on H changes; a failure leaves it unusable (destroy it)
     drop_operator(H);
+    H->bytes -= 12L * 16 * L.n_tab;
     fine_numbers(L, dom, dd, H->variant, s);
+    H->bytes += 12L * 16 * L.n_tab;
     dd.release();
     for (int l = 0; l + 1 < H->n_levels; ++l) {
         H->par[l] = level_params(H, l, s);
@@ -1276,23 +1282,27 @@ static void set_operator_impl(saamg_hierarchy* H, const saamg_domain* dom, hipSt
     DeviceDomain dd(dom, D, L.nbox, s);
     check_same_rows(H, dd, s);
     if (!H->op) {
-        FineLevel* op = new FineLevel(L);  // shares the segment masks and slots
+        // shares the segment masks and the rows' full slots; its own de-duplicated slots
+        // and table (fine_numbers)
+        FineLevel* op = new FineLevel(L);
         op->tab64 = nullptr;
         op->tab32 = nullptr;
         op->sigma = nullptr;
+        op->base = nullptr;
         try {
-            op->tab64 = (double*)dmalloc(8 * 16 * std::max<long>(L.n_irr, 1));
-            op->tab32 = (float*)dmalloc(4 * 16 * std::max<long>(L.n_irr, 1));
+            op->base = (int32_t*)dmalloc(4 * L.nseg);
             op->sigma = (double*)dmalloc(8 * L.nbox);
         } catch (...) {
-            for (void* p : {(void*)op->tab64, (void*)op->tab32, (void*)op->sigma}) dfree(p);
+            for (void* p : {(void*)op->base, (void*)op->sigma}) dfree(p);
             delete op;
             throw;
         }
         H->op = op;
-        H->bytes += 8L * L.nbox + 12L * 16 * L.n_irr;
+        H->bytes += 8L * L.nbox + 4L * L.nseg;
     }
+    H->bytes -= 12L * 16 * H->op->n_tab;
     fine_numbers(*H->op, dom, dd, H->variant, s);
+    H->bytes += 12L * 16 * H->op->n_tab;
 }
 
 template <class F>
@@ -1508,8 +1518,9 @@ int saamg_destroy(saamg_hierarchy* H) {
     // no queued work uses H any more (solves return complete, states are destroyed first)
     MemScope ms(H->mem, nullptr);
     FineLevel& L = H->l0;
-    for (void* p : {(void*)L.unk, (void*)L.irr, (void*)L.base, (void*)L.tab64, (void*)L.tab32,
-                    (void*)L.sigma, (void*)H->Ainv, (void*)H->cidx})
+    for (void* p : {(void*)L.unk, (void*)L.irr, (void*)L.base, (void*)L.base_full,
+                    (void*)L.tab64, (void*)L.tab32, (void*)L.sigma, (void*)H->Ainv,
+                    (void*)H->cidx})
         dfree(p);
     for (auto& C : H->lc) free_coarse(C);
     drop_operator(H);
@@ -1550,6 +1561,7 @@ int saamg_hierarchy_info(const saamg_hierarchy* H, saamg_info* info) {
         info->l0_wide = H->l0.wide;
         info->l0_wide_planes[0] = H->l0.wzb[1];
         info->l0_wide_planes[1] = H->l0.wzb[0];
+        info->table_rows[0] = H->l0.n_tab;
         for (int l = 1; l < H->n_levels; ++l) {
             info->table_rows[l] = H->lc[l - 1].n_tab;
             info->table_rows_t[l] = H->lc[l - 1].sym ? 0 : H->lc[l - 1].n_tabT;

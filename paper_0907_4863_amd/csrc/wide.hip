@@ -77,6 +77,7 @@ struct WPlane {
     int sp;         // the row's packed span word (wave-uniform; see wmarch)
     int tb0;        // table slot of the row's first irregular node (wave-uniform)
     bool ins1;      // lane inside the row's unknown span (in lanes) in plane z+1
+    bool reuse;     // the row's table rows are the previous plane's (staged already)
     long ib;        // box index of the span's first node in this plane (wave-uniform)
     Vec<TX, N> nxt, ym, yp;  // X at (z+1), (y-1), (y+1)
     TX edge;        // lanes 0 and 63: X beyond the span's ends (0 at the line's ends)
@@ -112,14 +113,16 @@ __device__ __forceinline__ void row6(const TV* p, T t[6]) {
 // row has unknowns and irregular nodes, and how many irregular nodes), which a plane step
 // reads with one broadcast; a lane takes its own segment word with cross-lane permutes.
 //
-// Table rows: the irregular nodes of a row's span have consecutive table slots, so the
-// wavefront reads them together, 16 bytes per lane (32 fp32 or 16 fp64 rows per load,
-// the first load issued a plane ahead), stages them in its slice of LDS, and each lane
-// reads the rows of its own irregular nodes from there.  Reading the rows lane by lane
-// instead issued up to 2 N loads per plane and took a quarter of the time of the fp32
-// stencil kernels.
-template <typename T, int N, bool STENCIL, bool TR, bool FULL, class TX, class Fetch, class Body,
-          class End = NoEnd>
+// Table rows (STENCIL, or TAB: the body receives the lane's rows as a last argument): the
+// irregular nodes of a row's span have consecutive table slots, so the wavefront reads
+// them together, 16 bytes per lane (32 fp32 or 16 fp64 rows per load, the first load
+// issued a plane ahead), stages them in its slice of LDS, and each lane reads the rows of
+// its own irregular nodes from there.  Reading the rows lane by lane instead issued up to
+// 2 N loads per plane and took a quarter of the time of the fp32 stencil kernels.  A row
+// whose rows are those of the plane before (its line repeats the line below: the same
+// slots) neither loads nor stages them again.
+template <typename T, int N, bool STENCIL, bool TR, bool FULL, bool TAB = STENCIL, class TX,
+          class Fetch, class Body, class End = NoEnd>
 __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict__ X, Fetch fetch,
                                        Body body, End end = End{}) {
     static_assert(N == 2 || N == 4, "16-byte lanes of 8- or 4-byte values");
@@ -220,6 +223,9 @@ __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict_
         P.nibr = ((lowh ? rlo : rhi) >> shh) & NM;
         P.rk0 = sb + (lowh ? (int)__popc(rlo & below) : (int)__popc(rlo) + (int)__popc(rhi & below));
         P.tb0 = __builtin_amdgcn_readlane(wb, k * N);
+        const int cnt = P.sp >> SP_CNT;
+        P.reuse = q > z0 && cnt <= R && P.tb0 == __builtin_amdgcn_readlane(wb, (k - 1) * N) &&
+                  cnt == (span_word(k - 1) >> SP_CNT);
         P.fv = fetch(Idx{ib, (unsigned)(N * lc)}, x0 + N * lc, y, q, P.nibr, P.rk0);
         if (STENCIL) {
             P.nxt = load_vec(ib + nxy, lc1);
@@ -228,7 +234,11 @@ __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict_
             P.edge = TX(0);
             if (lane == 0 && x0 > 0) P.edge = at(X, Idx{ib - 1, 0u});
             if (lane == kWave - 1 && x0 + W < v.nx) P.edge = at(X, Idx{ib, (unsigned)W});
-            P.trow = load_rows(P.tb0, 0, P.sp >> SP_CNT);
+        }
+        if (TAB) {
+#pragma unroll
+            for (int e = 0; e < 16 / (int)sizeof(T); ++e) P.trow[e] = T(0);
+            if (!P.reuse) P.trow = load_rows(P.tb0, 0, cnt);
         }
         return P;
     };
@@ -247,8 +257,8 @@ __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict_
             settle(P.ym);
             settle(P.yp);
             settle(P.edge);
-            settle(P.trow);
         }
+        if (TAB) settle(P.trow);
         settle(P.fv);
     };
     auto step = [&](const WP& P, int z) {
@@ -263,32 +273,34 @@ __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict_
                 cv.v[e] = T(c.v[e]);
                 ax.v[e] = T(0);
             }
-            if (STENCIL) {
-                // table rows of the lane's irregular nodes, staged through LDS one
-                // wavefront load at a time (one load for rows of up to R irregular nodes)
-                T t[N][6];
+            // table rows of the lane's irregular nodes, staged through LDS one wavefront
+            // load at a time (one load for rows of up to R irregular nodes)
+            T t[N][6];
 #pragma unroll
-                for (int e = 0; e < N; ++e)
+            for (int e = 0; e < N; ++e)
 #pragma unroll
-                    for (int d = 0; d < 6; ++d) t[e][d] = T(0);
-                if (P.sp & SP_IRR) {
-                    const int cnt = P.sp >> SP_CNT;
-                    for (int ch = 0; ch * R < cnt; ++ch) {
+                for (int d = 0; d < 6; ++d) t[e][d] = T(0);
+            if (TAB && (P.sp & SP_IRR)) {
+                const int cnt = P.sp >> SP_CNT;
+                for (int ch = 0; ch * R < cnt; ++ch) {
+                    if (!P.reuse) {  // (reuse: one load's rows, staged by the plane before)
                         const TV d = ch ? load_rows(P.tb0, ch, cnt) : P.trow;
                         __builtin_amdgcn_wave_barrier();
                         stage[lane] = d;
                         __builtin_amdgcn_wave_barrier();
-                        int r = P.rk0 - P.tb0 - ch * R;
-#pragma unroll
-                        for (int e = 0; e < N; ++e) {
-                            if ((P.nibr >> e) & 1u) {
-                                if (r >= 0 && r < R) row6<T>(stage + r * RV, t[e]);
-                                ++r;
-                            }
-                        }
-                        __builtin_amdgcn_wave_barrier();
                     }
+                    int r = P.rk0 - P.tb0 - ch * R;
+#pragma unroll
+                    for (int e = 0; e < N; ++e) {
+                        if ((P.nibr >> e) & 1u) {
+                            if (r >= 0 && r < R) row6<T>(stage + r * RV, t[e]);
+                            ++r;
+                        }
+                    }
+                    __builtin_amdgcn_wave_barrier();
                 }
+            }
+            if (STENCIL) {
                 const T left = T(wave_shift<true>(c.v[N - 1], P.edge));
                 const T right = T(wave_shift<false>(c.v[0], P.edge));
 #pragma unroll
@@ -306,8 +318,12 @@ __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict_
                     }
                 }
             }
-            if (FULL ? inb : P.nib != 0u)
-                body(Idx{P.ib, (unsigned)(N * lane)}, P.fv, cv, ax, xl, y, z, P.nib);
+            if (FULL ? inb : P.nib != 0u) {
+                if constexpr (TAB && !STENCIL)
+                    body(Idx{P.ib, (unsigned)(N * lane)}, P.fv, cv, ax, xl, y, z, P.nib, t);
+                else
+                    body(Idx{P.ib, (unsigned)(N * lane)}, P.fv, cv, ax, xl, y, z, P.nib);
+            }
         }
         if (STENCIL) {
             zm = c;
@@ -567,7 +583,6 @@ __global__ void __launch_bounds__(kMThreads) k_w_prolong(L0View<T> v, LCView<T> 
         T yn[2];   // y-face lines: the y-neighbour values of aggregates qx0, qx0+1
         T zn[2];   // z-face planes: the z-neighbour values of aggregates qx0, qx0+1
         Vec<T, N> x;
-        T t[N][6];
         unsigned irr;  // the lane's irregular bits
     };
     const int lane = threadIdx.x;
@@ -604,24 +619,13 @@ __global__ void __launch_bounds__(kMThreads) k_w_prolong(L0View<T> v, LCView<T> 
         }
         r.x = vldnt<N>(xv, i);
         r.irr = nibr;
-#pragma unroll
-        for (int e = 0; e < N; ++e)
-#pragma unroll
-            for (int d = 0; d < 6; ++d) r.t[e][d] = T(0);
-        int rk = rk0;
-#pragma unroll
-        for (int e = 0; e < N; ++e) {
-            if ((nibr >> e) & 1u) {
-                load_row6(v.tab, 0, (unsigned)rk, r.t[e]);
-                ++rk;
-            }
-        }
         return r;
     };
-    wmarch<T, N, false, false, kFullRows<T>>(
+    // the table rows come from the march (TAB)
+    wmarch<T, N, false, false, kFullRows<T>, true>(
         v, (const T*)nullptr, fetch,
         [&](Idx i, const R& r, const Vec<T, N>&, const Vec<T, N>&, int xl, int y, int z,
-            unsigned nib) {
+            unsigned nib, const T (&t)[N][6]) {
             const int xs = min(xl, v.nx - N);
             const int qx0 = xs / 3, fy = y - 3 * (y / 3), zr = z - 3 * (z / 3);
             T o[N];
@@ -642,8 +646,8 @@ __global__ void __launch_bounds__(kMThreads) k_w_prolong(L0View<T> v, LCView<T> 
                 const T czp = zr == 2 ? czf : c0;
                 T apv;
                 if ((r.irr >> e) & 1u) {
-                    apv = c0 + r.t[e][0] * cxm + r.t[e][1] * cxp + r.t[e][2] * cym +
-                          r.t[e][3] * cyp + r.t[e][4] * czm + r.t[e][5] * czp;
+                    apv = c0 + t[e][0] * cxm + t[e][1] * cxp + t[e][2] * cym + t[e][3] * cyp +
+                          t[e][4] * czm + t[e][5] * czp;
                 } else {
                     apv = c0 + v.c[0] * (cxm + cxp) + v.c[1] * (cym + cyp) + v.c[2] * (czm + czp);
                 }
