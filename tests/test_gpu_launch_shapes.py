@@ -80,6 +80,11 @@ def test_automatic_shape_of_the_full_size_problems():
               info["l0_wide_planes"], flush=True)
         assert (info["l0_planes"], info["l0_tile_x"]) == want, name
         assert info["l0_wide"] == 1 and info["l0_wide_planes"] == [8, 16], name
+        # the cross-section repeats along the pipe: the level-0 table holds the rows of a
+        # few planes (lines equal to the line below share its rows)
+        print(name, "table rows", info["table_rows"][0], "irregular rows", info["n_irregular"],
+              flush=True)
+        assert 0 < info["table_rows"][0] < info["n_irregular"] // 4, name
         sa.destroy(G)
 
 
