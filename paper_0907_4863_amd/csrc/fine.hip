@@ -48,16 +48,16 @@ bool l0_wide_default(int nx) { return nx % 4 == 0 && nx > 128; }
 
 // Which level-0 launchers run on 16-byte lanes when the hierarchy uses them (measured per
 // kernel on the 256 x 256 x 768 elliptic pipe, one-node against 16-byte lanes, us per
-// launch): every V-cycle kernel in both precisions (fp32 residual 132 -> 119, restriction
-// pass 125 -> 101, prolongation 130 -> 113; fp64 residual 282 -> 215, restriction pass
-// 208 -> 158), the fp64 residual and the direction update with an fp64 z (511 -> 489).
-// The direction update with an fp32 z (456 against 465) and the streaming r -= alpha q
-// (234 against 242, fp64 192 against 199) keep one node per lane.
-static bool pq_wide(const FineLevel& L, bool z32) { return L.wide && !z32; }
+// launch): every V-cycle kernel in both precisions (fp32 residual 132 -> 107, restriction
+// pass 125 -> 89; fp64 residual 282 -> 204, restriction pass 208 -> 141), the residual of
+// the CG and both forms of the direction update (fp64 511 -> 476; the mixed-precision
+// stencil pass q = A p 183 -> 174).  The streaming r -= alpha q keeps one node per lane
+// (234 against 242, fp64 192 against 199).
+static bool pq_wide(const FineLevel& L) { return L.wide; }
 
 long cg_resid_parts(const FineLevel& L) { return L.wide ? l0_wblocks(L, 2) : l0_blocks(L); }
 long cg_pq_parts(const FineLevel& L, bool z32) {
-    return pq_wide(L, z32) ? l0_wblocks(L, 2) : l0_blocks(L);
+    return pq_wide(L) ? l0_wblocks(L, z32 ? 4 : 2) : l0_blocks(L);
 }
 long cg_xr_parts(const FineLevel& L) { return l0_blocks(L); }
 long l0_dot_parts(const FineLevel& L, int bytes) {
@@ -1280,15 +1280,13 @@ void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, 
     HIPCHECK(hipGetLastError());
 }
 
-// Direction update with the product by A carried along:  p <- z + beta p and
-// q <- A z + beta q, which equals A p_new because q held A p_old.  The stencil runs on z
-// (fp32 in mixed precision), the sums in fp64; partials of p . q.  The previous step's
-// x += alpha p, deferred to here, is applied with the old p as it is read.  With an fp32 z
-// (mixed precision) it stores whole rows.  (Forming p_new at every stencil node from z and
-// the old p instead, and q = A p_new, moves 8 bytes less per unknown but needs twice the
-// stencil loads: measured slower on the 256 x 256 x 768 ellipse, 454 -> 488 us.)
-template <typename TZ>
-__global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ* __restrict__ zv,
+// Direction update with the product by A carried along (fp64):  p <- z + beta p and
+// q <- A z + beta q, which equals A p_new because q held A p_old.  Partials of p . q.  The
+// previous step's x += alpha p, deferred to here, is applied with the old p as it is read.
+// (Forming p_new at every stencil node from z and the old p instead, and q = A p_new, moves
+// 8 bytes less per unknown but needs twice the stencil loads: measured slower on the
+// 256 x 256 x 768 ellipse, 454 -> 488 us.)
+__global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const double* __restrict__ zv,
                                                     double* __restrict__ xv,
                                                     double* __restrict__ p, double* __restrict__ q,
                                                     const double* __restrict__ scal, double* part) {
@@ -1296,7 +1294,7 @@ __global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ*
     const double beta = scal[S_BETA];
     const double xa = scal[S_XA];
     double acc = 0.0;
-    l0_march<double, true, false, kFullRows<TZ>>(
+    l0_march<double, true, false, false>(
         v, [&](Idx j) { return at(zv, j); },
         [&](Idx i, int, int, int, bool, int) {
             return Vals<double, 3>{{at(p, i), at(q, i), at(xv, i)}};
@@ -1314,23 +1312,73 @@ __global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ*
     if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
+// Mixed precision keeps the direction in fp32 and forms the product from it, in two passes:
+//   x += alpha_prev p;  p <- fl32(z + beta p)        (k_cg_pupd, a stream)
+//   q = A p in fp64 from the stored p; partials of p . q   (k_cg_q, a stencil)
+// x += alpha p and r -= alpha q then use the same stored p and q = A p, so the recursive
+// residual follows the true one in fp64 arithmetic; rounding p to fp32 only perturbs the
+// conjugacy of the directions, at the level of the fp32 preconditioned residual z it is
+// formed from.  40 bytes per unknown instead of the fused fp64 form's 52.
+__global__ void __launch_bounds__(kMThreads) k_cg_pupd(L0View<double> v, const float* __restrict__ zv,
+                                                      float* __restrict__ p, double* __restrict__ xv,
+                                                      const double* __restrict__ scal) {
+    const double beta = scal[S_BETA];
+    const double xa = scal[S_XA];
+    struct R {
+        float z, p;
+        double x;
+    };
+    l0_march<double, false, false, true>(
+        v, [&](Idx) { return 0.0; },
+        [&](Idx i, int, int, int, bool, int) { return R{ntl(zv, i), at(p, i), at(xv, i)}; },
+        [&](Idx i, R f, double, double, int, int, int, bool, int rk) {
+            const bool u = rk >= 0;
+            nts(p, i, u ? (float)((double)f.z + beta * (double)f.p) : 0.0f);
+            nts(xv, i, u ? f.x + xa * (double)f.p : 0.0);
+        });
+}
+
+__global__ void __launch_bounds__(kMThreads) k_cg_q(L0View<double> v, const float* __restrict__ p,
+                                                   double* __restrict__ q, double* part) {
+    __shared__ double lds[kMThreads / kWave];
+    double acc = 0.0;
+    l0_march<double, true, false, false>(
+        v, [&](Idx j) { return at(p, j); }, NOFETCH,
+        [&](Idx i, NoVals, double pi, double ap, int, int, int, bool, int) {
+            nts(q, i, ap);
+            acc += pi * ap;
+        });
+    double sb = block_sum(acc, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
+}
+
 template <typename TZ>
-void cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
+void cg_pq(const FineLevel& L, const TZ* z, double* x, TZ* p, double* q, const double* scal,
            double* partials, hipStream_t s) {
-    KTimer kt_(T_CG_PQ, s, L.n_unknowns * (long)(sizeof(TZ) + 48) + l0_meta_bytes(L, 8, false));
     if constexpr (sizeof(TZ) == 8) {
-        if (pq_wide(L, false)) {
-            w_cg_pq<TZ>(L, z, x, p, q, scal, partials, kt_);
+        KTimer kt_(T_CG_PQ, s, L.n_unknowns * 56L + l0_meta_bytes(L, 8, false));
+        if (pq_wide(L)) {
+            w_cg_pq<double>(L, z, x, p, q, scal, partials, kt_);
             return;
         }
+        klaunch(kt_, true, k_cg_pq, l0_mgrid(L), dim3(kWave, kMY), L.view<double>(), z, x, p, q,
+                scal, partials);
+    } else {
+        // z, p: 4 + 4 read, p 4 written, x 8 + 8; p 4 read, q 8 written
+        KTimer kt_(T_CG_PQ, s, L.n_unknowns * 40L + 2 * l0_meta_bytes(L, 8, false));
+        if (pq_wide(L)) {
+            w_cg_pq_split(L, z, x, p, q, scal, partials, kt_);
+            return;
+        }
+        const dim3 g = l0_mgrid(L), b(kWave, kMY);
+        klaunch(kt_, false, k_cg_pupd, g, b, L.view<double>(), z, p, x, scal);
+        klaunch(kt_, true, k_cg_q, g, b, L.view<double>(), (const float*)p, q, partials);
     }
-    klaunch(kt_, true, (k_cg_pq<TZ>), l0_mgrid(L), dim3(kWave, kMY), L.view<double>(), z, x, p, q,
-            scal, partials);
     HIPCHECK(hipGetLastError());
 }
 template void cg_pq<double>(const FineLevel&, const double*, double*, double*, double*,
                             const double*, double*, hipStream_t);
-template void cg_pq<float>(const FineLevel&, const float*, double*, double*, double*,
+template void cg_pq<float>(const FineLevel&, const float*, double*, float*, double*,
                            const double*, double*, hipStream_t);
 
 // r -= alpha q (alpha = S_XA) and partials of r.r; r untouched when the step broke down
@@ -1374,23 +1422,31 @@ void cg_xr(const FineLevel& L, double* r, const double* q, const double* scal, d
     HIPCHECK(hipGetLastError());
 }
 
+template <typename TP>
 __global__ void __launch_bounds__(kMThreads) k_cg_xflush(L0View<double> v, double* __restrict__ xv,
-                                                        const double* __restrict__ p,
+                                                        const TP* __restrict__ p,
                                                         const double* __restrict__ scal) {
     const double xa = scal[S_XA];
     l0_march<double, false, false>(
         v, [&](Idx) { return 0.0; },
-        [&](Idx i, int, int, int, bool, int) { return Vals<double, 2>{{at(xv, i), at(p, i)}}; },
+        [&](Idx i, int, int, int, bool, int) {
+            return Vals<double, 2>{{at(xv, i), (double)at(p, i)}};
+        },
         [&](Idx i, Vals<double, 2> f, double, double, int, int, int, bool, int) {
             at(xv, i) = f.v[0] + xa * f.v[1];
         });
 }
 
-void cg_xflush(const FineLevel& L, double* x, const double* p, const double* scal, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_xflush, l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), x, p,
-                       scal);
+template <typename TP>
+void cg_xflush(const FineLevel& L, double* x, const TP* p, const double* scal, hipStream_t s) {
+    hipLaunchKernelGGL((k_cg_xflush<TP>), l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), x,
+                       p, scal);
     HIPCHECK(hipGetLastError());
 }
+template void cg_xflush<double>(const FineLevel&, double*, const double*, const double*,
+                                hipStream_t);
+template void cg_xflush<float>(const FineLevel&, double*, const float*, const double*,
+                               hipStream_t);
 
 // out = sigma x on every box node (0 where not an unknown): the caller's buffer.
 __global__ void __launch_bounds__(kThreads) k_cg_unscale(L0View<double> v, const double* __restrict__ sigma,

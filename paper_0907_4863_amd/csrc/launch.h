@@ -133,6 +133,9 @@ void w_cg_resid(const FineLevel& L, const double* bs, const double* x, double* r
 template <typename TZ>
 void w_cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
              double* partials, KTimer& kt);
+// mixed precision: fp32 direction, x += alpha p and p <- fl32(z + beta p), then q = A p
+void w_cg_pq_split(const FineLevel& L, const float* z, double* x, float* p, double* q,
+                   const double* scal, double* partials, KTimer& kt);
 
 // ---- level 0: CG (fp64)
 void cg_init(const FineLevel& L, const double* b, const double* x0, double* bs, double* x,
@@ -140,13 +143,17 @@ void cg_init(const FineLevel& L, const double* b, const double* x0, double* bs, 
 // r32 (nullable): fp32 copy of the residual for the fp32 V-cycle
 void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
               float* r32, hipStream_t s);
+// Direction update, the product by A and the partials of p . q; the direction p has z's
+// precision (fp32 in mixed precision: two passes, q = A p from the stored p; fp64: one pass
+// with the q-recursion).
 template <typename TZ>
-void cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
+void cg_pq(const FineLevel& L, const TZ* z, double* x, TZ* p, double* q, const double* scal,
            double* partials, hipStream_t s);
 void cg_xr(const FineLevel& L, double* r, const double* q, const double* scal, double* partials,
            float* r32, hipStream_t s);
 // x += S_XA p: the update the last step still owes x
-void cg_xflush(const FineLevel& L, double* x, const double* p, const double* scal, hipStream_t s);
+template <typename TP>
+void cg_xflush(const FineLevel& L, double* x, const TP* p, const double* scal, hipStream_t s);
 void cg_unscale(const FineLevel& L, const double* x, double* out, hipStream_t s);
 // out = in on the unknowns (out untouched elsewhere)
 void cg_mask_copy(const FineLevel& L, const double* in, double* out, float* out32, hipStream_t s);

@@ -376,9 +376,10 @@ struct saamg_state {
     double tol = 1e-8;
     int max_iter = 0;
     bool mixed = false;
-    double *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *bs = nullptr;
+    double *x = nullptr, *r = nullptr, *q = nullptr, *bs = nullptr;
     float* r32 = nullptr;  // fp32 copy of r (mixed precision)
-    void* z = nullptr;
+    void* z = nullptr;     // preconditioned residual, and the direction p: fp32 in mixed
+    void* p = nullptr;     // precision, fp64 otherwise
     VBuf<float> vf;
     VBuf<double> vd;
     double* part = nullptr;
@@ -412,12 +413,13 @@ static void state_alloc(saamg_state* S, saamg_hierarchy* H, bool pinned = true) 
     const long n = H->l0.nbox;
     S->x = (double*)dmalloc(8 * n);
     S->r = (double*)dmalloc(8 * n);
-    S->p = (double*)dmalloc(8 * n);
+    S->p = dmalloc((S->mixed ? 4 : 8) * n);
     S->q = (double*)dmalloc(8 * n);
     S->bs = (double*)dmalloc(8 * n);
     S->z = dmalloc((S->mixed ? 4 : 8) * n);
     if (S->mixed) S->r32 = (float*)dmalloc(4 * n);
-    S->bytes = 40L * n + (S->mixed ? 8 : 8) * n;
+    // x, r, q, b~ (fp64); p and z (fp32 in mixed precision, with the fp32 copy of r)
+    S->bytes = 32L * n + (S->mixed ? 12 : 16) * n;
     if (S->mixed) {
         S->vf.alloc(H);
         S->bytes += S->vf.bytes(H);
@@ -439,7 +441,8 @@ static void state_alloc(saamg_state* S, saamg_hierarchy* H, bool pinned = true) 
 }
 
 static void state_release(saamg_state* S) {
-    for (double* p : {S->x, S->r, S->p, S->q, S->bs}) dfree(p);
+    for (double* p : {S->x, S->r, S->q, S->bs}) dfree(p);
+    dfree(S->p);
     dfree(S->z);
     dfree(S->r32);
     S->r32 = nullptr;
@@ -449,8 +452,8 @@ static void state_release(saamg_state* S) {
     dfree(S->scal);
     if (S->hscal && S->hscal != S->hbuf) (void)hipHostFree(S->hscal);
     if (S->ev) (void)hipEventDestroy(S->ev);
-    S->x = S->r = S->p = S->q = S->bs = nullptr;
-    S->z = nullptr;
+    S->x = S->r = S->q = S->bs = nullptr;
+    S->z = S->p = nullptr;
     S->part = S->scal = S->hscal = nullptr;
     S->ev = nullptr;
 }
@@ -494,7 +497,7 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
     cg_resid(cg_op(H), S->bs, S->x, S->r, S->part, S->r32, S->s);
     finalize(S->part, cg_resid_parts(cg_op(H)), 2, S->scal, FIN_STORE, S_RR, S->s);
     scal_start(S->scal, S->tol, S->s);
-    zero_fill(S->p, 8 * H->l0.nbox, S->s);
+    zero_fill(S->p, (S->mixed ? 4 : 8) * H->l0.nbox, S->s);
     zero_fill(S->q, 8 * H->l0.nbox, S->s);
     read_scal(S);
     const double rr = S->hscal[S_RR], bb = S->hscal[S_BB];
@@ -531,9 +534,9 @@ static void state_enqueue(saamg_state* S) {
     const saamg_hierarchy* H = S->H;
     const FineLevel& L = cg_op(H);
     if (S->mixed)
-        cg_pq<float>(L, (const float*)S->z, S->x, S->p, S->q, S->scal, S->part, S->s);
+        cg_pq<float>(L, (const float*)S->z, S->x, (float*)S->p, S->q, S->scal, S->part, S->s);
     else
-        cg_pq<double>(L, (const double*)S->z, S->x, S->p, S->q, S->scal, S->part, S->s);
+        cg_pq<double>(L, (const double*)S->z, S->x, (double*)S->p, S->q, S->scal, S->part, S->s);
     finalize(S->part, cg_pq_parts(L, S->mixed), 1, S->scal, FIN_ALPHA, 0, S->s);
     cg_xr(L, S->r, S->q, S->scal, S->part, S->r32, S->s);
     finalize(S->part, cg_xr_parts(L), 1, S->scal, FIN_RR, 0, S->s);
@@ -548,7 +551,10 @@ static void state_enqueue(saamg_state* S) {
 // The step length a step still owes x (each step's x += alpha p is applied by the next
 // step's direction update): apply it now and clear it.  Needed before x is read.
 static void flush_x(saamg_state* S) {
-    cg_xflush(cg_op(S->H), S->x, S->p, S->scal, S->s);
+    if (S->mixed)
+        cg_xflush<float>(cg_op(S->H), S->x, (const float*)S->p, S->scal, S->s);
+    else
+        cg_xflush<double>(cg_op(S->H), S->x, (const double*)S->p, S->scal, S->s);
     finalize(S->part, 1, 0, S->scal, FIN_XA_CLEAR, 0, S->s);
 }
 

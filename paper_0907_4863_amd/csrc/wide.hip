@@ -788,4 +788,69 @@ void w_cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, c
 template void w_cg_pq<double>(const FineLevel&, const double*, double*, double*, double*,
                               const double*, double*, KTimer&);
 
+// Mixed precision's direction update in two passes (see k_cg_pupd and k_cg_q), 4 nodes per
+// lane: the fp32 direction and z move 16 bytes per lane, x and q 32.
+__global__ void __launch_bounds__(kMThreads) k_w_cg_pupd(L0View<double> v,
+                                                        const float* __restrict__ zv,
+                                                        float* __restrict__ p,
+                                                        double* __restrict__ xv,
+                                                        const double* __restrict__ scal) {
+    constexpr int N = 4;
+    const double beta = scal[S_BETA];
+    const double xa = scal[S_XA];
+    struct R {
+        Vec<float, N> z, p;
+        Vec<double, N> x;
+    };
+    wmarch<double, N, false, false, true>(
+        v, (const float*)nullptr,
+        [&](Idx i, int, int, int, unsigned, int) {
+            return R{vldnt<N>(zv, i), vld<N>(p, i), vld<N>(xv, i)};
+        },
+        [&](Idx i, const R& f, const Vec<double, N>&, const Vec<double, N>&, int, int, int,
+            unsigned nib) {
+            float pn[N];
+            double xo[N];
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                const bool u = (nib >> e) & 1u;
+                pn[e] = u ? (float)((double)f.z.v[e] + beta * (double)f.p.v[e]) : 0.0f;
+                xo[e] = u ? f.x.v[e] + xa * (double)f.p.v[e] : 0.0;
+            }
+            vstnt<N>(p, i, pn);
+            vstnt<N>(xv, i, xo);
+        });
+}
+
+__global__ void __launch_bounds__(kMThreads) k_w_cg_q(L0View<double> v, const float* __restrict__ p,
+                                                     double* __restrict__ q, double* part) {
+    constexpr int N = 4;
+    __shared__ double lds[kMThreads / kWave];
+    double acc = 0.0;
+    wmarch<double, N, true, false, false>(
+        v, p, WNOFETCH,
+        [&](Idx i, NoVals, const Vec<double, N>& pv, const Vec<double, N>& ap, int, int, int,
+            unsigned nib) {
+            double qo[N];
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                const bool u = (nib >> e) & 1u;
+                qo[e] = u ? ap.v[e] : 0.0;
+                acc += u ? pv.v[e] * ap.v[e] : 0.0;
+            }
+            vstnt<N>(q, i, qo);
+        });
+    const double sb = block_sum(acc, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
+}
+
+void w_cg_pq_split(const FineLevel& L, const float* z, double* x, float* p, double* q,
+                   const double* scal, double* partials, KTimer& kt_) {
+    const dim3 g((unsigned)l0_wblocks(L, 4)), b(kWave, kMY);
+    const L0View<double> v = wview<double>(L, 4);
+    klaunch(kt_, false, k_w_cg_pupd, g, b, v, z, p, x, scal);
+    klaunch(kt_, true, k_w_cg_q, g, b, v, (const float*)p, q, partials);
+    HIPCHECK(hipGetLastError());
+}
+
 }  // namespace saamg
