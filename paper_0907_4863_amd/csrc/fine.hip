@@ -56,8 +56,8 @@ bool l0_wide_default(int nx) { return nx % 4 == 0 && nx > 128; }
 static bool pq_wide(const FineLevel& L) { return L.wide; }
 
 long cg_resid_parts(const FineLevel& L) { return L.wide ? l0_wblocks(L, 2) : l0_blocks(L); }
-long cg_pq_parts(const FineLevel& L, bool z32) {
-    return pq_wide(L) ? l0_wblocks(L, z32 ? 4 : 2) : l0_blocks(L);
+long cg_pq_parts(const FineLevel& L, bool split) {
+    return pq_wide(L) ? l0_wblocks(L, split ? 4 : 2) : l0_blocks(L);
 }
 long cg_xr_parts(const FineLevel& L) { return l0_blocks(L); }
 long l0_dot_parts(const FineLevel& L, int bytes) {
@@ -1280,13 +1280,14 @@ void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, 
     HIPCHECK(hipGetLastError());
 }
 
-// Direction update with the product by A carried along (fp64):  p <- z + beta p and
+// Direction update with the product by A carried along (fp64 direction):  p <- z + beta p and
 // q <- A z + beta q, which equals A p_new because q held A p_old.  Partials of p . q.  The
 // previous step's x += alpha p, deferred to here, is applied with the old p as it is read.
 // (Forming p_new at every stencil node from z and the old p instead, and q = A p_new, moves
 // 8 bytes less per unknown but needs twice the stencil loads: measured slower on the
 // 256 x 256 x 768 ellipse, 454 -> 488 us.)
-__global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const double* __restrict__ zv,
+template <typename TZ>
+__global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ* __restrict__ zv,
                                                     double* __restrict__ xv,
                                                     double* __restrict__ p, double* __restrict__ q,
                                                     const double* __restrict__ scal, double* part) {
@@ -1294,7 +1295,7 @@ __global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const dou
     const double beta = scal[S_BETA];
     const double xa = scal[S_XA];
     double acc = 0.0;
-    l0_march<double, true, false, false>(
+    l0_march<double, true, false, kFullRows<TZ>>(
         v, [&](Idx j) { return at(zv, j); },
         [&](Idx i, int, int, int, bool, int) {
             return Vals<double, 3>{{at(p, i), at(q, i), at(xv, i)}};
@@ -1312,74 +1313,44 @@ __global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const dou
     if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
-// Mixed precision keeps the direction in fp32 and forms the product from it, in two passes:
-//   x += alpha_prev p;  p <- fl32(z + beta p)        (k_cg_pupd, a stream)
-//   q = A p in fp64 from the stored p; partials of p . q   (k_cg_q, a stencil)
+// On 16-byte lanes mixed precision keeps the direction in fp32 and forms the product from
+// it, in two passes:
+//   x += alpha_prev p;  p <- fl32(z + beta p)        (k_w_cg_pupd, a stream)
+//   q = A p in fp64 from the stored p; partials of p . q   (k_w_cg_q, a stencil)
 // x += alpha p and r -= alpha q then use the same stored p and q = A p, so the recursive
 // residual follows the true one in fp64 arithmetic; rounding p to fp32 only perturbs the
 // conjugacy of the directions, at the level of the fp32 preconditioned residual z it is
-// formed from.  40 bytes per unknown instead of the fused fp64 form's 52.
-__global__ void __launch_bounds__(kMThreads) k_cg_pupd(L0View<double> v, const float* __restrict__ zv,
-                                                      float* __restrict__ p, double* __restrict__ xv,
-                                                      const double* __restrict__ scal) {
-    const double beta = scal[S_BETA];
-    const double xa = scal[S_XA];
-    struct R {
-        float z, p;
-        double x;
-    };
-    l0_march<double, false, false, true>(
-        v, [&](Idx) { return 0.0; },
-        [&](Idx i, int, int, int, bool, int) { return R{ntl(zv, i), at(p, i), at(xv, i)}; },
-        [&](Idx i, R f, double, double, int, int, int, bool, int rk) {
-            const bool u = rk >= 0;
-            nts(p, i, u ? (float)((double)f.z + beta * (double)f.p) : 0.0f);
-            nts(xv, i, u ? f.x + xa * (double)f.p : 0.0);
-        });
-}
-
-__global__ void __launch_bounds__(kMThreads) k_cg_q(L0View<double> v, const float* __restrict__ p,
-                                                   double* __restrict__ q, double* part) {
-    __shared__ double lds[kMThreads / kWave];
-    double acc = 0.0;
-    l0_march<double, true, false, false>(
-        v, [&](Idx j) { return at(p, j); }, NOFETCH,
-        [&](Idx i, NoVals, double pi, double ap, int, int, int, bool, int) {
-            nts(q, i, ap);
-            acc += pi * ap;
-        });
-    double sb = block_sum(acc, lds);
-    if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
-}
+// formed from.  40 bytes per unknown instead of the fused form's 52 (on the 256 x 256 x 768
+// ellipse 398 against 447 us).  On one-node lanes, which serve the small boxes where each
+// launch's latency counts more than bytes, the fused form with an fp32 z stays.
+bool cg_split(const FineLevel& L, bool mixed) { return mixed && L.wide; }
 
 template <typename TZ>
-void cg_pq(const FineLevel& L, const TZ* z, double* x, TZ* p, double* q, const double* scal,
+void cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
            double* partials, hipStream_t s) {
+    KTimer kt_(T_CG_PQ, s, L.n_unknowns * (long)(sizeof(TZ) + 48) + l0_meta_bytes(L, 8, false));
     if constexpr (sizeof(TZ) == 8) {
-        KTimer kt_(T_CG_PQ, s, L.n_unknowns * 56L + l0_meta_bytes(L, 8, false));
         if (pq_wide(L)) {
             w_cg_pq<double>(L, z, x, p, q, scal, partials, kt_);
             return;
         }
-        klaunch(kt_, true, k_cg_pq, l0_mgrid(L), dim3(kWave, kMY), L.view<double>(), z, x, p, q,
-                scal, partials);
-    } else {
-        // z, p: 4 + 4 read, p 4 written, x 8 + 8; p 4 read, q 8 written
-        KTimer kt_(T_CG_PQ, s, L.n_unknowns * 40L + 2 * l0_meta_bytes(L, 8, false));
-        if (pq_wide(L)) {
-            w_cg_pq_split(L, z, x, p, q, scal, partials, kt_);
-            return;
-        }
-        const dim3 g = l0_mgrid(L), b(kWave, kMY);
-        klaunch(kt_, false, k_cg_pupd, g, b, L.view<double>(), z, p, x, scal);
-        klaunch(kt_, true, k_cg_q, g, b, L.view<double>(), (const float*)p, q, partials);
     }
+    klaunch(kt_, true, (k_cg_pq<TZ>), l0_mgrid(L), dim3(kWave, kMY), L.view<double>(), z, x, p, q,
+            scal, partials);
     HIPCHECK(hipGetLastError());
 }
 template void cg_pq<double>(const FineLevel&, const double*, double*, double*, double*,
                             const double*, double*, hipStream_t);
-template void cg_pq<float>(const FineLevel&, const float*, double*, float*, double*,
+template void cg_pq<float>(const FineLevel&, const float*, double*, double*, double*,
                            const double*, double*, hipStream_t);
+
+void cg_pq_split(const FineLevel& L, const float* z, double* x, float* p, double* q,
+                 const double* scal, double* partials, hipStream_t s) {
+    // z, p: 4 + 4 read, p 4 written, x 8 + 8; p 4 read, q 8 written
+    KTimer kt_(T_CG_PQ, s, L.n_unknowns * 40L + 2 * l0_meta_bytes(L, 8, false));
+    if (!pq_wide(L)) throw ApiError{SAAMG_INVALID_ARG, "the two-pass direction update needs 16-byte lanes"};
+    w_cg_pq_split(L, z, x, p, q, scal, partials, kt_);
+}
 
 // r -= alpha q (alpha = S_XA) and partials of r.r; r untouched when the step broke down
 // (S_XA = 0).  x receives alpha p later (the next k_cg_pq or k_cg_xflush).  With the fp32

@@ -52,7 +52,7 @@ long l0_wblocks(const FineLevel& L, int n);
 // not), cg_xr, and the V-cycle's fused r . z (its last Chebyshev step, or l0_dot) in a
 // working precision of `bytes` bytes.
 long cg_resid_parts(const FineLevel& L);
-long cg_pq_parts(const FineLevel& L, bool z32);
+long cg_pq_parts(const FineLevel& L, bool split);
 long cg_xr_parts(const FineLevel& L);
 long l0_dot_parts(const FineLevel& L, int bytes);
 int l0_choose_zb(int tx, int nsegx, int ny, int nz);
@@ -143,12 +143,15 @@ void cg_init(const FineLevel& L, const double* b, const double* x0, double* bs, 
 // r32 (nullable): fp32 copy of the residual for the fp32 V-cycle
 void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
               float* r32, hipStream_t s);
-// Direction update, the product by A and the partials of p . q; the direction p has z's
-// precision (fp32 in mixed precision: two passes, q = A p from the stored p; fp64: one pass
-// with the q-recursion).
+// Direction update, the product by A and the partials of p . q: one pass with the
+// q-recursion and an fp64 direction (z in the working precision), or (cg_split: mixed
+// precision on 16-byte lanes) two passes with an fp32 direction, q = A p from the stored p.
 template <typename TZ>
-void cg_pq(const FineLevel& L, const TZ* z, double* x, TZ* p, double* q, const double* scal,
+void cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
            double* partials, hipStream_t s);
+void cg_pq_split(const FineLevel& L, const float* z, double* x, float* p, double* q,
+                 const double* scal, double* partials, hipStream_t s);
+bool cg_split(const FineLevel& L, bool mixed);
 void cg_xr(const FineLevel& L, double* r, const double* q, const double* scal, double* partials,
            float* r32, hipStream_t s);
 // x += S_XA p: the update the last step still owes x

@@ -378,8 +378,9 @@ struct saamg_state {
     bool mixed = false;
     double *x = nullptr, *r = nullptr, *q = nullptr, *bs = nullptr;
     float* r32 = nullptr;  // fp32 copy of r (mixed precision)
-    void* z = nullptr;     // preconditioned residual, and the direction p: fp32 in mixed
-    void* p = nullptr;     // precision, fp64 otherwise
+    void* z = nullptr;     // preconditioned residual (fp32 in mixed precision)
+    void* p = nullptr;     // direction: fp32 when split (cg_split), else fp64
+    bool split = false;
     VBuf<float> vf;
     VBuf<double> vd;
     double* part = nullptr;
@@ -413,13 +414,14 @@ static void state_alloc(saamg_state* S, saamg_hierarchy* H, bool pinned = true) 
     const long n = H->l0.nbox;
     S->x = (double*)dmalloc(8 * n);
     S->r = (double*)dmalloc(8 * n);
-    S->p = dmalloc((S->mixed ? 4 : 8) * n);
+    S->split = cg_split(H->l0, S->mixed);
+    S->p = dmalloc((S->split ? 4 : 8) * n);
     S->q = (double*)dmalloc(8 * n);
     S->bs = (double*)dmalloc(8 * n);
     S->z = dmalloc((S->mixed ? 4 : 8) * n);
     if (S->mixed) S->r32 = (float*)dmalloc(4 * n);
-    // x, r, q, b~ (fp64); p and z (fp32 in mixed precision, with the fp32 copy of r)
-    S->bytes = 32L * n + (S->mixed ? 12 : 16) * n;
+    // x, r, q, b~ (fp64); p, z and the fp32 copy of r
+    S->bytes = 32L * n + (S->split ? 4 : 8) * n + 8L * n;  // z 8, or fp32 z and r32
     if (S->mixed) {
         S->vf.alloc(H);
         S->bytes += S->vf.bytes(H);
@@ -497,7 +499,7 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
     cg_resid(cg_op(H), S->bs, S->x, S->r, S->part, S->r32, S->s);
     finalize(S->part, cg_resid_parts(cg_op(H)), 2, S->scal, FIN_STORE, S_RR, S->s);
     scal_start(S->scal, S->tol, S->s);
-    zero_fill(S->p, (S->mixed ? 4 : 8) * H->l0.nbox, S->s);
+    zero_fill(S->p, (S->split ? 4 : 8) * H->l0.nbox, S->s);
     zero_fill(S->q, 8 * H->l0.nbox, S->s);
     read_scal(S);
     const double rr = S->hscal[S_RR], bb = S->hscal[S_BB];
@@ -533,11 +535,13 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
 static void state_enqueue(saamg_state* S) {
     const saamg_hierarchy* H = S->H;
     const FineLevel& L = cg_op(H);
-    if (S->mixed)
-        cg_pq<float>(L, (const float*)S->z, S->x, (float*)S->p, S->q, S->scal, S->part, S->s);
+    if (S->split)
+        cg_pq_split(L, (const float*)S->z, S->x, (float*)S->p, S->q, S->scal, S->part, S->s);
+    else if (S->mixed)
+        cg_pq<float>(L, (const float*)S->z, S->x, (double*)S->p, S->q, S->scal, S->part, S->s);
     else
         cg_pq<double>(L, (const double*)S->z, S->x, (double*)S->p, S->q, S->scal, S->part, S->s);
-    finalize(S->part, cg_pq_parts(L, S->mixed), 1, S->scal, FIN_ALPHA, 0, S->s);
+    finalize(S->part, cg_pq_parts(L, S->split), 1, S->scal, FIN_ALPHA, 0, S->s);
     cg_xr(L, S->r, S->q, S->scal, S->part, S->r32, S->s);
     finalize(S->part, cg_xr_parts(L), 1, S->scal, FIN_RR, 0, S->s);
     HIPCHECK(hipMemcpyAsync(S->hscal, S->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
@@ -551,7 +555,7 @@ static void state_enqueue(saamg_state* S) {
 // The step length a step still owes x (each step's x += alpha p is applied by the next
 // step's direction update): apply it now and clear it.  Needed before x is read.
 static void flush_x(saamg_state* S) {
-    if (S->mixed)
+    if (S->split)
         cg_xflush<float>(cg_op(S->H), S->x, (const float*)S->p, S->scal, S->s);
     else
         cg_xflush<double>(cg_op(S->H), S->x, (const double*)S->p, S->scal, S->s);

@@ -788,7 +788,7 @@ void w_cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, c
 template void w_cg_pq<double>(const FineLevel&, const double*, double*, double*, double*,
                               const double*, double*, KTimer&);
 
-// Mixed precision's direction update in two passes (see k_cg_pupd and k_cg_q), 4 nodes per
+// Mixed precision's direction update in two passes (see cg_pq_split in fine.hip), 4 nodes per
 // lane: the fp32 direction and z move 16 bytes per lane, x and q 32.
 __global__ void __launch_bounds__(kMThreads) k_w_cg_pupd(L0View<double> v,
                                                         const float* __restrict__ zv,
