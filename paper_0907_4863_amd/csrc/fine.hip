@@ -1112,13 +1112,35 @@ __global__ void __launch_bounds__(256) k_l0_restrict_sum(int nx, int ny, int nz,
     if (fd) fd[i] = c.invD[i] * acc;
 }
 
+// The second pass over x-folded sums (one value per aggregate x, y and layer): the 3 y-rows.
+template <typename T>
+__global__ void __launch_bounds__(256) k_l0_restrict_sum3(int nx, int ny, int nz, LCView<T> c,
+                                                          const T* __restrict__ yv,
+                                                          T* __restrict__ fc, T* __restrict__ fd) {
+    if (c.skip && *c.skip != 0.0) return;
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= (long)c.mx * c.my) return;
+    const int X = (int)(t % c.mx), Y = (int)(t / c.mx), Z = blockIdx.y;
+    const long mxq = (nx + 2) / 3;
+    T acc = 0;
+    for (int dy = 0; dy < 3; ++dy) {
+        const int y = 3 * Y + dy;
+        if (y >= ny) break;
+        acc += yv[X + mxq * y + mxq * ny * Z];
+    }
+    const long i = (X + 1) + (long)c.sx * (Y + 1) + c.sxy * (Z + 1);
+    fc[i] = acc;
+    if (fd) fd[i] = c.invD[i] * acc;
+}
+
 template <typename T>
 void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* fc, T* fd,
                  double omega, hipStream_t s) {
     KTimer kt_(T_L0_RESTRICT, s, (L.n_unknowns * 5 / 3 + C.n_unknowns * (fd ? 3 : 1)) *
                                         (long)sizeof(T) + l0_meta_bytes(L, sizeof(T), true));
+    bool folded = false;
     if (L.wide) {
-        w_restrict_y<T>(L, r, y, omega, kt_);
+        folded = w_restrict_y<T>(L, r, y, omega, kt_);
     } else {
         // z-slabs of a multiple of 3 planes, so that no aggregate plane is split between tiles
         L0View<T> v = L.view<T>();
@@ -1128,8 +1150,12 @@ void l0_restrict(const FineLevel& L, const CoarseLevel& C, const T* r, T* y, T* 
                 y, (T)omega);
     }
     dim3 g((unsigned)(((long)C.mx * C.my + 255) / 256), C.mz);
-    klaunch(kt_, true, (k_l0_restrict_sum<T>), g, dim3(256), L.nx, L.ny, L.nz, C.view<T>(),
-            (const T*)y, fc, fd);
+    if (folded)
+        klaunch(kt_, true, (k_l0_restrict_sum3<T>), g, dim3(256), L.nx, L.ny, L.nz, C.view<T>(),
+                (const T*)y, fc, fd);
+    else
+        klaunch(kt_, true, (k_l0_restrict_sum<T>), g, dim3(256), L.nx, L.ny, L.nz, C.view<T>(),
+                (const T*)y, fc, fd);
     HIPCHECK(hipGetLastError());
 }
 template void l0_restrict<double>(const FineLevel&, const CoarseLevel&, const double*, double*,

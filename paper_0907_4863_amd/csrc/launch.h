@@ -121,8 +121,9 @@ void w_cheb(const FineLevel& L, int mode, const T* f, const T* xin, const T* din
             KTimer& kt);
 template <typename T>
 void w_residual(const FineLevel& L, const T* f, const T* x, T* r, KTimer& kt);
+// returns true when y holds the x-folded sums (one per aggregate x, y, layer)
 template <typename T>
-void w_restrict_y(const FineLevel& L, const T* r, T* y, double omega, KTimer& kt);
+bool w_restrict_y(const FineLevel& L, const T* r, T* y, double omega, KTimer& kt);
 template <typename T>
 void w_prolong(const FineLevel& L, const CoarseLevel& C, const T* vc, T* x, double omega,
                KTimer& kt);

@@ -530,14 +530,18 @@ template void w_residual<double>(const FineLevel&, const double*, const double*,
 template void w_residual<float>(const FineLevel&, const float*, const float*, float*, KTimer&);
 
 // First pass of the restriction (see k_l0_restrict_y): y = r - w A^T r summed over the
-// three planes of each aggregate layer, one value per (x, y, layer) into yz.
-template <typename T>
+// three planes of each aggregate layer.  FOLD (a line that one wavefront spans): the lanes
+// also sum the x-triples of each aggregate, so that one value per (aggregate x, y, layer)
+// goes to yz; a lane owns the aggregates whose first node it holds and takes the nodes
+// beyond its own from the next lane.  Otherwise one value per (x, y, layer).
+template <typename T, bool FOLD>
 __global__ void __launch_bounds__(kMThreads) k_w_restrict_y(L0View<T> v, const T* __restrict__ r,
                                                            T* __restrict__ yz, T omega) {
     constexpr int N = kLanes<T>;
     T acc[N];
 #pragma unroll
     for (int e = 0; e < N; ++e) acc[e] = T(0);
+    const long mxq = (v.nx + 2) / 3;
     wmarch<T, N, true, true, false>(
         v, r, WNOFETCH,
         [&](Idx, NoVals, const Vec<T, N>& c, const Vec<T, N>& atr, int, int, int, unsigned nib) {
@@ -547,7 +551,24 @@ __global__ void __launch_bounds__(kMThreads) k_w_restrict_y(L0View<T> v, const T
         },
         [&](int z, bool last, int x, int y) {
             if (z % 3 == 2 || last) {
-                if (x < v.nx) vstnt<N>(yz, Idx{(long)v.nx * y + v.nxy * (z / 3), (unsigned)x}, acc);
+                if (FOLD) {
+                    T nx_[N];  // the next lane's sums (0 past the wavefront)
+#pragma unroll
+                    for (int e = 0; e < N; ++e) nx_[e] = wave_shift<false>(acc[e], T(0));
+                    const long row = mxq * y + mxq * v.ny * (z / 3);
+#pragma unroll
+                    for (int e = 0; e < N; ++e) {
+                        const int xe = x + e;
+                        if (xe % 3 == 0 && xe / 3 < mxq) {
+                            T s = T(0);
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) s += (e + k < N) ? acc[e + k] : nx_[e + k - N];
+                            yz[row + xe / 3] = s;
+                        }
+                    }
+                } else if (x < v.nx) {
+                    vstnt<N>(yz, Idx{(long)v.nx * y + v.nxy * (z / 3), (unsigned)x}, acc);
+                }
 #pragma unroll
                 for (int e = 0; e < N; ++e) acc[e] = T(0);
             }
@@ -555,17 +576,23 @@ __global__ void __launch_bounds__(kMThreads) k_w_restrict_y(L0View<T> v, const T
 }
 
 template <typename T>
-void w_restrict_y(const FineLevel& L, const T* r, T* y, double omega, KTimer& kt_) {
+bool w_restrict_y(const FineLevel& L, const T* r, T* y, double omega, KTimer& kt_) {
     // z-slabs of a multiple of 3 planes, so that no aggregate layer is split between tiles
     L0View<T> v = wview<T>(L, kLanes<T>);
     v.zb = std::max(3, v.zb / 3 * 3);
     const long blocks = (long)v.gx * v.gy * ((L.nz + v.zb - 1) / v.zb);
-    klaunch(kt_, false, (k_w_restrict_y<T>), dim3((unsigned)blocks), dim3(kWave, kMY), v, r, y,
-            (T)omega);
+    const bool fold = L.nx <= kWave * kLanes<T>;
+    if (fold)
+        klaunch(kt_, false, (k_w_restrict_y<T, true>), dim3((unsigned)blocks), dim3(kWave, kMY), v,
+                r, y, (T)omega);
+    else
+        klaunch(kt_, false, (k_w_restrict_y<T, false>), dim3((unsigned)blocks), dim3(kWave, kMY), v,
+                r, y, (T)omega);
     HIPCHECK(hipGetLastError());
+    return fold;
 }
-template void w_restrict_y<double>(const FineLevel&, const double*, double*, double, KTimer&);
-template void w_restrict_y<float>(const FineLevel&, const float*, float*, double, KTimer&);
+template bool w_restrict_y<double>(const FineLevel&, const double*, double*, double, KTimer&);
+template bool w_restrict_y<float>(const FineLevel&, const float*, float*, double, KTimer&);
 
 // Prolongation from level 1 (see k_l0_prolong): x += P v = P_tent v - w A (P_tent v).
 // A lane's N nodes lie in at most two aggregates along x; with their x-neighbour
