@@ -273,11 +273,28 @@ __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict_
                 cv.v[e] = T(c.v[e]);
                 ax.v[e] = T(0);
             }
-            // table rows of the lane's irregular nodes, staged through LDS one wavefront
-            // load at a time (one load for rows of up to R irregular nodes)
-            T t[N][6];
+            // the interior row at every node; irregular nodes are overwritten below
+            T left = T(0), right = T(0);
+            if (STENCIL) {
+                left = T(wave_shift<true>(c.v[N - 1], P.edge));
+                right = T(wave_shift<false>(c.v[0], P.edge));
 #pragma unroll
-            for (int e = 0; e < N; ++e)
+                for (int e = 0; e < N; ++e) {
+                    const T xm = e ? cv.v[e - 1] : left;
+                    const T xp = e < N - 1 ? cv.v[e + 1] : right;
+                    ax.v[e] = cv.v[e] + v.c[0] * (xm + xp) + v.c[1] * (T(P.ym.v[e]) + T(P.yp.v[e])) +
+                              v.c[2] * (T(zm.v[e]) + T(zp.v[e]));
+                }
+            }
+            // table rows of the lane's irregular nodes, staged through LDS one wavefront
+            // load at a time (one load for rows of up to R irregular nodes).  A stencil
+            // kernel applies each row as it reads it, so that one row (6 values) is live
+            // at a time instead of N: with N rows held, the fp64 kernels on 4-node lanes
+            // needed 137 registers (3 wavefronts per SIMD).
+            constexpr int NT = STENCIL ? 1 : N;  // rows handed to the body (TAB && !STENCIL)
+            T t[NT][6];
+#pragma unroll
+            for (int e = 0; e < NT; ++e)
 #pragma unroll
                 for (int d = 0; d < 6; ++d) t[e][d] = T(0);
             if (TAB && (P.sp & SP_IRR)) {
@@ -293,29 +310,23 @@ __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict_
 #pragma unroll
                     for (int e = 0; e < N; ++e) {
                         if ((P.nibr >> e) & 1u) {
-                            if (r >= 0 && r < R) row6<T>(stage + r * RV, t[e]);
+                            if (r >= 0 && r < R) {
+                                if constexpr (STENCIL) {
+                                    T t6[6];
+                                    row6<T>(stage + r * RV, t6);
+                                    const T xm = e ? cv.v[e - 1] : left;
+                                    const T xp = e < N - 1 ? cv.v[e + 1] : right;
+                                    ax.v[e] = cv.v[e] + t6[0] * xm + t6[1] * xp + t6[2] * T(P.ym.v[e]) +
+                                              t6[3] * T(P.yp.v[e]) + t6[4] * T(zm.v[e]) +
+                                              t6[5] * T(zp.v[e]);
+                                } else {
+                                    row6<T>(stage + r * RV, t[e]);
+                                }
+                            }
                             ++r;
                         }
                     }
                     __builtin_amdgcn_wave_barrier();
-                }
-            }
-            if (STENCIL) {
-                const T left = T(wave_shift<true>(c.v[N - 1], P.edge));
-                const T right = T(wave_shift<false>(c.v[0], P.edge));
-#pragma unroll
-                for (int e = 0; e < N; ++e) {
-                    const T xm = e ? cv.v[e - 1] : left;
-                    const T xp = e < N - 1 ? cv.v[e + 1] : right;
-                    const T ym = T(P.ym.v[e]), yp = T(P.yp.v[e]);
-                    const T zmv = T(zm.v[e]), zpv = T(zp.v[e]);
-                    if ((P.nibr >> e) & 1u) {
-                        ax.v[e] = cv.v[e] + t[e][0] * xm + t[e][1] * xp + t[e][2] * ym +
-                                  t[e][3] * yp + t[e][4] * zmv + t[e][5] * zpv;
-                    } else {
-                        ax.v[e] = cv.v[e] + v.c[0] * (xm + xp) + v.c[1] * (ym + yp) +
-                                  v.c[2] * (zmv + zpv);
-                    }
                 }
             }
             if (FULL ? inb : P.nib != 0u) {
