@@ -59,7 +59,7 @@ long cg_resid_parts(const FineLevel& L) { return L.wide ? l0_wblocks(L, 2) : l0_
 long cg_pq_parts(const FineLevel& L, bool split) {
     return pq_wide(L) ? l0_wblocks(L, split ? 4 : 2) : l0_blocks(L);
 }
-long cg_xr_parts(const FineLevel& L) { return l0_blocks(L); }
+long cg_xr_parts(const FineLevel& L, bool split) { return split ? l0_wblocks(L, 4) : l0_blocks(L); }
 long l0_dot_parts(const FineLevel& L, int bytes) {
     return L.wide ? l0_wblocks(L, l0_lanes(bytes)) : l0_blocks(L);
 }
@@ -1339,16 +1339,18 @@ __global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ*
     if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
-// On 16-byte lanes mixed precision keeps the direction in fp32 and forms the product from
-// it, in two passes:
-//   x += alpha_prev p;  p <- fl32(z + beta p)        (k_w_cg_pupd, a stream)
-//   q = A p in fp64 from the stored p; partials of p . q   (k_w_cg_q, a stencil)
-// x += alpha p and r -= alpha q then use the same stored p and q = A p, so the recursive
-// residual follows the true one in fp64 arithmetic; rounding p to fp32 only perturbs the
-// conjugacy of the directions, at the level of the fp32 preconditioned residual z it is
-// formed from.  40 bytes per unknown instead of the fused form's 52 (on the 256 x 256 x 768
-// ellipse 398 against 447 us).  On one-node lanes, which serve the small boxes where each
-// launch's latency counts more than bytes, the fused form with an fp32 z stays.
+// On 16-byte lanes mixed precision keeps the direction in fp32 and no q = A p vector: a
+// step is
+//   x += alpha_prev p;  pn = fl32(z + beta p);  partials of pn . A pn   (k_w_cg_pdir)
+//   r -= alpha A p, A p from the stored fp32 direction                  (k_w_cg_xr)
+// Both products are evaluated in fp64 by the same march on the same fp32 values, and
+// x += alpha p uses the stored p too, so the recursive residual follows the true one in
+// fp64 arithmetic; rounding p to fp32 only perturbs the conjugacy of the directions, at
+// the level of the fp32 preconditioned residual z it is formed from.  52 bytes per unknown
+// against 68 for the earlier split (a direction pass, q = A p stored, r -= alpha q) and 80
+// for the fused q-recursion with its r update.  On one-node lanes, which serve the small
+// boxes where each launch's latency counts more than bytes, the fused form with an fp32 z
+// stays.
 bool cg_split(const FineLevel& L, bool mixed) { return mixed && L.wide; }
 
 template <typename TZ>
@@ -1370,12 +1372,20 @@ template void cg_pq<double>(const FineLevel&, const double*, double*, double*, d
 template void cg_pq<float>(const FineLevel&, const float*, double*, double*, double*,
                            const double*, double*, hipStream_t);
 
-void cg_pq_split(const FineLevel& L, const float* z, double* x, float* p, double* q,
-                 const double* scal, double* partials, hipStream_t s) {
-    // z, p: 4 + 4 read, p 4 written, x 8 + 8; p 4 read, q 8 written
-    KTimer kt_(T_CG_PQ, s, L.n_unknowns * 40L + 2 * l0_meta_bytes(L, 8, false));
-    if (!pq_wide(L)) throw ApiError{SAAMG_INVALID_ARG, "the two-pass direction update needs 16-byte lanes"};
-    w_cg_pq_split(L, z, x, p, q, scal, partials, kt_);
+void cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, double* x,
+             const double* scal, double* partials, hipStream_t s) {
+    // z 4, p 4, x 8 read; pn 4, x 8 written
+    KTimer kt_(T_CG_PQ, s, L.n_unknowns * 28L + l0_meta_bytes(L, 8, false));
+    if (!pq_wide(L)) throw ApiError{SAAMG_INVALID_ARG, "the fp32-direction CG step needs 16-byte lanes"};
+    w_cg_pdir(L, z, p, pn, x, scal, partials, kt_);
+}
+
+void cg_xr_dir(const FineLevel& L, const float* p, double* r, float* r32, const double* scal,
+               double* partials, hipStream_t s) {
+    // p 4, r 8 read; r 8, r32 4 written
+    KTimer kt_(T_CG_XR, s, L.n_unknowns * 24L + l0_meta_bytes(L, 8, false));
+    if (!pq_wide(L)) throw ApiError{SAAMG_INVALID_ARG, "the fp32-direction CG step needs 16-byte lanes"};
+    w_cg_xr(L, p, r, r32, scal, partials, kt_);
 }
 
 // r -= alpha q (alpha = S_XA) and partials of r.r; r untouched when the step broke down

@@ -53,7 +53,7 @@ long l0_wblocks(const FineLevel& L, int n);
 // working precision of `bytes` bytes.
 long cg_resid_parts(const FineLevel& L);
 long cg_pq_parts(const FineLevel& L, bool split);
-long cg_xr_parts(const FineLevel& L);
+long cg_xr_parts(const FineLevel& L, bool split);
 long l0_dot_parts(const FineLevel& L, int bytes);
 int l0_choose_zb(int tx, int nsegx, int ny, int nz);
 // 16-byte lanes: whether a box of nx nodes per line uses them by default, and the planes
@@ -134,9 +134,12 @@ void w_cg_resid(const FineLevel& L, const double* bs, const double* x, double* r
 template <typename TZ>
 void w_cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
              double* partials, KTimer& kt);
-// mixed precision: fp32 direction, x += alpha p and p <- fl32(z + beta p), then q = A p
-void w_cg_pq_split(const FineLevel& L, const float* z, double* x, float* p, double* q,
-                   const double* scal, double* partials, KTimer& kt);
+// mixed precision, fp32 direction: x += alpha_prev p, pn = fl32(z + beta p) and the
+// partials of pn . A pn; then r -= alpha A p with A p from the stored direction
+void w_cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, double* x,
+               const double* scal, double* partials, KTimer& kt);
+void w_cg_xr(const FineLevel& L, const float* p, double* r, float* r32, const double* scal,
+             double* partials, KTimer& kt);
 
 // ---- level 0: CG (fp64)
 void cg_init(const FineLevel& L, const double* b, const double* x0, double* bs, double* x,
@@ -144,17 +147,21 @@ void cg_init(const FineLevel& L, const double* b, const double* x0, double* bs, 
 // r32 (nullable): fp32 copy of the residual for the fp32 V-cycle
 void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
               float* r32, hipStream_t s);
-// Direction update, the product by A and the partials of p . q: one pass with the
-// q-recursion and an fp64 direction (z in the working precision), or (cg_split: mixed
-// precision on 16-byte lanes) two passes with an fp32 direction, q = A p from the stored p.
+// Direction update, the product by A and the partials of p . q in one pass, with the
+// q-recursion and an fp64 direction (z in the working precision); cg_xr then takes
+// r -= alpha q.  Or (cg_split: mixed precision on 16-byte lanes) an fp32 direction in two
+// buffers and no q: cg_pdir updates x and the direction (p -> pn) with the partials of
+// pn . A pn, and cg_xr_dir takes r -= alpha A p from the stored direction.
 template <typename TZ>
 void cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
            double* partials, hipStream_t s);
-void cg_pq_split(const FineLevel& L, const float* z, double* x, float* p, double* q,
-                 const double* scal, double* partials, hipStream_t s);
+void cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, double* x,
+             const double* scal, double* partials, hipStream_t s);
 bool cg_split(const FineLevel& L, bool mixed);
 void cg_xr(const FineLevel& L, double* r, const double* q, const double* scal, double* partials,
            float* r32, hipStream_t s);
+void cg_xr_dir(const FineLevel& L, const float* p, double* r, float* r32, const double* scal,
+               double* partials, hipStream_t s);
 // x += S_XA p: the update the last step still owes x
 template <typename TP>
 void cg_xflush(const FineLevel& L, double* x, const TP* p, const double* scal, hipStream_t s);

@@ -380,6 +380,11 @@ struct saamg_state {
     float* r32 = nullptr;  // fp32 copy of r (mixed precision)
     void* z = nullptr;     // preconditioned residual (fp32 in mixed precision)
     void* p = nullptr;     // direction: fp32 when split (cg_split), else fp64
+    // split: the other direction buffer, which each step writes before the two swap.  It
+    // lies in q's memory (q itself is not used by a split solve, except as the scratch of
+    // a final true residual taken after the last x += alpha p).  pbuf owns p's allocation.
+    void* pn = nullptr;
+    void* pbuf = nullptr;
     bool split = false;
     VBuf<float> vf;
     VBuf<double> vd;
@@ -415,8 +420,9 @@ static void state_alloc(saamg_state* S, saamg_hierarchy* H, bool pinned = true) 
     S->x = (double*)dmalloc(8 * n);
     S->r = (double*)dmalloc(8 * n);
     S->split = cg_split(H->l0, S->mixed);
-    S->p = dmalloc((S->split ? 4 : 8) * n);
+    S->p = S->pbuf = dmalloc((S->split ? 4 : 8) * n);
     S->q = (double*)dmalloc(8 * n);
+    S->pn = S->split ? (void*)S->q : nullptr;
     S->bs = (double*)dmalloc(8 * n);
     S->z = dmalloc((S->mixed ? 4 : 8) * n);
     if (S->mixed) S->r32 = (float*)dmalloc(4 * n);
@@ -444,7 +450,7 @@ static void state_alloc(saamg_state* S, saamg_hierarchy* H, bool pinned = true) 
 
 static void state_release(saamg_state* S) {
     for (double* p : {S->x, S->r, S->q, S->bs}) dfree(p);
-    dfree(S->p);
+    dfree(S->pbuf);
     dfree(S->z);
     dfree(S->r32);
     S->r32 = nullptr;
@@ -455,7 +461,7 @@ static void state_release(saamg_state* S) {
     if (S->hscal && S->hscal != S->hbuf) (void)hipHostFree(S->hscal);
     if (S->ev) (void)hipEventDestroy(S->ev);
     S->x = S->r = S->q = S->bs = nullptr;
-    S->z = S->p = nullptr;
+    S->z = S->p = S->pn = S->pbuf = nullptr;
     S->part = S->scal = S->hscal = nullptr;
     S->ev = nullptr;
 }
@@ -535,15 +541,20 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
 static void state_enqueue(saamg_state* S) {
     const saamg_hierarchy* H = S->H;
     const FineLevel& L = cg_op(H);
-    if (S->split)
-        cg_pq_split(L, (const float*)S->z, S->x, (float*)S->p, S->q, S->scal, S->part, S->s);
-    else if (S->mixed)
+    if (S->split) {
+        cg_pdir(L, (const float*)S->z, (const float*)S->p, (float*)S->pn, S->x, S->scal, S->part,
+                S->s);
+        std::swap(S->p, S->pn);
+    } else if (S->mixed)
         cg_pq<float>(L, (const float*)S->z, S->x, (double*)S->p, S->q, S->scal, S->part, S->s);
     else
         cg_pq<double>(L, (const double*)S->z, S->x, (double*)S->p, S->q, S->scal, S->part, S->s);
     finalize(S->part, cg_pq_parts(L, S->split), 1, S->scal, FIN_ALPHA, 0, S->s);
-    cg_xr(L, S->r, S->q, S->scal, S->part, S->r32, S->s);
-    finalize(S->part, cg_xr_parts(L), 1, S->scal, FIN_RR, 0, S->s);
+    if (S->split)
+        cg_xr_dir(L, (const float*)S->p, S->r, S->r32, S->scal, S->part, S->s);
+    else
+        cg_xr(L, S->r, S->q, S->scal, S->part, S->r32, S->s);
+    finalize(S->part, cg_xr_parts(L, S->split), 1, S->scal, FIN_RR, 0, S->s);
     HIPCHECK(hipMemcpyAsync(S->hscal, S->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
                             S->s));
     if (S->ev) HIPCHECK(hipEventRecord(S->ev, S->s));

@@ -68,8 +68,58 @@ __device__ __forceinline__ Vec<T, N> vzero() {
     return r;
 }
 
+// Where a stencil march reads X.  A source brings a lane's N values with one load per
+// array (`ld`, issued a plane ahead and kept in flight as `raw`) and forms the values
+// when the plane is stepped (`val`); `ld1` / `val1` do the same for one node.
+// XArr: a plain array.
+template <class E>
+struct XArr {
+    using type = E;
+    template <int N>
+    using raw = Vec<E, N>;
+    using raw1 = E;
+    const E* a;
+    template <int N>
+    __device__ __forceinline__ Vec<E, N> ld(Idx k) const { return vld<N>(a, k); }
+    __device__ __forceinline__ E ld1(Idx k) const { return at(a, k); }
+    template <int N>
+    __device__ __forceinline__ Vec<E, N> val(const Vec<E, N>& r) const { return r; }
+    __device__ __forceinline__ E val1(E r) const { return r; }
+};
+
+// XDir: the next CG direction of mixed precision, fl32(z + beta p), formed from the
+// preconditioned residual z and the previous direction p (both fp32).  It is zero where
+// z and p are.
+struct XDir {
+    using type = float;
+    template <int N>
+    struct raw {
+        Vec<float, N> z, p;
+    };
+    struct raw1 {
+        float z, p;
+    };
+    const float* z;
+    const float* p;
+    double beta;
+    __device__ __forceinline__ float dir(float zz, float pp) const {
+        return (float)__builtin_fma(beta, (double)pp, (double)zz);
+    }
+    template <int N>
+    __device__ __forceinline__ raw<N> ld(Idx k) const { return raw<N>{vld<N>(z, k), vld<N>(p, k)}; }
+    __device__ __forceinline__ raw1 ld1(Idx k) const { return raw1{at(z, k), at(p, k)}; }
+    template <int N>
+    __device__ __forceinline__ Vec<float, N> val(const raw<N>& r) const {
+        Vec<float, N> o;
+#pragma unroll
+        for (int e = 0; e < N; ++e) o.v[e] = dir(r.z.v[e], r.p.v[e]);
+        return o;
+    }
+    __device__ __forceinline__ float val1(const raw1& r) const { return dir(r.z, r.p); }
+};
+
 // Loads of one plane of a wavefront's row (the 16-byte-lane counterpart of PlaneLoads).
-template <typename T, typename TX, int N, class FV>
+template <typename T, class XS, int N, class FV>
 struct WPlane {
     unsigned nib;   // unknown bits of the lane's N nodes
     unsigned nibr;  // irregular bits
@@ -79,8 +129,8 @@ struct WPlane {
     bool ins1;      // lane inside the row's unknown span (in lanes) in plane z+1
     bool reuse;     // the row's table rows are the previous plane's (staged already)
     long ib;        // box index of the span's first node in this plane (wave-uniform)
-    Vec<TX, N> nxt, ym, yp;  // X at (z+1), (y-1), (y+1)
-    TX edge;        // lanes 0 and 63: X beyond the span's ends (0 at the line's ends)
+    typename XS::template raw<N> nxt, ym, yp;  // X at (z+1), (y-1), (y+1), as loaded
+    typename XS::raw1 edge;  // lanes 0 and 63: X beyond the span's ends (0 at the line's ends)
     typename ExtVec<T, 16 / sizeof(T)>::type trow;  // 16 bytes of the row's first table rows
     FV fv;
 };
@@ -121,13 +171,14 @@ __device__ __forceinline__ void row6(const TV* p, T t[6]) {
 // 2 N loads per plane and took a quarter of the time of the fp32 stencil kernels.  A row
 // whose rows are those of the plane before (its line repeats the line below: the same
 // slots) neither loads nor stages them again.
-template <typename T, int N, bool STENCIL, bool TR, bool FULL, bool TAB = STENCIL, class TX,
+template <typename T, int N, bool STENCIL, bool TR, bool FULL, bool TAB = STENCIL, class XS,
           class Fetch, class Body, class End = NoEnd>
-__device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict__ X, Fetch fetch,
-                                       Body body, End end = End{}) {
+__device__ __forceinline__ void wmarch_x(const L0View<T>& v, const XS xs, Fetch fetch, Body body,
+                                         End end = End{}) {
     static_assert(N == 2 || N == 4, "16-byte lanes of 8- or 4-byte values");
+    using TX = typename XS::type;
     using FV = decltype(fetch(Idx{0, 0u}, 0, 0, 0, 0u, 0));
-    using WP = WPlane<T, TX, N, FV>;
+    using WP = WPlane<T, XS, N, FV>;
     using TV = typename ExtVec<T, 16 / sizeof(T)>::type;
     constexpr int W = kWave * N;      // nodes per wavefront span
     constexpr int LPW = kWave / N;    // lanes per 64-bit segment word
@@ -190,7 +241,7 @@ __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict_
     }
     auto span_word = [&](int k) { return __builtin_amdgcn_readlane(spk, k * N); };
     auto clamp_lane = [&](int sp) { return min(max(lane, sp & 255), (sp >> 8) & 255); };
-    auto load_vec = [&](long ibq, int lc) { return vld<N>(X, Idx{ibq, (unsigned)(N * lc)}); };
+    auto load_vec = [&](long ibq, int lc) { return xs.template ld<N>(Idx{ibq, (unsigned)(N * lc)}); };
     // 16 bytes of table rows tb0 + c R .. of a row with cnt irregular nodes
     auto load_rows = [&](int tb0, int c, int cnt) {
         TV d;
@@ -231,9 +282,9 @@ __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict_
             P.nxt = load_vec(ib + nxy, lc1);
             P.ym = load_vec(ib - nx, lc);
             P.yp = load_vec(ib + nx, lc);
-            P.edge = TX(0);
-            if (lane == 0 && x0 > 0) P.edge = at(X, Idx{ib - 1, 0u});
-            if (lane == kWave - 1 && x0 + W < v.nx) P.edge = at(X, Idx{ib, (unsigned)W});
+            P.edge = typename XS::raw1{};
+            if (lane == 0 && x0 > 0) P.edge = xs.ld1(Idx{ib - 1, 0u});
+            if (lane == kWave - 1 && x0 + W < v.nx) P.edge = xs.ld1(Idx{ib, (unsigned)W});
         }
         if (TAB) {
 #pragma unroll
@@ -245,10 +296,10 @@ __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict_
     Vec<TX, N> zm = vzero<TX, N>(), c = vzero<TX, N>();
     if (STENCIL) {
         int lc = clamp_lane(span_word(0));
-        zm = load_vec(rb + nxy * (z0 - 1), lc);
+        zm = xs.val(load_vec(rb + nxy * (z0 - 1), lc));
         if (lc != lane) zm = vzero<TX, N>();
         lc = clamp_lane(span_word(1));
-        c = load_vec(rb + nxy * z0, lc);
+        c = xs.val(load_vec(rb + nxy * z0, lc));
         if (lc != lane) c = vzero<TX, N>();
     }
     auto settle_plane = [&](const WP& P) {
@@ -265,7 +316,7 @@ __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict_
         settle_plane(P);
         if (z >= z1) return;
         Vec<TX, N> zp = vzero<TX, N>();
-        if (STENCIL && P.ins1) zp = P.nxt;
+        if (STENCIL && P.ins1) zp = xs.val(P.nxt);
         if (P.sp & SP_ANY) {
             Vec<T, N> cv, ax;
 #pragma unroll
@@ -275,14 +326,18 @@ __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict_
             }
             // the interior row at every node; irregular nodes are overwritten below
             T left = T(0), right = T(0);
+            Vec<TX, N> ymv = vzero<TX, N>(), ypv = vzero<TX, N>();
             if (STENCIL) {
-                left = T(wave_shift<true>(c.v[N - 1], P.edge));
-                right = T(wave_shift<false>(c.v[0], P.edge));
+                ymv = xs.val(P.ym);
+                ypv = xs.val(P.yp);
+                const TX edge = xs.val1(P.edge);
+                left = T(wave_shift<true>(c.v[N - 1], edge));
+                right = T(wave_shift<false>(c.v[0], edge));
 #pragma unroll
                 for (int e = 0; e < N; ++e) {
                     const T xm = e ? cv.v[e - 1] : left;
                     const T xp = e < N - 1 ? cv.v[e + 1] : right;
-                    ax.v[e] = cv.v[e] + v.c[0] * (xm + xp) + v.c[1] * (T(P.ym.v[e]) + T(P.yp.v[e])) +
+                    ax.v[e] = cv.v[e] + v.c[0] * (xm + xp) + v.c[1] * (T(ymv.v[e]) + T(ypv.v[e])) +
                               v.c[2] * (T(zm.v[e]) + T(zp.v[e]));
                 }
             }
@@ -316,8 +371,8 @@ __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict_
                                     row6<T>(stage + r * RV, t6);
                                     const T xm = e ? cv.v[e - 1] : left;
                                     const T xp = e < N - 1 ? cv.v[e + 1] : right;
-                                    ax.v[e] = cv.v[e] + t6[0] * xm + t6[1] * xp + t6[2] * T(P.ym.v[e]) +
-                                              t6[3] * T(P.yp.v[e]) + t6[4] * T(zm.v[e]) +
+                                    ax.v[e] = cv.v[e] + t6[0] * xm + t6[1] * xp + t6[2] * T(ymv.v[e]) +
+                                              t6[3] * T(ypv.v[e]) + t6[4] * T(zm.v[e]) +
                                               t6[5] * T(zp.v[e]);
                                 } else {
                                     row6<T>(stage + r * RV, t[e]);
@@ -352,6 +407,13 @@ __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict_
         pa = load_plane(min(z + 2, z1 - 1), ibz < ib_last ? ibz : ib_last);
         step(pb, z + 1);
     }
+}
+
+template <typename T, int N, bool STENCIL, bool TR, bool FULL, bool TAB = STENCIL, class TX,
+          class Fetch, class Body, class End = NoEnd>
+__device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict__ X, Fetch fetch,
+                                       Body body, End end = End{}) {
+    wmarch_x<T, N, STENCIL, TR, FULL, TAB>(v, XArr<TX>{X}, fetch, body, end);
 }
 
 #define WNOFETCH [&](Idx, int, int, int, unsigned, int) { return NoVals{}; }
@@ -826,68 +888,99 @@ void w_cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, c
 template void w_cg_pq<double>(const FineLevel&, const double*, double*, double*, double*,
                               const double*, double*, KTimer&);
 
-// Mixed precision's direction update in two passes (see cg_pq_split in fine.hip), 4 nodes per
-// lane: the fp32 direction and z move 16 bytes per lane, x and q 32.
-__global__ void __launch_bounds__(kMThreads) k_w_cg_pupd(L0View<double> v,
+// Mixed precision's CG step on 16-byte lanes (4 nodes per lane) in two passes that share
+// no q = A p vector.  The first takes the direction update and p . A p together: x +=
+// alpha_prev p_old and p_new = fl32(z + beta p_old), with p_new at the neighbour lines and
+// planes formed from z and p_old as the march reads them (XDir), so A p_new costs no pass
+// of its own.  p_new goes to the other direction buffer, since neighbouring blocks still
+// read p_old where this block has stored p_new.  The second recomputes A p from the
+// stored fp32 direction for r -= alpha A p.  Both evaluate A p with the same march and
+// arithmetic on the same fp32 values.  Per unknown: z 4, p_old 4, x 8 read, p_new 4, x 8
+// written; then p 4, r 8 read, r 8, r32 4 written.
+__global__ void __launch_bounds__(kMThreads) k_w_cg_pdir(L0View<double> v,
                                                         const float* __restrict__ zv,
-                                                        float* __restrict__ p,
+                                                        const float* __restrict__ p,
+                                                        float* __restrict__ pn,
                                                         double* __restrict__ xv,
-                                                        const double* __restrict__ scal) {
+                                                        const double* __restrict__ scal,
+                                                        double* part) {
     constexpr int N = 4;
+    __shared__ double lds[kMThreads / kWave];
     const double beta = scal[S_BETA];
     const double xa = scal[S_XA];
+    double acc = 0.0;
     struct R {
-        Vec<float, N> z, p;
+        Vec<float, N> p;
         Vec<double, N> x;
     };
-    wmarch<double, N, false, false, true>(
-        v, (const float*)nullptr,
-        [&](Idx i, int, int, int, unsigned, int) {
-            return R{vldnt<N>(zv, i), vld<N>(p, i), vld<N>(xv, i)};
-        },
-        [&](Idx i, const R& f, const Vec<double, N>&, const Vec<double, N>&, int, int, int,
+    wmarch_x<double, N, true, false, true>(
+        v, XDir{zv, p, beta},
+        [&](Idx i, int, int, int, unsigned, int) { return R{vld<N>(p, i), vldnt<N>(xv, i)}; },
+        [&](Idx i, const R& f, const Vec<double, N>& pv, const Vec<double, N>& ap, int, int, int,
             unsigned nib) {
-            float pn[N];
+            float po[N];
             double xo[N];
 #pragma unroll
             for (int e = 0; e < N; ++e) {
                 const bool u = (nib >> e) & 1u;
-                pn[e] = u ? (float)((double)f.z.v[e] + beta * (double)f.p.v[e]) : 0.0f;
+                po[e] = u ? (float)pv.v[e] : 0.0f;
                 xo[e] = u ? f.x.v[e] + xa * (double)f.p.v[e] : 0.0;
-            }
-            vstnt<N>(p, i, pn);
-            vstnt<N>(xv, i, xo);
-        });
-}
-
-__global__ void __launch_bounds__(kMThreads) k_w_cg_q(L0View<double> v, const float* __restrict__ p,
-                                                     double* __restrict__ q, double* part) {
-    constexpr int N = 4;
-    __shared__ double lds[kMThreads / kWave];
-    double acc = 0.0;
-    wmarch<double, N, true, false, false>(
-        v, p, WNOFETCH,
-        [&](Idx i, NoVals, const Vec<double, N>& pv, const Vec<double, N>& ap, int, int, int,
-            unsigned nib) {
-            double qo[N];
-#pragma unroll
-            for (int e = 0; e < N; ++e) {
-                const bool u = (nib >> e) & 1u;
-                qo[e] = u ? ap.v[e] : 0.0;
                 acc += u ? pv.v[e] * ap.v[e] : 0.0;
             }
-            vstnt<N>(q, i, qo);
+            vstnt<N>(pn, i, po);
+            vstnt<N>(xv, i, xo);
         });
     const double sb = block_sum(acc, lds);
     if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
-void w_cg_pq_split(const FineLevel& L, const float* z, double* x, float* p, double* q,
-                   const double* scal, double* partials, KTimer& kt_) {
-    const dim3 g((unsigned)l0_wblocks(L, 4)), b(kWave, kMY);
-    const L0View<double> v = wview<double>(L, 4);
-    klaunch(kt_, false, k_w_cg_pupd, g, b, v, z, p, x, scal);
-    klaunch(kt_, true, k_w_cg_q, g, b, v, (const float*)p, q, partials);
+// r -= alpha A p (alpha = S_XA; r left as it is when the step broke down), its fp32 copy
+// and partials of r . r.  Whole rows are stored (zero at the nodes that are not unknowns).
+__global__ void __launch_bounds__(kMThreads) k_w_cg_xr(L0View<double> v, const float* __restrict__ p,
+                                                      double* __restrict__ r,
+                                                      float* __restrict__ r32,
+                                                      const double* __restrict__ scal,
+                                                      double* part) {
+    constexpr int N = 4;
+    __shared__ double lds[kMThreads / kWave];
+    const double alpha = scal[S_XA];
+    const bool ok = alpha != 0.0;
+    double acc = 0.0;
+    wmarch<double, N, true, false, true>(
+        v, p, [&](Idx i, int, int, int, unsigned, int) { return vldnt<N>(r, i); },
+        [&](Idx i, const Vec<double, N>& rv, const Vec<double, N>&, const Vec<double, N>& ap, int,
+            int, int, unsigned nib) {
+            double ro[N];
+            float r3[N];
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                const bool u = (nib >> e) & 1u;
+                double ri = u ? rv.v[e] : 0.0;
+                if (ok) ri = u ? ri - alpha * ap.v[e] : 0.0;
+                ro[e] = ri;
+                r3[e] = (float)ri;
+                acc += ri * ri;
+            }
+            if (ok) {
+                vstnt<N>(r, i, ro);
+                vstnt<N>(r32, i, r3);
+            }
+        });
+    const double sb = block_sum(acc, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
+}
+
+void w_cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, double* x,
+               const double* scal, double* partials, KTimer& kt_) {
+    klaunch(kt_, true, k_w_cg_pdir, dim3((unsigned)l0_wblocks(L, 4)), dim3(kWave, kMY),
+            wview<double>(L, 4), z, p, pn, x, scal, partials);
+    HIPCHECK(hipGetLastError());
+}
+
+void w_cg_xr(const FineLevel& L, const float* p, double* r, float* r32, const double* scal,
+             double* partials, KTimer& kt_) {
+    klaunch(kt_, true, k_w_cg_xr, dim3((unsigned)l0_wblocks(L, 4)), dim3(kWave, kMY),
+            wview<double>(L, 4), p, r, r32, scal, partials);
     HIPCHECK(hipGetLastError());
 }
 
