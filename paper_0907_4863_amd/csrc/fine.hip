@@ -57,9 +57,11 @@ static bool pq_wide(const FineLevel& L) { return L.wide; }
 
 long cg_resid_parts(const FineLevel& L) { return L.wide ? l0_wblocks(L, 2) : l0_blocks(L); }
 long cg_pq_parts(const FineLevel& L, bool split) {
-    return pq_wide(L) ? l0_wblocks(L, split ? 4 : 2) : l0_blocks(L);
+    return pq_wide(L) ? l0_wblocks(L, split ? kCgDirLanes : 2) : l0_blocks(L);
 }
-long cg_xr_parts(const FineLevel& L, bool split) { return split ? l0_wblocks(L, 4) : l0_blocks(L); }
+long cg_xr_parts(const FineLevel& L, bool split) {
+    return split ? l0_wblocks(L, kCgXrLanes) : l0_blocks(L);
+}
 long l0_dot_parts(const FineLevel& L, int bytes) {
     return L.wide ? l0_wblocks(L, l0_lanes(bytes)) : l0_blocks(L);
 }
@@ -1339,14 +1341,15 @@ __global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ*
     if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
-// On 16-byte lanes mixed precision keeps the direction in fp32 and no q = A p vector: a
-// step is
+// On 16-byte-lane hierarchies mixed precision keeps the direction in fp32 and no q = A p
+// vector: a step is
 //   x += alpha_prev p;  pn = fl32(z + beta p);  partials of pn . A pn   (k_w_cg_pdir)
-//   r -= alpha A p, A p from the stored fp32 direction                  (k_w_cg_xr)
-// Both products are evaluated in fp64 by the same march on the same fp32 values, and
-// x += alpha p uses the stored p too, so the recursive residual follows the true one in
-// fp64 arithmetic; rounding p to fp32 only perturbs the conjugacy of the directions, at
-// the level of the fp32 preconditioned residual z it is formed from.  52 bytes per unknown
+//   r -= alpha A p, A p in fp64 from the stored fp32 direction          (k_w_cg_xr)
+// x += alpha p and r -= alpha A p use the same stored p and alpha, so the recursive
+// residual follows the true one in fp64 arithmetic whatever the rounding of alpha (whose
+// product pn . A pn is formed with the fp32 operator); rounding p to fp32 only perturbs
+// the conjugacy of the directions, at the level of the fp32 preconditioned residual z it
+// is formed from.  52 bytes per unknown
 // against 68 for the earlier split (a direction pass, q = A p stored, r -= alpha q) and 80
 // for the fused q-recursion with its r update.  On one-node lanes, which serve the small
 // boxes where each launch's latency counts more than bytes, the fused form with an fp32 z

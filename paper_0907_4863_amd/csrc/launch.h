@@ -134,6 +134,16 @@ void w_cg_resid(const FineLevel& L, const double* bs, const double* x, double* r
 template <typename TZ>
 void w_cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
              double* partials, KTimer& kt);
+// The fp32-direction CG step: nodes per lane of its two passes, and the arithmetic of the
+// first pass's product.  p . A p only sets the step length alpha, and x += alpha p and
+// r -= alpha A p take the same alpha, so its rounding leaves r the residual of x; it is
+// formed with the fp32 level-0 operator (summed in fp64).  r -= alpha A p takes A p in
+// fp64.  Two nodes per lane keep both passes at 4 wavefronts per SIMD (on the 256 x 256 x
+// 768 ellipse, per step: 4 nodes and an fp64 product 317 + 258 us, 4 nodes fp32 300 +
+// 258, 2 nodes fp64 280 + 225, 2 nodes fp32 268 + 225).
+using CgDirArith = float;
+constexpr int kCgDirLanes = 2;
+constexpr int kCgXrLanes = 2;
 // mixed precision, fp32 direction: x += alpha_prev p, pn = fl32(z + beta p) and the
 // partials of pn . A pn; then r -= alpha A p with A p from the stored direction
 void w_cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, double* x,

@@ -888,23 +888,22 @@ void w_cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, c
 template void w_cg_pq<double>(const FineLevel&, const double*, double*, double*, double*,
                               const double*, double*, KTimer&);
 
-// Mixed precision's CG step on 16-byte lanes (4 nodes per lane) in two passes that share
-// no q = A p vector.  The first takes the direction update and p . A p together: x +=
+// Mixed precision's CG step in two passes that share no q = A p vector (N nodes per lane;
+// the launchers take N and the first pass's arithmetic TA from kCgDirLanes, kCgXrLanes
+// and CgDirArith).  The first takes the direction update and p . A p together: x +=
 // alpha_prev p_old and p_new = fl32(z + beta p_old), with p_new at the neighbour lines and
 // planes formed from z and p_old as the march reads them (XDir), so A p_new costs no pass
 // of its own.  p_new goes to the other direction buffer, since neighbouring blocks still
-// read p_old where this block has stored p_new.  The second recomputes A p from the
-// stored fp32 direction for r -= alpha A p.  Both evaluate A p with the same march and
-// arithmetic on the same fp32 values.  Per unknown: z 4, p_old 4, x 8 read, p_new 4, x 8
-// written; then p 4, r 8 read, r 8, r32 4 written.
-__global__ void __launch_bounds__(kMThreads) k_w_cg_pdir(L0View<double> v,
-                                                        const float* __restrict__ zv,
+// read p_old where this block has stored p_new.  The second recomputes A p in fp64 from
+// the stored fp32 direction for r -= alpha A p.  Per unknown: z 4, p_old 4, x 8 read,
+// p_new 4, x 8 written; then p 4, r 8 read, r 8, r32 4 written.
+template <typename TA, int N>
+__global__ void __launch_bounds__(kMThreads) k_w_cg_pdir(L0View<TA> v, const float* __restrict__ zv,
                                                         const float* __restrict__ p,
                                                         float* __restrict__ pn,
                                                         double* __restrict__ xv,
                                                         const double* __restrict__ scal,
                                                         double* part) {
-    constexpr int N = 4;
     __shared__ double lds[kMThreads / kWave];
     const double beta = scal[S_BETA];
     const double xa = scal[S_XA];
@@ -913,10 +912,10 @@ __global__ void __launch_bounds__(kMThreads) k_w_cg_pdir(L0View<double> v,
         Vec<float, N> p;
         Vec<double, N> x;
     };
-    wmarch_x<double, N, true, false, true>(
+    wmarch_x<TA, N, true, false, true>(
         v, XDir{zv, p, beta},
         [&](Idx i, int, int, int, unsigned, int) { return R{vld<N>(p, i), vldnt<N>(xv, i)}; },
-        [&](Idx i, const R& f, const Vec<double, N>& pv, const Vec<double, N>& ap, int, int, int,
+        [&](Idx i, const R& f, const Vec<TA, N>& pv, const Vec<TA, N>& ap, int, int, int,
             unsigned nib) {
             float po[N];
             double xo[N];
@@ -925,7 +924,7 @@ __global__ void __launch_bounds__(kMThreads) k_w_cg_pdir(L0View<double> v,
                 const bool u = (nib >> e) & 1u;
                 po[e] = u ? (float)pv.v[e] : 0.0f;
                 xo[e] = u ? f.x.v[e] + xa * (double)f.p.v[e] : 0.0;
-                acc += u ? pv.v[e] * ap.v[e] : 0.0;
+                acc += u ? (double)pv.v[e] * (double)ap.v[e] : 0.0;
             }
             vstnt<N>(pn, i, po);
             vstnt<N>(xv, i, xo);
@@ -936,12 +935,12 @@ __global__ void __launch_bounds__(kMThreads) k_w_cg_pdir(L0View<double> v,
 
 // r -= alpha A p (alpha = S_XA; r left as it is when the step broke down), its fp32 copy
 // and partials of r . r.  Whole rows are stored (zero at the nodes that are not unknowns).
+template <int N>
 __global__ void __launch_bounds__(kMThreads) k_w_cg_xr(L0View<double> v, const float* __restrict__ p,
                                                       double* __restrict__ r,
                                                       float* __restrict__ r32,
                                                       const double* __restrict__ scal,
                                                       double* part) {
-    constexpr int N = 4;
     __shared__ double lds[kMThreads / kWave];
     const double alpha = scal[S_XA];
     const bool ok = alpha != 0.0;
@@ -972,15 +971,16 @@ __global__ void __launch_bounds__(kMThreads) k_w_cg_xr(L0View<double> v, const f
 
 void w_cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, double* x,
                const double* scal, double* partials, KTimer& kt_) {
-    klaunch(kt_, true, k_w_cg_pdir, dim3((unsigned)l0_wblocks(L, 4)), dim3(kWave, kMY),
-            wview<double>(L, 4), z, p, pn, x, scal, partials);
+    klaunch(kt_, true, (k_w_cg_pdir<CgDirArith, kCgDirLanes>),
+            dim3((unsigned)l0_wblocks(L, kCgDirLanes)), dim3(kWave, kMY),
+            wview<CgDirArith>(L, kCgDirLanes), z, p, pn, x, scal, partials);
     HIPCHECK(hipGetLastError());
 }
 
 void w_cg_xr(const FineLevel& L, const float* p, double* r, float* r32, const double* scal,
              double* partials, KTimer& kt_) {
-    klaunch(kt_, true, k_w_cg_xr, dim3((unsigned)l0_wblocks(L, 4)), dim3(kWave, kMY),
-            wview<double>(L, 4), p, r, r32, scal, partials);
+    klaunch(kt_, true, k_w_cg_xr<kCgXrLanes>, dim3((unsigned)l0_wblocks(L, kCgXrLanes)),
+            dim3(kWave, kMY), wview<double>(L, kCgXrLanes), p, r, r32, scal, partials);
     HIPCHECK(hipGetLastError());
 }
 
