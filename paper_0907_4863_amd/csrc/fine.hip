@@ -63,7 +63,7 @@ long cg_xr_parts(const FineLevel& L, bool split) {
     return split ? l0_wblocks(L, kCgXrLanes) : l0_blocks(L);
 }
 long l0_dot_parts(const FineLevel& L, int bytes) {
-    return L.wide ? l0_wblocks(L, l0_lanes(bytes)) : l0_blocks(L);
+    return L.wide ? l0_wblocks(L, dot_lanes(bytes)) : l0_blocks(L);
 }
 
 // Planes per block of the kernels on 16-byte lanes: at most 64 / n - 2 (the per-tile word

@@ -43,6 +43,19 @@ size_t pic_sort_bytes(long n, int bits);
 
 // Nodes per lane of the level-0 kernels on 16-byte lanes, for values of `bytes` bytes.
 constexpr int l0_lanes(int bytes) { return 16 / bytes; }
+// fp32 lanes per kernel group: the Chebyshev steps from a zero guess, the later Chebyshev
+// steps (which carry the fused r . z partials, so l0_dot_parts follows them, and so does
+// the dot of a one-level hierarchy), and the prolongation.  Two nodes per lane measured
+// slower for each (256 x 256 x 768 ellipse: zero-guess step 90.7 -> 97.1 us, later steps
+// 110.6 / 126.8 -> 114.8 / 132.8 us, prolongation 98.8 -> 111.5 us), unlike the CG step.
+constexpr int kChebZeroLanesF = 4;
+constexpr int kChebLanesF = 4;
+constexpr int kProlongLanesF = 4;
+constexpr int cheb_lanes(int bytes, int mode) {
+    return bytes == 8 ? 2 : (mode <= CHEB_ZERO2 ? kChebZeroLanesF : kChebLanesF);
+}
+constexpr int dot_lanes(int bytes) { return bytes == 8 ? 2 : kChebLanesF; }
+constexpr int prolong_lanes(int bytes) { return bytes == 8 ? 2 : kProlongLanesF; }
 // Number of partial sums (blocks) written by the level-0 reduction kernels of the
 // 64-node engine (the Lanczos kernels), and by those on 16-byte lanes with n nodes per lane.
 long l0_blocks(const FineLevel& L);

@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(kMThreads) k_w_cheb(L0View<T> v, const T* __re
                                                      const T* __restrict__ din, T* __restrict__ xout,
                                                      T* __restrict__ dout, T c1, T c2, T c20,
                                                      const double* __restrict__ fdot, double* part) {
-    constexpr int N = kLanes<T>;
+    constexpr int N = cheb_lanes((int)sizeof(T), MODE);
     __shared__ double lds[kMThreads / kWave];
     double acc = 0.0;
     constexpr bool LF = MODE == CHEB_FIRST || MODE == CHEB_NEXT || MODE == CHEB_NEXT_X ||
@@ -550,15 +550,19 @@ template <typename T>
 void w_cheb(const FineLevel& L, int mode, const T* f, const T* xin, const T* din, T* xout,
             T* dout, double c1, double c2, double c2_0, const double* fdot, double* dot,
             KTimer& kt_) {
-    const L0View<T> v = wview<T>(L, kLanes<T>);
-    const dim3 g = wgrid<T>(L), b(kWave, kMY);
+    const dim3 b(kWave, kMY);
 #define WCHEB_LAUNCH(M)                                                                        \
-    if (dot)                                                                                   \
-        klaunch(kt_, true, (k_w_cheb<T, M, true>), g, b, v, f, xin, din, xout, dout, (T)c1,    \
-                (T)c2, (T)c2_0, fdot, dot);                                                    \
-    else                                                                                       \
-        klaunch(kt_, true, (k_w_cheb<T, M, false>), g, b, v, f, xin, din, xout, dout, (T)c1,   \
-                (T)c2, (T)c2_0, fdot, dot);
+    {                                                                                          \
+        constexpr int n_ = cheb_lanes((int)sizeof(T), M);                                      \
+        const L0View<T> v = wview<T>(L, n_);                                                   \
+        const dim3 g((unsigned)l0_wblocks(L, n_));                                             \
+        if (dot)                                                                               \
+            klaunch(kt_, true, (k_w_cheb<T, M, true>), g, b, v, f, xin, din, xout, dout,       \
+                    (T)c1, (T)c2, (T)c2_0, fdot, dot);                                         \
+        else                                                                                   \
+            klaunch(kt_, true, (k_w_cheb<T, M, false>), g, b, v, f, xin, din, xout, dout,      \
+                    (T)c1, (T)c2, (T)c2_0, fdot, dot);                                         \
+    }
     switch (mode) {
         case CHEB_ZERO1: WCHEB_LAUNCH(CHEB_ZERO1) break;
         case CHEB_ZERO2: WCHEB_LAUNCH(CHEB_ZERO2) break;
@@ -677,7 +681,7 @@ template <typename T>
 __global__ void __launch_bounds__(kMThreads) k_w_prolong(L0View<T> v, LCView<T> c,
                                                         const T* __restrict__ vc,
                                                         T* __restrict__ xv, T omega) {
-    constexpr int N = kLanes<T>;
+    constexpr int N = prolong_lanes((int)sizeof(T));
     struct R {
         T row[4];  // coarse values at x-range qx0-1 .. qx0+2 of the node's layer
         T yn[2];   // y-face lines: the y-neighbour values of aggregates qx0, qx0+1
@@ -760,8 +764,9 @@ __global__ void __launch_bounds__(kMThreads) k_w_prolong(L0View<T> v, LCView<T> 
 template <typename T>
 void w_prolong(const FineLevel& L, const CoarseLevel& C, const T* vc, T* x, double omega,
                KTimer& kt_) {
-    klaunch(kt_, true, (k_w_prolong<T>), wgrid<T>(L), dim3(kWave, kMY), wview<T>(L, kLanes<T>),
-            C.view<T>(), vc, x, (T)omega);
+    constexpr int n = prolong_lanes((int)sizeof(T));
+    klaunch(kt_, true, (k_w_prolong<T>), dim3((unsigned)l0_wblocks(L, n)), dim3(kWave, kMY),
+            wview<T>(L, n), C.view<T>(), vc, x, (T)omega);
     HIPCHECK(hipGetLastError());
 }
 template void w_prolong<double>(const FineLevel&, const CoarseLevel&, const double*, double*,
@@ -769,11 +774,12 @@ template void w_prolong<double>(const FineLevel&, const CoarseLevel&, const doub
 template void w_prolong<float>(const FineLevel&, const CoarseLevel&, const float*, float*, double,
                                KTimer&);
 
-// Partial sums of a . b over the unknowns, on the tiling of the V-cycle kernels in T.
+// Partial sums of a . b over the unknowns, on the tiling of the Chebyshev steps that carry
+// the fused r . z partials.
 template <typename T>
 __global__ void __launch_bounds__(kMThreads) k_w_dot(L0View<T> v, const double* __restrict__ a,
                                                     const T* __restrict__ b, double* part) {
-    constexpr int N = kLanes<T>;
+    constexpr int N = dot_lanes((int)sizeof(T));
     __shared__ double lds[kMThreads / kWave];
     double acc = 0.0;
     struct R {
@@ -794,8 +800,9 @@ __global__ void __launch_bounds__(kMThreads) k_w_dot(L0View<T> v, const double* 
 
 template <typename T>
 void w_dot(const FineLevel& L, const double* a, const T* b, double* partials, hipStream_t s) {
-    hipLaunchKernelGGL((k_w_dot<T>), wgrid<T>(L), dim3(kWave, kMY), 0, s, wview<T>(L, kLanes<T>),
-                       a, b, partials);
+    constexpr int n = dot_lanes((int)sizeof(T));
+    hipLaunchKernelGGL((k_w_dot<T>), dim3((unsigned)l0_wblocks(L, n)), dim3(kWave, kMY), 0, s,
+                       wview<T>(L, n), a, b, partials);
     HIPCHECK(hipGetLastError());
 }
 template void w_dot<double>(const FineLevel&, const double*, const double*, double*, hipStream_t);
