@@ -422,9 +422,10 @@ int saamg_pic_destroy(saamg_pic* P);
  * summed start-to-end time, the launch count and the algorithmic bytes moved (each
  * array the kernel must read or write counted once over the unknowns it covers).
  * Classes: 0 level-0 Chebyshev steps, 1 level-0 residual, 2 restriction to level 1,
- * 3 prolongation from level 1, 4 CG direction update + product with A, 5 CG x/r update,
- * 6 all coarse-level kernels, 7 reduction finalisation.  At most 65536 launches are
- * kept between resets; later ones are not timed.
+ * 3 prolongation from level 1, 4 CG direction update + product with A, 5 CG r update,
+ * 6 all coarse-level kernels, 7 reduction finalisation, 8 x update from the ring of fp32
+ * CG directions (mixed precision on 16-byte lanes; the other forms update x in class 4).
+ * At most 65536 launches are kept between resets; later ones are not timed.
  */
 int saamg_timer_enable(int kind, int enable);
 int saamg_timer_read(int kind, double* total_ms, int64_t* launches, int64_t* alg_bytes);

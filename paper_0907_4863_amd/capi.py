@@ -553,7 +553,7 @@ def scaling(H: Hierarchy, sigma, stream=None) -> None:
 # --------------------------------------------------------------------------- timing
 
 TIMER_KINDS = {"l0_cheb": 0, "l0_resid": 1, "l0_restrict": 2, "l0_prolong": 3, "cg_pq": 4,
-               "cg_xr": 5, "coarse": 6, "finalize": 7}
+               "cg_xr": 5, "coarse": 6, "finalize": 7, "cg_x": 8}
 
 
 def timer_enable(kind: str, enable: bool = True) -> None:

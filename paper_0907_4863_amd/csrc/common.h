@@ -201,7 +201,7 @@ struct Tmp {
 // marker is added to the stream between kernels.
 enum TimerKind {
     T_L0_CHEB = 0, T_L0_RESID, T_L0_RESTRICT, T_L0_PROLONG, T_CG_PQ, T_CG_XR, T_COARSE,
-    T_FINALIZE, T_NKIND
+    T_FINALIZE, T_CG_X, T_NKIND
 };
 struct KTimer {
     int slot = -1;

@@ -339,11 +339,13 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(const double* __restri
             for (int q = 0; q < nq; ++q) scal[dst + q] = sums[q];
             break;
         case FIN_ALPHA: {
-            // the step is taken only when p.q > 0, r.z > 0 and alpha is finite
+            // the step is taken only when p.q > 0, r.z > 0 and alpha is finite; dst > 0
+            // also records the step length there (a direction ring's slot)
             const double a = scal[S_RHO] / sums[0];
             scal[S_PQ] = sums[0];
             scal[S_ALPHA] = a;
             scal[S_XA] = (sums[0] > 0.0 && scal[S_RHO] > 0.0 && isfinite(a)) ? a : 0.0;
+            if (dst > 0) scal[dst] = scal[S_XA];
             break;
         }
         case FIN_RHO_INIT:
@@ -1375,12 +1377,21 @@ template void cg_pq<double>(const FineLevel&, const double*, double*, double*, d
 template void cg_pq<float>(const FineLevel&, const float*, double*, double*, double*,
                            const double*, double*, hipStream_t);
 
-void cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, double* x,
-             const double* scal, double* partials, hipStream_t s) {
-    // z 4, p 4, x 8 read; pn 4, x 8 written
-    KTimer kt_(T_CG_PQ, s, L.n_unknowns * 28L + l0_meta_bytes(L, 8, false));
+void cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, const double* scal,
+             double* partials, hipStream_t s) {
+    // z 4, p 4 read; pn 4 written
+    KTimer kt_(T_CG_PQ, s, L.n_unknowns * 12L + l0_meta_bytes(L, 8, false));
     if (!pq_wide(L)) throw ApiError{SAAMG_INVALID_ARG, "the fp32-direction CG step needs 16-byte lanes"};
-    w_cg_pdir(L, z, p, pn, x, scal, partials, kt_);
+    w_cg_pdir(L, z, p, pn, scal, partials, kt_);
+}
+
+void cg_xring(const FineLevel& L, double* x, const float* ring, const double* scal,
+              const RingSlots& rs, hipStream_t s) {
+    // x 8 read and written, 4 per direction
+    KTimer kt_(T_CG_X, s, L.n_unknowns * (16L + 4L * rs.m));
+    if (rs.m < 1 || rs.m > kCgRing || L.nbox % 4 != 0)
+        throw ApiError{SAAMG_INVALID_ARG, "ring flush: 1..kCgRing directions, a box of 4-node lanes"};
+    w_cg_xring(L, x, ring, scal, rs, kt_);
 }
 
 void cg_xr_dir(const FineLevel& L, const float* p, double* r, float* r32, const double* scal,
@@ -1455,8 +1466,6 @@ void cg_xflush(const FineLevel& L, double* x, const TP* p, const double* scal, h
 }
 template void cg_xflush<double>(const FineLevel&, double*, const double*, const double*,
                                 hipStream_t);
-template void cg_xflush<float>(const FineLevel&, double*, const float*, const double*,
-                               hipStream_t);
 
 // out = sigma x on every box node (0 where not an unknown): the caller's buffer.
 __global__ void __launch_bounds__(kThreads) k_cg_unscale(L0View<double> v, const double* __restrict__ sigma,

@@ -28,7 +28,18 @@ enum Slot {
     S_XA,  // step length still owed to x (x += S_XA p); 0 after a broken-down step
     S_TOL,   // the solve's tolerance
     S_SKIP,  // nonzero: the queued V-cycle is not needed (the residual passes the test)
-    S_NSLOTS = 18
+    S_AR0 = 18,  // kCgRing slots: the step length of each direction in the ring (fp32 CG)
+    S_NSLOTS = S_AR0 + 16
+};
+// Directions of the fp32-direction CG step kept in a ring (x receives them every kCgRing
+// steps and before it is read; see k_cg_xring).  16 directions: a solve of up to 16 steps
+// updates x once, at 64 bytes per box node (3.2 GB on a 256 x 256 x 768 box).  With 8 a
+// flush took 391 us on that box (x and 8 directions, 6.2 TB/s), three per 22-step solve.
+constexpr int kCgRing = S_NSLOTS - S_AR0;
+// The pending directions of a ring flush: ring slots in the order of their steps.
+struct RingSlots {
+    int m;
+    int slot[kCgRing];
 };
 // Finalisation ops: how the summed partials update `scal`.
 enum FinOp { FIN_STORE = 0, FIN_ALPHA, FIN_RHO_INIT, FIN_RHO, FIN_LZ_ALPHA, FIN_LZ_BETA, FIN_NORM,
@@ -151,16 +162,21 @@ void w_cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, c
 // first pass's product.  p . A p only sets the step length alpha, and x += alpha p and
 // r -= alpha A p take the same alpha, so its rounding leaves r the residual of x; it is
 // formed with the fp32 level-0 operator (summed in fp64).  r -= alpha A p takes A p in
-// fp64.  Two nodes per lane keep both passes at 4 wavefronts per SIMD (on the 256 x 256 x
-// 768 ellipse, per step: 4 nodes and an fp64 product 317 + 258 us, 4 nodes fp32 300 +
-// 258, 2 nodes fp64 280 + 225, 2 nodes fp32 268 + 225).
+// fp64.  On the 256 x 256 x 768 ellipse, per step, when the first pass still updated x:
+// 4 nodes and an fp64 product 317 + 258 us, 4 nodes fp32 300 + 258, 2 nodes fp64
+// 280 + 225, 2 nodes fp32 268 + 225 (the x operands had cost the registers of a
+// wavefront per SIMD).  Without x the first pass takes 153 us on 2 nodes per lane and
+// 137 us on 4.
 using CgDirArith = float;
-constexpr int kCgDirLanes = 2;
+constexpr int kCgDirLanes = 4;
 constexpr int kCgXrLanes = 2;
-// mixed precision, fp32 direction: x += alpha_prev p, pn = fl32(z + beta p) and the
-// partials of pn . A pn; then r -= alpha A p with A p from the stored direction
-void w_cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, double* x,
-               const double* scal, double* partials, KTimer& kt);
+// mixed precision, fp32 direction: pn = fl32(z + beta p) and the partials of pn . A pn;
+// then r -= alpha A p with A p from the stored direction; x += alpha_j p_j over a ring's
+// pending directions
+void w_cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, const double* scal,
+               double* partials, KTimer& kt);
+void w_cg_xring(const FineLevel& L, double* x, const float* ring, const double* scal,
+                const RingSlots& rs, KTimer& kt);
 void w_cg_xr(const FineLevel& L, const float* p, double* r, float* r32, const double* scal,
              double* partials, KTimer& kt);
 
@@ -172,14 +188,17 @@ void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, 
               float* r32, hipStream_t s);
 // Direction update, the product by A and the partials of p . q in one pass, with the
 // q-recursion and an fp64 direction (z in the working precision); cg_xr then takes
-// r -= alpha q.  Or (cg_split: mixed precision on 16-byte lanes) an fp32 direction in two
-// buffers and no q: cg_pdir updates x and the direction (p -> pn) with the partials of
-// pn . A pn, and cg_xr_dir takes r -= alpha A p from the stored direction.
+// r -= alpha q.  Or (cg_split: mixed precision on 16-byte lanes) fp32 directions in a ring
+// and no q: cg_pdir forms the next direction (p -> pn) with the partials of pn . A pn,
+// cg_xr_dir takes r -= alpha A p from the stored direction, and cg_xring adds the ring's
+// pending alpha_j p_j to x.
 template <typename TZ>
 void cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
            double* partials, hipStream_t s);
-void cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, double* x,
-             const double* scal, double* partials, hipStream_t s);
+void cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, const double* scal,
+             double* partials, hipStream_t s);
+void cg_xring(const FineLevel& L, double* x, const float* ring, const double* scal,
+              const RingSlots& rs, hipStream_t s);
 bool cg_split(const FineLevel& L, bool mixed);
 void cg_xr(const FineLevel& L, double* r, const double* q, const double* scal, double* partials,
            float* r32, hipStream_t s);

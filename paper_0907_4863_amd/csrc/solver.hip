@@ -379,12 +379,13 @@ struct saamg_state {
     double *x = nullptr, *r = nullptr, *q = nullptr, *bs = nullptr;
     float* r32 = nullptr;  // fp32 copy of r (mixed precision)
     void* z = nullptr;     // preconditioned residual (fp32 in mixed precision)
-    void* p = nullptr;     // direction: fp32 when split (cg_split), else fp64
-    // split: the other direction buffer, which each step writes before the two swap.  It
-    // lies in q's memory (q itself is not used by a split solve, except as the scratch of
-    // a final true residual taken after the last x += alpha p).  pbuf owns p's allocation.
-    void* pn = nullptr;
-    void* pbuf = nullptr;
+    void* p = nullptr;     // direction (fp64; fp32 when split, then a slot of `ring`)
+    // split (cg_split): the last `ringk` fp32 directions, ring slot k % ringk holding step
+    // k's; x has received alpha_j p_j for all but the last `pend` of them.  q is then only
+    // the scratch of a final true residual.
+    float* ring = nullptr;
+    int ringk = 0, pend = 0;
+    long kdir = 0;  // directions formed so far in this solve
     bool split = false;
     VBuf<float> vf;
     VBuf<double> vd;
@@ -408,6 +409,21 @@ namespace saamg {
 // saamg_set_operator gave it (the preconditioner then keeps the hierarchy's).
 static const FineLevel& cg_op(const saamg_hierarchy* H) { return H->op ? *H->op : H->l0; }
 
+// Ring slot of direction k (k = -1: the one the first step reads) of a split state.
+static int ring_index(const saamg_state* S, long k) { return (int)(((k % S->ringk) + S->ringk) % S->ringk); }
+static float* ring_slot(const saamg_state* S, long k) {
+    return S->ring + (long)ring_index(S, k) * S->H->l0.nbox;
+}
+
+// x += alpha_j p_j for the ring's pending directions, in the order of their steps.
+static void ring_flush(saamg_state* S) {
+    RingSlots rs{};
+    rs.m = S->pend;
+    for (int j = 0; j < S->pend; ++j) rs.slot[j] = ring_index(S, S->kdir - S->pend + j);
+    cg_xring(cg_op(S->H), S->x, S->ring, S->scal, rs, S->s);
+    S->pend = 0;
+}
+
 // Partial sums written by the V-cycle's fused r . z (in the working precision).
 static long pc_parts(const saamg_state* S) { return l0_dot_parts(S->H->l0, S->mixed ? 4 : 8); }
 
@@ -420,14 +436,19 @@ static void state_alloc(saamg_state* S, saamg_hierarchy* H, bool pinned = true) 
     S->x = (double*)dmalloc(8 * n);
     S->r = (double*)dmalloc(8 * n);
     S->split = cg_split(H->l0, S->mixed);
-    S->p = S->pbuf = dmalloc((S->split ? 4 : 8) * n);
+    if (S->split) {
+        // a state that allocates nothing keeps 2 directions (flushed every other step)
+        S->ringk = pinned ? kCgRing : 2;
+        S->ring = (float*)dmalloc(4L * S->ringk * n);
+    } else {
+        S->p = dmalloc(8 * n);
+    }
     S->q = (double*)dmalloc(8 * n);
-    S->pn = S->split ? (void*)S->q : nullptr;
     S->bs = (double*)dmalloc(8 * n);
     S->z = dmalloc((S->mixed ? 4 : 8) * n);
     if (S->mixed) S->r32 = (float*)dmalloc(4 * n);
     // x, r, q, b~ (fp64); p, z and the fp32 copy of r
-    S->bytes = 32L * n + (S->split ? 4 : 8) * n + 8L * n;  // z 8, or fp32 z and r32
+    S->bytes = 32L * n + (S->split ? 4L * S->ringk : 8) * n + 8L * n;  // z 8, or fp32 z and r32
     if (S->mixed) {
         S->vf.alloc(H);
         S->bytes += S->vf.bytes(H);
@@ -450,7 +471,8 @@ static void state_alloc(saamg_state* S, saamg_hierarchy* H, bool pinned = true) 
 
 static void state_release(saamg_state* S) {
     for (double* p : {S->x, S->r, S->q, S->bs}) dfree(p);
-    dfree(S->pbuf);
+    dfree(S->p);
+    dfree(S->ring);
     dfree(S->z);
     dfree(S->r32);
     S->r32 = nullptr;
@@ -461,7 +483,8 @@ static void state_release(saamg_state* S) {
     if (S->hscal && S->hscal != S->hbuf) (void)hipHostFree(S->hscal);
     if (S->ev) (void)hipEventDestroy(S->ev);
     S->x = S->r = S->q = S->bs = nullptr;
-    S->z = S->p = S->pn = S->pbuf = nullptr;
+    S->z = S->p = nullptr;
+    S->ring = nullptr;
     S->part = S->scal = S->hscal = nullptr;
     S->ev = nullptr;
 }
@@ -505,7 +528,12 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
     cg_resid(cg_op(H), S->bs, S->x, S->r, S->part, S->r32, S->s);
     finalize(S->part, cg_resid_parts(cg_op(H)), 2, S->scal, FIN_STORE, S_RR, S->s);
     scal_start(S->scal, S->tol, S->s);
-    zero_fill(S->p, (S->split ? 4 : 8) * H->l0.nbox, S->s);
+    S->kdir = 0;
+    S->pend = 0;
+    if (S->split)  // the direction the first step reads (times beta = 0)
+        zero_fill(ring_slot(S, -1), 4 * H->l0.nbox, S->s);
+    else
+        zero_fill(S->p, 8 * H->l0.nbox, S->s);
     zero_fill(S->q, 8 * H->l0.nbox, S->s);
     read_scal(S);
     const double rr = S->hscal[S_RR], bb = S->hscal[S_BB];
@@ -542,18 +570,22 @@ static void state_enqueue(saamg_state* S) {
     const saamg_hierarchy* H = S->H;
     const FineLevel& L = cg_op(H);
     if (S->split) {
-        cg_pdir(L, (const float*)S->z, (const float*)S->p, (float*)S->pn, S->x, S->scal, S->part,
-                S->s);
-        std::swap(S->p, S->pn);
+        if (S->pend == S->ringk) ring_flush(S);  // the next direction overwrites the oldest
+        cg_pdir(L, (const float*)S->z, ring_slot(S, S->kdir - 1), ring_slot(S, S->kdir), S->scal,
+                S->part, S->s);
     } else if (S->mixed)
         cg_pq<float>(L, (const float*)S->z, S->x, (double*)S->p, S->q, S->scal, S->part, S->s);
     else
         cg_pq<double>(L, (const double*)S->z, S->x, (double*)S->p, S->q, S->scal, S->part, S->s);
-    finalize(S->part, cg_pq_parts(L, S->split), 1, S->scal, FIN_ALPHA, 0, S->s);
-    if (S->split)
-        cg_xr_dir(L, (const float*)S->p, S->r, S->r32, S->scal, S->part, S->s);
-    else
+    finalize(S->part, cg_pq_parts(L, S->split), 1, S->scal, FIN_ALPHA,
+             S->split ? S_AR0 + ring_index(S, S->kdir) : 0, S->s);
+    if (S->split) {
+        cg_xr_dir(L, ring_slot(S, S->kdir), S->r, S->r32, S->scal, S->part, S->s);
+        S->kdir += 1;
+        S->pend += 1;
+    } else {
         cg_xr(L, S->r, S->q, S->scal, S->part, S->r32, S->s);
+    }
     finalize(S->part, cg_xr_parts(L, S->split), 1, S->scal, FIN_RR, 0, S->s);
     HIPCHECK(hipMemcpyAsync(S->hscal, S->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
                             S->s));
@@ -563,13 +595,15 @@ static void state_enqueue(saamg_state* S) {
     finalize(S->part, pc_parts(S), 1, S->scal, FIN_RHO, 0, S->s);
 }
 
-// The step length a step still owes x (each step's x += alpha p is applied by the next
-// step's direction update): apply it now and clear it.  Needed before x is read.
+// The updates x still owes: the step length of the last step (applied by the next step's
+// direction update in the fused form), or the ring's pending directions.  Needed before x
+// is read.
 static void flush_x(saamg_state* S) {
-    if (S->split)
-        cg_xflush<float>(cg_op(S->H), S->x, (const float*)S->p, S->scal, S->s);
-    else
-        cg_xflush<double>(cg_op(S->H), S->x, (const double*)S->p, S->scal, S->s);
+    if (S->split) {
+        if (S->pend > 0) ring_flush(S);
+        return;
+    }
+    cg_xflush<double>(cg_op(S->H), S->x, (const double*)S->p, S->scal, S->s);
     finalize(S->part, 1, 0, S->scal, FIN_XA_CLEAR, 0, S->s);
 }
 
@@ -1640,7 +1674,9 @@ int saamg_footprint_bytes(int nx, int ny, int nz, int variant, int precision, in
         const bool mixed = precision == SAAMG_MIXED;
         const int na = variant == SAAMG_VARIANT_QUAD ? 27 : 14;
         double h = 8.0 * nbox + 20.0 * nbox / 64 + 0.2 * nbox * 12 * 16;  // sigma, masks, table
-        double st = 48.0 * nbox + (mixed ? 4 : 8) * nbox;
+        // x, r, q, b~, z, r32 and the direction (fp32 directions in a ring where mixed
+        // precision runs on 16-byte lanes)
+        double st = 48.0 * nbox + (mixed ? (l0_wide_default(nx) ? 4.0 * kCgRing : 4.0) : 8.0) * nbox;
         double w = mixed ? 4 : 8;
         st += 3 * w * nbox + w * nbox / 3;  // level-0 V-cycle vectors and restriction sums
         double m = nbox;

@@ -897,47 +897,72 @@ template void w_cg_pq<double>(const FineLevel&, const double*, double*, double*,
 
 // Mixed precision's CG step in two passes that share no q = A p vector (N nodes per lane;
 // the launchers take N and the first pass's arithmetic TA from kCgDirLanes, kCgXrLanes
-// and CgDirArith).  The first takes the direction update and p . A p together: x +=
-// alpha_prev p_old and p_new = fl32(z + beta p_old), with p_new at the neighbour lines and
-// planes formed from z and p_old as the march reads them (XDir), so A p_new costs no pass
-// of its own.  p_new goes to the other direction buffer, since neighbouring blocks still
-// read p_old where this block has stored p_new.  The second recomputes A p in fp64 from
-// the stored fp32 direction for r -= alpha A p.  Per unknown: z 4, p_old 4, x 8 read,
-// p_new 4, x 8 written; then p 4, r 8 read, r 8, r32 4 written.
+// and CgDirArith).  The directions live in a ring of kCgRing fp32 buffers.  The first pass
+// forms the new direction p_new = fl32(z + beta p_old) in the next ring buffer, with
+// p_new . A p_new: p_new at the neighbour lines and planes is formed from z and p_old as
+// the march reads them (XDir), so A p_new costs no pass of its own; neighbouring blocks
+// still read p_old where this block has stored p_new, hence two buffers.  The second
+// recomputes A p in fp64 from the stored fp32 direction for r -= alpha A p.  x is not
+// touched: it receives alpha_j p_j for the directions of the ring in one pass
+// (k_cg_xring) every kCgRing steps and before anything reads it.  Per unknown: z 4,
+// p_old 4 read, p_new 4 written; then p 4, r 8 read, r 8, r32 4 written; and x 16 plus
+// 4 per direction once per kCgRing steps.
 template <typename TA, int N>
 __global__ void __launch_bounds__(kMThreads) k_w_cg_pdir(L0View<TA> v, const float* __restrict__ zv,
                                                         const float* __restrict__ p,
                                                         float* __restrict__ pn,
-                                                        double* __restrict__ xv,
                                                         const double* __restrict__ scal,
                                                         double* part) {
     __shared__ double lds[kMThreads / kWave];
     const double beta = scal[S_BETA];
-    const double xa = scal[S_XA];
     double acc = 0.0;
-    struct R {
-        Vec<float, N> p;
-        Vec<double, N> x;
-    };
     wmarch_x<TA, N, true, false, true>(
-        v, XDir{zv, p, beta},
-        [&](Idx i, int, int, int, unsigned, int) { return R{vld<N>(p, i), vldnt<N>(xv, i)}; },
-        [&](Idx i, const R& f, const Vec<TA, N>& pv, const Vec<TA, N>& ap, int, int, int,
+        v, XDir{zv, p, beta}, WNOFETCH,
+        [&](Idx i, NoVals, const Vec<TA, N>& pv, const Vec<TA, N>& ap, int, int, int,
             unsigned nib) {
             float po[N];
-            double xo[N];
 #pragma unroll
             for (int e = 0; e < N; ++e) {
                 const bool u = (nib >> e) & 1u;
                 po[e] = u ? (float)pv.v[e] : 0.0f;
-                xo[e] = u ? f.x.v[e] + xa * (double)f.p.v[e] : 0.0;
                 acc += u ? (double)pv.v[e] * (double)ap.v[e] : 0.0;
             }
             vstnt<N>(pn, i, po);
-            vstnt<N>(xv, i, xo);
         });
     const double sb = block_sum(acc, lds);
     if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
+}
+
+// x += alpha_j p_j over the pending directions j of the ring, in the order of their steps
+// (one fused multiply-add per direction and node, as an update per step would take).  A
+// plain stream over the box, 4 nodes per thread: the directions and x are zero at the
+// nodes that are not unknowns, and so is every alpha_j p_j there.
+__global__ void __launch_bounds__(256) k_cg_xring(long n4, double* __restrict__ x,
+                                                 const float* __restrict__ ring, long stride,
+                                                 const double* __restrict__ scal, RingSlots rs) {
+    double a[kCgRing];
+#pragma unroll
+    for (int j = 0; j < kCgRing; ++j) a[j] = j < rs.m ? scal[S_AR0 + rs.slot[j]] : 0.0;
+    using F4 = ExtVec<float, 4>::type;
+    using D2 = ExtVec<double, 2>::type;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+         i += (long)gridDim.x * blockDim.x) {
+        D2* xp = reinterpret_cast<D2*>(x + 4 * i);
+        D2 lo = __builtin_nontemporal_load(xp), hi = __builtin_nontemporal_load(xp + 1);
+#pragma unroll
+        for (int j = 0; j < kCgRing; ++j) {
+            if (j < rs.m) {
+                const F4 pj = __builtin_nontemporal_load(
+                    reinterpret_cast<const F4*>(ring + rs.slot[j] * stride + 4 * i));
+                lo[0] = __builtin_fma(a[j], (double)pj[0], lo[0]);
+                lo[1] = __builtin_fma(a[j], (double)pj[1], lo[1]);
+                hi[0] = __builtin_fma(a[j], (double)pj[2], hi[0]);
+                hi[1] = __builtin_fma(a[j], (double)pj[3], hi[1]);
+            }
+        }
+        __builtin_nontemporal_store(lo, xp);
+        __builtin_nontemporal_store(hi, xp + 1);
+    }
 }
 
 // r -= alpha A p (alpha = S_XA; r left as it is when the step broke down), its fp32 copy
@@ -976,11 +1001,20 @@ __global__ void __launch_bounds__(kMThreads) k_w_cg_xr(L0View<double> v, const f
     if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
-void w_cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, double* x,
-               const double* scal, double* partials, KTimer& kt_) {
+void w_cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, const double* scal,
+               double* partials, KTimer& kt_) {
     klaunch(kt_, true, (k_w_cg_pdir<CgDirArith, kCgDirLanes>),
             dim3((unsigned)l0_wblocks(L, kCgDirLanes)), dim3(kWave, kMY),
-            wview<CgDirArith>(L, kCgDirLanes), z, p, pn, x, scal, partials);
+            wview<CgDirArith>(L, kCgDirLanes), z, p, pn, scal, partials);
+    HIPCHECK(hipGetLastError());
+}
+
+void w_cg_xring(const FineLevel& L, double* x, const float* ring, const double* scal,
+                const RingSlots& rs, KTimer& kt_) {
+    const long n4 = L.nbox / 4;
+    const long blocks = std::min<long>((n4 + 255) / 256, 8L * 1024);
+    klaunch(kt_, true, k_cg_xring, dim3((unsigned)std::max<long>(blocks, 1)), dim3(256), n4, x,
+            ring, L.nbox, scal, rs);
     HIPCHECK(hipGetLastError());
 }
 
