@@ -46,21 +46,17 @@ int l0_choose_zb(int tx, int nsegx, int ny, int nz) {
 // 64-node segments (shorter lines would leave most lanes of a 256-node span idle).
 bool l0_wide_default(int nx) { return nx % 4 == 0 && nx > 128; }
 
-// Which level-0 launchers run on 16-byte lanes when the hierarchy uses them (measured per
-// kernel on the 256 x 256 x 768 elliptic pipe, one-node against 16-byte lanes, us per
-// launch): every V-cycle kernel in both precisions (fp32 residual 132 -> 107, restriction
-// pass 125 -> 89; fp64 residual 282 -> 204, restriction pass 208 -> 141), the residual of
-// the CG and both forms of the direction update (fp64 511 -> 476; the mixed-precision
-// stencil pass q = A p 183 -> 174).  The streaming r -= alpha q keeps one node per lane
-// (234 against 242, fp64 192 against 199).
-static bool pq_wide(const FineLevel& L) { return L.wide; }
+// On a hierarchy with 16-byte lanes every V-cycle kernel, the CG's residual and the CG
+// step (its ring form, below) run on them (measured per kernel on the 256 x 256 x 768
+// elliptic pipe, one-node against 16-byte lanes, us per launch: fp32 residual 132 -> 107,
+// restriction pass 125 -> 89; fp64 residual 282 -> 204, restriction pass 208 -> 141).
 
 long cg_resid_parts(const FineLevel& L) { return L.wide ? l0_wblocks(L, 2) : l0_blocks(L); }
-long cg_pq_parts(const FineLevel& L, bool split) {
-    return pq_wide(L) ? l0_wblocks(L, split ? kCgDirLanes : 2) : l0_blocks(L);
+long cg_pq_parts(const FineLevel& L, bool ring, int bytes) {
+    return ring ? l0_wblocks(L, cg_dir_lanes(bytes)) : l0_blocks(L);
 }
-long cg_xr_parts(const FineLevel& L, bool split) {
-    return split ? l0_wblocks(L, kCgXrLanes) : l0_blocks(L);
+long cg_xr_parts(const FineLevel& L, bool ring, int bytes) {
+    return ring ? l0_wblocks(L, cg_xr_lanes(bytes)) : l0_blocks(L);
 }
 long l0_dot_parts(const FineLevel& L, int bytes) {
     return L.wide ? l0_wblocks(L, dot_lanes(bytes)) : l0_blocks(L);
@@ -1343,31 +1339,26 @@ __global__ void __launch_bounds__(kMThreads) k_cg_pq(L0View<double> v, const TZ*
     if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
-// On 16-byte-lane hierarchies mixed precision keeps the direction in fp32 and no q = A p
-// vector: a step is
-//   x += alpha_prev p;  pn = fl32(z + beta p);  partials of pn . A pn   (k_w_cg_pdir)
-//   r -= alpha A p, A p in fp64 from the stored fp32 direction          (k_w_cg_xr)
+// On 16-byte-lane hierarchies the CG step keeps its directions in a ring, in the working
+// precision, and no q = A p vector:
+//   pn = z + beta p (rounded to the working precision); partials of pn . A pn   (k_w_cg_pdir)
+//   r -= alpha A p, A p in fp64 from the stored direction                       (k_w_cg_xr)
+//   x += alpha_j p_j for the ring's directions, when it is full or x is read    (k_cg_xring)
 // x += alpha p and r -= alpha A p use the same stored p and alpha, so the recursive
 // residual follows the true one in fp64 arithmetic whatever the rounding of alpha (whose
-// product pn . A pn is formed with the fp32 operator); rounding p to fp32 only perturbs
-// the conjugacy of the directions, at the level of the fp32 preconditioned residual z it
-// is formed from.  52 bytes per unknown
-// against 68 for the earlier split (a direction pass, q = A p stored, r -= alpha q) and 80
-// for the fused q-recursion with its r update.  On one-node lanes, which serve the small
-// boxes where each launch's latency counts more than bytes, the fused form with an fp32 z
-// stays.
-bool cg_split(const FineLevel& L, bool mixed) { return mixed && L.wide; }
+// product pn . A pn mixed precision forms with the fp32 operator); rounding p to fp32 only
+// perturbs the conjugacy of the directions, at the level of the fp32 preconditioned
+// residual z it is formed from.  Per unknown and step, mixed precision: 12 + 24 bytes plus
+// (16 + 4 k) / k for a ring of k (40 with k = 16) against 80 for the fused q-recursion with
+// its r update; fp64: 24 + 24 + (16 + 8 k) / k (57) against 80.  On one-node lanes, which
+// serve the small boxes where each launch's latency counts more than bytes, the fused
+// form stays.
+bool cg_ring(const FineLevel& L) { return L.wide; }
 
 template <typename TZ>
 void cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
            double* partials, hipStream_t s) {
     KTimer kt_(T_CG_PQ, s, L.n_unknowns * (long)(sizeof(TZ) + 48) + l0_meta_bytes(L, 8, false));
-    if constexpr (sizeof(TZ) == 8) {
-        if (pq_wide(L)) {
-            w_cg_pq<double>(L, z, x, p, q, scal, partials, kt_);
-            return;
-        }
-    }
     klaunch(kt_, true, (k_cg_pq<TZ>), l0_mgrid(L), dim3(kWave, kMY), L.view<double>(), z, x, p, q,
             scal, partials);
     HIPCHECK(hipGetLastError());
@@ -1377,30 +1368,46 @@ template void cg_pq<double>(const FineLevel&, const double*, double*, double*, d
 template void cg_pq<float>(const FineLevel&, const float*, double*, double*, double*,
                            const double*, double*, hipStream_t);
 
-void cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, const double* scal,
+template <class E>
+void cg_pdir(const FineLevel& L, const E* z, const E* p, E* pn, const double* scal,
              double* partials, hipStream_t s) {
-    // z 4, p 4 read; pn 4 written
-    KTimer kt_(T_CG_PQ, s, L.n_unknowns * 12L + l0_meta_bytes(L, 8, false));
-    if (!pq_wide(L)) throw ApiError{SAAMG_INVALID_ARG, "the fp32-direction CG step needs 16-byte lanes"};
-    w_cg_pdir(L, z, p, pn, scal, partials, kt_);
+    // z, p read; pn written
+    KTimer kt_(T_CG_PQ, s, L.n_unknowns * 3L * (long)sizeof(E) + l0_meta_bytes(L, 8, false));
+    if (!cg_ring(L)) throw ApiError{SAAMG_INVALID_ARG, "the ring form of the CG step needs 16-byte lanes"};
+    w_cg_pdir<E>(L, z, p, pn, scal, partials, kt_);
 }
+template void cg_pdir<float>(const FineLevel&, const float*, const float*, float*, const double*,
+                             double*, hipStream_t);
+template void cg_pdir<double>(const FineLevel&, const double*, const double*, double*,
+                              const double*, double*, hipStream_t);
 
-void cg_xring(const FineLevel& L, double* x, const float* ring, const double* scal,
+template <class E>
+void cg_xring(const FineLevel& L, double* x, const E* ring, const double* scal,
               const RingSlots& rs, hipStream_t s) {
-    // x 8 read and written, 4 per direction
-    KTimer kt_(T_CG_X, s, L.n_unknowns * (16L + 4L * rs.m));
+    // x 8 read and written, one direction per pending step
+    KTimer kt_(T_CG_X, s, L.n_unknowns * (16L + (long)sizeof(E) * rs.m));
     if (rs.m < 1 || rs.m > kCgRing || L.nbox % 4 != 0)
         throw ApiError{SAAMG_INVALID_ARG, "ring flush: 1..kCgRing directions, a box of 4-node lanes"};
-    w_cg_xring(L, x, ring, scal, rs, kt_);
+    w_cg_xring<E>(L, x, ring, scal, rs, kt_);
 }
+template void cg_xring<float>(const FineLevel&, double*, const float*, const double*,
+                              const RingSlots&, hipStream_t);
+template void cg_xring<double>(const FineLevel&, double*, const double*, const double*,
+                               const RingSlots&, hipStream_t);
 
-void cg_xr_dir(const FineLevel& L, const float* p, double* r, float* r32, const double* scal,
+template <class E>
+void cg_xr_dir(const FineLevel& L, const E* p, double* r, float* r32, const double* scal,
                double* partials, hipStream_t s) {
-    // p 4, r 8 read; r 8, r32 4 written
-    KTimer kt_(T_CG_XR, s, L.n_unknowns * 24L + l0_meta_bytes(L, 8, false));
-    if (!pq_wide(L)) throw ApiError{SAAMG_INVALID_ARG, "the fp32-direction CG step needs 16-byte lanes"};
-    w_cg_xr(L, p, r, r32, scal, partials, kt_);
+    // p, r 8 read; r 8 (and r32 4) written
+    KTimer kt_(T_CG_XR, s, L.n_unknowns * (16L + (long)sizeof(E) + (r32 ? 4 : 0)) +
+                               l0_meta_bytes(L, 8, false));
+    if (!cg_ring(L)) throw ApiError{SAAMG_INVALID_ARG, "the ring form of the CG step needs 16-byte lanes"};
+    w_cg_xr<E>(L, p, r, r32, scal, partials, kt_);
 }
+template void cg_xr_dir<float>(const FineLevel&, const float*, double*, float*, const double*,
+                               double*, hipStream_t);
+template void cg_xr_dir<double>(const FineLevel&, const double*, double*, float*, const double*,
+                                double*, hipStream_t);
 
 // r -= alpha q (alpha = S_XA) and partials of r.r; r untouched when the step broke down
 // (S_XA = 0).  x receives alpha p later (the next k_cg_pq or k_cg_xflush).  With the fp32

@@ -76,8 +76,8 @@ long l0_wblocks(const FineLevel& L, int n);
 // not), cg_xr, and the V-cycle's fused r . z (its last Chebyshev step, or l0_dot) in a
 // working precision of `bytes` bytes.
 long cg_resid_parts(const FineLevel& L);
-long cg_pq_parts(const FineLevel& L, bool split);
-long cg_xr_parts(const FineLevel& L, bool split);
+long cg_pq_parts(const FineLevel& L, bool ring, int bytes);
+long cg_xr_parts(const FineLevel& L, bool ring, int bytes);
 long l0_dot_parts(const FineLevel& L, int bytes);
 int l0_choose_zb(int tx, int nsegx, int ny, int nz);
 // 16-byte lanes: whether a box of nx nodes per line uses them by default, and the planes
@@ -155,29 +155,40 @@ template <typename T>
 void w_dot(const FineLevel& L, const double* a, const T* b, double* partials, hipStream_t s);
 void w_cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
                 float* r32, hipStream_t s);
-template <typename TZ>
-void w_cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
-             double* partials, KTimer& kt);
-// The fp32-direction CG step: nodes per lane of its two passes, and the arithmetic of the
-// first pass's product.  p . A p only sets the step length alpha, and x += alpha p and
-// r -= alpha A p take the same alpha, so its rounding leaves r the residual of x; it is
-// formed with the fp32 level-0 operator (summed in fp64).  r -= alpha A p takes A p in
-// fp64.  On the 256 x 256 x 768 ellipse, per step, when the first pass still updated x:
-// 4 nodes and an fp64 product 317 + 258 us, 4 nodes fp32 300 + 258, 2 nodes fp64
-// 280 + 225, 2 nodes fp32 268 + 225 (the x operands had cost the registers of a
-// wavefront per SIMD).  Without x the first pass takes 153 us on 2 nodes per lane and
-// 137 us on 4.
+// The CG step on 16-byte lanes (directions in a ring): nodes per lane of its two passes,
+// and the arithmetic of the first pass's product in mixed precision.  p . A p only sets
+// the step length alpha, and x += alpha p and r -= alpha A p take the same alpha, so its
+// rounding leaves r the residual of x; in mixed precision it is formed with the fp32
+// level-0 operator (summed in fp64).  r -= alpha A p takes A p in fp64.  Mixed precision
+// on the 256 x 256 x 768 ellipse, per step, when the first pass still updated x: 4 nodes
+// and an fp64 product 317 + 258 us, 4 nodes fp32 300 + 258, 2 nodes fp64 280 + 225,
+// 2 nodes fp32 268 + 225 (the x operands had cost the registers of a wavefront per SIMD).
+// Without x the first pass takes 153 us on 2 nodes per lane and 137 us on 4.  fp64 keeps
+// 16-byte lanes (2 nodes) and fp64 arithmetic throughout.
 using CgDirArith = float;
 constexpr int kCgDirLanes = 4;
 constexpr int kCgXrLanes = 2;
-// mixed precision, fp32 direction: pn = fl32(z + beta p) and the partials of pn . A pn;
-// then r -= alpha A p with A p from the stored direction; x += alpha_j p_j over a ring's
-// pending directions
-void w_cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, const double* scal,
+constexpr int cg_dir_lanes(int bytes) { return bytes == 4 ? kCgDirLanes : 2; }
+constexpr int cg_xr_lanes(int bytes) { return bytes == 4 ? kCgXrLanes : 2; }
+// Ring length for directions of `bytes` bytes on a box of nbox nodes: kCgRing while the
+// ring stays within 8 GiB, down to 2 (x is then updated every other step, which moves
+// no more than one update per step).
+constexpr long kCgRingBudget = 8L << 30;
+inline int cg_ring_len(long nbox, int bytes) {
+    const long k = kCgRingBudget / (std::max(nbox, 1L) * bytes);
+    return (int)std::max(2L, std::min<long>(kCgRing, k));
+}
+// pn = z + beta p (rounded to E) and the partials of pn . A pn; r -= alpha A p with A p
+// from the stored direction (r32 nullable); x += alpha_j p_j over a ring's pending
+// directions
+template <class E>
+void w_cg_pdir(const FineLevel& L, const E* z, const E* p, E* pn, const double* scal,
                double* partials, KTimer& kt);
-void w_cg_xring(const FineLevel& L, double* x, const float* ring, const double* scal,
+template <class E>
+void w_cg_xring(const FineLevel& L, double* x, const E* ring, const double* scal,
                 const RingSlots& rs, KTimer& kt);
-void w_cg_xr(const FineLevel& L, const float* p, double* r, float* r32, const double* scal,
+template <class E>
+void w_cg_xr(const FineLevel& L, const E* p, double* r, float* r32, const double* scal,
              double* partials, KTimer& kt);
 
 // ---- level 0: CG (fp64)
@@ -188,21 +199,24 @@ void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, 
               float* r32, hipStream_t s);
 // Direction update, the product by A and the partials of p . q in one pass, with the
 // q-recursion and an fp64 direction (z in the working precision); cg_xr then takes
-// r -= alpha q.  Or (cg_split: mixed precision on 16-byte lanes) fp32 directions in a ring
-// and no q: cg_pdir forms the next direction (p -> pn) with the partials of pn . A pn,
-// cg_xr_dir takes r -= alpha A p from the stored direction, and cg_xring adds the ring's
-// pending alpha_j p_j to x.
+// r -= alpha q (one node per lane).  Or (cg_ring: 16-byte lanes) directions in a ring, in
+// the working precision, and no q: cg_pdir forms the next direction (p -> pn) with the
+// partials of pn . A pn, cg_xr_dir takes r -= alpha A p from the stored direction, and
+// cg_xring adds the ring's pending alpha_j p_j to x.
 template <typename TZ>
 void cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
            double* partials, hipStream_t s);
-void cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, const double* scal,
+template <class E>
+void cg_pdir(const FineLevel& L, const E* z, const E* p, E* pn, const double* scal,
              double* partials, hipStream_t s);
-void cg_xring(const FineLevel& L, double* x, const float* ring, const double* scal,
+template <class E>
+void cg_xring(const FineLevel& L, double* x, const E* ring, const double* scal,
               const RingSlots& rs, hipStream_t s);
-bool cg_split(const FineLevel& L, bool mixed);
+bool cg_ring(const FineLevel& L);
 void cg_xr(const FineLevel& L, double* r, const double* q, const double* scal, double* partials,
            float* r32, hipStream_t s);
-void cg_xr_dir(const FineLevel& L, const float* p, double* r, float* r32, const double* scal,
+template <class E>
+void cg_xr_dir(const FineLevel& L, const E* p, double* r, float* r32, const double* scal,
                double* partials, hipStream_t s);
 // x += S_XA p: the update the last step still owes x
 template <typename TP>

@@ -379,14 +379,14 @@ struct saamg_state {
     double *x = nullptr, *r = nullptr, *q = nullptr, *bs = nullptr;
     float* r32 = nullptr;  // fp32 copy of r (mixed precision)
     void* z = nullptr;     // preconditioned residual (fp32 in mixed precision)
-    void* p = nullptr;     // direction (fp64; fp32 when split, then a slot of `ring`)
-    // split (cg_split): the last `ringk` fp32 directions, ring slot k % ringk holding step
-    // k's; x has received alpha_j p_j for all but the last `pend` of them.  q is then only
-    // the scratch of a final true residual.
-    float* ring = nullptr;
-    int ringk = 0, pend = 0;
+    void* p = nullptr;     // direction of the fused form (fp64)
+    // ring form (cg_ring): the last `ringk` directions in the working precision (`pw`
+    // bytes), ring slot k % ringk holding step k's; x has received alpha_j p_j for all but
+    // the last `pend` of them.  q is then only the scratch of a final true residual.
+    void* ring = nullptr;
+    int ringk = 0, pend = 0, pw = 8;
     long kdir = 0;  // directions formed so far in this solve
-    bool split = false;
+    bool ringf = false;
     VBuf<float> vf;
     VBuf<double> vd;
     double* part = nullptr;
@@ -409,10 +409,13 @@ namespace saamg {
 // saamg_set_operator gave it (the preconditioner then keeps the hierarchy's).
 static const FineLevel& cg_op(const saamg_hierarchy* H) { return H->op ? *H->op : H->l0; }
 
-// Ring slot of direction k (k = -1: the one the first step reads) of a split state.
-static int ring_index(const saamg_state* S, long k) { return (int)(((k % S->ringk) + S->ringk) % S->ringk); }
-static float* ring_slot(const saamg_state* S, long k) {
-    return S->ring + (long)ring_index(S, k) * S->H->l0.nbox;
+// Ring slot of direction k (k = -1: the one the first step reads) of a ring-form state.
+static int ring_index(const saamg_state* S, long k) {
+    return (int)(((k % S->ringk) + S->ringk) % S->ringk);
+}
+template <class E>
+static E* ring_at(const saamg_state* S, long k) {
+    return (E*)S->ring + (long)ring_index(S, k) * S->H->l0.nbox;
 }
 
 // x += alpha_j p_j for the ring's pending directions, in the order of their steps.
@@ -420,7 +423,10 @@ static void ring_flush(saamg_state* S) {
     RingSlots rs{};
     rs.m = S->pend;
     for (int j = 0; j < S->pend; ++j) rs.slot[j] = ring_index(S, S->kdir - S->pend + j);
-    cg_xring(cg_op(S->H), S->x, S->ring, S->scal, rs, S->s);
+    if (S->mixed)
+        cg_xring<float>(cg_op(S->H), S->x, (const float*)S->ring, S->scal, rs, S->s);
+    else
+        cg_xring<double>(cg_op(S->H), S->x, (const double*)S->ring, S->scal, rs, S->s);
     S->pend = 0;
 }
 
@@ -435,11 +441,12 @@ static void state_alloc(saamg_state* S, saamg_hierarchy* H, bool pinned = true) 
     const long n = H->l0.nbox;
     S->x = (double*)dmalloc(8 * n);
     S->r = (double*)dmalloc(8 * n);
-    S->split = cg_split(H->l0, S->mixed);
-    if (S->split) {
+    S->ringf = cg_ring(H->l0);
+    S->pw = S->mixed ? 4 : 8;
+    if (S->ringf) {
         // a state that allocates nothing keeps 2 directions (flushed every other step)
-        S->ringk = pinned ? kCgRing : 2;
-        S->ring = (float*)dmalloc(4L * S->ringk * n);
+        S->ringk = pinned ? cg_ring_len(n, S->pw) : 2;
+        S->ring = dmalloc((size_t)S->pw * S->ringk * n);
     } else {
         S->p = dmalloc(8 * n);
     }
@@ -448,7 +455,7 @@ static void state_alloc(saamg_state* S, saamg_hierarchy* H, bool pinned = true) 
     S->z = dmalloc((S->mixed ? 4 : 8) * n);
     if (S->mixed) S->r32 = (float*)dmalloc(4 * n);
     // x, r, q, b~ (fp64); p, z and the fp32 copy of r
-    S->bytes = 32L * n + (S->split ? 4L * S->ringk : 8) * n + 8L * n;  // z 8, or fp32 z and r32
+    S->bytes = 32L * n + (S->ringf ? (long)S->pw * S->ringk : 8) * n + 8L * n;  // z 8, or fp32 z and r32
     if (S->mixed) {
         S->vf.alloc(H);
         S->bytes += S->vf.bytes(H);
@@ -530,8 +537,9 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
     scal_start(S->scal, S->tol, S->s);
     S->kdir = 0;
     S->pend = 0;
-    if (S->split)  // the direction the first step reads (times beta = 0)
-        zero_fill(ring_slot(S, -1), 4 * H->l0.nbox, S->s);
+    if (S->ringf)  // the direction the first step reads (times beta = 0)
+        zero_fill((char*)S->ring + (size_t)S->pw * ring_index(S, -1) * H->l0.nbox,
+                  (size_t)S->pw * H->l0.nbox, S->s);
     else
         zero_fill(S->p, 8 * H->l0.nbox, S->s);
     zero_fill(S->q, 8 * H->l0.nbox, S->s);
@@ -569,24 +577,32 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
 static void state_enqueue(saamg_state* S) {
     const saamg_hierarchy* H = S->H;
     const FineLevel& L = cg_op(H);
-    if (S->split) {
+    if (S->ringf) {
         if (S->pend == S->ringk) ring_flush(S);  // the next direction overwrites the oldest
-        cg_pdir(L, (const float*)S->z, ring_slot(S, S->kdir - 1), ring_slot(S, S->kdir), S->scal,
-                S->part, S->s);
+        if (S->mixed)
+            cg_pdir<float>(L, (const float*)S->z, ring_at<float>(S, S->kdir - 1),
+                           ring_at<float>(S, S->kdir), S->scal, S->part, S->s);
+        else
+            cg_pdir<double>(L, (const double*)S->z, ring_at<double>(S, S->kdir - 1),
+                            ring_at<double>(S, S->kdir), S->scal, S->part, S->s);
     } else if (S->mixed)
         cg_pq<float>(L, (const float*)S->z, S->x, (double*)S->p, S->q, S->scal, S->part, S->s);
     else
         cg_pq<double>(L, (const double*)S->z, S->x, (double*)S->p, S->q, S->scal, S->part, S->s);
-    finalize(S->part, cg_pq_parts(L, S->split), 1, S->scal, FIN_ALPHA,
-             S->split ? S_AR0 + ring_index(S, S->kdir) : 0, S->s);
-    if (S->split) {
-        cg_xr_dir(L, ring_slot(S, S->kdir), S->r, S->r32, S->scal, S->part, S->s);
+    finalize(S->part, cg_pq_parts(L, S->ringf, S->pw), 1, S->scal, FIN_ALPHA,
+             S->ringf ? S_AR0 + ring_index(S, S->kdir) : 0, S->s);
+    if (S->ringf) {
+        if (S->mixed)
+            cg_xr_dir<float>(L, ring_at<float>(S, S->kdir), S->r, S->r32, S->scal, S->part, S->s);
+        else
+            cg_xr_dir<double>(L, ring_at<double>(S, S->kdir), S->r, nullptr, S->scal, S->part,
+                              S->s);
         S->kdir += 1;
         S->pend += 1;
     } else {
         cg_xr(L, S->r, S->q, S->scal, S->part, S->r32, S->s);
     }
-    finalize(S->part, cg_xr_parts(L, S->split), 1, S->scal, FIN_RR, 0, S->s);
+    finalize(S->part, cg_xr_parts(L, S->ringf, S->pw), 1, S->scal, FIN_RR, 0, S->s);
     HIPCHECK(hipMemcpyAsync(S->hscal, S->scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost,
                             S->s));
     if (S->ev) HIPCHECK(hipEventRecord(S->ev, S->s));
@@ -599,7 +615,7 @@ static void state_enqueue(saamg_state* S) {
 // direction update in the fused form), or the ring's pending directions.  Needed before x
 // is read.
 static void flush_x(saamg_state* S) {
-    if (S->split) {
+    if (S->ringf) {
         if (S->pend > 0) ring_flush(S);
         return;
     }
@@ -1674,9 +1690,11 @@ int saamg_footprint_bytes(int nx, int ny, int nz, int variant, int precision, in
         const bool mixed = precision == SAAMG_MIXED;
         const int na = variant == SAAMG_VARIANT_QUAD ? 27 : 14;
         double h = 8.0 * nbox + 20.0 * nbox / 64 + 0.2 * nbox * 12 * 16;  // sigma, masks, table
-        // x, r, q, b~, z, r32 and the direction (fp32 directions in a ring where mixed
-        // precision runs on 16-byte lanes)
-        double st = 48.0 * nbox + (mixed ? (l0_wide_default(nx) ? 4.0 * kCgRing : 4.0) : 8.0) * nbox;
+        double st = 48.0 * nbox + (mixed ? 4 : 8) * nbox;
+        if (l0_wide_default(nx)) {  // the ring of directions in place of the fp64 direction
+            const int pw = mixed ? 4 : 8;
+            st += (double)(pw * cg_ring_len((long)nbox, pw) - 8) * nbox;
+        }
         double w = mixed ? 4 : 8;
         st += 3 * w * nbox + w * nbox / 3;  // level-0 V-cycle vectors and restriction sums
         double m = nbox;

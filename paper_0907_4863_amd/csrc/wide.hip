@@ -87,35 +87,36 @@ struct XArr {
     __device__ __forceinline__ E val1(E r) const { return r; }
 };
 
-// XDir: the next CG direction of mixed precision, fl32(z + beta p), formed from the
-// preconditioned residual z and the previous direction p (both fp32).  It is zero where
-// z and p are.
+// XDir: the next CG direction z + beta p (rounded to E), formed from the preconditioned
+// residual z and the previous direction p, both in E (fp32 in mixed precision).  It is
+// zero where z and p are.
+template <class E>
 struct XDir {
-    using type = float;
+    using type = E;
     template <int N>
     struct raw {
-        Vec<float, N> z, p;
+        Vec<E, N> z, p;
     };
     struct raw1 {
-        float z, p;
+        E z, p;
     };
-    const float* z;
-    const float* p;
+    const E* z;
+    const E* p;
     double beta;
-    __device__ __forceinline__ float dir(float zz, float pp) const {
-        return (float)__builtin_fma(beta, (double)pp, (double)zz);
+    __device__ __forceinline__ E dir(E zz, E pp) const {
+        return (E)__builtin_fma(beta, (double)pp, (double)zz);
     }
     template <int N>
     __device__ __forceinline__ raw<N> ld(Idx k) const { return raw<N>{vld<N>(z, k), vld<N>(p, k)}; }
     __device__ __forceinline__ raw1 ld1(Idx k) const { return raw1{at(z, k), at(p, k)}; }
     template <int N>
-    __device__ __forceinline__ Vec<float, N> val(const raw<N>& r) const {
-        Vec<float, N> o;
+    __device__ __forceinline__ Vec<E, N> val(const raw<N>& r) const {
+        Vec<E, N> o;
 #pragma unroll
         for (int e = 0; e < N; ++e) o.v[e] = dir(r.z.v[e], r.p.v[e]);
         return o;
     }
-    __device__ __forceinline__ float val1(const raw1& r) const { return dir(r.z, r.p); }
+    __device__ __forceinline__ E val1(const raw1& r) const { return dir(r.z, r.p); }
 };
 
 // Loads of one plane of a wavefront's row (the 16-byte-lane counterpart of PlaneLoads).
@@ -848,83 +849,36 @@ void w_cg_resid(const FineLevel& L, const double* bs, const double* x, double* r
     HIPCHECK(hipGetLastError());
 }
 
-// Direction update with the product by A carried along (see k_cg_pq): p <- z + beta p,
-// q <- A z + beta q, x += alpha_prev p_old; partials of p . q.
-template <typename TZ>
-__global__ void __launch_bounds__(kMThreads) k_w_cg_pq(L0View<double> v, const TZ* __restrict__ zv,
-                                                      double* __restrict__ xv,
-                                                      double* __restrict__ p, double* __restrict__ q,
-                                                      const double* __restrict__ scal, double* part) {
-    constexpr int N = 2;
-    __shared__ double lds[kMThreads / kWave];
-    const double beta = scal[S_BETA];
-    const double xa = scal[S_XA];
-    double acc = 0.0;
-    struct R {
-        Vec<double, N> p, q, x;
-    };
-    wmarch<double, N, true, false, kFullRows<TZ>>(
-        v, zv,
-        [&](Idx i, int, int, int, unsigned, int) { return R{vld<N>(p, i), vld<N>(q, i), vld<N>(xv, i)}; },
-        [&](Idx i, const R& f, const Vec<double, N>& z, const Vec<double, N>& az, int, int, int,
-            unsigned nib) {
-            double po[N], qo[N], xo[N];
-#pragma unroll
-            for (int e = 0; e < N; ++e) {
-                const bool u = (nib >> e) & 1u;
-                po[e] = u ? z.v[e] + beta * f.p.v[e] : 0.0;
-                qo[e] = u ? az.v[e] + beta * f.q.v[e] : 0.0;
-                xo[e] = u ? f.x.v[e] + xa * f.p.v[e] : 0.0;
-                acc += po[e] * qo[e];
-            }
-            vstnt<N>(xv, i, xo);
-            vstnt<N>(p, i, po);
-            vstnt<N>(q, i, qo);
-        });
-    const double sb = block_sum(acc, lds);
-    if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
-}
-
-template <typename TZ>
-void w_cg_pq(const FineLevel& L, const TZ* z, double* x, double* p, double* q, const double* scal,
-             double* partials, KTimer& kt_) {
-    klaunch(kt_, true, (k_w_cg_pq<TZ>), wgrid<double>(L), dim3(kWave, kMY), wview<double>(L, 2),
-            z, x, p, q, scal, partials);
-    HIPCHECK(hipGetLastError());
-}
-template void w_cg_pq<double>(const FineLevel&, const double*, double*, double*, double*,
-                              const double*, double*, KTimer&);
-
-// Mixed precision's CG step in two passes that share no q = A p vector (N nodes per lane;
-// the launchers take N and the first pass's arithmetic TA from kCgDirLanes, kCgXrLanes
-// and CgDirArith).  The directions live in a ring of kCgRing fp32 buffers.  The first pass
-// forms the new direction p_new = fl32(z + beta p_old) in the next ring buffer, with
-// p_new . A p_new: p_new at the neighbour lines and planes is formed from z and p_old as
-// the march reads them (XDir), so A p_new costs no pass of its own; neighbouring blocks
-// still read p_old where this block has stored p_new, hence two buffers.  The second
-// recomputes A p in fp64 from the stored fp32 direction for r -= alpha A p.  x is not
-// touched: it receives alpha_j p_j for the directions of the ring in one pass
-// (k_cg_xring) every kCgRing steps and before anything reads it.  Per unknown: z 4,
-// p_old 4 read, p_new 4 written; then p 4, r 8 read, r 8, r32 4 written; and x 16 plus
-// 4 per direction once per kCgRing steps.
-template <typename TA, int N>
-__global__ void __launch_bounds__(kMThreads) k_w_cg_pdir(L0View<TA> v, const float* __restrict__ zv,
-                                                        const float* __restrict__ p,
-                                                        float* __restrict__ pn,
+// The CG step on 16-byte lanes, in two passes that share no q = A p vector (N nodes per
+// lane and the first pass's arithmetic TA per precision: cg_dir_lanes, CgDirArith).  The
+// directions (in E: fp32 in mixed precision, else fp64) live in a ring of buffers.  The
+// first pass forms the new direction p_new = z + beta p_old (rounded to E) in the next
+// ring buffer, with p_new . A p_new: p_new at the neighbour lines and planes is formed
+// from z and p_old as the march reads them (XDir), so A p_new costs no pass of its own;
+// neighbouring blocks still read p_old where this block has stored p_new, hence separate
+// buffers.  The second recomputes A p in fp64 from the stored direction for
+// r -= alpha A p.  x is not touched: it receives alpha_j p_j for the ring's directions in
+// one pass (k_cg_xring) when the ring is full and before anything reads it.  Per unknown
+// (w = size of E): z w, p_old w read, p_new w written; then p w, r 8 read, r 8 (and r32 4)
+// written; and x 16 plus w per direction once per ring.
+template <typename TA, int N, class E>
+__global__ void __launch_bounds__(kMThreads) k_w_cg_pdir(L0View<TA> v, const E* __restrict__ zv,
+                                                        const E* __restrict__ p,
+                                                        E* __restrict__ pn,
                                                         const double* __restrict__ scal,
                                                         double* part) {
     __shared__ double lds[kMThreads / kWave];
     const double beta = scal[S_BETA];
     double acc = 0.0;
     wmarch_x<TA, N, true, false, true>(
-        v, XDir{zv, p, beta}, WNOFETCH,
+        v, XDir<E>{zv, p, beta}, WNOFETCH,
         [&](Idx i, NoVals, const Vec<TA, N>& pv, const Vec<TA, N>& ap, int, int, int,
             unsigned nib) {
-            float po[N];
+            E po[N];
 #pragma unroll
             for (int e = 0; e < N; ++e) {
                 const bool u = (nib >> e) & 1u;
-                po[e] = u ? (float)pv.v[e] : 0.0f;
+                po[e] = u ? (E)pv.v[e] : E(0);
                 acc += u ? (double)pv.v[e] * (double)ap.v[e] : 0.0;
             }
             vstnt<N>(pn, i, po);
@@ -937,14 +891,15 @@ __global__ void __launch_bounds__(kMThreads) k_w_cg_pdir(L0View<TA> v, const flo
 // (one fused multiply-add per direction and node, as an update per step would take).  A
 // plain stream over the box, 4 nodes per thread: the directions and x are zero at the
 // nodes that are not unknowns, and so is every alpha_j p_j there.
+template <class E>
 __global__ void __launch_bounds__(256) k_cg_xring(long n4, double* __restrict__ x,
-                                                 const float* __restrict__ ring, long stride,
+                                                 const E* __restrict__ ring, long stride,
                                                  const double* __restrict__ scal, RingSlots rs) {
     double a[kCgRing];
 #pragma unroll
     for (int j = 0; j < kCgRing; ++j) a[j] = j < rs.m ? scal[S_AR0 + rs.slot[j]] : 0.0;
-    using F4 = ExtVec<float, 4>::type;
     using D2 = ExtVec<double, 2>::type;
+    using P2 = typename ExtVec<E, 2>::type;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
          i += (long)gridDim.x * blockDim.x) {
         D2* xp = reinterpret_cast<D2*>(x + 4 * i);
@@ -952,12 +907,21 @@ __global__ void __launch_bounds__(256) k_cg_xring(long n4, double* __restrict__ 
 #pragma unroll
         for (int j = 0; j < kCgRing; ++j) {
             if (j < rs.m) {
-                const F4 pj = __builtin_nontemporal_load(
-                    reinterpret_cast<const F4*>(ring + rs.slot[j] * stride + 4 * i));
-                lo[0] = __builtin_fma(a[j], (double)pj[0], lo[0]);
-                lo[1] = __builtin_fma(a[j], (double)pj[1], lo[1]);
-                hi[0] = __builtin_fma(a[j], (double)pj[2], hi[0]);
-                hi[1] = __builtin_fma(a[j], (double)pj[3], hi[1]);
+                const E* pj = ring + rs.slot[j] * stride + 4 * i;
+                E q[4];
+                if constexpr (sizeof(E) == 4) {
+                    using F4 = ExtVec<float, 4>::type;
+                    const F4 t = __builtin_nontemporal_load(reinterpret_cast<const F4*>(pj));
+                    q[0] = t[0]; q[1] = t[1]; q[2] = t[2]; q[3] = t[3];
+                } else {
+                    const P2 t0 = __builtin_nontemporal_load(reinterpret_cast<const P2*>(pj));
+                    const P2 t1 = __builtin_nontemporal_load(reinterpret_cast<const P2*>(pj) + 1);
+                    q[0] = t0[0]; q[1] = t0[1]; q[2] = t1[0]; q[3] = t1[1];
+                }
+                lo[0] = __builtin_fma(a[j], (double)q[0], lo[0]);
+                lo[1] = __builtin_fma(a[j], (double)q[1], lo[1]);
+                hi[0] = __builtin_fma(a[j], (double)q[2], hi[0]);
+                hi[1] = __builtin_fma(a[j], (double)q[3], hi[1]);
             }
         }
         __builtin_nontemporal_store(lo, xp);
@@ -966,9 +930,10 @@ __global__ void __launch_bounds__(256) k_cg_xring(long n4, double* __restrict__ 
 }
 
 // r -= alpha A p (alpha = S_XA; r left as it is when the step broke down), its fp32 copy
-// and partials of r . r.  Whole rows are stored (zero at the nodes that are not unknowns).
-template <int N>
-__global__ void __launch_bounds__(kMThreads) k_w_cg_xr(L0View<double> v, const float* __restrict__ p,
+// (mixed precision) and partials of r . r.  Whole rows are stored (zero at the nodes that
+// are not unknowns).
+template <int N, class E>
+__global__ void __launch_bounds__(kMThreads) k_w_cg_xr(L0View<double> v, const E* __restrict__ p,
                                                       double* __restrict__ r,
                                                       float* __restrict__ r32,
                                                       const double* __restrict__ scal,
@@ -994,35 +959,52 @@ __global__ void __launch_bounds__(kMThreads) k_w_cg_xr(L0View<double> v, const f
             }
             if (ok) {
                 vstnt<N>(r, i, ro);
-                vstnt<N>(r32, i, r3);
+                if (r32) vstnt<N>(r32, i, r3);
             }
         });
     const double sb = block_sum(acc, lds);
     if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = sb;
 }
 
-void w_cg_pdir(const FineLevel& L, const float* z, const float* p, float* pn, const double* scal,
+template <class E>
+void w_cg_pdir(const FineLevel& L, const E* z, const E* p, E* pn, const double* scal,
                double* partials, KTimer& kt_) {
-    klaunch(kt_, true, (k_w_cg_pdir<CgDirArith, kCgDirLanes>),
-            dim3((unsigned)l0_wblocks(L, kCgDirLanes)), dim3(kWave, kMY),
-            wview<CgDirArith>(L, kCgDirLanes), z, p, pn, scal, partials);
+    using TA = std::conditional_t<sizeof(E) == 4, CgDirArith, double>;
+    constexpr int n = cg_dir_lanes((int)sizeof(E));
+    klaunch(kt_, true, (k_w_cg_pdir<TA, n, E>), dim3((unsigned)l0_wblocks(L, n)), dim3(kWave, kMY),
+            wview<TA>(L, n), z, p, pn, scal, partials);
     HIPCHECK(hipGetLastError());
 }
+template void w_cg_pdir<float>(const FineLevel&, const float*, const float*, float*, const double*,
+                               double*, KTimer&);
+template void w_cg_pdir<double>(const FineLevel&, const double*, const double*, double*,
+                                const double*, double*, KTimer&);
 
-void w_cg_xring(const FineLevel& L, double* x, const float* ring, const double* scal,
+template <class E>
+void w_cg_xring(const FineLevel& L, double* x, const E* ring, const double* scal,
                 const RingSlots& rs, KTimer& kt_) {
     const long n4 = L.nbox / 4;
     const long blocks = std::min<long>((n4 + 255) / 256, 8L * 1024);
-    klaunch(kt_, true, k_cg_xring, dim3((unsigned)std::max<long>(blocks, 1)), dim3(256), n4, x,
+    klaunch(kt_, true, k_cg_xring<E>, dim3((unsigned)std::max<long>(blocks, 1)), dim3(256), n4, x,
             ring, L.nbox, scal, rs);
     HIPCHECK(hipGetLastError());
 }
+template void w_cg_xring<float>(const FineLevel&, double*, const float*, const double*,
+                                const RingSlots&, KTimer&);
+template void w_cg_xring<double>(const FineLevel&, double*, const double*, const double*,
+                                 const RingSlots&, KTimer&);
 
-void w_cg_xr(const FineLevel& L, const float* p, double* r, float* r32, const double* scal,
+template <class E>
+void w_cg_xr(const FineLevel& L, const E* p, double* r, float* r32, const double* scal,
              double* partials, KTimer& kt_) {
-    klaunch(kt_, true, k_w_cg_xr<kCgXrLanes>, dim3((unsigned)l0_wblocks(L, kCgXrLanes)),
-            dim3(kWave, kMY), wview<double>(L, kCgXrLanes), p, r, r32, scal, partials);
+    constexpr int n = cg_xr_lanes((int)sizeof(E));
+    klaunch(kt_, true, (k_w_cg_xr<n, E>), dim3((unsigned)l0_wblocks(L, n)), dim3(kWave, kMY),
+            wview<double>(L, n), p, r, r32, scal, partials);
     HIPCHECK(hipGetLastError());
 }
+template void w_cg_xr<float>(const FineLevel&, const float*, double*, float*, const double*,
+                             double*, KTimer&);
+template void w_cg_xr<double>(const FineLevel&, const double*, double*, float*, const double*,
+                              double*, KTimer&);
 
 }  // namespace saamg
