@@ -241,26 +241,30 @@ def test_solve_mixed_matches_tight_oracle(name, wide):
     assert err <= 1e-6
 
 
+@pytest.mark.parametrize("precision", [W.PREC_MIXED, W.PREC_FP64])
 @pytest.mark.parametrize("wide", [0, 2])
-def test_mixed_solve_stopped_early(wide):
-    """A mixed-precision solve stopped by max_iter (NOT_CONVERGED) after k steps, on both CG
-    forms: the fused one (one node per lane) and the fp32 direction in two buffers (16-byte
-    lanes), where the final true residual takes q's memory after the last x += alpha p.
-    The returned x carries that last update: the reported true residual, which the oracle
-    recomputes from x, agrees with the recursive one (a missing alpha p would leave a
-    residual of the previous step's size), and a restart from x converges to the oracle's
-    solution."""
-    c = case("ell68_quad", W.PREC_MIXED, wide=wide)
+def test_solve_stopped_early(wide, precision):
+    """A solve stopped by max_iter (NOT_CONVERGED) after k steps, on both CG forms: the
+    fused one (one node per lane, x updated by the next step) and the ring of directions
+    (16-byte lanes, x updated from the ring when it is full and before x is read).  The
+    returned x carries every step: the reported true residual, which the oracle recomputes
+    from x, agrees with the recursive one (a missing alpha p would leave a residual of an
+    earlier step's size), and a restart from x converges to the oracle's solution."""
+    c = case("ell68_quad", precision, wide=wide)
     xref = operator.unscale(c.sys, solve.solve(c.sys, c.H, c.b, tol=1e-13).x)
-    for k in (1, 2, 5):
-        xk, rk = gpu_solve(c, c.b, max_iter=k)
+    # k = 20 > 16 directions: the ring is flushed once mid-solve (at a tolerance the solve
+    # cannot reach, so it still stops by max_iter); its residual is deep, so the two
+    # residuals and the oracle's are compared more loosely there
+    for k, tol in ((1, 1e-8), (2, 1e-8), (5, 1e-8), (20, 1e-15)):
+        xk, rk = gpu_solve(c, c.b, tol=tol, max_iter=k)
         r, bn = operator.scaled_residual(c.sys.dom, c.variant, xk, c.b)
         rel_o = np.linalg.norm(r) / bn
-        print(f"[stop {k} wide={wide}] true={rk['rel_res_true']:.6e} recursive="
+        print(f"[stop {k} wide={wide} prec={precision}] true={rk['rel_res_true']:.6e} recursive="
               f"{rk['rel_res_recursive']:.6e} oracle={rel_o:.6e}", flush=True)
         assert rk["status"] == sa.capi.NOT_CONVERGED and rk["iterations"] == k
-        assert abs(rk["rel_res_true"] - rk["rel_res_recursive"]) <= 1e-6 * rk["rel_res_true"]
-        assert abs(rel_o - rk["rel_res_true"]) <= 1e-7 * rel_o
+        loose = k > 10
+        assert abs(rk["rel_res_true"] - rk["rel_res_recursive"]) <= (1e-3 if loose else 1e-6) * rk["rel_res_true"]
+        assert abs(rel_o - rk["rel_res_true"]) <= (1e-4 if loose else 1e-7) * rel_o
         assert np.all(xk[~c.sys.dom.mask] == 0)
         x2, r2 = gpu_solve(c, c.b, x0=xk)
         assert r2["status"] == 0 and r2["rel_res_true"] <= 1e-8
