@@ -655,12 +655,13 @@ __global__ void __launch_bounds__(kMThreads) k_w_restrict_y(L0View<T> v, const T
 
 template <typename T>
 bool w_restrict_y(const FineLevel& L, const T* r, T* y, double omega, KTimer& kt_) {
-    // z-slabs of a multiple of 3 planes, so that no aggregate layer is split between tiles,
-    // half again as long as the other kernels' (the per-tile preload allows up to 64 / N - 2
-    // planes): 12 planes measured 80.6 us against 84.1 us for 6 on the 256 x 256 x 768
-    // ellipse in fp32
+    // z-slabs of a multiple of 3 planes, so that no aggregate layer is split between tiles;
+    // in fp32 half again as long as the other kernels' (the per-tile preload allows up to
+    // 64 / N - 2 planes): on the 256 x 256 x 768 ellipse 12 planes took 80.6 us against 84.1
+    // for 6, while fp64 took 133.5 us with 24 planes against 130.1 with 15
     L0View<T> v = wview<T>(L, kLanes<T>);
-    v.zb = std::max(3, std::min((kWave / kLanes<T> - 2) / 3 * 3, (3 * v.zb / 2) / 3 * 3));
+    const int zr = sizeof(T) == 4 ? 3 * v.zb / 2 : v.zb;
+    v.zb = std::max(3, std::min((kWave / kLanes<T> - 2) / 3 * 3, zr / 3 * 3));
     const long blocks = (long)v.gx * v.gy * ((L.nz + v.zb - 1) / v.zb);
     const bool fold = L.nx <= kWave * kLanes<T>;
     if (fold)
