@@ -252,8 +252,9 @@ int saamg_solve(saamg_hierarchy* H, const double* d_b, const double* d_x0, doubl
 
 /*
  * saamg_solve for callers that cannot allocate device memory (code under HIP graph
- * capture, tight serving loops, harnesses that forbid hipMalloc): the same solve, the same
- * kernels in the same order and the same results, with every work vector (PCG vectors,
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same solve and the
+ * same results (on 16-byte-lane hierarchies x takes the CG directions from a ring of 2
+ * instead of up to 16, the same updates in the same order), with every work vector (PCG vectors,
  * the V-cycle's vectors on all levels, block partials, scalars) carved out of a static
  * 64 MiB device array inside the library instead of allocated.  No hipMalloc, hipFree,
  * pinned host allocation, event creation or allocator callback happens in the call; the
