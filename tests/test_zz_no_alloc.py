@@ -1,8 +1,8 @@
 """GPU: saamg_solve_noalloc, whose work vectors live in the library's static scratch array,
 against saamg_solve on the same hierarchies, through the C interface.
 
-Two calls in a row, the second on a smaller problem (the array keeps the first call's
-contents, which must not leak into the second), in fp64 and mixed precision; the output
+Calls in a row on smaller and smaller problems (the array keeps the previous call's
+contents, which must not leak into the next), in fp64 and mixed precision; the output
 must match saamg_solve's to the parity bar (1e-8 fp64, 1e-6 mixed) with the same
 iteration count (the kernels and their order are the same, so it is expected bitwise),
 and the call must not go through the allocator.  A warm start is checked the same way,
@@ -18,8 +18,10 @@ sa = pytest.importorskip("paper_0907_4863_amd")
 
 pytestmark = pytest.mark.gpu
 
-# larger first, then smaller
-CASES = [("ell70_quad", W.Shape.ellipse(1.0, 0.6, 4.0), 70, 45, 66, W.VARIANT_QUAD),
+# larger first, then smaller; the first on 16-byte lanes (nx a multiple of 4 above 128), where
+# the allocation-free solve keeps 2 CG directions in its ring against up to 16
+CASES = [("ell132_quad", W.Shape.ellipse(1.0, 0.6, 4.0), 132, 45, 40, W.VARIANT_QUAD),
+         ("ell70_quad", W.Shape.ellipse(1.0, 0.6, 4.0), 70, 45, 66, W.VARIANT_QUAD),
          ("cyl33_lin", W.Shape.cylinder(1.0, 2.0), 33, 33, 33, W.VARIANT_LIN)]
 
 
