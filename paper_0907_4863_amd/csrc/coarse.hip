@@ -635,10 +635,31 @@ __device__ inline L0Slot l0_slot(const L0View<double>& v, int x, int y, int z) {
 }
 
 struct AccL0 {
+    // k_rap reads the patch's rows through codes computed once per node (kCache)
+    static constexpr bool kCache = true;
     L0View<double> v;
     __device__ bool inbox(int x, int y, int z) const {
         return x >= 0 && y >= 0 && z >= 0 && x < v.nx && y < v.ny && z < v.nz;
     }
+    // -1: not an unknown (or outside the box), -2: the interior row, else its table slot
+    __device__ int code(int x, int y, int z) const {
+        if (!inbox(x, y, z)) return -1;
+        const L0Slot n = l0_slot(v, x, y, z);
+        return !n.unk ? -1 : (n.irr ? n.rank : -2);
+    }
+    // the rows of rows() from a node's code
+    __device__ void rows_code(int c, double* a, double* at, bool* unk) const {
+        for (int k = 0; k < 27; ++k) a[k] = at[k] = 0.0;
+        *unk = c != -1;
+        if (c == -1) return;
+        a[13] = at[13] = 1.0;
+        for (int d = 0; d < 6; ++d) {
+            const int k = dir_to_k(d);
+            a[k] = c >= 0 ? v.tcoef(d, c) : v.c[d >> 1];
+            at[k] = c >= 0 ? v.tcoefT(d, c) : v.c[d >> 1];
+        }
+    }
+    __device__ double invd_code(int c) const { return c != -1 ? 1.0 : 0.0; }
     // 7-point rows: entries k = 13 and the six direction slots, zero elsewhere
     __device__ void rows(int x, int y, int z, double* a, double* at, bool* unk) const {
         for (int k = 0; k < 27; ++k) a[k] = at[k] = 0.0;
@@ -661,7 +682,11 @@ struct AccL0 {
 };
 
 struct AccLC {
+    static constexpr bool kCache = false;
     LCView<double> c;
+    __device__ int code(int, int, int) const { return 0; }
+    __device__ void rows_code(int, double*, double*, bool*) const {}
+    __device__ double invd_code(int) const { return 0.0; }
     __device__ bool inbox(int x, int y, int z) const {
         return x >= 0 && y >= 0 && z >= 0 && x < c.mx && y < c.my && z < c.mz;
     }
@@ -695,6 +720,7 @@ template <class Acc>
 __global__ void __launch_bounds__(256) k_rap(Acc acc, int fmx, int fmy, int fmz, LCView<double> cc,
                                              CoefOut out, double omega) {
     __shared__ double sv[125], sw[343], sy[729];
+    __shared__ int sc[Acc::kCache ? 729 : 1];  // codes of the patch's nodes (Acc::kCache)
     const int X = blockIdx.x, Y = blockIdx.y, Z = blockIdx.z;
     const int t = threadIdx.x;
     // patch position p (0..8 per axis) -> fine logical 3J - 3 + p
@@ -709,6 +735,23 @@ __global__ void __launch_bounds__(256) k_rap(Acc acc, int fmx, int fmy, int fmz,
         has = unk ? 1 : 0;
     }
     if (!__syncthreads_or(has)) return;
+    // every node the phases below evaluate lies in the 9^3 patch
+    if constexpr (Acc::kCache) {
+        for (int q = t; q < 729; q += blockDim.x) sc[q] = acc.code(ox + q % 9, oy + (q / 9) % 9, oz + q / 81);
+        __syncthreads();
+    }
+    auto rows_at = [&](int px, int py, int pz, double* ra, double* rat, bool* ru) {
+        if constexpr (Acc::kCache)
+            acc.rows_code(sc[px + 9 * py + 81 * pz], ra, rat, ru);
+        else
+            acc.rows(ox + px, oy + py, oz + pz, ra, rat, ru);
+    };
+    auto invd_at = [&](int px, int py, int pz) {
+        if constexpr (Acc::kCache)
+            return acc.invd_code(sc[px + 9 * py + 81 * pz]);
+        else
+            return acc.invd(ox + px, oy + py, oz + pz);
+    };
 
     auto in_block = [](int px, int py, int pz) {
         return px >= 3 && px < 6 && py >= 3 && py < 6 && pz >= 3 && pz < 6;
@@ -716,20 +759,20 @@ __global__ void __launch_bounds__(256) k_rap(Acc acc, int fmx, int fmy, int fmz,
     // phase 1: v on [2,7)^3
     for (int q = t; q < 125; q += blockDim.x) {
         const int px = 2 + q % 5, py = 2 + (q / 5) % 5, pz = 2 + q / 25;
-        acc.rows(ox + px, oy + py, oz + pz, a, at, &unk);
+        rows_at(px, py, pz, a, at, &unk);
         double s = 0.0;
         for (int k = 0; k < 27; ++k) {
             const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
             if (in_block(px + dx, py + dy, pz + dz)) s += a[k];
         }
         const double u = (unk && in_block(px, py, pz)) ? 1.0 : 0.0;
-        sv[q] = u - omega * acc.invd(ox + px, oy + py, oz + pz) * s;
+        sv[q] = u - omega * invd_at(px, py, pz) * s;
     }
     __syncthreads();
     // phase 2: t = A v on [1,8)^3
     for (int q = t; q < 343; q += blockDim.x) {
         const int px = 1 + q % 7, py = 1 + (q / 7) % 7, pz = 1 + q / 49;
-        acc.rows(ox + px, oy + py, oz + pz, a, at, &unk);
+        rows_at(px, py, pz, a, at, &unk);
         double s = 0.0;
         for (int k = 0; k < 27; ++k) {
             const int qx = px + k % 3 - 1 - 2, qy = py + (k / 3) % 3 - 1 - 2, qz = pz + k / 9 - 1 - 2;
@@ -742,7 +785,7 @@ __global__ void __launch_bounds__(256) k_rap(Acc acc, int fmx, int fmy, int fmz,
     // phase 3: y = t - w A^T D^-1 t on [0,9)^3 (zero at nodes that are not unknowns)
     for (int q = t; q < 729; q += blockDim.x) {
         const int px = q % 9, py = (q / 9) % 9, pz = q / 81;
-        acc.rows(ox + px, oy + py, oz + pz, a, at, &unk);
+        rows_at(px, py, pz, a, at, &unk);
         double yv = 0.0;
         if (unk) {
             double s = 0.0;
@@ -750,8 +793,7 @@ __global__ void __launch_bounds__(256) k_rap(Acc acc, int fmx, int fmy, int fmz,
                 const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
                 const int qx = px + dx - 1, qy = py + dy - 1, qz = pz + dz - 1;
                 if (qx >= 0 && qx < 7 && qy >= 0 && qy < 7 && qz >= 0 && qz < 7 && at[k] != 0.0)
-                    s += at[k] * acc.invd(ox + px + dx, oy + py + dy, oz + pz + dz) *
-                         sw[qx + 7 * qy + 49 * qz];
+                    s += at[k] * invd_at(px + dx, py + dy, pz + dz) * sw[qx + 7 * qy + 49 * qz];
             }
             const bool inw = px >= 1 && px < 8 && py >= 1 && py < 8 && pz >= 1 && pz < 8;
             const double tv = inw ? sw[(px - 1) + 7 * (py - 1) + 49 * (pz - 1)] : 0.0;
