@@ -372,6 +372,14 @@ int saamg_operator_apply(saamg_hierarchy* H, const double* d_x, double* d_y, voi
 /* D^-1/2 as a device box vector (0 at non-unknowns), fp64. */
 int saamg_scaling(saamg_hierarchy* H, double* d_sigma, void* stream);
 
+/* The explicit inverse of the coarsest operator held by the direct coarse level solver
+ * (Section 3.2, coarse level solver: the coarsest system is solved exactly).  *n_out
+ * receives its order n.  h_rows (nullable, host, n int64): the logical box index
+ * x + mx (y + my z) on the coarsest level of each row (and column), ascending.  h_inv
+ * (nullable, host, n * n fp64): the inverse, row-major.  Synchronous.  Errors:
+ * SAAMG_INVALID_ARG when H uses Gauss-Seidel sweeps as its coarse solver (no inverse). */
+int saamg_coarse_inverse(saamg_hierarchy* H, int32_t* n_out, int64_t* h_rows, double* h_inv);
+
 /* ---- particle coupling (Section 1 and Section 4: charge to the grid, field back) -------
  * A grid is the box of a discrete domain (nx, ny, nz), the box plane of the lattice's
  * plane 0 (1 with open ends, else 0), the coordinates of lattice node (0, 0, 0), the

@@ -11,5 +11,6 @@ from .capi import (  # noqa: F401
     domain_from_shape, footprint_bytes, hierarchy_info, level_apply, level_coefficients,
     operator_apply, pic_create, pic_deposit, pic_destroy, pic_gather, precond_apply, refresh,
     set_operator,
-    scaling, setup, solve, solve_noalloc, state_create, state_destroy, state_finish, state_query,
+    coarse_inverse, scaling, setup, solve, solve_noalloc, state_create, state_destroy,
+    state_finish, state_query,
 )

@@ -129,6 +129,7 @@ def lib() -> C.CDLL:
     L.saamg_precond_apply.argtypes = [_P, _P, _P, _P]
     L.saamg_operator_apply.argtypes = [_P, _P, _P, _P]
     L.saamg_scaling.argtypes = [_P, _P, _P]
+    L.saamg_coarse_inverse.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), _DP]
     L.saamg_timer_enable.argtypes = [C.c_int, C.c_int]
     L.saamg_timer_read.argtypes = [C.c_int, _DP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     _lib = L
@@ -548,6 +549,17 @@ def operator_apply(H: Hierarchy, x, y, stream=None) -> None:
 
 def scaling(H: Hierarchy, sigma, stream=None) -> None:
     _check(lib().saamg_scaling(H.handle, _dptr(sigma, H.nbox), _stream(stream)))
+
+
+def coarse_inverse(H: Hierarchy) -> Tuple[np.ndarray, np.ndarray]:
+    """(logical indices of the coarsest level's unknowns, their explicit inverse n x n)."""
+    n = C.c_int32(0)
+    _check(lib().saamg_coarse_inverse(H.handle, C.byref(n), None, None))
+    rows = np.zeros(n.value, dtype=np.int64)
+    inv = np.zeros((n.value, n.value), dtype=np.float64)
+    _check(lib().saamg_coarse_inverse(H.handle, C.byref(n), rows.ctypes.data_as(C.POINTER(C.c_int64)),
+                                      inv.ctypes.data_as(_DP)))
+    return rows, inv
 
 
 # --------------------------------------------------------------------------- timing

@@ -1159,105 +1159,134 @@ void dense_from_lc(const CoarseLevel& C, const long* cidx, const int32_t* cmap, 
 //   A_Kj <- P A_Kj (j outside K),  A_ij <- A_ij - A_iK A_Kj (new)  and  A_iK <- -A_iK P
 //   (i outside K),  A_KK <- P,
 // which is kb single-pivot steps applied at once.  Two launches per block: the first
-// inverts A_KK in LDS (every workgroup, the same arithmetic), forms the block row and
-// saves the old block column; the second does the rank-kb update.
+// inverts A_KK in LDS (every workgroup, the same arithmetic), forms the block row on the
+// matrix cores and saves the old block column; the second does the rank-kb update on the
+// matrix cores.
 constexpr int kGjB = 32;
 
-// Unpivoted Gauss-Jordan inverse of the kb x kb matrix M in LDS, in place (256 threads).
-__device__ void lds_gj_invert(double (*M)[kGjB + 1], int kb) {
-    for (int p = 0; p < kb; ++p) {
-        __syncthreads();
-        const double piv = 1.0 / M[p][p];
-        double v[4];
-        for (int q = 0; q < 4; ++q) {
-            const int e = threadIdx.x + 256 * q;
-            const int r = e / kGjB, c = e % kGjB;
-            v[q] = 0.0;
-            if (r < kb && c < kb) {
-                const double pc = M[p][c] * piv;  // scaled pivot row (rounded before use)
-                if (r == p)
-                    v[q] = (c == p) ? piv : pc;
-                else
-                    v[q] = (c == p) ? -M[r][p] * piv : M[r][c] - M[r][p] * pc;
-            }
-        }
-        __syncthreads();
-        for (int q = 0; q < 4; ++q) {
-            const int e = threadIdx.x + 256 * q;
-            const int r = e / kGjB, c = e % kGjB;
-            if (r < kb && c < kb) M[r][c] = v[q];
-        }
+typedef double gj_d4 __attribute__((ext_vector_type(4)));
+
+// Block step, part 1 (1024 threads).  Every workgroup inverts A_KK in LDS, one thread per
+// element of the kGjB x kGjB block and one barrier per pivot (the block is double-buffered:
+// pivot p reads buffer p % 2 and writes the other); entries past kb stay zero.  Then:
+//  * wavefront w forms the block row P A_Kj for the 16 columns j0 = 256 g + 16 w (outside
+//    the block) on the matrix cores, as two 16 x 16 tiles of kGjB / 4 steps each;
+//  * rows i = 256 g + t / 4 (outside the block) copy their old block-column entries to C
+//    (n x kGjB, 8 per thread, zero past kb);
+//  * workgroup 0 stores P (kGjB x kGjB, zero past kb).
+// Every global load is issued before the inversion.  Matrix-core operand layouts: see
+// k_gjb_update.
+__global__ void __launch_bounds__(1024) k_gjb_panel(double* __restrict__ A, int n, int k0, int kb,
+                                                    double* __restrict__ Pout,
+                                                    double* __restrict__ C) {
+    __shared__ double M[2][kGjB][kGjB + 1];
+    const int t = threadIdx.x, r = t / kGjB, c = t % kGjB;
+    const int lane = t & 63, w = t >> 6, lr = lane & 15, lk = lane >> 4;
+    const bool in = r < kb && c < kb;
+    M[0][r][c] = in ? A[(long)(k0 + r) * n + k0 + c] : 0.0;
+    // block-row operands: column jb of the old block row, rows 4 m + lk
+    const int j0 = blockIdx.x * 256 + 16 * w, jb = j0 + lr;
+    const bool tile = j0 < n && !(j0 >= k0 && j0 < k0 + kb);  // uniform over the wavefront
+    double bo[kGjB / 4];
+#pragma unroll
+    for (int m = 0; m < kGjB / 4; ++m) {
+        const int q = 4 * m + lk;
+        bo[m] = (tile && q < kb && jb < n) ? A[(long)(k0 + q) * n + jb] : 0.0;
     }
+    // old block column of row ic, entries c8 .. c8 + 7
+    const int ic = blockIdx.x * 256 + t / 4, c8 = 8 * (t % 4);
+    const bool crow = ic < n && (ic < k0 || ic >= k0 + kb);
+    double cv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) cv[e] = (crow && c8 + e < kb) ? A[(long)ic * n + k0 + c8 + e] : 0.0;
     __syncthreads();
-}
-
-// Block step, part 1.  Workgroup g: P into LDS; columns j = 256 g + t of the block row
-// (outside the block) become P A_Kj; rows i = 256 g + t (outside the block) copy their old
-// block-column entries to C (n x kGjB); workgroup 0 stores P.
-__global__ void __launch_bounds__(256) k_gjb_panel(double* __restrict__ A, int n, int k0, int kb,
-                                                   double* __restrict__ Pout,
-                                                   double* __restrict__ C) {
-    __shared__ double M[kGjB][kGjB + 1];
-    for (int e = threadIdx.x; e < kGjB * kGjB; e += 256) {
-        const int r = e / kGjB, c = e % kGjB;
-        M[r][c] = (r < kb && c < kb) ? A[(long)(k0 + r) * n + k0 + c] : 0.0;
+    for (int p = 0; p < kb; ++p) {
+        const int b = p & 1;
+        const double mpp = M[b][p][p], mpc = M[b][p][c], mrp = M[b][r][p], mrc = M[b][r][c];
+        const double piv = 1.0 / mpp;
+        const double pc = mpc * piv;  // scaled pivot row (rounded before use)
+        double v;
+        if (r == p)
+            v = (c == p) ? piv : pc;
+        else
+            v = (c == p) ? -mrp * piv : mrc - mrp * pc;
+        M[b ^ 1][r][c] = in ? v : 0.0;
+        __syncthreads();
     }
-    lds_gj_invert(M, kb);
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t < n && (t < k0 || t >= k0 + kb)) {
-        // fixed trip counts (guarded) keep old[] in registers
-        double old[kGjB];
+    const int f = kb & 1;  // buffer holding P
+    if (tile) {
+        gj_d4 d0 = {0.0, 0.0, 0.0, 0.0}, d1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int c = 0; c < kGjB; ++c) old[c] = c < kb ? A[(long)(k0 + c) * n + t] : 0.0;
-        for (int r = 0; r < kb; ++r) {
-            double acc = 0.0;
-#pragma unroll
-            for (int c = 0; c < kGjB; ++c)
-                if (c < kb) acc += M[r][c] * old[c];
-            A[(long)(k0 + r) * n + t] = acc;
+        for (int m = 0; m < kGjB / 4; ++m) {
+            d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(M[f][lr][4 * m + lk], bo[m], d0, 0, 0, 0);
+            d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(M[f][16 + lr][4 * m + lk], bo[m], d1, 0, 0, 0);
         }
-        for (int c = 0; c < kb; ++c) C[(long)t * kGjB + c] = A[(long)t * n + k0 + c];
+        if (jb < n)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r0 = lk + 4 * v, r1 = 16 + lk + 4 * v;
+                if (r0 < kb) A[(long)(k0 + r0) * n + jb] = d0[v];
+                if (r1 < kb) A[(long)(k0 + r1) * n + jb] = d1[v];
+            }
     }
-    if (blockIdx.x == 0)
-        for (int e = threadIdx.x; e < kGjB * kGjB; e += 256) Pout[e] = M[e / kGjB][e % kGjB];
+    if (crow)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) C[(long)ic * kGjB + c8 + e] = cv[e];
+    if (blockIdx.x == 0) Pout[t] = M[f][r][c];
 }
 
-// Block step, part 2: rows i0 .. i0 + kGjR - 1 (i0 = kGjR blockIdx.y), columns
-// j = 256 blockIdx.x + t.  The block row's column j (new, from part 1) is read once into
-// registers and serves all kGjR rows; the rows' saved block-column entries are staged in
-// LDS.
-constexpr int kGjR = 16;
+// Block step, part 2, on 16 x 16 tiles, one per wavefront (tile rows i0 = 16 blockIdx.y,
+// columns j0 = 64 blockIdx.x + 16 w).  K is kGjB-aligned and ends at a multiple of 16 or
+// at n, so a tile lies wholly inside or outside the block on each axis.  Outside the
+// block row, S = C_iK B_Kj with B_Kj the new block row (P's columns where j is in K) is
+// formed by v_mfma_f64_16x16x4_f64 over kGjB / 4 steps of 4 pivots, and A_ij <- A_ij - S
+// (A_iK <- -S in the block column).  Inside the block row only A_KK <- P is written (part
+// 1 wrote the rest).  Operand layouts of the instruction (lane l, 16 x 4 times 4 x 16):
+// A[l % 16][l / 16], B[l / 16][l % 16]; accumulator element v of lane l is
+// D[l / 16 + 4 v][l % 16] (rows interleaved by 4 across the lane groups, as measured on
+// gfx950).
 __global__ void __launch_bounds__(256) k_gjb_update(double* __restrict__ A, int n, int k0, int kb,
                                                     const double* __restrict__ P,
                                                     const double* __restrict__ C) {
-    __shared__ double cs[kGjR][kGjB];
-    const int i0 = blockIdx.y * kGjR;
-    for (int e = threadIdx.x; e < kGjR * kGjB; e += 256) {
-        const int r = e / kGjB, c = e % kGjB;
-        cs[r][c] = (i0 + r < n && c < kb) ? C[(long)(i0 + r) * kGjB + c] : 0.0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i0 = 16 * blockIdx.y, j0 = 64 * blockIdx.x + 16 * w;
+    if (j0 >= n) return;  // uniform over the wavefront
+    const bool rowK = i0 >= k0 && i0 < k0 + kb, colK = j0 >= k0 && j0 < k0 + kb;
+    const int lr = lane & 15, lk = lane >> 4;
+    if (rowK) {
+        if (colK)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + lk + 4 * v, j = j0 + lr;
+                if (i < n && j < n) A[(long)i * n + j] = P[(i - k0) * kGjB + (j - k0)];
+            }
+        return;
     }
-    __syncthreads();
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    const bool in_j = j >= k0 && j < k0 + kb;
-    double col[kGjB];
+    const int ia = i0 + lr;  // this lane's row of the C operand
+    const int jb = j0 + lr;  // this lane's column of the B operand
+    double a[kGjB / 4], b[kGjB / 4];
 #pragma unroll
-    for (int c = 0; c < kGjB; ++c)
-        col[c] = c < kb ? (in_j ? P[c * kGjB + (j - k0)] : A[(long)(k0 + c) * n + j]) : 0.0;
-    for (int r = 0; r < kGjR; ++r) {
-        const int i = i0 + r;
-        if (i >= n) break;
-        if (i >= k0 && i < k0 + kb) {
-            if (in_j) A[(long)i * n + j] = P[(i - k0) * kGjB + (j - k0)];
-            continue;  // the rest of the block row was formed in part 1
-        }
-        double acc = 0.0;
-#pragma unroll
-        for (int c = 0; c < kGjB; ++c) acc += cs[r][c] * col[c];
-        if (in_j)
-            A[(long)i * n + j] = -acc;
+    for (int m = 0; m < kGjB / 4; ++m) {
+        const int c = 4 * m + lk;
+        a[m] = ia < n ? C[(long)ia * kGjB + c] : 0.0;
+        if (colK)
+            b[m] = P[c * kGjB + (jb - k0)];
         else
-            A[(long)i * n + j] -= acc;
+            b[m] = (c < kb && jb < n) ? A[(long)(k0 + c) * n + jb] : 0.0;
+    }
+    double cur[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = i0 + lk + 4 * v;
+        cur[v] = (!colK && i < n && jb < n) ? A[(long)i * n + jb] : 0.0;
+    }
+    gj_d4 s = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < kGjB / 4; ++m) s = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[m], s, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = i0 + lk + 4 * v;
+        if (i < n && jb < n) A[(long)i * n + jb] = cur[v] - s[v];
     }
 }
 
@@ -1266,13 +1295,13 @@ __global__ void __launch_bounds__(256) k_gjb_update(double* __restrict__ A, int 
 void dense_invert(double* A, int n, hipStream_t s) {
     Tmp P(sizeof(double) * kGjB * kGjB), C(sizeof(double) * (size_t)n * kGjB);
     const unsigned gcol = (unsigned)((n + 255) / 256);
+    const dim3 gup((unsigned)((n + 63) / 64), (unsigned)((n + 15) / 16));
     for (int k0 = 0; k0 < n; k0 += kGjB) {
         const int kb = std::min(kGjB, n - k0);
-        hipLaunchKernelGGL(k_gjb_panel, dim3(gcol), dim3(256), 0, s, A, n, k0, kb, P.as<double>(),
+        hipLaunchKernelGGL(k_gjb_panel, dim3(gcol), dim3(1024), 0, s, A, n, k0, kb, P.as<double>(),
                            C.as<double>());
-        hipLaunchKernelGGL(k_gjb_update, dim3(gcol, (unsigned)((n + kGjR - 1) / kGjR)), dim3(256),
-                           0, s, A, n, k0, kb, (const double*)P.as<double>(),
-                           (const double*)C.as<double>());
+        hipLaunchKernelGGL(k_gjb_update, gup, dim3(256), 0, s, A, n, k0, kb,
+                           (const double*)P.as<double>(), (const double*)C.as<double>());
     }
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(s));

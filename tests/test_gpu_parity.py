@@ -311,6 +311,46 @@ def test_single_level_and_other_degrees():
         assert sa.hierarchy_info(G)["n_levels"] == len(H.levels)
 
 
+def _check_coarse_inverse(G, lv):
+    """The direct coarse solver's explicit inverse against the inverse of the oracle's
+    coarsest operator, element by element, and A_c G = I."""
+    rows, inv = sa.coarse_inverse(G)
+    assert np.array_equal(rows, lv.lin)
+    Ac = lv.A.toarray()
+    want = np.linalg.inv(Ac)
+    # both inverses carry rounding of about cond(A_c) n eps relative to max |A_c^-1|
+    assert emax(inv, want) <= 1e-12, (lv.n, emax(inv, want))
+    assert np.abs(Ac @ inv - np.eye(lv.n)).max() <= 1e-12 * np.abs(Ac).sum(axis=1).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_coarse_inverse_matches_oracle(name):
+    """Blocked Gauss-Jordan on the matrix cores: coarsest levels of 64..996 unknowns (2 to
+    32 blocks of 32 pivots, ragged last blocks)."""
+    c = case(name)
+    _check_coarse_inverse(c.G, c.H.levels[-1])
+
+
+def test_coarse_inverse_single_level_and_small():
+    """Single-level hierarchies (483 and 2,509 unknowns, the inverse of the level-0
+    operator) and a coarsest level of 27 unknowns (one partial block)."""
+    shape = W.Shape.cylinder(1.0, 2.0)
+    for (n, nz, mc, size) in ((11, 9, 1000, 483), (17, 15, 8000, 2509), (25, 21, 200, 27)):
+        print(f"[case] cylinder {n}x{n}x{nz} max_coarse={mc}", flush=True)
+        _, H = solve.build(shape, n, n, nz, W.VARIANT_QUAD, amg.Options(max_coarse=mc))
+        G = sa.setup(sa.domain_for(shape, n, n, nz), W.VARIANT_QUAD,
+                     sa.default_options(max_coarse=mc))
+        assert H.levels[-1].n == size
+        _check_coarse_inverse(G, H.levels[-1])
+        sa.destroy(G)
+
+
+def test_coarse_inverse_absent_for_gauss_seidel():
+    c = case("cyl33_lin", gs=True)
+    with pytest.raises(sa.SaamgError):
+        sa.coarse_inverse(c.G)
+
+
 def test_batched_states_equal_alone():
     """Each request's result is bitwise the same alone and inside a batch."""
     cs = [case("cyl33_lin", W.PREC_MIXED), case("ell70_quad", W.PREC_MIXED),
