@@ -954,6 +954,9 @@ static DomainPrep prepare_domain(const saamg_domain* dom, int variant, bool scan
         for (long k : {1L, (long)nz - 2})
             for (long t = 0; t < nxy; ++t)
                 if (m[t + nxy * k]) ends.push_back(t + nxy * k);
+    // at most one row per wall entry or end-plane unknown (no reallocation while filling)
+    D.nw_nodes.reserve((size_t)nw_in + ends.size());
+    D.nw_frac.reserve(6 * ((size_t)nw_in + ends.size()));
     auto add_row = [&](int64_t node) {
         D.nw_nodes.push_back(node);
         for (int q = 0; q < 6; ++q) D.nw_frac.push_back(1.0);
@@ -1923,6 +1926,35 @@ int saamg_scaling(saamg_hierarchy* H, double* d_sigma, void* stream) {
         HIPCHECK(hipMemcpyAsync(d_sigma, cg_op(H).sigma, 8 * H->l0.nbox, hipMemcpyDeviceToDevice,
                                 (hipStream_t)stream));
         HIPCHECK(hipStreamSynchronize((hipStream_t)stream));
+        return (int)SAAMG_OK;
+    });
+}
+
+int saamg_coarse_inverse(saamg_hierarchy* H, int32_t* n_out, int64_t* h_rows, double* h_inv) {
+    return guarded([&] {
+        if (!H || !n_out) throw ApiError{SAAMG_INVALID_ARG, "NULL argument"};
+        if (!H->Ainv)
+            throw ApiError{SAAMG_INVALID_ARG, "the hierarchy has no explicit coarse inverse"};
+        *n_out = H->nL;
+        if (!h_rows && !h_inv) return (int)SAAMG_OK;
+        HIPCHECK(hipSetDevice(H->device));
+        const int nL = H->nL, l = H->n_levels - 1;
+        if (h_rows) {
+            std::vector<long> cidx(nL);
+            HIPCHECK(hipMemcpy(cidx.data(), H->cidx, 8L * nL, hipMemcpyDeviceToHost));
+            int mx, my, mz;
+            level_dims(H, l, &mx, &my, &mz);
+            for (int r = 0; r < nL; ++r) {
+                long i = cidx[r];
+                if (l > 0) {  // padded storage (x + 1) + sx (y + 1) + sxy (z + 1)
+                    const CoarseLevel& C = H->lc[l - 1];
+                    const long z = i / C.sxy - 1, y = (i % C.sxy) / C.sx - 1, x = i % C.sx - 1;
+                    i = x + (long)mx * (y + (long)my * z);
+                }
+                h_rows[r] = i;
+            }
+        }
+        if (h_inv) HIPCHECK(hipMemcpy(h_inv, H->Ainv, 8L * nL * nL, hipMemcpyDeviceToHost));
         return (int)SAAMG_OK;
     });
 }
