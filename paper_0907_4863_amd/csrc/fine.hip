@@ -1269,19 +1269,21 @@ void cg_init(const FineLevel& L, const double* b, const double* x0, double* bs, 
     HIPCHECK(hipGetLastError());
 }
 
-// r = bs - A x; partials of r.r and bs.bs.
+// r = bs - A x; partials of r.r and bs.bs.  ZX: x = 0 (a start without an initial guess),
+// so r = bs and the march reads no stencil operand.
+template <bool ZX>
 __global__ void __launch_bounds__(kMThreads) k_cg_resid(L0View<double> v, const double* __restrict__ bs,
                                                        const double* __restrict__ xv,
                                                        double* __restrict__ r, double* part,
                                                        float* __restrict__ r32) {
     __shared__ double lds[kMThreads / kWave];
     double a0 = 0.0, a1 = 0.0;
-    l0_march<double, true, false>(
-        v, [&](Idx j) { return at(xv, j); },
+    l0_march<double, !ZX, false>(
+        v, [&](Idx j) { return ZX ? 0.0 : at(xv, j); },
         [&](Idx i, int, int, int, bool, int) { return Vals<double, 1>{{ntl(bs, i)}}; },
         [&](Idx i, Vals<double, 1> f, double, double ax, int, int, int, bool, int) {
             const double bi = f.v[0];
-            const double o = bi - ax;
+            const double o = ZX ? bi : bi - ax;
             nts(r, i, o);
             if (r32) nts(r32, i, (float)o);
             a0 += o * o;
@@ -1295,14 +1297,19 @@ __global__ void __launch_bounds__(kMThreads) k_cg_resid(L0View<double> v, const 
     }
 }
 
+// x == nullptr: x = 0.
 void cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
               float* r32, hipStream_t s) {
     if (L.wide) {
         w_cg_resid(L, bs, x, r, partials, r32, s);
         return;
     }
-    hipLaunchKernelGGL(k_cg_resid, l0_mgrid(L), dim3(kWave, kMY), 0, s, L.view<double>(), bs,
-                       x, r, partials, r32);
+    if (x)
+        hipLaunchKernelGGL(k_cg_resid<false>, l0_mgrid(L), dim3(kWave, kMY), 0, s,
+                           L.view<double>(), bs, x, r, partials, r32);
+    else
+        hipLaunchKernelGGL(k_cg_resid<true>, l0_mgrid(L), dim3(kWave, kMY), 0, s,
+                           L.view<double>(), bs, (const double*)nullptr, r, partials, r32);
     HIPCHECK(hipGetLastError());
 }
 

@@ -532,7 +532,8 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
     S->repl = 0;
     S->t0 = std::chrono::steady_clock::now();
     cg_init(cg_op(H), b, x0, S->bs, S->x, S->s);
-    cg_resid(cg_op(H), S->bs, S->x, S->r, S->part, S->r32, S->s);
+    // without an initial guess x = 0 and r = b~ (no product with A)
+    cg_resid(cg_op(H), S->bs, x0 ? S->x : nullptr, S->r, S->part, S->r32, S->s);
     finalize(S->part, cg_resid_parts(cg_op(H)), 2, S->scal, FIN_STORE, S_RR, S->s);
     scal_start(S->scal, S->tol, S->s);
     S->kdir = 0;
@@ -542,7 +543,9 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
                   (size_t)S->pw * H->l0.nbox, S->s);
     else
         zero_fill(S->p, 8 * H->l0.nbox, S->s);
-    zero_fill(S->q, 8 * H->l0.nbox, S->s);
+    // the fused form carries A p in q; the ring form uses q only as scratch for a true
+    // residual
+    if (!S->ringf) zero_fill(S->q, 8 * H->l0.nbox, S->s);
     read_scal(S);
     const double rr = S->hscal[S_RR], bb = S->hscal[S_BB];
     S->bnorm = std::sqrt(bb);

@@ -815,7 +815,9 @@ template void w_dot<float>(const FineLevel&, const double*, const float*, double
 
 // ---------------------------------------------------------------- CG (fp64, 2 nodes per lane)
 
-// r = bs - A x; partials of r.r and bs.bs (see k_cg_resid).
+// r = bs - A x; partials of r.r and bs.bs (see k_cg_resid).  ZX: x = 0 (a start without an
+// initial guess), so r = bs and the march reads no stencil operand.
+template <bool ZX>
 __global__ void __launch_bounds__(kMThreads) k_w_cg_resid(L0View<double> v,
                                                          const double* __restrict__ bs,
                                                          const double* __restrict__ xv,
@@ -824,7 +826,7 @@ __global__ void __launch_bounds__(kMThreads) k_w_cg_resid(L0View<double> v,
     constexpr int N = 2;
     __shared__ double lds[kMThreads / kWave];
     double a0 = 0.0, a1 = 0.0;
-    wmarch<double, N, true, false, false>(
+    wmarch<double, N, !ZX, false, false>(
         v, xv, [&](Idx i, int, int, int, unsigned, int) { return vldnt<N>(bs, i); },
         [&](Idx i, const Vec<double, N>& b, const Vec<double, N>&, const Vec<double, N>& ax, int,
             int, int, unsigned nib) {
@@ -832,7 +834,7 @@ __global__ void __launch_bounds__(kMThreads) k_w_cg_resid(L0View<double> v,
 #pragma unroll
             for (int e = 0; e < N; ++e) {
                 const bool u = (nib >> e) & 1u;
-                o[e] = u ? b.v[e] - ax.v[e] : 0.0;
+                o[e] = u ? (ZX ? b.v[e] : b.v[e] - ax.v[e]) : 0.0;
                 a0 += o[e] * o[e];
                 a1 += u ? b.v[e] * b.v[e] : 0.0;
             }
@@ -848,8 +850,12 @@ __global__ void __launch_bounds__(kMThreads) k_w_cg_resid(L0View<double> v,
 
 void w_cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
                 float* r32, hipStream_t s) {
-    hipLaunchKernelGGL(k_w_cg_resid, wgrid<double>(L), dim3(kWave, kMY), 0, s,
-                       wview<double>(L, 2), bs, x, r, partials, r32);
+    if (x)
+        hipLaunchKernelGGL(k_w_cg_resid<false>, wgrid<double>(L), dim3(kWave, kMY), 0, s,
+                           wview<double>(L, 2), bs, x, r, partials, r32);
+    else
+        hipLaunchKernelGGL(k_w_cg_resid<true>, wgrid<double>(L), dim3(kWave, kMY), 0, s,
+                           wview<double>(L, 2), bs, (const double*)nullptr, r, partials, r32);
     HIPCHECK(hipGetLastError());
 }
 
