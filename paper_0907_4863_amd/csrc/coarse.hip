@@ -756,15 +756,27 @@ __global__ void __launch_bounds__(256) k_rap(Acc acc, int fmx, int fmy, int fmz,
     auto in_block = [](int px, int py, int pz) {
         return px >= 3 && px < 6 && py >= 3 && py < 6 && pz >= 3 && pz < 6;
     };
+    // the offsets k (increasing) at which a row can be nonzero: the 7-point stencil on
+    // level 0, all 27 on the coarse levels.  Skipped terms are exact zeros, so the sums
+    // are those of the full loops.
+    auto for_k = [&](auto f) {
+        if constexpr (Acc::kCache) {
+            constexpr int k7[7] = {4, 10, 12, 13, 14, 16, 22};
+#pragma unroll
+            for (int j = 0; j < 7; ++j) f(k7[j]);
+        } else {
+            for (int k = 0; k < 27; ++k) f(k);
+        }
+    };
     // phase 1: v on [2,7)^3
     for (int q = t; q < 125; q += blockDim.x) {
         const int px = 2 + q % 5, py = 2 + (q / 5) % 5, pz = 2 + q / 25;
         rows_at(px, py, pz, a, at, &unk);
         double s = 0.0;
-        for (int k = 0; k < 27; ++k) {
+        for_k([&](int k) {
             const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
             if (in_block(px + dx, py + dy, pz + dz)) s += a[k];
-        }
+        });
         const double u = (unk && in_block(px, py, pz)) ? 1.0 : 0.0;
         sv[q] = u - omega * invd_at(px, py, pz) * s;
     }
@@ -774,11 +786,11 @@ __global__ void __launch_bounds__(256) k_rap(Acc acc, int fmx, int fmy, int fmz,
         const int px = 1 + q % 7, py = 1 + (q / 7) % 7, pz = 1 + q / 49;
         rows_at(px, py, pz, a, at, &unk);
         double s = 0.0;
-        for (int k = 0; k < 27; ++k) {
+        for_k([&](int k) {
             const int qx = px + k % 3 - 1 - 2, qy = py + (k / 3) % 3 - 1 - 2, qz = pz + k / 9 - 1 - 2;
             if (qx >= 0 && qx < 5 && qy >= 0 && qy < 5 && qz >= 0 && qz < 5)
                 s += a[k] * sv[qx + 5 * qy + 25 * qz];
-        }
+        });
         sw[q] = s;
     }
     __syncthreads();
@@ -789,12 +801,12 @@ __global__ void __launch_bounds__(256) k_rap(Acc acc, int fmx, int fmy, int fmz,
         double yv = 0.0;
         if (unk) {
             double s = 0.0;
-            for (int k = 0; k < 27; ++k) {
+            for_k([&](int k) {
                 const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
                 const int qx = px + dx - 1, qy = py + dy - 1, qz = pz + dz - 1;
                 if (qx >= 0 && qx < 7 && qy >= 0 && qy < 7 && qz >= 0 && qz < 7 && at[k] != 0.0)
                     s += at[k] * invd_at(px + dx, py + dy, pz + dz) * sw[qx + 7 * qy + 49 * qz];
-            }
+            });
             const bool inw = px >= 1 && px < 8 && py >= 1 && py < 8 && pz >= 1 && pz < 8;
             const double tv = inw ? sw[(px - 1) + 7 * (py - 1) + 49 * (pz - 1)] : 0.0;
             yv = tv - omega * s;
