@@ -10,7 +10,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsaamg.so")
-SOURCES = ["fine.hip", "wide.hip", "coarse.hip", "solver.hip", "pic.hip", "timer.hip", "domain.cpp"]
+SOURCES = ["fine.hip", "wide.hip", "coarse.hip", "solver.hip", "pic.hip", "timer.hip", "domain.cpp",
+           "host_prep.cpp"]
 # hbm_ceiling.hip is a separate program (see _build_ceiling), not part of the library
 ARCH = os.environ.get("SAAMG_ARCH", "gfx950")
 

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/saamg.h"
+#include "host_prep.h"
 
 namespace saamg {
 
@@ -135,10 +136,6 @@ __host__ __device__ inline double start_value(long lin) {
 struct HipError {
     hipError_t e;
     std::string where;
-};
-struct ApiError {
-    int status;
-    std::string msg;
 };
 
 void hip_check(hipError_t e, const char* what);

@@ -10,9 +10,11 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -864,124 +866,6 @@ static void validate_options(const saamg_options& o) {
         throw ApiError{SAAMG_INVALID_ARG, "l0_wide must be 0, 1 or 2"};
 }
 
-// Host-side checks of a domain and its near-wall rows: wall fractions below 1 (the
-// constant rule ignores them) and, with open ends, every end-plane unknown; six fractions
-// per row, 1 where no wall is cut.
-struct DomainPrep {
-    std::vector<int64_t> nw_nodes;
-    std::vector<double> nw_frac;
-};
-
-// scan_mask = false skips the mask's own checks (count, faces, open ends): a refresh
-// compares the mask with the hierarchy's, which passed them.
-static DomainPrep prepare_domain(const saamg_domain* dom, int variant, bool scan_mask = true) {
-    if (!dom || !dom->mask) throw ApiError{SAAMG_INVALID_ARG, "domain or mask is NULL"};
-    const int nx = dom->nx, ny = dom->ny, nz = dom->nz;
-    if (nx < 3 || ny < 3 || nz < 3) throw ApiError{SAAMG_INVALID_ARG, "box must be at least 3^3"};
-    if ((double)nx * ny * nz > 2.0e9) throw ApiError{SAAMG_INVALID_ARG, "box too large"};
-    if (!(dom->hx > 0) || !(dom->hy > 0) || !(dom->hz > 0))
-        throw ApiError{SAAMG_INVALID_ARG, "grid spacings must be positive"};
-    if (variant < SAAMG_VARIANT_CONST || variant > SAAMG_VARIANT_QUAD)
-        throw ApiError{SAAMG_INVALID_ARG, "unknown boundary variant"};
-    if (dom->n_wall < 0 || (dom->n_wall > 0 && (!dom->wall_node || !dom->wall_dir || !dom->wall_s)))
-        throw ApiError{SAAMG_INVALID_ARG, "wall arrays are NULL"};
-
-    DomainPrep D;
-    const long nxy = (long)nx * ny, nbox = nxy * nz;
-    const uint8_t* m = dom->mask;
-    // unknowns: their number, and none on a face of the box
-    if (scan_mask) {
-        // at least one unknown (the device counts them when it builds the segment masks)
-        bool any = false;
-        for (long t = 0; t < nbox && !any; ++t) any = m[t] != 0;
-        if (!any) throw ApiError{SAAMG_INVALID_ARG, "the domain has no unknowns"};
-        bool on_face = false;
-        for (long t = 0; t < nxy && !on_face; ++t) on_face = m[t] || m[t + nxy * (nz - 1)];
-        for (long k = 0; k < nz && !on_face; ++k)
-            for (long i = 0; i < nx; ++i)
-                on_face = on_face || m[i + nxy * k] || m[i + nx * (ny - 1) + nxy * k];
-        for (long k = 0; k < nz && !on_face; ++k)
-            for (long j = 0; j < ny; ++j)
-                on_face = on_face || m[nx * j + nxy * k] || m[nx - 1 + nx * j + nxy * k];
-        if (on_face) throw ApiError{SAAMG_INVALID_ARG, "an unknown lies on a face of the box"};
-    }
-
-    const bool open = dom->robin_d > 0.0;
-    if (dom->robin_d < 0.0 || !std::isfinite(dom->robin_d))
-        throw ApiError{SAAMG_INVALID_ARG, "robin_d must be 0 (closed ends) or positive"};
-    if (open && scan_mask) {
-        if (nz < 4) throw ApiError{SAAMG_INVALID_ARG, "open ends need at least 4 box planes"};
-        // end-plane unknowns (planes 1 and nz-2) need an unknown on the inner side
-        for (long j = 0; j < ny; ++j)
-            for (long i = 0; i < nx; ++i) {
-                const long a = i + nx * j + nxy, b = i + nx * j + nxy * (nz - 2);
-                if ((m[a] && !m[a + nxy]) || (m[b] && !m[b - nxy]))
-                    throw ApiError{SAAMG_INVALID_ARG,
-                                   "an open-end unknown has no unknown z-neighbour inside"};
-            }
-    }
-
-    // wall entries, checked and ordered by (node, direction); the domain builder emits
-    // them in that order already, so the sort is usually skipped
-    const int64_t nw_in = dom->n_wall;
-    const long step[6] = {-1, 1, -(long)nx, (long)nx, -nxy, nxy};
-    std::vector<int64_t> key(nw_in);
-    for (int64_t e = 0; e < nw_in; ++e) {
-        const int64_t node = dom->wall_node[e];
-        const int d = dom->wall_dir[e];
-        const double sv = dom->wall_s[e];
-        if (node < 0 || node >= nbox || d > 5)
-            throw ApiError{SAAMG_INVALID_ARG, "wall entry out of range"};
-        if (!m[node] || m[node + step[d]])
-            throw ApiError{SAAMG_INVALID_ARG,
-                           "wall entry must name an unknown whose neighbour is not an unknown"};
-        if (!(sv > 1e-12) || !(sv <= 1.0))
-            throw ApiError{SAAMG_INVALID_ARG, "wall fraction must lie in (1e-12, 1]"};
-        key[e] = node * 8 + d;
-    }
-    std::vector<int64_t> order;
-    const bool sorted = std::is_sorted(key.begin(), key.end());
-    if (!sorted) {
-        order.resize(nw_in);
-        for (int64_t e = 0; e < nw_in; ++e) order[e] = e;
-        std::sort(order.begin(), order.end(), [&](int64_t p, int64_t q) { return key[p] < key[q]; });
-    }
-    auto at = [&](int64_t r) { return sorted ? r : order[r]; };
-    for (int64_t r = 1; r < nw_in; ++r)
-        if (key[at(r)] == key[at(r - 1)]) throw ApiError{SAAMG_INVALID_ARG, "duplicate wall entry"};
-
-    // near-wall rows in node order: the cut entries (not for the constant rule) merged
-    // with the open-end planes' unknowns
-    std::vector<int64_t> ends;
-    if (open)
-        for (long k : {1L, (long)nz - 2})
-            for (long t = 0; t < nxy; ++t)
-                if (m[t + nxy * k]) ends.push_back(t + nxy * k);
-    // at most one row per wall entry or end-plane unknown (no reallocation while filling)
-    D.nw_nodes.reserve((size_t)nw_in + ends.size());
-    D.nw_frac.reserve(6 * ((size_t)nw_in + ends.size()));
-    auto add_row = [&](int64_t node) {
-        D.nw_nodes.push_back(node);
-        for (int q = 0; q < 6; ++q) D.nw_frac.push_back(1.0);
-    };
-    size_t ei = 0;
-    const bool cuts = variant != SAAMG_VARIANT_CONST;
-    for (int64_t r = 0; r < nw_in; ++r) {
-        const int64_t e = at(r);
-        const double sv = dom->wall_s[e];
-        if (!cuts || !(sv < 1.0)) continue;
-        const int64_t node = key[e] >> 3;
-        while (ei < ends.size() && ends[ei] < node) add_row(ends[ei++]);
-        if (ei < ends.size() && ends[ei] == node) ++ei;
-        if (D.nw_nodes.empty() || D.nw_nodes.back() != node) add_row(node);
-        D.nw_frac[D.nw_frac.size() - 6 + (key[e] & 7)] = sv;
-    }
-    while (ei < ends.size()) add_row(ends[ei++]);
-    return D;
-}
-
-// The domain on the device: mask, near-wall row index per box node (-1 elsewhere) and
-// the near-wall rows' fractions.
 struct DeviceDomain {
     uint8_t* mask = nullptr;
     int32_t* nwidx = nullptr;
