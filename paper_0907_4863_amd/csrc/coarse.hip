@@ -1025,7 +1025,7 @@ void lc_compress(CoarseLevel& C, hipStream_t s) {
     if (!C.slot) C.slot = (int32_t*)dmalloc(4 * n);
     int32_t* cnt = (int32_t*)dmalloc(4 * nw);
     int32_t* base = (int32_t*)dmalloc(4 * nw);
-    int64_t* tot = (int64_t*)dmalloc(8);
+    int64_t* tot = (int64_t*)dmalloc(8 * scan_words(nw));
     double* row = (double*)dmalloc(8 * 27);
     try {
         LCView<double> v = C.view<double>();
@@ -1108,7 +1108,7 @@ void lc_unknown_list(const CoarseLevel& C, long* out, int32_t* counter, hipStrea
     // counter: per-64 counts already produced by lc_finish; scan them in place into a copy
     const long nw = (C.nstore + 63) / 64;
     int32_t* base = (int32_t*)dmalloc(sizeof(int32_t) * nw);
-    int64_t* tot = (int64_t*)dmalloc(sizeof(int64_t));
+    int64_t* tot = (int64_t*)dmalloc(sizeof(int64_t) * scan_words(nw));
     exclusive_scan(counter, base, nw, tot, s);
     hipLaunchKernelGGL(k_lc_list, dim3((C.nstore + 255) / 256), dim3(256), 0, s, C.invD64,
                        C.nstore, base, out);

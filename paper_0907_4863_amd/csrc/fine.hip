@@ -485,21 +485,60 @@ bool l0_same_masks(const FineLevel& L, const uint64_t* unk, const uint64_t* irr,
     return h == 0;
 }
 
-// Single-block exclusive scan of int32 counts (setup only).
-__global__ void __launch_bounds__(1024) k_scan(const int32_t* in, int32_t* out, long n,
-                                               int64_t* total) {
+// Exclusive scan of int32 counts (setup only), in int64.  Tiles of kScanTile counts, one
+// per workgroup, 16 consecutive counts per thread: the tiles' sums (k_scan_sums), their
+// exclusive scan and the total by one workgroup (k_scan_top), then each tile's scan with
+// its offset (k_scan_apply).  One tile: k_scan_apply alone, which also writes the total.
+constexpr int kScanT = 256, kScanE = 16;
+constexpr long kScanTile = (long)kScanT * kScanE;
+
+long scan_words(long n) { return 1 + std::max(1L, (n + kScanTile - 1) / kScanTile); }
+
+// Sum of the 16 counts of this thread (0 past n).
+__device__ inline int64_t scan_thread_sum(const int32_t* in, long n, long i0) {
+    int64_t s = 0;
+#pragma unroll
+    for (int e = 0; e < kScanE; ++e) s += (i0 + e < n) ? in[i0 + e] : 0;
+    return s;
+}
+
+// Exclusive scan of one value per thread over the workgroup (kScanT threads).
+__device__ inline int64_t scan_block_excl(int64_t v, int64_t* lds) {
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int d = 1; d < kScanT; d <<= 1) {
+        const int64_t a = t >= d ? lds[t - d] : 0;
+        __syncthreads();
+        lds[t] += a;
+        __syncthreads();
+    }
+    return lds[t] - v;  // inclusive minus own
+}
+
+__global__ void __launch_bounds__(kScanT) k_scan_sums(const int32_t* __restrict__ in, long n,
+                                                     int64_t* __restrict__ bs) {
+    __shared__ int64_t lds[kScanT];
+    const long i0 = blockIdx.x * kScanTile + (long)threadIdx.x * kScanE;
+    const int64_t v = scan_thread_sum(in, n, i0);
+    const int64_t ex = scan_block_excl(v, lds);
+    if (threadIdx.x == kScanT - 1) bs[blockIdx.x] = ex + v;
+}
+
+// bs[0 .. nb) <- exclusive scan in place; *total <- the sum (one workgroup of 1024).
+__global__ void __launch_bounds__(1024) k_scan_top(int64_t* bs, long nb, int64_t* total) {
     __shared__ int64_t part[1024];
     const int t = threadIdx.x;
-    const long chunk = (n + 1023) / 1024;
-    const long a = t * chunk, b = min(n, a + chunk);
+    const long chunk = (nb + 1023) / 1024;
+    const long a = t * chunk, b = min(nb, a + chunk);
     int64_t s = 0;
-    for (long i = a; i < b; ++i) s += in[i];
+    for (long i = a; i < b; ++i) s += bs[i];
     part[t] = s;
     __syncthreads();
     if (t == 0) {
         int64_t acc = 0;
         for (int k = 0; k < 1024; ++k) {
-            int64_t v = part[k];
+            const int64_t v = part[k];
             part[k] = acc;
             acc += v;
         }
@@ -508,13 +547,50 @@ __global__ void __launch_bounds__(1024) k_scan(const int32_t* in, int32_t* out, 
     __syncthreads();
     int64_t acc = part[t];
     for (long i = a; i < b; ++i) {
-        if (out) out[i] = (int32_t)acc;
-        acc += in[i];
+        const int64_t v = bs[i];
+        bs[i] = acc;
+        acc += v;
+    }
+}
+
+// out[i] = (tile offset) + (counts before i in the tile); bs == nullptr: one tile, offset 0,
+// and *total = its sum.
+__global__ void __launch_bounds__(kScanT) k_scan_apply(const int32_t* __restrict__ in, long n,
+                                                      const int64_t* __restrict__ bs,
+                                                      int32_t* __restrict__ out, int64_t* total) {
+    __shared__ int64_t lds[kScanT];
+    const long i0 = blockIdx.x * kScanTile + (long)threadIdx.x * kScanE;
+    int32_t c[kScanE];
+    int64_t v = 0;
+#pragma unroll
+    for (int e = 0; e < kScanE; ++e) {
+        c[e] = (i0 + e < n) ? in[i0 + e] : 0;
+        v += c[e];
+    }
+    const int64_t ex = scan_block_excl(v, lds);
+    if (!bs && total && threadIdx.x == kScanT - 1) *total = ex + v;
+    if (!out) return;
+    int64_t acc = (bs ? bs[blockIdx.x] : 0) + ex;
+#pragma unroll
+    for (int e = 0; e < kScanE; ++e) {
+        if (i0 + e < n) out[i0 + e] = (int32_t)acc;
+        acc += c[e];
     }
 }
 
 void exclusive_scan(const int32_t* in, int32_t* out, long n, int64_t* total, hipStream_t s) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, in, out, n, total);
+    const long nb = std::max(1L, (n + kScanTile - 1) / kScanTile);
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanT), 0, s, in, n,
+                           (const int64_t*)nullptr, out, total);
+    } else {
+        int64_t* bs = total + 1;
+        hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(kScanT), 0, s, in, n, bs);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bs, nb, total);
+        if (out)
+            hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanT), 0, s, in, n,
+                               (const int64_t*)bs, out, (int64_t*)nullptr);
+    }
     HIPCHECK(hipGetLastError());
 }
 
@@ -751,7 +827,8 @@ __global__ void __launch_bounds__(kThreads) k_l0_line_copy(long nlines, int nseg
 
 void l0_dedup_table(FineLevel& L, const double* full64, const float* full32, hipStream_t s) {
     const long nlines = (long)L.ny * L.nz;
-    Tmp keep(4 * nlines), same(4 * nlines), off(4 * nlines), nb(4 * nlines), tot(8);
+    Tmp keep(4 * nlines), same(4 * nlines), off(4 * nlines), nb(4 * nlines),
+        tot(8 * scan_words(nlines));
     const dim3 gl((unsigned)((nlines + kBlockY - 1) / kBlockY)), bl(kWave, kBlockY);
     hipLaunchKernelGGL(k_l0_line_info, gl, bl, 0, s, L.view<double>(), (const int32_t*)L.base_full,
                        full64, L.n_irr, keep.as<int32_t>(), same.as<int32_t>());
@@ -794,7 +871,8 @@ __global__ void __launch_bounds__(kThreads) k_unknown_list(L0View<double> v, con
 
 void l0_unknown_list(const FineLevel& L, long* out, hipStream_t s) {
     // rank of unknowns by segment: scan the per-segment unknown counts
-    Tmp t_cnt(sizeof(int32_t) * L.nseg), t_base(sizeof(int32_t) * L.nseg), t_tot(sizeof(int64_t));
+    Tmp t_cnt(sizeof(int32_t) * L.nseg), t_base(sizeof(int32_t) * L.nseg),
+        t_tot(sizeof(int64_t) * scan_words(L.nseg));
     int32_t* cnt = t_cnt.as<int32_t>();
     int32_t* base = t_base.as<int32_t>();
     int64_t* tot = t_tot.as<int64_t>();

@@ -100,6 +100,10 @@ void l0_build_masks(FineLevel& L, const uint8_t* mask, const int32_t* nwidx, int
                     int32_t* cnt_unk, hipStream_t s);
 // true when the segment masks unk/irr equal L's
 bool l0_same_masks(const FineLevel& L, const uint64_t* unk, const uint64_t* irr, hipStream_t s);
+// Exclusive scan of n int32 counts into out (nullable), in int64 (outputs cast to int32);
+// total points to scan_words(n) int64 values: the sum goes to total[0], the rest is the
+// scan's scratch.
+long scan_words(long n);
 void exclusive_scan(const int32_t* in, int32_t* out, long n, int64_t* total, hipStream_t s);
 // The full table (one row per irregular node, slots from base_full) into tab64 / tab32
 // ([2][n_irr][8]) and sigma.

@@ -951,7 +951,7 @@ static int64_t galerkin(saamg_hierarchy* H, int l, CoarseLevel& C, double omega,
     try {
         lc_finish(C, cnt, s);
         lc_compress(C, s);
-        Tmp tot(8);
+        Tmp tot(8 * scan_words(4 * nb));
         exclusive_scan(cnt, nullptr, 4 * nb, tot.as<int64_t>(), s);
         HIPCHECK(hipMemcpyAsync(&nc, tot.p, 8, hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
@@ -1065,7 +1065,9 @@ static saamg_hierarchy* setup_impl(const saamg_domain* dom, int variant, const s
         DeviceDomain dd(dom, D, nbox, s);
         int64_t tots[2];
         {
-            Tmp cnt_irr(4 * L.nseg), cnt_unk(4 * L.nseg), d_tot(16);
+            // two totals: the second scan's total sits in the first one's scratch, which it
+            // no longer needs when the second scan (queued after it) writes there
+            Tmp cnt_irr(4 * L.nseg), cnt_unk(4 * L.nseg), d_tot(8 * (1 + scan_words(L.nseg)));
             l0_build_masks(L, dd.mask, dd.nwidx, cnt_irr.as<int32_t>(), cnt_unk.as<int32_t>(), s);
             exclusive_scan(cnt_irr.as<int32_t>(), L.base_full, L.nseg, d_tot.as<int64_t>(), s);
             exclusive_scan(cnt_unk.as<int32_t>(), nullptr, L.nseg, d_tot.as<int64_t>() + 1, s);
