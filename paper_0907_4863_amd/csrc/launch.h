@@ -71,6 +71,10 @@ constexpr int prolong_lanes(int bytes) { return bytes == 8 ? 2 : kProlongLanesF;
 // 64-node engine (the Lanczos kernels), and by those on 16-byte lanes with n nodes per lane.
 long l0_blocks(const FineLevel& L);
 long l0_wblocks(const FineLevel& L, int n);
+// Symmetric-part apply of the Lanczos estimate on 16-byte lanes (2 fp64 nodes per lane);
+// partials over l0_wblocks(L, 2) blocks.
+void w_lz_apply(const FineLevel& L, bool sym, const double* vin, const double* scal, double* u,
+                double* partials, hipStream_t s);
 // Partial sums (blocks) that the level-0 reduction launchers below write, for the lanes
 // each of them runs on (FineLevel::wide: see the launchers): cg_resid, cg_pq (fp32 z or
 // not), cg_xr, and the V-cycle's fused r . z (its last Chebyshev step, or l0_dot) in a

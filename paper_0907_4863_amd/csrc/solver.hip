@@ -746,9 +746,12 @@ static double tridiag_max_eig(const double* a, const double* b, int m) {
 static double lanczos_lambda(saamg_hierarchy* H, int l, hipStream_t s) {
     const long n = (l == 0) ? H->l0.nbox : H->lc[l - 1].nstore;
     const long nb = (l == 0) ? l0_blocks(H->l0) : lc_blocks(H->lc[l - 1]);
+    // level 0 on 16-byte lanes: the apply runs on the wide march (its own block count)
+    const bool wide = (l == 0) && H->l0.wide;
+    const long nb_apply = wide ? l0_wblocks(H->l0, 2) : nb;
     const long n_unk = (l == 0) ? H->l0.n_unknowns : H->lc[l - 1].n_unknowns;
     const int K = (int)std::min<long>(H->opt.eig_iters, n_unk);
-    Tmp t_cur(8 * n), t_prev(8 * n), t_u(8 * n), t_part(sizeof(double) * nb),
+    Tmp t_cur(8 * n), t_prev(8 * n), t_u(8 * n), t_part(sizeof(double) * std::max(nb, nb_apply)),
         t_scal(sizeof(double) * (S_NSLOTS + 2 * K));
     double* cur = t_cur.as<double>();
     double* prev = t_prev.as<double>();
@@ -761,11 +764,13 @@ static double lanczos_lambda(saamg_hierarchy* H, int l, hipStream_t s) {
         lc_lz_start(H->lc[l - 1], cur, part, s);
     finalize(part, nb, 1, scal, FIN_NORM, 0, s);
     for (int k = 0; k < K; ++k) {
-        if (l == 0)
+        if (wide)
+            w_lz_apply(H->l0, H->sym, cur, scal, u, part, s);
+        else if (l == 0)
             l0_lz_apply(H->l0, H->sym, cur, scal, u, part, s);
         else
             lc_lz_apply(H->lc[l - 1], cur, scal, u, part, s);
-        finalize(part, nb, 1, scal, FIN_LZ_ALPHA, S_NSLOTS + k, s);
+        finalize(part, nb_apply, 1, scal, FIN_LZ_ALPHA, S_NSLOTS + k, s);
         if (l == 0)
             l0_lz_update(H->l0, u, cur, prev, scal, part, s);
         else

@@ -172,10 +172,15 @@ __device__ __forceinline__ void row6(const TV* p, T t[6]) {
 // 2 N loads per plane and took a quarter of the time of the fp32 stencil kernels.  A row
 // whose rows are those of the plane before (its line repeats the line below: the same
 // slots) neither loads nor stages them again.
-template <typename T, int N, bool STENCIL, bool TR, bool FULL, bool TAB = STENCIL, class XS,
-          class Fetch, class Body, class End = NoEnd>
+//
+// BOTH (with STENCIL and TAB, not TR): an irregular node also applies its row of A^T (same
+// slot, staged beside the row of A) to the same neighbour values, without the diagonal,
+// and the body receives those sums as an extra argument after ax.
+template <typename T, int N, bool STENCIL, bool TR, bool FULL, bool TAB = STENCIL,
+          bool BOTH = false, class XS, class Fetch, class Body, class End = NoEnd>
 __device__ __forceinline__ void wmarch_x(const L0View<T>& v, const XS xs, Fetch fetch, Body body,
                                          End end = End{}) {
+    static_assert(!BOTH || (STENCIL && TAB && !TR), "BOTH applies A and A^T rows");
     static_assert(N == 2 || N == 4, "16-byte lanes of 8- or 4-byte values");
     using TX = typename XS::type;
     using FV = decltype(fetch(Idx{0, 0u}, 0, 0, 0, 0u, 0));
@@ -189,6 +194,7 @@ __device__ __forceinline__ void wmarch_x(const L0View<T>& v, const XS xs, Fetch 
     // packed span word: lo | hi << 8 | any << 16 | irregular << 17 | count << 18
     constexpr int SP_ANY = 1 << 16, SP_IRR = 1 << 17, SP_CNT = 18;
     __shared__ TV tl[kMY][kWave];  // each wavefront's staged table rows
+    __shared__ TV tl2[BOTH ? kMY : 1][BOTH ? kWave : 1];  // and of A^T (BOTH)
     if (v.skip && *v.skip != 0.0) return;  // wave-uniform: the whole grid returns
     int ws, y, bz;
     l0_tile(v, &ws, &y, &bz);
@@ -202,6 +208,7 @@ __device__ __forceinline__ void wmarch_x(const L0View<T>& v, const XS xs, Fetch 
     const long nx = v.nx, nxy = v.nxy;
     const T* tb = TR ? v.tabT : v.tab;
     TV* const stage = tl[threadIdx.y];
+    TV* const stage2 = tl2[BOTH ? threadIdx.y : 0];
     // words of (plane k = lane / N, segment j = lane % N) of the span, planes z0-1 .. z1
     uint64_t wu = 0, wr = 0;
     int wb = 0;
@@ -244,15 +251,16 @@ __device__ __forceinline__ void wmarch_x(const L0View<T>& v, const XS xs, Fetch 
     auto clamp_lane = [&](int sp) { return min(max(lane, sp & 255), (sp >> 8) & 255); };
     auto load_vec = [&](long ibq, int lc) { return xs.template ld<N>(Idx{ibq, (unsigned)(N * lc)}); };
     // 16 bytes of table rows tb0 + c R .. of a row with cnt irregular nodes
-    auto load_rows = [&](int tb0, int c, int cnt) {
+    auto load_rows_of = [&](const T* tbx, int tb0, int c, int cnt) {
         TV d;
 #pragma unroll
         for (int q = 0; q < 16 / (int)sizeof(T); ++q) d[q] = T(0);
         if (lane < min(cnt - c * R, R) * RV)
-            d = *reinterpret_cast<const TV*>(reinterpret_cast<const char*>(tb + 8 * ((long)tb0 + c * R)) +
+            d = *reinterpret_cast<const TV*>(reinterpret_cast<const char*>(tbx + 8 * ((long)tb0 + c * R)) +
                                              (unsigned)lane * 16u);
         return d;
     };
+    auto load_rows = [&](int tb0, int c, int cnt) { return load_rows_of(tb, tb0, c, cnt); };
     auto load_plane = [&](int q, long ib) {
         WP P;
         P.ib = ib;
@@ -319,11 +327,12 @@ __device__ __forceinline__ void wmarch_x(const L0View<T>& v, const XS xs, Fetch 
         Vec<TX, N> zp = vzero<TX, N>();
         if (STENCIL && P.ins1) zp = xs.val(P.nxt);
         if (P.sp & SP_ANY) {
-            Vec<T, N> cv, ax;
+            Vec<T, N> cv, ax, tsT;
 #pragma unroll
             for (int e = 0; e < N; ++e) {
                 cv.v[e] = T(c.v[e]);
                 ax.v[e] = T(0);
+                tsT.v[e] = T(0);
             }
             // the interior row at every node; irregular nodes are overwritten below
             T left = T(0), right = T(0);
@@ -358,8 +367,11 @@ __device__ __forceinline__ void wmarch_x(const L0View<T>& v, const XS xs, Fetch 
                 for (int ch = 0; ch * R < cnt; ++ch) {
                     if (!P.reuse) {  // (reuse: one load's rows, staged by the plane before)
                         const TV d = ch ? load_rows(P.tb0, ch, cnt) : P.trow;
+                        TV dT;
+                        if constexpr (BOTH) dT = load_rows_of(v.tabT, P.tb0, ch, cnt);
                         __builtin_amdgcn_wave_barrier();
                         stage[lane] = d;
+                        if constexpr (BOTH) stage2[lane] = dT;
                         __builtin_amdgcn_wave_barrier();
                     }
                     int r = P.rk0 - P.tb0 - ch * R;
@@ -375,6 +387,13 @@ __device__ __forceinline__ void wmarch_x(const L0View<T>& v, const XS xs, Fetch 
                                     ax.v[e] = cv.v[e] + t6[0] * xm + t6[1] * xp + t6[2] * T(ymv.v[e]) +
                                               t6[3] * T(ypv.v[e]) + t6[4] * T(zm.v[e]) +
                                               t6[5] * T(zp.v[e]);
+                                    if constexpr (BOTH) {
+                                        T u6[6];
+                                        row6<T>(stage2 + r * RV, u6);
+                                        tsT.v[e] = u6[0] * xm + u6[1] * xp + u6[2] * T(ymv.v[e]) +
+                                                   u6[3] * T(ypv.v[e]) + u6[4] * T(zm.v[e]) +
+                                                   u6[5] * T(zp.v[e]);
+                                    }
                                 } else {
                                     row6<T>(stage + r * RV, t[e]);
                                 }
@@ -388,6 +407,8 @@ __device__ __forceinline__ void wmarch_x(const L0View<T>& v, const XS xs, Fetch 
             if (FULL ? inb : P.nib != 0u) {
                 if constexpr (TAB && !STENCIL)
                     body(Idx{P.ib, (unsigned)(N * lane)}, P.fv, cv, ax, xl, y, z, P.nib, t);
+                else if constexpr (BOTH)
+                    body(Idx{P.ib, (unsigned)(N * lane)}, P.fv, cv, ax, tsT, xl, y, z, P.nib);
                 else
                     body(Idx{P.ib, (unsigned)(N * lane)}, P.fv, cv, ax, xl, y, z, P.nib);
             }
@@ -410,11 +431,11 @@ __device__ __forceinline__ void wmarch_x(const L0View<T>& v, const XS xs, Fetch 
     }
 }
 
-template <typename T, int N, bool STENCIL, bool TR, bool FULL, bool TAB = STENCIL, class TX,
-          class Fetch, class Body, class End = NoEnd>
+template <typename T, int N, bool STENCIL, bool TR, bool FULL, bool TAB = STENCIL,
+          bool BOTH = false, class TX, class Fetch, class Body, class End = NoEnd>
 __device__ __forceinline__ void wmarch(const L0View<T>& v, const TX* __restrict__ X, Fetch fetch,
                                        Body body, End end = End{}) {
-    wmarch_x<T, N, STENCIL, TR, FULL, TAB>(v, XArr<TX>{X}, fetch, body, end);
+    wmarch_x<T, N, STENCIL, TR, FULL, TAB, BOTH>(v, XArr<TX>{X}, fetch, body, end);
 }
 
 #define WNOFETCH [&](Idx, int, int, int, unsigned, int) { return NoVals{}; }
@@ -480,6 +501,67 @@ void w_apply(const FineLevel& L, bool trans, const T* x, T* y, hipStream_t s) {
 }
 template void w_apply<double>(const FineLevel&, bool, const double*, double*, hipStream_t);
 template void w_apply<float>(const FineLevel&, bool, const float*, float*, hipStream_t);
+
+// ---------------------------------------------------------------- Lanczos
+
+// u = S q with q = vin * scal[S_LZ_S] and S the symmetric part (A + A^T)/2, 2 nodes per
+// lane (see k_l0_lz_apply); partials of q.u.  Rows whose node is not irregular equal their
+// columns, so only irregular nodes (the fetched bits) take the row of A^T too.
+template <bool SYM>
+__global__ void __launch_bounds__(kMThreads) k_w_lz_apply(L0View<double> v,
+                                                         const double* __restrict__ vin,
+                                                         const double* __restrict__ scal,
+                                                         double* __restrict__ u, double* part) {
+    constexpr int N = 2;
+    __shared__ double lds[kMThreads / kWave];
+    const double sc = scal[S_LZ_S];
+    double a0 = 0.0;
+    auto irr_bits = [&](Idx, int, int, int, unsigned nibr, int) { return nibr; };
+    auto out = [&](Idx i, unsigned nibr, const Vec<double, N>& c, const Vec<double, N>& ax,
+                   const Vec<double, N>* ts, unsigned nib) {
+        double o[N];
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
+            const double q = sc * c.v[e], aq = sc * ax.v[e];
+            double oe = aq;
+            if (ts && ((nibr >> e) & 1u)) {
+                const double at = q + sc * ts->v[e];
+                oe = 0.5 * (aq + at);
+            }
+            const bool un = (nib >> e) & 1u;
+            o[e] = un ? oe : 0.0;
+            a0 += un ? q * o[e] : 0.0;
+        }
+        vstnt<N>(u, i, o);
+    };
+    if constexpr (SYM)
+        wmarch<double, N, true, false, false>(
+            v, vin, irr_bits,
+            [&](Idx i, unsigned nibr, const Vec<double, N>& c, const Vec<double, N>& ax, int, int,
+                int, unsigned nib) { out(i, nibr, c, ax, nullptr, nib); });
+    else
+        wmarch<double, N, true, false, false, true, true>(
+            v, vin, irr_bits,
+            [&](Idx i, unsigned nibr, const Vec<double, N>& c, const Vec<double, N>& ax,
+                const Vec<double, N>& ts, int, int, int, unsigned nib) {
+                out(i, nibr, c, ax, &ts, nib);
+            });
+    const double s0 = block_sum(a0, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = s0;
+}
+
+void w_lz_apply(const FineLevel& L, bool sym, const double* vin, const double* scal, double* u,
+                double* partials, hipStream_t s) {
+    const L0View<double> v = wview<double>(L, 2);
+    const dim3 g((unsigned)l0_wblocks(L, 2));
+    if (sym)
+        hipLaunchKernelGGL(k_w_lz_apply<true>, g, dim3(kWave, kMY), 0, s, v, vin, scal, u,
+                           partials);
+    else
+        hipLaunchKernelGGL(k_w_lz_apply<false>, g, dim3(kWave, kMY), 0, s, v, vin, scal, u,
+                           partials);
+    HIPCHECK(hipGetLastError());
+}
 
 // ---------------------------------------------------------------- V-cycle
 

@@ -34,6 +34,8 @@ CASES = {
     "cyl_robin_lin": (W.Shape.cylinder(1.0, 2.0), 27, 27, 25, W.VARIANT_LIN, True),
     "ell_robin_quad": (W.Shape.ellipse(1.0, 0.6, 4.0), 40, 26, 44, W.VARIANT_QUAD, True),
     "ell68_quad": (W.Shape.ellipse(1.0, 0.6, 4.0), 68, 45, 66, W.VARIANT_QUAD),
+    # a symmetric (linear) rule with nx a multiple of 4, for the 16-byte-lane layout
+    "cyl36_lin": (W.Shape.cylinder(1.0, 2.0), 36, 36, 40, W.VARIANT_LIN),
 }
 # (case, lanes): every case with the automatic level-0 lanes (one node per lane on these
 # short lines), and the cases whose nx is a multiple of 4 again on 16-byte lanes
@@ -127,6 +129,17 @@ def test_hierarchy_matches_oracle(name):
         if l < len(sizes) - 1:
             assert abs(c.info["lambda_est"][l] - lv.lam) <= 1e-10 * lv.lam
             assert abs(c.info["omega"][l] - lv.omega) <= 1e-10 * lv.omega
+
+
+@pytest.mark.parametrize("name", [n for n, w in LANES if w == 2])
+def test_spectral_estimates_on_wide_lanes(name):
+    """Level 0 on 16-byte lanes runs the Lanczos steps' symmetric-part apply on the wide
+    march (rows of A and A^T from the table at irregular nodes): the estimates and the
+    smoothing weights agree with the oracle's as on one-node lanes."""
+    c = case(name, wide=2)
+    for l, lv in enumerate(c.H.levels[:-1]):
+        assert abs(c.info["lambda_est"][l] - lv.lam) <= 1e-10 * lv.lam, (name, l)
+        assert abs(c.info["omega"][l] - lv.omega) <= 1e-10 * lv.omega, (name, l)
 
 
 @pytest.mark.parametrize("name", list(CASES))
