@@ -161,6 +161,10 @@ void w_prolong(const FineLevel& L, const CoarseLevel& C, const T* vc, T* x, doub
                KTimer& kt);
 template <typename T>
 void w_dot(const FineLevel& L, const double* a, const T* b, double* partials, hipStream_t s);
+// Solve start without an initial guess on 16-byte lanes (b 16-byte aligned): b~, x = 0,
+// r = b~, its fp32 copy and the partials of cg_resid in one pass.
+void w_cg_start(const FineLevel& L, const double* b, double* bs, double* x, double* r,
+                double* partials, float* r32, hipStream_t s);
 void w_cg_resid(const FineLevel& L, const double* bs, const double* x, double* r, double* partials,
                 float* r32, hipStream_t s);
 // The CG step on 16-byte lanes (directions in a ring): nodes per lane of its two passes,

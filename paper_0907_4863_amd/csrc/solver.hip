@@ -533,9 +533,14 @@ static void state_start(saamg_state* S, const double* b, const double* x0) {
     S->done = 0;
     S->repl = 0;
     S->t0 = std::chrono::steady_clock::now();
-    cg_init(cg_op(H), b, x0, S->bs, S->x, S->s);
-    // without an initial guess x = 0 and r = b~ (no product with A)
-    cg_resid(cg_op(H), S->bs, x0 ? S->x : nullptr, S->r, S->part, S->r32, S->s);
+    if (!x0 && cg_op(H).wide && (reinterpret_cast<uintptr_t>(b) & 15u) == 0) {
+        // without an initial guess x = 0 and r = b~: one pass on 16-byte lanes
+        w_cg_start(cg_op(H), b, S->bs, S->x, S->r, S->part, S->r32, S->s);
+    } else {
+        cg_init(cg_op(H), b, x0, S->bs, S->x, S->s);
+        // without an initial guess x = 0 and r = b~ (no product with A)
+        cg_resid(cg_op(H), S->bs, x0 ? S->x : nullptr, S->r, S->part, S->r32, S->s);
+    }
     finalize(S->part, cg_resid_parts(cg_op(H)), 2, S->scal, FIN_STORE, S_RR, S->s);
     scal_start(S->scal, S->tol, S->s);
     S->kdir = 0;

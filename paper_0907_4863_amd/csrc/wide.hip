@@ -941,6 +941,58 @@ void w_cg_resid(const FineLevel& L, const double* bs, const double* x, double* r
     HIPCHECK(hipGetLastError());
 }
 
+// Start of a solve without an initial guess, in one pass (2 nodes per lane): b~ = sigma rho b
+// as k_cg_init forms it, x = 0, and r = b~ with its fp32 copy and the partials of r.r and
+// b~.b~ exactly as k_w_cg_resid<true> forms them (same march, same grid, same order).
+__global__ void __launch_bounds__(kMThreads) k_w_cg_start(L0View<double> v,
+                                                         const double* __restrict__ sigma,
+                                                         const double* __restrict__ b,
+                                                         double* __restrict__ bs,
+                                                         double* __restrict__ xv,
+                                                         double* __restrict__ r, double* part,
+                                                         float* __restrict__ r32) {
+    constexpr int N = 2;
+    __shared__ double lds[kMThreads / kWave];
+    double a0 = 0.0, a1 = 0.0;
+    struct SB {
+        Vec<double, N> sg, b;
+    };
+    wmarch<double, N, false, false, false>(
+        v, (const double*)nullptr,
+        [&](Idx i, int, int, int, unsigned, int) { return SB{vldnt<N>(sigma, i), vldnt<N>(b, i)}; },
+        [&](Idx i, const SB& f, const Vec<double, N>&, const Vec<double, N>&, int, int, int z,
+            unsigned nib) {
+            // end-plane rows of open ends are halved, and so is their right-hand side
+            const double rho = (z == 1 || z == v.nz - 2) ? v.rho_end : 1.0;
+            double o[N], zero[N];
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                const bool u = (nib >> e) & 1u;
+                const double be = f.sg.v[e] * rho * f.b.v[e];
+                o[e] = u ? be : 0.0;
+                zero[e] = 0.0;
+                a0 += o[e] * o[e];
+                a1 += u ? o[e] * o[e] : 0.0;
+            }
+            vstnt<N>(bs, i, o);
+            vstnt<N>(xv, i, zero);
+            vstnt<N>(r, i, o);
+            if (r32) vstnt<N>(r32, i, o);
+        });
+    const double s0 = block_sum(a0, lds), s1 = block_sum(a1, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        part[blockIdx.x] = s0;
+        part[gridDim.x + blockIdx.x] = s1;
+    }
+}
+
+void w_cg_start(const FineLevel& L, const double* b, double* bs, double* x, double* r,
+                double* partials, float* r32, hipStream_t s) {
+    hipLaunchKernelGGL(k_w_cg_start, wgrid<double>(L), dim3(kWave, kMY), 0, s,
+                       wview<double>(L, 2), (const double*)L.sigma, b, bs, x, r, partials, r32);
+    HIPCHECK(hipGetLastError());
+}
+
 // The CG step on 16-byte lanes, in two passes that share no q = A p vector (N nodes per
 // lane and the first pass's arithmetic TA per precision: cg_dir_lanes, CgDirArith).  The
 // directions (in E: fp32 in mixed precision, else fp64) live in a ring of buffers.  The

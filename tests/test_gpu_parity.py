@@ -254,6 +254,27 @@ def test_solve_mixed_matches_tight_oracle(name, wide):
     assert err <= 1e-6
 
 
+@pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
+def test_solve_start_paths_agree(precision):
+    """A start without an initial guess takes one fused pass on 16-byte lanes when b is
+    16-byte aligned, else the two-pass start (b~ and x, then r = b~ with its partials):
+    both give bitwise the same solve."""
+    c = case("ell68_quad", precision, wide=2)
+    n = int(np.prod(c.dims))
+    b = c.to_dev(c.b)
+    buf = torch.zeros(n + 1, dtype=torch.float64, device=_dev())
+    buf[1:] = b
+    b_odd = buf[1:]  # 8 bytes past a 16-byte boundary
+    assert b.data_ptr() % 16 == 0 and b_odd.data_ptr() % 16 == 8
+    x1 = torch.zeros(n, dtype=torch.float64, device=_dev())
+    x2 = torch.zeros(n, dtype=torch.float64, device=_dev())
+    r1 = sa.solve(c.G, b, x1, tol=1e-8)
+    r2 = sa.solve(c.G, b_odd, x2, tol=1e-8)
+    assert r1["status"] == 0 and r2["status"] == 0
+    assert r1["iterations"] == r2["iterations"]
+    assert torch.equal(x1, x2)
+
+
 @pytest.mark.parametrize("precision", [W.PREC_MIXED, W.PREC_FP64])
 @pytest.mark.parametrize("wide", [0, 2])
 def test_solve_stopped_early(wide, precision):
