@@ -132,6 +132,11 @@ typedef struct {
        of the vector memory instructions per node; needs nx a multiple of 4); 0 =
        automatic (2 where nx is a multiple of 4 and above 128, else 1).    default 0 */
     int32_t l0_wide;
+    /* CG directions kept on 16-byte-lane hierarchies before x takes them (x is updated
+       from all of them in one pass when they are all in use and before x is read):
+       0 = automatic (32, fewer where 32 directions of the box would exceed 8 GiB, at least
+       2); else 2..32.  The iterates do not depend on it.                  default 0 */
+    int32_t cg_ring;
 } saamg_options;
 
 /* Outcome of one solve. rel_res_* are ||r||/||b|| of the scaled system. */

@@ -48,7 +48,7 @@ class Options(C.Structure):
                 ("omega_scale", C.c_double), ("coarse_solver", C.c_int32),
                 ("coarse_sweeps", C.c_int32), ("l0_planes", C.c_int32),
                 ("l0_tile_x", C.c_int32), ("alloc", ALLOC_FN), ("free", FREE_FN),
-                ("alloc_ctx", C.c_void_p), ("l0_wide", C.c_int32)]
+                ("alloc_ctx", C.c_void_p), ("l0_wide", C.c_int32), ("cg_ring", C.c_int32)]
 
 
 class Grid(C.Structure):

@@ -29,12 +29,13 @@ enum Slot {
     S_TOL,   // the solve's tolerance
     S_SKIP,  // nonzero: the queued V-cycle is not needed (the residual passes the test)
     S_AR0 = 18,  // kCgRing slots: the step length of each direction in the ring (fp32 CG)
-    S_NSLOTS = S_AR0 + 16
+    S_NSLOTS = S_AR0 + 32
 };
-// Directions of the fp32-direction CG step kept in a ring (x receives them every kCgRing
-// steps and before it is read; see k_cg_xring).  16 directions: a solve of up to 16 steps
-// updates x once, at 64 bytes per box node (3.2 GB on a 256 x 256 x 768 box).  With 8 a
-// flush took 391 us on that box (x and 8 directions, 6.2 TB/s), three per 22-step solve.
+// Directions of the CG step kept in a ring (x receives them every kCgRing steps and before
+// it is read; see k_cg_xring).  At most 32 directions (cg_ring_len): a solve of up to 32
+// steps updates x once (a 22-step solve on a 256 x 256 x 768 box: one pass over x and 22
+// fp32 directions instead of two passes, 16 and 6); with 8 a flush took 391 us on that box
+// (x and 8 directions, 6.2 TB/s), three per 22-step solve.
 constexpr int kCgRing = S_NSLOTS - S_AR0;
 // The pending directions of a ring flush: ring slots in the order of their steps.
 struct RingSlots {
@@ -186,7 +187,8 @@ constexpr int cg_xr_lanes(int bytes) { return bytes == 4 ? kCgXrLanes : 2; }
 // ring stays within 8 GiB, down to 2 (x is then updated every other step, which moves
 // no more than one update per step).
 constexpr long kCgRingBudget = 8L << 30;
-inline int cg_ring_len(long nbox, int bytes) {
+inline int cg_ring_len(long nbox, int bytes, int forced = 0) {
+    if (forced > 0) return std::min(forced, kCgRing);
     const long k = kCgRingBudget / (std::max(nbox, 1L) * bytes);
     return (int)std::max(2L, std::min<long>(kCgRing, k));
 }

@@ -447,7 +447,7 @@ static void state_alloc(saamg_state* S, saamg_hierarchy* H, bool pinned = true) 
     S->pw = S->mixed ? 4 : 8;
     if (S->ringf) {
         // a state that allocates nothing keeps 2 directions (flushed every other step)
-        S->ringk = pinned ? cg_ring_len(n, S->pw) : 2;
+        S->ringk = pinned ? cg_ring_len(n, S->pw, H->opt.cg_ring) : 2;
         S->ring = dmalloc((size_t)S->pw * S->ringk * n);
     } else {
         S->p = dmalloc(8 * n);
@@ -872,6 +872,8 @@ static void validate_options(const saamg_options& o) {
         throw ApiError{SAAMG_INVALID_ARG, "l0_tile_x must be 0, 1, 2 or 4"};
     if ((o.alloc == nullptr) != (o.free == nullptr))
         throw ApiError{SAAMG_INVALID_ARG, "alloc and free must both be set or both be NULL"};
+    if (o.cg_ring != 0 && (o.cg_ring < 2 || o.cg_ring > kCgRing))
+        throw ApiError{SAAMG_INVALID_ARG, "cg_ring must be 0 (automatic) or 2..32"};
     if (o.l0_wide < 0 || o.l0_wide > 2)
         throw ApiError{SAAMG_INVALID_ARG, "l0_wide must be 0, 1 or 2"};
 }
@@ -1444,6 +1446,7 @@ void saamg_default_options(saamg_options* o) {
     o->l0_planes = 0;
     o->l0_tile_x = 0;
     o->l0_wide = 0;
+    o->cg_ring = 0;
     o->alloc = nullptr;
     o->free = nullptr;
     o->alloc_ctx = nullptr;

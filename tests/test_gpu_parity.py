@@ -48,7 +48,7 @@ def _dev():
 
 
 class Case:
-    def __init__(self, name, precision=W.PREC_FP64, opts=None, gs=False, wide=0):
+    def __init__(self, name, precision=W.PREC_FP64, opts=None, gs=False, wide=0, ring=0):
         shape, nx, ny, nz, variant = CASES[name][:5]
         robin = len(CASES[name]) > 5 and CASES[name][5]
         self.name, self.shape, self.variant = name, shape, variant
@@ -60,7 +60,7 @@ class Case:
             opts = amg.Options(coarse_solver="gs")
         self.sys, self.H = solve.build(shape, nx, ny, nz, variant, opts, robin=robin)
         dom = sa.domain_for(shape, nx, ny, nz, open_ends=robin)
-        o = sa.default_options(precision=precision, l0_wide=wide)
+        o = sa.default_options(precision=precision, l0_wide=wide, cg_ring=ring)
         if opts is not None:
             o.max_coarse, o.cheb_degree = opts.max_coarse, opts.cheb_degree
             o.coarse_solver = sa.COARSE_GS if opts.coarse_solver == "gs" else sa.COARSE_DIRECT
@@ -88,10 +88,10 @@ class Case:
 _cache = {}
 
 
-def case(name, precision=W.PREC_FP64, gs=False, wide=0):
-    key = (name, precision, gs, wide)
+def case(name, precision=W.PREC_FP64, gs=False, wide=0, ring=0):
+    key = (name, precision, gs, wide, ring)
     if key not in _cache:
-        _cache[key] = Case(name, precision, gs=gs, wide=wide)
+        _cache[key] = Case(name, precision, gs=gs, wide=wide, ring=ring)
     return _cache[key]
 
 
@@ -275,6 +275,23 @@ def test_solve_start_paths_agree(precision):
     assert torch.equal(x1, x2)
 
 
+@pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
+def test_ring_length_leaves_the_iterates_unchanged(precision):
+    """The ring of CG directions on 16-byte lanes (2, 5, 16 or the automatic 32): x takes
+    the same updates in the same order however often it is flushed, so every length gives
+    bitwise the same solve."""
+    base = None
+    for ring in (0, 2, 5, 16):
+        c = case("ell68_quad", precision, wide=2, ring=ring)
+        xg, res = gpu_solve(c, c.b)
+        print(f"[ring {ring} prec={precision}] it={res['iterations']}", flush=True)
+        assert res["status"] == 0
+        if base is None:
+            base = (xg, res["iterations"])
+        else:
+            assert res["iterations"] == base[1] and np.array_equal(xg, base[0]), ring
+
+
 @pytest.mark.parametrize("precision", [W.PREC_MIXED, W.PREC_FP64])
 @pytest.mark.parametrize("wide", [0, 2])
 def test_solve_stopped_early(wide, precision):
@@ -284,9 +301,10 @@ def test_solve_stopped_early(wide, precision):
     returned x carries every step: the reported true residual, which the oracle recomputes
     from x, agrees with the recursive one (a missing alpha p would leave a residual of an
     earlier step's size), and a restart from x converges to the oracle's solution."""
-    c = case("ell68_quad", precision, wide=wide)
+    c = case("ell68_quad", precision, wide=wide, ring=16 if wide else 0)
     xref = operator.unscale(c.sys, solve.solve(c.sys, c.H, c.b, tol=1e-13).x)
-    # k = 20 > 16 directions: the ring is flushed once mid-solve (at a tolerance the solve
+    # k = 20 > 16 directions (a ring of 16 on the 16-byte lanes): the ring is flushed once
+    # mid-solve (at a tolerance the solve
     # cannot reach, so it still stops by max_iter); its residual is deep, so the two
     # residuals and the oracle's are compared more loosely there
     for k, tol in ((1, 1e-8), (2, 1e-8), (5, 1e-8), (20, 1e-15)):

@@ -19,7 +19,7 @@ sa = pytest.importorskip("paper_0907_4863_amd")
 pytestmark = pytest.mark.gpu
 
 # larger first, then smaller; the first on 16-byte lanes (nx a multiple of 4 above 128), where
-# the allocation-free solve keeps 2 CG directions in its ring against up to 16
+# the allocation-free solve keeps 2 CG directions in its ring against up to 32
 CASES = [("ell132_quad", W.Shape.ellipse(1.0, 0.6, 4.0), 132, 45, 40, W.VARIANT_QUAD),
          ("ell70_quad", W.Shape.ellipse(1.0, 0.6, 4.0), 70, 45, 66, W.VARIANT_QUAD),
          ("cyl33_lin", W.Shape.cylinder(1.0, 2.0), 33, 33, 33, W.VARIANT_LIN)]
