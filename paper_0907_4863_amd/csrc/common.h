@@ -260,6 +260,7 @@ struct CoarseLevel {
     int sym;
     double* coef64[27] = {};
     double* invD64 = nullptr;
+    double* block64 = nullptr;  // one allocation holding the coef64 arrays and invD64
     float* invD32 = nullptr;
     long n_unknowns = 0;
     // compressed operator: slot per storage node, interior stencil, table [tab_cap][kLcRow]

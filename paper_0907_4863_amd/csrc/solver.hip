@@ -814,23 +814,23 @@ static CoarseLevel make_coarse(int fmx, int fmy, int fmz, int sym) {
     C.sxy = (long)C.sx * C.sy;
     C.nstore = C.sxy * C.sz;
     C.sym = sym;
-    try {
-        for (int k = 0; k < 27; ++k)
-            if (!sym || k >= 13) C.coef64[k] = (double*)dmalloc(8 * C.nstore);
-        C.invD64 = (double*)dmalloc(8 * C.nstore);
-    } catch (...) {
-        free_coarse(C);
-        throw;
-    }
+    // the coefficient arrays (27, or the 14 of offsets k >= 13 on symmetric levels) and
+    // 1/diag in one allocation, each array 256-byte aligned: one zero fill for all of them
+    const long stride = (C.nstore + 31) & ~31L;
+    const int na = sym ? 14 : 27;
+    C.block64 = (double*)dmalloc(8 * stride * (na + 1));
+    int j = 0;
+    for (int k = 0; k < 27; ++k)
+        if (!sym || k >= 13) C.coef64[k] = C.block64 + stride * j++;
+    C.invD64 = C.block64 + stride * j;
     return C;
 }
 
 static void free_coarse(CoarseLevel& C) {
-    for (int k = 0; k < 27; ++k) {
-        dfree(C.coef64[k]);
-        C.coef64[k] = nullptr;
-    }
-    for (void* p : {(void*)C.invD64, (void*)C.invD32, (void*)C.slot, (void*)C.tab64, (void*)C.tab32,
+    dfree(C.block64);  // the coef64 arrays and invD64
+    C.block64 = nullptr;
+    for (int k = 0; k < 27; ++k) C.coef64[k] = nullptr;
+    for (void* p : {(void*)C.invD32, (void*)C.slot, (void*)C.tab64, (void*)C.tab32,
                     (void*)C.slotT, (void*)C.tabT64, (void*)C.tabT32})
         dfree(p);
     C.invD64 = nullptr;
@@ -843,7 +843,7 @@ static void free_coarse(CoarseLevel& C) {
 
 static int64_t coarse_bytes(const CoarseLevel& C, bool mixed) {
     const int na = C.sym ? 14 : 27;
-    return (int64_t)(na + 1) * C.nstore * 8 + 4L * C.nstore * (C.sym ? 1 : 2) +
+    return (int64_t)(na + 1) * ((C.nstore + 31) & ~31L) * 8 + 4L * C.nstore * (C.sym ? 1 : 2) +
            (mixed ? 4L * C.nstore : 0) + (long)kLcRow * (C.tab_cap + C.tabT_cap) * (mixed ? 12 : 8);
 }
 
